@@ -1,0 +1,466 @@
+"""Tensorial template matching, FP64 reference.  TEST INFRASTRUCTURE ONLY (see oracle/__init__).
+
+Everything here is the plain definition written out, in the paper's order:
+
+* filter h with 1D z-transform 1 + a(z + z^-1 - 2), a = 1/5, separable
+  (Sec. 2, after Eq. norm_f)                                   -> prefilter_*
+* binary ball mask m, M = sum m (Sec. 2; soft edge not used)   -> ball_mask
+* template zero-normalisation t' (Eq. norm_t)                  -> normalize_template
+* tensor template T_alpha = (1/N_q) sum_q v_q^alpha t'_q (Eq. tt, Alg. 1)
+                                                               -> tensor_template
+* local normalisation w(x) (Eq. norm_f)                        -> local_normalization
+* tensor field C_alpha = w (g * T_alpha), a correlation (Eq. tcc, Alg. 2,
+  Eq. correlation), by direct spatial sums                     -> tensor_field
+* Frobenius score ||C||_F (Sec. 3.2)                           -> score
+* SS-HOPM dominant eigenpair from given starts (Sec. 3.1)      -> sshopm, orient_multistart
+* Find Peaks: P highest scores at least two mask radii apart (Sec. 3.4)
+                                                               -> find_peaks
+* rotation-sampled TM c(x, R) = w (f * t'_R) (Eq. lncc)        -> brute_force_tm
+
+Readings of points the paper leaves open (each is listed in the design doc):
+* the image operator S reduces to h* on the image; the mask acts through t'
+  and w; correlation outputs exist only on the valid region, where the whole
+  template box lies inside the volume, and are 0 elsewhere;
+* g = h*f replicates the border voxel on the volume, t is zero-padded;
+* Alg. 1 rotates t', which already contains S, so no second filtering;
+* template centre c = L//2 per axis, mask m(p) = [|p - c|^2 <= r^2];
+* d' = 3 axis form: v_q = R(q) a for a fixed template axis a (default z);
+  d' = 4: v_q = q itself, the paper's quaternion form;
+* w = 0 where var <= eps_w * M * mean(g^2 over the volume), eps_w = 1e-6;
+* SS-HOPM maximises the signed value, on the tensor divided by its Frobenius
+  norm; its shift is alpha = max(0, -lambda_min(U)) with U the square matrix
+  unfolding (the paper's rule, Sec. 3.1); stop when |delta lambda| <= tol or
+  after max_iter steps; best start by largest lambda, lowest index on ties;
+  sign canonicalised so the last non-zero coordinate is positive.
+
+Parity status: every function here is pinned by tests/test_oracle_*.py
+(closed forms, invariants, brute force, textbook routines); the absolute
+values on the synthetic workloads are not printed in the paper.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import sym
+from .rotations import quat_to_matrix, rotate_template
+
+# ----------------------------------------------------------------------------
+# filter, mask, template normalisation
+# ----------------------------------------------------------------------------
+
+
+def filter_taps(a: float = 0.2) -> np.ndarray:
+    """Impulse response of 1 + a(z + z^-1 - 2): [a, 1 - 2a, a]."""
+    return np.array([a, 1.0 - 2.0 * a, a])
+
+
+def _filter_axis(x: np.ndarray, axis: int, a: float, mode: str) -> np.ndarray:
+    taps = filter_taps(a)
+    pad = [(0, 0)] * x.ndim
+    pad[axis] = (1, 1)
+    xp = np.pad(x, pad, mode=mode)
+    n = x.shape[axis]
+    lo = np.take(xp, np.arange(0, n), axis=axis)
+    mid = np.take(xp, np.arange(1, n + 1), axis=axis)
+    hi = np.take(xp, np.arange(2, n + 2), axis=axis)
+    return taps[0] * lo + taps[1] * mid + taps[2] * hi
+
+
+def prefilter_volume(f: np.ndarray, a: float = 0.2) -> np.ndarray:
+    """g = h * f, separable over z, y, x, border voxels replicated."""
+    g = np.asarray(f, dtype=np.float64)
+    for ax in range(3):
+        g = _filter_axis(g, ax, a, "edge")
+    return g
+
+
+def prefilter_box(f: np.ndarray, lo, hi, a: float = 0.2) -> np.ndarray:
+    """g = h * f restricted to the box [lo, hi) (z, y, x) of a larger volume.
+
+    Same values as prefilter_volume(f)[box]; only reads f around the box.
+    """
+    sl = []
+    pad = []
+    for ax in range(3):
+        a0, a1 = lo[ax] - 1, hi[ax] + 1
+        c0, c1 = max(a0, 0), min(a1, f.shape[ax])
+        sl.append(slice(c0, c1))
+        pad.append((c0 - a0, a1 - c1))
+    sub = np.pad(np.asarray(f[tuple(sl)], dtype=np.float64), pad, mode="edge")
+    g = sub
+    taps = filter_taps(a)
+    for ax in range(3):
+        n = g.shape[ax] - 2
+        g = (taps[0] * np.take(g, np.arange(0, n), axis=ax)
+             + taps[1] * np.take(g, np.arange(1, n + 1), axis=ax)
+             + taps[2] * np.take(g, np.arange(2, n + 2), axis=ax))
+        # the margin of the other axes stays until they are filtered
+    return g
+
+
+def prefilter_template(t: np.ndarray, a: float = 0.2) -> np.ndarray:
+    """h * t with zero padding outside the template box."""
+    g = np.asarray(t, dtype=np.float64)
+    for ax in range(3):
+        g = _filter_axis(g, ax, a, "constant")
+    return g
+
+
+def ball_mask(L: int, r: float) -> np.ndarray:
+    """m(p) = 1 if |p - c| <= r else 0, c = L//2 on every axis."""
+    idx = np.arange(L) - L // 2
+    zz, yy, xx = np.meshgrid(idx, idx, idx, indexing="ij")
+    return ((xx * xx + yy * yy + zz * zz) <= r * r).astype(np.float64)
+
+
+def normalize_template(t: np.ndarray, r: float, a: float = 0.2) -> np.ndarray:
+    """t' = m (S(t) - mu) / sqrt(<S(t)^2, 1> - <S(t), 1>^2 / M)   (Eq. norm_t).
+
+    S(t) = m (h * t); mu = <S(t), m> / M.
+    """
+    m = ball_mask(t.shape[0], r)
+    M = m.sum()
+    st = m * prefilter_template(t, a)
+    mu = np.sum(st * m) / M
+    sig = math.sqrt(np.sum(st * st) - np.sum(st) ** 2 / M)
+    return m * (st - mu) / sig
+
+
+# ----------------------------------------------------------------------------
+# tensor template (Alg. 1)
+# ----------------------------------------------------------------------------
+
+
+def direction_of(q, dprime: int, axis=(0.0, 0.0, 1.0)) -> np.ndarray:
+    """The vector whose n-th power stands for rotation q: R(q) a (d'=3) or q (d'=4)."""
+    q = np.asarray(q, dtype=np.float64)
+    q = q / np.linalg.norm(q)
+    if dprime == 4:
+        return q
+    return quat_to_matrix(q) @ np.asarray(axis, dtype=np.float64)
+
+
+def tensor_template(tn: np.ndarray, quats: np.ndarray, n: int, dprime: int = 3,
+                    axis=(0.0, 0.0, 1.0)) -> np.ndarray:
+    """T_alpha(p) = (1/N_q) sum_q v_q^alpha t'_q(p), shape (K, L, L, L).
+
+    For each q: rotate t' (trilinear pull-back), then add the monomial-weighted
+    copy to every component (Alg. 1), with equal quadrature weights 1/N_q.
+    """
+    L = tn.shape[0]
+    K = sym.n_components(n, dprime)
+    T = np.zeros((K, L, L, L))
+    for q in quats:
+        tq = rotate_template(tn, quat_to_matrix(q))
+        k = sym.monomials(direction_of(q, dprime, axis), n)
+        T += k[:, None, None, None] * tq[None]
+    return T / len(quats)
+
+
+# ----------------------------------------------------------------------------
+# valid region, local normalisation, tensor field
+# ----------------------------------------------------------------------------
+
+
+def valid_range(D: int, L: int):
+    """First and last voxel whose template window [x - c, x - c + L) lies inside [0, D)."""
+    c = L // 2
+    return c, D - L + c
+
+
+def _windows(g: np.ndarray, L: int):
+    return np.lib.stride_tricks.sliding_window_view(g, (L, L, L))
+
+
+def correlate_valid(g: np.ndarray, kernels: np.ndarray) -> np.ndarray:
+    """out[k, v] = sum_p g[v + p] kernels[k, p] for every v with the window inside g.
+
+    This is (g * t)(x) = sum_p g(x + p - c) t(p) (Eq. correlation) at the valid
+    voxel x = v + c.  kernels: (nk, L, L, L) -> (nk, Vz, Vy, Vx).
+    """
+    L = kernels.shape[-1]
+    win = _windows(np.asarray(g, dtype=np.float64), L)
+    Vz, Vy, Vx = win.shape[:3]
+    km = kernels.reshape(kernels.shape[0], -1).T                      # (L^3, nk)
+    out = np.empty((kernels.shape[0], Vz, Vy, Vx))
+    rows = max(1, int(2 ** 25 // max(1, Vx * L ** 3)))
+    for z in range(Vz):
+        for y0 in range(0, Vy, rows):
+            y1 = min(Vy, y0 + rows)
+            patch = win[z, y0:y1].reshape(-1, L ** 3)
+            out[:, z, y0:y1, :] = (patch @ km).T.reshape(-1, y1 - y0, Vx)
+    return out
+
+
+def volume_g2_mean(g: np.ndarray) -> float:
+    return float(np.mean(np.asarray(g, dtype=np.float64) ** 2))
+
+
+def local_variance(g: np.ndarray, mask: np.ndarray) -> np.ndarray:
+    """var(x) = <S(tau_x g)^2, 1> - <S(tau_x g), 1>^2 / M on the valid region (Eq. norm_f)."""
+    M = mask.sum()
+    s1 = correlate_valid(g, mask[None])[0]
+    s2 = correlate_valid(np.asarray(g, dtype=np.float64) ** 2, (mask * mask)[None])[0]
+    return s2 - s1 * s1 / M
+
+
+def local_normalization(g: np.ndarray, mask: np.ndarray, eps_w: float = 1e-6,
+                        g2_mean: float | None = None) -> np.ndarray:
+    """w(x) = 1 / sqrt(var(x)) on the valid region, 0 elsewhere (Eq. norm_f).
+
+    Guard: w = 0 where var <= eps_w * M * mean(g^2) (a flat or constant window).
+    Returns a full-size map.
+    """
+    L = mask.shape[0]
+    M = mask.sum()
+    if g2_mean is None:
+        g2_mean = volume_g2_mean(g)
+    var = local_variance(g, mask)
+    w_valid = np.where(var > eps_w * M * g2_mean, 1.0 / np.sqrt(np.maximum(var, 1e-300)), 0.0)
+    w = np.zeros(g.shape)
+    c = L // 2
+    Vz, Vy, Vx = var.shape
+    w[c:c + Vz, c:c + Vy, c:c + Vx] = w_valid
+    return w
+
+
+def tensor_field(g: np.ndarray, w: np.ndarray, T: np.ndarray) -> np.ndarray:
+    """C_alpha(x) = w(x) (g * T_alpha)(x) on the valid region (Eq. tcc, Alg. 2).
+
+    Returns (K, Vz, Vy, Vx) indexed from the first valid voxel.
+    """
+    L = T.shape[-1]
+    c = L // 2
+    raw = correlate_valid(g, T)
+    Vz, Vy, Vx = raw.shape[1:]
+    return raw * w[None, c:c + Vz, c:c + Vy, c:c + Vx]
+
+
+def patches_at(g_box_source, points, L: int, f=None, a: float = 0.2):
+    """Template windows g[x - c : x - c + L] at the given voxels (N, 3) (z, y, x).
+
+    If ``f`` is given, g = h * f is evaluated on each window from f (replicated
+    borders) instead of reading a precomputed g.
+    """
+    c = L // 2
+    out = np.empty((len(points), L, L, L))
+    for i, (z, y, x) in enumerate(points):
+        lo = (z - c, y - c, x - c)
+        hi = (z - c + L, y - c + L, x - c + L)
+        if f is not None:
+            out[i] = prefilter_box(f, lo, hi, a)
+        else:
+            out[i] = g_box_source[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]]
+    return out
+
+
+def field_at(patches: np.ndarray, mask: np.ndarray, T: np.ndarray, g2_mean: float,
+             eps_w: float = 1e-6):
+    """w, C at individual voxels from their template windows (same sums as above)."""
+    M = mask.sum()
+    P = patches.reshape(len(patches), -1)
+    s1 = P @ mask.reshape(-1)
+    s2 = (P * P) @ (mask * mask).reshape(-1)
+    var = s2 - s1 * s1 / M
+    w = np.where(var > eps_w * M * g2_mean, 1.0 / np.sqrt(np.maximum(var, 1e-300)), 0.0)
+    C = (P @ T.reshape(T.shape[0], -1).T) * w[:, None]                # (N, K)
+    return w, C
+
+
+# ----------------------------------------------------------------------------
+# score and orientation
+# ----------------------------------------------------------------------------
+
+
+def score(C: np.ndarray, n: int, dprime: int = 3) -> np.ndarray:
+    """c_hat = ||C||_F = sqrt(sum_alpha mu_alpha C_alpha^2) (Sec. 3.2).  C: (K, ...)."""
+    return sym.frobenius(C, n, dprime)
+
+
+def canonical_sign(u: np.ndarray) -> np.ndarray:
+    """Flip u so that its last non-zero coordinate is positive (u and -u are one answer)."""
+    u = np.array(u, dtype=np.float64)
+    for i in range(len(u) - 1, -1, -1):
+        if u[i] != 0.0:
+            return u if u[i] > 0 else -u
+    return u
+
+
+def sshopm(Cv: np.ndarray, n: int, u0, alpha: float, tol: float, max_iter: int):
+    """Shifted symmetric higher-order power method (Kolda & Mayo), maximising.
+
+    u <- (C u^{n-1} + alpha u) / ||.||;  lambda = <C, u^{(x)n}>.
+    Stops when |lambda_new - lambda| <= tol or after max_iter updates.
+    Returns (lambda, u, iterations, converged).
+    """
+    u = np.asarray(u0, dtype=np.float64)
+    u = u / np.linalg.norm(u)
+    g = sym.contract_n_minus_1(Cv, u, n)
+    lam = float(g @ u)
+    for it in range(1, max_iter + 1):
+        v = g + alpha * u
+        u = v / np.linalg.norm(v)
+        g = sym.contract_n_minus_1(Cv, u, n)
+        lam_new = float(g @ u)
+        if abs(lam_new - lam) <= tol:
+            return lam_new, u, it, True
+        lam = lam_new
+    return lam, u, max_iter, False
+
+
+def unfolding_shift(Cu: np.ndarray, n: int, d: int) -> float:
+    """alpha = max(0, -lambda_min(U)), U the d^{n/2} x d^{n/2} unfolding (Sec. 3.1)."""
+    return max(0.0, -float(np.linalg.eigvalsh(sym.unfolding(Cu, n, d)).min()))
+
+
+def orient_multistart(Cv: np.ndarray, n: int, starts: np.ndarray, tol: float = 1e-6,
+                      max_iter: int = 500, shift: float | None = None):
+    """Dominant eigenpair of one voxel's tensor from fixed starts (Sec. 3.1).
+
+    Works on C / ||C||_F with the unfolding shift unless ``shift`` is given.
+    Returns (lambda, u, per-start lambdas, per-start directions, per-start
+    iterations); lambdas are scaled back by ||C||_F.  A zero tensor gives
+    lambda = 0, u = 0.
+    """
+    d = starts.shape[1]
+    cn = float(sym.frobenius(Cv, n, d))
+    if cn == 0.0:
+        return (0.0, np.zeros(d), np.zeros(len(starts)), np.zeros((len(starts), d)),
+                np.zeros(len(starts), int))
+    Cu = np.asarray(Cv, dtype=np.float64) / cn
+    alpha = unfolding_shift(Cu, n, d) if shift is None else shift
+    lams, us, its = [], [], []
+    for s in starts:
+        lam, u, it, _ = sshopm(Cu, n, s, alpha, tol, max_iter)
+        lams.append(lam)
+        us.append(u)
+        its.append(it)
+    lams = np.array(lams)
+    best = int(np.argmax(lams))            # first maximum on ties
+    return cn * lams[best], canonical_sign(us[best]), cn * lams, np.array(us), np.array(its)
+
+
+def orientation_margin(lams: np.ndarray, us: np.ndarray, best_u: np.ndarray,
+                       sep_deg: float = 5.0) -> float:
+    """lambda_best minus the best lambda of starts that ended more than sep_deg away.
+
+    A small margin means two distinct local maxima are nearly tied and either
+    answer is correct; such voxels are reported as ambiguous.
+    """
+    far = angle_deg(us, best_u[None, :]) > sep_deg
+    if not np.any(far):
+        return np.inf
+    return float(np.max(lams) - np.max(lams[far]))
+
+
+def fibonacci_sphere(n: int) -> np.ndarray:
+    """n near-uniform points on S^2 (golden-angle spiral)."""
+    i = np.arange(n) + 0.5
+    z = 1.0 - 2.0 * i / n
+    r = np.sqrt(1.0 - z * z)
+    phi = np.pi * (3.0 - math.sqrt(5.0)) * i
+    return np.stack([r * np.cos(phi), r * np.sin(phi), z], axis=1)
+
+
+def reference_maxima(Cv: np.ndarray, n: int, grid: int = 20000, polish: int = 8,
+                     sep_deg: float = 5.0):
+    """Global maximiser by dense sampling + SS-HOPM polishing (d' = 3).
+
+    Evaluates <C, u^{(x)n}> on a Fibonacci sphere, polishes the best distinct
+    grid points, returns (lambda*, u*, lambda_2) where lambda_2 is the best
+    polished maximum more than sep_deg away from u* (up to sign), or -inf.
+    """
+    pts = fibonacci_sphere(grid)
+    vals = sym.weights(n, 3) * sym.monomials(pts, n) @ np.asarray(Cv, dtype=np.float64)
+    order = np.argsort(-vals)
+    cos_sep = math.cos(math.radians(sep_deg))
+    chosen = []
+    for i in order:
+        if all(abs(pts[i] @ pts[j]) < cos_sep for j in chosen):
+            chosen.append(i)
+        if len(chosen) >= polish:
+            break
+    cn = float(sym.frobenius(Cv, n, 3))
+    if cn == 0.0:
+        return 0.0, np.zeros(3), -np.inf
+    Cu = np.asarray(Cv, dtype=np.float64) / cn
+    found = []
+    for i in chosen:
+        lam, u, _, _ = sshopm(Cu, n, pts[i], float(n - 1), 1e-15, 50000)
+        found.append((lam * cn, canonical_sign(u)))
+    found.sort(key=lambda t: -t[0])
+    lam1, u1 = found[0]
+    lam2 = -np.inf
+    for lam, u in found[1:]:
+        if abs(u @ u1) < cos_sep:
+            lam2 = lam
+            break
+    return lam1, u1, lam2
+
+
+def angle_deg(u: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """Axis angle arccos|u.v| in degrees (u and -u are the same axis)."""
+    u = np.asarray(u, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    c = np.abs(np.sum(u * v, axis=-1)) / (np.linalg.norm(u, axis=-1) * np.linalg.norm(v, axis=-1))
+    return np.degrees(np.arccos(np.clip(c, 0.0, 1.0)))
+
+
+def quat_angle_deg(q1: np.ndarray, q2: np.ndarray) -> np.ndarray:
+    """Rotation distance 2 arccos|q1.q2| in degrees (Sec. 5.1)."""
+    c = np.abs(np.sum(np.asarray(q1) * np.asarray(q2), axis=-1))
+    return np.degrees(2.0 * np.arccos(np.clip(c, 0.0, 1.0)))
+
+
+# ----------------------------------------------------------------------------
+# peaks
+# ----------------------------------------------------------------------------
+
+
+def find_peaks(score_map: np.ndarray, valid_lo, valid_hi, top_p: int, min_dist: float):
+    """Greedy Find Peaks (Sec. 3.4): P highest scores, pairwise >= min_dist apart.
+
+    Candidates are the valid voxels [valid_lo, valid_hi] (inclusive, z, y, x);
+    order is descending score, then ascending linear index z*Y*X + y*X + x.
+    A candidate is kept if its distance to every kept peak is >= min_dist.
+    Returns (positions (P', 3) int64 z, y, x; scores (P',)).
+    """
+    Z, Y, X = score_map.shape
+    z0, y0, x0 = valid_lo
+    z1, y1, x1 = valid_hi
+    sub = score_map[z0:z1 + 1, y0:y1 + 1, x0:x1 + 1]
+    zz, yy, xx = np.meshgrid(np.arange(z0, z1 + 1), np.arange(y0, y1 + 1),
+                             np.arange(x0, x1 + 1), indexing="ij")
+    lin = (zz * Y * X + yy * X + xx).ravel()
+    vals = sub.ravel()
+    order = np.lexsort((lin, -vals))
+    kept = np.zeros((0, 3))
+    out_pos, out_val = [], []
+    d2 = float(min_dist) ** 2
+    for i in order:
+        if len(out_pos) >= top_p:
+            break
+        p = np.array([lin[i] // (Y * X), (lin[i] // X) % Y, lin[i] % X], dtype=np.float64)
+        if len(kept) and np.min(np.sum((kept - p) ** 2, axis=1)) < d2:
+            continue
+        kept = np.vstack([kept, p])
+        out_pos.append(p.astype(np.int64))
+        out_val.append(vals[i])
+    return np.array(out_pos, dtype=np.int64).reshape(-1, 3), np.array(out_val)
+
+
+# ----------------------------------------------------------------------------
+# rotation-sampled template matching (the comparison method; tests only)
+# ----------------------------------------------------------------------------
+
+
+def brute_force_tm(g: np.ndarray, w: np.ndarray, tn: np.ndarray, quats: np.ndarray) -> np.ndarray:
+    """c(x, R_q) = w(x) (g * t'_q)(x) on the valid region (Eq. lncc), shape (N_q, Vz, Vy, Vx)."""
+    L = tn.shape[0]
+    c = L // 2
+    rot = np.stack([rotate_template(tn, quat_to_matrix(q)) for q in quats])
+    raw = correlate_valid(g, rot)
+    Vz, Vy, Vx = raw.shape[1:]
+    return raw * w[None, c:c + Vz, c:c + Vy, c:c + Vx]

@@ -1,0 +1,387 @@
+"""Pins of the TTM oracle: closed forms, invariants, textbook routines, brute force."""
+import math
+
+import numpy as np
+import pytest
+import scipy.ndimage as ndi
+import scipy.signal as ss
+
+import synth
+from oracle import rotations as rot
+from oracle import sym, ttm
+
+
+def _tiny(seed=7, D=32, L=12, r=5.0, copies=2, amp=3.0):
+    return synth.make_tomogram("tiny", (D, D, D), L=L, n_blobs=3, n_copies=copies, min_sep=L,
+                               mask_radius=r, degree=4, seed=seed, snr=None, wedge=False,
+                               copy_amplitude=amp)
+
+
+# ---------------------------------------------------------------- P-1 filter
+def test_filter_impulse_and_frequency_response():
+    a = 0.2
+    imp = np.zeros((7, 7, 7))
+    imp[3, 3, 3] = 1.0
+    g = ttm.prefilter_template(imp, a)
+    taps = np.array([a, 1 - 2 * a, a])
+    want = np.zeros((7, 7, 7))
+    want[2:5, 2:5, 2:5] = taps[:, None, None] * taps[None, :, None] * taps[None, None, :]
+    assert np.allclose(g, want)
+    # 1D response 1 + a(z + 1/z - 2) on the unit circle = 1 - 4a sin^2(w/2) in [1 - 4a, 1]
+    w = np.linspace(0, np.pi, 101)
+    H = np.array([np.sum(taps * np.exp(-1j * k * np.array([-1, 0, 1]))) for k in w])
+    assert np.allclose(H.imag, 0, atol=1e-15)
+    assert np.allclose(H.real, 1 - 4 * a * np.sin(w / 2) ** 2)
+    assert H.real.min() == pytest.approx(0.2) and H.real.max() == pytest.approx(1.0)
+
+
+def test_prefilter_volume_matches_scipy_and_constants():
+    rng = np.random.default_rng(0)
+    f = rng.standard_normal((9, 10, 11))
+    taps = np.array([0.2, 0.6, 0.2])
+    want = f
+    for ax in range(3):
+        want = ndi.correlate1d(want, taps, axis=ax, mode="nearest")
+    assert np.allclose(ttm.prefilter_volume(f), want, atol=1e-13)
+    assert np.allclose(ttm.prefilter_volume(np.full((5, 6, 7), 3.25)), 3.25, atol=1e-14)
+
+
+def test_prefilter_box_equals_volume_filter():
+    rng = np.random.default_rng(1)
+    f = rng.standard_normal((20, 21, 22))
+    g = ttm.prefilter_volume(f)
+    for lo, hi in [((0, 0, 0), (5, 6, 7)), ((3, 4, 5), (20, 21, 22)), ((7, 2, 9), (15, 12, 19))]:
+        assert np.allclose(ttm.prefilter_box(f, lo, hi), g[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]])
+
+
+# ---------------------------------------------------------------- P-2 template
+def test_template_zero_normalised():
+    rng = np.random.default_rng(2)
+    for L, r in [(12, 5.0), (16, 7.0), (15, 6.5)]:
+        t = rng.standard_normal((L, L, L)) + 2.0
+        tn = ttm.normalize_template(t, r)
+        m = ttm.ball_mask(L, r)
+        assert abs(tn.sum()) < 1e-12
+        assert np.sum(tn * tn) == pytest.approx(1.0, abs=1e-12)
+        assert np.all(tn[m == 0] == 0)
+
+
+def test_lncc_bounded_by_one():
+    w = _tiny()
+    g = ttm.prefilter_volume(w.volume)
+    m = ttm.ball_mask(12, 5.0)
+    wm = ttm.local_normalization(g, m)
+    tn = ttm.normalize_template(w.template, 5.0)
+    c = ttm.brute_force_tm(g, wm, tn, synth.rotation_samples(1))
+    assert np.abs(c).max() <= 1.0 + 1e-12
+    # exact copy at the planted pose is found at the planted centre
+    R = w.rotations[0]
+    q = _mat2quat(R)
+    c0 = ttm.brute_force_tm(g, wm, tn, q[None])[0]
+    lo, _ = ttm.valid_range(32, 12)
+    z, y, x = w.centres[0]
+    assert np.unravel_index(np.argmax(c0), c0.shape) == (z - lo, y - lo, x - lo)
+
+
+def _mat2quat(R):
+    w = math.sqrt(max(0.0, 1 + R[0, 0] + R[1, 1] + R[2, 2])) / 2
+    x = math.copysign(math.sqrt(max(0.0, 1 + R[0, 0] - R[1, 1] - R[2, 2])) / 2, R[2, 1] - R[1, 2])
+    y = math.copysign(math.sqrt(max(0.0, 1 - R[0, 0] + R[1, 1] - R[2, 2])) / 2, R[0, 2] - R[2, 0])
+    z = math.copysign(math.sqrt(max(0.0, 1 - R[0, 0] - R[1, 1] + R[2, 2])) / 2, R[1, 0] - R[0, 1])
+    return np.array([w, x, y, z])
+
+
+# ---------------------------------------------------------------- P-12 correlation
+def test_correlate_valid_matches_scipy_direct():
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal((14, 13, 15))
+    k = rng.standard_normal((2, 5, 5, 5))
+    out = ttm.correlate_valid(g, k)
+    for i in range(2):
+        want = ss.correlate(g, k[i], mode="valid", method="direct")
+        assert np.allclose(out[i], want, atol=1e-12)
+
+
+def test_correlation_theorem_small():
+    # FFT correlation (numpy, FP64) equals the direct sums on the valid region
+    rng = np.random.default_rng(4)
+    D, L = 16, 6
+    g = rng.standard_normal((D, D, D))
+    k = rng.standard_normal((L, L, L))
+    kp = np.zeros((D, D, D))
+    kp[:L, :L, :L] = k
+    fft = np.real(np.fft.ifftn(np.fft.fftn(g) * np.conj(np.fft.fftn(kp))))
+    direct = ttm.correlate_valid(g, k[None])[0]
+    V = D - L + 1
+    assert np.allclose(fft[:V, :V, :V], direct, atol=1e-11)
+
+
+# ---------------------------------------------------------------- P-11 local variance
+def test_local_variance_textbook_and_invariances():
+    rng = np.random.default_rng(5)
+    D, L, r = 18, 8, 3.0
+    f = rng.standard_normal((D, D, D))
+    g = ttm.prefilter_volume(f)
+    m = ttm.ball_mask(L, r)
+    M = m.sum()
+    var = ttm.local_variance(g, m)
+    # textbook: M times the population variance of the window voxels inside the ball
+    win = np.lib.stride_tricks.sliding_window_view(g, (L, L, L))
+    sel = m.astype(bool)
+    for (z, y, x) in [(0, 0, 0), (3, 7, 2), (10, 10, 10)]:
+        vals = win[z, y, x][sel]
+        assert var[z, y, x] == pytest.approx(M * np.var(vals), rel=1e-10)
+    w1 = ttm.local_normalization(g, m)
+    w2 = ttm.local_normalization(ttm.prefilter_volume(f + 17.0), m)
+    assert np.allclose(w1, w2, rtol=1e-8)
+    c0, c1 = ttm.valid_range(D, L)
+    assert np.all(w1[:c0] == 0) and np.all(w1[c1 + 1:] == 0)
+    assert np.all(w1[c0:c1 + 1, c0:c1 + 1, c0:c1 + 1] > 0)
+    wc = ttm.local_normalization(ttm.prefilter_volume(np.full((D, D, D), 2.5)), m)
+    assert np.all(wc == 0)
+
+
+# ---------------------------------------------------------------- P-3 TTM vs TM identity
+@pytest.mark.parametrize("n,dprime", [(4, 3), (2, 3), (2, 4)])
+def test_field_equals_rotation_average_of_tm(n, dprime):
+    w = _tiny(seed=11, D=24, L=10, r=4.0, copies=1)
+    g = ttm.prefilter_volume(w.volume)
+    m = ttm.ball_mask(10, 4.0)
+    wm = ttm.local_normalization(g, m)
+    tn = ttm.normalize_template(w.template, 4.0)
+    Q = synth.rotation_samples(3)                    # 72 rotations
+    T = ttm.tensor_template(tn, Q, n, dprime)
+    C = ttm.tensor_field(g, wm, T)
+    c = ttm.brute_force_tm(g, wm, tn, Q)            # (Nq, V, V, V)
+    rng = np.random.default_rng(6)
+    V = np.stack([ttm.direction_of(q, dprime) for q in Q])
+    for _ in range(3):
+        u = rng.standard_normal(dprime)
+        lhs = np.tensordot(sym.weights(n, dprime) * sym.monomials(u, n), C, axes=(0, 0))
+        rhs = np.tensordot((V @ u) ** n, c, axes=(0, 0)) / len(Q)
+        assert np.allclose(lhs, rhs, atol=1e-12 * np.abs(rhs).max() + 1e-14)
+
+
+def test_trace_reduces_to_averaged_template_correlation():
+    # P-7: sum over pairwise traces <C, E> with E.v^n = |v|^n equals w (g * t_bar),
+    # t_bar the rotation-averaged template; n = 0 gives the same field directly.
+    w = _tiny(seed=12, D=22, L=10, r=4.0, copies=1)
+    g = ttm.prefilter_volume(w.volume)
+    m = ttm.ball_mask(10, 4.0)
+    wm = ttm.local_normalization(g, m)
+    tn = ttm.normalize_template(w.template, 4.0)
+    Q = synth.rotation_samples(2)
+    tbar = np.mean([rot.rotate_template(tn, rot.quat_to_matrix(q)) for q in Q], axis=0)
+    c = 5
+    want = ss.correlate(g, tbar, mode="valid", method="direct")
+    V = want.shape[0]
+    want = want * wm[c:c + V, c:c + V, c:c + V]
+    C0 = ttm.tensor_field(g, wm, ttm.tensor_template(tn, Q, 0))
+    assert np.allclose(C0[0], want, atol=1e-12)
+    n = 4
+    C4 = ttm.tensor_field(g, wm, ttm.tensor_template(tn, Q, n))
+    # trace: sum_{i,j} C_{iijj} (full tensor); built from the full expansion per voxel
+    tr = np.zeros(C4.shape[1:])
+    idx = sym.index_of(n, 3)
+    for i in range(3):
+        for j in range(3):
+            cnt = [0, 0, 0]
+            cnt[i] += 2
+            cnt[j] += 2
+            tr += C4[idx[tuple(cnt)]]
+    assert np.allclose(tr, want, atol=1e-12)
+
+
+# ---------------------------------------------------------------- P-5 equivariance
+def test_tensor_template_octahedral_equivariance():
+    L, r, n = 13, 4.0, 4
+    rng = np.random.default_rng(8)
+    t = ndi.gaussian_filter(rng.standard_normal((L, L, L)), 1.0)
+    tn = ttm.normalize_template(t, r)
+    Q = synth.rotation_samples(2)
+    T = ttm.tensor_template(tn, Q, n)
+    c = L // 2
+    idx = np.arange(L) - c
+    zz, yy, xx = np.meshgrid(idx, idx, idx, indexing="ij")
+    P = np.stack([xx, yy, zz], axis=-1)
+    for G in rot.cube_group()[:8]:
+        # T(c + G (p - c)) = G^{(x)n} . T(p)
+        dst = np.rint(P @ G.T).astype(int) + c
+        lhs = T[:, dst[..., 2], dst[..., 1], dst[..., 0]]
+        rhs = np.stack([sym.rotate(T[:, z, y, x], G, n) for z in range(L) for y in range(L)
+                        for x in range(L)], axis=1).reshape(T.shape)
+        assert np.allclose(lhs, rhs, atol=1e-12)
+
+
+def test_tensor_field_octahedral_equivariance():
+    D, L, r, n = 21, 9, 3.5, 4
+    rng = np.random.default_rng(9)
+    f = rng.standard_normal((D, D, D))
+    t = ndi.gaussian_filter(rng.standard_normal((L, L, L)), 1.0)
+    tn = ttm.normalize_template(t, r)
+    T = ttm.tensor_template(tn, synth.rotation_samples(2), n)
+    m = ttm.ball_mask(L, r)
+
+    def field(vol):
+        g = ttm.prefilter_volume(vol)
+        return ttm.tensor_field(g, ttm.local_normalization(g, m), T)
+
+    C = field(f)
+    cv = (D - 1) / 2
+    idx = np.arange(D) - cv
+    zz, yy, xx = np.meshgrid(idx, idx, idx, indexing="ij")
+    P = np.stack([xx, yy, zz], axis=-1)
+    c0 = L // 2
+    V = D - L + 1
+    for G in rot.cube_group()[1:6]:
+        # f'(x) = f(cv + G^T (x - cv)): an exact voxel permutation
+        src = np.rint(P @ G + cv).astype(int)
+        fr = f[src[..., 2], src[..., 1], src[..., 0]]
+        Cr = field(fr)
+        # C'(cv + G (x - cv)) = G^{(x)n} C(x) for valid x
+        for (z, y, x) in [(0, 0, 0), (3, 5, 7), (V - 1, 2, V - 1), (6, 6, 6)]:
+            p = np.array([x + c0, y + c0, z + c0]) - cv
+            q = np.rint(G @ p + cv).astype(int) - c0
+            got = Cr[:, q[2], q[1], q[0]]
+            want = sym.rotate(C[:, z, y, x], G, n)
+            assert np.allclose(got, want, atol=1e-12)
+
+
+# ---------------------------------------------------------------- P-8 .. P-10 orientation
+@pytest.mark.parametrize("n", [4, 6])
+def test_rank_one_recovers_direction(n):
+    rng = np.random.default_rng(10)
+    starts = synth.start_vectors().astype(np.float64)
+    for _ in range(5):
+        v = rng.standard_normal(3)
+        v /= np.linalg.norm(v)
+        lam0 = rng.uniform(0.5, 3.0)
+        C = lam0 * sym.monomials(v, n)
+        lam, u, *_ = ttm.orient_multistart(C, n, starts, tol=1e-14, max_iter=5000)
+        assert lam == pytest.approx(lam0, rel=1e-9)
+        assert ttm.angle_deg(u, v) < 1e-4
+        assert ttm.score(C, n) == pytest.approx(lam0)
+
+
+def test_degree_two_is_symmetric_eigenproblem():
+    rng = np.random.default_rng(11)
+    starts = synth.start_vectors().astype(np.float64)
+    for _ in range(10):
+        A = rng.standard_normal((3, 3))
+        A = A + A.T
+        C = np.array([A[0, 0], A[0, 1], A[0, 2], A[1, 1], A[1, 2], A[2, 2]])
+        assert np.allclose(sym.to_full(C, 2, 3), A)
+        ev, evec = np.linalg.eigh(A)
+        lam, u, *_ = ttm.orient_multistart(C, 2, starts, tol=1e-15, max_iter=20000)
+        assert lam == pytest.approx(ev[-1], rel=1e-9)
+        assert ttm.angle_deg(u, evec[:, -1]) < 1e-4
+
+
+@pytest.mark.parametrize("n", [4, 6])
+def test_sshopm_monotone_fixed_point_and_bracket(n):
+    rng = np.random.default_rng(12)
+    for _ in range(6):
+        C = rng.standard_normal(sym.n_components(n, 3))
+        cn = ttm.score(C, n)
+        Cu = C / cn
+        alpha = ttm.unfolding_shift(Cu, n, 3)
+        u = rng.standard_normal(3)
+        u /= np.linalg.norm(u)
+        lam_prev = -np.inf
+        for _ in range(3000):
+            g = sym.contract_n_minus_1(Cu, u, n)
+            lam = g @ u
+            assert lam >= lam_prev - 1e-13
+            lam_prev = lam
+            v = g + alpha * u
+            u = v / np.linalg.norm(v)
+        g = sym.contract_n_minus_1(Cu, u, n)
+        assert np.linalg.norm(g - (g @ u) * u) < 1e-8
+        lam, *_ = ttm.orient_multistart(C, n, synth.start_vectors(count=64).astype(np.float64),
+                                        tol=1e-13, max_iter=20000)
+        # spectral-norm bracket: ||C||_F / 2^{n-1} <= max|lambda| <= ||C||_F (Sec. 3.2)
+        lam_min, *_ = ttm.orient_multistart(-C, n, synth.start_vectors(count=64).astype(np.float64),
+                                            tol=1e-13, max_iter=20000)
+        spec = max(abs(lam), abs(lam_min))
+        assert cn / 2 ** (n - 1) <= spec + 1e-12
+        assert spec <= cn + 1e-12
+
+
+def test_orientation_rotates_with_tensor():
+    # P-4: lambda(G.C) = lambda(C) and u(G.C) = G u(C)
+    rng = np.random.default_rng(13)
+    n = 6
+    starts = synth.start_vectors(count=32).astype(np.float64)
+    for _ in range(4):
+        v = rng.standard_normal(3)
+        C = sym.monomials(v / np.linalg.norm(v), n) * 2 + 0.3 * rng.standard_normal(28)
+        G, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+        if np.linalg.det(G) < 0:
+            G[:, 0] *= -1
+        lam, u, *_ = ttm.orient_multistart(C, n, starts, tol=1e-14, max_iter=20000)
+        lam2, u2, *_ = ttm.orient_multistart(sym.rotate(C, G, n), n, starts, tol=1e-14, max_iter=20000)
+        assert lam2 == pytest.approx(lam, rel=1e-9)
+        assert ttm.angle_deg(u2, G @ u) < 1e-4
+
+
+def test_reference_maxima_agree_with_multistart():
+    rng = np.random.default_rng(14)
+    n = 6
+    for _ in range(3):
+        C = rng.standard_normal(28)
+        lam, u, *_ = ttm.orient_multistart(C, n, synth.start_vectors(count=64).astype(np.float64),
+                                           tol=1e-14, max_iter=20000)
+        lr, ur, l2 = ttm.reference_maxima(C, n, grid=4000)
+        assert lr >= lam - 1e-9
+        if lr - lam < 1e-9:
+            assert ttm.angle_deg(u, ur) < 1e-3
+
+
+# ---------------------------------------------------------------- P-13 peaks
+def _greedy_brute(vals, lin, shape, P, D):
+    order = sorted(range(len(vals)), key=lambda i: (-vals[i], lin[i]))
+    Y, X = shape[1], shape[2]
+    out = []
+    for i in order:
+        if len(out) >= P:
+            break
+        p = np.array([lin[i] // (Y * X), (lin[i] // X) % Y, lin[i] % X])
+        if all(np.sum((p - q) ** 2) >= D * D for q in out):
+            out.append(p)
+    return np.array(out)
+
+
+def test_find_peaks_brute_force_with_ties():
+    rng = np.random.default_rng(15)
+    s = np.round(rng.uniform(0, 1, (12, 13, 14)), 2)       # many exact ties
+    lo, hi = (2, 1, 3), (10, 11, 12)
+    pk, pv = ttm.find_peaks(s, lo, hi, 15, 3.0)
+    zz, yy, xx = np.meshgrid(range(lo[0], hi[0] + 1), range(lo[1], hi[1] + 1),
+                             range(lo[2], hi[2] + 1), indexing="ij")
+    lin = (zz * 13 * 14 + yy * 14 + xx).ravel()
+    vals = s[lo[0]:hi[0] + 1, lo[1]:hi[1] + 1, lo[2]:hi[2] + 1].ravel()
+    want = _greedy_brute(vals, lin, s.shape, 15, 3.0)
+    assert np.array_equal(pk, want)
+    assert np.array_equal(pv, s[pk[:, 0], pk[:, 1], pk[:, 2]])
+
+
+def test_planted_copies_recovered_at_high_snr():
+    w = synth.make_tomogram("p", (48, 48, 48), L=16, n_blobs=3, n_copies=4, min_sep=20,
+                            mask_radius=7.0, degree=4, seed=21, snr=None, wedge=False,
+                            copy_amplitude=20.0)
+    g = ttm.prefilter_volume(w.volume)
+    m = ttm.ball_mask(16, 7.0)
+    wm = ttm.local_normalization(g, m)
+    tn = ttm.normalize_template(w.template, 7.0)
+    T = ttm.tensor_template(tn, synth.rotation_samples(10), 4)
+    C = ttm.tensor_field(g, wm, T)
+    s = ttm.score(C, 4)
+    lo, hi = ttm.valid_range(48, 16)
+    smap = np.zeros(g.shape)
+    smap[lo:hi + 1, lo:hi + 1, lo:hi + 1] = s
+    pk, _ = ttm.find_peaks(smap, (lo,) * 3, (hi,) * 3, len(w.centres), 14.0)
+    # every planted copy has a peak within the mask radius (the Frobenius score is
+    # a position proxy that may shift by a few voxels, Sec. 5.1, Table 1)
+    for c in w.centres:
+        d = np.min(np.linalg.norm(pk - c, axis=1))
+        assert d <= 7.0
