@@ -1,0 +1,222 @@
+/*
+ * ttm.h -- C ABI of the MI355X (gfx950) tensorial template matching engine.
+ *
+ * Method: Martinez-Sanchez et al., "Tensorial template matching for fast
+ * cross-correlation with rotations and its application for tomography"
+ * (arXiv 2408.02398).  The library computes, on one GPU,
+ *
+ *   g      = h * f                         prefilter (Sec. 2, operator S)
+ *   w(x)   = 1/sqrt(local masked variance)  (Eq. norm_f)
+ *   C_a(x) = w(x) (g * T_a)(x)             tensor field, one FFT correlation
+ *                                          per independent component a (Eq. tcc, Alg. 2)
+ *   c(x)   = ||C(x)||_F                    position score (Sec. 3.2)
+ *   lambda(x), u(x)                        dominant eigenpair of C(x) by SS-HOPM (Sec. 3.1)
+ *   peaks                                  P best scores >= 2r apart (Sec. 3.4)
+ *
+ * and the one-time tensor template T_a (Eq. tt, Alg. 1) with its spectra.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Volumes are float32, layout [z][y][x] with x fastest; vectors are (x, y, z).
+ * - Degree n is even (Sec. 3.1: the orientation theorem needs even n), 0 <= n <= 8.
+ * - d' = 3: components are indexed by alpha = (ax, ay, az), |alpha| = n, in
+ *   graded-lex order (descending ax, then descending ay); K = (n+1)(n+2)/2.
+ *   Component alpha holds the full-tensor entry, so ||C||_F^2 = sum mu_a C_a^2
+ *   with mu_a = n!/(ax! ay! az!).  d' = 4 (quaternion form, K = binom(n+3,3))
+ *   is accepted by ttm_build_tensor / ttm_template_spectra / ttm_correlate and
+ *   the score; orientation extraction at d' = 4 returns TTM_EUNSUPPORTED.
+ * - Template: cubic L^3, centre c = L/2 (integer division) on every axis,
+ *   binary ball mask m(p) = [|p - c|^2 <= r^2].
+ * - Valid region of a volume of extent D along an axis: voxels x with
+ *   c <= x <= D - L + c (the whole template window lies inside the volume).
+ *   Full-size output maps are 0 outside it.
+ * - Every buffer argument is caller-owned.  Pointers documented "device"
+ *   must be device memory on the context's GPU; "host" pointers are read or
+ *   written synchronously before the call returns.
+ * - Calls enqueue on `stream` (a hipStream_t, NULL = the null stream) and
+ *   return; results are ready when the stream reaches them.  Only
+ *   ttm_find_peaks synchronises (it returns the peak count to the host).
+ * - Errors: argument checks are synchronous and return a negative
+ *   ttm_status without enqueuing anything; ttm_last_error() gives a message
+ *   (per calling thread).  Device faults surface as TTM_EDEVICE from the next
+ *   call that observes them.  Nothing aborts or throws across the ABI.
+ * - Workspace: entry points taking (ws, ws_bytes) need a device scratch
+ *   buffer of at least ttm_workspace_size(...) bytes, 256-byte aligned; they
+ *   return TTM_EWORKSPACE if it is smaller.  They allocate nothing.
+ * - Thread safety: one context per host thread; calls that share a workspace
+ *   must be ordered on one stream.
+ */
+#ifndef TTM_H_
+#define TTM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TTM_OK = 0,
+  TTM_EINVAL = -1,        /* bad argument (shape, degree, pointer, option) */
+  TTM_ENOMEM = -2,        /* context allocation failed                      */
+  TTM_EDEVICE = -3,       /* HIP runtime or device error                    */
+  TTM_EUNSUPPORTED = -4,  /* valid request outside what this build computes */
+  TTM_EWORKSPACE = -5     /* workspace smaller than ttm_workspace_size()    */
+} ttm_status;
+
+typedef enum { TTM_F32 = 0, TTM_BF16 = 1 } ttm_dtype;
+
+/* Operations for ttm_workspace_size. */
+typedef enum {
+  TTM_OP_SPECTRA = 1,
+  TTM_OP_NORMALIZE = 2,
+  TTM_OP_CORRELATE = 3,
+  TTM_OP_PEAKS = 4
+} ttm_op;
+
+typedef struct ttm_ctx ttm_ctx;
+
+/* Geometry and method constants. */
+typedef struct {
+  int32_t degree;       /* n, even, 0..8                                    */
+  int32_t dprime;       /* 3 (template-axis form) or 4 (quaternion form)    */
+  int32_t L;            /* template edge, 2..64                             */
+  float mask_radius;    /* r, 0 < r < L/2                                   */
+  float filter_a;       /* a of the filter 1 + a(z + 1/z - 2), 0 < a < 1/4  */
+  float eps_w;          /* w = 0 where var <= eps_w * M * mean(g^2)         */
+  float axis[3];        /* d' = 3: template axis a (unit), default (0,0,1)  */
+} ttm_desc;
+
+/* Context: owns the per-device FFT twiddle tables. */
+int ttm_create(ttm_ctx** out, int device);
+void ttm_destroy(ttm_ctx* ctx);
+const char* ttm_last_error(void);
+
+/* K = binom(n + d' - 1, n), or -1 for an unsupported (n, d'). */
+int ttm_n_components(int degree, int dprime);
+/* Complex (float2) elements of one half spectrum of an N^3 real array:
+ * N * (N/2 + 1) * N.  Spectra are stored [kz][kx][ky] (ky fastest). */
+size_t ttm_spectrum_elems(int fft_n);
+/* FFT edges this build supports (powers of two 32..512): 1 if supported. */
+int ttm_fft_supported(int fft_n);
+
+/* Workspace bytes for an operation at FFT edge fft_n on an nz x ny x nx
+ * volume (0 for an invalid request). */
+size_t ttm_workspace_size(const ttm_desc* desc, int op, int fft_n, int nz, int ny, int nx);
+
+/*
+ * Tensor template, Eq. tt and Alg. 1 (one-time per template).
+ *   t'    = m (S(t) - mu) / sigma_t        (Eq. norm_t; S(t) = m (h * t), zero padding)
+ *   T_a(p) = (1/nq) sum_q v_q^a t'(c + R(q)^T (p - c))
+ * with trilinear interpolation, zero outside the box, and v_q = R(q) axis
+ * (d' = 3) or v_q = q (d' = 4).
+ *   tmpl   device, L^3 float
+ *   quats  device, nq x 4 float unit quaternions (w, x, y, z), equal weights
+ *   T_out  device, K x L^3 float
+ *   tn_out device, L^3 float: receives t' (required; also the working copy)
+ * Errors: TTM_EINVAL for nq < 1, null pointers, bad desc.
+ */
+int ttm_build_tensor(ttm_ctx* ctx, const ttm_desc* desc, const float* tmpl,
+                     const float* quats, int nq, float* T_out, float* tn_out, void* stream);
+
+/*
+ * Spectra of the template fields for correlation at FFT edge fft_n (Alg. 2,
+ * F(T_i)): each field is placed at the origin of a zero N^3 array and
+ * forward-transformed (unnormalised e^{-i}).  Output: K component spectra
+ * followed by the spectrum of the mask m, (K + 1) x ttm_spectrum_elems(N)
+ * float2, device.  Requires L <= fft_n.
+ */
+int ttm_template_spectra(ttm_ctx* ctx, const ttm_desc* desc, const float* T, int fft_n,
+                         void* spec_out, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Prefilter and local normalisation (Sec. 2, Eq. norm_f).
+ *   g_out = h * vol (3-tap separable, border voxels replicated), full size
+ *   w_out(x) = 1/sqrt(var(x)) on the valid region, 0 elsewhere, where
+ *     var(x) = sum_p m(p) g(x+p-c)^2 - (sum_p m(p) g(x+p-c))^2 / M
+ *   evaluated by FFT correlation with the mask on fft_n^3 tiles, with the
+ *   data centred by the volume mean and the difference formed in FP64;
+ *   w = 0 where var <= eps_w * M * mean(g^2).
+ *   stats_out device double[2]: {mean(g), mean(g^2)} over the volume.
+ *   mask_spec: the mask spectrum from ttm_template_spectra at fft_n.
+ */
+int ttm_normalize(ttm_ctx* ctx, const ttm_desc* desc, const float* vol, int nz, int ny,
+                  int nx, const void* mask_spec, int fft_n, float* g_out, float* w_out,
+                  double* stats_out, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Tensor field on a box of the valid region (Eq. tcc, Alg. 2):
+ *   C_a(x) = w(x) * F^{-1}{ F(g) conj(F(T_a)) }(x)   for x in the box
+ * computed on fft_n^3 tiles (each tile yields (fft_n - L + 1)^3 outputs).
+ *   g, w     device, nz x ny x nx float (from ttm_normalize)
+ *   stats    device double[2] from ttm_normalize (the mean centres the FFT input)
+ *   spec     device, component spectra from ttm_template_spectra at fft_n
+ *   box_lo   host int32[3] (z, y, x) first voxel; box_size host int32[3];
+ *            the box must lie in the valid region
+ *   C_out    device, K x bz x by x bx, float32 or bfloat16 (out_dtype)
+ */
+int ttm_correlate(ttm_ctx* ctx, const ttm_desc* desc, const float* g, const float* w,
+                  int nz, int ny, int nx, const double* stats, const void* spec, int fft_n,
+                  const int32_t box_lo[3], const int32_t box_size[3], int out_dtype,
+                  void* C_out, void* ws, size_t ws_bytes, void* stream);
+
+/* ttm_extract mode bits. */
+#define TTM_SCORE 1       /* write c = ||C||_F                                   */
+#define TTM_ORIENT 2      /* write lambda and u (dominant eigenpair by SS-HOPM)  */
+#define TTM_START_MLP 4   /* seed SS-HOPM from the MLP; fall back to multistart  */
+
+typedef struct {
+  int32_t mode;            /* TTM_SCORE | TTM_ORIENT [| TTM_START_MLP]            */
+  int32_t n_starts;        /* number of fixed start vectors, 1..64                */
+  const float* starts;     /* device, n_starts x d' unit vectors                  */
+  const void* mlp;         /* device, packed MLP parameters (ttm_mlp_*), or NULL  */
+  float fallback_kappa;    /* learned start: fall back when lambda < kappa * c    */
+  int32_t max_iter;        /* SS-HOPM iteration cap per start                     */
+  float tol;               /* stop when |delta lambda| <= tol (on C / ||C||_F)    */
+} ttm_extract_opts;
+
+/*
+ * Per-voxel score and orientation (Sec. 3.1, 3.2) for a box of field values.
+ *   C         device, K x bz x by x bx (in_dtype float32 or bfloat16)
+ *   score     device map or NULL; lambda device map or NULL; dir device map
+ *             (3 floats per voxel, [z][y][x][3]) or NULL
+ *   out_lo    host int32[3]: where voxel (0,0,0) of the box lands in the maps
+ *   out_dims  host int32[3]: extent (z, y, x) of the output maps
+ *   n_fallback device int32 counter incremented per voxel whose learned start
+ *             fell back to the multistart search, or NULL
+ * Orientation: alpha = max(0, -lambda_min(U)) with U the square unfolding of
+ * C/||C||_F; SS-HOPM u <- (C u^{n-1} + alpha u)/||.|| from every start until
+ * |delta lambda| <= tol or max_iter; the largest lambda wins (first on ties);
+ * u is signed so its last non-zero coordinate is positive.
+ */
+int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
+                const int32_t box_size[3], const ttm_extract_opts* opts, float* score,
+                float* lambda, float* dir, const int32_t out_lo[3], const int32_t out_dims[3],
+                int32_t* n_fallback, void* stream);
+
+/*
+ * Find Peaks (Sec. 3.4): visit the voxels of [valid_lo, valid_hi] (inclusive,
+ * z y x) in descending score, ties by ascending linear index z*ny*nx + y*nx + x,
+ * and keep a voxel when its Euclidean distance to every kept peak is
+ * >= min_dist; stop after top_p peaks.
+ *   peaks_out device int32 top_p x 3 (z, y, x); vals_out device float top_p
+ *   n_found   host int32: number of peaks written (synchronises the stream)
+ */
+int ttm_find_peaks(ttm_ctx* ctx, const float* score, int nz, int ny, int nx,
+                   const int32_t valid_lo[3], const int32_t valid_hi[3], int top_p,
+                   float min_dist, int32_t* peaks_out, float* vals_out, int32_t* n_found,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* Stand-alone 3D FFT of an N^3 real array to its half spectrum and back
+ * (the transforms used inside ttm_correlate), for tests and benchmarks.
+ * Forward: spec = F(x) unnormalised; inverse: x = F^{-1}(spec) * scale.
+ * The inverse overwrites spec. */
+int ttm_fft3d_r2c(ttm_ctx* ctx, const float* x, int fft_n, void* spec, void* stream);
+int ttm_fft3d_c2r(ttm_ctx* ctx, void* spec, int fft_n, float scale, float* x, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TTM_H_ */

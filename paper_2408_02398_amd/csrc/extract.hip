@@ -1,0 +1,210 @@
+// extract.hip -- per-voxel score and orientation from the tensor field (gfx950).
+//
+// One lane per voxel; the K components of C(x) live in registers for the
+// whole search.  Components are read plane by plane ([K][box] layout), so
+// every load is coalesced across the wavefront.
+//
+// Score: c = ||C||_F = sqrt(sum_a mu_a C_a^2) (Sec. 3.2).
+// Orientation (Sec. 3.1): on C / c, the SS-HOPM shift is
+// alpha = max(0, -lambda_min(U)) with U the square matrix unfolding.  U is
+// zero off the symmetric (n/2)-tensors, where it equals
+// B[b, g] = sqrt(mu_b mu_g) C_{b+g}, so lambda_min(U) = min(0, lambda_min(B));
+// B (10 x 10 at n = 6) is diagonalised by cyclic Jacobi sweeps in registers.
+// Each lane then runs SS-HOPM from every start in turn, moving to its next
+// start as soon as the current one has converged, so lanes of a wavefront do
+// not wait for each other's slow starts.
+#include "internal.hpp"
+#include "sym_tables.hpp"
+
+namespace ttm {
+
+
+namespace {
+
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) {
+  return __uint_as_float(((unsigned int)h) << 16);
+}
+
+__host__ __device__ constexpr int multinom3(int a, int b, int c) {
+  return factorial(a + b + c) / (factorial(a) * factorial(b) * factorial(c));
+}
+
+// g = C u^{n-1}: g_i = sum_{|beta| = n-1} mu_beta C_{beta + e_i} u^beta.
+template <int N>
+__device__ __forceinline__ void contract(const float (&c)[ncomp3(N)], float x, float y, float z,
+                                         float& g0, float& g1, float& g2) {
+  float px[N], py[N], pz[N];
+  px[0] = py[0] = pz[0] = 1.0f;
+#pragma unroll
+  for (int k = 1; k < N; ++k) {
+    px[k] = px[k - 1] * x;
+    py[k] = py[k - 1] * y;
+    pz[k] = pz[k - 1] * z;
+  }
+  g0 = g1 = g2 = 0.0f;
+#pragma unroll
+  for (int a = N - 1; a >= 0; --a) {
+#pragma unroll
+    for (int b = N - 1 - a; b >= 0; --b) {
+      const int cc = N - 1 - a - b;
+      const float m = (float)multinom3(a, b, cc) * (px[a] * (py[b] * pz[cc]));
+      g0 = fmaf(m, c[comp_index3(N, a + 1, b)], g0);
+      g1 = fmaf(m, c[comp_index3(N, a, b + 1)], g1);
+      g2 = fmaf(m, c[comp_index3(N, a, b)], g2);
+    }
+  }
+}
+
+// Upper-triangle storage index of (p, q), p <= q, in an M x M matrix.
+__host__ __device__ constexpr int tri(int M, int p, int q) {
+  return p <= q ? p * M - p * (p - 1) / 2 + (q - p) : q * M - q * (q - 1) / 2 + (p - q);
+}
+
+// lambda_min of B[b, g] = sqrt(mu_b mu_g) c_{b+g} over |b| = |g| = n/2.
+template <int N>
+__device__ __forceinline__ float unfolding_lambda_min(const float (&c)[ncomp3(N)]) {
+  constexpr int H = N / 2;
+  constexpr int M = ncomp3(H);
+  constexpr Sym3<H> hs{};
+  float A[M * (M + 1) / 2];
+#pragma unroll
+  for (int p = 0; p < M; ++p) {
+#pragma unroll
+    for (int q = p; q < M; ++q) {
+      const float s = sqrtf(hs.mu[p] * hs.mu[q]);
+      A[tri(M, p, q)] = s * c[comp_index3(N, hs.ax[p] + hs.ax[q], hs.ay[p] + hs.ay[q])];
+    }
+  }
+  for (int sweep = 0; sweep < 6; ++sweep) {
+#pragma unroll
+    for (int p = 0; p < M - 1; ++p) {
+#pragma unroll
+      for (int q = p + 1; q < M; ++q) {
+        const float apq = A[tri(M, p, q)];
+        const float app = A[tri(M, p, p)], aqq = A[tri(M, q, q)];
+        // theta = (aqq - app) / (2 apq); apq = 0 gives t = 0 (no rotation)
+        const float theta = 0.5f * (aqq - app) / apq;
+        const float t = copysignf(1.0f / (fabsf(theta) + sqrtf(fmaf(theta, theta, 1.0f))), theta);
+        const float tt = (apq == 0.0f || !(fabsf(theta) < 1e30f)) ? 0.0f : t;
+        const float cs = 1.0f / sqrtf(fmaf(tt, tt, 1.0f));
+        const float sn = tt * cs;
+        A[tri(M, p, p)] = app - tt * apq;
+        A[tri(M, q, q)] = aqq + tt * apq;
+        A[tri(M, p, q)] = 0.0f;
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+          if (r == p || r == q) continue;
+          const float arp = A[tri(M, r, p)], arq = A[tri(M, r, q)];
+          A[tri(M, r, p)] = cs * arp - sn * arq;
+          A[tri(M, r, q)] = sn * arp + cs * arq;
+        }
+      }
+    }
+  }
+  float lmin = A[tri(M, 0, 0)];
+#pragma unroll
+  for (int p = 1; p < M; ++p) lmin = fminf(lmin, A[tri(M, p, p)]);
+  return lmin;
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void k_extract(ExtractArgs a) {
+  constexpr int K = ncomp3(N);
+  constexpr Sym3<N> sy{};
+  __shared__ float st[64 * 3];
+  for (int i = threadIdx.x; i < a.n_starts * 3; i += blockDim.x) st[i] = a.starts[i];
+  __syncthreads();
+  const size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= a.plane) return;
+  float c[K];
+  if (a.in_dtype == 1) {
+    const unsigned short* p = reinterpret_cast<const unsigned short*>(a.C);
+#pragma unroll
+    for (int k = 0; k < K; ++k) c[k] = bf16_to_f32(p[k * a.plane + v]);
+  } else {
+    const float* p = reinterpret_cast<const float*>(a.C);
+#pragma unroll
+    for (int k = 0; k < K; ++k) c[k] = p[k * a.plane + v];
+  }
+  float f2 = 0.0f;
+#pragma unroll
+  for (int k = 0; k < K; ++k) f2 = fmaf(sy.mu[k] * c[k], c[k], f2);
+  const float cn = sqrtf(f2);
+  const int bx = a.bx, by = a.by;
+  const int vx = (int)(v % bx), vy = (int)((v / bx) % by), vz = (int)(v / ((size_t)bx * by));
+  const size_t o = ((size_t)(a.oz + vz) * a.dy + (a.oy + vy)) * a.dx + (a.ox + vx);
+  if (a.mode & 1) a.score[o] = cn;
+  if constexpr (N >= 2) {
+    if (a.mode & 2) {
+      float lam_best = 0.0f, bx0 = 0.0f, by0 = 0.0f, bz0 = 0.0f;
+      if (cn > 0.0f) {
+        const float inv = 1.0f / cn;
+#pragma unroll
+        for (int k = 0; k < K; ++k) c[k] *= inv;
+        const float alpha = fmaxf(0.0f, -unfolding_lambda_min<N>(c));
+        lam_best = -INFINITY;
+        int s = 0, it = 0;
+        float ux = st[0], uy = st[1], uz = st[2];
+        float g0, g1, g2;
+        {
+          const float r = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
+          ux *= r; uy *= r; uz *= r;
+        }
+        contract<N>(c, ux, uy, uz, g0, g1, g2);
+        float lam = g0 * ux + g1 * uy + g2 * uz;
+        while (true) {
+          float wx = fmaf(alpha, ux, g0), wy = fmaf(alpha, uy, g1), wz = fmaf(alpha, uz, g2);
+          const float r = 1.0f / sqrtf(wx * wx + wy * wy + wz * wz);
+          ux = wx * r; uy = wy * r; uz = wz * r;
+          contract<N>(c, ux, uy, uz, g0, g1, g2);
+          const float lam_new = g0 * ux + g1 * uy + g2 * uz;
+          ++it;
+          const bool done = fabsf(lam_new - lam) <= a.tol || it >= a.max_iter;
+          lam = lam_new;
+          if (done) {
+            if (lam > lam_best) {
+              lam_best = lam;
+              bx0 = ux; by0 = uy; bz0 = uz;
+            }
+            if (++s >= a.n_starts) break;
+            ux = st[3 * s]; uy = st[3 * s + 1]; uz = st[3 * s + 2];
+            const float rr = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
+            ux *= rr; uy *= rr; uz *= rr;
+            contract<N>(c, ux, uy, uz, g0, g1, g2);
+            lam = g0 * ux + g1 * uy + g2 * uz;
+            it = 0;
+          }
+        }
+        // u and -u are the same answer: make the last non-zero coordinate positive
+        const float sg = (bz0 != 0.0f) ? bz0 : ((by0 != 0.0f) ? by0 : bx0);
+        if (sg < 0.0f) {
+          bx0 = -bx0; by0 = -by0; bz0 = -bz0;
+        }
+        lam_best *= cn;
+      }
+      if (a.lam) a.lam[o] = lam_best;
+      if (a.dir) {
+        a.dir[3 * o + 0] = bx0;
+        a.dir[3 * o + 1] = by0;
+        a.dir[3 * o + 2] = bz0;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+int launch_extract(int degree, const ExtractArgs& a, hipStream_t s) {
+  const unsigned nb = (unsigned)((a.plane + 255) / 256);
+  switch (degree) {
+    case 0: hipLaunchKernelGGL(k_extract<0>, dim3(nb), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_extract<2>, dim3(nb), dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(k_extract<4>, dim3(nb), dim3(256), 0, s, a); break;
+    case 6: hipLaunchKernelGGL(k_extract<6>, dim3(nb), dim3(256), 0, s, a); break;
+    default: set_error("ttm_extract: degree %d not built for d'=3 extraction", degree); return -4;
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : hip_status(e, "extract launch");
+}
+
+}  // namespace ttm

@@ -1,0 +1,332 @@
+// fft.hip -- batched 3D real FFTs for the tensor-field correlations (gfx950).
+//
+// Spectrum layout: [kz][kx][ky], ky fastest, kx in 0..N/2 (the R2C half).
+// Forward = X pass (two real rows packed as one complex row, R2C split on
+// the way out, transposed store so ky becomes contiguous), Y pass (contiguous
+// rows), Z pass (strided columns, 16 columns per workgroup so every global
+// access is a 128-byte segment).  Inverse = Z pass with the spectral product
+// fused in (one read of G per tile for all components), Y pass, X pass with
+// the C2R merge, 1/N^3 scale, weight map, crop and dtype conversion fused
+// into the store.
+#include "internal.hpp"
+
+namespace ttm {
+
+namespace {
+
+constexpr int kRowsX = 16;  // real rows per workgroup in the X passes (8 packed pairs)
+
+__device__ __forceinline__ float load_src(const RealSrc& s, int b, int z, int y, int x) {
+  const int gz = s.oz + z, gy = s.oy + y, gx = s.ox + x;
+  if (gz < 0 || gz >= s.dz || gy < 0 || gy >= s.dy || gx < 0 || gx >= s.dx) return 0.0f;
+  float v = s.p[b * s.batch_stride + ((size_t)gz * s.dy + gy) * s.dx + gx];
+  if (s.center) v = (float)((double)v - s.center[0]);
+  if (s.square) v = v * v;
+  return v;
+}
+
+__device__ __forceinline__ unsigned short f32_to_bf16(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+  return (unsigned short)(u >> 16);
+}
+
+// ---------------------------------------------------------------- X forward
+template <int N>
+__global__ __launch_bounds__(8 * Plan<N>::T) void k_r2c_x(RealSrc src, cf* __restrict__ spec,
+                                                          size_t spec_stride,
+                                                          const cf* __restrict__ tw) {
+  constexpr int T = Plan<N>::T, E = N / T, NP = kRowsX / 2, NH = N / 2 + 1;
+  constexpr int S = lds_stride<N>();
+  constexpr int RS = N + 8;  // padded real row
+  constexpr int BYTES_A = kRowsX * RS * 4, BYTES_B = NP * S * 8;
+  __shared__ __align__(16) unsigned char smem[BYTES_A > BYTES_B ? BYTES_A : BYTES_B];
+  float* rows = reinterpret_cast<float*>(smem);
+  cf* xl = reinterpret_cast<cf*>(smem);
+  const int tid = threadIdx.x;
+  const int y0 = blockIdx.x * kRowsX, z = blockIdx.y, b = blockIdx.z;
+  for (int e = tid; e < kRowsX * N; e += NP * T) {
+    const int r = e / N, x = e % N;
+    rows[r * RS + x] = load_src(src, b, z, y0 + r, x);
+  }
+  __syncthreads();
+  const int p = tid / T, t = tid % T;
+  cf v[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int n = t + T * j;
+    v[j] = cf{rows[(2 * p) * RS + n], rows[(2 * p + 1) * RS + n]};
+  }
+  __syncthreads();  // rows and xl share memory
+  fft_1d<N, false>(v, xl + p * S, tw, t);
+#pragma unroll
+  for (int j = 0; j < E; ++j) xl[p * S + lds_idx(t + T * j)] = v[j];
+  __syncthreads();
+  cf* out = spec + b * spec_stride + (size_t)z * NH * N + y0;
+  for (int e = tid; e < NH * kRowsX; e += NP * T) {
+    const int r = e % kRowsX, kx = e / kRowsX, pp = r >> 1;
+    const cf zk = xl[pp * S + lds_idx(kx)];
+    const cf zn = cconj(xl[pp * S + lds_idx((N - kx) & (N - 1))]);
+    cf o;
+    if ((r & 1) == 0) {
+      o = cscale(cadd(zk, zn), 0.5f);              // (Z[k] + conj Z[N-k]) / 2
+    } else {
+      const cf d = csub(zk, zn);                   // (Z[k] - conj Z[N-k]) / 2i
+      o = cf{0.5f * d.y, -0.5f * d.x};
+    }
+    out[(size_t)kx * N + r] = o;
+  }
+}
+
+// ---------------------------------------------------------------- Y (rows)
+template <int N, bool INV>
+__global__ __launch_bounds__((128 / Plan<N>::T > 0 ? 128 / Plan<N>::T : 1) * Plan<N>::T) void
+k_c2c_rows(cf* __restrict__ data, size_t batch_stride, int row_limit, const cf* __restrict__ tw) {
+  constexpr int T = Plan<N>::T, E = N / T, RB = (128 / T > 0 ? 128 / T : 1);
+  constexpr int S = lds_stride<N>();
+  __shared__ cf xl[RB * S];
+  const int tid = threadIdx.x;
+  const int r = tid / T, t = tid % T;
+  const int row = blockIdx.x * RB + r;
+  // rows are (z, kx): z = row / (N/2+1); rows with z >= row_limit are not needed
+  if ((int)(blockIdx.x * RB) / (N / 2 + 1) >= row_limit) return;  // uniform per workgroup
+  cf* base = data + blockIdx.y * batch_stride + (size_t)row * N;
+  cf v[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) v[j] = base[t + T * j];
+  fft_1d<N, INV>(v, xl + r * S, tw, t);
+#pragma unroll
+  for (int j = 0; j < E; ++j) base[t + T * j] = v[j];
+}
+
+// ---------------------------------------------------------------- Z (columns)
+template <int N> struct ColBlock { static constexpr int CB = (N >= 512 ? 8 : 16); };
+
+template <int N, bool INV>
+__global__ __launch_bounds__(ColBlock<N>::CB * Plan<N>::T) void k_c2c_cols(
+    cf* __restrict__ data, size_t batch_stride, const cf* __restrict__ tw) {
+  constexpr int T = Plan<N>::T, E = N / T, CB = ColBlock<N>::CB, NC = (N / 2 + 1) * N;
+  constexpr int S = lds_stride<N>();
+  __shared__ cf xl[CB * S];
+  const int tid = threadIdx.x;
+  const int c = tid % CB, t = tid / CB;
+  const int col = blockIdx.x * CB + c;
+  cf* base = data + blockIdx.y * batch_stride + col;
+  cf v[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) v[j] = base[(size_t)(t + T * j) * NC];
+  fft_1d<N, INV>(v, xl + c * S, tw, t);
+#pragma unroll
+  for (int j = 0; j < E; ++j) base[(size_t)(t + T * j) * NC] = v[j];
+}
+
+// Inverse Z pass with the spectral product: out_a = Z^-1( G conj(S_a) ).
+template <int N>
+__global__ __launch_bounds__(ColBlock<N>::CB * Plan<N>::T) void k_zinv_mul(
+    const cf* __restrict__ G, const cf* __restrict__ Sp, size_t s_stride, int A,
+    const double* __restrict__ center, cf* __restrict__ out, size_t out_stride, int z_limit,
+    const cf* __restrict__ tw) {
+  constexpr int T = Plan<N>::T, E = N / T, CB = ColBlock<N>::CB, NC = (N / 2 + 1) * N;
+  constexpr int S = lds_stride<N>();
+  __shared__ cf xl[CB * S];
+  const int tid = threadIdx.x;
+  const int c = tid % CB, t = tid / CB;
+  const int col = blockIdx.x * CB + c;
+  cf g[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) g[j] = G[(size_t)(t + T * j) * NC + col];
+  // DC bin (kz = kx = ky = 0) is element j = 0 of thread t = 0 in column 0:
+  // restore the mean removed before the forward transform.
+  const bool dc = (col == 0 && t == 0);
+  const float dc_add = (dc && center) ? (float)(center[0] * (double)N * (double)N * (double)N) : 0.0f;
+  for (int a = 0; a < A; ++a) {
+    cf v[E];
+    const cf* sa = Sp ? Sp + a * s_stride + col : nullptr;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      if (sa) {
+        const cf s = sa[(size_t)(t + T * j) * NC];
+        cf gg = g[j];
+        if (j == 0 && dc) gg.x += dc_add;
+        v[j] = cmulc(gg, s);
+      } else {
+        v[j] = g[j];
+      }
+    }
+    fft_1d<N, true>(v, xl + c * S, tw, t);
+    cf* o = out + a * out_stride + col;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int zz = t + T * j;
+      if (zz < z_limit) o[(size_t)zz * NC] = v[j];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- X inverse
+template <int N>
+__global__ __launch_bounds__(8 * Plan<N>::T) void k_c2r_x(const cf* __restrict__ spec,
+                                                          size_t spec_stride, RealDst dst,
+                                                          const cf* __restrict__ tw) {
+  constexpr int T = Plan<N>::T, E = N / T, NP = kRowsX / 2, NH = N / 2 + 1;
+  constexpr int S = lds_stride<N>();
+  constexpr int SPS = NH + 1;  // padded spectrum row
+  constexpr int BYTES_A = kRowsX * SPS * 8, BYTES_B = NP * S * 8, BYTES_C = kRowsX * (N + 4) * 4;
+  constexpr int BYTES = BYTES_A > BYTES_B ? (BYTES_A > BYTES_C ? BYTES_A : BYTES_C)
+                                          : (BYTES_B > BYTES_C ? BYTES_B : BYTES_C);
+  __shared__ __align__(16) unsigned char smem[BYTES];
+  cf* sp = reinterpret_cast<cf*>(smem);
+  cf* xl = reinterpret_cast<cf*>(smem);
+  float* orow = reinterpret_cast<float*>(smem);
+  const int tid = threadIdx.x;
+  const int y0 = blockIdx.x * kRowsX, z = blockIdx.y, b = blockIdx.z;
+  if (z >= dst.sz || y0 >= dst.sy) return;  // uniform: nothing of this block is kept
+  const cf* in = spec + b * spec_stride + (size_t)z * NH * N + y0;
+  for (int e = tid; e < NH * kRowsX; e += NP * T) {
+    const int r = e % kRowsX, kx = e / kRowsX;
+    sp[r * SPS + kx] = in[(size_t)kx * N + r];
+  }
+  __syncthreads();
+  const int p = tid / T, t = tid % T;
+  cf v[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int n = t + T * j;
+    cf a, bb;
+    if (n <= N / 2) {
+      a = sp[(2 * p) * SPS + n];
+      bb = sp[(2 * p + 1) * SPS + n];
+      if (n == 0 || n == N / 2) {  // spectra of real rows: these bins are real
+        a.y = 0.0f;
+        bb.y = 0.0f;
+      }
+    } else {
+      a = cconj(sp[(2 * p) * SPS + (N - n)]);
+      bb = cconj(sp[(2 * p + 1) * SPS + (N - n)]);
+    }
+    v[j] = cf{a.x - bb.y, a.y + bb.x};  // A + iB
+  }
+  __syncthreads();
+  fft_1d<N, true>(v, xl + p * S, tw, t);
+  constexpr int RS = N + 4;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int n = t + T * j;
+    orow[(2 * p) * RS + n] = v[j].x;
+    orow[(2 * p + 1) * RS + n] = v[j].y;
+  }
+  __syncthreads();
+  const int nrows = min(kRowsX, dst.sy - y0);
+  const int sx = dst.sx;
+  for (int e = tid; e < nrows * sx; e += NP * T) {
+    const int r = e / sx, x = e % sx;
+    float val = orow[r * RS + x] * dst.scale;
+    if (dst.w) {
+      val *= dst.w[((size_t)(dst.woz + z) * dst.wy + (dst.woy + y0 + r)) * dst.wx + dst.wox + x];
+    }
+    const size_t o = b * dst.batch_stride +
+                     ((size_t)(dst.vz0 + z) * dst.by + (dst.vy0 + y0 + r)) * dst.bx + dst.vx0 + x;
+    if (dst.dtype == 1) {
+      reinterpret_cast<unsigned short*>(dst.p)[o] = f32_to_bf16(val);
+    } else {
+      reinterpret_cast<float*>(dst.p)[o] = val;
+    }
+  }
+}
+
+__global__ void k_twiddles(cf* tw_all) {
+  const int sizes[5] = {32, 64, 128, 256, 512};
+  int off = 0;
+  for (int s = 0; s < 5; ++s) {
+    const int N = sizes[s];
+    for (int e = threadIdx.x; e < N; e += blockDim.x) {
+      double sv, cv;
+      sincospi(-2.0 * (double)e / (double)N, &sv, &cv);
+      tw_all[off + e] = cf{(float)cv, (float)sv};
+    }
+    off += N;
+  }
+}
+
+template <int N>
+int forward_n(const RealSrc& src, int batch, cf* spec, size_t spec_stride, const cf* tw,
+              hipStream_t s) {
+  constexpr int T = Plan<N>::T;
+  hipLaunchKernelGGL(k_r2c_x<N>, dim3(N / kRowsX, N, batch), dim3(8 * T), 0, s, src, spec,
+                     spec_stride, tw);
+  constexpr int RB = (128 / T > 0 ? 128 / T : 1);
+  constexpr int NROWS = N * (N / 2 + 1);
+  hipLaunchKernelGGL((k_c2c_rows<N, false>), dim3(NROWS / RB, batch), dim3(RB * T), 0, s, spec,
+                     spec_stride, N, tw);
+  constexpr int CB = ColBlock<N>::CB;
+  hipLaunchKernelGGL((k_c2c_cols<N, false>), dim3(NROWS / CB, batch), dim3(CB * T), 0, s, spec,
+                     spec_stride, tw);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : hip_status(e, "fft forward launch");
+}
+
+template <int N>
+int inverse_n(const cf* G, const cf* Sp, size_t s_stride, int A, const double* center, cf* work,
+              size_t work_stride, const RealDst& dst, const cf* tw, hipStream_t s) {
+  constexpr int T = Plan<N>::T;
+  constexpr int NROWS = N * (N / 2 + 1);
+  constexpr int CB = ColBlock<N>::CB;
+  const int zlim = dst.sz;
+  hipLaunchKernelGGL(k_zinv_mul<N>, dim3(NROWS / CB, 1), dim3(CB * T), 0, s, G, Sp, s_stride, A,
+                     center, work, work_stride, zlim, tw);
+  constexpr int RB = (128 / T > 0 ? 128 / T : 1);
+  hipLaunchKernelGGL((k_c2c_rows<N, true>), dim3(NROWS / RB, A), dim3(RB * T), 0, s, work,
+                     work_stride, zlim, tw);
+  hipLaunchKernelGGL(k_c2r_x<N>, dim3(N / kRowsX, N, A), dim3(8 * T), 0, s, work, work_stride,
+                     dst, tw);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : hip_status(e, "fft inverse launch");
+}
+
+}  // namespace
+
+int twiddle_offset(int N) {
+  switch (N) {
+    case 32: return 0;
+    case 64: return 32;
+    case 128: return 96;
+    case 256: return 224;
+    case 512: return 480;
+    default: return -1;
+  }
+}
+
+int init_twiddles(cf* tw_all, hipStream_t s) {
+  hipLaunchKernelGGL(k_twiddles, dim3(1), dim3(256), 0, s, tw_all);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : hip_status(e, "twiddle init");
+}
+
+int fft3d_forward(int N, const RealSrc& src, int batch, cf* spec, size_t spec_stride,
+                  const cf* tw_all, hipStream_t s) {
+  const cf* tw = tw_all + twiddle_offset(N);
+  switch (N) {
+    case 32: return forward_n<32>(src, batch, spec, spec_stride, tw, s);
+    case 64: return forward_n<64>(src, batch, spec, spec_stride, tw, s);
+    case 128: return forward_n<128>(src, batch, spec, spec_stride, tw, s);
+    case 256: return forward_n<256>(src, batch, spec, spec_stride, tw, s);
+    case 512: return forward_n<512>(src, batch, spec, spec_stride, tw, s);
+    default: set_error("unsupported FFT edge %d", N); return -4;
+  }
+}
+
+int fft3d_inverse_mul(int N, const cf* G, const cf* Sp, size_t s_stride, int A,
+                      const double* center, cf* work, size_t work_stride, const RealDst& dst,
+                      const cf* tw_all, hipStream_t s) {
+  const cf* tw = tw_all + twiddle_offset(N);
+  switch (N) {
+    case 32: return inverse_n<32>(G, Sp, s_stride, A, center, work, work_stride, dst, tw, s);
+    case 64: return inverse_n<64>(G, Sp, s_stride, A, center, work, work_stride, dst, tw, s);
+    case 128: return inverse_n<128>(G, Sp, s_stride, A, center, work, work_stride, dst, tw, s);
+    case 256: return inverse_n<256>(G, Sp, s_stride, A, center, work, work_stride, dst, tw, s);
+    case 512: return inverse_n<512>(G, Sp, s_stride, A, center, work, work_stride, dst, tw, s);
+    default: set_error("unsupported FFT edge %d", N); return -4;
+  }
+}
+
+}  // namespace ttm

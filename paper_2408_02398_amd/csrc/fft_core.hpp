@@ -1,0 +1,235 @@
+// fft_core.hpp -- in-register / LDS building blocks of the batched 1D FFTs
+// that make up the 3D transforms (gfx950, wave64).
+//
+// A length-N transform is spread over T threads; thread t owns the E = N/T
+// elements with index t + T*j (j < E), before and after the transform.  The
+// transform runs as a sequence of Stockham radix-R stages (N = R0*R1[*R2]):
+// butterfly i = t + T*b reads x[i + m*N/R] (m < R), twiddles by
+// W_{P*R}^{(i mod P)*m}, applies a radix-R DFT in registers and writes
+// x'[(i - i mod P)*R + i mod P + m*P], P being the product of the earlier
+// radices.  The first stage reads from and the last stage writes to the
+// registers directly; the stages in between exchange through LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ttm {
+
+struct cf {  // complex float, 8-byte aligned like float2
+  float x, y;
+};
+
+__device__ __forceinline__ cf cmake(float a, float b) { return cf{a, b}; }
+__device__ __forceinline__ cf cadd(cf a, cf b) { return cf{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ cf csub(cf a, cf b) { return cf{a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ cf cmul(cf a, cf b) {
+  return cf{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+__device__ __forceinline__ cf cmulc(cf a, cf b) {
+  return cf{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+__device__ __forceinline__ cf cconj(cf a) { return cf{a.x, -a.y}; }
+__device__ __forceinline__ cf cscale(cf a, float s) { return cf{a.x * s, a.y * s}; }
+// multiply by -i (forward) or +i (inverse) depending on INV
+template <bool INV>
+__device__ __forceinline__ cf rot_quarter(cf a) {
+  return INV ? cf{-a.y, a.x} : cf{a.y, -a.x};
+}
+
+// cos(2 pi k / 16), k = 0..15
+__device__ constexpr float kCos16[16] = {
+    1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
+    0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
+    -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f,
+    0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f};
+
+// a * W_16^e with W = exp(-2 pi i / 16) (forward) or its conjugate (inverse);
+// e is a compile-time constant so trivial factors cost nothing.
+template <int E16, bool INV>
+__device__ __forceinline__ cf twiddle16(cf a) {
+  constexpr int e = ((E16 % 16) + 16) % 16;
+  if constexpr (e == 0) {
+    return a;
+  } else if constexpr (e == 4) {
+    return rot_quarter<INV>(a);
+  } else if constexpr (e == 8) {
+    return cf{-a.x, -a.y};
+  } else if constexpr (e == 12) {
+    return rot_quarter<!INV>(a);
+  } else {
+    const float c = kCos16[e];
+    const float s = INV ? kCos16[(e + 12) % 16] : -kCos16[(e + 12) % 16];  // +-sin(2 pi e/16)
+    return cf{a.x * c - a.y * s, a.x * s + a.y * c};
+  }
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft2(cf& a0, cf& a1) {
+  cf t = a0;
+  a0 = cadd(t, a1);
+  a1 = csub(t, a1);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(cf& a0, cf& a1, cf& a2, cf& a3) {
+  cf t0 = cadd(a0, a2), t1 = csub(a0, a2);
+  cf t2 = cadd(a1, a3), t3 = rot_quarter<INV>(csub(a1, a3));
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+
+// Radix-R DFT of a[0..R-1] in place, natural order in and out, R in {2,4,8,16}.
+// R = 8 and 16 use one four-step split: n = n1 + R1 n2, k = R2 k1 + k2.
+template <int R, bool INV>
+__device__ __forceinline__ void dft(cf* a) {
+  if constexpr (R == 1) {
+  } else if constexpr (R == 2) {
+    dft2<INV>(a[0], a[1]);
+  } else if constexpr (R == 4) {
+    dft4<INV>(a[0], a[1], a[2], a[3]);
+  } else if constexpr (R == 8) {
+    // R1 = 2, R2 = 4
+    dft4<INV>(a[0], a[2], a[4], a[6]);                 // n1 = 0
+    dft4<INV>(a[1], a[3], a[5], a[7]);                 // n1 = 1
+    // Y[1][k2] *= W_8^{k2}
+    a[3] = twiddle16<2, INV>(a[3]);
+    a[5] = twiddle16<4, INV>(a[5]);
+    a[7] = twiddle16<6, INV>(a[7]);
+    cf y[8] = {a[0], a[2], a[4], a[6], a[1], a[3], a[5], a[7]};  // y[n1*4 + k2]
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+      cf u0 = y[k2], u1 = y[4 + k2];
+      dft2<INV>(u0, u1);
+      a[k2] = u0;       // k = 4*0 + k2
+      a[4 + k2] = u1;   // k = 4*1 + k2
+    }
+  } else if constexpr (R == 16) {
+    // R1 = 4, R2 = 4
+    cf y[16];
+#pragma unroll
+    for (int n1 = 0; n1 < 4; ++n1) {
+      cf b0 = a[n1], b1 = a[n1 + 4], b2 = a[n1 + 8], b3 = a[n1 + 12];
+      dft4<INV>(b0, b1, b2, b3);
+      y[n1 * 4 + 0] = b0;
+      y[n1 * 4 + 1] = b1;
+      y[n1 * 4 + 2] = b2;
+      y[n1 * 4 + 3] = b3;
+    }
+    y[5] = twiddle16<1, INV>(y[5]);
+    y[6] = twiddle16<2, INV>(y[6]);
+    y[7] = twiddle16<3, INV>(y[7]);
+    y[9] = twiddle16<2, INV>(y[9]);
+    y[10] = twiddle16<4, INV>(y[10]);
+    y[11] = twiddle16<6, INV>(y[11]);
+    y[13] = twiddle16<3, INV>(y[13]);
+    y[14] = twiddle16<6, INV>(y[14]);
+    y[15] = twiddle16<9, INV>(y[15]);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+      cf b0 = y[k2], b1 = y[4 + k2], b2 = y[8 + k2], b3 = y[12 + k2];
+      dft4<INV>(b0, b1, b2, b3);
+      a[k2] = b0;
+      a[4 + k2] = b1;
+      a[8 + k2] = b2;
+      a[12 + k2] = b3;
+    }
+  } else {
+    static_assert(R == 2, "unsupported radix");
+  }
+}
+
+// Plans: threads per transform and stage radices for each supported edge.
+template <int N> struct Plan;
+template <> struct Plan<32> { static constexpr int T = 4, R0 = 4, R1 = 8, R2 = 1; };
+template <> struct Plan<64> { static constexpr int T = 8, R0 = 8, R1 = 8, R2 = 1; };
+template <> struct Plan<128> { static constexpr int T = 8, R0 = 8, R1 = 16, R2 = 1; };
+template <> struct Plan<256> { static constexpr int T = 16, R0 = 16, R1 = 16, R2 = 1; };
+template <> struct Plan<512> { static constexpr int T = 64, R0 = 8, R1 = 8, R2 = 8; };
+
+// LDS footprint (complex elements) of one transform's exchange area: one
+// padding element per 16 keeps stride-16 exchanges conflict-free and one more
+// per transform separates transforms that share a wavefront.
+template <int N>
+__host__ __device__ constexpr int lds_stride() { return N + N / 16 + 1; }
+__device__ __forceinline__ int lds_idx(int i) { return i + (i >> 4); }
+
+// Twiddle W_N^e (e < N) from the table tw[e] = exp(-2 pi i e / N).
+template <bool INV>
+__device__ __forceinline__ cf tw_get(const cf* __restrict__ tw, int e) {
+  cf w = tw[e];
+  return INV ? cconj(w) : w;
+}
+
+// One Stockham stage from LDS to LDS (or registers for the last stage).
+// span = P (product of earlier radices).  Reads x[i + m*N/R], writes
+// x'[(i - k)*R + k + m*P] with k = i mod P.
+template <int N, int T, int R, int P, bool LAST, bool INV>
+__device__ __forceinline__ void stage_lds(cf (&v)[N / T], cf* lds, const cf* __restrict__ tw,
+                                          int t) {
+  constexpr int E = N / T;
+  constexpr int NB = E / R;
+  static_assert(E % R == 0, "plan: radix must divide per-thread count");
+  cf u[E];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int i = t + T * b;
+#pragma unroll
+    for (int m = 0; m < R; ++m) u[b * R + m] = lds[lds_idx(i + m * (N / R))];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int i = t + T * b;
+    const int k = i % P;
+    cf* w = &u[b * R];
+    if constexpr (P > 1) {
+      constexpr int S = N / (P * R);
+#pragma unroll
+      for (int m = 1; m < R; ++m) w[m] = cmul(w[m], tw_get<INV>(tw, k * m * S));
+    }
+    dft<R, INV>(w);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) v[b + m * NB] = w[m];      // index t + T*(b + m*NB)
+    } else {
+#pragma unroll
+      for (int m = 0; m < R; ++m) lds[lds_idx((i - k) * R + k + m * P)] = w[m];
+    }
+  }
+  if constexpr (!LAST) __syncthreads();
+}
+
+// Full transform.  On entry v[j] = x[t + T*j]; on exit v[j] = X[t + T*j].
+// lds: this transform's exchange area (lds_stride<N>() elements).
+// Every thread of the workgroup must call it (it contains barriers).
+template <int N, bool INV>
+__device__ __forceinline__ void fft_1d(cf (&v)[N / Plan<N>::T], cf* lds, const cf* __restrict__ tw,
+                                       int t) {
+  using PL = Plan<N>;
+  constexpr int T = PL::T, E = N / T, R0 = PL::R0, R1 = PL::R1, R2 = PL::R2;
+  constexpr int NB0 = E / R0;
+  static_assert(E % R0 == 0, "plan");
+  // stage 0 (P = 1): inputs of butterfly b are v[b + m*NB0]; no twiddles
+#pragma unroll
+  for (int b = 0; b < NB0; ++b) {
+    cf w[R0];
+#pragma unroll
+    for (int m = 0; m < R0; ++m) w[m] = v[b + m * NB0];
+    dft<R0, INV>(w);
+    const int i = t + T * b;
+#pragma unroll
+    for (int m = 0; m < R0; ++m) lds[lds_idx(i * R0 + m)] = w[m];
+  }
+  __syncthreads();
+  if constexpr (R2 == 1) {
+    stage_lds<N, T, R1, R0, true, INV>(v, lds, tw, t);
+  } else {
+    stage_lds<N, T, R1, R0, false, INV>(v, lds, tw, t);
+    stage_lds<N, T, R2, R0 * R1, true, INV>(v, lds, tw, t);
+  }
+}
+
+}  // namespace ttm

@@ -1,0 +1,105 @@
+// internal.hpp -- declarations shared by the HIP translation units of libttm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "fft_core.hpp"
+
+namespace ttm {
+
+// ----------------------------------------------------------------------------
+// error reporting (thread-local message behind ttm_last_error)
+// ----------------------------------------------------------------------------
+void set_error(const char* fmt, ...);
+int hip_status(hipError_t e, const char* what);
+
+#define TTM_HIP(call)                                          \
+  do {                                                         \
+    hipError_t e_ = (call);                                    \
+    if (e_ != hipSuccess) return ::ttm::hip_status(e_, #call); \
+  } while (0)
+
+// ----------------------------------------------------------------------------
+// real-space tile source / destination descriptors for the FFT passes
+// ----------------------------------------------------------------------------
+
+// Tile element (z, y, x) of batch b is src[b][oz + z][oy + y][ox + x] when that
+// voxel lies inside the dz x dy x dx source, else 0.  If `center` is set the
+// value is (v - center[0]); if `square` it is then squared.
+struct RealSrc {
+  const float* p;
+  size_t batch_stride;
+  int dz, dy, dx;
+  int oz, oy, ox;
+  const double* center;
+  int square;
+};
+
+// Tile output (z, y, x) with z < sz, y < sy, x < sx lands at
+// dst[b][vz0 + z][vy0 + y][vx0 + x] in a bz x by x bx array, multiplied by
+// `scale` and, when `w` is set, by w[woz + z][woy + y][wox + x] of a
+// wz x wy x wx map.  dtype: 0 = float32, 1 = bfloat16.
+struct RealDst {
+  void* p;
+  int dtype;
+  size_t batch_stride;
+  int by, bx;
+  int vz0, vy0, vx0;
+  int sz, sy, sx;
+  const float* w;
+  int wy, wx;
+  int woz, woy, wox;
+  float scale;
+};
+
+// Twiddle table for edge N inside the context table.
+int twiddle_offset(int N);
+constexpr int kTwiddleTotal = 32 + 64 + 128 + 256 + 512;
+
+// Forward 3D R2C of `batch` N^3 tiles into half spectra [kz][kx][ky]
+// (spec_stride complex elements apart).
+int fft3d_forward(int N, const RealSrc& src, int batch, cf* spec, size_t spec_stride,
+                  const cf* tw_all, hipStream_t s);
+
+// Inverse: for every a < A, spectrum_a = G * conj(S_a) (+ DC term
+// center * N^3 * Re S_a(0) when center is set) is inverse-transformed and the
+// cropped, scaled real output written through `dst` (batch index a).
+// `work` holds A spectra.  If S is null, G itself (A = 1) is inverted.
+int fft3d_inverse_mul(int N, const cf* G, const cf* S, size_t s_stride, int A,
+                      const double* center, cf* work, size_t work_stride, const RealDst& dst,
+                      const cf* tw_all, hipStream_t s);
+
+int init_twiddles(cf* tw_all, hipStream_t s);
+
+// Per-voxel extraction launch (extract.hip).
+struct ExtractArgs {
+  const void* C;       // K planes of `plane` voxels (float32 or bfloat16)
+  int in_dtype;
+  size_t plane;        // bz * by * bx
+  int by, bx;
+  float* score;
+  float* lam;
+  float* dir;
+  int oz, oy, ox;      // map position of box voxel (0,0,0)
+  int dy, dx;          // map extent along y and x
+  int mode;
+  const float* starts;
+  int n_starts;
+  int max_iter;
+  float tol;
+};
+int launch_extract(int degree, const ExtractArgs& a, hipStream_t s);
+
+// Find Peaks (peaks.hip).
+size_t peaks_workspace(int64_t n_voxels);
+int find_peaks(const float* score, int nz, int ny, int nx, const int32_t lo[3],
+               const int32_t hi[3], int top_p, float min_dist, int32_t* peaks_out,
+               float* vals_out, int32_t* n_found_host, void* ws, size_t ws_bytes, hipStream_t s);
+
+// Zero-fill with a kernel (graph-capture friendly, unlike memset nodes).
+void fill_zero(void* p, size_t bytes, hipStream_t s);
+
+}  // namespace ttm

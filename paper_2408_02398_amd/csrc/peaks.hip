@@ -1,0 +1,350 @@
+// peaks.hip -- exact greedy Find Peaks on the GPU (gfx950).
+//
+// The rule (Sec. 3.4): visit voxels by descending score, ties by ascending
+// linear index, keep a voxel when every kept peak is at least D away, stop
+// at P.  A voxel's fate depends only on higher-ranked voxels, so the first P
+// kept peaks are decided by the voxels ranked above the P-th of them.  The
+// search therefore runs on the top-ranked candidates only:
+//   1. 16-bit histogram of the score bit patterns (scores are >= 0, so the
+//      bit pattern is monotone in the value),
+//   2. the host picks the histogram bin above which at least `want`
+//      candidates lie and the kernels compact them as 64-bit keys
+//      (~score_bits << 32 | linear index), so ascending key order is exactly
+//      the visiting order,
+//   3. LSD radix sort of the keys (8-bit digits, stable ranks from wavefront
+//      ballots),
+//   4. one workgroup walks the sorted keys in chunks: every lane tests its
+//      candidate against the kept peaks through a spatial hash of cell size
+//      D, then the survivors of the chunk are settled in order.
+// If fewer than P peaks are found while lower-ranked voxels remain, the host
+// doubles `want` and repeats.
+#include <cstring>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace ttm {
+
+namespace {
+
+constexpr int kHistBins = 65536;
+constexpr int kSortIPT = 16;           // keys per thread per sort block
+constexpr int kSortBlock = 256;        // threads per sort block
+constexpr int kSortTile = kSortIPT * kSortBlock;
+
+__device__ __forceinline__ unsigned score_bits(float s) {
+  // scores are norms (>= 0); clamp anything else to 0 so the order is monotone
+  return (s > 0.0f) ? __float_as_uint(s) : 0u;
+}
+
+struct Region {
+  int nz, ny, nx;
+  int z0, y0, x0, z1, y1, x1;  // inclusive valid box
+};
+
+__global__ void k_hist(const float* __restrict__ score, Region r, unsigned* __restrict__ hist) {
+  const int x = r.x0 + blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = r.y0 + blockIdx.y, z = r.z0 + blockIdx.z;
+  if (x > r.x1) return;
+  const unsigned b = score_bits(score[((size_t)z * r.ny + y) * r.nx + x]) >> 16;
+  atomicAdd(&hist[b], 1u);
+}
+
+__global__ void k_compact(const float* __restrict__ score, Region r, unsigned bin_lo,
+                          unsigned long long* __restrict__ keys, unsigned* __restrict__ counter) {
+  const int x = r.x0 + blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = r.y0 + blockIdx.y, z = r.z0 + blockIdx.z;
+  if (x > r.x1) return;
+  const size_t lin = ((size_t)z * r.ny + y) * r.nx + x;
+  const unsigned bits = score_bits(score[lin]);
+  if ((bits >> 16) >= bin_lo) {
+    const unsigned slot = atomicAdd(counter, 1u);
+    keys[slot] = ((unsigned long long)(~bits) << 32) | (unsigned long long)lin;
+  }
+}
+
+__global__ void k_fill(unsigned long long* __restrict__ keys, size_t from, size_t to) {
+  const size_t i = from + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < to) keys[i] = ~0ull;
+}
+
+// ---------------------------------------------------------------- radix sort
+__global__ __launch_bounds__(kSortBlock) void k_rs_hist(const unsigned long long* __restrict__ keys,
+                                                        int shift, unsigned* __restrict__ hist,
+                                                        int nblocks) {
+  __shared__ unsigned h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const size_t base = (size_t)blockIdx.x * kSortTile;
+  for (int i = 0; i < kSortIPT; ++i) {
+    const unsigned d = (unsigned)(keys[base + i * kSortBlock + threadIdx.x] >> shift) & 255u;
+    atomicAdd(&h[d], 1u);
+  }
+  __syncthreads();
+  hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// exclusive scan of n values by one workgroup of 1024 threads
+__global__ __launch_bounds__(1024) void k_scan(unsigned* __restrict__ a, int n) {
+  __shared__ unsigned part[1024];
+  const int t = threadIdx.x;
+  const int per = (n + 1023) / 1024;
+  const int lo = min(n, t * per), hi = min(n, lo + per);
+  unsigned s = 0;
+  for (int i = lo; i < hi; ++i) s += a[i];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    unsigned v = (t >= off) ? part[t - off] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  unsigned run = (t == 0) ? 0u : part[t - 1];
+  for (int i = lo; i < hi; ++i) {
+    const unsigned v = a[i];
+    a[i] = run;
+    run += v;
+  }
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_rs_scatter(
+    const unsigned long long* __restrict__ in, unsigned long long* __restrict__ out, int shift,
+    const unsigned* __restrict__ offs, int nblocks) {
+  constexpr int NW = kSortBlock / 64;
+  __shared__ unsigned run[256];
+  __shared__ unsigned wcnt[NW][256];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  run[tid] = offs[(size_t)tid * nblocks + blockIdx.x];
+  const size_t base = (size_t)blockIdx.x * kSortTile;
+  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int i = 0; i < kSortIPT; ++i) {
+#pragma unroll
+    for (int w = 0; w < NW; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    const unsigned long long key = in[base + i * kSortBlock + tid];
+    const unsigned d = (unsigned)(key >> shift) & 255u;
+    unsigned long long same = ~0ull;
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const unsigned long long bal = __ballot((d >> bit) & 1u);
+      same &= ((d >> bit) & 1u) ? bal : ~bal;
+    }
+    const unsigned rank = __popcll(same & lt);
+    if (rank == 0) wcnt[wv][d] = __popcll(same);
+    __syncthreads();
+    unsigned before = 0;
+    for (int w = 0; w < wv; ++w) before += wcnt[w][d];
+    out[run[d] + before + rank] = key;
+    __syncthreads();
+    unsigned tot = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) tot += wcnt[w][tid];
+    run[tid] += tot;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- greedy walk
+constexpr int kGreedyThreads = 1024;
+constexpr int kMaxPeaks = 2048;
+constexpr int kMaxCells = 16384;
+
+struct GreedyArgs {
+  const unsigned long long* keys;
+  int m;                  // number of candidate keys (sorted ascending)
+  int nz, ny, nx;
+  float d2;               // squared exclusion distance
+  float cell;             // hash cell edge (>= exclusion distance)
+  int gz, gy, gx;         // hash grid extent
+  int top_p;
+  int* peaks;             // top_p x 3
+  float* vals;
+  int* n_found;           // device
+};
+
+__global__ __launch_bounds__(kGreedyThreads) void k_greedy(GreedyArgs g) {
+  __shared__ short head[kMaxCells];
+  __shared__ short next[kMaxPeaks];
+  __shared__ short pz[kMaxPeaks], py[kMaxPeaks], px[kMaxPeaks];
+  __shared__ int surv[kGreedyThreads];
+  __shared__ int nsurv, nkept, stop;
+  const int tid = threadIdx.x;
+  const int ncell = g.gz * g.gy * g.gx;
+  for (int i = tid; i < ncell; i += kGreedyThreads) head[i] = (short)-1;
+  if (tid == 0) {
+    nkept = 0;
+    stop = 0;
+  }
+  __syncthreads();
+  const size_t yx = (size_t)g.ny * g.nx;
+  for (int base = 0; base < g.m; base += kGreedyThreads) {
+    if (tid == 0) nsurv = 0;
+    __syncthreads();
+    const int idx = base + tid;
+    int cz = 0, cy = 0, cxx = 0;
+    bool alive = false;
+    if (idx < g.m) {
+      const unsigned long long key = g.keys[idx];
+      const size_t lin = (size_t)(key & 0xffffffffull);
+      cz = (int)(lin / yx);
+      cy = (int)((lin / g.nx) % g.ny);
+      cxx = (int)(lin % g.nx);
+      alive = true;
+      const int hz = (int)(cz / g.cell), hy = (int)(cy / g.cell), hx = (int)(cxx / g.cell);
+      for (int dz = -1; dz <= 1 && alive; ++dz) {
+        const int z2 = hz + dz;
+        if (z2 < 0 || z2 >= g.gz) continue;
+        for (int dy = -1; dy <= 1 && alive; ++dy) {
+          const int y2 = hy + dy;
+          if (y2 < 0 || y2 >= g.gy) continue;
+          for (int dx = -1; dx <= 1 && alive; ++dx) {
+            const int x2 = hx + dx;
+            if (x2 < 0 || x2 >= g.gx) continue;
+            for (int p = head[(z2 * g.gy + y2) * g.gx + x2]; p >= 0; p = next[p]) {
+              const float ddz = (float)(cz - pz[p]), ddy = (float)(cy - py[p]),
+                          ddx = (float)(cxx - px[p]);
+              if (ddz * ddz + ddy * ddy + ddx * ddx < g.d2) {
+                alive = false;
+                break;
+              }
+            }
+          }
+        }
+      }
+    }
+    if (alive) surv[atomicAdd(&nsurv, 1)] = tid;
+    __syncthreads();
+    if (tid == 0) {
+      // survivors were appended in arbitrary order: settle them by rank
+      const int ns = nsurv;
+      for (int i = 1; i < ns; ++i) {  // insertion sort on tid (= rank within chunk)
+        const int v = surv[i];
+        int j = i - 1;
+        while (j >= 0 && surv[j] > v) {
+          surv[j + 1] = surv[j];
+          --j;
+        }
+        surv[j + 1] = v;
+      }
+      const int first_new = nkept;
+      for (int i = 0; i < ns && nkept < g.top_p; ++i) {
+        const unsigned long long key = g.keys[base + surv[i]];
+        const size_t lin = (size_t)(key & 0xffffffffull);
+        const int z = (int)(lin / yx), y = (int)((lin / g.nx) % g.ny), x = (int)(lin % g.nx);
+        bool ok = true;
+        for (int p = first_new; p < nkept; ++p) {
+          const float ddz = (float)(z - pz[p]), ddy = (float)(y - py[p]), ddx = (float)(x - px[p]);
+          if (ddz * ddz + ddy * ddy + ddx * ddx < g.d2) {
+            ok = false;
+            break;
+          }
+        }
+        if (!ok) continue;
+        const int k = nkept++;
+        pz[k] = (short)z;
+        py[k] = (short)y;
+        px[k] = (short)x;
+        const int cell = ((int)(z / g.cell) * g.gy + (int)(y / g.cell)) * g.gx + (int)(x / g.cell);
+        next[k] = head[cell];
+        head[cell] = (short)k;
+        g.peaks[3 * k + 0] = z;
+        g.peaks[3 * k + 1] = y;
+        g.peaks[3 * k + 2] = x;
+        g.vals[k] = __uint_as_float(~(unsigned)(key >> 32));
+      }
+      if (nkept >= g.top_p) stop = 1;
+    }
+    __syncthreads();
+    if (stop) break;
+  }
+  if (tid == 0) *g.n_found = nkept;
+}
+
+}  // namespace
+
+size_t peaks_workspace(int64_t n_voxels) {
+  const size_t cand = (size_t)n_voxels + kSortTile;
+  const size_t nblk = (cand + kSortTile - 1) / kSortTile;
+  return 2 * cand * 8 + kHistBins * 4 + 256 * nblk * 4 + 256 + 1024;
+}
+
+int find_peaks(const float* score, int nz, int ny, int nx, const int32_t lo[3],
+               const int32_t hi[3], int top_p, float min_dist, int32_t* peaks_out,
+               float* vals_out, int32_t* n_found_host, void* ws, size_t ws_bytes,
+               hipStream_t s) {
+  Region r{nz, ny, nx, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]};
+  const int64_t nvalid = (int64_t)(hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1);
+  const size_t need = peaks_workspace(nvalid);
+  if (ws_bytes < need) {
+    set_error("ttm_find_peaks: workspace %zu < %zu bytes", ws_bytes, need);
+    return -5;
+  }
+  const float cell = fmaxf(min_dist, 1.0f);
+  const int gz = (int)(nz / cell) + 1, gy = (int)(ny / cell) + 1, gx = (int)(nx / cell) + 1;
+  if ((int64_t)gz * gy * gx > kMaxCells || top_p > kMaxPeaks || nz > 32767 || ny > 32767 ||
+      nx > 32767) {
+    set_error("ttm_find_peaks: exclusion grid %dx%dx%d or top_p %d too large", gz, gy, gx, top_p);
+    return -4;
+  }
+  char* w = static_cast<char*>(ws);
+  const size_t cand_cap = (size_t)nvalid + kSortTile;
+  unsigned long long* keys_a = reinterpret_cast<unsigned long long*>(w);
+  unsigned long long* keys_b = keys_a + cand_cap;
+  unsigned* hist = reinterpret_cast<unsigned*>(keys_b + cand_cap);
+  unsigned* counter = hist + kHistBins;
+  int* nfound_dev = reinterpret_cast<int*>(counter + 64);
+  unsigned* shist = reinterpret_cast<unsigned*>(nfound_dev + 64);
+
+  fill_zero(hist, kHistBins * 4, s);
+  const dim3 grid((hi[2] - lo[2] + 1 + 255) / 256, hi[1] - lo[1] + 1, hi[0] - lo[0] + 1);
+  hipLaunchKernelGGL(k_hist, grid, dim3(256), 0, s, score, r, hist);
+  std::vector<unsigned> h(kHistBins);
+  TTM_HIP(hipMemcpyAsync(h.data(), hist, kHistBins * 4, hipMemcpyDeviceToHost, s));
+  TTM_HIP(hipStreamSynchronize(s));
+
+  int64_t want = std::max<int64_t>(64 * (int64_t)top_p, 1 << 16);
+  while (true) {
+    // lowest bin such that the bins at or above it hold >= want voxels
+    int64_t acc = 0;
+    int bin = kHistBins - 1;
+    for (; bin >= 0; --bin) {
+      acc += h[bin];
+      if (acc >= want) break;
+    }
+    if (bin < 0) bin = 0;
+    const bool all = (acc >= nvalid) || bin == 0;
+    const int64_t m = acc;
+    const size_t mpad = ((size_t)m + kSortTile - 1) / kSortTile * kSortTile;
+    const int nblk = (int)(mpad / kSortTile);
+    fill_zero(counter, 4, s);
+    hipLaunchKernelGGL(k_compact, grid, dim3(256), 0, s, score, r, (unsigned)bin, keys_a, counter);
+    if (mpad > (size_t)m) {
+      hipLaunchKernelGGL(k_fill, dim3((unsigned)((mpad - m + 255) / 256)), dim3(256), 0, s, keys_a,
+                         (size_t)m, mpad);
+    }
+    unsigned long long* src = keys_a;
+    unsigned long long* dst = keys_b;
+    for (int shift = 0; shift < 64; shift += 8) {
+      hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(kSortBlock), 0, s, src, shift, shist, nblk);
+      hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, shist, 256 * nblk);
+      hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(kSortBlock), 0, s, src, dst, shift, shist,
+                         nblk);
+      std::swap(src, dst);
+    }
+    GreedyArgs ga{src, (int)m, nz, ny, nx, min_dist * min_dist, cell, gz, gy, gx, top_p,
+                  peaks_out, vals_out, nfound_dev};
+    hipLaunchKernelGGL(k_greedy, dim3(1), dim3(kGreedyThreads), 0, s, ga);
+    TTM_HIP(hipGetLastError());
+    int nf = 0;
+    TTM_HIP(hipMemcpyAsync(&nf, nfound_dev, 4, hipMemcpyDeviceToHost, s));
+    TTM_HIP(hipStreamSynchronize(s));
+    if (nf >= top_p || all) {
+      *n_found_host = nf;
+      return 0;
+    }
+    want *= 4;
+  }
+}
+
+}  // namespace ttm

@@ -1,0 +1,282 @@
+"""Python binding of libttm: torch device tensors in, torch device tensors out.
+
+Argument marshalling only -- every step runs in the HIP kernels behind the C
+ABI (include/ttm.h).  Tensors must live on the context's GPU; calls are
+enqueued on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+from ._lib import Desc, ExtractOpts, I32x3, call, load
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need_cuda(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("libttm needs device tensors")
+        if t is not None and not t.is_contiguous():
+            raise ValueError("libttm needs contiguous tensors")
+
+
+def n_components(degree: int, dprime: int = 3) -> int:
+    return load().ttm_n_components(degree, dprime)
+
+
+def spectrum_elems(fft_n: int) -> int:
+    return load().ttm_spectrum_elems(fft_n)
+
+
+def make_desc(degree: int, L_edge: int, mask_radius: float, dprime: int = 3,
+              filter_a: float = 0.2, eps_w: float = 1e-6, axis=(0.0, 0.0, 1.0)) -> Desc:
+    d = Desc()
+    d.degree, d.dprime, d.L = degree, dprime, L_edge
+    d.mask_radius, d.filter_a, d.eps_w = mask_radius, filter_a, eps_w
+    for i in range(3):
+        d.axis[i] = axis[i]
+    return d
+
+
+class Context:
+    """Owns a libttm context (twiddle tables) on one device."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        call("ttm_create", C.byref(h), device)
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            load().ttm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ws(desc: Desc, op: int, fft_n: int, dims=(0, 0, 0), device=None) -> torch.Tensor:
+    n = load().ttm_workspace_size(C.byref(desc), op, fft_n, *dims)
+    if n == 0:
+        raise ValueError("invalid workspace request")
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def build_tensor(ctx: Context, desc: Desc, tmpl: torch.Tensor, quats: torch.Tensor):
+    """Tensor template T (K x L^3) and t' (L^3), Alg. 1."""
+    _need_cuda(tmpl, quats)
+    K = n_components(desc.degree, desc.dprime)
+    Le = desc.L
+    T = torch.empty((K, Le, Le, Le), dtype=torch.float32, device=tmpl.device)
+    tn = torch.empty((Le, Le, Le), dtype=torch.float32, device=tmpl.device)
+    call("ttm_build_tensor", ctx.h, C.byref(desc), _ptr(tmpl), _ptr(quats), quats.shape[0],
+         _ptr(T), _ptr(tn), _stream())
+    return T, tn
+
+
+def template_spectra(ctx: Context, desc: Desc, T: torch.Tensor, fft_n: int) -> torch.Tensor:
+    """(K + 1) half spectra (last: mask), float32 view (K+1, N, N/2+1, N, 2)."""
+    _need_cuda(T)
+    K = n_components(desc.degree, desc.dprime)
+    out = torch.empty((K + 1, fft_n, fft_n // 2 + 1, fft_n, 2), dtype=torch.float32, device=T.device)
+    ws = _ws(desc, L.TTM_OP_SPECTRA, fft_n, device=T.device)
+    call("ttm_template_spectra", ctx.h, C.byref(desc), _ptr(T), fft_n, _ptr(out), _ptr(ws),
+         ws.numel(), _stream())
+    return out
+
+
+def normalize(ctx: Context, desc: Desc, vol: torch.Tensor, spectra: torch.Tensor, fft_n: int,
+              ws: torch.Tensor | None = None):
+    """g = h*f, w (full size, 0 off the valid region), stats = (mean g, mean g^2)."""
+    _need_cuda(vol, spectra)
+    nz, ny, nx = vol.shape
+    g = torch.empty_like(vol)
+    w = torch.empty_like(vol)
+    stats = torch.empty(2, dtype=torch.float64, device=vol.device)
+    if ws is None:
+        ws = _ws(desc, L.TTM_OP_NORMALIZE, fft_n, (nz, ny, nx), device=vol.device)
+    mask_spec = spectra[-1]
+    call("ttm_normalize", ctx.h, C.byref(desc), _ptr(vol), nz, ny, nx, _ptr(mask_spec), fft_n,
+         _ptr(g), _ptr(w), _ptr(stats), _ptr(ws), ws.numel(), _stream())
+    return g, w, stats
+
+
+def correlate(ctx: Context, desc: Desc, g: torch.Tensor, w: torch.Tensor, stats: torch.Tensor,
+              spectra: torch.Tensor, fft_n: int, box_lo, box_size, dtype=torch.float32,
+              out: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
+    """C (K x bz x by x bx) on a box of the valid region (Eq. tcc / Alg. 2)."""
+    _need_cuda(g, w, stats, spectra)
+    nz, ny, nx = g.shape
+    K = n_components(desc.degree, desc.dprime)
+    if out is None:
+        out = torch.empty((K, *box_size), dtype=dtype, device=g.device)
+    code = L.TTM_BF16 if out.dtype == torch.bfloat16 else L.TTM_F32
+    if ws is None:
+        ws = _ws(desc, L.TTM_OP_CORRELATE, fft_n, (nz, ny, nx), device=g.device)
+    call("ttm_correlate", ctx.h, C.byref(desc), _ptr(g), _ptr(w), nz, ny, nx, _ptr(stats),
+         _ptr(spectra), fft_n, I32x3(*box_lo), I32x3(*box_size), code, _ptr(out), _ptr(ws),
+         ws.numel(), _stream())
+    return out
+
+
+def extract(ctx: Context, desc: Desc, Cf: torch.Tensor, *, score=None, lam=None, direction=None,
+            out_lo=(0, 0, 0), out_dims=None, starts: torch.Tensor | None = None,
+            orient: bool = True, max_iter: int = 500, tol: float = 1e-6):
+    """Score / lambda / direction maps for the box held in Cf (K x bz x by x bx)."""
+    _need_cuda(Cf, score, lam, direction, starts)
+    box = tuple(Cf.shape[1:])
+    if out_dims is None:
+        out_dims = box
+    dev = Cf.device
+    if score is None:
+        score = torch.zeros(out_dims, dtype=torch.float32, device=dev)
+    mode = L.TTM_SCORE
+    opts = ExtractOpts()
+    if orient:
+        mode |= L.TTM_ORIENT
+        if lam is None:
+            lam = torch.zeros(out_dims, dtype=torch.float32, device=dev)
+        if direction is None:
+            direction = torch.zeros((*out_dims, 3), dtype=torch.float32, device=dev)
+        if starts is None:
+            raise ValueError("orientation needs start vectors")
+        opts.n_starts = starts.shape[0]
+        opts.starts = starts.data_ptr()
+    opts.mode = mode
+    opts.max_iter = max_iter
+    opts.tol = tol
+    code = L.TTM_BF16 if Cf.dtype == torch.bfloat16 else L.TTM_F32
+    call("ttm_extract", ctx.h, C.byref(desc), _ptr(Cf), code, I32x3(*box), C.byref(opts),
+         _ptr(score), _ptr(lam) if orient else None, _ptr(direction) if orient else None,
+         I32x3(*out_lo), I32x3(*out_dims), None, _stream())
+    return score, lam, direction
+
+
+def find_peaks(ctx: Context, score: torch.Tensor, valid_lo, valid_hi, top_p: int, min_dist: float,
+               ws: torch.Tensor | None = None):
+    """Greedy peaks: (positions int32 (P', 3) z,y,x; scores (P',)) on the device."""
+    _need_cuda(score)
+    nz, ny, nx = score.shape
+    peaks = torch.empty((top_p, 3), dtype=torch.int32, device=score.device)
+    vals = torch.empty(top_p, dtype=torch.float32, device=score.device)
+    nf = C.c_int32(0)
+    if ws is None:
+        d = make_desc(2, 4, 1.0)
+        ws = _ws(d, L.TTM_OP_PEAKS, 32, (nz, ny, nx), device=score.device)
+    call("ttm_find_peaks", ctx.h, _ptr(score), nz, ny, nx, I32x3(*valid_lo), I32x3(*valid_hi),
+         top_p, float(min_dist), _ptr(peaks), _ptr(vals), C.byref(nf), _ptr(ws), ws.numel(),
+         _stream())
+    return peaks[:nf.value], vals[:nf.value]
+
+
+def fft3d_r2c(ctx: Context, x: torch.Tensor) -> torch.Tensor:
+    _need_cuda(x)
+    N = x.shape[0]
+    out = torch.empty((N, N // 2 + 1, N, 2), dtype=torch.float32, device=x.device)
+    call("ttm_fft3d_r2c", ctx.h, _ptr(x), N, _ptr(out), _stream())
+    return out
+
+
+def fft3d_c2r(ctx: Context, spec: torch.Tensor, scale: float = 1.0) -> torch.Tensor:
+    """Inverse of fft3d_r2c times scale; overwrites spec."""
+    _need_cuda(spec)
+    N = spec.shape[0]
+    x = torch.empty((N, N, N), dtype=torch.float32, device=spec.device)
+    call("ttm_fft3d_c2r", ctx.h, _ptr(spec), N, float(scale), _ptr(x), _stream())
+    return x
+
+
+# ----------------------------------------------------------------------------
+# full pass over a tomogram (tiling driver)
+# ----------------------------------------------------------------------------
+
+
+def valid_bounds(shape, L_edge: int):
+    c = L_edge // 2
+    lo = (c, c, c)
+    hi = tuple(d - L_edge + c for d in shape)
+    return lo, hi
+
+
+def tile_boxes(shape, L_edge: int, fft_n: int):
+    """Valid-region boxes of (fft_n - L + 1)^3 voxels covering the valid region."""
+    lo, hi = valid_bounds(shape, L_edge)
+    step = fft_n - L_edge + 1
+    boxes = []
+    for z in range(lo[0], hi[0] + 1, step):
+        for y in range(lo[1], hi[1] + 1, step):
+            for x in range(lo[2], hi[2] + 1, step):
+                size = (min(step, hi[0] - z + 1), min(step, hi[1] - y + 1), min(step, hi[2] - x + 1))
+                boxes.append(((z, y, x), size))
+    return boxes
+
+
+@dataclass
+class PassResult:
+    score: torch.Tensor
+    lam: torch.Tensor | None
+    direction: torch.Tensor | None
+    peaks: torch.Tensor | None
+    peak_vals: torch.Tensor | None
+    w: torch.Tensor
+    g: torch.Tensor
+
+
+class Engine:
+    """A TTM full pass with preallocated buffers: normalise, correlate per tile,
+    extract per tile into the volume maps, then Find Peaks."""
+
+    def __init__(self, ctx: Context, desc: Desc, spectra: torch.Tensor, fft_n: int, shape,
+                 starts: torch.Tensor | None, field_dtype=torch.float32, orient: bool = True,
+                 max_iter: int = 500, tol: float = 1e-6):
+        self.ctx, self.desc, self.spectra, self.fft_n = ctx, desc, spectra, fft_n
+        self.shape = tuple(shape)
+        self.starts, self.orient = starts, orient
+        self.max_iter, self.tol = max_iter, tol
+        dev = spectra.device
+        nz, ny, nx = self.shape
+        K = n_components(desc.degree, desc.dprime)
+        self.boxes = tile_boxes(self.shape, desc.L, fft_n)
+        step = fft_n - desc.L + 1
+        self.K = K
+        self.Cbuf = torch.empty(K * step ** 3, dtype=field_dtype, device=dev)
+        self.ws_norm = _ws(desc, L.TTM_OP_NORMALIZE, fft_n, self.shape, device=dev)
+        self.ws_corr = _ws(desc, L.TTM_OP_CORRELATE, fft_n, self.shape, device=dev)
+        self.ws_peaks = _ws(desc, L.TTM_OP_PEAKS, fft_n, self.shape, device=dev)
+        self.score = torch.zeros(self.shape, dtype=torch.float32, device=dev)
+        self.lam = torch.zeros(self.shape, dtype=torch.float32, device=dev) if orient else None
+        self.dir = torch.zeros((*self.shape, 3), dtype=torch.float32, device=dev) if orient else None
+
+    def run(self, vol: torch.Tensor, top_p: int | None = None, min_dist: float | None = None,
+            tiles=None) -> PassResult:
+        g, w, stats = normalize(self.ctx, self.desc, vol, self.spectra, self.fft_n, ws=self.ws_norm)
+        for (lo, size) in (self.boxes if tiles is None else tiles):
+            Ct = self.Cbuf[: self.K * size[0] * size[1] * size[2]].view(self.K, *size)
+            correlate(self.ctx, self.desc, g, w, stats, self.spectra, self.fft_n, lo, size, out=Ct,
+                      ws=self.ws_corr)
+            extract(self.ctx, self.desc, Ct, score=self.score, lam=self.lam, direction=self.dir,
+                    out_lo=lo, out_dims=self.shape, starts=self.starts, orient=self.orient,
+                    max_iter=self.max_iter, tol=self.tol)
+        peaks = vals = None
+        if top_p:
+            vlo, vhi = valid_bounds(self.shape, self.desc.L)
+            peaks, vals = find_peaks(self.ctx, self.score, vlo, vhi, top_p,
+                                     2.0 * self.desc.mask_radius if min_dist is None else min_dist,
+                                     ws=self.ws_peaks)
+        return PassResult(self.score, self.lam, self.dir, peaks, vals, w, g)

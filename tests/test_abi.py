@@ -1,0 +1,49 @@
+"""The C-ABI library loads and exports every entry point include/ttm.h declares (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ttm.h")
+LIB = os.path.join(ROOT, "paper_2408_02398_amd", "libttm.so")
+
+
+def declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ttm_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for n in ["ttm_build_tensor", "ttm_correlate", "ttm_extract", "ttm_normalize",
+              "ttm_create", "ttm_destroy", "ttm_last_error", "ttm_workspace_size",
+              "ttm_template_spectra", "ttm_find_peaks"]:
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libttm.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    for n in declared():
+        assert hasattr(lib, n), n
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libttm.so not built")
+def test_host_only_queries():
+    from paper_2408_02398_amd import _lib as L
+    from paper_2408_02398_amd import ttm
+    lib = L.load()
+    assert lib.ttm_n_components(4, 3) == 15
+    assert lib.ttm_n_components(6, 3) == 28
+    assert lib.ttm_n_components(4, 4) == 35
+    assert lib.ttm_n_components(3, 3) == 10 and lib.ttm_n_components(10, 3) == -1
+    assert lib.ttm_spectrum_elems(256) == 256 * 129 * 256
+    assert lib.ttm_fft_supported(256) == 1 and lib.ttm_fft_supported(96) == 0
+    d = ttm.make_desc(6, 40, 17.0)
+    ws = lib.ttm_workspace_size(ctypes.byref(d), L.TTM_OP_CORRELATE, 256, 512, 928, 928)
+    assert ws >= 29 * 256 * 129 * 256 * 8
+    assert lib.ttm_workspace_size(ctypes.byref(d), L.TTM_OP_CORRELATE, 32, 64, 64, 64) == 0  # L > N
+    assert lib.ttm_workspace_size(None, L.TTM_OP_CORRELATE, 256, 1, 1, 1) == 0

@@ -1,0 +1,280 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Sizes are chosen so the oracle finishes in seconds while the GPU path still
+runs several FFT tiles with ragged tails.  Tolerances:
+* FFT: normwise relative error <= 2e-6 (FP32 transform of unit-variance data);
+* scores: |c_gpu - c_orc| <= 1e-4 max(c_orc(x), median c_orc);
+* field: ||dC(x)||_F <= 1e-4 max(c_orc(x), median c_orc);
+* orientation: <= 1 degree at voxels whose best local maximum beats every
+  other one (> 5 degrees away) by more than 1e-4 c; lambda within the score
+  tolerance;
+* peaks: bit-exact (positions and float values) on maps both sides read from
+  the same input, and on full passes where the peak margins are clear.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import sym, ttm as orc
+from tests.gpu_common import rel_err, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def T():
+    require_gpu()
+    from paper_2408_02398_amd import ttm
+    return ttm
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    return T.Context(0)
+
+
+def cuda(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def host(t):
+    return t.detach().float().cpu().numpy().astype(np.float64) if t.dtype != torch.float64 else t.cpu().numpy()
+
+
+# ------------------------------------------------------------------ FFT
+@pytest.mark.parametrize("N", [32, 64, 128, 256])
+def test_fft_r2c_matches_numpy(T, ctx, N):
+    print(f"[fft r2c N={N}]", flush=True)
+    x = np.random.default_rng(N).standard_normal((N, N, N)).astype(np.float32)
+    spec = host(T.fft3d_r2c(ctx, cuda(x)))
+    got = spec[..., 0] + 1j * spec[..., 1]                     # [kz][kx][ky]
+    want = np.fft.rfftn(x.astype(np.float64)).transpose(0, 2, 1)
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) < 2e-6
+
+
+def test_fft_small_direct_dft(T, ctx):
+    N = 32
+    x = np.random.default_rng(5).standard_normal((N, N, N)).astype(np.float32)
+    n = np.arange(N)
+    W = np.exp(-2j * np.pi * np.outer(n, n) / N)              # DFT matrix, by definition
+    want = np.einsum("az,by,cx,zyx->abc", W, W, W[: N // 2 + 1], x.astype(np.float64), optimize=True)
+    spec = host(T.fft3d_r2c(ctx, cuda(x)))
+    got = (spec[..., 0] + 1j * spec[..., 1]).transpose(0, 2, 1)
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) < 2e-6
+
+
+@pytest.mark.parametrize("N", [32, 64, 256])
+def test_fft_roundtrip(T, ctx, N):
+    x = np.random.default_rng(N + 1).standard_normal((N, N, N)).astype(np.float32)
+    spec = T.fft3d_r2c(ctx, cuda(x))
+    y = host(T.fft3d_c2r(ctx, spec, 1.0 / N ** 3))
+    assert rel_err(y, x) < 2e-6
+
+
+# ------------------------------------------------------------------ pipeline pieces
+@pytest.fixture(scope="module")
+def small():
+    """A ragged multi-tile case: 50 x 61 x 72 volume, L = 12, FFT tiles of 32 (step 21)."""
+    w = synth.make_tomogram("ragged", (50, 61, 72), L=12, n_blobs=3, n_copies=4, min_sep=12,
+                            mask_radius=5.0, degree=4, seed=17, snr=None, wedge=False,
+                            copy_amplitude=2.0)
+    n, L, r = 4, 12, 5.0
+    Q = synth.rotation_samples(10)
+    tn = orc.normalize_template(w.template, r)
+    Tt = orc.tensor_template(tn, Q, n)
+    g = orc.prefilter_volume(w.volume)
+    m = orc.ball_mask(L, r)
+    wmap = orc.local_normalization(g, m)
+    C = orc.tensor_field(g, wmap, Tt)
+    return dict(w=w, n=n, L=L, r=r, Q=Q, tn=tn, Tt=Tt, g=g, wmap=wmap, C=C,
+                score=orc.score(C, n))
+
+
+def test_build_tensor_matches_oracle(T, ctx, small):
+    d = T.make_desc(small["n"], small["L"], small["r"])
+    Tg, tng = T.build_tensor(ctx, d, cuda(small["w"].template), cuda(small["Q"]))
+    assert rel_err(host(tng), small["tn"]) < 2e-6
+    err = np.linalg.norm(host(Tg) - small["Tt"]) / np.linalg.norm(small["Tt"])
+    assert err < 1e-5
+
+
+def test_normalize_matches_oracle(T, ctx, small):
+    d = T.make_desc(small["n"], small["L"], small["r"])
+    spec = T.template_spectra(ctx, d, cuda(small["Tt"]), 32)
+    vol = cuda(small["w"].volume)
+    g, w, stats = T.normalize(ctx, d, vol, spec, 32)
+    st = stats.cpu().numpy()
+    assert st[0] == pytest.approx(np.mean(small["g"]), rel=1e-6, abs=1e-9)
+    assert st[1] == pytest.approx(np.mean(small["g"] ** 2), rel=1e-6)
+    assert rel_err(host(g), small["g"]) < 1e-6
+    wg, wo = host(w), small["wmap"]
+    assert np.all(wg[wo == 0] == 0)
+    nz = wo > 0
+    assert np.max(np.abs(wg[nz] - wo[nz]) / wo[nz]) < 1e-4
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_correlate_and_score_match_oracle(T, ctx, small, dtype):
+    n, L = small["n"], small["L"]
+    d = T.make_desc(n, L, small["r"])
+    spec = T.template_spectra(ctx, d, cuda(small["Tt"]), 32)
+    g, w, stats = T.normalize(ctx, d, cuda(small["w"].volume), spec, 32)
+    lo, hi = T.valid_bounds(small["w"].volume.shape, L)
+    size = tuple(h - l + 1 for l, h in zip(lo, hi))
+    Cg = T.correlate(ctx, d, g, w, stats, spec, 32, lo, size, dtype=dtype)
+    Cg_h = host(Cg)
+    Co = small["C"]
+    cs = small["score"]
+    floor = np.maximum(cs, np.median(cs))
+    dC = np.sqrt(np.tensordot(sym.weights(n, 3), (Cg_h - Co) ** 2, axes=(0, 0)))
+    tol = 1e-4 if dtype == torch.float32 else 1e-2
+    assert np.max(dC / floor) < tol
+    score, _, _ = T.extract(ctx, d, Cg, orient=False)
+    sg = host(score)
+    assert np.max(np.abs(sg - cs) / floor) < tol
+
+
+def test_correlate_sub_box_and_single_voxel(T, ctx, small):
+    n, L = small["n"], small["L"]
+    d = T.make_desc(n, L, small["r"])
+    spec = T.template_spectra(ctx, d, cuda(small["Tt"]), 32)
+    g, w, stats = T.normalize(ctx, d, cuda(small["w"].volume), spec, 32)
+    c = L // 2
+    for lo, size in [((c + 3, c + 5, c + 7), (30, 9, 44)), ((c, c, c), (1, 1, 1)),
+                     ((38, 49, 60), (1, 1, 1))]:
+        Cg = host(T.correlate(ctx, d, g, w, stats, spec, 32, lo, size))
+        Co = small["C"][:, lo[0] - c:lo[0] - c + size[0], lo[1] - c:lo[1] - c + size[1],
+                        lo[2] - c:lo[2] - c + size[2]]
+        cs = orc.score(Co, n)
+        floor = np.maximum(cs, np.median(small["score"]))
+        dC = np.sqrt(np.tensordot(sym.weights(n, 3), (Cg - Co) ** 2, axes=(0, 0)))
+        assert np.max(dC / floor) < 1e-4
+
+
+def test_orientation_matches_oracle(T, ctx, small):
+    n = small["n"]
+    d = T.make_desc(n, small["L"], small["r"])
+    Co = small["C"]
+    K = Co.shape[0]
+    rng = np.random.default_rng(3)
+    flat = Co.reshape(K, -1)
+    idx = rng.choice(flat.shape[1], 160, replace=False)
+    Cs = np.ascontiguousarray(flat[:, idx]).reshape(K, 1, 1, -1)
+    starts = synth.start_vectors()
+    score, lam, u = T.extract(ctx, d, cuda(Cs), starts=cuda(starts), max_iter=500, tol=1e-6)
+    lg, ug = host(lam).ravel(), host(u).reshape(-1, 3)
+    cs = orc.score(Co, n)
+    med = np.median(cs)
+    checked = 0
+    for j, i in enumerate(idx):
+        v = flat[:, i]
+        lam_o, u_o, lams, us, _ = orc.orient_multistart(v, n, starts.astype(np.float64), tol=1e-6,
+                                                        max_iter=500)
+        cn = orc.score(v, n)
+        assert abs(lg[j] - lam_o) <= 1e-4 * max(cn, med)
+        margin = orc.orientation_margin(lams, us, u_o)
+        if margin > 1e-4 * cn:
+            assert orc.angle_deg(ug[j], u_o) < 1.0
+            checked += 1
+    assert checked >= 100
+
+
+def test_orientation_rank_one_and_zero(T, ctx):
+    n = 6
+    d = T.make_desc(n, 16, 7.0)
+    rng = np.random.default_rng(9)
+    vs = rng.standard_normal((64, 3))
+    vs /= np.linalg.norm(vs, axis=1, keepdims=True)
+    lam0 = rng.uniform(0.5, 2.0, 64)
+    C = (lam0[:, None] * sym.monomials(vs, n)).T.reshape(28, 1, 1, 64).copy()
+    C[:, 0, 0, 0] = 0.0                                          # zero tensor
+    score, lam, u = T.extract(ctx, d, cuda(C), starts=cuda(synth.start_vectors()))
+    lg, ug, sg = host(lam).ravel(), host(u).reshape(-1, 3), host(score).ravel()
+    assert lg[0] == 0 and np.all(ug[0] == 0) and sg[0] == 0
+    assert np.allclose(lg[1:], lam0[1:], rtol=1e-4)
+    assert np.allclose(sg[1:], lam0[1:], rtol=1e-5)
+    assert np.max(orc.angle_deg(ug[1:], vs[1:])) < 0.05
+    # canonical sign: last non-zero coordinate positive
+    assert np.all(ug[1:, 2] > 0)
+
+
+# ------------------------------------------------------------------ peaks
+@pytest.mark.parametrize("seed,shape,P,D", [(1, (20, 23, 26), 40, 3.0), (2, (40, 41, 42), 200, 5.5),
+                                            (3, (9, 10, 11), 5000, 1.0)])
+def test_find_peaks_bit_exact_on_shared_map(T, ctx, seed, shape, P, D):
+    rng = np.random.default_rng(seed)
+    s = np.round(rng.uniform(0, 1, shape), 3).astype(np.float32)   # many exact ties
+    lo = (1, 2, 3)
+    hi = (shape[0] - 2, shape[1] - 1, shape[2] - 4)
+    P = min(P, 2000)
+    pk, pv = T.find_peaks(ctx, cuda(s), lo, hi, P, D)
+    pko, pvo = orc.find_peaks(s.astype(np.float64), lo, hi, P, D)
+    assert np.array_equal(pk.cpu().numpy().astype(np.int64), pko)
+    assert np.array_equal(pv.cpu().numpy(), pvo.astype(np.float32))
+
+
+def test_peak_errors(T, ctx):
+    from paper_2408_02398_amd._lib import TTMError
+    s = cuda(np.zeros((8, 8, 8), np.float32))
+    with pytest.raises(TTMError):
+        T.find_peaks(ctx, s, (0, 0, 0), (8, 7, 7), 3, 1.0)      # region outside the map
+    with pytest.raises(TTMError):
+        T.find_peaks(ctx, s, (0, 0, 0), (7, 7, 7), 0, 1.0)      # top_p < 1
+
+
+def test_boundary_errors(T, ctx, small):
+    from paper_2408_02398_amd._lib import TTMError
+    d = T.make_desc(4, 12, 5.0)
+    spec = T.template_spectra(ctx, d, cuda(small["Tt"]), 32)
+    g, w, stats = T.normalize(ctx, d, cuda(small["w"].volume), spec, 32)
+    with pytest.raises(TTMError):   # box outside the valid region
+        T.correlate(ctx, d, g, w, stats, spec, 32, (0, 6, 6), (2, 2, 2))
+    bad = T.make_desc(3, 12, 5.0)  # odd degree
+    with pytest.raises(TTMError):
+        T.correlate(ctx, bad, g, w, stats, spec, 32, (6, 6, 6), (2, 2, 2))
+    big = T.make_desc(4, 40, 17.0)
+    with pytest.raises(TTMError):   # L > FFT edge
+        T.template_spectra(ctx, big, cuda(np.zeros((15, 40, 40, 40), np.float32)), 32)
+    with pytest.raises(TTMError):
+        T.fft3d_r2c(ctx, cuda(np.zeros((48, 48, 48), np.float32)))   # unsupported edge
+
+
+# ------------------------------------------------------------------ full pass, 64^3, n = 4
+def test_full_pass_64cube(T, ctx):
+    print("[full pass 64^3 n=4]", flush=True)
+    w = synth.make_config("c1_64cube_n4")
+    n, L, r = 4, 16, 7.0
+    Q = synth.rotation_samples(50)
+    d = T.make_desc(n, L, r)
+    Tg, _ = T.build_tensor(ctx, d, cuda(w.template), cuda(Q))
+    spec = T.template_spectra(ctx, d, Tg, 64)
+    starts = cuda(synth.start_vectors())
+    eng = T.Engine(ctx, d, spec, 64, w.volume.shape, starts)
+    res = eng.run(cuda(w.volume), top_p=5)
+    # oracle
+    tn = orc.normalize_template(w.template, r)
+    Tt = orc.tensor_template(tn, Q, n)
+    g = orc.prefilter_volume(w.volume)
+    wm = orc.local_normalization(g, orc.ball_mask(L, r))
+    C = orc.tensor_field(g, wm, Tt)
+    cs = orc.score(C, n)
+    lo, hi = T.valid_bounds(w.volume.shape, L)
+    sg = host(res.score)[lo[0]:hi[0] + 1, lo[1]:hi[1] + 1, lo[2]:hi[2] + 1]
+    floor = np.maximum(cs, np.median(cs))
+    assert np.max(np.abs(sg - cs) / floor) < 1e-4
+    full = np.zeros(w.volume.shape)
+    full[lo[0]:hi[0] + 1, lo[1]:hi[1] + 1, lo[2]:hi[2] + 1] = cs
+    pko, pvo = orc.find_peaks(full, lo, hi, 5, 2 * r)
+    pk = res.peaks.cpu().numpy().astype(np.int64)
+    assert np.array_equal(pk, pko)
+    # orientation at the peaks
+    ug = host(res.direction)
+    for p in pko:
+        v = C[:, p[0] - lo[0], p[1] - lo[1], p[2] - lo[2]]
+        lam_o, u_o, lams, us, _ = orc.orient_multistart(v, n, synth.start_vectors().astype(np.float64))
+        if orc.orientation_margin(lams, us, u_o) > 1e-4 * orc.score(v, n):
+            assert orc.angle_deg(ug[p[0], p[1], p[2]], u_o) < 1.0
