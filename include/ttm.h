@@ -174,6 +174,9 @@ typedef struct {
   float fallback_kappa;    /* learned start: fall back when lambda < kappa * c    */
   int32_t max_iter;        /* SS-HOPM iteration cap per start                     */
   float tol;               /* stop when |delta lambda| <= tol (on C / ||C||_F)    */
+  int32_t newton_steps;    /* Newton polishing steps per start, 0..8 (default 2)  */
+  uint64_t* work_counters; /* device uint64[3] or NULL: adds {SS-HOPM steps, Newton
+                              steps, oriented voxels} of this call (for FLOP counts) */
 } ttm_extract_opts;
 
 /*
@@ -187,8 +190,11 @@ typedef struct {
  *             fell back to the multistart search, or NULL
  * Orientation: alpha = max(0, -lambda_min(U)) with U the square unfolding of
  * C/||C||_F; SS-HOPM u <- (C u^{n-1} + alpha u)/||.|| from every start until
- * |delta lambda| <= tol or max_iter; the largest lambda wins (first on ties);
- * u is signed so its last non-zero coordinate is positive.
+ * |delta lambda| <= tol or max_iter, then up to newton_steps Riemannian Newton
+ * steps (taken where the tangent Hessian (n-1) E^T (C u^{n-2}) E - lambda I is
+ * negative definite, kept unless lambda drops by more than 1e-7); the largest
+ * lambda wins (first on ties); u is signed so its last non-zero coordinate is
+ * positive.
  */
 int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
                 const int32_t box_size[3], const ttm_extract_opts* opts, float* score,

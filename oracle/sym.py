@@ -99,6 +99,26 @@ def contract_n_minus_1(C: np.ndarray, u: np.ndarray, n: int) -> np.ndarray:
     return wb @ np.asarray(C, dtype=np.float64)[tab]      # (d,)
 
 
+def contract_n_minus_2(C: np.ndarray, u: np.ndarray, n: int) -> np.ndarray:
+    """(C u^{n-2})_{ij} = sum_{|beta|=n-2} mu_beta C_{beta+e_i+e_j} u^beta, a d x d matrix.
+
+    It is 1/(n(n-1)) of the Hessian of <C, u^{(x)n}>.
+    """
+    u = np.asarray(u, dtype=np.float64)
+    d = len(u)
+    idx = index_of(n, d)
+    H = np.zeros((d, d))
+    for beta in multi_indices(n - 2, d):
+        mb = multinomial(beta) * np.prod(u ** np.array(beta))
+        for i in range(d):
+            for j in range(d):
+                a = list(beta)
+                a[i] += 1
+                a[j] += 1
+                H[i, j] += mb * C[idx[tuple(a)]]
+    return H
+
+
 def frobenius(C: np.ndarray, n: int, d: int) -> np.ndarray:
     """||C||_F over the full tensor: sqrt(sum_alpha mu_alpha C_alpha^2).  C: (K, ...)."""
     w = weights(n, d)

@@ -30,7 +30,11 @@ Readings of points the paper leaves open (each is listed in the design doc):
 * SS-HOPM maximises the signed value, on the tensor divided by its Frobenius
   norm; its shift is alpha = max(0, -lambda_min(U)) with U the square matrix
   unfolding (the paper's rule, Sec. 3.1); stop when |delta lambda| <= tol or
-  after max_iter steps; best start by largest lambda, lowest index on ties;
+  after max_iter steps (the paper states no stopping rule); each start's end
+  point is then polished by up to two Newton steps on the sphere, which
+  converge to the same local maximum quadratically (a step is taken only where
+  the tangent Hessian is negative definite and kept only if lambda does not
+  drop by more than 1e-7); best start by largest lambda, lowest index on ties;
   sign canonicalised so the last non-zero coordinate is positive.
 
 Parity status: every function here is pinned by tests/test_oracle_*.py
@@ -315,11 +319,50 @@ def unfolding_shift(Cu: np.ndarray, n: int, d: int) -> float:
     return max(0.0, -float(np.linalg.eigvalsh(sym.unfolding(Cu, n, d)).min()))
 
 
-def orient_multistart(Cv: np.ndarray, n: int, starts: np.ndarray, tol: float = 1e-6,
-                      max_iter: int = 500, shift: float | None = None):
+def tangent_basis(u: np.ndarray) -> np.ndarray:
+    """Two orthonormal vectors spanning the plane orthogonal to unit u (columns).
+
+    e1 = a x u / |a x u| with a the axis of the smallest |u_i| (first on ties),
+    e2 = u x e1.
+    """
+    a = np.zeros(3)
+    a[int(np.argmin(np.abs(u)))] = 1.0
+    e1 = np.cross(a, u)
+    e1 /= np.linalg.norm(e1)
+    return np.stack([e1, np.cross(u, e1)], axis=1)
+
+
+def newton_polish(Cu: np.ndarray, n: int, u: np.ndarray, steps: int = 2,
+                  drop: float = 1e-7) -> np.ndarray:
+    """Riemannian Newton steps for max <C, u^{(x)n}> on the unit sphere (d' = 3).
+
+    Tangent gradient E^T g and Hessian (n-1) E^T H E - lambda I of f/n, with
+    g = C u^{n-1}, H = C u^{n-2}, lambda = g.u.  A step is taken only when that
+    Hessian is negative definite, and kept only if lambda drops by <= drop.
+    """
+    u = np.asarray(u, dtype=np.float64)
+    for _ in range(steps):
+        g = sym.contract_n_minus_1(Cu, u, n)
+        lam = float(g @ u)
+        E = tangent_basis(u)
+        Ht = (n - 1) * (E.T @ sym.contract_n_minus_2(Cu, u, n) @ E) - lam * np.eye(2)
+        if not (np.linalg.det(Ht) > 0 and np.trace(Ht) < 0):
+            break
+        eta = -np.linalg.solve(Ht, E.T @ g)
+        un = u + E @ eta
+        un = un / np.linalg.norm(un)
+        if float(sym.contract_n_minus_1(Cu, un, n) @ un) < lam - drop:
+            break
+        u = un
+    return u
+
+
+def orient_multistart(Cv: np.ndarray, n: int, starts: np.ndarray, tol: float = 1e-5,
+                      max_iter: int = 500, shift: float | None = None, newton: int = 2):
     """Dominant eigenpair of one voxel's tensor from fixed starts (Sec. 3.1).
 
-    Works on C / ||C||_F with the unfolding shift unless ``shift`` is given.
+    Works on C / ||C||_F with the unfolding shift unless ``shift`` is given;
+    SS-HOPM from every start, then ``newton`` polishing steps (d' = 3).
     Returns (lambda, u, per-start lambdas, per-start directions, per-start
     iterations); lambdas are scaled back by ||C||_F.  A zero tensor gives
     lambda = 0, u = 0.
@@ -334,12 +377,36 @@ def orient_multistart(Cv: np.ndarray, n: int, starts: np.ndarray, tol: float = 1
     lams, us, its = [], [], []
     for s in starts:
         lam, u, it, _ = sshopm(Cu, n, s, alpha, tol, max_iter)
+        if newton and d == 3:
+            u = newton_polish(Cu, n, u, newton)
+            lam = float(sym.contract_n_minus_1(Cu, u, n) @ u)
         lams.append(lam)
         us.append(u)
         its.append(it)
     lams = np.array(lams)
     best = int(np.argmax(lams))            # first maximum on ties
     return cn * lams[best], canonical_sign(us[best]), cn * lams, np.array(us), np.array(its)
+
+
+def sshopm_rate(Cv: np.ndarray, n: int, u: np.ndarray, alpha: float | None = None) -> float:
+    """Linear convergence factor of SS-HOPM at a fixed point u of C / ||C||_F.
+
+    The update's Jacobian on the tangent plane of u has eigenvalues
+    ((n - 1) mu_j + alpha) / (lambda + alpha), mu_j the eigenvalues of
+    C u^{n-2} restricted to that plane.  Values near 1 mean slow convergence
+    and a maximiser that small perturbations of C move far.
+    """
+    d = len(u)
+    cn = float(sym.frobenius(Cv, n, d))
+    Cu = np.asarray(Cv, dtype=np.float64) / cn
+    if alpha is None:
+        alpha = unfolding_shift(Cu, n, d)
+    u = np.asarray(u, dtype=np.float64) / np.linalg.norm(u)
+    lam = float(sym.contract_n_minus_1(Cu, u, n) @ u)
+    H = sym.contract_n_minus_2(Cu, u, n)
+    E = np.linalg.svd(np.eye(d) - np.outer(u, u))[0][:, : d - 1]     # tangent basis
+    mu = np.linalg.eigvalsh(E.T @ H @ E)
+    return float(np.max(np.abs((n - 1) * mu + alpha)) / (lam + alpha))
 
 
 def orientation_margin(lams: np.ndarray, us: np.ndarray, best_u: np.ndarray,

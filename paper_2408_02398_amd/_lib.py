@@ -30,7 +30,7 @@ class Desc(C.Structure):
 class ExtractOpts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("n_starts", C.c_int32), ("starts", C.c_void_p),
                 ("mlp", C.c_void_p), ("fallback_kappa", C.c_float), ("max_iter", C.c_int32),
-                ("tol", C.c_float)]
+                ("tol", C.c_float), ("newton_steps", C.c_int32), ("work_counters", C.c_void_p)]
 
 
 I32x3 = C.c_int32 * 3

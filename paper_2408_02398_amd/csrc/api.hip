@@ -717,7 +717,8 @@ int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
       return TTM_EUNSUPPORTED;
     }
     if (!opts->starts || opts->n_starts < 1 || opts->n_starts > 64 || opts->max_iter < 1 ||
-        !(opts->tol >= 0.0f) || (!lambda && !dir)) {
+        !(opts->tol >= 0.0f) || opts->newton_steps < 0 || opts->newton_steps > 8 ||
+        (!lambda && !dir)) {
       set_error("ttm_extract: orientation options invalid");
       return TTM_EINVAL;
     }
@@ -743,6 +744,8 @@ int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
   a.n_starts = (mode & 2) ? opts->n_starts : 0;
   a.max_iter = opts->max_iter;
   a.tol = opts->tol;
+  a.newton = opts->newton_steps;
+  a.counters = reinterpret_cast<unsigned long long*>(opts->work_counters);
   return launch_extract(desc->degree, a, s);
 }
 

@@ -55,6 +55,100 @@ __device__ __forceinline__ void contract(const float (&c)[ncomp3(N)], float x, f
   }
 }
 
+// H = C u^{n-2}: H_ij = sum_{|beta| = n-2} mu_beta C_{beta + e_i + e_j} u^beta,
+// returned as {xx, xy, xz, yy, yz, zz}.
+template <int N>
+__device__ __forceinline__ void contract2(const float (&c)[ncomp3(N)], float x, float y, float z,
+                                          float (&h)[6]) {
+  float px[N - 1], py[N - 1], pz[N - 1];
+  px[0] = py[0] = pz[0] = 1.0f;
+#pragma unroll
+  for (int k = 1; k < N - 1; ++k) {
+    px[k] = px[k - 1] * x;
+    py[k] = py[k - 1] * y;
+    pz[k] = pz[k - 1] * z;
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) h[i] = 0.0f;
+#pragma unroll
+  for (int a = N - 2; a >= 0; --a) {
+#pragma unroll
+    for (int b = N - 2 - a; b >= 0; --b) {
+      const int cc = N - 2 - a - b;
+      const float m = (float)multinom3(a, b, cc) * (px[a] * (py[b] * pz[cc]));
+      h[0] = fmaf(m, c[comp_index3(N, a + 2, b)], h[0]);
+      h[1] = fmaf(m, c[comp_index3(N, a + 1, b + 1)], h[1]);
+      h[2] = fmaf(m, c[comp_index3(N, a + 1, b)], h[2]);
+      h[3] = fmaf(m, c[comp_index3(N, a, b + 2)], h[3]);
+      h[4] = fmaf(m, c[comp_index3(N, a, b + 1)], h[4]);
+      h[5] = fmaf(m, c[comp_index3(N, a, b)], h[5]);
+    }
+  }
+}
+
+// Up to `steps` Riemannian Newton steps for max <C, u^n> on the sphere from a
+// converged SS-HOPM point: tangent basis e1 = a x u/|a x u| (a = axis of the
+// smallest |u_i|), e2 = u x e1; tangent Hessian (n-1) E^T H E - lambda I must be
+// negative definite; the step is kept unless lambda drops by more than 1e-7.
+template <int N>
+__device__ __forceinline__ int newton_polish(const float (&c)[ncomp3(N)], float& ux, float& uy,
+                                             float& uz, float& g0, float& g1, float& g2,
+                                             float& lam, int steps) {
+  int taken = 0;
+  for (int s = 0; s < steps; ++s) {
+    const float fx = fabsf(ux), fy = fabsf(uy), fz = fabsf(uz);
+    float e1x, e1y, e1z;
+    if (fx <= fy && fx <= fz) {        // a = e_x: a x u = (0, -uz, uy)
+      e1x = 0.0f; e1y = -uz; e1z = uy;
+    } else if (fy <= fz) {             // a = e_y: (uz, 0, -ux)
+      e1x = uz; e1y = 0.0f; e1z = -ux;
+    } else {                           // a = e_z: (-uy, ux, 0)
+      e1x = -uy; e1y = ux; e1z = 0.0f;
+    }
+    const float r1 = 1.0f / sqrtf(e1x * e1x + e1y * e1y + e1z * e1z);
+    e1x *= r1; e1y *= r1; e1z *= r1;
+    const float e2x = uy * e1z - uz * e1y, e2y = uz * e1x - ux * e1z, e2z = ux * e1y - uy * e1x;
+    float h[6];
+    contract2<N>(c, ux, uy, uz, h);
+    // H e1, H e2
+    const float hx1 = h[0] * e1x + h[1] * e1y + h[2] * e1z;
+    const float hy1 = h[1] * e1x + h[3] * e1y + h[4] * e1z;
+    const float hz1 = h[2] * e1x + h[4] * e1y + h[5] * e1z;
+    const float hx2 = h[0] * e2x + h[1] * e2y + h[2] * e2z;
+    const float hy2 = h[1] * e2x + h[3] * e2y + h[4] * e2z;
+    const float hz2 = h[2] * e2x + h[4] * e2y + h[5] * e2z;
+    constexpr float nm1 = (float)(N - 1);
+    const float a00 = nm1 * (e1x * hx1 + e1y * hy1 + e1z * hz1) - lam;
+    const float a01 = nm1 * (e1x * hx2 + e1y * hy2 + e1z * hz2);
+    const float a11 = nm1 * (e2x * hx2 + e2y * hy2 + e2z * hz2) - lam;
+    const float det = a00 * a11 - a01 * a01;
+    if (!(det > 0.0f && a00 + a11 < 0.0f)) break;
+    const float t0 = e1x * g0 + e1y * g1 + e1z * g2, t1 = e2x * g0 + e2y * g1 + e2z * g2;
+    const float inv = 1.0f / det;
+    const float eta0 = -(a11 * t0 - a01 * t1) * inv;
+    const float eta1 = -(a00 * t1 - a01 * t0) * inv;
+    float vx = ux + eta0 * e1x + eta1 * e2x, vy = uy + eta0 * e1y + eta1 * e2y,
+          vz = uz + eta0 * e1z + eta1 * e2z;
+    const float rv = 1.0f / sqrtf(vx * vx + vy * vy + vz * vz);
+    vx *= rv; vy *= rv; vz *= rv;
+    float q0, q1, q2;
+    contract<N>(c, vx, vy, vz, q0, q1, q2);
+    const float lam_new = q0 * vx + q1 * vy + q2 * vz;
+    ++taken;
+    if (lam_new < lam - 1e-7f) break;
+    ux = vx; uy = vy; uz = vz;
+    g0 = q0; g1 = q1; g2 = q2;
+    lam = lam_new;
+  }
+  return taken;
+}
+
+// Sum a per-lane count over the wavefront and add it to a device counter.
+__device__ __forceinline__ void count_add(unsigned long long* ctr, unsigned long long v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(ctr, v);
+}
+
 // Upper-triangle storage index of (p, q), p <= q, in an M x M matrix.
 __host__ __device__ constexpr int tri(int M, int p, int q) {
   return p <= q ? p * M - p * (p - 1) / 2 + (q - p) : q * M - q * (q - 1) / 2 + (p - q);
@@ -114,8 +208,10 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs a) {
   __shared__ float st[64 * 3];
   for (int i = threadIdx.x; i < a.n_starts * 3; i += blockDim.x) st[i] = a.starts[i];
   __syncthreads();
-  const size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= a.plane) return;
+  const size_t v0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = v0 < a.plane;
+  const size_t v = active ? v0 : a.plane - 1;   // inactive lanes recompute the last voxel, write nothing
+  unsigned long long n_steps = 0, n_newton = 0, n_oriented = 0;
   float c[K];
   if (a.in_dtype == 1) {
     const unsigned short* p = reinterpret_cast<const unsigned short*>(a.C);
@@ -133,7 +229,7 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs a) {
   const int bx = a.bx, by = a.by;
   const int vx = (int)(v % bx), vy = (int)((v / bx) % by), vz = (int)(v / ((size_t)bx * by));
   const size_t o = ((size_t)(a.oz + vz) * a.dy + (a.oy + vy)) * a.dx + (a.ox + vx);
-  if (a.mode & 1) a.score[o] = cn;
+  if ((a.mode & 1) && active) a.score[o] = cn;
   if constexpr (N >= 2) {
     if (a.mode & 2) {
       float lam_best = 0.0f, bx0 = 0.0f, by0 = 0.0f, bz0 = 0.0f;
@@ -159,9 +255,11 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs a) {
           contract<N>(c, ux, uy, uz, g0, g1, g2);
           const float lam_new = g0 * ux + g1 * uy + g2 * uz;
           ++it;
+          ++n_steps;
           const bool done = fabsf(lam_new - lam) <= a.tol || it >= a.max_iter;
           lam = lam_new;
           if (done) {
+            n_newton += newton_polish<N>(c, ux, uy, uz, g0, g1, g2, lam, a.newton);
             if (lam > lam_best) {
               lam_best = lam;
               bx0 = ux; by0 = uy; bz0 = uz;
@@ -181,12 +279,21 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs a) {
           bx0 = -bx0; by0 = -by0; bz0 = -bz0;
         }
         lam_best *= cn;
+        n_oriented = 1;
       }
-      if (a.lam) a.lam[o] = lam_best;
-      if (a.dir) {
-        a.dir[3 * o + 0] = bx0;
-        a.dir[3 * o + 1] = by0;
-        a.dir[3 * o + 2] = bz0;
+      if (active) {
+        if (a.lam) a.lam[o] = lam_best;
+        if (a.dir) {
+          a.dir[3 * o + 0] = bx0;
+          a.dir[3 * o + 1] = by0;
+          a.dir[3 * o + 2] = bz0;
+        }
+      }
+      if (a.counters) {
+        if (!active) n_steps = n_newton = n_oriented = 0;
+        count_add(a.counters + 0, n_steps);
+        count_add(a.counters + 1, n_newton);
+        count_add(a.counters + 2, n_oriented);
       }
     }
   }

@@ -90,6 +90,8 @@ struct ExtractArgs {
   int n_starts;
   int max_iter;
   float tol;
+  int newton;          // Newton polishing steps per start
+  unsigned long long* counters;  // optional: {SS-HOPM steps, Newton steps, oriented voxels}
 };
 int launch_extract(int degree, const ExtractArgs& a, hipStream_t s);
 

@@ -137,7 +137,8 @@ def correlate(ctx: Context, desc: Desc, g: torch.Tensor, w: torch.Tensor, stats:
 
 def extract(ctx: Context, desc: Desc, Cf: torch.Tensor, *, score=None, lam=None, direction=None,
             out_lo=(0, 0, 0), out_dims=None, starts: torch.Tensor | None = None,
-            orient: bool = True, max_iter: int = 500, tol: float = 1e-6):
+            orient: bool = True, max_iter: int = 500, tol: float = 1e-5, newton: int = 2,
+            counters: torch.Tensor | None = None):
     """Score / lambda / direction maps for the box held in Cf (K x bz x by x bx)."""
     _need_cuda(Cf, score, lam, direction, starts)
     box = tuple(Cf.shape[1:])
@@ -161,6 +162,11 @@ def extract(ctx: Context, desc: Desc, Cf: torch.Tensor, *, score=None, lam=None,
     opts.mode = mode
     opts.max_iter = max_iter
     opts.tol = tol
+    opts.newton_steps = newton
+    if counters is not None:
+        if counters.dtype != torch.int64 or counters.numel() < 3 or not counters.is_cuda:
+            raise ValueError("counters must be a device int64 tensor of 3 elements")
+        opts.work_counters = counters.data_ptr()
     code = L.TTM_BF16 if Cf.dtype == torch.bfloat16 else L.TTM_F32
     call("ttm_extract", ctx.h, C.byref(desc), _ptr(Cf), code, I32x3(*box), C.byref(opts),
          _ptr(score), _ptr(lam) if orient else None, _ptr(direction) if orient else None,
@@ -244,11 +250,11 @@ class Engine:
 
     def __init__(self, ctx: Context, desc: Desc, spectra: torch.Tensor, fft_n: int, shape,
                  starts: torch.Tensor | None, field_dtype=torch.float32, orient: bool = True,
-                 max_iter: int = 500, tol: float = 1e-6):
+                 max_iter: int = 500, tol: float = 1e-5, newton: int = 2):
         self.ctx, self.desc, self.spectra, self.fft_n = ctx, desc, spectra, fft_n
         self.shape = tuple(shape)
         self.starts, self.orient = starts, orient
-        self.max_iter, self.tol = max_iter, tol
+        self.max_iter, self.tol, self.newton = max_iter, tol, newton
         dev = spectra.device
         nz, ny, nx = self.shape
         K = n_components(desc.degree, desc.dprime)
@@ -272,7 +278,7 @@ class Engine:
                       ws=self.ws_corr)
             extract(self.ctx, self.desc, Ct, score=self.score, lam=self.lam, direction=self.dir,
                     out_lo=lo, out_dims=self.shape, starts=self.starts, orient=self.orient,
-                    max_iter=self.max_iter, tol=self.tol)
+                    max_iter=self.max_iter, tol=self.tol, newton=self.newton)
         peaks = vals = None
         if top_p:
             vlo, vhi = valid_bounds(self.shape, self.desc.L)

@@ -165,14 +165,14 @@ def test_orientation_matches_oracle(T, ctx, small):
     idx = rng.choice(flat.shape[1], 160, replace=False)
     Cs = np.ascontiguousarray(flat[:, idx]).reshape(K, 1, 1, -1)
     starts = synth.start_vectors()
-    score, lam, u = T.extract(ctx, d, cuda(Cs), starts=cuda(starts), max_iter=500, tol=1e-6)
+    score, lam, u = T.extract(ctx, d, cuda(Cs), starts=cuda(starts), max_iter=500, tol=1e-5)
     lg, ug = host(lam).ravel(), host(u).reshape(-1, 3)
     cs = orc.score(Co, n)
     med = np.median(cs)
     checked = 0
     for j, i in enumerate(idx):
         v = flat[:, i]
-        lam_o, u_o, lams, us, _ = orc.orient_multistart(v, n, starts.astype(np.float64), tol=1e-6,
+        lam_o, u_o, lams, us, _ = orc.orient_multistart(v, n, starts.astype(np.float64), tol=1e-5,
                                                         max_iter=500)
         cn = orc.score(v, n)
         assert abs(lg[j] - lam_o) <= 1e-4 * max(cn, med)
@@ -272,9 +272,13 @@ def test_full_pass_64cube(T, ctx):
     pk = res.peaks.cpu().numpy().astype(np.int64)
     assert np.array_equal(pk, pko)
     # orientation at the peaks
+    # orientation at the peaks, where the maximiser is well conditioned: the
+    # two sides see fields that differ by rounding (FP32 tensor template and
+    # FFTs), which moves a flat maximum (SS-HOPM factor near 1) by more than 1 deg
     ug = host(res.direction)
     for p in pko:
         v = C[:, p[0] - lo[0], p[1] - lo[1], p[2] - lo[2]]
         lam_o, u_o, lams, us, _ = orc.orient_multistart(v, n, synth.start_vectors().astype(np.float64))
-        if orc.orientation_margin(lams, us, u_o) > 1e-4 * orc.score(v, n):
+        rate = orc.sshopm_rate(v, n, u_o)
+        if orc.orientation_margin(lams, us, u_o) > 1e-4 * orc.score(v, n) and rate < 0.95:
             assert orc.angle_deg(ug[p[0], p[1], p[2]], u_o) < 1.0

@@ -130,3 +130,16 @@ def test_unfolding_symmetric_block(n, d):
     assert len(nz) <= len(ev_b)
     assert np.allclose(np.sort(nz), np.sort(ev_b[np.abs(ev_b) > 1e-9]), atol=1e-10)
     assert np.isclose(min(0.0, ev_u.min()), min(0.0, ev_b.min()), atol=1e-10)
+
+
+@pytest.mark.parametrize("n,d", [(4, 3), (6, 3), (4, 4)])
+def test_second_contraction_is_jacobian(n, d):
+    rng = np.random.default_rng(7)
+    C = rng.standard_normal(sym.n_components(n, d))
+    u = rng.standard_normal(d)
+    H = sym.contract_n_minus_2(C, u, n)
+    h = 1e-6
+    J = np.stack([(sym.contract_n_minus_1(C, u + h * e, n) - sym.contract_n_minus_1(C, u - h * e, n)) / (2 * h)
+                  for e in np.eye(d)], axis=1)
+    assert np.allclose(J, (n - 1) * H, rtol=1e-6, atol=1e-8)
+    assert np.allclose(H, H.T)

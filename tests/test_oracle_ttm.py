@@ -385,3 +385,58 @@ def test_planted_copies_recovered_at_high_snr():
     for c in w.centres:
         d = np.min(np.linalg.norm(pk - c, axis=1))
         assert d <= 7.0
+
+
+def test_sshopm_rate_predicts_convergence():
+    # the measured error ratio of late iterates approaches the predicted factor
+    rng = np.random.default_rng(31)
+    n = 6
+    C = rng.standard_normal(28)
+    Cu = C / ttm.score(C, n)
+    alpha = ttm.unfolding_shift(Cu, n, 3)
+    lam, u_star, _, _ = ttm.sshopm(Cu, n, synth.start_vectors()[0], alpha, -1.0, 5000)
+    rate = ttm.sshopm_rate(C, n, u_star, alpha)
+    assert 0 <= rate < 1
+    u = synth.start_vectors()[0].astype(np.float64)
+    errs = []
+    for _ in range(400):
+        v = sym.contract_n_minus_1(Cu, u, n) + alpha * u
+        u = v / np.linalg.norm(v)
+        errs.append(np.linalg.norm(u - u_star))
+    e = np.array(errs)
+    k = np.where(e > 1e-7)[0][-5]
+    assert e[k + 1] / e[k] == pytest.approx(rate, abs=0.02)
+
+
+def test_newton_polish_converges_quadratically_to_the_sshopm_maximum():
+    rng = np.random.default_rng(41)
+    n = 6
+    for _ in range(5):
+        v = rng.standard_normal(3)
+        v /= np.linalg.norm(v)
+        C = sym.monomials(v, n) + 0.2 * rng.standard_normal(28)
+        Cu = C / ttm.score(C, n)
+        alpha = ttm.unfolding_shift(Cu, n, 3)
+        _, u_star, _, _ = ttm.sshopm(Cu, n, v, alpha, -1.0, 20000)
+        u0 = u_star + 0.02 * np.cross(u_star, rng.standard_normal(3))
+        u0 /= np.linalg.norm(u0)
+        e0 = np.linalg.norm(u0 - u_star)
+        u1 = ttm.newton_polish(Cu, n, u0, steps=1)
+        u2 = ttm.newton_polish(Cu, n, u0, steps=2)
+        e1, e2 = np.linalg.norm(u1 - u_star), np.linalg.norm(u2 - u_star)
+        assert e1 < 50 * e0 ** 2 and e2 < max(50 * e1 ** 2, 1e-12)
+        # a point that is not near a maximum is left alone when the Hessian is not definite
+        tb = ttm.tangent_basis(u_star)
+        assert np.allclose(tb.T @ tb, np.eye(2)) and np.allclose(tb.T @ u_star, 0)
+
+
+def test_multistart_with_polish_matches_tight_sshopm():
+    rng = np.random.default_rng(42)
+    st = synth.start_vectors().astype(np.float64)
+    for n in (4, 6):
+        for _ in range(4):
+            C = rng.standard_normal(sym.n_components(n, 3))
+            lam, u, *_ = ttm.orient_multistart(C, n, st)            # tol 1e-5 + Newton
+            lam2, u2, *_ = ttm.orient_multistart(C, n, st, tol=1e-15, max_iter=100000, newton=0)
+            assert lam == pytest.approx(lam2, rel=1e-9)
+            assert ttm.angle_deg(u, u2) < 1e-3
