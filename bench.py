@@ -57,7 +57,8 @@ def extract_flops(n: int, n_starts: int = 16) -> dict:
     newton = contract2 + contract + 106
     jacobi = 6 * (H * (H - 1) // 2) * (6 * (H - 2) + 20)
     setup = K + H * (H + 1) // 2 + jacobi + n_starts * (contract + 13)
-    return dict(score=2 * K + 1, step=step, newton=newton, setup=setup)
+    setup_one = K + H * (H + 1) // 2 + jacobi + (contract + 13) + K   # learned: one start + features
+    return dict(score=2 * K + 1, step=step, newton=newton, setup=setup, setup_one=setup_one)
 
 
 def main():
@@ -70,6 +71,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=400, help="voxels in the oracle timing sample")
     ap.add_argument("--field-dtype", default="f32", choices=["f32", "bf16"])
+    ap.add_argument("--start", default="both", choices=["plain", "learned", "both"])
+    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--max-wrong", type=float, default=0.03,
+                    help="fallback calibration: accepted learned voxels off by > 1 deg at most this often")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -96,6 +101,7 @@ def main():
     d = ttm.make_desc(n, L, r)
     vol = torch.from_numpy(wl.volume).to(dev)
     Q = torch.from_numpy(synth.rotation_samples(args.nq_base)).float().to(dev)
+    p = synth.CONFIGS[cfg_name]
     t1 = time.time()
     Tg, _ = ttm.build_tensor(ctx, d, torch.from_numpy(wl.template).to(dev), Q)
     spec = ttm.template_spectra(ctx, d, Tg, fft_n)
@@ -103,93 +109,131 @@ def main():
     log(f"[bench] tensor template ({Q.shape[0]} rotations) + spectra in {time.time() - t1:.2f}s")
     starts = torch.from_numpy(synth.start_vectors()).to(dev)
     field_dtype = torch.bfloat16 if args.field_dtype == "bf16" else torch.float32
-    eng = ttm.Engine(ctx, d, spec, fft_n, vol.shape, starts, field_dtype=field_dtype)
-    n_tiles = len(eng.boxes)
-    nvox = int(np.prod(vol.shape))
     lo, hi = ttm.valid_bounds(vol.shape, L)
+    nvox = int(np.prod(vol.shape))
     nvalid = int(np.prod([h - l + 1 for l, h in zip(lo, hi)]))
+
+    learn_info = None
+    net, kappa = None, 0.0
+    if args.start in ("learned", "both"):
+        from paper_2408_02398_amd import learn
+        t2 = time.time()
+        tr = [synth.make_tomogram(f"train{i}", (256, 256, 256), L=L, n_blobs=p["n_blobs"],
+                                  n_copies=100, min_sep=p["min_sep"], mask_radius=r, degree=n,
+                                  seed=1000 + i, snr=p["snr"], wedge=p["wedge"],
+                                  template_seed=p["seed"]) for i in range(3)]
+        assert all(np.array_equal(t.template, wl.template) for t in tr)
+        vols = [torch.from_numpy(t.volume).to(dev) for t in tr]
+        spec_tr = spec if fft_n == 256 else ttm.template_spectra(ctx, d, Tg, 256)
+        log(f"[bench] training tomograms generated in {time.time() - t2:.1f}s")
+        net, kappa, learn_info = learn.build_learned_start(
+            ctx, d, spec_tr, 256, vols, starts, steps=args.train_steps, max_wrong=args.max_wrong,
+            log=log)
+        del vols
 
     # per-stage timing with events on the stream the library launches on
     stream = torch.cuda.current_stream()
     counters = torch.zeros(3, dtype=torch.int64, device=dev)   # extraction work (timed steps)
 
-    def one_pass(timed: bool):
-        ev = {}
-        if timed:
-            ev["norm"] = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-            ev["norm"][0].record(stream)
-        g, w, stats = ttm.normalize(ctx, d, vol, spec, fft_n, ws=eng.ws_norm)
-        if timed:
-            ev["norm"][1].record(stream)
-        corr_ev, ext_ev = [], []
-        for (blo, size) in eng.boxes:
-            Ct = eng.Cbuf[: eng.K * size[0] * size[1] * size[2]].view(eng.K, *size)
-            if timed:
-                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record(stream)
-            ttm.correlate(ctx, d, g, w, stats, spec, fft_n, blo, size, out=Ct, ws=eng.ws_corr)
-            if timed:
-                b.record(stream)
-                corr_ev.append((a, b))
-                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record(stream)
-            ttm.extract(ctx, d, Ct, score=eng.score, lam=eng.lam, direction=eng.dir, out_lo=blo,
-                        out_dims=eng.shape, starts=starts, orient=True,
-                        counters=counters if timed else None)
-            if timed:
-                b.record(stream)
-                ext_ev.append((a, b, int(np.prod(size))))
-        if timed:
-            ev["peaks"] = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-            ev["peaks"][0].record(stream)
-        pk, pv = ttm.find_peaks(ctx, eng.score, lo, hi, top_p, 2.0 * r, ws=eng.ws_peaks)
-        if timed:
-            ev["peaks"][1].record(stream)
-        return ev, corr_ev, ext_ev, pk
+    def run_mode(mode: str):
+        eng = ttm.Engine(ctx, d, spec, fft_n, vol.shape, starts, field_dtype=field_dtype,
+                         mlp=net if mode == "learned" else None, kappa=kappa)
 
-    for i in range(args.warmup):
-        log(f"[bench] warmup {i + 1}/{args.warmup}")
-        one_pass(False)
-    torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    stage = {"normalize": 0.0, "correlate": 0.0, "extract": 0.0, "peaks": 0.0}
-    ext_launch_ms, corr_launch_ms = [], []
-    torch.cuda.synchronize()
-    start.record(stream)
-    wall0 = time.time()
-    for i in range(args.steps):
-        ev, corr_ev, ext_ev, pk = one_pass(True)
-        log(f"[bench] step {i + 1}/{args.steps} issued")
-        stage_ev = (ev, corr_ev, ext_ev)
+        def one_pass(timed: bool):
+            ev = {}
+            if timed:
+                ev["norm"] = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                ev["norm"][0].record(stream)
+            g, w, stats = ttm.normalize(ctx, d, vol, spec, fft_n, ws=eng.ws_norm)
+            if timed:
+                ev["norm"][1].record(stream)
+            corr_ev, ext_ev = [], []
+            for (blo, size) in eng.boxes:
+                Ct = eng.Cbuf[: eng.K * size[0] * size[1] * size[2]].view(eng.K, *size)
+                if timed:
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                ttm.correlate(ctx, d, g, w, stats, spec, fft_n, blo, size, out=Ct, ws=eng.ws_corr)
+                if timed:
+                    b.record(stream)
+                    corr_ev.append((a, b))
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                ttm.extract(ctx, d, Ct, score=eng.score, lam=eng.lam, direction=eng.dir, out_lo=blo,
+                            out_dims=eng.shape, starts=starts, orient=True, mlp=eng.mlp,
+                            kappa=eng.kappa, fallbacks=eng.fallbacks, ws=eng.ws_extract,
+                            counters=counters if timed else None)
+                if timed:
+                    b.record(stream)
+                    ext_ev.append((a, b, int(np.prod(size))))
+            if timed:
+                ev["peaks"] = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                ev["peaks"][0].record(stream)
+            pk, pv = ttm.find_peaks(ctx, eng.score, lo, hi, top_p, 2.0 * r, ws=eng.ws_peaks)
+            if timed:
+                ev["peaks"][1].record(stream)
+            return ev, corr_ev, ext_ev, pk
+
+        for i in range(args.warmup):
+            log(f"[bench] {mode}: warmup {i + 1}/{args.warmup}")
+            one_pass(False)
         torch.cuda.synchronize()
-        stage["normalize"] += ev["norm"][0].elapsed_time(ev["norm"][1])
-        stage["peaks"] += ev["peaks"][0].elapsed_time(ev["peaks"][1])
-        for a, b in corr_ev:
-            t = a.elapsed_time(b)
-            stage["correlate"] += t
-            corr_launch_ms.append(t)
-        for a, b, nv in ext_ev:
-            t = a.elapsed_time(b)
-            stage["extract"] += t
-            ext_launch_ms.append((t, nv))
-    stop.record(stream)
-    torch.cuda.synchronize()
-    wall = time.time() - wall0
-    total_ms = start.elapsed_time(stop)
-    ms_step = total_ms / args.steps
+        counters.zero_()
+        eng.fallbacks.zero_()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        stage = {"normalize": 0.0, "correlate": 0.0, "extract": 0.0, "peaks": 0.0}
+        ext_launch_ms, corr_launch_ms = [], []
+        torch.cuda.synchronize()
+        start.record(stream)
+        wall0 = time.time()
+        for i in range(args.steps):
+            ev, corr_ev, ext_ev, pk = one_pass(True)
+            torch.cuda.synchronize()
+            log(f"[bench] {mode}: step {i + 1}/{args.steps} done")
+            stage["normalize"] += ev["norm"][0].elapsed_time(ev["norm"][1])
+            stage["peaks"] += ev["peaks"][0].elapsed_time(ev["peaks"][1])
+            for a, b in corr_ev:
+                t = a.elapsed_time(b)
+                stage["correlate"] += t
+                corr_launch_ms.append(t)
+            for a, b, nv in ext_ev:
+                t = a.elapsed_time(b)
+                stage["extract"] += t
+                ext_launch_ms.append((t, nv))
+        stop.record(stream)
+        torch.cuda.synchronize()
+        res = dict(eng=eng, pk=pk, stage=stage, ext=ext_launch_ms, corr=corr_launch_ms,
+                   ms_step=start.elapsed_time(stop) / args.steps, wall=time.time() - wall0,
+                   counters=[int(v) for v in counters.cpu().tolist()],
+                   fallbacks=int(eng.fallbacks.item()) // max(args.steps, 1))
+        return res
+
+    modes = ["plain", "learned"] if args.start == "both" else [args.start]
+    results = {m: run_mode(m) for m in modes}
+    main_mode = "learned" if "learned" in results else "plain"
+    R = results[main_mode]
+    ms_step = R["ms_step"]
     value = nvox / (ms_step / 1e3)
-    n_peaks = int(pk.shape[0])
+    n_peaks = int(R["pk"].shape[0])
+    n_tiles = len(R["eng"].boxes)
+
+    # accuracy gate: learned vs plain (plain is the judge) on the voxels that matter
+    gate = None
+    if "learned" in results and "plain" in results:
+        gate = accuracy_gate(results["plain"], results["learned"], lo, hi, top_p, ttm, torch)
 
     # roofline of the dominant kernel
     K = ttm.n_components(n, 3)
     se = ttm.spectrum_elems(fft_n)
     step_ = fft_n - L + 1
+    stage = R["stage"]
+    corr_launch_ms, ext_launch_ms = R["corr"], R["ext"]
     corr_avg = float(np.mean(corr_launch_ms))
     ext_avg = float(np.mean([t for t, _ in ext_launch_ms]))
     # correlation launch (full interior tile): compulsory bytes = read the g tile,
     # the K template spectra, the w crop, write the K cropped field planes
     corr_bytes = 4 * fft_n ** 3 + K * se * 8 + 4 * step_ ** 3 + 4 * K * step_ ** 3
-    corr_full = [t for t, (blo, size) in zip(corr_launch_ms, eng.boxes * args.steps)
+    corr_full = [t for t, (blo, size) in zip(corr_launch_ms, R["eng"].boxes * args.steps)
                  if size == (step_, step_, step_)]
     corr_full_avg = float(np.mean(corr_full)) if corr_full else corr_avg
     dominant = "extract" if stage["extract"] >= stage["correlate"] else "correlate"
@@ -201,12 +245,13 @@ def main():
                     "traffic": None}
     else:
         f = extract_flops(n)
-        steps_, newton_, oriented = (int(v) for v in counters.cpu().tolist())
+        steps_, newton_, oriented = R["counters"]
         voxels = sum(nv for _, nv in ext_launch_ms)
-        flops = (voxels * f["score"] + oriented * f["setup"] + steps_ * f["step"]
-                 + newton_ * f["newton"])
+        mlp_flops = 2 * (32 * 64 + 64 * 64 + 64 * 16) if main_mode == "learned" else 0
+        flops = (voxels * (f["score"] + mlp_flops) + oriented * f["setup_one" if main_mode == "learned" else "setup"]
+                 + steps_ * f["step"] + newton_ * f["newton"])
         ach = flops / (stage["extract"] / 1e3) / 1e12
-        roofline = {"bound": "alu", "kernel": f"k_extract<{n}> (16-start SS-HOPM + Newton)",
+        roofline = {"bound": "alu", "kernel": f"k_extract<{n}> ({main_mode} start) + fallback",
                     "achieved": ach, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": ach / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
                     "avg_launch_ms": ext_avg,
@@ -217,6 +262,7 @@ def main():
                  "achieved": corr_bytes / (corr_full_avg / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
                  "unit": "GB/s", "avg_launch_ms": corr_full_avg, "bytes_per_launch": corr_bytes}
     corr_roof["frac"] = corr_roof["achieved"] / HBM_PEAK_GBS
+    wall = R["wall"]
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -233,13 +279,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if field_dtype == torch.float32 else "f32-fft/bf16-field",
+        "dtype": ("f32" if field_dtype == torch.float32 else "f32-fft/bf16-field")
+                 + ("+bf16-mlp" if main_mode == "learned" else ""),
         "data": "synthetic",
         "config": {"workload": cfg_name, "shape": list(vol.shape), "degree": n, "K": K,
                    "template_edge": L, "mask_radius": r, "fft_tile": fft_n, "tiles": n_tiles,
-                   "valid_voxels": nvalid, "top_p": top_p, "start": "plain 16-start",
+                   "valid_voxels": nvalid, "top_p": top_p,
+                   "start": "learned (MLP + multistart fallback)" if main_mode == "learned" else "plain 16-start",
                    "rotations": int(Q.shape[0])},
-        "start_mode": {"plain_voxels_per_s": value, "learned_voxels_per_s": None},
+        "start_mode": {m: {"voxels_per_s": nvox / (results[m]["ms_step"] / 1e3),
+                           "ms_per_step": results[m]["ms_step"],
+                           "stages_ms_per_step": {k: v / args.steps for k, v in results[m]["stage"].items()},
+                           "fallback_voxels_per_step": results[m]["fallbacks"] if m == "learned" else None}
+                       for m in results},
+        "accuracy_gate": gate,
+        "learned_start_training": learn_info,
         "stages_ms_per_step": {k: v / args.steps for k, v in stage.items()},
         "valid_voxels_per_s": nvalid / (ms_step / 1e3),
         "peaks_found": n_peaks,
@@ -249,6 +303,49 @@ def main():
         "wall_s": wall,
     }
     print(json.dumps(out), flush=True)
+
+
+def accuracy_gate(plain, learned, lo, hi, top_p, ttm, torch):
+    """Median angle between learned and plain directions on the top 1% scores
+    plus the r_s = 3 voxel spheres around the plain pass's peaks (Sec. 3.3)."""
+    sp = plain["eng"].score
+    sl = slice(lo[0], hi[0] + 1), slice(lo[1], hi[1] + 1), slice(lo[2], hi[2] + 1)
+    sv = sp[sl]
+    gen = torch.Generator(device=sv.device)
+    gen.manual_seed(0)
+    flat = sv.reshape(-1)
+    sample = flat[torch.randint(0, flat.numel(), (min(flat.numel(), 8_000_000),), generator=gen,
+                                device=sv.device)]
+    thr = torch.quantile(sample, 0.99)
+    mask = torch.zeros_like(sp, dtype=torch.bool)
+    mask[sl] = sv >= thr
+    pk = plain["pk"].long()
+    rs = 3
+    offs = torch.stack(torch.meshgrid(*[torch.arange(-rs, rs + 1, device=sv.device)] * 3,
+                                      indexing="ij"), -1).reshape(-1, 3)
+    offs = offs[(offs ** 2).sum(1) <= rs * rs]
+    pts = (pk[:, None, :] + offs[None]).reshape(-1, 3)
+    for a in range(3):
+        pts[:, a] = pts[:, a].clamp(lo[a], hi[a])
+    mask[pts[:, 0], pts[:, 1], pts[:, 2]] = True
+    ua, ub = plain["eng"].dir[mask], learned["eng"].dir[mask]
+    c = torch.abs((ua * ub).sum(-1)) / (ua.norm(dim=-1) * ub.norm(dim=-1)).clamp_min(1e-30)
+    ang = torch.rad2deg(torch.arccos(c.clamp(max=1.0)))
+    # peaks: position agreement of the two passes
+    pl, pn = plain["pk"], learned["pk"]
+    same_peaks = bool(pl.shape == pn.shape and torch.equal(pl, pn))
+    allv = (plain["eng"].dir[sl].reshape(-1, 3), learned["eng"].dir[sl].reshape(-1, 3))
+    idx = torch.randint(0, allv[0].shape[0], (min(allv[0].shape[0], 4_000_000),), generator=gen,
+                        device=sv.device)
+    ca = torch.abs((allv[0][idx] * allv[1][idx]).sum(-1)).clamp(max=1.0)
+    ang_all = torch.rad2deg(torch.arccos(ca))
+    return {"voxels": int(mask.sum().item()), "median_deg": float(ang.median().item()),
+            "p90_deg": float(torch.quantile(ang, 0.9).item()) if ang.numel() < 16_000_000 else None,
+            "frac_within_1deg": float((ang <= 1.0).float().mean().item()),
+            "pass": bool(ang.median().item() <= 1.0),
+            "all_valid_sample_median_deg": float(ang_all.median().item()),
+            "all_valid_sample_frac_within_1deg": float((ang_all <= 1.0).float().mean().item()),
+            "peaks_identical": same_peaks}
 
 
 def cpu_baseline(wl, Q, n, L, r, sample):

@@ -72,7 +72,9 @@ typedef enum {
   TTM_OP_SPECTRA = 1,
   TTM_OP_NORMALIZE = 2,
   TTM_OP_CORRELATE = 3,
-  TTM_OP_PEAKS = 4
+  TTM_OP_PEAKS = 4,
+  TTM_OP_EXTRACT = 5,     /* nz x ny x nx = the extraction box            */
+  TTM_OP_MLP_TRAIN = 6    /* nz = batch size, ny = nx = 1                 */
 } ttm_op;
 
 typedef struct ttm_ctx ttm_ctx;
@@ -165,13 +167,16 @@ int ttm_correlate(ttm_ctx* ctx, const ttm_desc* desc, const float* g, const floa
 #define TTM_SCORE 1       /* write c = ||C||_F                                   */
 #define TTM_ORIENT 2      /* write lambda and u (dominant eigenpair by SS-HOPM)  */
 #define TTM_START_MLP 4   /* seed SS-HOPM from the MLP; fall back to multistart  */
+#define TTM_START_ONLY 8  /* with TTM_START_MLP: write the network's unit start
+                             direction to dir (lambda = 0), no search          */
 
 typedef struct {
   int32_t mode;            /* TTM_SCORE | TTM_ORIENT [| TTM_START_MLP]            */
   int32_t n_starts;        /* number of fixed start vectors, 1..64                */
   const float* starts;     /* device, n_starts x d' unit vectors                  */
-  const void* mlp;         /* device, packed MLP parameters (ttm_mlp_*), or NULL  */
-  float fallback_kappa;    /* learned start: fall back when lambda < kappa * c    */
+  const void* mlp;         /* device, packed MLP parameters (ttm_mlp_pack), or NULL */
+  float fallback_kappa;    /* learned start: fall back when lambda < kappa * c, or
+                              when SS-HOPM from the learned start did not reach tol */
   int32_t max_iter;        /* SS-HOPM iteration cap per start                     */
   float tol;               /* stop when |delta lambda| <= tol (on C / ||C||_F)    */
   int32_t newton_steps;    /* Newton polishing steps per start, 0..8 (default 2)  */
@@ -188,6 +193,15 @@ typedef struct {
  *   out_dims  host int32[3]: extent (z, y, x) of the output maps
  *   n_fallback device int32 counter incremented per voxel whose learned start
  *             fell back to the multistart search, or NULL
+ *   ws        device workspace of ttm_workspace_size(desc, TTM_OP_EXTRACT, 0,
+ *             bz, by, bx) bytes (the fallback queue); may be NULL without
+ *             TTM_START_MLP
+ * Learned start (TTM_START_MLP): per wavefront of 64 voxels the network
+ * (ttm_mlp_train_step) maps x = sqrt(mu_a) C_a / ||C||_F to a start direction
+ * on the BF16 matrix cores; SS-HOPM (+ polish) runs from it alone.  Voxels
+ * whose result is not converged or has lambda < fallback_kappa * ||C||_F are
+ * queued and re-run by a second kernel with the full multistart search, and
+ * the better of the two answers is kept.  Requires lambda and dir.
  * Orientation: alpha = max(0, -lambda_min(U)) with U the square unfolding of
  * C/||C||_F; SS-HOPM u <- (C u^{n-1} + alpha u)/||.|| from every start until
  * |delta lambda| <= tol or max_iter, then up to newton_steps Riemannian Newton
@@ -199,7 +213,34 @@ typedef struct {
 int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
                 const int32_t box_size[3], const ttm_extract_opts* opts, float* score,
                 float* lambda, float* dir, const int32_t out_lo[3], const int32_t out_dims[3],
-                int32_t* n_fallback, void* stream);
+                int32_t* n_fallback, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Learned start network (a seed for the orientation search of Sec. 3.1):
+ * x (K <= 32 features, zero padded) -> 64 -> relu -> 64 -> relu -> 3, BF16
+ * weights, FP32 accumulation, activations rounded to BF16.
+ * FP32 master parameters (ttm_mlp_param_count() floats, layout W1[32][64],
+ * b1[64], W2[64][64], b2[64], W3[64][16], b3[16]; rows of W1 beyond K and
+ * columns of W3 beyond 3 are kept 0); packed inference copy of
+ * ttm_mlp_packed_bytes() bytes.
+ */
+size_t ttm_mlp_param_count(void);
+size_t ttm_mlp_packed_bytes(void);
+/* packed = BF16 fragment-ordered copy of params (device -> device). */
+int ttm_mlp_pack(ttm_ctx* ctx, const float* params, void* packed, void* stream);
+/*
+ * One training step on B pairs (d' = 3): C device B x K raw tensors (row per
+ * sample), targets device B x 3 directions.  Loss mean(1 - (u.t/|t|)^2), u =
+ * y/|y| (sign invariant).  Adam (beta 0.9, 0.999, eps 1e-8, bias corrected,
+ * step >= 1) on params with moments adam_m, adam_v (device, param_count
+ * floats each) when lr > 0.  Optional outputs: packed (updated inference
+ * copy), loss_out (device float, loss before the update), grads_out (device,
+ * param_count floats).  ws: ttm_workspace_size(desc, TTM_OP_MLP_TRAIN, 0, B, 1, 1).
+ */
+int ttm_mlp_train_step(ttm_ctx* ctx, const ttm_desc* desc, const float* C, const float* targets,
+                       int B, float* params, float* adam_m, float* adam_v, int step, float lr,
+                       void* packed, float* loss_out, float* grads_out, void* ws, size_t ws_bytes,
+                       void* stream);
 
 /*
  * Find Peaks (Sec. 3.4): visit the voxels of [valid_lo, valid_hi] (inclusive,

@@ -47,12 +47,25 @@ def features(C: np.ndarray, n: int, d: int = 3) -> np.ndarray:
     return np.where(nrm > 0, x / np.where(nrm > 0, nrm, 1.0), 0.0)
 
 
-def forward(p: dict, X: np.ndarray):
-    z1 = X @ p["W1"] + p["b1"]
-    h1 = np.maximum(z1, 0.0)
-    z2 = h1 @ p["W2"] + p["b2"]
-    h2 = np.maximum(z2, 0.0)
-    y = h2 @ p["W3"] + p["b3"]
+def bf16_round(a: np.ndarray) -> np.ndarray:
+    """Round to the nearest bfloat16 (ties to even), returned as float64.
+
+    Emulates the storage precision of the kernels' matrix-core operands.
+    """
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward(p: dict, X: np.ndarray, bf16: bool = False):
+    """Forward pass; bf16=True rounds x, the weights and h1, h2 as the kernels store them."""
+    r = bf16_round if bf16 else (lambda a: a)
+    z1 = r(X) @ r(p["W1"]) + p["b1"]
+    h1 = r(np.maximum(z1, 0.0))
+    z2 = h1 @ r(p["W2"]) + p["b2"]
+    h2 = r(np.maximum(z2, 0.0))
+    y = h2 @ r(p["W3"]) + p["b3"]
     return y, (X, z1, h1, z2, h2, y)
 
 
@@ -107,3 +120,56 @@ def predict(p: dict, C: np.ndarray, n: int, d: int = 3) -> np.ndarray:
     """Unit start directions for tensors C (B, K)."""
     y, _ = forward(p, features(C, n, d))
     return y / np.linalg.norm(y, axis=1, keepdims=True)
+
+
+def pad_params(p: dict, k_in: int, d_out: int = 3) -> np.ndarray:
+    """Flatten to the kernels' master layout: W1[32][64], b1[64], W2[64][64], b2[64],
+    W3[64][16], b3[16] (padding rows / columns zero)."""
+    W1 = np.zeros((32, HIDDEN))
+    W1[:k_in] = p["W1"]
+    W3 = np.zeros((HIDDEN, 16))
+    W3[:, :d_out] = p["W3"]
+    b3 = np.zeros(16)
+    b3[:d_out] = p["b3"]
+    return np.concatenate([W1.ravel(), p["b1"], p["W2"].ravel(), p["b2"], W3.ravel(), b3])
+
+
+def unpad_params(flat: np.ndarray, k_in: int, d_out: int = 3) -> dict:
+    flat = np.asarray(flat, dtype=np.float64)
+    o = 0
+    W1 = flat[o:o + 32 * HIDDEN].reshape(32, HIDDEN)[:k_in]; o += 32 * HIDDEN
+    b1 = flat[o:o + HIDDEN]; o += HIDDEN
+    W2 = flat[o:o + HIDDEN * HIDDEN].reshape(HIDDEN, HIDDEN); o += HIDDEN * HIDDEN
+    b2 = flat[o:o + HIDDEN]; o += HIDDEN
+    W3 = flat[o:o + HIDDEN * 16].reshape(HIDDEN, 16)[:, :d_out]; o += HIDDEN * 16
+    b3 = flat[o:o + 16][:d_out]
+    return {"W1": W1, "b1": b1, "W2": W2, "b2": b2, "W3": W3, "b3": b3}
+
+
+def orient_learned(Cv: np.ndarray, n: int, p: dict, starts: np.ndarray, kappa: float,
+                   tol: float = 1e-5, max_iter: int = 500, newton: int = 2, bf16: bool = True):
+    """Orientation with the learned start and its multistart fallback (d' = 3).
+
+    SS-HOPM (+ polish) from the network's direction; if it does not reach tol,
+    or lambda / ||C||_F < kappa, the multistart search runs too and the larger
+    lambda wins.  Returns (lambda, u, fell_back).
+    """
+    from . import ttm
+    cn = float(sym.frobenius(Cv, n, 3))
+    if cn == 0.0:
+        return 0.0, np.zeros(3), False
+    y, _ = forward(p, features(Cv[None, :], n), bf16=bf16)
+    y = y[0]
+    ny = np.linalg.norm(y)
+    Cu = np.asarray(Cv, dtype=np.float64) / cn
+    alpha = ttm.unfolding_shift(Cu, n, 3)
+    u0 = y / ny if ny > 0 else starts[0]
+    lam, u, _, conv = ttm.sshopm(Cu, n, u0, alpha, tol, max_iter)
+    u = ttm.newton_polish(Cu, n, u, newton)
+    lam = float(sym.contract_n_minus_1(Cu, u, n) @ u)
+    if conv and ny > 0 and lam >= kappa:
+        return cn * lam, ttm.canonical_sign(u), False
+    lam_p, u_p, *_ = ttm.orient_multistart(Cv, n, starts, tol, max_iter, newton=newton)
+    if lam_p > cn * lam:
+        return lam_p, u_p, True
+    return cn * lam, ttm.canonical_sign(u), True

@@ -11,6 +11,7 @@
 
 #include "../../include/ttm.h"
 #include "internal.hpp"
+#include "mlp_core.hpp"
 
 struct ttm_ctx {
   int device;
@@ -382,6 +383,8 @@ bool valid_desc(const ttm_desc* d) {
   return true;
 }
 
+constexpr int kMlpInMax = kMlpIn;
+
 bool fft_ok(int N) { return N == 32 || N == 64 || N == 128 || N == 256 || N == 512; }
 
 size_t spec_elems(int N) { return (size_t)N * (N / 2 + 1) * N; }
@@ -447,7 +450,7 @@ int ttm_create(ttm_ctx** out, int device) {
     if (e != hipSuccess) rc = hip_status(e, "ttm_create");
   }
   if (rc != 0) {
-    hipFree(c->twiddles);
+    (void)hipFree(c->twiddles);
     delete c;
     return rc;
   }
@@ -457,8 +460,8 @@ int ttm_create(ttm_ctx** out, int device) {
 
 void ttm_destroy(ttm_ctx* ctx) {
   if (!ctx) return;
-  hipSetDevice(ctx->device);
-  hipFree(ctx->twiddles);
+  (void)hipSetDevice(ctx->device);
+  (void)hipFree(ctx->twiddles);
   delete ctx;
 }
 
@@ -481,6 +484,12 @@ size_t ttm_workspace_size(const ttm_desc* desc, int op, int fft_n, int nz, int n
       return (size_t)(1 + K) * align256(spec_elems(fft_n) * 8);
     case TTM_OP_PEAKS:
       return align256(peaks_workspace((int64_t)nz * ny * nx));
+    case TTM_OP_EXTRACT:
+      if (nz < 1 || ny < 1 || nx < 1) return 0;
+      return 256 + align256((size_t)nz * ny * nx * 4);
+    case TTM_OP_MLP_TRAIN:
+      if (nz < 1) return 0;
+      return align256(mlp_train_workspace(nz));
     default:
       return 0;
   }
@@ -685,8 +694,7 @@ int ttm_correlate(ttm_ctx* ctx, const ttm_desc* desc, const float* g, const floa
 int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
                 const int32_t box_size[3], const ttm_extract_opts* opts, float* score, float* lambda,
                 float* dir, const int32_t out_lo[3], const int32_t out_dims[3], int32_t* n_fallback,
-                void* stream) {
-  (void)n_fallback;
+                void* ws, size_t ws_bytes, void* stream) {
   if (!ctx || !valid_desc(desc)) return TTM_EINVAL;
   if (!C || !box_size || !opts || !out_lo || !out_dims || (in_dtype != TTM_F32 && in_dtype != TTM_BF16)) {
     set_error("ttm_extract: null pointer or bad dtype");
@@ -699,7 +707,7 @@ int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
     }
   }
   const int mode = opts->mode;
-  if ((mode & ~7) || !(mode & 3)) {
+  if ((mode & ~15) || !(mode & 3) || ((mode & 8) && !(mode & 4)) || ((mode & 4) && !(mode & 2))) {
     set_error("ttm_extract: mode %d invalid", mode);
     return TTM_EINVAL;
   }
@@ -707,13 +715,10 @@ int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
     set_error("ttm_extract: score map is NULL");
     return TTM_EINVAL;
   }
+  const size_t plane = (size_t)box_size[0] * box_size[1] * box_size[2];
   if (mode & 2) {
-    if (desc->dprime != 3 || desc->degree < 2) {
-      set_error("ttm_extract: orientation needs d'=3 and degree >= 2");
-      return TTM_EUNSUPPORTED;
-    }
-    if (mode & 4) {
-      set_error("ttm_extract: learned start not available in this build");
+    if (desc->dprime != 3 || desc->degree < 2 || desc->degree > 6) {
+      set_error("ttm_extract: orientation needs d'=3 and degree 2..6");
       return TTM_EUNSUPPORTED;
     }
     if (!opts->starts || opts->n_starts < 1 || opts->n_starts > 64 || opts->max_iter < 1 ||
@@ -722,13 +727,28 @@ int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
       set_error("ttm_extract: orientation options invalid");
       return TTM_EINVAL;
     }
+    if (mode & 4) {
+      if (!opts->mlp || !lambda || !dir || !(opts->fallback_kappa == opts->fallback_kappa)) {
+        set_error("ttm_extract: learned start needs mlp, lambda, dir and a kappa");
+        return TTM_EINVAL;
+      }
+      if (ncomp(desc->degree, 3) > kMlpInMax) {
+        set_error("ttm_extract: learned start takes at most %d components", kMlpInMax);
+        return TTM_EUNSUPPORTED;
+      }
+      const size_t need = 256 + align256(plane * 4);
+      if (!ws || ws_bytes < need) {
+        set_error("ttm_extract: workspace %zu < %zu", ws_bytes, need);
+        return TTM_EWORKSPACE;
+      }
+    }
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   TTM_HIP(hipSetDevice(ctx->device));
   ExtractArgs a{};
   a.C = C;
   a.in_dtype = in_dtype;
-  a.plane = (size_t)box_size[0] * box_size[1] * box_size[2];
+  a.plane = plane;
   a.by = box_size[1];
   a.bx = box_size[2];
   a.score = score;
@@ -739,14 +759,60 @@ int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
   a.ox = out_lo[2];
   a.dy = out_dims[1];
   a.dx = out_dims[2];
-  a.mode = mode;
+  a.mode = mode & 7;
   a.starts = opts->starts;
   a.n_starts = (mode & 2) ? opts->n_starts : 0;
   a.max_iter = opts->max_iter;
   a.tol = opts->tol;
   a.newton = opts->newton_steps;
   a.counters = reinterpret_cast<unsigned long long*>(opts->work_counters);
+  if (mode & 4) {
+    a.mlp = static_cast<const unsigned char*>(opts->mlp);
+    a.kappa = opts->fallback_kappa;
+    a.start_only = (mode & 8) ? 1 : 0;
+    a.fb_count = static_cast<unsigned*>(ws);
+    a.fb_queue = reinterpret_cast<unsigned*>(static_cast<char*>(ws) + 256);
+    a.fb_total = n_fallback;
+    fill_zero(ws, 256, s);
+  }
   return launch_extract(desc->degree, a, s);
+}
+
+size_t ttm_mlp_param_count(void) { return kMlpParams; }
+size_t ttm_mlp_packed_bytes(void) { return kMlpPackedBytes; }
+
+int ttm_mlp_pack(ttm_ctx* ctx, const float* params, void* packed, void* stream) {
+  if (!ctx || !params || !packed) {
+    set_error("ttm_mlp_pack: null pointer");
+    return TTM_EINVAL;
+  }
+  TTM_HIP(hipSetDevice(ctx->device));
+  return mlp_pack(params, static_cast<unsigned char*>(packed), static_cast<hipStream_t>(stream));
+}
+
+int ttm_mlp_train_step(ttm_ctx* ctx, const ttm_desc* desc, const float* Cin, const float* targets,
+                       int B, float* params, float* adam_m, float* adam_v, int step, float lr,
+                       void* packed, float* loss_out, float* grads_out, void* ws, size_t ws_bytes,
+                       void* stream) {
+  if (!ctx || !valid_desc(desc)) return TTM_EINVAL;
+  if (desc->dprime != 3 || desc->degree < 2 || desc->degree > 6) {
+    set_error("ttm_mlp_train_step: needs d'=3 and degree 2..6");
+    return TTM_EUNSUPPORTED;
+  }
+  if (!Cin || !targets || !params || !loss_out || !ws || B < 1 ||
+      (lr > 0.0f && (!adam_m || !adam_v || step < 1)) || !(lr >= 0.0f)) {
+    set_error("ttm_mlp_train_step: null pointer, B < 1 or bad Adam arguments");
+    return TTM_EINVAL;
+  }
+  const size_t need = align256(mlp_train_workspace(B));
+  if (ws_bytes < need) {
+    set_error("ttm_mlp_train_step: workspace %zu < %zu", ws_bytes, need);
+    return TTM_EWORKSPACE;
+  }
+  TTM_HIP(hipSetDevice(ctx->device));
+  return mlp_train_step(desc->degree, Cin, targets, B, params, adam_m, adam_v, step, lr,
+                        static_cast<unsigned char*>(packed), loss_out, grads_out, ws,
+                        static_cast<hipStream_t>(stream));
 }
 
 int ttm_find_peaks(ttm_ctx* ctx, const float* score, int nz, int ny, int nx,

@@ -14,6 +14,7 @@
 // start as soon as the current one has converged, so lanes of a wavefront do
 // not wait for each other's slow starts.
 #include "internal.hpp"
+#include "mlp_core.hpp"
 #include "sym_tables.hpp"
 
 namespace ttm {
@@ -201,18 +202,73 @@ __device__ __forceinline__ float unfolding_lambda_min(const float (&c)[ncomp3(N)
   return lmin;
 }
 
+// SS-HOPM from one start (then Newton polish).  Returns lambda on C/||C||_F;
+// u is updated in place; `conv` tells whether |delta lambda| <= tol was reached.
 template <int N>
-__global__ __launch_bounds__(256) void k_extract(ExtractArgs a) {
+__device__ __forceinline__ float refine(const float (&c)[ncomp3(N)], float alpha, float& ux,
+                                        float& uy, float& uz, float tol, int max_iter, int newton,
+                                        unsigned long long& n_steps, unsigned long long& n_newton,
+                                        bool& conv) {
+  {
+    const float r = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
+    ux *= r; uy *= r; uz *= r;
+  }
+  float g0, g1, g2;
+  contract<N>(c, ux, uy, uz, g0, g1, g2);
+  float lam = g0 * ux + g1 * uy + g2 * uz;
+  conv = false;
+  for (int it = 0; it < max_iter; ++it) {
+    const float wx = fmaf(alpha, ux, g0), wy = fmaf(alpha, uy, g1), wz = fmaf(alpha, uz, g2);
+    const float r = 1.0f / sqrtf(wx * wx + wy * wy + wz * wz);
+    ux = wx * r; uy = wy * r; uz = wz * r;
+    contract<N>(c, ux, uy, uz, g0, g1, g2);
+    const float lam_new = g0 * ux + g1 * uy + g2 * uz;
+    ++n_steps;
+    const bool done = fabsf(lam_new - lam) <= tol;
+    lam = lam_new;
+    if (done) {
+      conv = true;
+      break;
+    }
+  }
+  n_newton += newton_polish<N>(c, ux, uy, uz, g0, g1, g2, lam, newton);
+  return lam;
+}
+
+// Best of SS-HOPM (+ polish) from every fixed start; a lane moves to its next
+// start as soon as the current one ends.  Returns lambda on C/||C||_F.
+template <int N>
+__device__ __forceinline__ float multistart(const float (&c)[ncomp3(N)], float alpha,
+                                            const float* st, int n_starts, float tol, int max_iter,
+                                            int newton, float& bx, float& by, float& bz,
+                                            unsigned long long& n_steps,
+                                            unsigned long long& n_newton) {
+  float best = -INFINITY;
+  for (int s = 0; s < n_starts; ++s) {
+    float ux = st[3 * s], uy = st[3 * s + 1], uz = st[3 * s + 2];
+    bool conv;
+    const float lam = refine<N>(c, alpha, ux, uy, uz, tol, max_iter, newton, n_steps, n_newton, conv);
+    if (lam > best) {
+      best = lam;
+      bx = ux; by = uy; bz = uz;
+    }
+  }
+  return best;
+}
+
+__device__ __forceinline__ void canonical(float& x, float& y, float& z) {
+  // u and -u are the same answer: make the last non-zero coordinate positive
+  const float sg = (z != 0.0f) ? z : ((y != 0.0f) ? y : x);
+  if (sg < 0.0f) {
+    x = -x; y = -y; z = -z;
+  }
+}
+
+// Load the K components of box voxel v, return ||C||_F.
+template <int N>
+__device__ __forceinline__ float load_tensor(const ExtractArgs& a, size_t v, float (&c)[ncomp3(N)]) {
   constexpr int K = ncomp3(N);
   constexpr Sym3<N> sy{};
-  __shared__ float st[64 * 3];
-  for (int i = threadIdx.x; i < a.n_starts * 3; i += blockDim.x) st[i] = a.starts[i];
-  __syncthreads();
-  const size_t v0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool active = v0 < a.plane;
-  const size_t v = active ? v0 : a.plane - 1;   // inactive lanes recompute the last voxel, write nothing
-  unsigned long long n_steps = 0, n_newton = 0, n_oriented = 0;
-  float c[K];
   if (a.in_dtype == 1) {
     const unsigned short* p = reinterpret_cast<const unsigned short*>(a.C);
 #pragma unroll
@@ -225,60 +281,81 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs a) {
   float f2 = 0.0f;
 #pragma unroll
   for (int k = 0; k < K; ++k) f2 = fmaf(sy.mu[k] * c[k], c[k], f2);
-  const float cn = sqrtf(f2);
-  const int bx = a.bx, by = a.by;
-  const int vx = (int)(v % bx), vy = (int)((v / bx) % by), vz = (int)(v / ((size_t)bx * by));
-  const size_t o = ((size_t)(a.oz + vz) * a.dy + (a.oy + vy)) * a.dx + (a.ox + vx);
+  return sqrtf(f2);
+}
+
+__device__ __forceinline__ size_t map_index(const ExtractArgs& a, size_t v) {
+  const int vx = (int)(v % a.bx), vy = (int)((v / a.bx) % a.by), vz = (int)(v / ((size_t)a.bx * a.by));
+  return ((size_t)(a.oz + vz) * a.dy + (a.oy + vy)) * a.dx + (a.ox + vx);
+}
+
+template <int N, bool MLP>
+__global__ __launch_bounds__(256) void k_extract(ExtractArgs a) {
+  constexpr int K = ncomp3(N);
+  constexpr Sym3<N> sy{};
+  __shared__ float st[64 * 3];
+  for (int i = threadIdx.x; i < a.n_starts * 3; i += blockDim.x) st[i] = a.starts[i];
+  __syncthreads();
+  const size_t v0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = v0 < a.plane;
+  const size_t v = active ? v0 : a.plane - 1;   // inactive lanes recompute the last voxel, write nothing
+  unsigned long long n_steps = 0, n_newton = 0, n_oriented = 0;
+  float c[K];
+  const float cn = load_tensor<N>(a, v, c);
+  const size_t o = map_index(a, v);
   if ((a.mode & 1) && active) a.score[o] = cn;
   if constexpr (N >= 2) {
     if (a.mode & 2) {
       float lam_best = 0.0f, bx0 = 0.0f, by0 = 0.0f, bz0 = 0.0f;
-      if (cn > 0.0f) {
-        const float inv = 1.0f / cn;
+      const float inv = cn > 0.0f ? 1.0f / cn : 0.0f;
+      if constexpr (MLP) {
+        // ---- learned start: features -> BF16 MLP on the matrix cores;
+        // per wavefront [64][64] bf16 activations and [64][4] outputs
+        __shared__ unsigned short hs[4][64 * kMlpHid];
+        __shared__ float ys[4][64 * 4];
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        unsigned short* xs = &hs[wv][64 * kMlpIn];
+#pragma unroll
+        for (int k = 0; k < kMlpIn; ++k)
+          xs[lane * kMlpIn + k] = k < K ? bf16_bits(sqrtf(sy.mu[k]) * c[k] * inv) : (unsigned short)0;
+        __syncthreads();
+        float y0, y1, y2;
+        mlp_forward_wave(hs[wv], ys[wv], a.mlp, lane, y0, y1, y2);
+        const float ny = sqrtf(y0 * y0 + y1 * y1 + y2 * y2);
+        bool fallback = !(ny > 0.0f);
+        float ux = fallback ? st[0] : y0, uy = fallback ? st[1] : y1, uz = fallback ? st[2] : y2;
+        if (a.start_only) {
+          const float r = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
+          bx0 = ux * r; by0 = uy * r; bz0 = uz * r;
+          fallback = false;
+        } else if (cn > 0.0f) {
+#pragma unroll
+          for (int k = 0; k < K; ++k) c[k] *= inv;
+          const float alpha = fmaxf(0.0f, -unfolding_lambda_min<N>(c));
+          bool conv;
+          const float lam = refine<N>(c, alpha, ux, uy, uz, a.tol, a.max_iter, a.newton, n_steps,
+                                      n_newton, conv);
+          fallback = fallback || !conv || !(lam >= a.kappa);
+          bx0 = ux; by0 = uy; bz0 = uz;
+          canonical(bx0, by0, bz0);
+          lam_best = lam * cn;
+          n_oriented = 1;
+        } else {
+          fallback = false;
+        }
+        if (active && fallback) {
+          const unsigned slot = atomicAdd(a.fb_count, 1u);
+          a.fb_queue[slot] = (unsigned)v;
+        }
+      } else if (cn > 0.0f) {
+        // ---- plain multistart
 #pragma unroll
         for (int k = 0; k < K; ++k) c[k] *= inv;
         const float alpha = fmaxf(0.0f, -unfolding_lambda_min<N>(c));
-        lam_best = -INFINITY;
-        int s = 0, it = 0;
-        float ux = st[0], uy = st[1], uz = st[2];
-        float g0, g1, g2;
-        {
-          const float r = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
-          ux *= r; uy *= r; uz *= r;
-        }
-        contract<N>(c, ux, uy, uz, g0, g1, g2);
-        float lam = g0 * ux + g1 * uy + g2 * uz;
-        while (true) {
-          float wx = fmaf(alpha, ux, g0), wy = fmaf(alpha, uy, g1), wz = fmaf(alpha, uz, g2);
-          const float r = 1.0f / sqrtf(wx * wx + wy * wy + wz * wz);
-          ux = wx * r; uy = wy * r; uz = wz * r;
-          contract<N>(c, ux, uy, uz, g0, g1, g2);
-          const float lam_new = g0 * ux + g1 * uy + g2 * uz;
-          ++it;
-          ++n_steps;
-          const bool done = fabsf(lam_new - lam) <= a.tol || it >= a.max_iter;
-          lam = lam_new;
-          if (done) {
-            n_newton += newton_polish<N>(c, ux, uy, uz, g0, g1, g2, lam, a.newton);
-            if (lam > lam_best) {
-              lam_best = lam;
-              bx0 = ux; by0 = uy; bz0 = uz;
-            }
-            if (++s >= a.n_starts) break;
-            ux = st[3 * s]; uy = st[3 * s + 1]; uz = st[3 * s + 2];
-            const float rr = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
-            ux *= rr; uy *= rr; uz *= rr;
-            contract<N>(c, ux, uy, uz, g0, g1, g2);
-            lam = g0 * ux + g1 * uy + g2 * uz;
-            it = 0;
-          }
-        }
-        // u and -u are the same answer: make the last non-zero coordinate positive
-        const float sg = (bz0 != 0.0f) ? bz0 : ((by0 != 0.0f) ? by0 : bx0);
-        if (sg < 0.0f) {
-          bx0 = -bx0; by0 = -by0; bz0 = -bz0;
-        }
-        lam_best *= cn;
+        const float lam = multistart<N>(c, alpha, st, a.n_starts, a.tol, a.max_iter, a.newton, bx0,
+                                        by0, bz0, n_steps, n_newton);
+        canonical(bx0, by0, bz0);
+        lam_best = lam * cn;
         n_oriented = 1;
       }
       if (active) {
@@ -299,19 +376,71 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs a) {
   }
 }
 
+// Fallback of the learned start: the voxels queued by k_extract run the full
+// multistart search; the better of that and the learned answer is kept.
+template <int N>
+__global__ __launch_bounds__(256) void k_extract_fallback(ExtractArgs a) {
+  constexpr int K = ncomp3(N);
+  __shared__ float st[64 * 3];
+  for (int i = threadIdx.x; i < a.n_starts * 3; i += blockDim.x) st[i] = a.starts[i];
+  __syncthreads();
+  const unsigned count = *a.fb_count;
+  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && a.fb_total) atomicAdd(a.fb_total, (int)count);
+  if (i >= count) return;
+  const size_t v = a.fb_queue[i];
+  float c[K];
+  const float cn = load_tensor<N>(a, v, c);
+  if (!(cn > 0.0f)) return;
+  const float inv = 1.0f / cn;
+#pragma unroll
+  for (int k = 0; k < K; ++k) c[k] *= inv;
+  const float alpha = fmaxf(0.0f, -unfolding_lambda_min<N>(c));
+  unsigned long long n_steps = 0, n_newton = 0;
+  float bx0 = 0.0f, by0 = 0.0f, bz0 = 0.0f;
+  const float lam = multistart<N>(c, alpha, st, a.n_starts, a.tol, a.max_iter, a.newton, bx0, by0,
+                                  bz0, n_steps, n_newton) * cn;
+  const size_t o = map_index(a, v);
+  if (lam > a.lam[o]) {
+    canonical(bx0, by0, bz0);
+    a.lam[o] = lam;
+    a.dir[3 * o + 0] = bx0;
+    a.dir[3 * o + 1] = by0;
+    a.dir[3 * o + 2] = bz0;
+  }
+  if (a.counters) {
+    atomicAdd(a.counters + 0, n_steps);
+    atomicAdd(a.counters + 1, n_newton);
+  }
+}
+
 }  // namespace
 
-int launch_extract(int degree, const ExtractArgs& a, hipStream_t s) {
+template <int N>
+int launch_n(const ExtractArgs& a, hipStream_t s) {
   const unsigned nb = (unsigned)((a.plane + 255) / 256);
-  switch (degree) {
-    case 0: hipLaunchKernelGGL(k_extract<0>, dim3(nb), dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_extract<2>, dim3(nb), dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL(k_extract<4>, dim3(nb), dim3(256), 0, s, a); break;
-    case 6: hipLaunchKernelGGL(k_extract<6>, dim3(nb), dim3(256), 0, s, a); break;
-    default: set_error("ttm_extract: degree %d not built for d'=3 extraction", degree); return -4;
+  if constexpr (N >= 2) {
+    if ((a.mode & 6) == 6) {
+      hipLaunchKernelGGL((k_extract<N, true>), dim3(nb), dim3(256), 0, s, a);
+      if (!a.start_only) hipLaunchKernelGGL(k_extract_fallback<N>, dim3(nb), dim3(256), 0, s, a);
+    } else {
+      hipLaunchKernelGGL((k_extract<N, false>), dim3(nb), dim3(256), 0, s, a);
+    }
+  } else {
+    hipLaunchKernelGGL((k_extract<N, false>), dim3(nb), dim3(256), 0, s, a);
   }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : hip_status(e, "extract launch");
+}
+
+int launch_extract(int degree, const ExtractArgs& a, hipStream_t s) {
+  switch (degree) {
+    case 0: return launch_n<0>(a, s);
+    case 2: return launch_n<2>(a, s);
+    case 4: return launch_n<4>(a, s);
+    case 6: return launch_n<6>(a, s);
+    default: set_error("ttm_extract: degree %d not built for d'=3 extraction", degree); return -4;
+  }
 }
 
 }  // namespace ttm

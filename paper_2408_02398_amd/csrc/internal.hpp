@@ -92,6 +92,13 @@ struct ExtractArgs {
   float tol;
   int newton;          // Newton polishing steps per start
   unsigned long long* counters;  // optional: {SS-HOPM steps, Newton steps, oriented voxels}
+  // learned start
+  const unsigned char* mlp;      // packed BF16 parameters
+  float kappa;                   // fall back when lambda / ||C||_F < kappa
+  int start_only;                // write the network's start direction only
+  unsigned* fb_count;            // fallback queue length (workspace)
+  unsigned* fb_queue;            // fallback voxel indices (workspace)
+  int* fb_total;                 // optional caller counter of fallbacks
 };
 int launch_extract(int degree, const ExtractArgs& a, hipStream_t s);
 
@@ -100,6 +107,13 @@ size_t peaks_workspace(int64_t n_voxels);
 int find_peaks(const float* score, int nz, int ny, int nx, const int32_t lo[3],
                const int32_t hi[3], int top_p, float min_dist, int32_t* peaks_out,
                float* vals_out, int32_t* n_found_host, void* ws, size_t ws_bytes, hipStream_t s);
+
+// Learned start training (mlp.hip).
+size_t mlp_train_workspace(int B);
+int mlp_train_step(int degree, const float* Cin, const float* T, int B, float* params, float* adam_m,
+                   float* adam_v, int step, float lr, unsigned char* packed, float* loss_out,
+                   float* grads_out, void* ws, hipStream_t s);
+int mlp_pack(const float* params, unsigned char* packed, hipStream_t s);
 
 // Zero-fill with a kernel (graph-capture friendly, unlike memset nodes).
 void fill_zero(void* p, size_t bytes, hipStream_t s);

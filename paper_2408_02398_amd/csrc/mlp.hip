@@ -1,0 +1,278 @@
+// mlp.hip -- training of the learned start on the GPU (BF16 matrix cores, FP32
+// accumulation and FP32 master weights with Adam), and packing of the
+// inference parameters.
+//
+// One training step on a batch of B (tensor, target direction) pairs:
+//   X  = features(C)                         B x 32
+//   Z1 = X W1 + b1,  H1 = bf16(relu Z1)      B x 64
+//   Z2 = H1 W2 + b2, H2 = bf16(relu Z2)      B x 64
+//   Y  = H2 W3 + b3                          B x 16 (3 used)
+//   L  = mean_b 1 - (y_b . t_b / |y_b||t_b|)^2
+//   dY, then dW3 = H2^T dY, dZ2 = (dY W3^T) * [Z2 > 0], dW2 = H1^T dZ2,
+//   dZ1 = (dZ2 W2^T) * [Z1 > 0], dW1 = X^T dZ1, bias gradients = column sums,
+//   Adam on the FP32 masters, then the BF16 fragment-ordered inference copy.
+// Every product goes through one BF16 MFMA GEMM kernel (operands rounded to
+// BF16 on load, FP32 accumulation).
+#include "internal.hpp"
+#include "mlp_core.hpp"
+#include "sym_tables.hpp"
+
+namespace ttm {
+
+namespace {
+
+// C[M][N] = op(A)[M][K] op(B)[K][N] with op = transpose when TA / TB.
+// A element (m, k) = TA ? A[k * lda + m] : A[m * lda + k]; B (k, n) likewise.
+// Epilogues: 0 store; 1 + bias[n]; 2 + bias[n], store Z to C and
+// bf16(relu(Z)) to C2; 3 multiply by [mask[m][n] > 0].
+// Workgroup: 4 wavefronts, 32 x 32 output tile, K in steps of 16.
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm_bf16(const float* __restrict__ A, int lda,
+                                                   const float* __restrict__ B, int ldb,
+                                                   float* __restrict__ C, int ldc, int M, int N,
+                                                   int K, int epi, const float* __restrict__ bias,
+                                                   float* __restrict__ C2,
+                                                   const float* __restrict__ mask) {
+  __shared__ unsigned short As[32][16 + 2];
+  __shared__ unsigned short Bs[16][32 + 2];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
+  const int wm = (w >> 1) * 16, wn = (w & 1) * 16;
+  const int r16 = lane & 15, q = lane >> 4;
+  f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    // 512 A elements and 512 B elements per step; 2 of each per thread
+    for (int e = tid; e < 512; e += 256) {
+      const int r = e / 16, c = e % 16;       // A tile (32 x 16)
+      const int m = m0 + r, k = k0 + c;
+      float va = 0.0f;
+      if (m < M && k < K) va = TA ? A[(size_t)k * lda + m] : A[(size_t)m * lda + k];
+      As[r][c] = bf16_bits(va);
+      const int kb = e / 32, nb = e % 32;     // B tile (16 x 32)
+      const int kk = k0 + kb, n = n0 + nb;
+      float vb = 0.0f;
+      if (kk < K && n < N) vb = TB ? B[(size_t)n * ldb + kk] : B[(size_t)kk * ldb + n];
+      Bs[kb][nb] = bf16_bits(vb);
+    }
+    __syncthreads();
+    bf16x4 a, b;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      a[j] = (short)As[wm + r16][4 * q + j];
+      b[j] = (short)Bs[4 * q + j][wn + r16];
+    }
+    acc = mfma16(a, b, acc);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int m = m0 + wm + 4 * q + j, n = n0 + wn + r16;
+    if (m >= M || n >= N) continue;
+    float v = acc[j];
+    const size_t o = (size_t)m * ldc + n;
+    if (epi == 1 || epi == 2) v += bias[n];
+    if (epi == 3) v = mask[o] > 0.0f ? v : 0.0f;
+    C[o] = v;
+    if (epi == 2) C2[o] = bf16_round(fmaxf(v, 0.0f));
+  }
+}
+
+// x = sqrt(mu_a) C_a / ||C||_F, zero padded to 32 columns; C is B x K (row per sample).
+template <int N>
+__global__ void k_features(const float* __restrict__ Cin, int B, float* __restrict__ X) {
+  constexpr int K = ncomp3(N);
+  constexpr Sym3<N> sy{};
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  float c[K];
+  float f2 = 0.0f;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    c[k] = Cin[(size_t)b * K + k] * sqrtf(sy.mu[k]);
+    f2 = fmaf(c[k], c[k], f2);
+  }
+  const float inv = f2 > 0.0f ? 1.0f / sqrtf(f2) : 0.0f;
+#pragma unroll
+  for (int k = 0; k < kMlpIn; ++k) X[(size_t)b * kMlpIn + k] = k < K ? c[k] * inv : 0.0f;
+}
+
+// dL/dY for L = mean 1 - (u.t)^2, u = y/|y|: dY = -2 c (t - c u) / (|y| B); per-block loss sums.
+__global__ __launch_bounds__(256) void k_loss(const float* __restrict__ Y, const float* __restrict__ T,
+                                              int B, float* __restrict__ dY,
+                                              float* __restrict__ part) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  float l = 0.0f;
+  if (b < B) {
+    const float y0 = Y[(size_t)b * kMlpOut], y1 = Y[(size_t)b * kMlpOut + 1], y2 = Y[(size_t)b * kMlpOut + 2];
+    float t0 = T[3 * b], t1 = T[3 * b + 1], t2 = T[3 * b + 2];
+    const float tn = 1.0f / sqrtf(t0 * t0 + t1 * t1 + t2 * t2);
+    t0 *= tn; t1 *= tn; t2 *= tn;
+    const float ny = sqrtf(y0 * y0 + y1 * y1 + y2 * y2);
+    const float iy = ny > 0.0f ? 1.0f / ny : 0.0f;
+    const float u0 = y0 * iy, u1 = y1 * iy, u2 = y2 * iy;
+    const float c = u0 * t0 + u1 * t1 + u2 * t2;
+    l = 1.0f - c * c;
+    const float s = -2.0f * c * iy / (float)B;
+    float* d = dY + (size_t)b * kMlpOut;
+    d[0] = s * (t0 - c * u0);
+    d[1] = s * (t1 - c * u1);
+    d[2] = s * (t2 - c * u2);
+    for (int k = 3; k < kMlpOut; ++k) d[k] = 0.0f;
+  }
+  __shared__ float red[256];
+  red[threadIdx.x] = l;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Column sums of a B x N matrix (bias gradients): one thread per column, fixed order.
+__global__ void k_colsum(const float* __restrict__ D, int B, int N, float* __restrict__ out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.0f;
+  for (int b = 0; b < B; ++b) s += D[(size_t)b * N + n];
+  out[n] = s;
+}
+
+__global__ void k_sum(const float* __restrict__ part, int n, float scale, float* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    float s = 0.0f;
+    for (int i = 0; i < n; ++i) s += part[i];
+    out[0] = s * scale;
+  }
+}
+
+// Adam with bias correction on the FP32 masters; padded rows / columns stay 0.
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int n_params, float lr, float b1, float b2, float eps,
+                       float bc1, float bc2, int K, int dout) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_params) return;
+  bool pad = false;
+  if (i < kOffB1) pad = (i / kMlpHid) >= K;                               // W1 rows >= K
+  else if (i >= kOffW3 && i < kOffB3) pad = ((i - kOffW3) % kMlpOut) >= dout;
+  else if (i >= kOffB3) pad = (i - kOffB3) >= dout;
+  if (pad) {
+    p[i] = 0.0f;
+    m[i] = 0.0f;
+    v[i] = 0.0f;
+    return;
+  }
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// FP32 masters -> BF16 fragment-ordered weights + FP32 biases.
+__global__ void k_pack(const float* __restrict__ p, unsigned char* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  // fragments: W1 8, W2 16, W3 4 -> 28 fragments x 64 lanes x 4 values
+  if (t < 28 * 64) {
+    const int frag = t / 64, lane = t % 64, r16 = lane & 15, q = lane >> 4;
+    const float* W;
+    int ld, s, nt, off, f;
+    if (frag < 8) {
+      W = p + kOffW1; ld = kMlpHid; f = frag; off = kPkW1;
+    } else if (frag < 24) {
+      W = p + kOffW2; ld = kMlpHid; f = frag - 8; off = kPkW2;
+    } else {
+      W = p + kOffW3; ld = kMlpOut; f = frag - 24; off = kPkW3;
+    }
+    if (frag < 24) {
+      s = f / 4; nt = f % 4;
+    } else {
+      s = f; nt = 0;
+    }
+    unsigned short* o = reinterpret_cast<unsigned short*>(out + off) + ((size_t)f * 64 + lane) * 4;
+    for (int j = 0; j < 4; ++j) o[j] = bf16_bits(W[(16 * s + 4 * q + j) * ld + 16 * nt + r16]);
+  }
+  if (t < kMlpHid) {
+    reinterpret_cast<float*>(out + kPkB1)[t] = p[kOffB1 + t];
+    reinterpret_cast<float*>(out + kPkB2)[t] = p[kOffB2 + t];
+  }
+  if (t < kMlpOut) reinterpret_cast<float*>(out + kPkB3)[t] = p[kOffB3 + t];
+}
+
+template <bool TA, bool TB>
+void gemm(const float* A, int lda, const float* B, int ldb, float* C, int ldc, int M, int N, int K,
+          int epi, const float* bias, float* C2, const float* mask, hipStream_t s) {
+  hipLaunchKernelGGL((k_gemm_bf16<TA, TB>), dim3((N + 31) / 32, (M + 31) / 32), dim3(256), 0, s,
+                     A, lda, B, ldb, C, ldc, M, N, K, epi, bias, C2, mask);
+}
+
+}  // namespace
+
+size_t mlp_train_workspace(int B) {
+  // X (32) + Z1, H1, Z2, H2, dZ1, dZ2 (64 each) + Y, dY (16 each) per sample,
+  // gradient block, loss partials
+  return ((size_t)B * (32 + 6 * 64 + 2 * 16) + kMlpParams + (B + 255) / 256 + 64) * 4 + 1024;
+}
+
+int mlp_train_step(int degree, const float* Cin, const float* T, int B, float* params, float* adam_m,
+                   float* adam_v, int step, float lr, unsigned char* packed, float* loss_out,
+                   float* grads_out, void* ws, hipStream_t s) {
+  float* w = static_cast<float*>(ws);
+  float* X = w;
+  float* Z1 = X + (size_t)B * 32;
+  float* H1 = Z1 + (size_t)B * 64;
+  float* Z2 = H1 + (size_t)B * 64;
+  float* H2 = Z2 + (size_t)B * 64;
+  float* dZ1 = H2 + (size_t)B * 64;
+  float* dZ2 = dZ1 + (size_t)B * 64;
+  float* Y = dZ2 + (size_t)B * 64;
+  float* dY = Y + (size_t)B * 16;
+  float* G = dY + (size_t)B * 16;
+  float* part = G + kMlpParams;
+  const int nb = (B + 255) / 256;
+  switch (degree) {
+    case 2: hipLaunchKernelGGL(k_features<2>, dim3(nb), dim3(256), 0, s, Cin, B, X); break;
+    case 4: hipLaunchKernelGGL(k_features<4>, dim3(nb), dim3(256), 0, s, Cin, B, X); break;
+    case 6: hipLaunchKernelGGL(k_features<6>, dim3(nb), dim3(256), 0, s, Cin, B, X); break;
+    default: set_error("mlp: degree %d not built", degree); return -4;
+  }
+  const float* W1 = params + kOffW1;
+  const float* W2 = params + kOffW2;
+  const float* W3 = params + kOffW3;
+  // forward
+  gemm<false, false>(X, 32, W1, 64, Z1, 64, B, 64, 32, 2, params + kOffB1, H1, nullptr, s);
+  gemm<false, false>(H1, 64, W2, 64, Z2, 64, B, 64, 64, 2, params + kOffB2, H2, nullptr, s);
+  gemm<false, false>(H2, 64, W3, 16, Y, 16, B, 16, 64, 1, params + kOffB3, nullptr, nullptr, s);
+  hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, s, Y, T, B, dY, part);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(64), 0, s, part, nb, 1.0f / (float)B, loss_out);
+  // backward
+  gemm<true, false>(H2, 64, dY, 16, G + kOffW3, 16, 64, 16, B, 0, nullptr, nullptr, nullptr, s);
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(64), 0, s, dY, B, 16, G + kOffB3);
+  gemm<false, true>(dY, 16, W3, 16, dZ2, 64, B, 64, 16, 3, nullptr, nullptr, Z2, s);
+  gemm<true, false>(H1, 64, dZ2, 64, G + kOffW2, 64, 64, 64, B, 0, nullptr, nullptr, nullptr, s);
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(64), 0, s, dZ2, B, 64, G + kOffB2);
+  gemm<false, true>(dZ2, 64, W2, 64, dZ1, 64, B, 64, 64, 3, nullptr, nullptr, Z1, s);
+  gemm<true, false>(X, 32, dZ1, 64, G + kOffW1, 64, 32, 64, B, 0, nullptr, nullptr, nullptr, s);
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(64), 0, s, dZ1, B, 64, G + kOffB1);
+  if (grads_out) {
+    TTM_HIP(hipMemcpyAsync(grads_out, G, kMlpParams * 4, hipMemcpyDeviceToDevice, s));
+  }
+  if (lr > 0.0f) {
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float bc1 = 1.0f - powf(b1, (float)step), bc2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, params, G, adam_m,
+                       adam_v, kMlpParams, lr, b1, b2, eps, bc1, bc2, ncomp3(degree), 3);
+  }
+  if (packed) hipLaunchKernelGGL(k_pack, dim3(7), dim3(256), 0, s, params, packed);
+  TTM_HIP(hipGetLastError());
+  return 0;
+}
+
+int mlp_pack(const float* params, unsigned char* packed, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack, dim3(7), dim3(256), 0, s, params, packed);
+  TTM_HIP(hipGetLastError());
+  return 0;
+}
+
+}  // namespace ttm

@@ -27,7 +27,7 @@ namespace ttm {
 
 namespace {
 
-constexpr int kHistBins = 65536;
+constexpr int kHistBins = 4096;   // per level: bits [31:20], then [19:8]
 constexpr int kSortIPT = 16;           // keys per thread per sort block
 constexpr int kSortBlock = 256;        // threads per sort block
 constexpr int kSortTile = kSortIPT * kSortBlock;
@@ -42,22 +42,43 @@ struct Region {
   int z0, y0, x0, z1, y1, x1;  // inclusive valid box
 };
 
-__global__ void k_hist(const float* __restrict__ score, Region r, unsigned* __restrict__ hist) {
-  const int x = r.x0 + blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = r.y0 + blockIdx.y, z = r.z0 + blockIdx.z;
-  if (x > r.x1) return;
-  const unsigned b = score_bits(score[((size_t)z * r.ny + y) * r.nx + x]) >> 16;
-  atomicAdd(&hist[b], 1u);
+// Histogram of one 12-bit field of the score bit patterns over the region,
+// privatised in LDS per workgroup.  level 0: bits [31:20] of every voxel;
+// level 1: bits [19:8] of the voxels whose bits [31:20] equal `top`.
+// Each workgroup covers 8 rows (y) of one z slice.
+__global__ __launch_bounds__(256) void k_hist(const float* __restrict__ score, Region r, int level,
+                                              unsigned top, unsigned* __restrict__ hist) {
+  __shared__ unsigned h[kHistBins];
+  for (int i = threadIdx.x; i < kHistBins; i += 256) h[i] = 0;
+  __syncthreads();
+  const int z = r.z0 + blockIdx.z;
+  const int nxv = r.x1 - r.x0 + 1;
+  for (int yy = 0; yy < 8; ++yy) {
+    const int y = r.y0 + blockIdx.y * 8 + yy;
+    if (y > r.y1) break;
+    const float* row = score + ((size_t)z * r.ny + y) * r.nx + r.x0;
+    for (int x = blockIdx.x * 256 + threadIdx.x; x < nxv; x += 256 * gridDim.x) {
+      const unsigned b = score_bits(row[x]);
+      if (level == 0) {
+        atomicAdd(&h[b >> 20], 1u);
+      } else if ((b >> 20) == top) {
+        atomicAdd(&h[(b >> 8) & 0xFFFu], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kHistBins; i += 256)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
 }
 
-__global__ void k_compact(const float* __restrict__ score, Region r, unsigned bin_lo,
+__global__ void k_compact(const float* __restrict__ score, Region r, unsigned key_lo,
                           unsigned long long* __restrict__ keys, unsigned* __restrict__ counter) {
   const int x = r.x0 + blockIdx.x * blockDim.x + threadIdx.x;
   const int y = r.y0 + blockIdx.y, z = r.z0 + blockIdx.z;
   if (x > r.x1) return;
   const size_t lin = ((size_t)z * r.ny + y) * r.nx + x;
   const unsigned bits = score_bits(score[lin]);
-  if ((bits >> 16) >= bin_lo) {
+  if (bits >= key_lo) {
     const unsigned slot = atomicAdd(counter, 1u);
     keys[slot] = ((unsigned long long)(~bits) << 32) | (unsigned long long)lin;
   }
@@ -296,29 +317,53 @@ int find_peaks(const float* score, int nz, int ny, int nx, const int32_t lo[3],
   int* nfound_dev = reinterpret_cast<int*>(counter + 64);
   unsigned* shist = reinterpret_cast<unsigned*>(nfound_dev + 64);
 
-  fill_zero(hist, kHistBins * 4, s);
   const dim3 grid((hi[2] - lo[2] + 1 + 255) / 256, hi[1] - lo[1] + 1, hi[0] - lo[0] + 1);
-  hipLaunchKernelGGL(k_hist, grid, dim3(256), 0, s, score, r, hist);
-  std::vector<unsigned> h(kHistBins);
-  TTM_HIP(hipMemcpyAsync(h.data(), hist, kHistBins * 4, hipMemcpyDeviceToHost, s));
+  const dim3 hgrid(1, (hi[1] - lo[1] + 1 + 7) / 8, hi[0] - lo[0] + 1);
+  std::vector<unsigned> h0(kHistBins), h1(kHistBins);
+  fill_zero(hist, kHistBins * 4, s);
+  hipLaunchKernelGGL(k_hist, hgrid, dim3(256), 0, s, score, r, 0, 0u, hist);
+  TTM_HIP(hipMemcpyAsync(h0.data(), hist, kHistBins * 4, hipMemcpyDeviceToHost, s));
   TTM_HIP(hipStreamSynchronize(s));
+  int top_cached = -1;
 
   int64_t want = std::max<int64_t>(64 * (int64_t)top_p, 1 << 16);
   while (true) {
-    // lowest bin such that the bins at or above it hold >= want voxels
-    int64_t acc = 0;
-    int bin = kHistBins - 1;
-    for (; bin >= 0; --bin) {
-      acc += h[bin];
-      if (acc >= want) break;
+    // coarse bin (bits 31:20) such that it and the bins above hold >= want voxels
+    int64_t above = 0;
+    int b0 = kHistBins - 1;
+    for (; b0 >= 0; --b0) {
+      if (above + h0[b0] >= want) break;
+      above += h0[b0];
     }
-    if (bin < 0) bin = 0;
-    const bool all = (acc >= nvalid) || bin == 0;
+    unsigned key_lo = 0;
+    int64_t acc = 0;
+    if (b0 < 0) {
+      key_lo = 0;             // every voxel
+      acc = above;
+    } else {
+      if (top_cached != b0) {
+        fill_zero(hist, kHistBins * 4, s);
+        hipLaunchKernelGGL(k_hist, hgrid, dim3(256), 0, s, score, r, 1, (unsigned)b0, hist);
+        TTM_HIP(hipMemcpyAsync(h1.data(), hist, kHistBins * 4, hipMemcpyDeviceToHost, s));
+        TTM_HIP(hipStreamSynchronize(s));
+        top_cached = b0;
+      }
+      int64_t in = 0;
+      int b1 = kHistBins - 1;
+      for (; b1 > 0; --b1) {
+        if (above + in + h1[b1] >= want) break;
+        in += h1[b1];
+      }
+      in += h1[b1];
+      key_lo = ((unsigned)b0 << 20) | ((unsigned)b1 << 8);
+      acc = above + in;
+    }
+    const bool all = (acc >= nvalid) || key_lo == 0;
     const int64_t m = acc;
     const size_t mpad = ((size_t)m + kSortTile - 1) / kSortTile * kSortTile;
     const int nblk = (int)(mpad / kSortTile);
     fill_zero(counter, 4, s);
-    hipLaunchKernelGGL(k_compact, grid, dim3(256), 0, s, score, r, (unsigned)bin, keys_a, counter);
+    hipLaunchKernelGGL(k_compact, grid, dim3(256), 0, s, score, r, key_lo, keys_a, counter);
     if (mpad > (size_t)m) {
       hipLaunchKernelGGL(k_fill, dim3((unsigned)((mpad - m + 255) / 256)), dim3(256), 0, s, keys_a,
                          (size_t)m, mpad);

@@ -138,8 +138,15 @@ def correlate(ctx: Context, desc: Desc, g: torch.Tensor, w: torch.Tensor, stats:
 def extract(ctx: Context, desc: Desc, Cf: torch.Tensor, *, score=None, lam=None, direction=None,
             out_lo=(0, 0, 0), out_dims=None, starts: torch.Tensor | None = None,
             orient: bool = True, max_iter: int = 500, tol: float = 1e-5, newton: int = 2,
-            counters: torch.Tensor | None = None):
-    """Score / lambda / direction maps for the box held in Cf (K x bz x by x bx)."""
+            counters: torch.Tensor | None = None, mlp: "MLP | None" = None, kappa: float = 0.0,
+            start_only: bool = False, fallbacks: torch.Tensor | None = None,
+            ws: torch.Tensor | None = None):
+    """Score / lambda / direction maps for the box held in Cf (K x bz x by x bx).
+
+    With ``mlp`` the orientation search starts from the learned start and falls
+    back to the multistart search where lambda / ||C|| < kappa or SS-HOPM did
+    not converge.  ``fallbacks`` (device int32[1]) accumulates the fallback count.
+    """
     _need_cuda(Cf, score, lam, direction, starts)
     box = tuple(Cf.shape[1:])
     if out_dims is None:
@@ -159,6 +166,14 @@ def extract(ctx: Context, desc: Desc, Cf: torch.Tensor, *, score=None, lam=None,
             raise ValueError("orientation needs start vectors")
         opts.n_starts = starts.shape[0]
         opts.starts = starts.data_ptr()
+        if mlp is not None:
+            mode |= L.TTM_START_MLP
+            if start_only:
+                mode |= L.TTM_START_ONLY
+            opts.mlp = mlp.packed.data_ptr()
+            opts.fallback_kappa = kappa
+            if ws is None:
+                ws = _ws(desc, L.TTM_OP_EXTRACT, 0, box, device=dev)
     opts.mode = mode
     opts.max_iter = max_iter
     opts.tol = tol
@@ -170,8 +185,47 @@ def extract(ctx: Context, desc: Desc, Cf: torch.Tensor, *, score=None, lam=None,
     code = L.TTM_BF16 if Cf.dtype == torch.bfloat16 else L.TTM_F32
     call("ttm_extract", ctx.h, C.byref(desc), _ptr(Cf), code, I32x3(*box), C.byref(opts),
          _ptr(score), _ptr(lam) if orient else None, _ptr(direction) if orient else None,
-         I32x3(*out_lo), I32x3(*out_dims), None, _stream())
+         I32x3(*out_lo), I32x3(*out_dims), _ptr(fallbacks), _ptr(ws),
+         0 if ws is None else ws.numel(), _stream())
     return score, lam, direction
+
+
+class MLP:
+    """Learned start: FP32 master parameters, Adam moments and the packed BF16 copy."""
+
+    def __init__(self, ctx: Context, desc: Desc, params: torch.Tensor):
+        lib = load()
+        self.n_params = lib.ttm_mlp_param_count()
+        if params.numel() != self.n_params or params.dtype != torch.float32 or not params.is_cuda:
+            raise ValueError(f"params must be {self.n_params} float32 device values")
+        self.ctx, self.desc = ctx, desc
+        self.params = params.contiguous().clone()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.packed = torch.empty(lib.ttm_mlp_packed_bytes(), dtype=torch.uint8, device=params.device)
+        self.step = 0
+        self.loss = torch.zeros(1, dtype=torch.float32, device=params.device)
+        self._ws = None
+        self.pack()
+
+    def pack(self):
+        call("ttm_mlp_pack", self.ctx.h, _ptr(self.params), _ptr(self.packed), _stream())
+
+    def train_step(self, Cs: torch.Tensor, targets: torch.Tensor, lr: float,
+                   grads: torch.Tensor | None = None) -> torch.Tensor:
+        """One Adam step on a batch (Cs: B x K raw tensors, targets: B x 3); returns the loss."""
+        _need_cuda(Cs, targets, grads)
+        B = Cs.shape[0]
+        if self._ws is None or self._ws.numel() < load().ttm_workspace_size(
+                C.byref(self.desc), L.TTM_OP_MLP_TRAIN, 0, B, 1, 1):
+            self._ws = _ws(self.desc, L.TTM_OP_MLP_TRAIN, 0, (B, 1, 1), device=Cs.device)
+        if lr > 0:
+            self.step += 1
+        call("ttm_mlp_train_step", self.ctx.h, C.byref(self.desc), _ptr(Cs), _ptr(targets), B,
+             _ptr(self.params), _ptr(self.m), _ptr(self.v), max(self.step, 1), float(lr),
+             _ptr(self.packed), _ptr(self.loss), _ptr(grads), _ptr(self._ws), self._ws.numel(),
+             _stream())
+        return self.loss
 
 
 def find_peaks(ctx: Context, score: torch.Tensor, valid_lo, valid_hi, top_p: int, min_dist: float,
@@ -250,11 +304,13 @@ class Engine:
 
     def __init__(self, ctx: Context, desc: Desc, spectra: torch.Tensor, fft_n: int, shape,
                  starts: torch.Tensor | None, field_dtype=torch.float32, orient: bool = True,
-                 max_iter: int = 500, tol: float = 1e-5, newton: int = 2):
+                 max_iter: int = 500, tol: float = 1e-5, newton: int = 2,
+                 mlp: MLP | None = None, kappa: float = 0.0):
         self.ctx, self.desc, self.spectra, self.fft_n = ctx, desc, spectra, fft_n
         self.shape = tuple(shape)
         self.starts, self.orient = starts, orient
         self.max_iter, self.tol, self.newton = max_iter, tol, newton
+        self.mlp, self.kappa = mlp, kappa
         dev = spectra.device
         nz, ny, nx = self.shape
         K = n_components(desc.degree, desc.dprime)
@@ -265,6 +321,8 @@ class Engine:
         self.ws_norm = _ws(desc, L.TTM_OP_NORMALIZE, fft_n, self.shape, device=dev)
         self.ws_corr = _ws(desc, L.TTM_OP_CORRELATE, fft_n, self.shape, device=dev)
         self.ws_peaks = _ws(desc, L.TTM_OP_PEAKS, fft_n, self.shape, device=dev)
+        self.ws_extract = _ws(desc, L.TTM_OP_EXTRACT, 0, (step, step, step), device=dev)
+        self.fallbacks = torch.zeros(1, dtype=torch.int32, device=dev)
         self.score = torch.zeros(self.shape, dtype=torch.float32, device=dev)
         self.lam = torch.zeros(self.shape, dtype=torch.float32, device=dev) if orient else None
         self.dir = torch.zeros((*self.shape, 3), dtype=torch.float32, device=dev) if orient else None
@@ -278,7 +336,8 @@ class Engine:
                       ws=self.ws_corr)
             extract(self.ctx, self.desc, Ct, score=self.score, lam=self.lam, direction=self.dir,
                     out_lo=lo, out_dims=self.shape, starts=self.starts, orient=self.orient,
-                    max_iter=self.max_iter, tol=self.tol, newton=self.newton)
+                    max_iter=self.max_iter, tol=self.tol, newton=self.newton, mlp=self.mlp,
+                    kappa=self.kappa, fallbacks=self.fallbacks, ws=self.ws_extract)
         peaks = vals = None
         if top_p:
             vlo, vhi = valid_bounds(self.shape, self.desc.L)

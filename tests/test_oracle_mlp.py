@@ -82,3 +82,13 @@ def test_training_reduces_loss_on_a_learnable_map():
         mlp.adam_step(p, mlp.backward(p, cache, v), st, lr=3e-3)
     l1 = mlp.loss(mlp.forward(p, X)[0], v)
     assert l1 < 0.2 * l0
+
+
+def test_bf16_round_known_values():
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -9, -2.5, 3.140625, 1e-3])
+    r = mlp.bf16_round(vals)
+    assert r[0] == 1.0
+    assert r[1] == 1.0                      # tie: rounds to even mantissa
+    assert r[2] == 1.0 + 2 ** -7            # above the tie: rounds up
+    assert r[3] == -2.5 and r[4] == 3.140625
+    assert abs(r[5] - 1e-3) / 1e-3 < 2 ** -8
