@@ -199,9 +199,11 @@ typedef struct {
  * Learned start (TTM_START_MLP): per wavefront of 64 voxels the network
  * (ttm_mlp_train_step) maps x = sqrt(mu_a) C_a / ||C||_F to a start direction
  * on the BF16 matrix cores; SS-HOPM (+ polish) runs from it alone.  Voxels
- * whose result is not converged or has lambda < fallback_kappa * ||C||_F are
- * queued and re-run by a second kernel with the full multistart search, and
- * the better of the two answers is kept.  Requires lambda and dir.
+ * whose result is not converged, has lambda < fallback_kappa * ||C||_F, or is
+ * beaten by the value of <C, s^n> at one of the fixed starts s (SS-HOPM never
+ * lowers lambda, so the multistart answer is then higher) are queued and
+ * re-run by a second kernel with the full multistart search; the better of
+ * the two answers is kept.  Requires lambda and dir.
  * Orientation: alpha = max(0, -lambda_min(U)) with U the square unfolding of
  * C/||C||_F; SS-HOPM u <- (C u^{n-1} + alpha u)/||.|| from every start until
  * |delta lambda| <= tol or max_iter, then up to newton_steps Riemannian Newton

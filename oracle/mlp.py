@@ -151,8 +151,10 @@ def orient_learned(Cv: np.ndarray, n: int, p: dict, starts: np.ndarray, kappa: f
     """Orientation with the learned start and its multistart fallback (d' = 3).
 
     SS-HOPM (+ polish) from the network's direction; if it does not reach tol,
-    or lambda / ||C||_F < kappa, the multistart search runs too and the larger
-    lambda wins.  Returns (lambda, u, fell_back).
+    or lambda / ||C||_F < kappa, or some fixed start already has a larger value
+    of <C, s^n> than the learned lambda (SS-HOPM never decreases lambda, so the
+    multistart answer is then larger), the multistart search runs too and the
+    larger lambda wins.  Returns (lambda, u, fell_back).
     """
     from . import ttm
     cn = float(sym.frobenius(Cv, n, 3))
@@ -167,7 +169,9 @@ def orient_learned(Cv: np.ndarray, n: int, p: dict, starts: np.ndarray, kappa: f
     lam, u, _, conv = ttm.sshopm(Cu, n, u0, alpha, tol, max_iter)
     u = ttm.newton_polish(Cu, n, u, newton)
     lam = float(sym.contract_n_minus_1(Cu, u, n) @ u)
-    if conv and ny > 0 and lam >= kappa:
+    # a fixed start scoring above the learned answer means the multistart wins
+    beaten = any(sym.inner_power(Cu, s / np.linalg.norm(s), n) > lam for s in starts)
+    if conv and ny > 0 and lam >= kappa and not beaten:
         return cn * lam, ttm.canonical_sign(u), False
     lam_p, u_p, *_ = ttm.orient_multistart(Cv, n, starts, tol, max_iter, newton=newton)
     if lam_p > cn * lam:

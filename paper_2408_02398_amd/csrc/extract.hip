@@ -335,7 +335,17 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs a) {
           bool conv;
           const float lam = refine<N>(c, alpha, ux, uy, uz, a.tol, a.max_iter, a.newton, n_steps,
                                       n_newton, conv);
-          fallback = fallback || !conv || !(lam >= a.kappa);
+          // screening: SS-HOPM never lowers lambda, so a fixed start that already
+          // scores above the learned answer proves the multistart answer is higher
+          bool beaten = false;
+          for (int s = 0; s < a.n_starts; ++s) {
+            const float sx = st[3 * s], sy = st[3 * s + 1], sz = st[3 * s + 2];
+            const float rs = 1.0f / sqrtf(sx * sx + sy * sy + sz * sz);
+            float q0, q1, q2;
+            contract<N>(c, sx * rs, sy * rs, sz * rs, q0, q1, q2);
+            beaten = beaten || ((q0 * sx + q1 * sy + q2 * sz) * rs > lam);
+          }
+          fallback = fallback || !conv || !(lam >= a.kappa) || beaten;
           bx0 = ux; by0 = uy; bz0 = uz;
           canonical(bx0, by0, bz0);
           lam_best = lam * cn;

@@ -6,11 +6,12 @@ labelled with the plain multistart answer at each sampled voxel.  Every step
 runs through libttm (correlation, extraction, the BF16 training kernels);
 this module only selects voxels and batches.
 
-Calibration picks the fallback threshold kappa on held-out voxels: the
-smallest kappa such that among voxels whose learned lambda / ||C||_F is at
-least kappa, at most `max_wrong` of them end more than 1 degree from the
-multistart answer.  Voxels below kappa (or not converged) take the multistart
-fallback.
+Calibration picks the fallback threshold kappa on held-out voxels of the
+highest scores (the voxels whose orientation is used): the smallest kappa
+such that among them, those whose learned lambda / ||C||_F is at least kappa
+end more than 1 degree from the multistart answer at most `max_wrong` of the
+time.  Voxels below kappa, not converged, or beaten by a fixed start take the
+multistart fallback.
 """
 from __future__ import annotations
 
@@ -118,7 +119,7 @@ def init_params(K: int, seed: int = 0, device="cuda") -> torch.Tensor:
 
 
 def build_learned_start(ctx, desc, spectra, fft_n, tomograms, starts, *, n_uniform=60000,
-                        n_top=60000, steps=3000, batch=4096, lr=3e-3, max_wrong=0.02, seed=0,
+                        n_top=60000, steps=6000, batch=8192, lr=3e-3, max_wrong=0.03, seed=0,
                         log=print) -> tuple:
     """Collect on all but the last tomogram, train, calibrate kappa on the last one."""
     t0 = time.time()
@@ -126,7 +127,8 @@ def build_learned_start(ctx, desc, spectra, fft_n, tomograms, starts, *, n_unifo
                   for i, v in enumerate(tomograms[:-1])]
     data = TrainingSet(torch.cat([d.C for d in train_sets]), torch.cat([d.u for d in train_sets]),
                        torch.cat([d.score for d in train_sets]))
-    held = collect(ctx, desc, spectra, fft_n, tomograms[-1], starts, n_uniform, n_top, seed + 99)
+    held = collect(ctx, desc, spectra, fft_n, tomograms[-1], starts, 0, n_top, seed + 99)
+    held_u = collect(ctx, desc, spectra, fft_n, tomograms[-1], starts, n_uniform, 0, seed + 98)
     torch.cuda.synchronize()
     t1 = time.time()
     K = ttm.n_components(desc.degree, desc.dprime)
@@ -135,6 +137,12 @@ def build_learned_start(ctx, desc, spectra, fft_n, tomograms, starts, *, n_unifo
     torch.cuda.synchronize()
     t2 = time.time()
     cal = calibrate(ctx, desc, net, held, starts, max_wrong=max_wrong)
+    ang_u, _, fb_u = evaluate(ctx, desc, net, held_u, starts, kappa=cal["kappa"])
+    ang_t, _, fb_t = evaluate(ctx, desc, net, held, starts, kappa=cal["kappa"])
+    cal.update({"heldout_top_within_1deg": float((ang_t <= 1.0).float().mean().item()),
+                "heldout_top_fallback": fb_t / len(ang_t),
+                "heldout_uniform_within_1deg": float((ang_u <= 1.0).float().mean().item()),
+                "heldout_uniform_fallback": fb_u / len(ang_u)})
     info = {"train_samples": int(data.C.shape[0]), "heldout_samples": int(held.C.shape[0]),
             "collect_s": t1 - t0, "train_s": t2 - t1, "loss_curve": curve, **cal}
     log(f"[learn] {info}")
