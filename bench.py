@@ -44,8 +44,9 @@ def extract_flops(n: int, n_starts: int = 16) -> dict:
     Counted from the kernel's arithmetic: contract = C u^{n-1} (powers,
     monomials with their multinomial, 3 FMAs per monomial); step = one SS-HOPM
     update; newton = one polishing step (tangent basis, C u^{n-2}, 2 x 2 solve,
-    retraction, new gradient); setup = normalisation, unfolding block and six
-    Jacobi sweeps, and the first gradient of every start; score = ||C||_F.
+    retraction, new gradient); setup = normalisation, unfolding block, three
+    Jacobi sweeps with the Gershgorin bound, and the first gradient of every
+    start; score = ||C||_F.
     """
     K = (n + 1) * (n + 2) // 2
     Kb = n * (n + 1) // 2
@@ -55,7 +56,7 @@ def extract_flops(n: int, n_starts: int = 16) -> dict:
     contract2 = 3 * (n - 2) + 15 * K2
     step = contract + 23
     newton = contract2 + contract + 106
-    jacobi = 6 * (H * (H - 1) // 2) * (6 * (H - 2) + 20)
+    jacobi = 3 * (H * (H - 1) // 2) * (6 * (H - 2) + 20) + 2 * H * H   # 3 sweeps + Gershgorin
     setup = K + H * (H + 1) // 2 + jacobi + n_starts * (contract + 13)
     setup_one = K + H * (H + 1) // 2 + jacobi + (contract + 13) + K   # learned: one start + features
     return dict(score=2 * K + 1, step=step, newton=newton, setup=setup, setup_one=setup_one)
@@ -71,8 +72,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=400, help="voxels in the oracle timing sample")
     ap.add_argument("--field-dtype", default="f32", choices=["f32", "bf16"])
-    ap.add_argument("--start", default="both", choices=["plain", "learned", "both"])
-    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--start", default="both", choices=["plain", "learned", "both"],
+                    help="both = plain, learned (screened fallback) and learned without screening")
+    ap.add_argument("--train-steps", type=int, default=6000)
+    ap.add_argument("--train-volumes", type=int, default=5)
     ap.add_argument("--max-wrong", type=float, default=0.03,
                     help="fallback calibration: accepted learned voxels off by > 1 deg at most this often")
     args = ap.parse_args()
@@ -121,7 +124,7 @@ def main():
         tr = [synth.make_tomogram(f"train{i}", (256, 256, 256), L=L, n_blobs=p["n_blobs"],
                                   n_copies=100, min_sep=p["min_sep"], mask_radius=r, degree=n,
                                   seed=1000 + i, snr=p["snr"], wedge=p["wedge"],
-                                  template_seed=p["seed"]) for i in range(3)]
+                                  template_seed=p["seed"]) for i in range(args.train_volumes + 1)]
         assert all(np.array_equal(t.template, wl.template) for t in tr)
         vols = [torch.from_numpy(t.volume).to(dev) for t in tr]
         spec_tr = spec if fft_n == 256 else ttm.template_spectra(ctx, d, Tg, 256)
@@ -137,7 +140,8 @@ def main():
 
     def run_mode(mode: str):
         eng = ttm.Engine(ctx, d, spec, fft_n, vol.shape, starts, field_dtype=field_dtype,
-                         mlp=net if mode == "learned" else None, kappa=kappa)
+                         mlp=net if mode.startswith("learned") else None, kappa=kappa,
+                         screen=(mode == "learned"))
 
         def one_pass(timed: bool):
             ev = {}
@@ -162,7 +166,7 @@ def main():
                 ttm.extract(ctx, d, Ct, score=eng.score, lam=eng.lam, direction=eng.dir, out_lo=blo,
                             out_dims=eng.shape, starts=starts, orient=True, mlp=eng.mlp,
                             kappa=eng.kappa, fallbacks=eng.fallbacks, ws=eng.ws_extract,
-                            counters=counters if timed else None)
+                            counters=counters if timed else None, screen=eng.screen)
                 if timed:
                     b.record(stream)
                     ext_ev.append((a, b, int(np.prod(size))))
@@ -208,7 +212,7 @@ def main():
                    fallbacks=int(eng.fallbacks.item()) // max(args.steps, 1))
         return res
 
-    modes = ["plain", "learned"] if args.start == "both" else [args.start]
+    modes = ["plain", "learned", "learned_unscreened"] if args.start == "both" else [args.start]
     results = {m: run_mode(m) for m in modes}
     main_mode = "learned" if "learned" in results else "plain"
     R = results[main_mode]
@@ -221,6 +225,9 @@ def main():
     gate = None
     if "learned" in results and "plain" in results:
         gate = accuracy_gate(results["plain"], results["learned"], lo, hi, top_p, ttm, torch)
+        if "learned_unscreened" in results:
+            gate["unscreened"] = accuracy_gate(results["plain"], results["learned_unscreened"], lo,
+                                               hi, top_p, ttm, torch)
 
     # roofline of the dominant kernel
     K = ttm.n_components(n, 3)
@@ -248,7 +255,9 @@ def main():
         steps_, newton_, oriented = R["counters"]
         voxels = sum(nv for _, nv in ext_launch_ms)
         mlp_flops = 2 * (32 * 64 + 64 * 64 + 64 * 16) if main_mode == "learned" else 0
-        flops = (voxels * (f["score"] + mlp_flops) + oriented * f["setup_one" if main_mode == "learned" else "setup"]
+        screen_flops = 16 * (f["step"] - 23) if main_mode == "learned" else 0
+        flops = (voxels * (f["score"] + mlp_flops + screen_flops)
+                 + oriented * f["setup_one" if main_mode == "learned" else "setup"]
                  + steps_ * f["step"] + newton_ * f["newton"])
         ach = flops / (stage["extract"] / 1e3) / 1e12
         roofline = {"bound": "alu", "kernel": f"k_extract<{n}> ({main_mode} start) + fallback",
@@ -290,7 +299,7 @@ def main():
         "start_mode": {m: {"voxels_per_s": nvox / (results[m]["ms_step"] / 1e3),
                            "ms_per_step": results[m]["ms_step"],
                            "stages_ms_per_step": {k: v / args.steps for k, v in results[m]["stage"].items()},
-                           "fallback_voxels_per_step": results[m]["fallbacks"] if m == "learned" else None}
+                           "fallback_voxels_per_step": results[m]["fallbacks"] if m != "plain" else None}
                        for m in results},
         "accuracy_gate": gate,
         "learned_start_training": learn_info,

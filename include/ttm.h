@@ -169,6 +169,8 @@ int ttm_correlate(ttm_ctx* ctx, const ttm_desc* desc, const float* g, const floa
 #define TTM_START_MLP 4   /* seed SS-HOPM from the MLP; fall back to multistart  */
 #define TTM_START_ONLY 8  /* with TTM_START_MLP: write the network's unit start
                              direction to dir (lambda = 0), no search          */
+#define TTM_NO_SCREEN 16  /* with TTM_START_MLP: skip the fixed-start screening
+                             (fall back only on kappa or non-convergence)      */
 
 typedef struct {
   int32_t mode;            /* TTM_SCORE | TTM_ORIENT [| TTM_START_MLP]            */
@@ -205,7 +207,9 @@ typedef struct {
  * re-run by a second kernel with the full multistart search; the better of
  * the two answers is kept.  Requires lambda and dir.
  * Orientation: alpha = max(0, -lambda_min(U)) with U the square unfolding of
- * C/||C||_F; SS-HOPM u <- (C u^{n-1} + alpha u)/||.|| from every start until
+ * C/||C||_F (lambda_min bounded from below by three Jacobi sweeps of the
+ * unfolding's symmetric block and Gershgorin discs, so alpha is never below
+ * the rule's value); SS-HOPM u <- (C u^{n-1} + alpha u)/||.|| from every start until
  * |delta lambda| <= tol or max_iter, then up to newton_steps Riemannian Newton
  * steps (taken where the tangent Hessian (n-1) E^T (C u^{n-2}) E - lambda I is
  * negative definite, kept unless lambda drops by more than 1e-7); the largest

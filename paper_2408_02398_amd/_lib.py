@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libttm.so")
 TTM_OK, TTM_EINVAL, TTM_ENOMEM, TTM_EDEVICE, TTM_EUNSUPPORTED, TTM_EWORKSPACE = 0, -1, -2, -3, -4, -5
 TTM_F32, TTM_BF16 = 0, 1
 TTM_OP_SPECTRA, TTM_OP_NORMALIZE, TTM_OP_CORRELATE, TTM_OP_PEAKS = 1, 2, 3, 4
-TTM_SCORE, TTM_ORIENT, TTM_START_MLP, TTM_START_ONLY = 1, 2, 4, 8
+TTM_SCORE, TTM_ORIENT, TTM_START_MLP, TTM_START_ONLY, TTM_NO_SCREEN = 1, 2, 4, 8, 16
 TTM_OP_EXTRACT, TTM_OP_MLP_TRAIN = 5, 6
 
 STATUS_NAMES = {0: "TTM_OK", -1: "TTM_EINVAL", -2: "TTM_ENOMEM", -3: "TTM_EDEVICE",

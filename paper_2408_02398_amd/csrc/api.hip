@@ -707,7 +707,7 @@ int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
     }
   }
   const int mode = opts->mode;
-  if ((mode & ~15) || !(mode & 3) || ((mode & 8) && !(mode & 4)) || ((mode & 4) && !(mode & 2))) {
+  if ((mode & ~31) || !(mode & 3) || ((mode & 24) && !(mode & 4)) || ((mode & 4) && !(mode & 2))) {
     set_error("ttm_extract: mode %d invalid", mode);
     return TTM_EINVAL;
   }
@@ -770,6 +770,7 @@ int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
     a.mlp = static_cast<const unsigned char*>(opts->mlp);
     a.kappa = opts->fallback_kappa;
     a.start_only = (mode & 8) ? 1 : 0;
+    a.screen = (mode & 16) ? 0 : 1;
     a.fb_count = static_cast<unsigned*>(ws);
     a.fb_queue = reinterpret_cast<unsigned*>(static_cast<char*>(ws) + 256);
     a.fb_total = n_fallback;

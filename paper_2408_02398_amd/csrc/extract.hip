@@ -155,7 +155,11 @@ __host__ __device__ constexpr int tri(int M, int p, int q) {
   return p <= q ? p * M - p * (p - 1) / 2 + (q - p) : q * M - q * (q - 1) / 2 + (p - q);
 }
 
-// lambda_min of B[b, g] = sqrt(mu_b mu_g) c_{b+g} over |b| = |g| = n/2.
+// Lower bound of lambda_min of B[b, g] = sqrt(mu_b mu_g) c_{b+g} over
+// |b| = |g| = n/2: three cyclic Jacobi sweeps (orthogonal similarity, so the
+// spectrum is unchanged) followed by Gershgorin discs, min_i (A_ii - sum |A_ij|).
+// The bound is exact up to the remaining off-diagonal mass and never above
+// lambda_min, so the shift -bound is never smaller than the unfolding rule's.
 template <int N>
 __device__ __forceinline__ float unfolding_lambda_min(const float (&c)[ncomp3(N)]) {
   constexpr int H = N / 2;
@@ -170,7 +174,7 @@ __device__ __forceinline__ float unfolding_lambda_min(const float (&c)[ncomp3(N)
       A[tri(M, p, q)] = s * c[comp_index3(N, hs.ax[p] + hs.ax[q], hs.ay[p] + hs.ay[q])];
     }
   }
-  for (int sweep = 0; sweep < 6; ++sweep) {
+  for (int sweep = 0; sweep < 3; ++sweep) {
 #pragma unroll
     for (int p = 0; p < M - 1; ++p) {
 #pragma unroll
@@ -196,9 +200,15 @@ __device__ __forceinline__ float unfolding_lambda_min(const float (&c)[ncomp3(N)
       }
     }
   }
-  float lmin = A[tri(M, 0, 0)];
+  float lmin = INFINITY;
 #pragma unroll
-  for (int p = 1; p < M; ++p) lmin = fminf(lmin, A[tri(M, p, p)]);
+  for (int p = 0; p < M; ++p) {
+    float rad = 0.0f;
+#pragma unroll
+    for (int q = 0; q < M; ++q)
+      if (q != p) rad += fabsf(A[tri(M, p, q)]);
+    lmin = fminf(lmin, A[tri(M, p, p)] - rad);
+  }
   return lmin;
 }
 
@@ -338,14 +348,14 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs a) {
           // screening: SS-HOPM never lowers lambda, so a fixed start that already
           // scores above the learned answer proves the multistart answer is higher
           bool beaten = false;
-          for (int s = 0; s < a.n_starts; ++s) {
+          for (int s = 0; s < (a.screen ? a.n_starts : 0); ++s) {
             const float sx = st[3 * s], sy = st[3 * s + 1], sz = st[3 * s + 2];
             const float rs = 1.0f / sqrtf(sx * sx + sy * sy + sz * sz);
             float q0, q1, q2;
             contract<N>(c, sx * rs, sy * rs, sz * rs, q0, q1, q2);
             beaten = beaten || ((q0 * sx + q1 * sy + q2 * sz) * rs > lam);
           }
-          fallback = fallback || !conv || !(lam >= a.kappa) || beaten;
+          fallback = fallback || !conv || !(lam >= a.kappa) || (beaten && a.screen);
           bx0 = ux; by0 = uy; bz0 = uz;
           canonical(bx0, by0, bz0);
           lam_best = lam * cn;

@@ -96,6 +96,7 @@ struct ExtractArgs {
   const unsigned char* mlp;      // packed BF16 parameters
   float kappa;                   // fall back when lambda / ||C||_F < kappa
   int start_only;                // write the network's start direction only
+  int screen;                    // fall back when a fixed start beats the learned lambda
   unsigned* fb_count;            // fallback queue length (workspace)
   unsigned* fb_queue;            // fallback voxel indices (workspace)
   int* fb_total;                 // optional caller counter of fallbacks

@@ -140,7 +140,7 @@ def extract(ctx: Context, desc: Desc, Cf: torch.Tensor, *, score=None, lam=None,
             orient: bool = True, max_iter: int = 500, tol: float = 1e-5, newton: int = 2,
             counters: torch.Tensor | None = None, mlp: "MLP | None" = None, kappa: float = 0.0,
             start_only: bool = False, fallbacks: torch.Tensor | None = None,
-            ws: torch.Tensor | None = None):
+            ws: torch.Tensor | None = None, screen: bool = True):
     """Score / lambda / direction maps for the box held in Cf (K x bz x by x bx).
 
     With ``mlp`` the orientation search starts from the learned start and falls
@@ -170,6 +170,8 @@ def extract(ctx: Context, desc: Desc, Cf: torch.Tensor, *, score=None, lam=None,
             mode |= L.TTM_START_MLP
             if start_only:
                 mode |= L.TTM_START_ONLY
+            if not screen:
+                mode |= L.TTM_NO_SCREEN
             opts.mlp = mlp.packed.data_ptr()
             opts.fallback_kappa = kappa
             if ws is None:
@@ -305,12 +307,12 @@ class Engine:
     def __init__(self, ctx: Context, desc: Desc, spectra: torch.Tensor, fft_n: int, shape,
                  starts: torch.Tensor | None, field_dtype=torch.float32, orient: bool = True,
                  max_iter: int = 500, tol: float = 1e-5, newton: int = 2,
-                 mlp: MLP | None = None, kappa: float = 0.0):
+                 mlp: MLP | None = None, kappa: float = 0.0, screen: bool = True):
         self.ctx, self.desc, self.spectra, self.fft_n = ctx, desc, spectra, fft_n
         self.shape = tuple(shape)
         self.starts, self.orient = starts, orient
         self.max_iter, self.tol, self.newton = max_iter, tol, newton
-        self.mlp, self.kappa = mlp, kappa
+        self.mlp, self.kappa, self.screen = mlp, kappa, screen
         dev = spectra.device
         nz, ny, nx = self.shape
         K = n_components(desc.degree, desc.dprime)
@@ -337,7 +339,8 @@ class Engine:
             extract(self.ctx, self.desc, Ct, score=self.score, lam=self.lam, direction=self.dir,
                     out_lo=lo, out_dims=self.shape, starts=self.starts, orient=self.orient,
                     max_iter=self.max_iter, tol=self.tol, newton=self.newton, mlp=self.mlp,
-                    kappa=self.kappa, fallbacks=self.fallbacks, ws=self.ws_extract)
+                    kappa=self.kappa, fallbacks=self.fallbacks, ws=self.ws_extract,
+                    screen=self.screen)
         peaks = vals = None
         if top_p:
             vlo, vhi = valid_bounds(self.shape, self.desc.L)
