@@ -28,6 +28,8 @@ WORKLOADS = {
     "c3_512x928x928_n6": ("c3_512x928x928_n6", 256, 2000),
     "c2_256cube_n6": ("c2_256cube_n6", 256, 200),
     "c1_64cube_n4": ("c1_64cube_n4", 64, 5),
+    # 64 subtomograms, edges in {96,128,160,192}, 3 templates, one graph launch per batch
+    "c5_batch64_n6": ("c5_batch64_n6", 0, 60),
 }
 
 HBM_PEAK_GBS = 8000.0
@@ -76,7 +78,9 @@ def main():
                     help="both = plain, learned (screened fallback) and learned without screening")
     ap.add_argument("--train-steps", type=int, default=6000)
     ap.add_argument("--train-volumes", type=int, default=5)
-    ap.add_argument("--max-wrong", type=float, default=0.03,
+    ap.add_argument("--precision-report", action="store_true",
+                    help="FP32 vs BF16 field storage: throughput and error against the FP64 oracle")
+    ap.add_argument("--max-wrong", type=float, default=0.05,
                     help="fallback calibration: accepted learned voxels off by > 1 deg at most this often")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -92,9 +96,15 @@ def main():
         print(json.dumps({"error": "no GPU"}))
         sys.exit(2)
     cfg_name, fft_n, top_p = WORKLOADS[args.workload]
+    if cfg_name == "c5_batch64_n6":
+        print(json.dumps(bench_batch(args, top_p)), flush=True)
+        return
     p = synth.CONFIGS[cfg_name]
     n, L, r = p["degree"], p["L"], p["mask_radius"]
 
+    if args.precision_report:
+        print(json.dumps(precision_report(args, cfg_name, fft_n, top_p)), flush=True)
+        return
     t0 = time.time()
     log(f"[bench] generating {cfg_name} ...")
     wl = synth.make_config(cfg_name)
@@ -355,6 +365,192 @@ def accuracy_gate(plain, learned, lo, hi, top_p, ttm, torch):
             "all_valid_sample_median_deg": float(ang_all.median().item()),
             "all_valid_sample_frac_within_1deg": float((ang_all <= 1.0).float().mean().item()),
             "peaks_identical": same_peaks}
+
+
+def bench_batch(args, top_p):
+    """64 uneven subtomograms with 3 templates, recorded into one HIP graph per batch:
+    plain and learned starts, throughput = all subtomogram voxels / replay time."""
+    import torch
+
+    import synth
+    from paper_2408_02398_amd import learn, ttm
+    n = 6
+    t0 = time.time()
+    tmpls, items = synth.batch_items(seed=5, n_items=64)
+    log(f"[bench] batch generated in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    ctx = ttm.Context(0)
+    Q = torch.from_numpy(synth.rotation_samples(args.nq_base)).float().to(dev)
+    starts = torch.from_numpy(synth.start_vectors()).to(dev)
+    templates = []
+    for vol, r, tm in tmpls:
+        d = ttm.make_desc(n, vol.shape[0], r)
+        Tg, _ = ttm.build_tensor(ctx, d, torch.from_numpy(vol).to(dev), Q)
+        templates.append((d, Tg))
+    cost = ttm.autotune(ctx, templates[-1][0])
+    log(f"[bench] FFT tile cost (ms): {cost}")
+    shapes = [it["volume"].shape for it in items]
+    owner = [it["template"] for it in items]
+    nvox = int(sum(np.prod(s) for s in shapes))
+
+    mlps, learn_info = None, []
+    if args.start in ("learned", "both"):
+        mlps = []
+        for ti, (vol, r, tm) in enumerate(tmpls):
+            d, Tg = templates[ti]
+            spec = ttm.template_spectra(ctx, d, Tg, 256)
+            trv = []
+            for k in range(4):
+                rng = np.random.default_rng(7000 + 10 * ti + k)
+                cen = synth.place_centres(rng, (192, 192, 192), 40, r, margin=tm.L // 2 + 1)
+                rot = synth.random_rotations(rng, len(cen))
+                sig = synth.render_copies((192, 192, 192), tm, cen, rot)
+                sd = float(np.sqrt(np.var(vol[synth.ball(tm.L, r)]) / 0.1))
+                v = sig + (sd * rng.standard_normal((192, 192, 192), dtype=np.float32))
+                trv.append(torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32)).to(dev))
+            net, kap, info = learn.build_learned_start(ctx, d, spec, 256, trv, starts,
+                                                       steps=args.train_steps // 2, log=log)
+            mlps.append(net)
+            learn_info.append(info)
+    results = {}
+    modes = ["plain", "learned"] if args.start == "both" else [args.start]
+    for mode in modes:
+        be = ttm.BatchEngine(ctx, templates, shapes, owner, starts, top_p,
+                             mlps=mlps if mode == "learned" else None, kappa=-1e30, cost=cost)
+        for i, it in enumerate(items):
+            be.volumes[i].copy_(torch.from_numpy(it["volume"]).to(dev))
+        be.capture()
+        for _ in range(args.warmup):
+            be.replay()
+        torch.cuda.synchronize()
+        be.fallbacks.zero_()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.steps):
+            be.replay()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / args.steps
+        log(f"[bench] batch {mode}: {ms:.1f} ms per batch")
+        results[mode] = dict(be=be, ms=ms, fallbacks=int(be.fallbacks.item()) // max(args.steps, 1))
+    gate = None
+    if "plain" in results and "learned" in results:
+        angs = []
+        for i in range(len(items)):
+            bp, bl = results["plain"]["be"], results["learned"]["be"]
+            d = templates[owner[i]][0]
+            lo, hi = ttm.valid_bounds(shapes[i], d.L)
+            sl = tuple(slice(x, y + 1) for x, y in zip(lo, hi))
+            sc = bp.score[i][sl]
+            thr = torch.quantile(sc.reshape(-1)[:: max(1, sc.numel() // 1_000_000)], 0.99)
+            m = sc >= thr
+            ua, ub = bp.direction[i][sl][m], bl.direction[i][sl][m]
+            c = torch.abs((ua * ub).sum(-1)).clamp(max=1.0)
+            angs.append(torch.rad2deg(torch.arccos(c)))
+        ang = torch.cat(angs)
+        gate = {"voxels": int(ang.numel()), "median_deg": float(ang.median()),
+                "frac_within_1deg": float((ang <= 1.0).float().mean()),
+                "pass": bool(ang.median() <= 1.0),
+                "peaks_identical": all(torch.equal(results["plain"]["be"].peaks[i],
+                                                   results["learned"]["be"].peaks[i])
+                                       for i in range(len(items)))}
+    main = "learned" if "learned" in results else "plain"
+    ms = results[main]["ms"]
+    return {"metric": "tomogram voxels/sec scored (TTM full pass), learned vs plain start at <=1 deg error",
+            "value": nvox / (ms / 1e3), "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32" + ("+bf16-mlp" if main == "learned" else ""),
+            "data": "synthetic",
+            "config": {"workload": "c5_batch64_n6", "items": len(items), "degree": n, "K": 28,
+                       "edges": sorted(set(int(s[0]) for s in shapes)), "templates": len(templates),
+                       "fft_edges_chosen": {str(k): ttm.BatchEngine.__name__ and int(sum(1 for f in results[main]["be"].fft if f == k)) for k in sorted(set(results[main]["be"].fft))},
+                       "voxels": nvox, "top_p_per_item": top_p, "launch": "one HIP graph per batch"},
+            "start_mode": {m: {"voxels_per_s": nvox / (results[m]["ms"] / 1e3), "ms_per_step": results[m]["ms"],
+                               "fallback_voxels_per_step": results[m]["fallbacks"] if m != "plain" else None}
+                           for m in results},
+            "accuracy_gate": gate, "autotune_tile_ms": cost, "learned_start_training": learn_info}
+
+
+def precision_report(args, cfg_name, fft_n, top_p, n_sample=150):
+    """Field stored in BF16 (FFTs and accumulation FP32, variance FP64) against FP32 storage:
+    pass throughput (plain start), score / lambda / angle differences over all valid voxels, and
+    both against the FP64 oracle at sampled voxels (oracle field by direct sums)."""
+    import torch
+
+    import synth
+    from oracle import ttm as orc
+    from paper_2408_02398_amd import ttm
+    p = synth.CONFIGS[cfg_name]
+    n, L, r = p["degree"], p["L"], p["mask_radius"]
+    wl = synth.make_config(cfg_name)
+    dev = torch.device("cuda:0")
+    ctx = ttm.Context(0)
+    d = ttm.make_desc(n, L, r)
+    Qn = synth.rotation_samples(100)              # 2400 rotations: the oracle builds T too
+    Tg, _ = ttm.build_tensor(ctx, d, torch.from_numpy(wl.template).to(dev),
+                             torch.from_numpy(Qn).float().to(dev))
+    spec = ttm.template_spectra(ctx, d, Tg, fft_n)
+    starts = torch.from_numpy(synth.start_vectors()).to(dev)
+    vol = torch.from_numpy(wl.volume).to(dev)
+    lo, hi = ttm.valid_bounds(vol.shape, L)
+    out = {"workload": cfg_name, "rotations": int(len(Qn))}
+    maps = {}
+    for name, dt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
+        eng = ttm.Engine(ctx, d, spec, fft_n, vol.shape, starts, field_dtype=dt)
+        eng.run(vol, top_p=top_p)
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(args.steps):
+            res = eng.run(vol, top_p=top_p)
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / args.steps
+        out[name] = {"ms_per_step": ms, "voxels_per_s": float(np.prod(vol.shape)) / (ms / 1e3)}
+        maps[name] = (res.score.clone(), res.lam.clone(), res.direction.clone(), res.peaks.clone())
+    sl = tuple(slice(a, b + 1) for a, b in zip(lo, hi))
+    s32, s16 = maps["f32"][0][sl], maps["bf16"][0][sl]
+    floor = torch.maximum(s32, s32.median())
+    u32, u16 = maps["f32"][2][sl].reshape(-1, 3), maps["bf16"][2][sl].reshape(-1, 3)
+    ang = torch.rad2deg(torch.arccos(torch.abs((u32 * u16).sum(-1)).clamp(max=1.0)))
+    out["bf16_vs_f32"] = {"score_max_rel": float(((s16 - s32).abs() / floor).max()),
+                          "score_median_rel": float(((s16 - s32).abs() / floor).median()),
+                          "angle_median_deg": float(ang.median()),
+                          "angle_frac_within_1deg": float((ang <= 1).float().mean()),
+                          "peaks_identical": bool(torch.equal(maps["f32"][3], maps["bf16"][3]))}
+    # FP64 oracle at sampled voxels: the peaks of the FP32 pass plus random valid voxels
+    rng = np.random.default_rng(5)
+    pk = maps["f32"][3].cpu().numpy()[: n_sample // 3]
+    rnd = np.stack([rng.integers(a, b + 1, n_sample - len(pk)) for a, b in zip(lo, hi)], 1)
+    pts = np.concatenate([pk, rnd]).astype(np.int64)
+    tn = orc.normalize_template(wl.template, r)
+    T = orc.tensor_template(tn, Qn, n)
+    g2 = orc.volume_g2_mean(orc.prefilter_volume(wl.volume))
+    _, Co = orc.field_at(orc.patches_at(None, pts, L, f=wl.volume), orc.ball_mask(L, r), T, g2)
+    so = orc.score(Co.T, n)
+    st = synth.start_vectors().astype(np.float64)
+    lam_o, u_o, ok = [], [], []
+    for i in range(len(pts)):
+        lmb, u, lams, us, _ = orc.orient_multistart(Co[i], n, st)
+        lam_o.append(lmb)
+        u_o.append(u)
+        ok.append(orc.orientation_margin(lams, us, u) > 1e-4 * so[i])
+    lam_o, u_o, ok = np.array(lam_o), np.array(u_o), np.array(ok)
+    med = float(np.median(so))
+    for name in ("f32", "bf16"):
+        sc, lm, dr, _ = (m.cpu().numpy() for m in maps[name])
+        sg = sc[pts[:, 0], pts[:, 1], pts[:, 2]]
+        lg = lm[pts[:, 0], pts[:, 1], pts[:, 2]]
+        ug = dr[pts[:, 0], pts[:, 1], pts[:, 2]]
+        a = orc.angle_deg(ug, u_o)
+        out[name]["vs_fp64_oracle"] = {
+            "voxels": int(len(pts)),
+            "score_max_rel": float(np.max(np.abs(sg - so) / np.maximum(so, med))),
+            "lambda_max_rel": float(np.max(np.abs(lg - lam_o) / np.maximum(so, med))),
+            "angle_median_deg": float(np.median(a[ok])) if ok.any() else None,
+            "angle_max_deg_unambiguous": float(np.max(a[ok])) if ok.any() else None,
+            "unambiguous": int(ok.sum())}
+    return out
 
 
 def cpu_baseline(wl, Q, n, L, r, sample):

@@ -261,6 +261,18 @@ int ttm_find_peaks(ttm_ctx* ctx, const float* score, int nz, int ny, int nx,
                    float min_dist, int32_t* peaks_out, float* vals_out, int32_t* n_found,
                    void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * Find Peaks with the same rule and result as ttm_find_peaks, for callers
+ * that cannot synchronise (e.g. under stream / graph capture): every valid
+ * voxel is a candidate (sorted on the device), nothing is copied to the host,
+ * and the number of peaks found is written to the device int32 n_found.
+ * Workspace as ttm_find_peaks; the volume must hold fewer than 2^31 voxels.
+ */
+int ttm_find_peaks_async(ttm_ctx* ctx, const float* score, int nz, int ny, int nx,
+                         const int32_t valid_lo[3], const int32_t valid_hi[3], int top_p,
+                         float min_dist, int32_t* peaks_out, float* vals_out, int32_t* n_found,
+                         void* ws, size_t ws_bytes, void* stream);
+
 /* Stand-alone 3D FFT of an N^3 real array to its half spectrum and back
  * (the transforms used inside ttm_correlate), for tests and benchmarks.
  * Forward: spec = F(x) unnormalised; inverse: x = F^{-1}(spec) * scale.

@@ -65,6 +65,9 @@ SIGNATURES = {
     "ttm_find_peaks": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int32),
                                  C.POINTER(C.c_int32), C.c_int, C.c_float, vp, vp,
                                  C.POINTER(C.c_int32), vp, C.c_size_t, vp]),
+    "ttm_find_peaks_async": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_int32), C.c_int, C.c_float, vp, vp, vp, vp,
+                                       C.c_size_t, vp]),
     "ttm_fft3d_r2c": (C.c_int, [vp, vp, C.c_int, vp, vp]),
     "ttm_fft3d_c2r": (C.c_int, [vp, vp, C.c_int, C.c_float, vp, vp]),
 }

@@ -843,6 +843,32 @@ int ttm_find_peaks(ttm_ctx* ctx, const float* score, int nz, int ny, int nx,
                     n_found, ws, ws_bytes, static_cast<hipStream_t>(stream));
 }
 
+int ttm_find_peaks_async(ttm_ctx* ctx, const float* score, int nz, int ny, int nx,
+                         const int32_t valid_lo[3], const int32_t valid_hi[3], int top_p,
+                         float min_dist, int32_t* peaks_out, float* vals_out, int32_t* n_found,
+                         void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || !score || !valid_lo || !valid_hi || !peaks_out || !vals_out || !n_found || !ws ||
+      top_p < 1 || !(min_dist >= 0.0f)) {
+    set_error("ttm_find_peaks_async: null pointer, top_p < 1 or negative distance");
+    return TTM_EINVAL;
+  }
+  const int dims[3] = {nz, ny, nx};
+  for (int a = 0; a < 3; ++a) {
+    if (valid_lo[a] < 0 || valid_hi[a] >= dims[a] || valid_lo[a] > valid_hi[a]) {
+      set_error("ttm_find_peaks_async: region axis %d [%d, %d] outside [0, %d)", a, valid_lo[a],
+                valid_hi[a], dims[a]);
+      return TTM_EINVAL;
+    }
+  }
+  if ((int64_t)nz * ny * nx >= (int64_t)1 << 31) {
+    set_error("ttm_find_peaks_async: volume exceeds 2^31 voxels");
+    return TTM_EUNSUPPORTED;
+  }
+  TTM_HIP(hipSetDevice(ctx->device));
+  return find_peaks_async(score, nz, ny, nx, valid_lo, valid_hi, top_p, min_dist, peaks_out,
+                          vals_out, n_found, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
 int ttm_fft3d_r2c(ttm_ctx* ctx, const float* x, int fft_n, void* spec, void* stream) {
   if (!ctx || !x || !spec) {
     set_error("ttm_fft3d_r2c: null pointer");

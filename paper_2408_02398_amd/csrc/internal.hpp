@@ -108,6 +108,10 @@ size_t peaks_workspace(int64_t n_voxels);
 int find_peaks(const float* score, int nz, int ny, int nx, const int32_t lo[3],
                const int32_t hi[3], int top_p, float min_dist, int32_t* peaks_out,
                float* vals_out, int32_t* n_found_host, void* ws, size_t ws_bytes, hipStream_t s);
+int find_peaks_async(const float* score, int nz, int ny, int nx, const int32_t lo[3],
+                     const int32_t hi[3], int top_p, float min_dist, int32_t* peaks_out,
+                     float* vals_out, int32_t* n_found_dev, void* ws, size_t ws_bytes,
+                     hipStream_t s);
 
 // Learned start training (mlp.hip).
 size_t mlp_train_workspace(int B);

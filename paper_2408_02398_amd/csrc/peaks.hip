@@ -25,6 +25,8 @@
 
 namespace ttm {
 
+size_t peaks_workspace(int64_t n_voxels);
+
 namespace {
 
 constexpr int kHistBins = 4096;   // per level: bits [31:20], then [19:8]
@@ -283,6 +285,60 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy(GreedyArgs g) {
 }
 
 }  // namespace
+
+// Exact Find Peaks with every valid voxel as a candidate and no host
+// synchronisation (the count stays on the device), for graph capture.
+int find_peaks_async(const float* score, int nz, int ny, int nx, const int32_t lo[3],
+                     const int32_t hi[3], int top_p, float min_dist, int32_t* peaks_out,
+                     float* vals_out, int32_t* n_found_dev, void* ws, size_t ws_bytes,
+                     hipStream_t s) {
+  Region r{nz, ny, nx, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]};
+  const int64_t nvalid = (int64_t)(hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1);
+  const size_t need = peaks_workspace(nvalid);
+  if (ws_bytes < need) {
+    set_error("ttm_find_peaks_async: workspace %zu < %zu bytes", ws_bytes, need);
+    return -5;
+  }
+  const float cell = fmaxf(min_dist, 1.0f);
+  const int gz = (int)(nz / cell) + 1, gy = (int)(ny / cell) + 1, gx = (int)(nx / cell) + 1;
+  if ((int64_t)gz * gy * gx > kMaxCells || top_p > kMaxPeaks || nz > 32767 || ny > 32767 ||
+      nx > 32767) {
+    set_error("ttm_find_peaks_async: exclusion grid %dx%dx%d or top_p %d too large", gz, gy, gx,
+              top_p);
+    return -4;
+  }
+  char* w = static_cast<char*>(ws);
+  const size_t cand_cap = (size_t)nvalid + kSortTile;
+  unsigned long long* keys_a = reinterpret_cast<unsigned long long*>(w);
+  unsigned long long* keys_b = keys_a + cand_cap;
+  unsigned* hist = reinterpret_cast<unsigned*>(keys_b + cand_cap);
+  unsigned* counter = hist + kHistBins;
+  unsigned* shist = reinterpret_cast<unsigned*>(counter + 128);
+  const dim3 grid((hi[2] - lo[2] + 1 + 255) / 256, hi[1] - lo[1] + 1, hi[0] - lo[0] + 1);
+  const size_t m = (size_t)nvalid;
+  const size_t mpad = (m + kSortTile - 1) / kSortTile * kSortTile;
+  const int nblk = (int)(mpad / kSortTile);
+  fill_zero(counter, 4, s);
+  hipLaunchKernelGGL(k_compact, grid, dim3(256), 0, s, score, r, 0u, keys_a, counter);
+  if (mpad > m) {
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((mpad - m + 255) / 256)), dim3(256), 0, s, keys_a, m,
+                       mpad);
+  }
+  unsigned long long* src = keys_a;
+  unsigned long long* dst = keys_b;
+  for (int shift = 0; shift < 64; shift += 8) {
+    hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(kSortBlock), 0, s, src, shift, shist, nblk);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, shist, 256 * nblk);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(kSortBlock), 0, s, src, dst, shift, shist,
+                       nblk);
+    std::swap(src, dst);
+  }
+  GreedyArgs ga{src, (int)m, nz, ny, nx, min_dist * min_dist, cell, gz, gy, gx, top_p,
+                peaks_out, vals_out, n_found_dev};
+  hipLaunchKernelGGL(k_greedy, dim3(1), dim3(kGreedyThreads), 0, s, ga);
+  TTM_HIP(hipGetLastError());
+  return 0;
+}
 
 size_t peaks_workspace(int64_t n_voxels) {
   const size_t cand = (size_t)n_voxels + kSortTile;

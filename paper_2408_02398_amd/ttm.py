@@ -10,6 +10,7 @@ import ctypes as C
 import math
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 from . import _lib as L
@@ -247,6 +248,17 @@ def find_peaks(ctx: Context, score: torch.Tensor, valid_lo, valid_hi, top_p: int
     return peaks[:nf.value], vals[:nf.value]
 
 
+def find_peaks_async(ctx: Context, score: torch.Tensor, valid_lo, valid_hi, top_p: int,
+                     min_dist: float, peaks: torch.Tensor, vals: torch.Tensor,
+                     n_found: torch.Tensor, ws: torch.Tensor) -> None:
+    """Find Peaks without host synchronisation (graph-capture safe); n_found stays on the device."""
+    _need_cuda(score, peaks, vals, n_found, ws)
+    nz, ny, nx = score.shape
+    call("ttm_find_peaks_async", ctx.h, _ptr(score), nz, ny, nx, I32x3(*valid_lo),
+         I32x3(*valid_hi), top_p, float(min_dist), _ptr(peaks), _ptr(vals), _ptr(n_found),
+         _ptr(ws), ws.numel(), _stream())
+
+
 def fft3d_r2c(ctx: Context, x: torch.Tensor) -> torch.Tensor:
     _need_cuda(x)
     N = x.shape[0]
@@ -348,3 +360,165 @@ class Engine:
                                      2.0 * self.desc.mask_radius if min_dist is None else min_dist,
                                      ws=self.ws_peaks)
         return PassResult(self.score, self.lam, self.dir, peaks, vals, w, g)
+
+
+# ----------------------------------------------------------------------------
+# batches of uneven subtomograms and several templates (one graph launch)
+# ----------------------------------------------------------------------------
+
+FFT_EDGES = (64, 128, 256, 512)
+
+
+def tiles_for(shape, L_edge: int, fft_n: int) -> int:
+    step = fft_n - L_edge + 1
+    if step < 1:
+        return 0
+    return int(np.prod([-(-(d - L_edge + 1) // step) for d in shape]))
+
+
+def pick_fft(shape, L_edge: int, cost: dict | None = None) -> int:
+    """FFT edge of least modelled cost: tiles(N) x cost(N); cost defaults to N^3 log2 N."""
+    best, best_c = None, None
+    for N in FFT_EDGES:
+        t = tiles_for(shape, L_edge, N)
+        if t == 0:
+            continue
+        c = t * (cost[N] if cost and N in cost else N ** 3 * np.log2(N))
+        if best_c is None or c < best_c:
+            best, best_c = N, c
+    if best is None:
+        raise ValueError("no supported FFT edge fits the template")
+    return best
+
+
+class BatchEngine:
+    """Full TTM passes over many subtomograms of uneven size with several
+    templates, recorded once into a HIP graph and replayed with one launch.
+
+    templates: list of (desc, T) with T the K x L^3 tensor template;
+    shapes: per-item volume shape; owner: per-item template index.
+    Inputs are copied into ``self.volumes[i]`` before ``replay()``; outputs are
+    ``score[i]``, ``lam[i]``, ``direction[i]``, ``peaks[i]``, ``vals[i]`` and
+    ``n_found[i]`` (device).  ``cost`` maps FFT edge -> measured cost of one tile
+    (see ``autotune``); without it the edge is chosen by N^3 log N.
+    """
+
+    def __init__(self, ctx: Context, templates, shapes, owner, starts: torch.Tensor, top_p: int,
+                 mlps=None, kappa: float = 0.0, field_dtype=torch.float32, cost: dict | None = None,
+                 orient: bool = True):
+        self.ctx, self.templates, self.shapes, self.owner = ctx, templates, [tuple(s) for s in shapes], owner
+        self.starts, self.top_p, self.mlps, self.kappa = starts, top_p, mlps, kappa
+        self.orient, self.field_dtype = orient, field_dtype
+        dev = starts.device
+        self.fft = [pick_fft(s, templates[o][0].L, cost) for s, o in zip(self.shapes, owner)]
+        self.spectra = {}
+        for i, (s, o) in enumerate(zip(self.shapes, owner)):
+            key = (o, self.fft[i])
+            if key not in self.spectra:
+                d, T = templates[o]
+                self.spectra[key] = template_spectra(ctx, d, T, self.fft[i])
+        self.volumes = [torch.zeros(s, dtype=torch.float32, device=dev) for s in self.shapes]
+        self.score = [torch.zeros(s, dtype=torch.float32, device=dev) for s in self.shapes]
+        self.lam = [torch.zeros(s, dtype=torch.float32, device=dev) for s in self.shapes]
+        self.direction = [torch.zeros((*s, 3), dtype=torch.float32, device=dev) for s in self.shapes]
+        self.peaks = [torch.zeros((top_p, 3), dtype=torch.int32, device=dev) for _ in self.shapes]
+        self.vals = [torch.zeros(top_p, dtype=torch.float32, device=dev) for _ in self.shapes]
+        self.n_found = torch.zeros(len(self.shapes), dtype=torch.int32, device=dev)
+        self.fallbacks = torch.zeros(1, dtype=torch.int32, device=dev)
+        # shared workspaces, each sized for the largest request of its kind
+        ws_norm = ws_corr = ws_peaks = ws_ext = 0
+        cmax = 0
+        lib = load()
+        for s, o, N in zip(self.shapes, owner, self.fft):
+            d = templates[o][0]
+            ws_norm = max(ws_norm, lib.ttm_workspace_size(C.byref(d), L.TTM_OP_NORMALIZE, N, *s))
+            ws_corr = max(ws_corr, lib.ttm_workspace_size(C.byref(d), L.TTM_OP_CORRELATE, N, *s))
+            ws_peaks = max(ws_peaks, lib.ttm_workspace_size(C.byref(d), L.TTM_OP_PEAKS, N, *s))
+            v = [x - d.L + 1 for x in s]
+            ws_ext = max(ws_ext, lib.ttm_workspace_size(C.byref(d), L.TTM_OP_EXTRACT, 0, *v))
+            cmax = max(cmax, n_components(d.degree, d.dprime) * int(np.prod(v)))
+        self.ws_norm = torch.empty(ws_norm, dtype=torch.uint8, device=dev)
+        self.ws_corr = torch.empty(ws_corr, dtype=torch.uint8, device=dev)
+        self.ws_peaks = torch.empty(ws_peaks, dtype=torch.uint8, device=dev)
+        self.ws_ext = torch.empty(ws_ext, dtype=torch.uint8, device=dev)
+        self.Cbuf = torch.empty(cmax, dtype=field_dtype, device=dev)
+        self.g = [torch.empty(s, dtype=torch.float32, device=dev) for s in self.shapes]
+        self.w = [torch.empty(s, dtype=torch.float32, device=dev) for s in self.shapes]
+        self.stats = torch.zeros((len(self.shapes), 2), dtype=torch.float64, device=dev)
+        self.graph = None
+
+    def _normalize_into(self, i):
+        d = self.templates[self.owner[i]][0]
+        N = self.fft[i]
+        nz, ny, nx = self.shapes[i]
+        spec = self.spectra[(self.owner[i], N)]
+        call("ttm_normalize", self.ctx.h, C.byref(d), _ptr(self.volumes[i]), nz, ny, nx,
+             _ptr(spec[-1]), N, _ptr(self.g[i]), _ptr(self.w[i]), _ptr(self.stats[i]),
+             _ptr(self.ws_norm), self.ws_norm.numel(), _stream())
+
+    def run_eager(self):
+        """All items in order on the current stream (also what the graph records)."""
+        for i, s in enumerate(self.shapes):
+            o = self.owner[i]
+            d = self.templates[o][0]
+            N = self.fft[i]
+            spec = self.spectra[(o, N)]
+            K = n_components(d.degree, d.dprime)
+            self._normalize_into(i)
+            lo, hi = valid_bounds(s, d.L)
+            size = tuple(h - l + 1 for l, h in zip(lo, hi))
+            Ct = self.Cbuf[: K * int(np.prod(size))].view(K, *size)
+            correlate(self.ctx, d, self.g[i], self.w[i], self.stats[i], spec, N, lo, size, out=Ct,
+                      ws=self.ws_corr)
+            mlp = self.mlps[o] if self.mlps is not None else None
+            extract(self.ctx, d, Ct, score=self.score[i], lam=self.lam[i], direction=self.direction[i],
+                    out_lo=lo, out_dims=s, starts=self.starts, orient=self.orient, mlp=mlp,
+                    kappa=self.kappa, fallbacks=self.fallbacks, ws=self.ws_ext)
+            find_peaks_async(self.ctx, self.score[i], lo, hi, self.top_p, 2.0 * d.mask_radius,
+                             self.peaks[i], self.vals[i], self.n_found[i:i + 1], self.ws_peaks)
+
+    def capture(self):
+        """Record the whole batch into one HIP graph (after a warm-up on a side stream)."""
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self.run_eager()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.run_eager()
+        torch.cuda.synchronize()
+
+    def replay(self):
+        if self.graph is None:
+            self.capture()
+        self.graph.replay()
+
+
+def autotune(ctx: Context, desc: Desc, edges=FFT_EDGES, reps: int = 3) -> dict:
+    """Measured cost (ms) of one full-tile correlation per FFT edge (normalisation excluded)."""
+    cost = {}
+    dev = torch.device("cuda", ctx.device)
+    K = n_components(desc.degree, desc.dprime)
+    for N in edges:
+        if N < desc.L:
+            continue
+        T = torch.zeros((K, desc.L, desc.L, desc.L), dtype=torch.float32, device=dev)
+        spec = template_spectra(ctx, desc, T, N)
+        vol = torch.randn((N, N, N), dtype=torch.float32, device=dev)
+        g, w, stats = normalize(ctx, desc, vol, spec, N)
+        lo, hi = valid_bounds(vol.shape, desc.L)
+        size = tuple(h - l + 1 for l, h in zip(lo, hi))
+        out = torch.empty((K, *size), dtype=torch.float32, device=dev)
+        ws = _ws(desc, L.TTM_OP_CORRELATE, N, vol.shape, device=dev)
+        correlate(ctx, desc, g, w, stats, spec, N, lo, size, out=out, ws=ws)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            correlate(ctx, desc, g, w, stats, spec, N, lo, size, out=out, ws=ws)
+        b.record()
+        torch.cuda.synchronize()
+        cost[N] = a.elapsed_time(b) / reps
+        del T, spec, vol, g, w, out, ws
+    return cost

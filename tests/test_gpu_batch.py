@@ -1,0 +1,117 @@
+"""Batches of uneven subtomograms with several templates in one HIP graph.
+
+Checks: the graph replays (three, with eager work and synchronisation in
+between) reproduce the eager batch bit for bit; each item equals the
+stand-alone full pass of the same volume; the host-sync-free Find Peaks
+equals the synchronising one on shared maps.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_common import require_gpu
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def T():
+    require_gpu()
+    from paper_2408_02398_amd import ttm
+    return ttm
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    return T.Context(0)
+
+
+def cuda(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+@pytest.mark.parametrize("seed,shape,P,D", [(1, (20, 23, 26), 40, 3.0), (4, (33, 30, 31), 300, 4.5)])
+def test_async_peaks_equal_sync_peaks(T, ctx, seed, shape, P, D):
+    rng = np.random.default_rng(seed)
+    s = cuda(np.round(rng.uniform(0, 1, shape), 3).astype(np.float32))
+    lo, hi = (1, 2, 3), (shape[0] - 2, shape[1] - 1, shape[2] - 4)
+    pk, pv = T.find_peaks(ctx, s, lo, hi, P, D)
+    peaks = torch.zeros((P, 3), dtype=torch.int32, device="cuda")
+    vals = torch.zeros(P, dtype=torch.float32, device="cuda")
+    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+    d = T.make_desc(2, 4, 1.0)
+    ws = T._ws(d, 4, 32, shape, device="cuda")
+    T.find_peaks_async(ctx, s, lo, hi, P, D, peaks, vals, nf, ws)
+    n = int(nf.item())
+    assert n == pk.shape[0]
+    assert torch.equal(peaks[:n], pk) and torch.equal(vals[:n], pv)
+
+
+def _batch(T, ctx):
+    rng = np.random.default_rng(11)
+    templates, tmodels = [], []
+    for i, (L, r) in enumerate([(12, 5.0), (16, 7.0)]):
+        tm = synth.blob_template(np.random.default_rng(100 + i), L, 3)
+        Q = synth.rotation_samples(5)
+        d = T.make_desc(4, L, r)
+        Tg, _ = T.build_tensor(ctx, d, cuda(tm.volume()), cuda(Q))
+        templates.append((d, Tg))
+        tmodels.append(tm)
+    shapes = [(40, 40, 40), (48, 44, 52), (64, 64, 64), (36, 60, 41)]
+    owner = [0, 1, 0, 1]
+    vols = [rng.standard_normal(s).astype(np.float32) for s in shapes]
+    for v, o in zip(vols, owner):
+        tm = tmodels[o]
+        c = np.array(v.shape) // 2
+        rot = synth.random_rotations(rng, 1)
+        v += 3.0 * synth.render_copies(v.shape, tm, c[None], rot)
+    starts = cuda(synth.start_vectors())
+    be = T.BatchEngine(ctx, templates, shapes, owner, starts, top_p=3)
+    return be, vols, templates, shapes, owner, starts
+
+
+def test_batch_graph_replays_match_eager_and_single_passes(T, ctx):
+    be, vols, templates, shapes, owner, starts = _batch(T, ctx)
+    for i, v in enumerate(vols):
+        be.volumes[i].copy_(cuda(v))
+    be.run_eager()
+    torch.cuda.synchronize()
+    ref = [(be.score[i].clone(), be.lam[i].clone(), be.direction[i].clone(), be.peaks[i].clone(),
+            int(be.n_found[i].item())) for i in range(len(shapes))]
+    # each item equals the stand-alone engine on the same volume
+    for i, s in enumerate(shapes):
+        d, Tg = templates[owner[i]]
+        spec = T.template_spectra(ctx, d, Tg, be.fft[i])
+        eng = T.Engine(ctx, d, spec, be.fft[i], s, starts)
+        res = eng.run(cuda(vols[i]), top_p=3)
+        assert torch.equal(res.score, ref[i][0])
+        assert torch.equal(res.lam, ref[i][1])
+        assert torch.equal(res.direction, ref[i][2])
+        assert torch.equal(res.peaks, ref[i][3][:ref[i][4]])
+    be.capture()
+    for rep in range(3):
+        for i in range(len(shapes)):
+            be.score[i].zero_()
+            be.lam[i].zero_()
+            be.direction[i].zero_()
+        be.n_found.zero_()
+        _ = torch.randn(1000, device="cuda").sum().item()        # eager work between replays
+        be.replay()
+        torch.cuda.synchronize()
+        for i in range(len(shapes)):
+            assert torch.equal(be.score[i], ref[i][0]), (rep, i)
+            assert torch.equal(be.lam[i], ref[i][1]), (rep, i)
+            assert torch.equal(be.direction[i], ref[i][2]), (rep, i)
+            assert int(be.n_found[i].item()) == ref[i][4]
+            assert torch.equal(be.peaks[i], ref[i][3]), (rep, i)
+
+
+def test_pick_fft_and_tiles(T):
+    assert T.tiles_for((96, 96, 96), 40, 128) == 1
+    assert T.tiles_for((192, 192, 192), 40, 128) == 8
+    assert T.pick_fft((96, 96, 96), 40) == 128
+    # default model N^3 log2 N: one 256^3 tile (1.3e8) loses to eight 128^3 tiles (1.2e8)
+    assert T.pick_fft((192, 160, 192), 24) == 128
+    # a measured cost that makes small tiles cheap enough changes the choice
+    assert T.pick_fft((192, 192, 192), 40, {64: 0.001, 128: 1.0, 256: 100.0, 512: 1e4}) == 64
