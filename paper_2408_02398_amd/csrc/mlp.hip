@@ -26,13 +26,15 @@ namespace {
 // Epilogues: 0 store; 1 + bias[n]; 2 + bias[n], store Z to C and
 // bf16(relu(Z)) to C2; 3 multiply by [mask[m][n] > 0].
 // Workgroup: 4 wavefronts, 32 x 32 output tile, K in steps of 16.
+// With gridDim.z > 1 (split K, epilogue 0 only) workgroup z covers K-chunk z
+// and writes its partial tile to C + z * M * ldc; k_splitk_sum adds them in order.
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_gemm_bf16(const float* __restrict__ A, int lda,
                                                    const float* __restrict__ B, int ldb,
                                                    float* __restrict__ C, int ldc, int M, int N,
                                                    int K, int epi, const float* __restrict__ bias,
                                                    float* __restrict__ C2,
-                                                   const float* __restrict__ mask) {
+                                                   const float* __restrict__ mask, int kchunk) {
   __shared__ unsigned short As[32][16 + 2];
   __shared__ unsigned short Bs[16][32 + 2];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -40,18 +42,20 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const float* __restrict__ A, 
   const int wm = (w >> 1) * 16, wn = (w & 1) * 16;
   const int r16 = lane & 15, q = lane >> 4;
   f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
+  C += (size_t)blockIdx.z * M * ldc;
+  for (int k0 = kbeg; k0 < kend; k0 += 16) {
     // 512 A elements and 512 B elements per step; 2 of each per thread
     for (int e = tid; e < 512; e += 256) {
       const int r = e / 16, c = e % 16;       // A tile (32 x 16)
       const int m = m0 + r, k = k0 + c;
       float va = 0.0f;
-      if (m < M && k < K) va = TA ? A[(size_t)k * lda + m] : A[(size_t)m * lda + k];
+      if (m < M && k < kend) va = TA ? A[(size_t)k * lda + m] : A[(size_t)m * lda + k];
       As[r][c] = bf16_bits(va);
       const int kb = e / 32, nb = e % 32;     // B tile (16 x 32)
       const int kk = k0 + kb, n = n0 + nb;
       float vb = 0.0f;
-      if (kk < K && n < N) vb = TB ? B[(size_t)n * ldb + kk] : B[(size_t)kk * ldb + n];
+      if (kk < kend && n < N) vb = TB ? B[(size_t)n * ldb + kk] : B[(size_t)kk * ldb + n];
       Bs[kb][nb] = bf16_bits(vb);
     }
     __syncthreads();
@@ -75,6 +79,15 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const float* __restrict__ A, 
     C[o] = v;
     if (epi == 2) C2[o] = bf16_round(fmaxf(v, 0.0f));
   }
+}
+
+__global__ void k_splitk_sum(const float* __restrict__ part, int nsplit, size_t n,
+                             float* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.0f;
+  for (int z = 0; z < nsplit; ++z) s += part[(size_t)z * n + i];
+  out[i] = s;
 }
 
 // x = sqrt(mu_a) C_a / ||C||_F, zero padded to 32 columns; C is B x K (row per sample).
@@ -129,13 +142,20 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ Y, const
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// Column sums of a B x N matrix (bias gradients): one thread per column, fixed order.
-__global__ void k_colsum(const float* __restrict__ D, int B, int N, float* __restrict__ out) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+// Column sums of a B x N matrix (bias gradients, N <= 64) in two fixed-order
+// stages: each workgroup sums a chunk of kColRows rows, then one pass adds the chunks.
+constexpr int kColRows = 256;
+__global__ __launch_bounds__(256) void k_colsum_part(const float* __restrict__ D, int B, int N,
+                                                     float* __restrict__ part) {
+  __shared__ float red[4][64];
+  const int c = threadIdx.x & 63, sub = threadIdx.x >> 6;
+  const int r0 = blockIdx.x * kColRows;
   float s = 0.0f;
-  for (int b = 0; b < B; ++b) s += D[(size_t)b * N + n];
-  out[n] = s;
+  if (c < N)
+    for (int r = r0 + sub; r < min(B, r0 + kColRows); r += 4) s += D[(size_t)r * N + c];
+  red[sub][c] = s;
+  __syncthreads();
+  if (sub == 0 && c < N) part[(size_t)blockIdx.x * N + c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
 }
 
 __global__ void k_sum(const float* __restrict__ part, int n, float scale, float* __restrict__ out) {
@@ -202,17 +222,38 @@ __global__ void k_pack(const float* __restrict__ p, unsigned char* __restrict__ 
 
 template <bool TA, bool TB>
 void gemm(const float* A, int lda, const float* B, int ldb, float* C, int ldc, int M, int N, int K,
-          int epi, const float* bias, float* C2, const float* mask, hipStream_t s) {
-  hipLaunchKernelGGL((k_gemm_bf16<TA, TB>), dim3((N + 31) / 32, (M + 31) / 32), dim3(256), 0, s,
-                     A, lda, B, ldb, C, ldc, M, N, K, epi, bias, C2, mask);
+          int epi, const float* bias, float* C2, const float* mask, hipStream_t s,
+          float* splitk_ws = nullptr, int nsplit = 1) {
+  if (nsplit > 1) {
+    const int kchunk = ((K + nsplit - 1) / nsplit + 15) / 16 * 16;
+    const int nz = (K + kchunk - 1) / kchunk;
+    hipLaunchKernelGGL((k_gemm_bf16<TA, TB>), dim3((N + 31) / 32, (M + 31) / 32, nz), dim3(256), 0, s,
+                       A, lda, B, ldb, splitk_ws, ldc, M, N, K, 0, nullptr, nullptr, nullptr, kchunk);
+    const size_t n = (size_t)M * ldc;
+    hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, splitk_ws,
+                       nz, n, C);
+    return;
+  }
+  hipLaunchKernelGGL((k_gemm_bf16<TA, TB>), dim3((N + 31) / 32, (M + 31) / 32, 1), dim3(256), 0, s,
+                     A, lda, B, ldb, C, ldc, M, N, K, epi, bias, C2, mask, K);
 }
+
+void colsum(const float* D, int B, int N, float* out, float* part, hipStream_t s) {
+  const int nchunk = (B + kColRows - 1) / kColRows;
+  hipLaunchKernelGGL(k_colsum_part, dim3(nchunk), dim3(256), 0, s, D, B, N, part);
+  hipLaunchKernelGGL(k_splitk_sum, dim3(1), dim3(64), 0, s, part, nchunk, (size_t)N, out);
+}
+
+constexpr int kSplit = 64;
 
 }  // namespace
 
 size_t mlp_train_workspace(int B) {
   // X (32) + Z1, H1, Z2, H2, dZ1, dZ2 (64 each) + Y, dY (16 each) per sample,
   // gradient block, loss partials
-  return ((size_t)B * (32 + 6 * 64 + 2 * 16) + kMlpParams + (B + 255) / 256 + 64) * 4 + 1024;
+  // + split-K partial tiles (kSplit x 64 x 64) + column-sum partials
+  return ((size_t)B * (32 + 6 * 64 + 2 * 16) + kMlpParams + (B + 255) / 256 + 64 +
+          (size_t)kSplit * 64 * 64 + (size_t)((B + 255) / 256) * 64) * 4 + 1024;
 }
 
 int mlp_train_step(int degree, const float* Cin, const float* T, int B, float* params, float* adam_m,
@@ -231,6 +272,8 @@ int mlp_train_step(int degree, const float* Cin, const float* T, int B, float* p
   float* G = dY + (size_t)B * 16;
   float* part = G + kMlpParams;
   const int nb = (B + 255) / 256;
+  float* skw = part + nb + 64;                         // split-K partials
+  float* cpart = skw + (size_t)kSplit * 64 * 64;       // column-sum partials
   switch (degree) {
     case 2: hipLaunchKernelGGL(k_features<2>, dim3(nb), dim3(256), 0, s, Cin, B, X); break;
     case 4: hipLaunchKernelGGL(k_features<4>, dim3(nb), dim3(256), 0, s, Cin, B, X); break;
@@ -247,14 +290,15 @@ int mlp_train_step(int degree, const float* Cin, const float* T, int B, float* p
   hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, s, Y, T, B, dY, part);
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(64), 0, s, part, nb, 1.0f / (float)B, loss_out);
   // backward
-  gemm<true, false>(H2, 64, dY, 16, G + kOffW3, 16, 64, 16, B, 0, nullptr, nullptr, nullptr, s);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(64), 0, s, dY, B, 16, G + kOffB3);
+  const int ns = B >= 2048 ? kSplit : 1;
+  gemm<true, false>(H2, 64, dY, 16, G + kOffW3, 16, 64, 16, B, 0, nullptr, nullptr, nullptr, s, skw, ns);
+  colsum(dY, B, 16, G + kOffB3, cpart, s);
   gemm<false, true>(dY, 16, W3, 16, dZ2, 64, B, 64, 16, 3, nullptr, nullptr, Z2, s);
-  gemm<true, false>(H1, 64, dZ2, 64, G + kOffW2, 64, 64, 64, B, 0, nullptr, nullptr, nullptr, s);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(64), 0, s, dZ2, B, 64, G + kOffB2);
+  gemm<true, false>(H1, 64, dZ2, 64, G + kOffW2, 64, 64, 64, B, 0, nullptr, nullptr, nullptr, s, skw, ns);
+  colsum(dZ2, B, 64, G + kOffB2, cpart, s);
   gemm<false, true>(dZ2, 64, W2, 64, dZ1, 64, B, 64, 64, 3, nullptr, nullptr, Z1, s);
-  gemm<true, false>(X, 32, dZ1, 64, G + kOffW1, 64, 32, 64, B, 0, nullptr, nullptr, nullptr, s);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(64), 0, s, dZ1, B, 64, G + kOffB1);
+  gemm<true, false>(X, 32, dZ1, 64, G + kOffW1, 64, 32, 64, B, 0, nullptr, nullptr, nullptr, s, skw, ns);
+  colsum(dZ1, B, 64, G + kOffB1, cpart, s);
   if (grads_out) {
     TTM_HIP(hipMemcpyAsync(grads_out, G, kMlpParams * 4, hipMemcpyDeviceToDevice, s));
   }

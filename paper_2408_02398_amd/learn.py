@@ -99,7 +99,10 @@ def calibrate(ctx, desc, net, data: TrainingSet, starts, max_wrong: float = 0.02
     frac = torch.cumsum(wrong, 0) / torch.arange(1, len(wrong) + 1, device=wrong.device)
     ok = torch.nonzero(frac <= max_wrong).flatten()
     n_acc = int(ok.max().item()) + 1 if ok.numel() else 0
-    kappa = float(lam_hat[order[n_acc - 1]].item()) if n_acc > 0 else float("inf")
+    if n_acc == len(wrong):
+        kappa = float("-inf")        # every calibration voxel accepted: no lower bound is justified
+    else:
+        kappa = float(lam_hat[order[n_acc - 1]].item()) if n_acc > 0 else float("inf")
     return {"kappa": kappa, "accepted_fraction": n_acc / len(wrong),
             "wrong_without_fallback": float((ang > 1.0).float().mean().item()),
             "median_angle_without_fallback": float(ang.median().item()),
