@@ -40,6 +40,17 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def clean(o):
+    """Strict JSON: non-finite floats become None."""
+    if isinstance(o, float):
+        return o if math.isfinite(o) else None
+    if isinstance(o, dict):
+        return {k: clean(v) for k, v in o.items()}
+    if isinstance(o, (list, tuple)):
+        return [clean(v) for v in o]
+    return o
+
+
 def extract_flops(n: int, n_starts: int = 16) -> dict:
     """FP32 operations (an FMA counts 2) of the extraction kernel's pieces, d' = 3, degree n.
 
@@ -78,6 +89,8 @@ def main():
                     help="both = plain, learned (screened fallback) and learned without screening")
     ap.add_argument("--train-steps", type=int, default=6000)
     ap.add_argument("--train-volumes", type=int, default=5)
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="run the tile correlations on the same stream as the extractions")
     ap.add_argument("--precision-report", action="store_true",
                     help="FP32 vs BF16 field storage: throughput and error against the FP64 oracle")
     ap.add_argument("--max-wrong", type=float, default=0.05,
@@ -97,13 +110,13 @@ def main():
         sys.exit(2)
     cfg_name, fft_n, top_p = WORKLOADS[args.workload]
     if cfg_name == "c5_batch64_n6":
-        print(json.dumps(bench_batch(args, top_p)), flush=True)
+        print(json.dumps(clean(bench_batch(args, top_p))), flush=True)
         return
     p = synth.CONFIGS[cfg_name]
     n, L, r = p["degree"], p["L"], p["mask_radius"]
 
     if args.precision_report:
-        print(json.dumps(precision_report(args, cfg_name, fft_n, top_p)), flush=True)
+        print(json.dumps(clean(precision_report(args, cfg_name, fft_n, top_p))), flush=True)
         return
     t0 = time.time()
     log(f"[bench] generating {cfg_name} ...")
@@ -154,39 +167,10 @@ def main():
                          screen=(mode == "learned"))
 
         def one_pass(timed: bool):
-            ev = {}
-            if timed:
-                ev["norm"] = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                ev["norm"][0].record(stream)
-            g, w, stats = ttm.normalize(ctx, d, vol, spec, fft_n, ws=eng.ws_norm)
-            if timed:
-                ev["norm"][1].record(stream)
-            corr_ev, ext_ev = [], []
-            for (blo, size) in eng.boxes:
-                Ct = eng.Cbuf[: eng.K * size[0] * size[1] * size[2]].view(eng.K, *size)
-                if timed:
-                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                    a.record(stream)
-                ttm.correlate(ctx, d, g, w, stats, spec, fft_n, blo, size, out=Ct, ws=eng.ws_corr)
-                if timed:
-                    b.record(stream)
-                    corr_ev.append((a, b))
-                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                    a.record(stream)
-                ttm.extract(ctx, d, Ct, score=eng.score, lam=eng.lam, direction=eng.dir, out_lo=blo,
-                            out_dims=eng.shape, starts=starts, orient=True, mlp=eng.mlp,
-                            kappa=eng.kappa, fallbacks=eng.fallbacks, ws=eng.ws_extract,
-                            counters=counters if timed else None, screen=eng.screen)
-                if timed:
-                    b.record(stream)
-                    ext_ev.append((a, b, int(np.prod(size))))
-            if timed:
-                ev["peaks"] = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                ev["peaks"][0].record(stream)
-            pk, pv = ttm.find_peaks(ctx, eng.score, lo, hi, top_p, 2.0 * r, ws=eng.ws_peaks)
-            if timed:
-                ev["peaks"][1].record(stream)
-            return ev, corr_ev, ext_ev, pk
+            tm = {} if timed else None
+            res = eng.run(vol, top_p=top_p, timing=tm, overlap=not args.no_overlap,
+                          counters=counters if timed else None)
+            return tm, res.peaks
 
         for i in range(args.warmup):
             log(f"[bench] {mode}: warmup {i + 1}/{args.warmup}")
@@ -201,19 +185,19 @@ def main():
         start.record(stream)
         wall0 = time.time()
         for i in range(args.steps):
-            ev, corr_ev, ext_ev, pk = one_pass(True)
+            tm, pk = one_pass(True)
             torch.cuda.synchronize()
             log(f"[bench] {mode}: step {i + 1}/{args.steps} done")
-            stage["normalize"] += ev["norm"][0].elapsed_time(ev["norm"][1])
-            stage["peaks"] += ev["peaks"][0].elapsed_time(ev["peaks"][1])
-            for a, b in corr_ev:
+            stage["normalize"] += sum(a.elapsed_time(b) for a, b in tm["normalize"])
+            stage["peaks"] += sum(a.elapsed_time(b) for a, b in tm["peaks"])
+            for a, b, size in tm["correlate"]:
                 t = a.elapsed_time(b)
                 stage["correlate"] += t
                 corr_launch_ms.append(t)
-            for a, b, nv in ext_ev:
+            for a, b, size in tm["extract"]:
                 t = a.elapsed_time(b)
                 stage["extract"] += t
-                ext_launch_ms.append((t, nv))
+                ext_launch_ms.append((t, int(np.prod(size))))
         stop.record(stream)
         torch.cuda.synchronize()
         res = dict(eng=eng, pk=pk, stage=stage, ext=ext_launch_ms, corr=corr_launch_ms,
@@ -321,7 +305,7 @@ def main():
         "cpu_baseline": cpu,
         "wall_s": wall,
     }
-    print(json.dumps(out), flush=True)
+    print(json.dumps(clean(out)), flush=True)
 
 
 def accuracy_gate(plain, learned, lo, hi, top_p, ttm, torch):

@@ -331,7 +331,11 @@ class Engine:
         self.boxes = tile_boxes(self.shape, desc.L, fft_n)
         step = fft_n - desc.L + 1
         self.K = K
-        self.Cbuf = torch.empty(K * step ** 3, dtype=field_dtype, device=dev)
+        # two tile buffers: the correlation of tile k+1 runs on a side stream
+        # while tile k is extracted on the caller's stream
+        self.Cbufs = [torch.empty(K * step ** 3, dtype=field_dtype, device=dev) for _ in range(2)]
+        self.Cbuf = self.Cbufs[0]
+        self.side = torch.cuda.Stream(device=dev)
         self.ws_norm = _ws(desc, L.TTM_OP_NORMALIZE, fft_n, self.shape, device=dev)
         self.ws_corr = _ws(desc, L.TTM_OP_CORRELATE, fft_n, self.shape, device=dev)
         self.ws_peaks = _ws(desc, L.TTM_OP_PEAKS, fft_n, self.shape, device=dev)
@@ -342,23 +346,75 @@ class Engine:
         self.dir = torch.zeros((*self.shape, 3), dtype=torch.float32, device=dev) if orient else None
 
     def run(self, vol: torch.Tensor, top_p: int | None = None, min_dist: float | None = None,
-            tiles=None) -> PassResult:
+            tiles=None, overlap: bool = True, timing: dict | None = None,
+            counters: torch.Tensor | None = None) -> PassResult:
+        """One full pass.  With ``overlap`` the correlations run one tile ahead on a
+        side stream (HBM-bound) under the extractions (ALU-bound).  ``timing``, if
+        given, receives lists of (start, end) events per stage."""
+        main = torch.cuda.current_stream()
+        side = self.side if overlap else main
+
+        def ev():
+            return torch.cuda.Event(enable_timing=True) if timing is not None else None
+
+        def rec(e, stream):
+            if e is not None:
+                e.record(stream)
+
+        if timing is not None:
+            for k in ("normalize", "correlate", "extract", "peaks"):
+                timing.setdefault(k, [])
+        e0, e1 = ev(), ev()
+        rec(e0, main)
         g, w, stats = normalize(self.ctx, self.desc, vol, self.spectra, self.fft_n, ws=self.ws_norm)
-        for (lo, size) in (self.boxes if tiles is None else tiles):
-            Ct = self.Cbuf[: self.K * size[0] * size[1] * size[2]].view(self.K, *size)
-            correlate(self.ctx, self.desc, g, w, stats, self.spectra, self.fft_n, lo, size, out=Ct,
-                      ws=self.ws_corr)
+        rec(e1, main)
+        if timing is not None:
+            timing["normalize"].append((e0, e1))
+        boxes = self.boxes if tiles is None else tiles
+        if overlap:
+            side.wait_stream(main)
+        free = [None, None]
+        for k, (lo, size) in enumerate(boxes):
+            b = k % 2
+            Ct = self.Cbufs[b][: self.K * size[0] * size[1] * size[2]].view(self.K, *size)
+            with torch.cuda.stream(side):
+                if free[b] is not None:
+                    side.wait_event(free[b])
+                a0, a1 = ev(), ev()
+                rec(a0, side)
+                correlate(self.ctx, self.desc, g, w, stats, self.spectra, self.fft_n, lo, size,
+                          out=Ct, ws=self.ws_corr)
+                rec(a1, side)
+                ready = torch.cuda.Event()
+                ready.record(side)
+            if timing is not None:
+                timing["correlate"].append((a0, a1, size))
+            main.wait_event(ready)
+            x0, x1 = ev(), ev()
+            rec(x0, main)
             extract(self.ctx, self.desc, Ct, score=self.score, lam=self.lam, direction=self.dir,
                     out_lo=lo, out_dims=self.shape, starts=self.starts, orient=self.orient,
                     max_iter=self.max_iter, tol=self.tol, newton=self.newton, mlp=self.mlp,
                     kappa=self.kappa, fallbacks=self.fallbacks, ws=self.ws_extract,
-                    screen=self.screen)
+                    screen=self.screen, counters=counters)
+            rec(x1, main)
+            if timing is not None:
+                timing["extract"].append((x0, x1, size))
+            free[b] = torch.cuda.Event()
+            free[b].record(main)
+        if overlap:
+            main.wait_stream(side)
         peaks = vals = None
         if top_p:
+            p0, p1 = ev(), ev()
+            rec(p0, main)
             vlo, vhi = valid_bounds(self.shape, self.desc.L)
             peaks, vals = find_peaks(self.ctx, self.score, vlo, vhi, top_p,
                                      2.0 * self.desc.mask_radius if min_dist is None else min_dist,
                                      ws=self.ws_peaks)
+            rec(p1, main)
+            if timing is not None:
+                timing["peaks"].append((p0, p1))
         return PassResult(self.score, self.lam, self.dir, peaks, vals, w, g)
 
 
