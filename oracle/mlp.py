@@ -147,19 +147,27 @@ def unpad_params(flat: np.ndarray, k_in: int, d_out: int = 3) -> dict:
 
 
 def orient_learned(Cv: np.ndarray, n: int, p: dict, starts: np.ndarray, kappa: float,
-                   tol: float = 1e-5, max_iter: int = 500, newton: int = 2, bf16: bool = True):
+                   tol: float = 1e-5, max_iter: int = 500, newton: int = 2, bf16: bool = True,
+                   detail: bool = False):
     """Orientation with the learned start and its multistart fallback (d' = 3).
 
     SS-HOPM (+ polish) from the network's direction; if it does not reach tol,
     or lambda / ||C||_F < kappa, or some fixed start already has a larger value
     of <C, s^n> than the learned lambda (SS-HOPM never decreases lambda, so the
     multistart answer is then larger), the multistart search runs too and the
-    larger lambda wins.  Returns (lambda, u, fell_back).
+    larger lambda wins.  Returns (lambda, u, fell_back), and with ``detail`` a
+    fourth item: a dict with the learned answer (lam_learned, u_learned), how
+    far each fallback test was from flipping (beat_gap = best fixed-start value
+    minus the learned lambda, kappa_gap = lambda / ||C||_F - kappa, both scaled
+    by ||C||_F where they are values of the tensor) and, after a fallback, the
+    multistart's per-start lambdas and directions.
     """
     from . import ttm
     cn = float(sym.frobenius(Cv, n, 3))
     if cn == 0.0:
-        return 0.0, np.zeros(3), False
+        out = (0.0, np.zeros(3), False)
+        return out + ({"lam_learned": 0.0, "u_learned": np.zeros(3), "beat_gap": -np.inf,
+                       "kappa_gap": np.inf, "lams": None, "us": None},) if detail else out
     y, _ = forward(p, features(Cv[None, :], n), bf16=bf16)
     y = y[0]
     ny = np.linalg.norm(y)
@@ -170,10 +178,17 @@ def orient_learned(Cv: np.ndarray, n: int, p: dict, starts: np.ndarray, kappa: f
     u = ttm.newton_polish(Cu, n, u, newton)
     lam = float(sym.contract_n_minus_1(Cu, u, n) @ u)
     # a fixed start scoring above the learned answer means the multistart wins
-    beaten = any(sym.inner_power(Cu, s / np.linalg.norm(s), n) > lam for s in starts)
+    fs = max(sym.inner_power(Cu, s / np.linalg.norm(s), n) for s in starts)
+    beaten = fs > lam
+    info = {"lam_learned": cn * lam, "u_learned": ttm.canonical_sign(u), "beat_gap": cn * (fs - lam),
+            "kappa_gap": lam - kappa, "lams": None, "us": None}
     if conv and ny > 0 and lam >= kappa and not beaten:
-        return cn * lam, ttm.canonical_sign(u), False
-    lam_p, u_p, *_ = ttm.orient_multistart(Cv, n, starts, tol, max_iter, newton=newton)
+        out = (cn * lam, ttm.canonical_sign(u), False)
+        return out + (info,) if detail else out
+    lam_p, u_p, lams, us, _ = ttm.orient_multistart(Cv, n, starts, tol, max_iter, newton=newton)
+    info["lams"], info["us"] = lams, us
     if lam_p > cn * lam:
-        return lam_p, u_p, True
-    return cn * lam, ttm.canonical_sign(u), True
+        out = (lam_p, u_p, True)
+    else:
+        out = (cn * lam, ttm.canonical_sign(u), True)
+    return out + (info,) if detail else out

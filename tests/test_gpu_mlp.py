@@ -13,7 +13,7 @@ import pytest
 import synth
 from oracle import mlp as omlp
 from oracle import sym, ttm as orc
-from tests.gpu_common import require_gpu
+from tests.gpu_common import oracle_trained_params, require_gpu
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -127,7 +127,10 @@ def test_training_learns_and_learned_path_matches_oracle(T, ctx):
         last = net.train_step(Cg, tg, lr=3e-3)
     last = float(last.item())
     assert last < 0.25 * first
-    # learned orientation path vs the oracle's reading of it on held-out tensors
+    # learned orientation path vs the oracle's reading of it on held-out tensors;
+    # both sides take the network that the oracle trained on the CPU
+    pl = oracle_trained_params(12, n)
+    net = T.MLP(ctx, d, cuda(omlp.pad_params(pl, K)))
     Bt = 128
     vt = rng.standard_normal((Bt, 3))
     vt /= np.linalg.norm(vt, axis=1, keepdims=True)
@@ -138,7 +141,6 @@ def test_training_learns_and_learned_path_matches_oracle(T, ctx):
     _, lam, u = T.extract(ctx, d, cuda(Ct.T.reshape(K, 1, 1, Bt)), starts=cuda(starts), mlp=net,
                           kappa=kappa, fallbacks=fb)
     lg, ug = lam.cpu().numpy().ravel(), u.cpu().numpy().reshape(Bt, 3)
-    pl = omlp.unpad_params(net.params.cpu().numpy(), K)
     nfb = 0
     for i in range(Bt):
         lo, uo, fell = omlp.orient_learned(Ct[i], n, pl, starts.astype(np.float64), kappa)
