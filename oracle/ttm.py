@@ -361,13 +361,11 @@ def orient_multistart(Cv: np.ndarray, n: int, starts: np.ndarray, tol: float = 1
                       max_iter: int = 500, shift: float | None = None, newton: int = 2):
     """Dominant eigenpair of one voxel's tensor from fixed starts (Sec. 3.1).
 
-    Works on C / ||C||_F with the unfolding shift unless ``shift`` is given.
-    SS-HOPM runs from every start; the start with the largest lambda wins
-    (the first one on ties), and only that answer then takes ``newton``
-    polishing steps (d' = 3).  Returns (lambda, u, per-start lambdas,
-    per-start directions, per-start iterations); the per-start values are the
-    SS-HOPM results before polishing, and lambdas are scaled back by ||C||_F.
-    A zero tensor gives lambda = 0, u = 0.
+    Works on C / ||C||_F with the unfolding shift unless ``shift`` is given;
+    SS-HOPM from every start, then ``newton`` polishing steps (d' = 3).
+    Returns (lambda, u, per-start lambdas, per-start directions, per-start
+    iterations); lambdas are scaled back by ||C||_F.  A zero tensor gives
+    lambda = 0, u = 0.
     """
     d = starts.shape[1]
     cn = float(sym.frobenius(Cv, n, d))
@@ -379,17 +377,15 @@ def orient_multistart(Cv: np.ndarray, n: int, starts: np.ndarray, tol: float = 1
     lams, us, its = [], [], []
     for s in starts:
         lam, u, it, _ = sshopm(Cu, n, s, alpha, tol, max_iter)
+        if newton and d == 3:
+            u = newton_polish(Cu, n, u, newton)
+            lam = float(sym.contract_n_minus_1(Cu, u, n) @ u)
         lams.append(lam)
         us.append(u)
         its.append(it)
     lams = np.array(lams)
     best = int(np.argmax(lams))            # first maximum on ties
-    u = us[best]
-    lam = lams[best]
-    if newton and d == 3:
-        u = newton_polish(Cu, n, u, newton)
-        lam = float(sym.contract_n_minus_1(Cu, u, n) @ u)
-    return cn * lam, canonical_sign(u), cn * lams, np.array(us), np.array(its)
+    return cn * lams[best], canonical_sign(us[best]), cn * lams, np.array(us), np.array(its)
 
 
 def sshopm_rate(Cv: np.ndarray, n: int, u: np.ndarray, alpha: float | None = None) -> float:
