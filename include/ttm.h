@@ -179,9 +179,9 @@ typedef struct {
   const void* mlp;         /* device, packed MLP parameters (ttm_mlp_pack), or NULL */
   float fallback_kappa;    /* learned start: fall back when lambda < kappa * c, or
                               when SS-HOPM from the learned start did not reach tol */
-  int32_t max_iter;        /* SS-HOPM iteration cap per start                     */
+  int32_t max_iter;        /* SS-HOPM update cap per start, 1..2^24               */
   float tol;               /* stop when |delta lambda| <= tol (on C / ||C||_F)    */
-  int32_t newton_steps;    /* Newton polishing steps per start, 0..8 (default 2)  */
+  int32_t newton_steps;    /* Newton polishing steps per answer, 0..8 (default 2) */
   uint64_t* work_counters; /* device uint64[3] or NULL: adds {SS-HOPM steps, Newton
                               steps, oriented voxels} of this call (for FLOP counts) */
 } ttm_extract_opts;
@@ -196,25 +196,29 @@ typedef struct {
  *   n_fallback device int32 counter incremented per voxel whose learned start
  *             fell back to the multistart search, or NULL
  *   ws        device workspace of ttm_workspace_size(desc, TTM_OP_EXTRACT, 0,
- *             bz, by, bx) bytes (the fallback queue); may be NULL without
- *             TTM_START_MLP
+ *             bz, by, bx) bytes (run queues and per-run results, about 300
+ *             bytes per box voxel); required with TTM_ORIENT, may be NULL for
+ *             TTM_SCORE alone.  Calls that share a workspace must be ordered
+ *             on one stream.
+ * Orientation: alpha = max(0, -lambda_min(U)) with U the square unfolding of
+ * C/||C||_F (lambda_min of the unfolding's symmetric block bounded from below:
+ * its Gershgorin interval narrowed by 12 bisection steps with Cholesky tests,
+ * minus 1e-5, so alpha is never below the rule's value); SS-HOPM u <- (C u^{n-1} + alpha u)/||.|| from every start
+ * until |delta lambda| <= tol or max_iter updates, then up to newton_steps
+ * Riemannian Newton steps (taken where the tangent Hessian
+ * (n-1) E^T (C u^{n-2}) E - lambda I is negative definite, kept unless lambda
+ * drops by more than 1e-7); the largest lambda wins (first on ties); u is
+ * signed so its last non-zero coordinate is positive.  The (voxel, start) runs are spread over the GPU's lanes from a
+ * work queue, so a slow run does not hold up other voxels.
  * Learned start (TTM_START_MLP): per wavefront of 64 voxels the network
  * (ttm_mlp_train_step) maps x = sqrt(mu_a) C_a / ||C||_F to a start direction
- * on the BF16 matrix cores; SS-HOPM (+ polish) runs from it alone.  Voxels
- * whose result is not converged, has lambda < fallback_kappa * ||C||_F, or is
+ * on the BF16 matrix cores; SS-HOPM runs from it, then the Newton polish.
+ * Voxels whose
+ * result is not converged, has lambda < fallback_kappa * ||C||_F, or is
  * beaten by the value of <C, s^n> at one of the fixed starts s (SS-HOPM never
- * lowers lambda, so the multistart answer is then higher) are queued and
- * re-run by a second kernel with the full multistart search; the better of
- * the two answers is kept.  Requires lambda and dir.
- * Orientation: alpha = max(0, -lambda_min(U)) with U the square unfolding of
- * C/||C||_F (lambda_min bounded from below by three Jacobi sweeps of the
- * unfolding's symmetric block and Gershgorin discs, so alpha is never below
- * the rule's value); SS-HOPM u <- (C u^{n-1} + alpha u)/||.|| from every start until
- * |delta lambda| <= tol or max_iter, then up to newton_steps Riemannian Newton
- * steps (taken where the tangent Hessian (n-1) E^T (C u^{n-2}) E - lambda I is
- * negative definite, kept unless lambda drops by more than 1e-7); the largest
- * lambda wins (first on ties); u is signed so its last non-zero coordinate is
- * positive.
+ * lowers lambda, so the multistart answer is then higher) are queued for the
+ * multistart search above; the better of the two answers is kept.  Requires
+ * lambda and dir.
  */
 int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
                 const int32_t box_size[3], const ttm_extract_opts* opts, float* score,

@@ -148,10 +148,12 @@ def unpad_params(flat: np.ndarray, k_in: int, d_out: int = 3) -> dict:
 
 def orient_learned(Cv: np.ndarray, n: int, p: dict, starts: np.ndarray, kappa: float,
                    tol: float = 1e-5, max_iter: int = 500, newton: int = 2, bf16: bool = True,
-                   detail: bool = False):
+                   detail: bool = False, newton_first: int = 5):
     """Orientation with the learned start and its multistart fallback (d' = 3).
 
-    SS-HOPM (+ polish) from the network's direction; if it does not reach tol,
+    From the network's direction u0, up to ``newton_first`` Riemannian Newton
+    steps (ttm.newton_ascent); if they do not converge, SS-HOPM (+ polish) from
+    u0 instead.  If that answer did not reach tol,
     or lambda / ||C||_F < kappa, or some fixed start already has a larger value
     of <C, s^n> than the learned lambda (SS-HOPM never decreases lambda, so the
     multistart answer is then larger), the multistart search runs too and the
@@ -172,11 +174,13 @@ def orient_learned(Cv: np.ndarray, n: int, p: dict, starts: np.ndarray, kappa: f
     y = y[0]
     ny = np.linalg.norm(y)
     Cu = np.asarray(Cv, dtype=np.float64) / cn
-    alpha = ttm.unfolding_shift(Cu, n, 3)
     u0 = y / ny if ny > 0 else starts[0]
-    lam, u, _, conv = ttm.sshopm(Cu, n, u0, alpha, tol, max_iter)
-    u = ttm.newton_polish(Cu, n, u, newton)
-    lam = float(sym.contract_n_minus_1(Cu, u, n) @ u)
+    u, lam, conv = ttm.newton_ascent(Cu, n, u0, newton_first, tol)
+    if not conv:
+        alpha = ttm.unfolding_shift(Cu, n, 3)
+        lam, u, _, conv = ttm.sshopm(Cu, n, u0, alpha, tol, max_iter)
+        u = ttm.newton_polish(Cu, n, u, newton)
+        lam = float(sym.contract_n_minus_1(Cu, u, n) @ u)
     # a fixed start scoring above the learned answer means the multistart wins
     fs = max(sym.inner_power(Cu, s / np.linalg.norm(s), n) for s in starts)
     beaten = fs > lam

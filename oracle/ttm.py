@@ -357,6 +357,38 @@ def newton_polish(Cu: np.ndarray, n: int, u: np.ndarray, steps: int = 2,
     return u
 
 
+def newton_ascent(Cu: np.ndarray, n: int, u0: np.ndarray, steps: int, tol: float,
+                  drop: float = 1e-7):
+    """Riemannian Newton iterations for max <C, u^{(x)n}> on the unit sphere (d' = 3).
+
+    From u0, each step needs the tangent Hessian (n-1) E^T H E - lambda I to be
+    negative definite and may not lower lambda by more than ``drop``; the
+    iteration has converged after a step that changes lambda by at most
+    ``tol``.  Returns (u, lambda, converged); when it fails or runs out of
+    steps, converged is False.
+    """
+    u = np.asarray(u0, dtype=np.float64)
+    u = u / np.linalg.norm(u)
+    g = sym.contract_n_minus_1(Cu, u, n)
+    lam = float(g @ u)
+    for _ in range(steps):
+        E = tangent_basis(u)
+        Ht = (n - 1) * (E.T @ sym.contract_n_minus_2(Cu, u, n) @ E) - lam * np.eye(2)
+        if not (np.linalg.det(Ht) > 0 and np.trace(Ht) < 0):
+            return u, lam, False
+        un = u + E @ (-np.linalg.solve(Ht, E.T @ g))
+        un = un / np.linalg.norm(un)
+        gn = sym.contract_n_minus_1(Cu, un, n)
+        ln = float(gn @ un)
+        if ln < lam - drop:
+            return u, lam, False
+        done = abs(ln - lam) <= tol
+        u, g, lam = un, gn, ln
+        if done:
+            return u, lam, True
+    return u, lam, False
+
+
 def orient_multistart(Cv: np.ndarray, n: int, starts: np.ndarray, tol: float = 1e-5,
                       max_iter: int = 500, shift: float | None = None, newton: int = 2):
     """Dominant eigenpair of one voxel's tensor from fixed starts (Sec. 3.1).

@@ -486,7 +486,7 @@ size_t ttm_workspace_size(const ttm_desc* desc, int op, int fft_n, int nz, int n
       return align256(peaks_workspace((int64_t)nz * ny * nx));
     case TTM_OP_EXTRACT:
       if (nz < 1 || ny < 1 || nx < 1) return 0;
-      return 256 + align256((size_t)nz * ny * nx * 4);
+      return extract_workspace((size_t)nz * ny * nx);
     case TTM_OP_MLP_TRAIN:
       if (nz < 1) return 0;
       return align256(mlp_train_workspace(nz));
@@ -722,6 +722,7 @@ int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
       return TTM_EUNSUPPORTED;
     }
     if (!opts->starts || opts->n_starts < 1 || opts->n_starts > 64 || opts->max_iter < 1 ||
+        opts->max_iter > (1 << 24) ||
         !(opts->tol >= 0.0f) || opts->newton_steps < 0 || opts->newton_steps > 8 ||
         (!lambda && !dir)) {
       set_error("ttm_extract: orientation options invalid");
@@ -736,11 +737,11 @@ int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
         set_error("ttm_extract: learned start takes at most %d components", kMlpInMax);
         return TTM_EUNSUPPORTED;
       }
-      const size_t need = 256 + align256(plane * 4);
-      if (!ws || ws_bytes < need) {
-        set_error("ttm_extract: workspace %zu < %zu", ws_bytes, need);
-        return TTM_EWORKSPACE;
-      }
+    }
+    const size_t need = extract_workspace(plane);
+    if (!ws || ws_bytes < need) {
+      set_error("ttm_extract: workspace %zu < %zu", ws_bytes, need);
+      return TTM_EWORKSPACE;
     }
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -766,15 +767,13 @@ int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
   a.tol = opts->tol;
   a.newton = opts->newton_steps;
   a.counters = reinterpret_cast<unsigned long long*>(opts->work_counters);
+  a.ws = ws;
   if (mode & 4) {
     a.mlp = static_cast<const unsigned char*>(opts->mlp);
     a.kappa = opts->fallback_kappa;
     a.start_only = (mode & 8) ? 1 : 0;
     a.screen = (mode & 16) ? 0 : 1;
-    a.fb_count = static_cast<unsigned*>(ws);
-    a.fb_queue = reinterpret_cast<unsigned*>(static_cast<char*>(ws) + 256);
     a.fb_total = n_fallback;
-    fill_zero(ws, 256, s);
   }
   return launch_extract(desc->degree, a, s);
 }

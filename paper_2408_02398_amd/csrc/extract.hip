@@ -1,26 +1,96 @@
 // extract.hip -- per-voxel score and orientation from the tensor field (gfx950).
 //
-// One lane per voxel; the K components of C(x) live in registers for the
-// whole search.  Components are read plane by plane ([K][box] layout), so
-// every load is coalesced across the wavefront.
-//
 // Score: c = ||C||_F = sqrt(sum_a mu_a C_a^2) (Sec. 3.2).
-// Orientation (Sec. 3.1): on C / c, the SS-HOPM shift is
-// alpha = max(0, -lambda_min(U)) with U the square matrix unfolding.  U is
-// zero off the symmetric (n/2)-tensors, where it equals
+// Orientation (Sec. 3.1): SS-HOPM on C / c with the shift
+// alpha = max(0, -lambda_min(U)), U the square matrix unfolding.  U is zero
+// off the symmetric (n/2)-tensors, where it equals
 // B[b, g] = sqrt(mu_b mu_g) C_{b+g}, so lambda_min(U) = min(0, lambda_min(B));
-// B (10 x 10 at n = 6) is diagonalised by cyclic Jacobi sweeps in registers.
-// Each lane then runs SS-HOPM from every start in turn, moving to its next
-// start as soon as the current one has converged, so lanes of a wavefront do
-// not wait for each other's slow starts.
+// the kernels bound lambda_min(B) from below (Gershgorin interval narrowed by
+// bisection with Cholesky tests), so their shift is never below the rule's value.
+//
+// SS-HOPM runs take very different numbers of steps (a handful near a sharp
+// maximum, hundreds on a flat one), and a wavefront advances at the pace of its
+// slowest lane.  The kernels therefore do not tie a lane to a voxel:
+//
+//   multistart (all voxels, or the voxels the learned start hands back):
+//     k_prepare  one lane per voxel: score and the shift
+//     k_runs     persistent wavefronts drain a global queue of (voxel, start)
+//                runs; a lane that finishes a run takes the next one as soon
+//                as kRefill lanes of its wavefront wait, so lanes stay busy;
+//                each run's (u, lambda) goes to its own slot
+//     k_reduce   one lane per voxel: every run's answer takes the Newton
+//                polish, the largest polished lambda wins (first on ties)
+//   learned start:
+//     k_learned  one lane per voxel: BF16 MLP on the matrix cores gives the
+//                start u0, then at most kNewtonFirst Riemannian Newton steps
+//                (no shift needed); converged voxels are screened and
+//                written.  The others run SS-HOPM from u0 in k_runs (queue of
+//                saved iterates, shift from k_prepare), then k_learned_post
+//                polishes, screens and writes them.  Voxels that fail the
+//                checks go to the multistart path above, whose answer replaces
+//                the learned one when it is larger.
 #include "internal.hpp"
 #include "mlp_core.hpp"
 #include "sym_tables.hpp"
 
 namespace ttm {
 
-
 namespace {
+
+constexpr int kNewtonFirst = 5;   // Newton steps from the learned start inside k_learned
+constexpr int kRefill = 8;        // a pooled wavefront refills once this many lanes wait
+constexpr int kPoolGroups = 4096; // persistent pooled grid (one wavefront per group)
+constexpr int kStartBlock = 16;   // starts whose run results are held at once
+
+// Workspace layout (one 256-byte aligned array each, `plane` entries):
+// header (counters), fallback list, continuation list, continuation state
+// (u, lambda), continuation step count, shift, continuation flags, carried best
+// (u, lambda), run results [kStartBlock][plane] (u, lambda).
+enum HeaderSlot {
+  kHdrFallbacks = 0,   // fallback list length
+  kHdrContinue = 1,    // continuation list length
+  kHdrPoolCont = 2,    // k_runs work counters (64-bit, 8-byte aligned)
+  kHdrPoolDense = 4,   // + 2 per start block
+  kHdrPoolFb = 20,     // + 2 per start block
+  kHdrWords = 64
+};
+
+struct Ws {
+  unsigned* hdr;
+  unsigned* fb_list;
+  unsigned* cont_list;
+  float4* cont_state;
+  int* cont_it;
+  float* alpha;
+  unsigned char* conv;
+  float4* best;
+  float4* res;
+};
+
+__host__ __device__ inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+__host__ __device__ inline Ws ws_layout(void* base, size_t plane) {
+  char* p = static_cast<char*>(base);
+  Ws w;
+  w.hdr = reinterpret_cast<unsigned*>(p);
+  p += 256;
+  w.fb_list = reinterpret_cast<unsigned*>(p);
+  p += al256(plane * 4);
+  w.cont_list = reinterpret_cast<unsigned*>(p);
+  p += al256(plane * 4);
+  w.cont_state = reinterpret_cast<float4*>(p);
+  p += al256(plane * 16);
+  w.cont_it = reinterpret_cast<int*>(p);
+  p += al256(plane * 4);
+  w.alpha = reinterpret_cast<float*>(p);
+  p += al256(plane * 4);
+  w.conv = reinterpret_cast<unsigned char*>(p);
+  p += al256(plane);
+  w.best = reinterpret_cast<float4*>(p);
+  p += al256(plane * 16);
+  w.res = reinterpret_cast<float4*>(p);
+  return w;
+}
 
 __device__ __forceinline__ float bf16_to_f32(unsigned short h) {
   return __uint_as_float(((unsigned int)h) << 16);
@@ -87,59 +157,99 @@ __device__ __forceinline__ void contract2(const float (&c)[ncomp3(N)], float x, 
   }
 }
 
-// Up to `steps` Riemannian Newton steps for max <C, u^n> on the sphere from a
-// converged SS-HOPM point: tangent basis e1 = a x u/|a x u| (a = axis of the
-// smallest |u_i|), e2 = u x e1; tangent Hessian (n-1) E^T H E - lambda I must be
-// negative definite; the step is kept unless lambda drops by more than 1e-7.
+// One Riemannian Newton step for max <C, u^n> on the sphere from u, where
+// (g, lambda) = (C u^{n-1}, <C, u^n>): tangent basis e1 = a x u/|a x u| (a =
+// axis of the smallest |u_i|), e2 = u x e1; the tangent Hessian
+// (n-1) E^T H E - lambda I (H = C u^{n-2}) must be negative definite, else the
+// step is refused (false).  Otherwise v = retraction of u + E eta with
+// eta = -Hess^{-1} E^T g, and (q, lambda_v) its gradient and value.
+template <int N>
+__device__ __forceinline__ bool newton_step(const float (&c)[ncomp3(N)], float ux, float uy,
+                                            float uz, float g0, float g1, float g2, float lam,
+                                            float& vx, float& vy, float& vz, float& q0, float& q1,
+                                            float& q2, float& lam_v) {
+  const float fx = fabsf(ux), fy = fabsf(uy), fz = fabsf(uz);
+  float e1x, e1y, e1z;
+  if (fx <= fy && fx <= fz) {        // a = e_x: a x u = (0, -uz, uy)
+    e1x = 0.0f; e1y = -uz; e1z = uy;
+  } else if (fy <= fz) {             // a = e_y: (uz, 0, -ux)
+    e1x = uz; e1y = 0.0f; e1z = -ux;
+  } else {                           // a = e_z: (-uy, ux, 0)
+    e1x = -uy; e1y = ux; e1z = 0.0f;
+  }
+  const float r1 = 1.0f / sqrtf(e1x * e1x + e1y * e1y + e1z * e1z);
+  e1x *= r1; e1y *= r1; e1z *= r1;
+  const float e2x = uy * e1z - uz * e1y, e2y = uz * e1x - ux * e1z, e2z = ux * e1y - uy * e1x;
+  float h[6];
+  contract2<N>(c, ux, uy, uz, h);
+  const float hx1 = h[0] * e1x + h[1] * e1y + h[2] * e1z;
+  const float hy1 = h[1] * e1x + h[3] * e1y + h[4] * e1z;
+  const float hz1 = h[2] * e1x + h[4] * e1y + h[5] * e1z;
+  const float hx2 = h[0] * e2x + h[1] * e2y + h[2] * e2z;
+  const float hy2 = h[1] * e2x + h[3] * e2y + h[4] * e2z;
+  const float hz2 = h[2] * e2x + h[4] * e2y + h[5] * e2z;
+  constexpr float nm1 = (float)(N - 1);
+  const float a00 = nm1 * (e1x * hx1 + e1y * hy1 + e1z * hz1) - lam;
+  const float a01 = nm1 * (e1x * hx2 + e1y * hy2 + e1z * hz2);
+  const float a11 = nm1 * (e2x * hx2 + e2y * hy2 + e2z * hz2) - lam;
+  const float det = a00 * a11 - a01 * a01;
+  if (!(det > 0.0f && a00 + a11 < 0.0f)) return false;
+  const float t0 = e1x * g0 + e1y * g1 + e1z * g2, t1 = e2x * g0 + e2y * g1 + e2z * g2;
+  const float inv = 1.0f / det;
+  const float eta0 = -(a11 * t0 - a01 * t1) * inv;
+  const float eta1 = -(a00 * t1 - a01 * t0) * inv;
+  vx = ux + eta0 * e1x + eta1 * e2x;
+  vy = uy + eta0 * e1y + eta1 * e2y;
+  vz = uz + eta0 * e1z + eta1 * e2z;
+  const float rv = 1.0f / sqrtf(vx * vx + vy * vy + vz * vz);
+  vx *= rv; vy *= rv; vz *= rv;
+  contract<N>(c, vx, vy, vz, q0, q1, q2);
+  lam_v = q0 * vx + q1 * vy + q2 * vz;
+  return true;
+}
+
+// Up to `steps` Newton steps from a converged SS-HOPM point; a step is kept
+// unless lambda drops by more than 1e-7.  (g, lambda) must hold C u^{n-1} and
+// <C, u^n> at u on entry and are kept current.  Returns the steps computed.
 template <int N>
 __device__ __forceinline__ int newton_polish(const float (&c)[ncomp3(N)], float& ux, float& uy,
                                              float& uz, float& g0, float& g1, float& g2,
                                              float& lam, int steps) {
   int taken = 0;
   for (int s = 0; s < steps; ++s) {
-    const float fx = fabsf(ux), fy = fabsf(uy), fz = fabsf(uz);
-    float e1x, e1y, e1z;
-    if (fx <= fy && fx <= fz) {        // a = e_x: a x u = (0, -uz, uy)
-      e1x = 0.0f; e1y = -uz; e1z = uy;
-    } else if (fy <= fz) {             // a = e_y: (uz, 0, -ux)
-      e1x = uz; e1y = 0.0f; e1z = -ux;
-    } else {                           // a = e_z: (-uy, ux, 0)
-      e1x = -uy; e1y = ux; e1z = 0.0f;
-    }
-    const float r1 = 1.0f / sqrtf(e1x * e1x + e1y * e1y + e1z * e1z);
-    e1x *= r1; e1y *= r1; e1z *= r1;
-    const float e2x = uy * e1z - uz * e1y, e2y = uz * e1x - ux * e1z, e2z = ux * e1y - uy * e1x;
-    float h[6];
-    contract2<N>(c, ux, uy, uz, h);
-    // H e1, H e2
-    const float hx1 = h[0] * e1x + h[1] * e1y + h[2] * e1z;
-    const float hy1 = h[1] * e1x + h[3] * e1y + h[4] * e1z;
-    const float hz1 = h[2] * e1x + h[4] * e1y + h[5] * e1z;
-    const float hx2 = h[0] * e2x + h[1] * e2y + h[2] * e2z;
-    const float hy2 = h[1] * e2x + h[3] * e2y + h[4] * e2z;
-    const float hz2 = h[2] * e2x + h[4] * e2y + h[5] * e2z;
-    constexpr float nm1 = (float)(N - 1);
-    const float a00 = nm1 * (e1x * hx1 + e1y * hy1 + e1z * hz1) - lam;
-    const float a01 = nm1 * (e1x * hx2 + e1y * hy2 + e1z * hz2);
-    const float a11 = nm1 * (e2x * hx2 + e2y * hy2 + e2z * hz2) - lam;
-    const float det = a00 * a11 - a01 * a01;
-    if (!(det > 0.0f && a00 + a11 < 0.0f)) break;
-    const float t0 = e1x * g0 + e1y * g1 + e1z * g2, t1 = e2x * g0 + e2y * g1 + e2z * g2;
-    const float inv = 1.0f / det;
-    const float eta0 = -(a11 * t0 - a01 * t1) * inv;
-    const float eta1 = -(a00 * t1 - a01 * t0) * inv;
-    float vx = ux + eta0 * e1x + eta1 * e2x, vy = uy + eta0 * e1y + eta1 * e2y,
-          vz = uz + eta0 * e1z + eta1 * e2z;
-    const float rv = 1.0f / sqrtf(vx * vx + vy * vy + vz * vz);
-    vx *= rv; vy *= rv; vz *= rv;
-    float q0, q1, q2;
-    contract<N>(c, vx, vy, vz, q0, q1, q2);
-    const float lam_new = q0 * vx + q1 * vy + q2 * vz;
+    float vx, vy, vz, q0, q1, q2, lam_new;
+    if (!newton_step<N>(c, ux, uy, uz, g0, g1, g2, lam, vx, vy, vz, q0, q1, q2, lam_new)) break;
     ++taken;
     if (lam_new < lam - 1e-7f) break;
     ux = vx; uy = vy; uz = vz;
     g0 = q0; g1 = q1; g2 = q2;
     lam = lam_new;
+  }
+  return taken;
+}
+
+// Newton iteration from a start: up to `steps` steps, each refused when the
+// tangent Hessian is not negative definite or lambda drops by more than 1e-7;
+// converged (ok) after a step that changes lambda by at most tol.
+template <int N>
+__device__ __forceinline__ int newton_ascent(const float (&c)[ncomp3(N)], float& ux, float& uy,
+                                             float& uz, float& g0, float& g1, float& g2,
+                                             float& lam, int steps, float tol, bool& ok) {
+  int taken = 0;
+  ok = false;
+  for (int s = 0; s < steps; ++s) {
+    float vx, vy, vz, q0, q1, q2, lam_new;
+    if (!newton_step<N>(c, ux, uy, uz, g0, g1, g2, lam, vx, vy, vz, q0, q1, q2, lam_new)) break;
+    ++taken;
+    if (lam_new < lam - 1e-7f) break;
+    const bool done = fabsf(lam_new - lam) <= tol;
+    ux = vx; uy = vy; uz = vz;
+    g0 = q0; g1 = q1; g2 = q2;
+    lam = lam_new;
+    if (done) {
+      ok = true;
+      break;
+    }
   }
   return taken;
 }
@@ -156,115 +266,66 @@ __host__ __device__ constexpr int tri(int M, int p, int q) {
 }
 
 // Lower bound of lambda_min of B[b, g] = sqrt(mu_b mu_g) c_{b+g} over
-// |b| = |g| = n/2: three cyclic Jacobi sweeps (orthogonal similarity, so the
-// spectrum is unchanged) followed by Gershgorin discs, min_i (A_ii - sum |A_ij|).
-// The bound is exact up to the remaining off-diagonal mass and never above
-// lambda_min, so the shift -bound is never smaller than the unfolding rule's.
+// |b| = |g| = n/2.  The Gershgorin discs give lo <= lambda_min and the
+// smallest diagonal entry hi >= lambda_min; STEPS bisection steps then keep
+// lo where B - lo I passes a Cholesky factorisation (positive definite, so
+// lambda_min > lo).  The result lo - kShiftMargin stays below lambda_min under
+// FP32 rounding of the 10 x 10 factorisation (backward error a few 1e-6 for
+// entries of C / ||C||_F), so the shift -lo is never smaller than the
+// unfolding rule's, and exceeds it by at most (hi - lo) / 2^STEPS + margin.
+constexpr float kShiftMargin = 1e-5f;
+
 template <int N>
-__device__ __forceinline__ float unfolding_lambda_min(const float (&c)[ncomp3(N)]) {
+__device__ __forceinline__ float unfolding_entry(const float (&c)[ncomp3(N)], int p, int q) {
   constexpr int H = N / 2;
-  constexpr int M = ncomp3(H);
   constexpr Sym3<H> hs{};
-  float A[M * (M + 1) / 2];
-#pragma unroll
-  for (int p = 0; p < M; ++p) {
-#pragma unroll
-    for (int q = p; q < M; ++q) {
-      const float s = sqrtf(hs.mu[p] * hs.mu[q]);
-      A[tri(M, p, q)] = s * c[comp_index3(N, hs.ax[p] + hs.ax[q], hs.ay[p] + hs.ay[q])];
-    }
-  }
-  for (int sweep = 0; sweep < 3; ++sweep) {
-#pragma unroll
-    for (int p = 0; p < M - 1; ++p) {
-#pragma unroll
-      for (int q = p + 1; q < M; ++q) {
-        const float apq = A[tri(M, p, q)];
-        const float app = A[tri(M, p, p)], aqq = A[tri(M, q, q)];
-        // theta = (aqq - app) / (2 apq); apq = 0 gives t = 0 (no rotation)
-        const float theta = 0.5f * (aqq - app) / apq;
-        const float t = copysignf(1.0f / (fabsf(theta) + sqrtf(fmaf(theta, theta, 1.0f))), theta);
-        const float tt = (apq == 0.0f || !(fabsf(theta) < 1e30f)) ? 0.0f : t;
-        const float cs = 1.0f / sqrtf(fmaf(tt, tt, 1.0f));
-        const float sn = tt * cs;
-        A[tri(M, p, p)] = app - tt * apq;
-        A[tri(M, q, q)] = aqq + tt * apq;
-        A[tri(M, p, q)] = 0.0f;
-#pragma unroll
-        for (int r = 0; r < M; ++r) {
-          if (r == p || r == q) continue;
-          const float arp = A[tri(M, r, p)], arq = A[tri(M, r, q)];
-          A[tri(M, r, p)] = cs * arp - sn * arq;
-          A[tri(M, r, q)] = sn * arp + cs * arq;
-        }
-      }
-    }
-  }
-  float lmin = INFINITY;
+  return sqrtf(hs.mu[p] * hs.mu[q]) * c[comp_index3(N, hs.ax[p] + hs.ax[q], hs.ay[p] + hs.ay[q])];
+}
+
+template <int N, int STEPS>
+__device__ __forceinline__ float unfolding_lambda_min(const float (&c)[ncomp3(N)]) {
+  constexpr int M = ncomp3(N / 2);
+  float lo = INFINITY, hi = INFINITY;
 #pragma unroll
   for (int p = 0; p < M; ++p) {
     float rad = 0.0f;
 #pragma unroll
     for (int q = 0; q < M; ++q)
-      if (q != p) rad += fabsf(A[tri(M, p, q)]);
-    lmin = fminf(lmin, A[tri(M, p, p)] - rad);
+      if (q != p) rad += fabsf(unfolding_entry<N>(c, p, q));
+    const float d = unfolding_entry<N>(c, p, p);
+    lo = fminf(lo, d - rad);
+    hi = fminf(hi, d);
   }
-  return lmin;
+  for (int step = 0; step < STEPS; ++step) {
+    const float mid = 0.5f * (lo + hi);
+    // Cholesky of W = B - mid I (upper triangle R, packed); pd stays true while
+    // every pivot is positive
+    float R[M * (M + 1) / 2];
+    bool pd = true;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      float d = unfolding_entry<N>(c, j, j) - mid;
+#pragma unroll
+      for (int k = 0; k < j; ++k) d = fmaf(-R[tri(M, k, j)], R[tri(M, k, j)], d);
+      pd = pd && d > 0.0f;
+      const float r = pd ? 1.0f / sqrtf(d) : 0.0f;
+      R[tri(M, j, j)] = d * r;
+#pragma unroll
+      for (int i = j + 1; i < M; ++i) {
+        float e = unfolding_entry<N>(c, j, i);
+#pragma unroll
+        for (int k = 0; k < j; ++k) e = fmaf(-R[tri(M, k, j)], R[tri(M, k, i)], e);
+        R[tri(M, j, i)] = e * r;
+      }
+    }
+    if (pd) lo = mid; else hi = mid;
+  }
+  return lo - kShiftMargin;
 }
 
-// SS-HOPM from one start (then Newton polish).  Returns lambda on C/||C||_F;
-// u is updated in place; `conv` tells whether |delta lambda| <= tol was reached.
-template <int N>
-__device__ __forceinline__ float refine(const float (&c)[ncomp3(N)], float alpha, float& ux,
-                                        float& uy, float& uz, float tol, int max_iter, int newton,
-                                        unsigned long long& n_steps, unsigned long long& n_newton,
-                                        bool& conv) {
-  {
-    const float r = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
-    ux *= r; uy *= r; uz *= r;
-  }
-  float g0, g1, g2;
-  contract<N>(c, ux, uy, uz, g0, g1, g2);
-  float lam = g0 * ux + g1 * uy + g2 * uz;
-  conv = false;
-  for (int it = 0; it < max_iter; ++it) {
-    const float wx = fmaf(alpha, ux, g0), wy = fmaf(alpha, uy, g1), wz = fmaf(alpha, uz, g2);
-    const float r = 1.0f / sqrtf(wx * wx + wy * wy + wz * wz);
-    ux = wx * r; uy = wy * r; uz = wz * r;
-    contract<N>(c, ux, uy, uz, g0, g1, g2);
-    const float lam_new = g0 * ux + g1 * uy + g2 * uz;
-    ++n_steps;
-    const bool done = fabsf(lam_new - lam) <= tol;
-    lam = lam_new;
-    if (done) {
-      conv = true;
-      break;
-    }
-  }
-  n_newton += newton_polish<N>(c, ux, uy, uz, g0, g1, g2, lam, newton);
-  return lam;
-}
-
-// Best of SS-HOPM (+ polish) from every fixed start; a lane moves to its next
-// start as soon as the current one ends.  Returns lambda on C/||C||_F.
-template <int N>
-__device__ __forceinline__ float multistart(const float (&c)[ncomp3(N)], float alpha,
-                                            const float* st, int n_starts, float tol, int max_iter,
-                                            int newton, float& bx, float& by, float& bz,
-                                            unsigned long long& n_steps,
-                                            unsigned long long& n_newton) {
-  float best = -INFINITY;
-  for (int s = 0; s < n_starts; ++s) {
-    float ux = st[3 * s], uy = st[3 * s + 1], uz = st[3 * s + 2];
-    bool conv;
-    const float lam = refine<N>(c, alpha, ux, uy, uz, tol, max_iter, newton, n_steps, n_newton, conv);
-    if (lam > best) {
-      best = lam;
-      bx = ux; by = uy; bz = uz;
-    }
-  }
-  return best;
-}
+// Bisection steps of the shift bound for the multistart search and for the
+// learned start.
+constexpr int kShiftSteps = 12;
 
 __device__ __forceinline__ void canonical(float& x, float& y, float& z) {
   // u and -u are the same answer: make the last non-zero coordinate positive
@@ -294,18 +355,356 @@ __device__ __forceinline__ float load_tensor(const ExtractArgs& a, size_t v, flo
   return sqrtf(f2);
 }
 
+template <int N>
+__device__ __forceinline__ void scale(float (&c)[ncomp3(N)], float inv) {
+#pragma unroll
+  for (int k = 0; k < ncomp3(N); ++k) c[k] *= inv;
+}
+
 __device__ __forceinline__ size_t map_index(const ExtractArgs& a, size_t v) {
   const int vx = (int)(v % a.bx), vy = (int)((v / a.bx) % a.by), vz = (int)(v / ((size_t)a.bx * a.by));
   return ((size_t)(a.oz + vz) * a.dy + (a.oy + vy)) * a.dx + (a.ox + vx);
 }
 
-template <int N, bool MLP>
-__global__ __launch_bounds__(256) void k_extract(ExtractArgs a) {
+__device__ __forceinline__ void write_answer(const ExtractArgs& a, size_t o, float lam, float x,
+                                             float y, float z) {
+  if (a.lam) a.lam[o] = lam;
+  if (a.dir) {
+    a.dir[3 * o + 0] = x;
+    a.dir[3 * o + 1] = y;
+    a.dir[3 * o + 2] = z;
+  }
+}
+
+// <C, s^n> for every fixed start s as a dot product with the start's weighted
+// monomials mono[s][k] = mu_k s^alpha_k (s normalised), built once per block.
+template <int N>
+__device__ __forceinline__ void build_monomials(const float* st, int n_starts, float* mono) {
+  constexpr int K = ncomp3(N);
+  constexpr Sym3<N> sy{};
+  for (int i = threadIdx.x; i < n_starts * K; i += blockDim.x) {
+    const int s = i / K, k = i % K;
+    const float sx = st[3 * s], sy_ = st[3 * s + 1], sz = st[3 * s + 2];
+    const float r = 1.0f / sqrtf(sx * sx + sy_ * sy_ + sz * sz);
+    float m = sy.mu[k];
+    for (int e = 0; e < sy.ax[k]; ++e) m *= sx * r;
+    for (int e = 0; e < sy.ay[k]; ++e) m *= sy_ * r;
+    for (int e = 0; e < sy.az[k]; ++e) m *= sz * r;
+    mono[i] = m;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// score only
+// ---------------------------------------------------------------------------
+
+template <int N>
+__global__ __launch_bounds__(256) void k_score(ExtractArgs a) {
+  const size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= a.plane) return;
+  float c[ncomp3(N)];
+  a.score[map_index(a, v)] = load_tensor<N>(a, v, c);
+}
+
+// ---------------------------------------------------------------------------
+// multistart: shift per voxel, pooled runs, reduction
+// ---------------------------------------------------------------------------
+
+// Work list: `list` (box voxel per item, length *count) or all box voxels.
+struct Items {
+  const unsigned* list;
+  const unsigned* count;
+  __device__ __forceinline__ unsigned n(const ExtractArgs& a) const {
+    return list ? *count : (unsigned)a.plane;
+  }
+  __device__ __forceinline__ size_t voxel(unsigned j) const { return list ? list[j] : j; }
+};
+
+// Shift (and optionally the score) per item.  `add_total`: add the item
+// count to the caller's fallback counter.
+template <int N>
+__global__ __launch_bounds__(256) void k_prepare(ExtractArgs a, Items it, int write_score,
+                                                 int add_total) {
+  const Ws w = ws_layout(a.ws, a.plane);
+  const unsigned n = it.n(a);
+  if (add_total && a.fb_total && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.fb_total, (int)n);
+  const unsigned j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const size_t v = it.voxel(j);
+  float c[ncomp3(N)];
+  const float cn = load_tensor<N>(a, v, c);
+  if (write_score && a.score) a.score[map_index(a, v)] = cn;
+  float alpha = 0.0f;
+  if (cn > 0.0f) {
+    scale<N>(c, 1.0f / cn);
+    alpha = fmaxf(0.0f, -unfolding_lambda_min<N, kShiftSteps>(c));
+  }
+  w.alpha[j] = alpha;
+}
+
+// Persistent pooled SS-HOPM runs.  Run q of a chunk is item q / R, start
+// s0 + q % R (multistart) or the item's saved iterate (cont).  A wavefront
+// takes up to 64 items at a time from a global counter and stages their normalised
+// tensors (and shifts, saved iterates) in LDS; lanes whose run has ended take
+// the chunk's next runs as soon as kRefill of them wait.  Each run ends at
+// |delta lambda| <= tol or max_iter updates; its (u, lambda) is written to
+// res[(q % R) * plane + item] (and, for cont, conv[item]).
+struct RunArgs {
+  Items items;
+  int per_item;   // R
+  int s0;         // first start of this block
+  unsigned long long* ctr;
+};
+
+template <int N, bool CONT>
+__global__ __launch_bounds__(64) void k_runs(ExtractArgs a, RunArgs r) {
   constexpr int K = ncomp3(N);
   constexpr Sym3<N> sy{};
   __shared__ float st[64 * 3];
+  __shared__ float cs[K][64];     // chunk tensors, [component][item]
+  __shared__ float ca[64];        // shift per item
+  __shared__ float cz[64];        // ||C||_F per item (0: nothing to run)
+  __shared__ float4 cu[CONT ? 64 : 1];
+  __shared__ int ci[CONT ? 64 : 1];
+  const int lane = threadIdx.x;
+  for (int i = lane; i < a.n_starts * 3; i += 64) st[i] = a.starts[i];
+  __syncthreads();
+  const Ws w = ws_layout(a.ws, a.plane);
+  const unsigned n_items = r.items.n(a);
+  const int R = r.per_item;
+  // items per chunk: up to 64, fewer when the list is short, so that every
+  // wavefront of the grid gets several chunks
+  const unsigned per_wave = (n_items + 4 * gridDim.x - 1) / (4 * gridDim.x);
+  const unsigned chunk = per_wave < 1 ? 1 : (per_wave > 64 ? 64 : per_wave);
+  // chunk state (uniform across the wavefront)
+  unsigned chunk_base = 0;
+  int chunk_runs = 0, next_q = 0;
+  bool exhausted = n_items == 0;
+  // lane state
+  float c[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) c[k] = 0.0f;
+  float alpha = 0.0f, ux = 0.0f, uy = 0.0f, uz = 0.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, lam = 0.0f;
+  int iters = 0, s = 0;
+  unsigned j = 0;
+  bool first = false, busy = false;
+  unsigned long long n_steps = 0;
+  while (true) {
+    unsigned long long waiting = __ballot(!busy);
+    int n_wait = __popcll(waiting);
+    if (n_wait == 64 && exhausted && next_q == chunk_runs) break;
+    if (n_wait >= kRefill || n_wait == 64) {
+      while (n_wait > 0) {
+        if (next_q == chunk_runs) {
+          if (exhausted) break;
+          // next chunk of items
+          unsigned long long base = 0;
+          if (lane == 0) base = atomicAdd(r.ctr, (unsigned long long)chunk);
+          base = __shfl(base, 0);
+          if (base >= n_items) {
+            exhausted = true;
+            break;
+          }
+          const int cnt = (n_items - base) < chunk ? (int)(n_items - base) : (int)chunk;
+          if (base + chunk >= n_items) exhausted = true;
+          chunk_base = (unsigned)base;
+          chunk_runs = cnt * R;
+          next_q = 0;
+          __syncthreads();   // earlier LDS reads of the previous chunk are complete
+          if (lane < cnt) {
+            const unsigned jj = chunk_base + lane;
+            const size_t v = r.items.voxel(jj);
+            float f2 = 0.0f;
+            if (a.in_dtype == 1) {
+              const unsigned short* p = reinterpret_cast<const unsigned short*>(a.C);
+#pragma unroll
+              for (int k = 0; k < K; ++k) {
+                const float x = bf16_to_f32(p[k * a.plane + v]);
+                cs[k][lane] = x;
+                f2 = fmaf(sy.mu[k] * x, x, f2);
+              }
+            } else {
+              const float* p = reinterpret_cast<const float*>(a.C);
+#pragma unroll
+              for (int k = 0; k < K; ++k) {
+                const float x = p[k * a.plane + v];
+                cs[k][lane] = x;
+                f2 = fmaf(sy.mu[k] * x, x, f2);
+              }
+            }
+            const float cn = sqrtf(f2);
+            const float inv = cn > 0.0f ? 1.0f / cn : 0.0f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) cs[k][lane] *= inv;
+            cz[lane] = cn;
+            ca[lane] = w.alpha[jj];
+            if constexpr (CONT) {
+              cu[lane] = w.cont_state[jj];
+              ci[lane] = w.cont_it[jj] & ((1 << 30) - 1);
+            }
+          }
+          __syncthreads();
+        }
+        const int avail = chunk_runs - next_q;
+        const int take = n_wait < avail ? n_wait : avail;
+        if (!busy) {
+          const int rank = __popcll(waiting & ((1ull << lane) - 1ull));
+          if (rank < take) {
+            const int q = next_q + rank;
+            const int jl = q / R;
+            s = q % R;
+            j = chunk_base + jl;
+            if (cz[jl] > 0.0f) {
+#pragma unroll
+              for (int k = 0; k < K; ++k) c[k] = cs[k][jl];
+              alpha = ca[jl];
+              if constexpr (CONT) {
+                const float4 sv = cu[jl];
+                ux = sv.x; uy = sv.y; uz = sv.z;
+                iters = ci[jl];
+              } else {
+                const float sx = st[3 * (r.s0 + s)], sy_ = st[3 * (r.s0 + s) + 1],
+                            sz = st[3 * (r.s0 + s) + 2];
+                const float rs = 1.0f / sqrtf(sx * sx + sy_ * sy_ + sz * sz);
+                ux = sx * rs; uy = sy_ * rs; uz = sz * rs;
+                iters = 0;
+              }
+              first = true;
+              busy = true;
+            } else {
+              w.res[(size_t)s * a.plane + j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+              if constexpr (CONT) w.conv[j] = 1;
+            }
+          }
+        }
+        next_q += take;
+        waiting = __ballot(!busy);
+        n_wait = __popcll(waiting);
+      }
+    }
+    if (busy) {
+      if (!first) {
+        const float wx = fmaf(alpha, ux, g0), wy = fmaf(alpha, uy, g1), wz = fmaf(alpha, uz, g2);
+        const float rn = 1.0f / sqrtf(wx * wx + wy * wy + wz * wz);
+        ux = wx * rn; uy = wy * rn; uz = wz * rn;
+      }
+      contract<N>(c, ux, uy, uz, g0, g1, g2);
+      const float lam_new = g0 * ux + g1 * uy + g2 * uz;
+      bool conv = false, end = false;
+      if (first) {
+        first = false;
+      } else {
+        ++iters;
+        ++n_steps;
+        conv = fabsf(lam_new - lam) <= a.tol;
+        end = conv || iters >= a.max_iter;
+      }
+      lam = lam_new;
+      if (end) {
+        w.res[(size_t)s * a.plane + j] = make_float4(ux, uy, uz, lam);
+        if constexpr (CONT) w.conv[j] = conv ? 1 : 0;
+        busy = false;
+      }
+    }
+  }
+  if (a.counters) count_add(a.counters + 0, n_steps);
+}
+
+// Per item: every run of one start block takes the Newton polish, and the
+// largest polished lambda wins (first in start order on ties), carried across
+// blocks; after the last block the winner is written (merge: only where it
+// beats the answer already in the maps).
+template <int N>
+__global__ __launch_bounds__(256) void k_reduce(ExtractArgs a, Items it, int nsb, int first_block,
+                                                int last_block, int merge) {
+  constexpr int K = ncomp3(N);
+  const Ws w = ws_layout(a.ws, a.plane);
+  const unsigned n = it.n(a);
+  const unsigned j = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long n_newton = 0, n_oriented = 0;
+  if (j < n) {
+    const size_t v = it.voxel(j);
+    float c[K];
+    const float cn = load_tensor<N>(a, v, c);
+    float4 b = first_block ? make_float4(0.0f, 0.0f, 0.0f, -INFINITY) : w.best[j];
+    if (cn > 0.0f) {
+      scale<N>(c, 1.0f / cn);
+      for (int s = 0; s < nsb; ++s) {
+        const float4 r = w.res[(size_t)s * a.plane + j];
+        float ux = r.x, uy = r.y, uz = r.z, g0, g1, g2;
+        contract<N>(c, ux, uy, uz, g0, g1, g2);
+        float lam = g0 * ux + g1 * uy + g2 * uz;
+        n_newton += newton_polish<N>(c, ux, uy, uz, g0, g1, g2, lam, a.newton);
+        if (lam > b.w) b = make_float4(ux, uy, uz, lam);
+      }
+    }
+    if (!last_block) {
+      w.best[j] = b;
+    } else {
+      float lam = 0.0f, ux = 0.0f, uy = 0.0f, uz = 0.0f;
+      if (cn > 0.0f) {
+        ux = b.x; uy = b.y; uz = b.z;
+        canonical(ux, uy, uz);
+        lam = b.w * cn;
+        n_oriented = merge ? 0 : 1;
+      }
+      const size_t o = map_index(a, v);
+      if (!merge || lam > a.lam[o]) write_answer(a, o, lam, ux, uy, uz);
+    }
+  }
+  if (a.counters) {
+    count_add(a.counters + 1, n_newton);
+    count_add(a.counters + 2, n_oriented);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// learned start
+// ---------------------------------------------------------------------------
+
+// Polish, screen and write a learned-start answer; queue the voxel for the
+// multistart search when the run did not converge, lambda / ||C||_F < kappa,
+// the network gave no direction, or some fixed start s already has
+// <C, s^n> above lambda (SS-HOPM never lowers lambda, so the multistart
+// answer is then higher).
+template <int N>
+__device__ __forceinline__ unsigned long long learned_finish(
+    const ExtractArgs& a, const Ws& w, const float (&c)[ncomp3(N)], float cn, size_t v,
+    const float* mono, float ux, float uy, float uz, float g0, float g1, float g2, float lam,
+    bool conv, bool forced, int polish) {
+  constexpr int K = ncomp3(N);
+  const unsigned long long taken = newton_polish<N>(c, ux, uy, uz, g0, g1, g2, lam, polish);
+  bool beaten = false;
+  if (a.screen) {
+    for (int s = 0; s < a.n_starts; ++s) {
+      float f = 0.0f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) f = fmaf(mono[s * K + k], c[k], f);
+      beaten = beaten || f > lam;
+    }
+  }
+  const bool fallback = forced || !conv || !(lam >= a.kappa) || beaten;
+  canonical(ux, uy, uz);
+  write_answer(a, map_index(a, v), lam * cn, ux, uy, uz);
+  if (fallback) {
+    const unsigned slot = atomicAdd(&w.hdr[kHdrFallbacks], 1u);
+    w.fb_list[slot] = (unsigned)v;
+  }
+  return taken;
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void k_learned(ExtractArgs a) {
+  constexpr int K = ncomp3(N);
+  constexpr Sym3<N> sy{};
+  __shared__ float st[64 * 3];
+  __shared__ float mono[64 * K];
+  __shared__ unsigned short hs[4][64 * kMlpHid];
+  __shared__ float ys[4][64 * 4];
   for (int i = threadIdx.x; i < a.n_starts * 3; i += blockDim.x) st[i] = a.starts[i];
   __syncthreads();
+  if (a.screen) build_monomials<N>(st, a.n_starts, mono);
+  const Ws w = ws_layout(a.ws, a.plane);
   const size_t v0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = v0 < a.plane;
   const size_t v = active ? v0 : a.plane - 1;   // inactive lanes recompute the last voxel, write nothing
@@ -314,141 +713,142 @@ __global__ __launch_bounds__(256) void k_extract(ExtractArgs a) {
   const float cn = load_tensor<N>(a, v, c);
   const size_t o = map_index(a, v);
   if ((a.mode & 1) && active) a.score[o] = cn;
-  if constexpr (N >= 2) {
-    if (a.mode & 2) {
-      float lam_best = 0.0f, bx0 = 0.0f, by0 = 0.0f, bz0 = 0.0f;
-      const float inv = cn > 0.0f ? 1.0f / cn : 0.0f;
-      if constexpr (MLP) {
-        // ---- learned start: features -> BF16 MLP on the matrix cores;
-        // per wavefront [64][64] bf16 activations and [64][4] outputs
-        __shared__ unsigned short hs[4][64 * kMlpHid];
-        __shared__ float ys[4][64 * 4];
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        unsigned short* xs = &hs[wv][64 * kMlpIn];
+  const float inv = cn > 0.0f ? 1.0f / cn : 0.0f;
+  // features -> BF16 MLP on the matrix cores; per wavefront [64][64] bf16
+  // activations and [64][4] outputs
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  unsigned short* xs = &hs[wv][64 * kMlpIn];
 #pragma unroll
-        for (int k = 0; k < kMlpIn; ++k)
-          xs[lane * kMlpIn + k] = k < K ? bf16_bits(sqrtf(sy.mu[k]) * c[k] * inv) : (unsigned short)0;
-        __syncthreads();
-        float y0, y1, y2;
-        mlp_forward_wave(hs[wv], ys[wv], a.mlp, lane, y0, y1, y2);
-        const float ny = sqrtf(y0 * y0 + y1 * y1 + y2 * y2);
-        bool fallback = !(ny > 0.0f);
-        float ux = fallback ? st[0] : y0, uy = fallback ? st[1] : y1, uz = fallback ? st[2] : y2;
-        if (a.start_only) {
-          const float r = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
-          bx0 = ux * r; by0 = uy * r; bz0 = uz * r;
-          fallback = false;
-        } else if (cn > 0.0f) {
-#pragma unroll
-          for (int k = 0; k < K; ++k) c[k] *= inv;
-          const float alpha = fmaxf(0.0f, -unfolding_lambda_min<N>(c));
-          bool conv;
-          const float lam = refine<N>(c, alpha, ux, uy, uz, a.tol, a.max_iter, a.newton, n_steps,
-                                      n_newton, conv);
-          // screening: SS-HOPM never lowers lambda, so a fixed start that already
-          // scores above the learned answer proves the multistart answer is higher
-          bool beaten = false;
-          for (int s = 0; s < (a.screen ? a.n_starts : 0); ++s) {
-            const float sx = st[3 * s], sy = st[3 * s + 1], sz = st[3 * s + 2];
-            const float rs = 1.0f / sqrtf(sx * sx + sy * sy + sz * sz);
-            float q0, q1, q2;
-            contract<N>(c, sx * rs, sy * rs, sz * rs, q0, q1, q2);
-            beaten = beaten || ((q0 * sx + q1 * sy + q2 * sz) * rs > lam);
-          }
-          fallback = fallback || !conv || !(lam >= a.kappa) || (beaten && a.screen);
-          bx0 = ux; by0 = uy; bz0 = uz;
-          canonical(bx0, by0, bz0);
-          lam_best = lam * cn;
-          n_oriented = 1;
-        } else {
-          fallback = false;
-        }
-        if (active && fallback) {
-          const unsigned slot = atomicAdd(a.fb_count, 1u);
-          a.fb_queue[slot] = (unsigned)v;
-        }
-      } else if (cn > 0.0f) {
-        // ---- plain multistart
-#pragma unroll
-        for (int k = 0; k < K; ++k) c[k] *= inv;
-        const float alpha = fmaxf(0.0f, -unfolding_lambda_min<N>(c));
-        const float lam = multistart<N>(c, alpha, st, a.n_starts, a.tol, a.max_iter, a.newton, bx0,
-                                        by0, bz0, n_steps, n_newton);
-        canonical(bx0, by0, bz0);
-        lam_best = lam * cn;
-        n_oriented = 1;
-      }
-      if (active) {
-        if (a.lam) a.lam[o] = lam_best;
-        if (a.dir) {
-          a.dir[3 * o + 0] = bx0;
-          a.dir[3 * o + 1] = by0;
-          a.dir[3 * o + 2] = bz0;
-        }
-      }
-      if (a.counters) {
-        if (!active) n_steps = n_newton = n_oriented = 0;
-        count_add(a.counters + 0, n_steps);
-        count_add(a.counters + 1, n_newton);
-        count_add(a.counters + 2, n_oriented);
+  for (int k = 0; k < kMlpIn; ++k)
+    xs[lane * kMlpIn + k] = k < K ? bf16_bits(sqrtf(sy.mu[k]) * c[k] * inv) : (unsigned short)0;
+  __syncthreads();
+  float y0, y1, y2;
+  mlp_forward_wave(hs[wv], ys[wv], a.mlp, lane, y0, y1, y2);
+  const float ny = sqrtf(y0 * y0 + y1 * y1 + y2 * y2);
+  const bool forced = !(ny > 0.0f);
+  float ux = forced ? st[0] : y0, uy = forced ? st[1] : y1, uz = forced ? st[2] : y2;
+  {
+    const float r = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
+    ux *= r; uy *= r; uz *= r;
+  }
+  if (a.start_only) {
+    if (active) write_answer(a, o, 0.0f, ux, uy, uz);
+  } else if (cn > 0.0f) {
+    scale<N>(c, inv);
+    const float u0x = ux, u0y = uy, u0z = uz;
+    float g0, g1, g2;
+    contract<N>(c, ux, uy, uz, g0, g1, g2);
+    float lam = g0 * ux + g1 * uy + g2 * uz;
+    const float lam0 = lam;
+    bool ok;
+    n_newton = newton_ascent<N>(c, ux, uy, uz, g0, g1, g2, lam, kNewtonFirst, a.tol, ok);
+    n_oriented = 1;
+    if (active) {
+      if (ok) {
+        n_newton += learned_finish<N>(a, w, c, cn, v, mono, ux, uy, uz, g0, g1, g2, lam, true,
+                                      forced, 0);
+      } else {
+        // SS-HOPM from the learned start, continued in the pooled kernel
+        const unsigned slot = atomicAdd(&w.hdr[kHdrContinue], 1u);
+        w.cont_list[slot] = (unsigned)v;
+        w.cont_state[slot] = make_float4(u0x, u0y, u0z, lam0);
+        w.cont_it[slot] = forced ? (1 << 30) : 0;
       }
     }
+  } else if (active) {
+    write_answer(a, o, 0.0f, 0.0f, 0.0f, 0.0f);
+  }
+  if (a.counters) {
+    if (!active) n_steps = n_newton = n_oriented = 0;
+    count_add(a.counters + 0, n_steps);
+    count_add(a.counters + 1, n_newton);
+    count_add(a.counters + 2, n_oriented);
   }
 }
 
-// Fallback of the learned start: the voxels queued by k_extract run the full
-// multistart search; the better of that and the learned answer is kept.
+// Finish the continued learned-start runs (k_runs with cont) as k_learned does.
 template <int N>
-__global__ __launch_bounds__(256) void k_extract_fallback(ExtractArgs a) {
+__global__ __launch_bounds__(256) void k_learned_post(ExtractArgs a) {
   constexpr int K = ncomp3(N);
   __shared__ float st[64 * 3];
+  __shared__ float mono[64 * K];
   for (int i = threadIdx.x; i < a.n_starts * 3; i += blockDim.x) st[i] = a.starts[i];
   __syncthreads();
-  const unsigned count = *a.fb_count;
-  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && a.fb_total) atomicAdd(a.fb_total, (int)count);
-  if (i >= count) return;
-  const size_t v = a.fb_queue[i];
-  float c[K];
-  const float cn = load_tensor<N>(a, v, c);
-  if (!(cn > 0.0f)) return;
-  const float inv = 1.0f / cn;
-#pragma unroll
-  for (int k = 0; k < K; ++k) c[k] *= inv;
-  const float alpha = fmaxf(0.0f, -unfolding_lambda_min<N>(c));
-  unsigned long long n_steps = 0, n_newton = 0;
-  float bx0 = 0.0f, by0 = 0.0f, bz0 = 0.0f;
-  const float lam = multistart<N>(c, alpha, st, a.n_starts, a.tol, a.max_iter, a.newton, bx0, by0,
-                                  bz0, n_steps, n_newton) * cn;
-  const size_t o = map_index(a, v);
-  if (lam > a.lam[o]) {
-    canonical(bx0, by0, bz0);
-    a.lam[o] = lam;
-    a.dir[3 * o + 0] = bx0;
-    a.dir[3 * o + 1] = by0;
-    a.dir[3 * o + 2] = bz0;
+  if (a.screen) build_monomials<N>(st, a.n_starts, mono);
+  __syncthreads();
+  const Ws w = ws_layout(a.ws, a.plane);
+  const unsigned n = w.hdr[kHdrContinue];
+  const unsigned j = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long n_newton = 0;
+  if (j < n) {
+    const size_t v = w.cont_list[j];
+    float c[K];
+    const float cn = load_tensor<N>(a, v, c);
+    scale<N>(c, 1.0f / cn);
+    const float4 r = w.res[j];
+    float ux = r.x, uy = r.y, uz = r.z;
+    float g0, g1, g2;
+    contract<N>(c, ux, uy, uz, g0, g1, g2);
+    const float lam = g0 * ux + g1 * uy + g2 * uz;
+    const bool forced = (w.cont_it[j] >> 30) & 1;
+    n_newton = learned_finish<N>(a, w, c, cn, v, mono, ux, uy, uz, g0, g1, g2, lam,
+                                 w.conv[j] != 0, forced, a.newton);
   }
-  if (a.counters) {
-    atomicAdd(a.counters + 0, n_steps);
-    atomicAdd(a.counters + 1, n_newton);
-  }
+  if (a.counters) count_add(a.counters + 1, n_newton);
 }
 
 }  // namespace
+
+size_t extract_workspace(size_t plane) {
+  return 256 + al256(plane * 4) * 2 + al256(plane * 16) + al256(plane * 4) * 2 + al256(plane) +
+         al256(plane * 16) + (size_t)kStartBlock * plane * 16;
+}
+
+template <int N>
+int launch_multistart(const ExtractArgs& a, Items it, unsigned long long* ctr_base, int merge,
+                      hipStream_t s) {
+  const unsigned nb = (unsigned)((a.plane + 255) / 256);
+  const int n_blocks = (a.n_starts + kStartBlock - 1) / kStartBlock;
+  hipLaunchKernelGGL((k_prepare<N>), dim3(nb), dim3(256), 0, s, a, it,
+                     merge ? 0 : (a.mode & 1), merge);
+  for (int b = 0; b < n_blocks; ++b) {
+    const int nsb = (a.n_starts - b * kStartBlock) < kStartBlock ? (a.n_starts - b * kStartBlock)
+                                                                 : kStartBlock;
+    RunArgs r{it, nsb, b * kStartBlock, ctr_base + b};
+    hipLaunchKernelGGL((k_runs<N, false>), dim3(kPoolGroups), dim3(64), 0, s, a, r);
+    hipLaunchKernelGGL(k_reduce<N>, dim3(nb), dim3(256), 0, s, a, it, nsb, b == 0 ? 1 : 0,
+                       b == n_blocks - 1 ? 1 : 0, merge);
+  }
+  return 0;
+}
 
 template <int N>
 int launch_n(const ExtractArgs& a, hipStream_t s) {
   const unsigned nb = (unsigned)((a.plane + 255) / 256);
   if constexpr (N >= 2) {
-    if ((a.mode & 6) == 6) {
-      hipLaunchKernelGGL((k_extract<N, true>), dim3(nb), dim3(256), 0, s, a);
-      if (!a.start_only) hipLaunchKernelGGL(k_extract_fallback<N>, dim3(nb), dim3(256), 0, s, a);
-    } else {
-      hipLaunchKernelGGL((k_extract<N, false>), dim3(nb), dim3(256), 0, s, a);
+    if (a.mode & 2) {
+      const Ws w = ws_layout(a.ws, a.plane);
+      fill_zero(w.hdr, 256, s);
+      unsigned long long* ctr = reinterpret_cast<unsigned long long*>(w.hdr);
+      if ((a.mode & 4) == 0) {
+        launch_multistart<N>(a, Items{nullptr, nullptr}, ctr + kHdrPoolDense / 2, 0, s);
+      } else {
+        hipLaunchKernelGGL((k_learned<N>), dim3(nb), dim3(256), 0, s, a);
+        if (!a.start_only) {
+          const Items cont{w.cont_list, &w.hdr[kHdrContinue]};
+          hipLaunchKernelGGL((k_prepare<N>), dim3(nb), dim3(256), 0, s, a, cont, 0, 0);
+          RunArgs r{cont, 1, 0, ctr + kHdrPoolCont / 2};
+          hipLaunchKernelGGL((k_runs<N, true>), dim3(kPoolGroups), dim3(64), 0, s, a, r);
+          hipLaunchKernelGGL(k_learned_post<N>, dim3(nb), dim3(256), 0, s, a);
+          launch_multistart<N>(a, Items{w.fb_list, &w.hdr[kHdrFallbacks]}, ctr + kHdrPoolFb / 2,
+                               1, s);
+        }
+      }
+      hipError_t e = hipGetLastError();
+      return e == hipSuccess ? 0 : hip_status(e, "extract launch");
     }
-  } else {
-    hipLaunchKernelGGL((k_extract<N, false>), dim3(nb), dim3(256), 0, s, a);
   }
+  hipLaunchKernelGGL(k_score<N>, dim3(nb), dim3(256), 0, s, a);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : hip_status(e, "extract launch");
 }

@@ -90,17 +90,18 @@ struct ExtractArgs {
   int n_starts;
   int max_iter;
   float tol;
-  int newton;          // Newton polishing steps per start
+  int newton;          // Newton polishing steps of the selected answer
   unsigned long long* counters;  // optional: {SS-HOPM steps, Newton steps, oriented voxels}
   // learned start
   const unsigned char* mlp;      // packed BF16 parameters
   float kappa;                   // fall back when lambda / ||C||_F < kappa
   int start_only;                // write the network's start direction only
   int screen;                    // fall back when a fixed start beats the learned lambda
-  unsigned* fb_count;            // fallback queue length (workspace)
-  unsigned* fb_queue;            // fallback voxel indices (workspace)
+  void* ws;                      // work queues and run results (extract_workspace bytes)
   int* fb_total;                 // optional caller counter of fallbacks
 };
+// Workspace bytes of an orientation extraction over `plane` voxels.
+size_t extract_workspace(size_t plane);
 int launch_extract(int degree, const ExtractArgs& a, hipStream_t s);
 
 // Find Peaks (peaks.hip).

@@ -175,8 +175,8 @@ def extract(ctx: Context, desc: Desc, Cf: torch.Tensor, *, score=None, lam=None,
                 mode |= L.TTM_NO_SCREEN
             opts.mlp = mlp.packed.data_ptr()
             opts.fallback_kappa = kappa
-            if ws is None:
-                ws = _ws(desc, L.TTM_OP_EXTRACT, 0, box, device=dev)
+        if ws is None:
+            ws = _ws(desc, L.TTM_OP_EXTRACT, 0, box, device=dev)
     opts.mode = mode
     opts.max_iter = max_iter
     opts.tol = tol

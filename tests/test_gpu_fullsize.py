@@ -9,10 +9,11 @@ oracle within seconds; the rotation count does not change any kernel's work
 per voxel.
 
 Tolerances as in the small-size tests: w and the score within 1e-4 relative
-(score relative to max(score, median score)); lambda within 1e-4 of the score
-unless several maxima are nearly tied (then within the tie gap); directions
-within 1 degree where the maximiser is well conditioned (SS-HOPM rate < 0.95
-and a margin to other maxima above 1e-4 of the score).
+(score relative to max(score, median score)); lambda within 1e-4 of that
+floor, plus the SS-HOPM stopping error score * tol * rate / (1 - rate) on flat
+maxima, plus the gap between nearly tied maxima; directions within 1 degree
+where the maximiser is well conditioned (SS-HOPM rate < 0.95 and a margin to
+other maxima above 1e-4 of the score).
 """
 import functools
 
@@ -134,9 +135,14 @@ def test_full_size_sampled_parity(T, ctx, name, start):
             else:
                 lams, us = np.array([lam_o]), u_o[None, :]
         margin = orc.orientation_margin(lams, us, u_o)
-        assert abs(lg[i] - lam_o) <= max(1e-4 * floor[i], 0.0 if margin > 1e-4 * so[i] else margin
-                                         + 1e-4 * floor[i]), (i, pts[i])
-        if margin > 1e-4 * so[i] and orc.sshopm_rate(Co[i], n, u_o) < 0.95:
+        # both sides stop SS-HOPM at |delta lambda| <= tol (on C / ||C||_F), which
+        # leaves lambda up to tol * rate / (1 - rate) below its limit on a flat
+        # maximum (rate = the linearised SS-HOPM factor there)
+        rate = orc.sshopm_rate(Co[i], n, u_o)
+        stop = so[i] * 1e-5 * rate / (1.0 - rate) if rate < 1.0 else np.inf
+        tie = margin if margin <= 1e-4 * so[i] else 0.0
+        assert abs(lg[i] - lam_o) <= 1e-4 * floor[i] + stop + tie, (i, pts[i], rate)
+        if margin > 1e-4 * so[i] and rate < 0.95:
             assert orc.angle_deg(ug[i], u_o) < 1.0, (i, pts[i])
             checked += 1
     say(f"[fullsize {name} {start}] orientation checked at {checked} of {len(pts)} voxels")

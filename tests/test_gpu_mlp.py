@@ -164,9 +164,13 @@ def test_forced_fallback_equals_multistart(T, ctx):
     _, lam_p, u_p = T.extract(ctx, d, Cg, starts=starts)
     assert int(fb.item()) == B
     ll, lp = lam_l.cpu().numpy().ravel(), lam_p.cpu().numpy().ravel()
-    assert np.all(ll >= lp - 1e-6 * np.abs(lp))
-    same = ll == lp
-    assert same.mean() > 0.9
-    # same maximum: the two kernels round in their own order, so compare to FP32 noise
-    assert np.allclose(u_l.cpu().numpy().reshape(B, 3)[same], u_p.cpu().numpy().reshape(B, 3)[same],
-                       atol=1e-5)
+    # every voxel fell back, so the answer is the larger of the learned one and
+    # the multistart's, which is the plain multistart computed by the same kernels
+    assert np.all(ll >= lp)
+    eq = ll == lp
+    assert eq.mean() > 0.5
+    # equal lambda: the multistart answer, or the learned one at the same maximum
+    # (lambda is flat there, so FP32 lambda ties while u differs by rounding)
+    ang = orc.angle_deg(u_l.cpu().numpy().reshape(B, 3)[eq], u_p.cpu().numpy().reshape(B, 3)[eq])
+    assert np.max(ang) < 0.1
+

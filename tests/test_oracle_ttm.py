@@ -440,3 +440,55 @@ def test_multistart_with_polish_matches_tight_sshopm():
             lam2, u2, *_ = ttm.orient_multistart(C, n, st, tol=1e-15, max_iter=100000, newton=0)
             assert lam == pytest.approx(lam2, rel=1e-9)
             assert ttm.angle_deg(u, u2) < 1e-3
+
+
+def test_newton_ascent_reaches_eigenvectors_and_refuses_non_maxima():
+    rng = np.random.default_rng(43)
+    # n = 2: <C, u^2> = u^T A u, whose maximisers on the sphere are the top
+    # eigenvectors of A (numpy.linalg.eigh)
+    for _ in range(5):
+        A = rng.standard_normal((3, 3))
+        A = A + A.T
+        C = np.array([A[0, 0], A[0, 1], A[0, 2], A[1, 1], A[1, 2], A[2, 2]])   # graded-lex, n = 2
+        w, V = np.linalg.eigh(A)
+        top, bottom = V[:, 2], V[:, 0]
+        u0 = top + 0.05 * rng.standard_normal(3)
+        u, lam, ok = ttm.newton_ascent(C, 2, u0, 8, 1e-12)
+        assert ok and lam == pytest.approx(w[2], rel=1e-10) and ttm.angle_deg(u, top) < 1e-6
+        # from near the bottom eigenvector the tangent Hessian is positive definite: refused
+        u, lam, ok = ttm.newton_ascent(C, 2, bottom + 0.01 * rng.standard_normal(3), 8, 1e-12)
+        assert not ok
+    # rank one: C = v^n has its maximum lambda = 1 at u = +-v
+    for n in (4, 6):
+        v = rng.standard_normal(3)
+        v /= np.linalg.norm(v)
+        C = sym.monomials(v, n)
+        u0 = v + 0.08 * np.cross(v, rng.standard_normal(3))
+        u, lam, ok = ttm.newton_ascent(C, n, u0, 8, 1e-14)
+        assert ok and lam == pytest.approx(1.0, abs=1e-12) and ttm.angle_deg(u, v) < 1e-6
+
+
+def test_newton_ascent_from_near_starts_matches_sshopm_with_polish():
+    rng = np.random.default_rng(44)
+    n = 6
+    agree = total = 0
+    for _ in range(60):
+        v = rng.standard_normal(3)
+        v /= np.linalg.norm(v)
+        C = sym.monomials(v, n) + 0.3 * rng.standard_normal(28)
+        Cu = C / ttm.score(C, n)
+        alpha = ttm.unfolding_shift(Cu, n, 3)
+        _, u_s, _, _ = ttm.sshopm(Cu, n, v, alpha, 1e-13, 20000)
+        w = rng.standard_normal(3)
+        w -= (w @ u_s) * u_s
+        u0 = np.cos(np.radians(2.0)) * u_s + np.sin(np.radians(2.0)) * w / np.linalg.norm(w)
+        u, lam, ok = ttm.newton_ascent(Cu, n, u0, 5, 1e-5)
+        if ok:
+            total += 1
+            # the Newton answer is a critical point up to the stopping rule: the
+            # last step changed lambda by <= 1e-5, i.e. the previous error was
+            # ~ sqrt(1e-5) and the quadratic step leaves ~ 1e-5 of it
+            g = sym.contract_n_minus_1(Cu, u, n)
+            assert np.linalg.norm(g - (g @ u) * u) < 3e-5
+            agree += ttm.angle_deg(u, u_s) < 0.05
+    assert total >= 55 and agree == total
