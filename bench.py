@@ -1,8 +1,9 @@
 """Benchmark: tomogram voxels per second for a full TTM pass on one MI355X.
 
 A step is one full pass over the tomogram: prefilter + local normalisation,
-the K FFT correlations on overlapping 256^3 tiles, per-voxel score and
-orientation (SS-HOPM) on every valid voxel, and Find Peaks.  The tomogram and
+the K FFT correlations on overlapping tiles (512^3 for the 512 x 928 x 928
+tomogram: 4 tiles), per-voxel score and orientation (SS-HOPM) on every valid
+voxel, and Find Peaks.  The tomogram and
 the template spectra are resident on the GPU before timing starts; the
 one-time tensor template and its spectra are built beforehand and are not
 timed (the paper excludes template generation too).
@@ -25,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 WORKLOADS = {
     # name: (synth config, FFT tile edge, peaks P)
-    "c3_512x928x928_n6": ("c3_512x928x928_n6", 256, 2000),
+    "c3_512x928x928_n6": ("c3_512x928x928_n6", 512, 2000),
     "c2_256cube_n6": ("c2_256cube_n6", 256, 200),
     "c1_64cube_n4": ("c1_64cube_n4", 64, 5),
     # 64 subtomograms, edges in {96,128,160,192}, 3 templates, one graph launch per batch
@@ -51,28 +52,30 @@ def clean(o):
     return o
 
 
-def extract_flops(n: int, n_starts: int = 16) -> dict:
-    """FP32 operations (an FMA counts 2) of the extraction kernel's pieces, d' = 3, degree n.
+def extract_flops(n: int, n_starts: int = 16, shift_steps: int = 12) -> dict:
+    """FP32 operations (an FMA counts 2) of the extraction kernels' pieces, d' = 3, degree n.
 
-    Counted from the kernel's arithmetic: contract = C u^{n-1} (powers,
+    Counted from the kernels' arithmetic: contract = C u^{n-1} (powers,
     monomials with their multinomial, 3 FMAs per monomial); step = one SS-HOPM
-    update; newton = one polishing step (tangent basis, C u^{n-2}, 2 x 2 solve,
-    retraction, new gradient); setup = normalisation, unfolding block, three
-    Jacobi sweeps with the Gershgorin bound, and the first gradient of every
-    start; score = ||C||_F.
+    update; newton = one Newton step (tangent basis, C u^{n-2}, 2 x 2 solve,
+    retraction, new gradient); shift = Gershgorin interval of the unfolding
+    block plus `shift_steps` Cholesky bisection tests; run = start
+    normalisation and its first gradient, plus the gradient the reduction
+    recomputes at the run's answer; score = ||C||_F; learned = features and
+    the first gradient of the learned start (its BF16 MLP runs on the matrix
+    cores and is counted apart); screen = <C, s^n> for every fixed start.
     """
     K = (n + 1) * (n + 2) // 2
     Kb = n * (n + 1) // 2
     K2 = (n - 1) * n // 2
-    H = (n // 2 + 1) * (n // 2 + 2) // 2
+    M = (n // 2 + 1) * (n // 2 + 2) // 2
     contract = 3 * (n - 1) + 9 * Kb
     contract2 = 3 * (n - 2) + 15 * K2
-    step = contract + 23
-    newton = contract2 + contract + 106
-    jacobi = 3 * (H * (H - 1) // 2) * (6 * (H - 2) + 20) + 2 * H * H   # 3 sweeps + Gershgorin
-    setup = K + H * (H + 1) // 2 + jacobi + n_starts * (contract + 13)
-    setup_one = K + H * (H + 1) // 2 + jacobi + (contract + 13) + K   # learned: one start + features
-    return dict(score=2 * K + 1, step=step, newton=newton, setup=setup, setup_one=setup_one)
+    chol = M * (M + 1) // 2 + sum(2 * j + 3 for j in range(M)) + sum((M - 1 - j) * (2 * j + 1) for j in range(M))
+    return dict(score=2 * K + 1, step=contract + 23, newton=contract2 + contract + 106,
+                shift=2 * M * M + shift_steps * chol, run=2 * contract + 10,
+                learned=2 * K + contract, screen=n_starts * 2 * K,
+                mlp_mfma=2 * (32 * 64 + 64 * 64 + 64 * 16))
 
 
 def main():
@@ -81,6 +84,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3_512x928x928_n6", choices=sorted(WORKLOADS))
+    ap.add_argument("--fft", type=int, default=0, help="FFT tile edge (0: the workload's default)")
     ap.add_argument("--nq-base", type=int, default=1000, help="super-Fibonacci points per cube rotation")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=400, help="voxels in the oracle timing sample")
@@ -109,6 +113,8 @@ def main():
         print(json.dumps({"error": "no GPU"}))
         sys.exit(2)
     cfg_name, fft_n, top_p = WORKLOADS[args.workload]
+    if args.fft:
+        fft_n = args.fft
     if cfg_name == "c5_batch64_n6":
         print(json.dumps(clean(bench_batch(args, top_p))), flush=True)
         return
@@ -159,17 +165,17 @@ def main():
 
     # per-stage timing with events on the stream the library launches on
     stream = torch.cuda.current_stream()
-    counters = torch.zeros(3, dtype=torch.int64, device=dev)   # extraction work (timed steps)
+    counters = torch.zeros(5, dtype=torch.int64, device=dev)   # extraction work (timed steps)
 
     def run_mode(mode: str):
         eng = ttm.Engine(ctx, d, spec, fft_n, vol.shape, starts, field_dtype=field_dtype,
                          mlp=net if mode.startswith("learned") else None, kappa=kappa,
                          screen=(mode == "learned"))
 
-        def one_pass(timed: bool):
+        def one_pass(timed: bool, count: bool = False):
             tm = {} if timed else None
             res = eng.run(vol, top_p=top_p, timing=tm, overlap=not args.no_overlap,
-                          counters=counters if timed else None)
+                          counters=counters if count else None)
             return tm, res.peaks
 
         for i in range(args.warmup):
@@ -200,10 +206,17 @@ def main():
                 ext_launch_ms.append((t, int(np.prod(size))))
         stop.record(stream)
         torch.cuda.synchronize()
+        fallbacks = int(eng.fallbacks.item()) // max(args.steps, 1)
+        wall = time.time() - wall0
+        # work counts (SS-HOPM updates, Newton steps, ...) come from one more,
+        # untimed pass: their per-wavefront atomics would slow the timed ones
+        counters.zero_()
+        one_pass(False, count=True)
+        torch.cuda.synchronize()
+        per_pass = [int(v) for v in counters.cpu().tolist()]
         res = dict(eng=eng, pk=pk, stage=stage, ext=ext_launch_ms, corr=corr_launch_ms,
-                   ms_step=start.elapsed_time(stop) / args.steps, wall=time.time() - wall0,
-                   counters=[int(v) for v in counters.cpu().tolist()],
-                   fallbacks=int(eng.fallbacks.item()) // max(args.steps, 1))
+                   ms_step=start.elapsed_time(stop) / args.steps, wall=wall,
+                   counters=[v * args.steps for v in per_pass], fallbacks=fallbacks)
         return res
 
     modes = ["plain", "learned", "learned_unscreened"] if args.start == "both" else [args.start]
@@ -238,33 +251,37 @@ def main():
                  if size == (step_, step_, step_)]
     corr_full_avg = float(np.mean(corr_full)) if corr_full else corr_avg
     dominant = "extract" if stage["extract"] >= stage["correlate"] else "correlate"
-    roofline = None
-    if dominant == "correlate":
-        ach = corr_bytes / (corr_full_avg / 1e3) / 1e9
-        roofline = {"bound": "hbm", "kernel": "ttm_correlate (tile of 256^3)", "achieved": ach,
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                    "traffic": None}
-    else:
-        f = extract_flops(n)
-        steps_, newton_, oriented = R["counters"]
-        voxels = sum(nv for _, nv in ext_launch_ms)
-        mlp_flops = 2 * (32 * 64 + 64 * 64 + 64 * 16) if main_mode == "learned" else 0
-        screen_flops = 16 * (f["step"] - 23) if main_mode == "learned" else 0
-        flops = (voxels * (f["score"] + mlp_flops + screen_flops)
-                 + oriented * f["setup_one" if main_mode == "learned" else "setup"]
-                 + steps_ * f["step"] + newton_ * f["newton"])
-        ach = flops / (stage["extract"] / 1e3) / 1e12
-        roofline = {"bound": "alu", "kernel": f"k_extract<{n}> ({main_mode} start) + fallback",
-                    "achieved": ach, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": ach / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
-                    "avg_launch_ms": ext_avg,
-                    "flops_per_launch": flops / len(ext_launch_ms),
-                    "sshopm_steps_per_oriented_voxel": steps_ / max(oriented, 1),
-                    "newton_steps_per_oriented_voxel": newton_ / max(oriented, 1)}
-    corr_roof = {"bound": "hbm", "kernel": "ttm_correlate, full tile",
+    f = extract_flops(n)
+    steps_, newton_, oriented, shifts, runs = R["counters"]
+    voxels = sum(nv for _, nv in ext_launch_ms)
+    learned = main_mode.startswith("learned")
+    flops = (voxels * f["score"] + shifts * f["shift"] + runs * f["run"] + steps_ * f["step"]
+             + newton_ * f["newton"])
+    if learned:
+        flops += oriented * (f["learned"] + (f["screen"] if main_mode == "learned" else 0))
+    mfma = oriented * f["mlp_mfma"] if learned else 0
+    ach = flops / (stage["extract"] / 1e3) / 1e12
+    roofline = {"bound": "alu",
+                "kernel": f"ttm_extract call ({'k_learned + ' if learned else ''}k_prepare, "
+                          f"k_runs, k_reduce), degree {n}, {main_mode} start",
+                "achieved": ach, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                "avg_launch_ms": ext_avg,
+                "flops_per_launch": flops / len(ext_launch_ms),
+                "mlp_mfma_flops_per_launch": mfma / len(ext_launch_ms),
+                "sshopm_updates_per_oriented_voxel": steps_ / max(oriented, 1),
+                "newton_steps_per_oriented_voxel": newton_ / max(oriented, 1),
+                "shift_bounds_per_oriented_voxel": shifts / max(oriented, 1),
+                "runs_per_oriented_voxel": runs / max(oriented, 1)}
+    corr_roof = {"bound": "hbm", "kernel": f"ttm_correlate, full {fft_n}^3 tile",
                  "achieved": corr_bytes / (corr_full_avg / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
-                 "unit": "GB/s", "avg_launch_ms": corr_full_avg, "bytes_per_launch": corr_bytes}
+                 "unit": "GB/s", "avg_launch_ms": corr_full_avg, "bytes_per_launch": corr_bytes,
+                 "traffic": None}
     corr_roof["frac"] = corr_roof["achieved"] / HBM_PEAK_GBS
+    # the stage with the larger event-timed total is reported as "roofline"
+    ext_roof = roofline
+    if dominant == "correlate":
+        roofline, corr_roof = corr_roof, ext_roof
     wall = R["wall"]
 
     cpu = None
@@ -301,7 +318,8 @@ def main():
         "valid_voxels_per_s": nvalid / (ms_step / 1e3),
         "peaks_found": n_peaks,
         "roofline": roofline,
-        "roofline_correlate": corr_roof,
+        "dominant_stage": dominant,
+        ("roofline_extract" if dominant == "correlate" else "roofline_correlate"): corr_roof,
         "cpu_baseline": cpu,
         "wall_s": wall,
     }

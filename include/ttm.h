@@ -182,8 +182,11 @@ typedef struct {
   int32_t max_iter;        /* SS-HOPM update cap per start, 1..2^24               */
   float tol;               /* stop when |delta lambda| <= tol (on C / ||C||_F)    */
   int32_t newton_steps;    /* Newton polishing steps per answer, 0..8 (default 2) */
-  uint64_t* work_counters; /* device uint64[3] or NULL: adds {SS-HOPM steps, Newton
-                              steps, oriented voxels} of this call (for FLOP counts) */
+  uint64_t* work_counters; /* device uint64[5] or NULL: adds {SS-HOPM updates,
+                              Newton steps, oriented voxels, shift bounds computed,
+                              SS-HOPM runs started} of this call (for FLOP counts;
+                              counting costs atomics per wavefront, so leave it
+                              NULL where the call is timed) */
 } ttm_extract_opts;
 
 /*

@@ -21,8 +21,9 @@
 //     k_reduce   one lane per voxel: every run's answer takes the Newton
 //                polish, the largest polished lambda wins (first on ties)
 //   learned start:
-//     k_learned  one lane per voxel: BF16 MLP on the matrix cores gives the
-//                start u0, then at most kNewtonFirst Riemannian Newton steps
+//     k_mlp_start  persistent wavefronts with the network in registers: the
+//                BF16 MLP on the matrix cores gives each voxel's start u0
+//     k_learned  one lane per voxel: at most kNewtonFirst Riemannian Newton steps
 //                (no shift needed); converged voxels are screened and
 //                written.  The others run SS-HOPM from u0 in k_runs (queue of
 //                saved iterates, shift from k_prepare), then k_learned_post
@@ -63,7 +64,7 @@ struct Ws {
   int* cont_it;
   float* alpha;
   unsigned char* conv;
-  float4* best;
+  float4* best;      // carried multistart best; learned start u0 before that
   float4* res;
 };
 
@@ -428,18 +429,23 @@ __global__ __launch_bounds__(256) void k_prepare(ExtractArgs a, Items it, int wr
   const Ws w = ws_layout(a.ws, a.plane);
   const unsigned n = it.n(a);
   if (add_total && a.fb_total && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.fb_total, (int)n);
+  if ((size_t)blockIdx.x * blockDim.x >= n) return;   // whole block past the list
   const unsigned j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const size_t v = it.voxel(j);
-  float c[ncomp3(N)];
-  const float cn = load_tensor<N>(a, v, c);
-  if (write_score && a.score) a.score[map_index(a, v)] = cn;
-  float alpha = 0.0f;
-  if (cn > 0.0f) {
-    scale<N>(c, 1.0f / cn);
-    alpha = fmaxf(0.0f, -unfolding_lambda_min<N, kShiftSteps>(c));
+  unsigned long long n_shift = 0;
+  if (j < n) {
+    const size_t v = it.voxel(j);
+    float c[ncomp3(N)];
+    const float cn = load_tensor<N>(a, v, c);
+    if (write_score && a.score) a.score[map_index(a, v)] = cn;
+    float alpha = 0.0f;
+    if (cn > 0.0f) {
+      scale<N>(c, 1.0f / cn);
+      alpha = fmaxf(0.0f, -unfolding_lambda_min<N, kShiftSteps>(c));
+      n_shift = 1;
+    }
+    w.alpha[j] = alpha;
   }
-  w.alpha[j] = alpha;
+  if (a.counters) count_add(a.counters + 3, n_shift);
 }
 
 // Persistent pooled SS-HOPM runs.  Run q of a chunk is item q / R, start
@@ -488,7 +494,7 @@ __global__ __launch_bounds__(64) void k_runs(ExtractArgs a, RunArgs r) {
   int iters = 0, s = 0;
   unsigned j = 0;
   bool first = false, busy = false;
-  unsigned long long n_steps = 0;
+  unsigned long long n_steps = 0, n_runs = 0;
   while (true) {
     unsigned long long waiting = __ballot(!busy);
     int n_wait = __popcll(waiting);
@@ -571,6 +577,7 @@ __global__ __launch_bounds__(64) void k_runs(ExtractArgs a, RunArgs r) {
               }
               first = true;
               busy = true;
+              ++n_runs;
             } else {
               w.res[(size_t)s * a.plane + j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
               if constexpr (CONT) w.conv[j] = 1;
@@ -607,7 +614,10 @@ __global__ __launch_bounds__(64) void k_runs(ExtractArgs a, RunArgs r) {
       }
     }
   }
-  if (a.counters) count_add(a.counters + 0, n_steps);
+  if (a.counters) {
+    count_add(a.counters + 0, n_steps);
+    count_add(a.counters + 4, n_runs);
+  }
 }
 
 // Per item: every run of one start block takes the Newton polish, and the
@@ -693,49 +703,77 @@ __device__ __forceinline__ unsigned long long learned_finish(
   return taken;
 }
 
+// Learned start directions: persistent wavefronts (one per workgroup) hold the
+// network in registers and run it on 64 voxels at a time; writes the score
+// and u0 = y / |y| (best[v] = (u0, 1 if the network gave no direction and
+// start 0 stands in)), or with start_only the direction maps.
+constexpr int kMlpGroups = 3072;
+
+template <int N>
+__global__ __launch_bounds__(64) void k_mlp_start(ExtractArgs a) {
+  constexpr int K = ncomp3(N);
+  constexpr Sym3<N> sy{};
+  __shared__ unsigned short hs[64 * kMlpHid];
+  __shared__ float ys[64 * 4];
+  const int lane = threadIdx.x;
+  const Ws w = ws_layout(a.ws, a.plane);
+  MlpRegs net;
+  load_mlp_regs(a.mlp, lane, net);
+  const float s0x = a.starts[0], s0y = a.starts[1], s0z = a.starts[2];
+  const size_t n_groups = (a.plane + 63) / 64;
+  for (size_t gi = blockIdx.x; gi < n_groups; gi += gridDim.x) {
+    const size_t v0 = gi * 64 + lane;
+    const bool active = v0 < a.plane;
+    const size_t v = active ? v0 : a.plane - 1;
+    float c[K];
+    const float cn = load_tensor<N>(a, v, c);
+    const size_t o = map_index(a, v);
+    if ((a.mode & 1) && active) a.score[o] = cn;
+    const float inv = cn > 0.0f ? 1.0f / cn : 0.0f;
+    unsigned short* xs = hs + 64 * kMlpIn;
+#pragma unroll
+    for (int k = 0; k < kMlpIn; ++k)
+      xs[lane * kMlpIn + k] = k < K ? bf16_bits(sqrtf(sy.mu[k]) * c[k] * inv) : (unsigned short)0;
+    __syncthreads();
+    float y0, y1, y2;
+    mlp_forward(hs, ys, net, lane, y0, y1, y2);
+    const float ny = sqrtf(y0 * y0 + y1 * y1 + y2 * y2);
+    const bool forced = !(ny > 0.0f);
+    float ux = forced ? s0x : y0, uy = forced ? s0y : y1, uz = forced ? s0z : y2;
+    const float r = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
+    ux *= r; uy *= r; uz *= r;
+    if (active) {
+      if (a.start_only) write_answer(a, o, 0.0f, ux, uy, uz);
+      else w.best[v] = make_float4(ux, uy, uz, forced ? 1.0f : 0.0f);
+    }
+    __syncthreads();   // ys / hs are reused by the next group
+  }
+}
+
+// Learned-start search, one lane per voxel: up to kNewtonFirst Newton steps
+// from u0; converged voxels are screened and written, the others queued for
+// SS-HOPM from u0.
 template <int N>
 __global__ __launch_bounds__(256) void k_learned(ExtractArgs a) {
   constexpr int K = ncomp3(N);
-  constexpr Sym3<N> sy{};
   __shared__ float st[64 * 3];
   __shared__ float mono[64 * K];
-  __shared__ unsigned short hs[4][64 * kMlpHid];
-  __shared__ float ys[4][64 * 4];
   for (int i = threadIdx.x; i < a.n_starts * 3; i += blockDim.x) st[i] = a.starts[i];
   __syncthreads();
   if (a.screen) build_monomials<N>(st, a.n_starts, mono);
+  __syncthreads();
   const Ws w = ws_layout(a.ws, a.plane);
   const size_t v0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = v0 < a.plane;
   const size_t v = active ? v0 : a.plane - 1;   // inactive lanes recompute the last voxel, write nothing
-  unsigned long long n_steps = 0, n_newton = 0, n_oriented = 0;
+  unsigned long long n_newton = 0, n_oriented = 0;
   float c[K];
   const float cn = load_tensor<N>(a, v, c);
-  const size_t o = map_index(a, v);
-  if ((a.mode & 1) && active) a.score[o] = cn;
-  const float inv = cn > 0.0f ? 1.0f / cn : 0.0f;
-  // features -> BF16 MLP on the matrix cores; per wavefront [64][64] bf16
-  // activations and [64][4] outputs
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  unsigned short* xs = &hs[wv][64 * kMlpIn];
-#pragma unroll
-  for (int k = 0; k < kMlpIn; ++k)
-    xs[lane * kMlpIn + k] = k < K ? bf16_bits(sqrtf(sy.mu[k]) * c[k] * inv) : (unsigned short)0;
-  __syncthreads();
-  float y0, y1, y2;
-  mlp_forward_wave(hs[wv], ys[wv], a.mlp, lane, y0, y1, y2);
-  const float ny = sqrtf(y0 * y0 + y1 * y1 + y2 * y2);
-  const bool forced = !(ny > 0.0f);
-  float ux = forced ? st[0] : y0, uy = forced ? st[1] : y1, uz = forced ? st[2] : y2;
-  {
-    const float r = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
-    ux *= r; uy *= r; uz *= r;
-  }
-  if (a.start_only) {
-    if (active) write_answer(a, o, 0.0f, ux, uy, uz);
-  } else if (cn > 0.0f) {
-    scale<N>(c, inv);
-    const float u0x = ux, u0y = uy, u0z = uz;
+  if (cn > 0.0f) {
+    scale<N>(c, 1.0f / cn);
+    const float4 s0 = w.best[v];
+    const bool forced = s0.w != 0.0f;
+    float ux = s0.x, uy = s0.y, uz = s0.z;
     float g0, g1, g2;
     contract<N>(c, ux, uy, uz, g0, g1, g2);
     float lam = g0 * ux + g1 * uy + g2 * uz;
@@ -751,16 +789,15 @@ __global__ __launch_bounds__(256) void k_learned(ExtractArgs a) {
         // SS-HOPM from the learned start, continued in the pooled kernel
         const unsigned slot = atomicAdd(&w.hdr[kHdrContinue], 1u);
         w.cont_list[slot] = (unsigned)v;
-        w.cont_state[slot] = make_float4(u0x, u0y, u0z, lam0);
+        w.cont_state[slot] = make_float4(s0.x, s0.y, s0.z, lam0);
         w.cont_it[slot] = forced ? (1 << 30) : 0;
       }
     }
   } else if (active) {
-    write_answer(a, o, 0.0f, 0.0f, 0.0f, 0.0f);
+    write_answer(a, map_index(a, v), 0.0f, 0.0f, 0.0f, 0.0f);
   }
   if (a.counters) {
-    if (!active) n_steps = n_newton = n_oriented = 0;
-    count_add(a.counters + 0, n_steps);
+    if (!active) n_newton = n_oriented = 0;
     count_add(a.counters + 1, n_newton);
     count_add(a.counters + 2, n_oriented);
   }
@@ -833,8 +870,11 @@ int launch_n(const ExtractArgs& a, hipStream_t s) {
       if ((a.mode & 4) == 0) {
         launch_multistart<N>(a, Items{nullptr, nullptr}, ctr + kHdrPoolDense / 2, 0, s);
       } else {
-        hipLaunchKernelGGL((k_learned<N>), dim3(nb), dim3(256), 0, s, a);
+        const size_t n_groups = (a.plane + 63) / 64;
+        const unsigned mg = (unsigned)(n_groups < (size_t)kMlpGroups ? n_groups : kMlpGroups);
+        hipLaunchKernelGGL((k_mlp_start<N>), dim3(mg), dim3(64), 0, s, a);
         if (!a.start_only) {
+          hipLaunchKernelGGL((k_learned<N>), dim3(nb), dim3(256), 0, s, a);
           const Items cont{w.cont_list, &w.hdr[kHdrContinue]};
           hipLaunchKernelGGL((k_prepare<N>), dim3(nb), dim3(256), 0, s, a, cont, 0, 0);
           RunArgs r{cont, 1, 0, ctr + kHdrPoolCont / 2};

@@ -179,7 +179,9 @@ __global__ __launch_bounds__(8 * Plan<N>::T) void k_c2r_x(const cf* __restrict__
   cf* xl = reinterpret_cast<cf*>(smem);
   float* orow = reinterpret_cast<float*>(smem);
   const int tid = threadIdx.x;
-  const int y0 = blockIdx.x * kRowsX, z = blockIdx.y, b = blockIdx.z;
+  // component fastest in the grid, so the workgroups that share a crop's
+  // weight-map rows run together and find them in the L2
+  const int b = blockIdx.x, y0 = blockIdx.y * kRowsX, z = blockIdx.z;
   if (z >= dst.sz || y0 >= dst.sy) return;  // uniform: nothing of this block is kept
   const cf* in = spec + b * spec_stride + (size_t)z * NH * N + y0;
   for (int e = tid; e < NH * kRowsX; e += NP * T) {
@@ -277,7 +279,7 @@ int inverse_n(const cf* G, const cf* Sp, size_t s_stride, int A, const double* c
   constexpr int RB = (128 / T > 0 ? 128 / T : 1);
   hipLaunchKernelGGL((k_c2c_rows<N, true>), dim3(NROWS / RB, A), dim3(RB * T), 0, s, work,
                      work_stride, zlim, tw);
-  hipLaunchKernelGGL(k_c2r_x<N>, dim3(N / kRowsX, N, A), dim3(8 * T), 0, s, work, work_stride,
+  hipLaunchKernelGGL(k_c2r_x<N>, dim3(A, N / kRowsX, N), dim3(8 * T), 0, s, work, work_stride,
                      dst, tw);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : hip_status(e, "fft inverse launch");

@@ -69,20 +69,43 @@ __device__ __forceinline__ bf16x4 load_frag(const unsigned char* wp, int off, in
   return r;
 }
 
-// Forward pass of one wavefront's 64 rows (rows = lanes).
-//   hs: this wave's [64][64] bf16 LDS scratch; its upper half (bytes 4096..8191)
-//       holds the input features x as [64][32] bf16 on entry.
-//   ys: this wave's [64][4] f32 LDS scratch.
-//   wp: packed parameters (global memory).
-// Returns y (3 floats) of the calling lane's row.  Every thread of the
-// workgroup must call it together (it contains workgroup barriers).
-__device__ __forceinline__ void mlp_forward_wave(unsigned short* hs, float* ys,
-                                                 const unsigned char* __restrict__ wp, int lane,
-                                                 float& y0, float& y1, float& y2) {
-  const unsigned short* xs = hs + 64 * kMlpIn;   // upper half
+// One lane's share of the packed network, held in registers for the life of
+// a wavefront: its B fragments of W1 (8), W2 (16), W3 (4) and the biases of
+// its output columns (16 nt + lane % 16).
+struct MlpRegs {
+  bf16x4 w1[8], w2[16], w3[4];
+  float b1[4], b2[4], b3;
+};
+
+__device__ __forceinline__ void load_mlp_regs(const unsigned char* __restrict__ wp, int lane,
+                                              MlpRegs& r) {
   const float* b1 = reinterpret_cast<const float*>(wp + kPkB1);
   const float* b2 = reinterpret_cast<const float*>(wp + kPkB2);
   const float* b3 = reinterpret_cast<const float*>(wp + kPkB3);
+  const int r16 = lane & 15;
+#pragma unroll
+  for (int f = 0; f < 8; ++f) r.w1[f] = load_frag(wp, kPkW1, f, lane);
+#pragma unroll
+  for (int f = 0; f < 16; ++f) r.w2[f] = load_frag(wp, kPkW2, f, lane);
+#pragma unroll
+  for (int f = 0; f < 4; ++f) r.w3[f] = load_frag(wp, kPkW3, f, lane);
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    r.b1[nt] = b1[16 * nt + r16];
+    r.b2[nt] = b2[16 * nt + r16];
+  }
+  r.b3 = r16 < 3 ? b3[r16] : 0.0f;
+}
+
+// Forward pass of one wavefront's 64 rows (rows = lanes); the workgroup is
+// this one wavefront (the barriers order its LDS traffic).
+//   hs: [64][64] bf16 LDS scratch; its upper half (bytes 4096..8191) holds the
+//       input features x as [64][32] bf16 on entry.
+//   ys: [64][4] f32 LDS scratch.
+// Returns y (3 floats) of the calling lane's row.
+__device__ __forceinline__ void mlp_forward(unsigned short* hs, float* ys, const MlpRegs& w,
+                                            int lane, float& y0, float& y1, float& y2) {
+  const unsigned short* xs = hs + 64 * kMlpIn;   // upper half
   const int r16 = lane & 15, q = lane >> 4;
   // ---- layer 1: h1 = relu(x W1 + b1); row block m of h1 overwrites x rows
   //      already consumed (x sits in rows 32..63 of the scratch)
@@ -96,7 +119,7 @@ __device__ __forceinline__ void mlp_forward_wave(unsigned short* hs, float* ys,
 #pragma unroll
       for (int j = 0; j < 4; ++j) a[j] = (short)xs[(16 * m + r16) * kMlpIn + 16 * s + 4 * q + j];
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma16(a, load_frag(wp, kPkW1, s * 4 + nt, lane), acc[nt]);
+      for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma16(a, w.w1[s * 4 + nt], acc[nt]);
     }
     __syncthreads();
 #pragma unroll
@@ -104,7 +127,7 @@ __device__ __forceinline__ void mlp_forward_wave(unsigned short* hs, float* ys,
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         hs[(16 * m + 4 * q + j) * kMlpHid + 16 * nt + r16] =
-            bf16_bits(fmaxf(acc[nt][j] + b1[16 * nt + r16], 0.0f));
+            bf16_bits(fmaxf(acc[nt][j] + w.b1[nt], 0.0f));
     __syncthreads();
   }
   // ---- layer 2: h2 = relu(h1 W2 + b2), in place row block by row block
@@ -118,7 +141,7 @@ __device__ __forceinline__ void mlp_forward_wave(unsigned short* hs, float* ys,
 #pragma unroll
       for (int j = 0; j < 4; ++j) a[j] = (short)hs[(16 * m + r16) * kMlpHid + 16 * s + 4 * q + j];
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma16(a, load_frag(wp, kPkW2, s * 4 + nt, lane), acc[nt]);
+      for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma16(a, w.w2[s * 4 + nt], acc[nt]);
     }
     __syncthreads();
 #pragma unroll
@@ -126,7 +149,7 @@ __device__ __forceinline__ void mlp_forward_wave(unsigned short* hs, float* ys,
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         hs[(16 * m + 4 * q + j) * kMlpHid + 16 * nt + r16] =
-            bf16_bits(fmaxf(acc[nt][j] + b2[16 * nt + r16], 0.0f));
+            bf16_bits(fmaxf(acc[nt][j] + w.b2[nt], 0.0f));
     __syncthreads();
   }
   // ---- layer 3: y = h2 W3 + b3 (16 padded outputs, 3 used)
@@ -137,11 +160,11 @@ __device__ __forceinline__ void mlp_forward_wave(unsigned short* hs, float* ys,
       bf16x4 a;
 #pragma unroll
       for (int j = 0; j < 4; ++j) a[j] = (short)hs[(16 * m + r16) * kMlpHid + 16 * s + 4 * q + j];
-      acc = mfma16(a, load_frag(wp, kPkW3, s, lane), acc);
+      acc = mfma16(a, w.w3[s], acc);
     }
     if (r16 < 3) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) ys[(16 * m + 4 * q + j) * 4 + r16] = acc[j] + b3[r16];
+      for (int j = 0; j < 4; ++j) ys[(16 * m + 4 * q + j) * 4 + r16] = acc[j] + w.b3;
     }
   }
   __syncthreads();

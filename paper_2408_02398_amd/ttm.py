@@ -182,8 +182,8 @@ def extract(ctx: Context, desc: Desc, Cf: torch.Tensor, *, score=None, lam=None,
     opts.tol = tol
     opts.newton_steps = newton
     if counters is not None:
-        if counters.dtype != torch.int64 or counters.numel() < 3 or not counters.is_cuda:
-            raise ValueError("counters must be a device int64 tensor of 3 elements")
+        if counters.dtype != torch.int64 or counters.numel() < 5 or not counters.is_cuda:
+            raise ValueError("counters must be a device int64 tensor of 5 elements")
         opts.work_counters = counters.data_ptr()
     code = L.TTM_BF16 if Cf.dtype == torch.bfloat16 else L.TTM_F32
     call("ttm_extract", ctx.h, C.byref(desc), _ptr(Cf), code, I32x3(*box), C.byref(opts),

@@ -1,6 +1,7 @@
 """Parity at the full workload sizes, in the launch configuration of the
-benchmark: 256^3 FFT tiles, tile correlations overlapped with extraction on a
-side stream, Find Peaks over the whole volume.  The FP64 oracle cannot run a
+benchmark: its FFT tile (512^3 for the 512 x 928 x 928 tomogram, one 256^3
+transform for 256^3), tile correlations overlapped with extraction on a side
+stream, Find Peaks over the whole volume.  The FP64 oracle cannot run a
 whole 512 x 928 x 928 pass, so it computes sampled voxels one by one from the
 raw tomogram (Eq. norm_f, Eq. tcc, Sec. 3.1 / 3.2): w, the score, lambda and
 the orientation at the first peaks, at tile seams and at random valid voxels.
@@ -85,6 +86,9 @@ def oracle_field(vol, pts, L, r, Tt):
     return orc.field_at(patches, orc.ball_mask(L, r), Tt, g2)
 
 
+FFT_TILE = {"c2_256cube_n6": 256, "c3_512x928x928_n6": 512}
+
+
 @pytest.mark.parametrize("name", ["c2_256cube_n6", "c3_512x928x928_n6"])
 @pytest.mark.parametrize("start", ["multistart", "learned"])
 def test_full_size_sampled_parity(T, ctx, name, start):
@@ -94,14 +98,14 @@ def test_full_size_sampled_parity(T, ctx, name, start):
     wl, Q, Tt = workload(name)
     d = T.make_desc(n, L, r)
     Tg, _ = T.build_tensor(ctx, d, cuda(wl.template), cuda(Q))
-    spec = T.template_spectra(ctx, d, Tg, 256)
+    spec = T.template_spectra(ctx, d, Tg, FFT_TILE[name])
     starts = synth.start_vectors()
     K = sym.n_components(n, 3)
     mlp, kappa, pl = None, 0.0, None
     if start == "learned":
         pl = oracle_trained_params(13, n)
         mlp, kappa = T.MLP(ctx, d, cuda(omlp.pad_params(pl, K))), 0.3
-    eng = T.Engine(ctx, d, spec, 256, wl.volume.shape, cuda(starts), mlp=mlp, kappa=kappa)
+    eng = T.Engine(ctx, d, spec, FFT_TILE[name], wl.volume.shape, cuda(starts), mlp=mlp, kappa=kappa)
     say(f"[fullsize {name} {start}] GPU pass over {len(eng.boxes)} tiles")
     res = eng.run(cuda(wl.volume), top_p=50)
     torch.cuda.synchronize()
