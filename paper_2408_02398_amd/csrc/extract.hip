@@ -60,13 +60,17 @@ struct Ws {
   unsigned* hdr;
   unsigned* fb_list;
   unsigned* cont_list;
-  float4* cont_state;
-  int* cont_it;
+  float4* cont_state;   // per box voxel: learned start u0 and its lambda
+  int* cont_it;         // per box voxel: 1 << 30 when the network gave no direction
   float* alpha;
   unsigned char* conv;
   float4* best;      // carried multistart best; learned start u0 before that
+  unsigned char* status;  // per box voxel: 0 answered, 1 continue with SS-HOPM, 2 fall back
+  unsigned* blocksum;     // per compaction block: count, then offset
   float4* res;
 };
+
+constexpr int kCompactBlock = 4096;   // voxels per compaction workgroup (256 threads x 16)
 
 __host__ __device__ inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -89,6 +93,10 @@ __host__ __device__ inline Ws ws_layout(void* base, size_t plane) {
   p += al256(plane);
   w.best = reinterpret_cast<float4*>(p);
   p += al256(plane * 16);
+  w.status = reinterpret_cast<unsigned char*>(p);
+  p += al256(plane);
+  w.blocksum = reinterpret_cast<unsigned*>(p);
+  p += al256(((plane + kCompactBlock - 1) / kCompactBlock) * 4);
   w.res = reinterpret_cast<float4*>(p);
   return w;
 }
@@ -356,6 +364,32 @@ __device__ __forceinline__ float load_tensor(const ExtractArgs& a, size_t v, flo
   return sqrtf(f2);
 }
 
+// The K components of box voxel v, as stored (no arithmetic, so a lane can
+// issue them for its next voxel and keep working on the current one).
+template <int N>
+__device__ __forceinline__ void load_raw(const ExtractArgs& a, size_t v, float (&c)[ncomp3(N)]) {
+  constexpr int K = ncomp3(N);
+  if (a.in_dtype == 1) {
+    const unsigned short* p = reinterpret_cast<const unsigned short*>(a.C);
+#pragma unroll
+    for (int k = 0; k < K; ++k) c[k] = bf16_to_f32(p[k * a.plane + v]);
+  } else {
+    const float* p = reinterpret_cast<const float*>(a.C);
+#pragma unroll
+    for (int k = 0; k < K; ++k) c[k] = p[k * a.plane + v];
+  }
+}
+
+// ||C||_F of loaded components (the same sum load_tensor forms).
+template <int N>
+__device__ __forceinline__ float frob(const float (&c)[ncomp3(N)]) {
+  constexpr Sym3<N> sy{};
+  float f2 = 0.0f;
+#pragma unroll
+  for (int k = 0; k < ncomp3(N); ++k) f2 = fmaf(sy.mu[k] * c[k], c[k], f2);
+  return sqrtf(f2);
+}
+
 template <int N>
 __device__ __forceinline__ void scale(float (&c)[ncomp3(N)], float inv) {
 #pragma unroll
@@ -545,8 +579,8 @@ __global__ __launch_bounds__(64) void k_runs(ExtractArgs a, RunArgs r) {
             cz[lane] = cn;
             ca[lane] = w.alpha[jj];
             if constexpr (CONT) {
-              cu[lane] = w.cont_state[jj];
-              ci[lane] = w.cont_it[jj] & ((1 << 30) - 1);
+              cu[lane] = w.cont_state[v];
+              ci[lane] = w.cont_it[v] & ((1 << 30) - 1);
             }
           }
           __syncthreads();
@@ -672,8 +706,8 @@ __global__ __launch_bounds__(256) void k_reduce(ExtractArgs a, Items it, int nsb
 // learned start
 // ---------------------------------------------------------------------------
 
-// Polish, screen and write a learned-start answer; queue the voxel for the
-// multistart search when the run did not converge, lambda / ||C||_F < kappa,
+// Polish, screen and write a learned-start answer; mark the voxel for the
+// multistart search (status 2) when the run did not converge, lambda / ||C||_F < kappa,
 // the network gave no direction, or some fixed start s already has
 // <C, s^n> above lambda (SS-HOPM never lowers lambda, so the multistart
 // answer is then higher).
@@ -696,10 +730,7 @@ __device__ __forceinline__ unsigned long long learned_finish(
   const bool fallback = forced || !conv || !(lam >= a.kappa) || beaten;
   canonical(ux, uy, uz);
   write_answer(a, map_index(a, v), lam * cn, ux, uy, uz);
-  if (fallback) {
-    const unsigned slot = atomicAdd(&w.hdr[kHdrFallbacks], 1u);
-    w.fb_list[slot] = (unsigned)v;
-  }
+  w.status[v] = fallback ? 2 : 0;
   return taken;
 }
 
@@ -707,7 +738,7 @@ __device__ __forceinline__ unsigned long long learned_finish(
 // network in registers and run it on 64 voxels at a time; writes the score
 // and u0 = y / |y| (best[v] = (u0, 1 if the network gave no direction and
 // start 0 stands in)), or with start_only the direction maps.
-constexpr int kMlpGroups = 3072;
+constexpr int kMlpGroups = 2048;
 
 template <int N>
 __global__ __launch_bounds__(64) void k_mlp_start(ExtractArgs a) {
@@ -721,12 +752,23 @@ __global__ __launch_bounds__(64) void k_mlp_start(ExtractArgs a) {
   load_mlp_regs(a.mlp, lane, net);
   const float s0x = a.starts[0], s0y = a.starts[1], s0z = a.starts[2];
   const size_t n_groups = (a.plane + 63) / 64;
+  float c[K];
+  if (blockIdx.x < n_groups) {
+    const size_t v0 = (size_t)blockIdx.x * 64 + lane;
+    load_raw<N>(a, v0 < a.plane ? v0 : a.plane - 1, c);
+  }
   for (size_t gi = blockIdx.x; gi < n_groups; gi += gridDim.x) {
     const size_t v0 = gi * 64 + lane;
     const bool active = v0 < a.plane;
     const size_t v = active ? v0 : a.plane - 1;
-    float c[K];
-    const float cn = load_tensor<N>(a, v, c);
+    // the next group's tensors are loaded while this group runs through the network
+    float cx[K];
+    const size_t gn = gi + gridDim.x;
+    if (gn < n_groups) {
+      const size_t vn = gn * 64 + lane;
+      load_raw<N>(a, vn < a.plane ? vn : a.plane - 1, cx);
+    }
+    const float cn = frob<N>(c);
     const size_t o = map_index(a, v);
     if ((a.mode & 1) && active) a.score[o] = cn;
     const float inv = cn > 0.0f ? 1.0f / cn : 0.0f;
@@ -747,12 +789,20 @@ __global__ __launch_bounds__(64) void k_mlp_start(ExtractArgs a) {
       else w.best[v] = make_float4(ux, uy, uz, forced ? 1.0f : 0.0f);
     }
     __syncthreads();   // ys / hs are reused by the next group
+#pragma unroll
+    for (int k = 0; k < K; ++k) c[k] = cx[k];
   }
 }
 
 // Learned-start search, one lane per voxel: up to kNewtonFirst Newton steps
-// from u0; converged voxels are screened and written, the others queued for
-// SS-HOPM from u0.
+// from u0; converged voxels are screened and written (status 0 or 2), the
+// others marked for SS-HOPM from u0 (status 1, with u0 and its lambda kept
+// per voxel).  The workgroups are persistent and each lane loads its next
+// voxel's tensor before working on the current one; nothing in the loop
+// waits on a memory result, so the loads' latency hides behind the Newton
+// steps.
+constexpr int kLearnedGroups = 1024;
+
 template <int N>
 __global__ __launch_bounds__(256) void k_learned(ExtractArgs a) {
   constexpr int K = ncomp3(N);
@@ -763,41 +813,54 @@ __global__ __launch_bounds__(256) void k_learned(ExtractArgs a) {
   if (a.screen) build_monomials<N>(st, a.n_starts, mono);
   __syncthreads();
   const Ws w = ws_layout(a.ws, a.plane);
-  const size_t v0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool active = v0 < a.plane;
-  const size_t v = active ? v0 : a.plane - 1;   // inactive lanes recompute the last voxel, write nothing
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
   unsigned long long n_newton = 0, n_oriented = 0;
+  size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   float c[K];
-  const float cn = load_tensor<N>(a, v, c);
-  if (cn > 0.0f) {
-    scale<N>(c, 1.0f / cn);
-    const float4 s0 = w.best[v];
-    const bool forced = s0.w != 0.0f;
-    float ux = s0.x, uy = s0.y, uz = s0.z;
-    float g0, g1, g2;
-    contract<N>(c, ux, uy, uz, g0, g1, g2);
-    float lam = g0 * ux + g1 * uy + g2 * uz;
-    const float lam0 = lam;
-    bool ok;
-    n_newton = newton_ascent<N>(c, ux, uy, uz, g0, g1, g2, lam, kNewtonFirst, a.tol, ok);
-    n_oriented = 1;
-    if (active) {
+  float4 s0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (v < a.plane) {
+    load_raw<N>(a, v, c);
+    s0 = w.best[v];
+  }
+  while (v < a.plane) {
+    const size_t vn = v + stride;
+    float cx[K];
+    float4 s0x = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (vn < a.plane) {
+      load_raw<N>(a, vn, cx);
+      s0x = w.best[vn];
+    }
+    const float cn = frob<N>(c);
+    if (cn > 0.0f) {
+      scale<N>(c, 1.0f / cn);
+      const bool forced = s0.w != 0.0f;
+      float ux = s0.x, uy = s0.y, uz = s0.z;
+      float g0, g1, g2;
+      contract<N>(c, ux, uy, uz, g0, g1, g2);
+      float lam = g0 * ux + g1 * uy + g2 * uz;
+      const float lam0 = lam;
+      bool ok;
+      n_newton += newton_ascent<N>(c, ux, uy, uz, g0, g1, g2, lam, kNewtonFirst, a.tol, ok);
+      n_oriented += 1;
       if (ok) {
         n_newton += learned_finish<N>(a, w, c, cn, v, mono, ux, uy, uz, g0, g1, g2, lam, true,
                                       forced, 0);
       } else {
-        // SS-HOPM from the learned start, continued in the pooled kernel
-        const unsigned slot = atomicAdd(&w.hdr[kHdrContinue], 1u);
-        w.cont_list[slot] = (unsigned)v;
-        w.cont_state[slot] = make_float4(s0.x, s0.y, s0.z, lam0);
-        w.cont_it[slot] = forced ? (1 << 30) : 0;
+        // SS-HOPM from the learned start, run by the pooled kernel
+        w.status[v] = 1;
+        w.cont_state[v] = make_float4(s0.x, s0.y, s0.z, lam0);
+        w.cont_it[v] = forced ? (1 << 30) : 0;
       }
+    } else {
+      write_answer(a, map_index(a, v), 0.0f, 0.0f, 0.0f, 0.0f);
+      w.status[v] = 0;
     }
-  } else if (active) {
-    write_answer(a, map_index(a, v), 0.0f, 0.0f, 0.0f, 0.0f);
+    v = vn;
+    s0 = s0x;
+#pragma unroll
+    for (int k = 0; k < K; ++k) c[k] = cx[k];
   }
   if (a.counters) {
-    if (!active) n_newton = n_oriented = 0;
     count_add(a.counters + 1, n_newton);
     count_add(a.counters + 2, n_oriented);
   }
@@ -827,18 +890,105 @@ __global__ __launch_bounds__(256) void k_learned_post(ExtractArgs a) {
     float g0, g1, g2;
     contract<N>(c, ux, uy, uz, g0, g1, g2);
     const float lam = g0 * ux + g1 * uy + g2 * uz;
-    const bool forced = (w.cont_it[j] >> 30) & 1;
+    const bool forced = (w.cont_it[v] >> 30) & 1;
     n_newton = learned_finish<N>(a, w, c, cn, v, mono, ux, uy, uz, g0, g1, g2, lam,
                                  w.conv[j] != 0, forced, a.newton);
   }
   if (a.counters) count_add(a.counters + 1, n_newton);
 }
 
+// ---------------------------------------------------------------------------
+// list compaction: the box voxels whose status equals `value`, in voxel order
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ unsigned block_count(const unsigned char* status, size_t plane,
+                                                size_t base, unsigned char value,
+                                                unsigned& mine_mask) {
+  // thread t of the workgroup owns voxels base + t * 16 ... + 15
+  mine_mask = 0;
+  const size_t v0 = base + (size_t)threadIdx.x * 16;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const size_t v = v0 + i;
+    if (v < plane && status[v] == value) mine_mask |= 1u << i;
+  }
+  return __popc(mine_mask);
+}
+
+__global__ __launch_bounds__(256) void k_flag_count(const unsigned char* status, size_t plane,
+                                                    unsigned char value, unsigned* blocksum) {
+  __shared__ unsigned part[4];
+  unsigned mask;
+  unsigned cnt = block_count(status, plane, (size_t)blockIdx.x * kCompactBlock, value, mask);
+  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) blocksum[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+
+// Exclusive scan of the block counts (one workgroup); total -> *count.
+__global__ __launch_bounds__(1024) void k_flag_scan(unsigned* blocksum, int nblk, unsigned* count) {
+  __shared__ unsigned sums[1024];
+  unsigned carry = 0;
+  for (int base = 0; base < nblk; base += 1024) {
+    const int i = base + (int)threadIdx.x;
+    const unsigned x = i < nblk ? blocksum[i] : 0u;
+    sums[threadIdx.x] = x;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const unsigned y = threadIdx.x >= (unsigned)off ? sums[threadIdx.x - off] : 0u;
+      __syncthreads();
+      sums[threadIdx.x] += y;
+      __syncthreads();
+    }
+    if (i < nblk) blocksum[i] = carry + sums[threadIdx.x] - x;
+    const unsigned tot = sums[1023];
+    __syncthreads();
+    carry += tot;
+  }
+  if (threadIdx.x == 0) *count = carry;
+}
+
+__global__ __launch_bounds__(256) void k_flag_scatter(const unsigned char* status, size_t plane,
+                                                      unsigned char value,
+                                                      const unsigned* blocksum, unsigned* list) {
+  __shared__ unsigned part[4];
+  unsigned mask;
+  const size_t base = (size_t)blockIdx.x * kCompactBlock;
+  const unsigned cnt = block_count(status, plane, base, value, mask);
+  // inclusive scan over the workgroup's threads (in thread order = voxel order)
+  unsigned incl = cnt;
+  const int lane = threadIdx.x & 63;
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned y = __shfl_up(incl, off);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) part[threadIdx.x >> 6] = incl;
+  __syncthreads();
+  unsigned wave_off = 0;
+  for (int wv = 0; wv < (int)(threadIdx.x >> 6); ++wv) wave_off += part[wv];
+  unsigned pos = blocksum[blockIdx.x] + wave_off + incl - cnt;
+  const size_t v0 = base + (size_t)threadIdx.x * 16;
+#pragma unroll
+  for (int i = 0; i < 16; ++i)
+    if (mask & (1u << i)) list[pos++] = (unsigned)(v0 + i);
+}
+
+void compact(const Ws& w, size_t plane, unsigned char value, unsigned* list, unsigned* count,
+             hipStream_t s) {
+  const int nblk = (int)((plane + kCompactBlock - 1) / kCompactBlock);
+  hipLaunchKernelGGL(k_flag_count, dim3(nblk), dim3(256), 0, s, w.status, plane, value, w.blocksum);
+  hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, s, w.blocksum, nblk, count);
+  hipLaunchKernelGGL(k_flag_scatter, dim3(nblk), dim3(256), 0, s, w.status, plane, value,
+                     w.blocksum, list);
+}
+
 }  // namespace
 
 size_t extract_workspace(size_t plane) {
   return 256 + al256(plane * 4) * 2 + al256(plane * 16) + al256(plane * 4) * 2 + al256(plane) +
-         al256(plane * 16) + (size_t)kStartBlock * plane * 16;
+         al256(plane * 16) + al256(plane) + al256(((plane + kCompactBlock - 1) / kCompactBlock) * 4) +
+         (size_t)kStartBlock * plane * 16;
 }
 
 template <int N>
@@ -874,12 +1024,15 @@ int launch_n(const ExtractArgs& a, hipStream_t s) {
         const unsigned mg = (unsigned)(n_groups < (size_t)kMlpGroups ? n_groups : kMlpGroups);
         hipLaunchKernelGGL((k_mlp_start<N>), dim3(mg), dim3(64), 0, s, a);
         if (!a.start_only) {
-          hipLaunchKernelGGL((k_learned<N>), dim3(nb), dim3(256), 0, s, a);
+          const unsigned lg = nb < (unsigned)kLearnedGroups ? nb : (unsigned)kLearnedGroups;
+          hipLaunchKernelGGL((k_learned<N>), dim3(lg), dim3(256), 0, s, a);
+          compact(w, a.plane, 1, w.cont_list, &w.hdr[kHdrContinue], s);
           const Items cont{w.cont_list, &w.hdr[kHdrContinue]};
           hipLaunchKernelGGL((k_prepare<N>), dim3(nb), dim3(256), 0, s, a, cont, 0, 0);
           RunArgs r{cont, 1, 0, ctr + kHdrPoolCont / 2};
           hipLaunchKernelGGL((k_runs<N, true>), dim3(kPoolGroups), dim3(64), 0, s, a, r);
           hipLaunchKernelGGL(k_learned_post<N>, dim3(nb), dim3(256), 0, s, a);
+          compact(w, a.plane, 2, w.fb_list, &w.hdr[kHdrFallbacks], s);
           launch_multistart<N>(a, Items{w.fb_list, &w.hdr[kHdrFallbacks]}, ctr + kHdrPoolFb / 2,
                                1, s);
         }
