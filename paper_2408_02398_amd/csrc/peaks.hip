@@ -13,9 +13,11 @@
 //      the visiting order,
 //   3. LSD radix sort of the keys (8-bit digits, stable ranks from wavefront
 //      ballots),
-//   4. one workgroup walks the sorted keys in chunks: every lane tests its
-//      candidate against the kept peaks through a spatial hash of cell size
-//      D, then the survivors of the chunk are settled in order.
+//   4. one workgroup walks the sorted keys in chunks of 1024: every lane
+//      tests its candidate against the kept peaks through a spatial hash of
+//      cell size D; the survivors, compacted in rank order, are settled 64 at
+//      a time by one wavefront (pairwise conflict bitmasks, then a 64-step
+//      in-order acceptance on those masks).
 // If fewer than P peaks are found while lower-ranked voxels remain, the host
 // doubles `want` and repeats.
 #include <cstring>
@@ -186,13 +188,23 @@ struct GreedyArgs {
   int* n_found;           // device
 };
 
+// Orders one wavefront's LDS writes before its later reads by other lanes
+// (a wavefront's LDS instructions execute in order; this keeps the compiler
+// from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 __global__ __launch_bounds__(kGreedyThreads) void k_greedy(GreedyArgs g) {
   __shared__ short head[kMaxCells];
   __shared__ short next[kMaxPeaks];
   __shared__ short pz[kMaxPeaks], py[kMaxPeaks], px[kMaxPeaks];
-  __shared__ int surv[kGreedyThreads];
-  __shared__ int nsurv, nkept, stop;
-  const int tid = threadIdx.x;
+  __shared__ short sz[kGreedyThreads], sy[kGreedyThreads], sx[kGreedyThreads];
+  __shared__ int srank[kGreedyThreads];   // rank within the chunk of each survivor
+  __shared__ int wsum[kGreedyThreads / 64];
+  __shared__ int nkept, stop;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int ncell = g.gz * g.gy * g.gx;
   for (int i = tid; i < ncell; i += kGreedyThreads) head[i] = (short)-1;
   if (tid == 0) {
@@ -202,8 +214,6 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy(GreedyArgs g) {
   __syncthreads();
   const size_t yx = (size_t)g.ny * g.nx;
   for (int base = 0; base < g.m; base += kGreedyThreads) {
-    if (tid == 0) nsurv = 0;
-    __syncthreads();
     const int idx = base + tid;
     int cz = 0, cy = 0, cxx = 0;
     bool alive = false;
@@ -236,47 +246,85 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy(GreedyArgs g) {
         }
       }
     }
-    if (alive) surv[atomicAdd(&nsurv, 1)] = tid;
+    // survivors in rank order: wavefront ballots, then the waves' offsets
+    const unsigned long long bal = __ballot(alive);
+    if (lane == 0) wsum[wv] = __popcll(bal);
     __syncthreads();
-    if (tid == 0) {
-      // survivors were appended in arbitrary order: settle them by rank
-      const int ns = nsurv;
-      for (int i = 1; i < ns; ++i) {  // insertion sort on tid (= rank within chunk)
-        const int v = surv[i];
-        int j = i - 1;
-        while (j >= 0 && surv[j] > v) {
-          surv[j + 1] = surv[j];
-          --j;
-        }
-        surv[j + 1] = v;
-      }
+    int off = 0;
+    for (int w = 0; w < wv; ++w) off += wsum[w];
+    int ns = 0;
+    for (int w = 0; w < kGreedyThreads / 64; ++w) ns += wsum[w];
+    if (alive) {
+      const int pos = off + __popcll(bal & ((1ull << lane) - 1ull));
+      sz[pos] = (short)cz;
+      sy[pos] = (short)cy;
+      sx[pos] = (short)cxx;
+      srank[pos] = tid;
+    }
+    __syncthreads();
+    // settle the survivors in order, 64 at a time on wavefront 0: a survivor
+    // is kept when no peak kept earlier in this chunk and no kept survivor
+    // ahead of it in its group lies within D
+    if (wv == 0) {
       const int first_new = nkept;
-      for (int i = 0; i < ns && nkept < g.top_p; ++i) {
-        const unsigned long long key = g.keys[base + surv[i]];
-        const size_t lin = (size_t)(key & 0xffffffffull);
-        const int z = (int)(lin / yx), y = (int)((lin / g.nx) % g.ny), x = (int)(lin % g.nx);
-        bool ok = true;
-        for (int p = first_new; p < nkept; ++p) {
-          const float ddz = (float)(z - pz[p]), ddy = (float)(y - py[p]), ddx = (float)(x - px[p]);
-          if (ddz * ddz + ddy * ddy + ddx * ddx < g.d2) {
-            ok = false;
-            break;
+      for (int g0 = 0; g0 < ns; g0 += 64) {
+        if (nkept >= g.top_p) break;
+        const int i = g0 + lane;
+        bool cand = i < ns;
+        int z = 0, y = 0, x = 0;
+        if (cand) {
+          z = sz[i];
+          y = sy[i];
+          x = sx[i];
+          for (int p = first_new; p < nkept && cand; ++p) {
+            const float ddz = (float)(z - pz[p]), ddy = (float)(y - py[p]), ddx = (float)(x - px[p]);
+            if (ddz * ddz + ddy * ddy + ddx * ddx < g.d2) cand = false;
           }
         }
-        if (!ok) continue;
-        const int k = nkept++;
-        pz[k] = (short)z;
-        py[k] = (short)y;
-        px[k] = (short)x;
-        const int cell = ((int)(z / g.cell) * g.gy + (int)(y / g.cell)) * g.gx + (int)(x / g.cell);
-        next[k] = head[cell];
-        head[cell] = (short)k;
-        g.peaks[3 * k + 0] = z;
-        g.peaks[3 * k + 1] = y;
-        g.peaks[3 * k + 2] = x;
-        g.vals[k] = __uint_as_float(~(unsigned)(key >> 32));
+        // conflicts with the group's survivors ahead of this one
+        unsigned long long conf = 0;
+        for (int j = 0; j < lane && g0 + j < ns; ++j) {
+          const float ddz = (float)(z - sz[g0 + j]), ddy = (float)(y - sy[g0 + j]),
+                      ddx = (float)(x - sx[g0 + j]);
+          if (ddz * ddz + ddy * ddy + ddx * ddx < g.d2) conf |= 1ull << j;
+        }
+        const unsigned long long cands = __ballot(cand);
+        unsigned long long kept = 0;
+        int room = g.top_p - nkept;
+        for (int l = 0; l < 64 && room > 0; ++l) {
+          const unsigned long long cl = __shfl(conf, l);
+          if (((cands >> l) & 1ull) && !(cl & kept)) {
+            kept |= 1ull << l;
+            --room;
+          }
+        }
+        if ((kept >> lane) & 1ull) {
+          const int k = nkept + __popcll(kept & ((1ull << lane) - 1ull));
+          pz[k] = (short)z;
+          py[k] = (short)y;
+          px[k] = (short)x;
+          const unsigned long long key = g.keys[base + srank[i]];
+          g.peaks[3 * k + 0] = z;
+          g.peaks[3 * k + 1] = y;
+          g.peaks[3 * k + 2] = x;
+          g.vals[k] = __uint_as_float(~(unsigned)(key >> 32));
+        }
+        wave_lds_sync();
+        if (lane == 0) {
+          // hash insertion in rank order
+          const int nk = __popcll(kept);
+          for (int t = 0; t < nk; ++t) {
+            const int k = nkept + t;
+            const int cell =
+                ((int)(pz[k] / g.cell) * g.gy + (int)(py[k] / g.cell)) * g.gx + (int)(px[k] / g.cell);
+            next[k] = head[cell];
+            head[cell] = (short)k;
+          }
+          nkept += nk;
+          if (nkept >= g.top_p) stop = 1;
+        }
+        wave_lds_sync();
       }
-      if (nkept >= g.top_p) stop = 1;
     }
     __syncthreads();
     if (stop) break;
