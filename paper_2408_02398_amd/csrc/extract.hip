@@ -744,8 +744,7 @@ template <int N>
 __global__ __launch_bounds__(64) void k_mlp_start(ExtractArgs a) {
   constexpr int K = ncomp3(N);
   constexpr Sym3<N> sy{};
-  __shared__ unsigned short hs[64 * kMlpHid];
-  __shared__ float ys[64 * 4];
+  __shared__ unsigned short xs[64 * kMlpIn];
   const int lane = threadIdx.x;
   const Ws w = ws_layout(a.ws, a.plane);
   MlpRegs net;
@@ -772,13 +771,11 @@ __global__ __launch_bounds__(64) void k_mlp_start(ExtractArgs a) {
     const size_t o = map_index(a, v);
     if ((a.mode & 1) && active) a.score[o] = cn;
     const float inv = cn > 0.0f ? 1.0f / cn : 0.0f;
-    unsigned short* xs = hs + 64 * kMlpIn;
 #pragma unroll
     for (int k = 0; k < kMlpIn; ++k)
       xs[lane * kMlpIn + k] = k < K ? bf16_bits(sqrtf(sy.mu[k]) * c[k] * inv) : (unsigned short)0;
-    __syncthreads();
     float y0, y1, y2;
-    mlp_forward(hs, ys, net, lane, y0, y1, y2);
+    mlp_forward(xs, net, lane, y0, y1, y2);
     const float ny = sqrtf(y0 * y0 + y1 * y1 + y2 * y2);
     const bool forced = !(ny > 0.0f);
     float ux = forced ? s0x : y0, uy = forced ? s0y : y1, uz = forced ? s0z : y2;
@@ -788,7 +785,7 @@ __global__ __launch_bounds__(64) void k_mlp_start(ExtractArgs a) {
       if (a.start_only) write_answer(a, o, 0.0f, ux, uy, uz);
       else w.best[v] = make_float4(ux, uy, uz, forced ? 1.0f : 0.0f);
     }
-    __syncthreads();   // ys / hs are reused by the next group
+    __syncthreads();   // xs is rewritten by the next group
 #pragma unroll
     for (int k = 0; k < K; ++k) c[k] = cx[k];
   }

@@ -70,11 +70,15 @@ __device__ __forceinline__ bf16x4 load_frag(const unsigned char* wp, int off, in
 }
 
 // One lane's share of the packed network, held in registers for the life of
-// a wavefront: its B fragments of W1 (8), W2 (16), W3 (4) and the biases of
-// its output columns (16 nt + lane % 16).
+// a wavefront.  The network runs transposed, H^T = W^T X^T, so that the
+// weights are the A operands and each layer's D fragments are exactly the
+// next layer's B fragments (no exchange between layers).  The packed B
+// fragment (s, nt) of W, W[16 s + 4 (L/16) + j][16 nt + L % 16], is the A
+// fragment of W^T for row tile nt and k tile s, so the packed layout serves
+// unchanged.  Biases are held for the D rows of this lane: unit 16 m + 4 (L/16) + j.
 struct MlpRegs {
   bf16x4 w1[8], w2[16], w3[4];
-  float b1[4], b2[4], b3;
+  float b1[4][4], b2[4][4], b3[4];
 };
 
 __device__ __forceinline__ void load_mlp_regs(const unsigned char* __restrict__ wp, int lane,
@@ -82,7 +86,7 @@ __device__ __forceinline__ void load_mlp_regs(const unsigned char* __restrict__ 
   const float* b1 = reinterpret_cast<const float*>(wp + kPkB1);
   const float* b2 = reinterpret_cast<const float*>(wp + kPkB2);
   const float* b3 = reinterpret_cast<const float*>(wp + kPkB3);
-  const int r16 = lane & 15;
+  const int q = lane >> 4;
 #pragma unroll
   for (int f = 0; f < 8; ++f) r.w1[f] = load_frag(wp, kPkW1, f, lane);
 #pragma unroll
@@ -90,87 +94,89 @@ __device__ __forceinline__ void load_mlp_regs(const unsigned char* __restrict__ 
 #pragma unroll
   for (int f = 0; f < 4; ++f) r.w3[f] = load_frag(wp, kPkW3, f, lane);
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt) {
-    r.b1[nt] = b1[16 * nt + r16];
-    r.b2[nt] = b2[16 * nt + r16];
-  }
-  r.b3 = r16 < 3 ? b3[r16] : 0.0f;
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      r.b1[m][j] = b1[16 * m + 4 * q + j];
+      r.b2[m][j] = b2[16 * m + 4 * q + j];
+    }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) r.b3[j] = b3[4 * q + j];
 }
 
-// Forward pass of one wavefront's 64 rows (rows = lanes); the workgroup is
-// this one wavefront (the barriers order its LDS traffic).
-//   hs: [64][64] bf16 LDS scratch; its upper half (bytes 4096..8191) holds the
-//       input features x as [64][32] bf16 on entry.
-//   ys: [64][4] f32 LDS scratch.
-// Returns y (3 floats) of the calling lane's row.
-__device__ __forceinline__ void mlp_forward(unsigned short* hs, float* ys, const MlpRegs& w,
-                                            int lane, float& y0, float& y1, float& y2) {
-  const unsigned short* xs = hs + 64 * kMlpIn;   // upper half
+__device__ __forceinline__ bf16x4 relu_bf16(const f32x4& acc, const float (&b)[4]) {
+  bf16x4 h;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) h[j] = (short)bf16_bits(fmaxf(acc[j] + b[j], 0.0f));
+  return h;
+}
+
+// Forward pass of one wavefront's 64 voxels (voxel = lane).
+//   xs: this wavefront's [64][32] bf16 features in LDS, written by the lanes
+//       before the call (the call starts with a barrier of the one-wavefront
+//       workgroup).
+// Returns y (3 floats) of the calling lane's voxel.
+__device__ __forceinline__ void mlp_forward(const unsigned short* xs, const MlpRegs& w, int lane,
+                                            float& y0, float& y1, float& y2) {
   const int r16 = lane & 15, q = lane >> 4;
-  // ---- layer 1: h1 = relu(x W1 + b1); row block m of h1 overwrites x rows
-  //      already consumed (x sits in rows 32..63 of the scratch)
-  for (int m = 0; m < 4; ++m) {
-    f32x4 acc[4];
+  __syncthreads();
+  // B fragments of X^T: lane L holds x[voxel 16 nt + L % 16][feature 16 s + 4 (L/16) + j]
+  bf16x4 xb[2][4];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int s = 0; s < kMlpIn / 16; ++s) {
-      bf16x4 a;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) a[j] = (short)xs[(16 * m + r16) * kMlpIn + 16 * s + 4 * q + j];
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma16(a, w.w1[s * 4 + nt], acc[nt]);
-    }
-    __syncthreads();
+  for (int s = 0; s < 2; ++s)
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        hs[(16 * m + 4 * q + j) * kMlpHid + 16 * nt + r16] =
-            bf16_bits(fmaxf(acc[nt][j] + w.b1[nt], 0.0f));
-    __syncthreads();
-  }
-  // ---- layer 2: h2 = relu(h1 W2 + b2), in place row block by row block
-  for (int m = 0; m < 4; ++m) {
-    f32x4 acc[4];
+      for (int j = 0; j < 4; ++j) xb[s][nt][j] = (short)xs[(16 * nt + r16) * kMlpIn + 16 * s + 4 * q + j];
+  // layer 1: H1^T (64 x 64) = W1^T (64 x 32) X^T (32 x 64)
+  bf16x4 h1[4][4];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int s = 0; s < kMlpHid / 16; ++s) {
-      bf16x4 a;
+    for (int nt = 0; nt < 4; ++nt) {
+      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int j = 0; j < 4; ++j) a[j] = (short)hs[(16 * m + r16) * kMlpHid + 16 * s + 4 * q + j];
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma16(a, w.w2[s * 4 + nt], acc[nt]);
+      for (int s = 0; s < 2; ++s) acc = mfma16(w.w1[s * 4 + m], xb[s][nt], acc);
+      h1[m][nt] = relu_bf16(acc, w.b1[m]);
     }
-    __syncthreads();
+  // layer 2: H2^T = W2^T H1^T
+  bf16x4 h2[4][4];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+  for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        hs[(16 * m + 4 * q + j) * kMlpHid + 16 * nt + r16] =
-            bf16_bits(fmaxf(acc[nt][j] + w.b2[nt], 0.0f));
-    __syncthreads();
-  }
-  // ---- layer 3: y = h2 W3 + b3 (16 padded outputs, 3 used)
-  for (int m = 0; m < 4; ++m) {
+    for (int nt = 0; nt < 4; ++nt) {
+      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc = mfma16(w.w2[s * 4 + m], h1[s][nt], acc);
+      h2[m][nt] = relu_bf16(acc, w.b2[m]);
+    }
+  // layer 3: Y^T (16 x 64) = W3^T H2^T; lanes 0..15 hold rows 0..3 (outputs)
+  // of voxel columns 16 nt + lane
+  float yv[3][4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
     f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int s = 0; s < kMlpHid / 16; ++s) {
-      bf16x4 a;
+    for (int s = 0; s < 4; ++s) acc = mfma16(w.w3[s], h2[s][nt], acc);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) a[j] = (short)hs[(16 * m + r16) * kMlpHid + 16 * s + 4 * q + j];
-      acc = mfma16(a, w.w3[s], acc);
-    }
-    if (r16 < 3) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) ys[(16 * m + 4 * q + j) * 4 + r16] = acc[j] + w.b3;
-    }
+    for (int i = 0; i < 3; ++i) yv[i][nt] = acc[i] + w.b3[i];
   }
-  __syncthreads();
-  y0 = ys[lane * 4 + 0];
-  y1 = ys[lane * 4 + 1];
-  y2 = ys[lane * 4 + 2];
+  // each voxel lane fetches its outputs from lane (voxel % 16) of tile voxel / 16
+  const int src = lane & 15, tile = lane >> 4;
+  float y[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    float pick = 0.0f;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const float t = __shfl(yv[i][nt], src);
+      pick = (tile == nt) ? t : pick;
+    }
+    y[i] = pick;
+  }
+  y0 = y[0];
+  y1 = y[1];
+  y2 = y[2];
 }
 
 }  // namespace ttm
