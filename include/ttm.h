@@ -74,7 +74,8 @@ typedef enum {
   TTM_OP_CORRELATE = 3,
   TTM_OP_PEAKS = 4,
   TTM_OP_EXTRACT = 5,     /* nz x ny x nx = the extraction box            */
-  TTM_OP_MLP_TRAIN = 6    /* nz = batch size, ny = nx = 1                 */
+  TTM_OP_MLP_TRAIN = 6,   /* nz = batch size, ny = nx = 1                 */
+  TTM_OP_PREFILTER = 7    /* nz x ny x nx = the volume (fft_n unused)     */
 } ttm_op;
 
 typedef struct ttm_ctx ttm_ctx;
@@ -146,6 +147,28 @@ int ttm_template_spectra(ttm_ctx* ctx, const ttm_desc* desc, const float* T, int
 int ttm_normalize(ttm_ctx* ctx, const ttm_desc* desc, const float* vol, int nz, int ny,
                   int nx, const void* mask_spec, int fft_n, float* g_out, float* w_out,
                   double* stats_out, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * The two halves of ttm_normalize, so that the local normalisation of one
+ * tile can run just before that tile's correlation (Sec. 2, Eq. norm_f).
+ * ttm_prefilter: g_out = h * vol and stats_out = {mean(g), mean(g^2)} as in
+ *   ttm_normalize; if w_out is not NULL it is cleared to 0 (the value outside
+ *   the valid region).  ws: ttm_workspace_size(desc, TTM_OP_PREFILTER, 0, nz,
+ *   ny, nx) bytes.
+ * ttm_normalize_box: w_out on the box (host int32[3] lo and size, z y x,
+ *   inside the valid region) from g and stats of ttm_prefilter, computed on
+ *   the same fft_n^3 sub-tiles as ttm_normalize, so a partition of the valid
+ *   region into boxes aligned to the step fft_n - L + 1 from the valid corner
+ *   reproduces ttm_normalize's w bit for bit.  ws: ttm_workspace_size(desc,
+ *   TTM_OP_NORMALIZE, fft_n, nz, ny, nx) bytes.
+ */
+int ttm_prefilter(ttm_ctx* ctx, const ttm_desc* desc, const float* vol, int nz, int ny, int nx,
+                  float* g_out, float* w_out, double* stats_out, void* ws, size_t ws_bytes,
+                  void* stream);
+int ttm_normalize_box(ttm_ctx* ctx, const ttm_desc* desc, const float* g, int nz, int ny, int nx,
+                      const double* stats, const void* mask_spec, int fft_n,
+                      const int32_t box_lo[3], const int32_t box_size[3], float* w_out, void* ws,
+                      size_t ws_bytes, void* stream);
 
 /*
  * Tensor field on a box of the valid region (Eq. tcc, Alg. 2):

@@ -16,7 +16,7 @@ TTM_OK, TTM_EINVAL, TTM_ENOMEM, TTM_EDEVICE, TTM_EUNSUPPORTED, TTM_EWORKSPACE = 
 TTM_F32, TTM_BF16 = 0, 1
 TTM_OP_SPECTRA, TTM_OP_NORMALIZE, TTM_OP_CORRELATE, TTM_OP_PEAKS = 1, 2, 3, 4
 TTM_SCORE, TTM_ORIENT, TTM_START_MLP, TTM_START_ONLY, TTM_NO_SCREEN = 1, 2, 4, 8, 16
-TTM_OP_EXTRACT, TTM_OP_MLP_TRAIN = 5, 6
+TTM_OP_EXTRACT, TTM_OP_MLP_TRAIN, TTM_OP_PREFILTER = 5, 6, 7
 
 STATUS_NAMES = {0: "TTM_OK", -1: "TTM_EINVAL", -2: "TTM_ENOMEM", -3: "TTM_EDEVICE",
                 -4: "TTM_EUNSUPPORTED", -5: "TTM_EWORKSPACE"}
@@ -51,6 +51,11 @@ SIGNATURES = {
     "ttm_template_spectra": (C.c_int, [vp, DP, vp, C.c_int, vp, vp, C.c_size_t, vp]),
     "ttm_normalize": (C.c_int, [vp, DP, vp, C.c_int, C.c_int, C.c_int, vp, C.c_int, vp, vp, vp,
                                 vp, C.c_size_t, vp]),
+    "ttm_prefilter": (C.c_int, [vp, DP, vp, C.c_int, C.c_int, C.c_int, vp, vp, vp, vp,
+                                C.c_size_t, vp]),
+    "ttm_normalize_box": (C.c_int, [vp, DP, vp, C.c_int, C.c_int, C.c_int, vp, vp, C.c_int,
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_int32), vp, vp, C.c_size_t,
+                                    vp]),
     "ttm_correlate": (C.c_int, [vp, DP, vp, vp, C.c_int, C.c_int, C.c_int, vp, vp, C.c_int,
                                 C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int, vp, vp,
                                 C.c_size_t, vp]),

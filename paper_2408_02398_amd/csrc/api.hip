@@ -473,6 +473,9 @@ size_t ttm_workspace_size(const ttm_desc* desc, int op, int fft_n, int nz, int n
   switch (op) {
     case TTM_OP_SPECTRA:
       return align256(L * L * L * 4);
+    case TTM_OP_PREFILTER:
+      if (nz < 1 || ny < 1 || nx < 1) return 0;
+      return align256(prefilter_blocks(nz, ny, nx) * 16);
     case TTM_OP_NORMALIZE: {
       if (!fft_ok(fft_n) || desc->L > fft_n) return 0;
       const size_t step = (size_t)(fft_n - desc->L + 1);
@@ -558,6 +561,126 @@ int ttm_template_spectra(ttm_ctx* ctx, const ttm_desc* desc, const float* T, int
   return fft3d_forward(fft_n, msrc, 1, out + (size_t)K * se, se, ctx->twiddles, s);
 }
 
+namespace {
+
+// w on the sub-tiles (edge fft_n - L + 1) of a box of the valid region.
+int normalize_boxes(ttm_ctx* ctx, const ttm_desc* desc, const float* g, int nz, int ny, int nx,
+                    const double* stats, const void* mask_spec, int fft_n, const int32_t box_lo[3],
+                    const int32_t box_size[3], float* w_out, void* ws, hipStream_t s) {
+  const int L = desc->L;
+  const size_t se = spec_elems(fft_n);
+  const size_t sb = align256(se * 8);
+  const int step = fft_n - L + 1;
+  char* w = static_cast<char*>(ws);
+  cf* G1 = reinterpret_cast<cf*>(w);
+  cf* G2 = reinterpret_cast<cf*>(w + sb);
+  cf* work = reinterpret_cast<cf*>(w + 2 * sb);
+  float* s1 = reinterpret_cast<float*>(w + 3 * sb);
+  float* s2 = reinterpret_cast<float*>(w + 3 * sb + align256((size_t)step * step * step * 4));
+  const int c = L / 2;
+  const double M = mask_count(L, desc->mask_radius);
+  const cf* mspec = static_cast<const cf*>(mask_spec);
+  const float scale = 1.0f / ((float)fft_n * fft_n * fft_n);
+  for (int dz = 0; dz < box_size[0]; dz += step) {
+    const int szz = std::min(step, box_size[0] - dz);
+    for (int dy = 0; dy < box_size[1]; dy += step) {
+      const int syy = std::min(step, box_size[1] - dy);
+      for (int dx = 0; dx < box_size[2]; dx += step) {
+        const int sxx = std::min(step, box_size[2] - dx);
+        const int oz = box_lo[0] + dz, oy = box_lo[1] + dy, ox = box_lo[2] + dx;
+        RealSrc src{g, 0, nz, ny, nx, oz - c, oy - c, ox - c, stats, 0};
+        int rc = fft3d_forward(fft_n, src, 1, G1, se, ctx->twiddles, s);
+        if (rc) return rc;
+        src.square = 1;
+        rc = fft3d_forward(fft_n, src, 1, G2, se, ctx->twiddles, s);
+        if (rc) return rc;
+        RealDst d1{s1, 0, 0, syy, sxx, 0, 0, 0, szz, syy, sxx, nullptr, 0, 0, 0, 0, 0, scale};
+        rc = fft3d_inverse_mul(fft_n, G1, mspec, 0, 1, nullptr, work, se, d1, ctx->twiddles, s);
+        if (rc) return rc;
+        RealDst d2 = d1;
+        d2.p = s2;
+        rc = fft3d_inverse_mul(fft_n, G2, mspec, 0, 1, nullptr, work, se, d2, ctx->twiddles, s);
+        if (rc) return rc;
+        const size_t nbx = (size_t)szz * syy * sxx;
+        hipLaunchKernelGGL(k_var_combine, dim3((unsigned)((nbx + 255) / 256)), dim3(256), 0, s, s1,
+                           s2, szz, syy, sxx, M, (double)desc->eps_w, stats, w_out, ny, nx, oz,
+                           oy, ox);
+      }
+    }
+  }
+  TTM_HIP(hipGetLastError());
+  return TTM_OK;
+}
+
+void prefilter_stats(const ttm_desc* desc, const float* vol, int nz, int ny, int nx, float* g_out,
+                     double* stats_out, double* part, hipStream_t s) {
+  const dim3 pg((nx + 255) / 256, ny, (nz + kPfZ - 1) / kPfZ);
+  hipLaunchKernelGGL(k_prefilter, pg, dim3(256), 0, s, vol, g_out, nz, ny, nx, desc->filter_a, part);
+  hipLaunchKernelGGL(k_stats, dim3(1), dim3(1024), 0, s, part, prefilter_blocks(nz, ny, nx),
+                     1.0 / ((double)nz * ny * nx), stats_out);
+}
+
+bool box_in_valid(const ttm_desc* desc, int nz, int ny, int nx, const int32_t box_lo[3],
+                  const int32_t box_size[3], const char* fn) {
+  const int L = desc->L, c = L / 2;
+  const int dims[3] = {nz, ny, nx};
+  for (int a = 0; a < 3; ++a) {
+    if (box_size[a] < 1 || box_lo[a] < c || box_lo[a] + box_size[a] - 1 > dims[a] - L + c) {
+      set_error("%s: box axis %d [%d, +%d) outside the valid region [%d, %d]", fn, a, box_lo[a],
+                box_size[a], c, dims[a] - L + c);
+      return false;
+    }
+  }
+  return true;
+}
+
+}  // namespace
+
+int ttm_prefilter(ttm_ctx* ctx, const ttm_desc* desc, const float* vol, int nz, int ny, int nx,
+                  float* g_out, float* w_out, double* stats_out, void* ws, size_t ws_bytes,
+                  void* stream) {
+  if (!ctx || !valid_desc(desc)) return TTM_EINVAL;
+  if (!vol || !g_out || !stats_out || !ws || nz < 1 || ny < 1 || nx < 1) {
+    set_error("ttm_prefilter: null pointer or empty volume");
+    return TTM_EINVAL;
+  }
+  const size_t need = ttm_workspace_size(desc, TTM_OP_PREFILTER, 0, nz, ny, nx);
+  if (ws_bytes < need) {
+    set_error("ttm_prefilter: workspace %zu < %zu", ws_bytes, need);
+    return TTM_EWORKSPACE;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  TTM_HIP(hipSetDevice(ctx->device));
+  prefilter_stats(desc, vol, nz, ny, nx, g_out, stats_out, static_cast<double*>(ws), s);
+  if (w_out) fill_zero(w_out, (size_t)nz * ny * nx * 4, s);
+  TTM_HIP(hipGetLastError());
+  return TTM_OK;
+}
+
+int ttm_normalize_box(ttm_ctx* ctx, const ttm_desc* desc, const float* g, int nz, int ny, int nx,
+                      const double* stats, const void* mask_spec, int fft_n,
+                      const int32_t box_lo[3], const int32_t box_size[3], float* w_out, void* ws,
+                      size_t ws_bytes, void* stream) {
+  if (!ctx || !valid_desc(desc)) return TTM_EINVAL;
+  if (!fft_ok(fft_n)) {
+    set_error("ttm_normalize_box: FFT edge %d not supported", fft_n);
+    return TTM_EUNSUPPORTED;
+  }
+  if (!g || !stats || !mask_spec || !w_out || !ws || !box_lo || !box_size || desc->L > fft_n) {
+    set_error("ttm_normalize_box: null pointer or L > fft_n");
+    return TTM_EINVAL;
+  }
+  if (!box_in_valid(desc, nz, ny, nx, box_lo, box_size, "ttm_normalize_box")) return TTM_EINVAL;
+  const size_t need = ttm_workspace_size(desc, TTM_OP_NORMALIZE, fft_n, nz, ny, nx);
+  if (ws_bytes < need) {
+    set_error("ttm_normalize_box: workspace %zu < %zu", ws_bytes, need);
+    return TTM_EWORKSPACE;
+  }
+  TTM_HIP(hipSetDevice(ctx->device));
+  return normalize_boxes(ctx, desc, g, nz, ny, nx, stats, mask_spec, fft_n, box_lo, box_size, w_out,
+                         ws, static_cast<hipStream_t>(stream));
+}
+
 int ttm_normalize(ttm_ctx* ctx, const ttm_desc* desc, const float* vol, int nz, int ny, int nx,
                   const void* mask_spec, int fft_n, float* g_out, float* w_out, double* stats_out,
                   void* ws, size_t ws_bytes, void* stream) {
@@ -579,56 +702,17 @@ int ttm_normalize(ttm_ctx* ctx, const ttm_desc* desc, const float* vol, int nz, 
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   TTM_HIP(hipSetDevice(ctx->device));
-  const size_t se = spec_elems(fft_n);
-  const size_t sb = align256(se * 8);
-  const int step = fft_n - L + 1;
-  char* w = static_cast<char*>(ws);
-  cf* G1 = reinterpret_cast<cf*>(w);
-  cf* G2 = reinterpret_cast<cf*>(w + sb);
-  cf* work = reinterpret_cast<cf*>(w + 2 * sb);
-  float* s1 = reinterpret_cast<float*>(w + 3 * sb);
-  float* s2 = reinterpret_cast<float*>(w + 3 * sb + align256((size_t)step * step * step * 4));
-  double* part = reinterpret_cast<double*>(w + 3 * sb + 2 * align256((size_t)step * step * step * 4));
-
-  const dim3 pg((nx + 255) / 256, ny, (nz + kPfZ - 1) / kPfZ);
-  hipLaunchKernelGGL(k_prefilter, pg, dim3(256), 0, s, vol, g_out, nz, ny, nx, desc->filter_a, part);
-  hipLaunchKernelGGL(k_stats, dim3(1), dim3(1024), 0, s, part, prefilter_blocks(nz, ny, nx),
-                     1.0 / ((double)nz * ny * nx), stats_out);
+  const size_t sb = align256(spec_elems(fft_n) * 8);
+  const size_t step = (size_t)(fft_n - L + 1);
+  double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + 3 * sb +
+                                           2 * align256(step * step * step * 4));
+  prefilter_stats(desc, vol, nz, ny, nx, g_out, stats_out, part, s);
   fill_zero(w_out, (size_t)nz * ny * nx * 4, s);
   const int c = L / 2;
-  const int vlo[3] = {c, c, c};
-  const int vhi[3] = {nz - L + c, ny - L + c, nx - L + c};
-  const double M = mask_count(L, desc->mask_radius);
-  const cf* mspec = static_cast<const cf*>(mask_spec);
-  const float scale = 1.0f / ((float)fft_n * fft_n * fft_n);
-  for (int oz = vlo[0]; oz <= vhi[0]; oz += step) {
-    const int szz = std::min(step, vhi[0] - oz + 1);
-    for (int oy = vlo[1]; oy <= vhi[1]; oy += step) {
-      const int syy = std::min(step, vhi[1] - oy + 1);
-      for (int ox = vlo[2]; ox <= vhi[2]; ox += step) {
-        const int sxx = std::min(step, vhi[2] - ox + 1);
-        RealSrc src{g_out, 0, nz, ny, nx, oz - c, oy - c, ox - c, stats_out, 0};
-        int rc = fft3d_forward(fft_n, src, 1, G1, se, ctx->twiddles, s);
-        if (rc) return rc;
-        src.square = 1;
-        rc = fft3d_forward(fft_n, src, 1, G2, se, ctx->twiddles, s);
-        if (rc) return rc;
-        RealDst d1{s1, 0, 0, syy, sxx, 0, 0, 0, szz, syy, sxx, nullptr, 0, 0, 0, 0, 0, scale};
-        rc = fft3d_inverse_mul(fft_n, G1, mspec, 0, 1, nullptr, work, se, d1, ctx->twiddles, s);
-        if (rc) return rc;
-        RealDst d2 = d1;
-        d2.p = s2;
-        rc = fft3d_inverse_mul(fft_n, G2, mspec, 0, 1, nullptr, work, se, d2, ctx->twiddles, s);
-        if (rc) return rc;
-        const size_t nbx = (size_t)szz * syy * sxx;
-        hipLaunchKernelGGL(k_var_combine, dim3((unsigned)((nbx + 255) / 256)), dim3(256), 0, s, s1,
-                           s2, szz, syy, sxx, M, (double)desc->eps_w, stats_out, w_out, ny, nx, oz,
-                           oy, ox);
-      }
-    }
-  }
-  TTM_HIP(hipGetLastError());
-  return TTM_OK;
+  const int32_t lo[3] = {c, c, c};
+  const int32_t size[3] = {nz - L + 1, ny - L + 1, nx - L + 1};
+  return normalize_boxes(ctx, desc, g_out, nz, ny, nx, stats_out, mask_spec, fft_n, lo, size, w_out,
+                         ws, s);
 }
 
 int ttm_correlate(ttm_ctx* ctx, const ttm_desc* desc, const float* g, const float* wmap, int nz,

@@ -118,6 +118,33 @@ def normalize(ctx: Context, desc: Desc, vol: torch.Tensor, spectra: torch.Tensor
     return g, w, stats
 
 
+def prefilter(ctx: Context, desc: Desc, vol: torch.Tensor, ws: torch.Tensor | None = None):
+    """g = h*f, w cleared to 0, stats = (mean g, mean g^2): the first half of normalize."""
+    _need_cuda(vol)
+    nz, ny, nx = vol.shape
+    g = torch.empty_like(vol)
+    w = torch.empty_like(vol)
+    stats = torch.empty(2, dtype=torch.float64, device=vol.device)
+    if ws is None:
+        ws = _ws(desc, L.TTM_OP_PREFILTER, 0, (nz, ny, nx), device=vol.device)
+    call("ttm_prefilter", ctx.h, C.byref(desc), _ptr(vol), nz, ny, nx, _ptr(g), _ptr(w),
+         _ptr(stats), _ptr(ws), ws.numel(), _stream())
+    return g, w, stats
+
+
+def normalize_box(ctx: Context, desc: Desc, g: torch.Tensor, stats: torch.Tensor,
+                  spectra: torch.Tensor, fft_n: int, box_lo, box_size, w: torch.Tensor,
+                  ws: torch.Tensor | None = None) -> None:
+    """w on one box of the valid region (the second half of normalize)."""
+    _need_cuda(g, stats, spectra, w)
+    nz, ny, nx = g.shape
+    if ws is None:
+        ws = _ws(desc, L.TTM_OP_NORMALIZE, fft_n, (nz, ny, nx), device=g.device)
+    call("ttm_normalize_box", ctx.h, C.byref(desc), _ptr(g), nz, ny, nx, _ptr(stats),
+         _ptr(spectra[-1]), fft_n, I32x3(*box_lo), I32x3(*box_size), _ptr(w), _ptr(ws),
+         ws.numel(), _stream())
+
+
 def correlate(ctx: Context, desc: Desc, g: torch.Tensor, w: torch.Tensor, stats: torch.Tensor,
               spectra: torch.Tensor, fft_n: int, box_lo, box_size, dtype=torch.float32,
               out: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
@@ -313,8 +340,9 @@ class PassResult:
 
 
 class Engine:
-    """A TTM full pass with preallocated buffers: normalise, correlate per tile,
-    extract per tile into the volume maps, then Find Peaks."""
+    """A TTM full pass with preallocated buffers: prefilter, then per tile the
+    local normalisation and correlation (side stream, one tile ahead) and the
+    extraction into the volume maps, then Find Peaks."""
 
     def __init__(self, ctx: Context, desc: Desc, spectra: torch.Tensor, fft_n: int, shape,
                  starts: torch.Tensor | None, field_dtype=torch.float32, orient: bool = True,
@@ -336,6 +364,7 @@ class Engine:
         self.Cbufs = [torch.empty(K * step ** 3, dtype=field_dtype, device=dev) for _ in range(2)]
         self.Cbuf = self.Cbufs[0]
         self.side = torch.cuda.Stream(device=dev)
+        self.ws_pre = _ws(desc, L.TTM_OP_PREFILTER, 0, self.shape, device=dev)
         self.ws_norm = _ws(desc, L.TTM_OP_NORMALIZE, fft_n, self.shape, device=dev)
         self.ws_corr = _ws(desc, L.TTM_OP_CORRELATE, fft_n, self.shape, device=dev)
         self.ws_peaks = _ws(desc, L.TTM_OP_PEAKS, fft_n, self.shape, device=dev)
@@ -366,7 +395,7 @@ class Engine:
                 timing.setdefault(k, [])
         e0, e1 = ev(), ev()
         rec(e0, main)
-        g, w, stats = normalize(self.ctx, self.desc, vol, self.spectra, self.fft_n, ws=self.ws_norm)
+        g, w, stats = prefilter(self.ctx, self.desc, vol, ws=self.ws_pre)
         rec(e1, main)
         if timing is not None:
             timing["normalize"].append((e0, e1))
@@ -378,6 +407,13 @@ class Engine:
             b = k % 2
             Ct = self.Cbufs[b][: self.K * size[0] * size[1] * size[2]].view(self.K, *size)
             with torch.cuda.stream(side):
+                # the tile's local normalisation (Eq. norm_f) runs just before its
+                # correlation, so only the first tile's is on the critical path
+                n0, n1 = ev(), ev()
+                rec(n0, side)
+                normalize_box(self.ctx, self.desc, g, stats, self.spectra, self.fft_n, lo, size, w,
+                              ws=self.ws_norm)
+                rec(n1, side)
                 if free[b] is not None:
                     side.wait_event(free[b])
                 a0, a1 = ev(), ev()
@@ -388,6 +424,7 @@ class Engine:
                 ready = torch.cuda.Event()
                 ready.record(side)
             if timing is not None:
+                timing["normalize"].append((n0, n1))
                 timing["correlate"].append((a0, a1, size))
             main.wait_event(ready)
             x0, x1 = ev(), ev()

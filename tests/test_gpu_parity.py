@@ -117,6 +117,34 @@ def test_normalize_matches_oracle(T, ctx, small):
     assert np.max(np.abs(wg[nz] - wo[nz]) / wo[nz]) < 1e-4
 
 
+def test_prefilter_and_box_normalisation_reproduce_normalize(T, ctx, small):
+    """ttm_prefilter + ttm_normalize_box over the tile boxes == ttm_normalize, bit for bit,
+    and a box that is not step-aligned still matches to FP32 rounding."""
+    d = T.make_desc(small["n"], small["L"], small["r"])
+    spec = T.template_spectra(ctx, d, cuda(small["Tt"]), 32)
+    vol = cuda(small["w"].volume)
+    g0, w0, s0 = T.normalize(ctx, d, vol, spec, 32)
+    g1, w1, s1 = T.prefilter(ctx, d, vol)
+    assert torch.equal(g0, g1) and torch.equal(s0, s1)
+    assert torch.count_nonzero(w1).item() == 0
+    for lo, size in T.tile_boxes(tuple(vol.shape), small["L"], 32):
+        T.normalize_box(ctx, d, g1, s1, spec, 32, lo, size, w1)
+    torch.cuda.synchronize()
+    assert torch.equal(w0, w1)
+    lo, hi = T.valid_bounds(tuple(vol.shape), small["L"])
+    w2 = torch.zeros_like(w1)
+    box_lo = (lo[0] + 3, lo[1] + 5, lo[2] + 1)
+    box = (min(20, hi[0] - box_lo[0] + 1), min(9, hi[1] - box_lo[1] + 1), min(25, hi[2] - box_lo[2] + 1))
+    T.normalize_box(ctx, d, g1, s1, spec, 32, box_lo, box, w2)
+    sl = tuple(slice(a, a + b) for a, b in zip(box_lo, box))
+    a, b = host(w2)[sl], host(w0)[sl]
+    assert np.max(np.abs(a - b) / np.maximum(b, 1e-30)) < 1e-4
+    assert np.count_nonzero(host(w2)) == np.count_nonzero(a)
+    from paper_2408_02398_amd._lib import TTMError
+    with pytest.raises(TTMError):
+        T.normalize_box(ctx, d, g1, s1, spec, 32, (0, 0, 0), (4, 4, 4), w2)
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
 def test_correlate_and_score_match_oracle(T, ctx, small, dtype):
     n, L = small["n"], small["L"]
