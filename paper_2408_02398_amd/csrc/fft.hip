@@ -14,7 +14,7 @@ namespace ttm {
 
 namespace {
 
-constexpr int kRowsX = 16;  // real rows per workgroup in the X passes (8 packed pairs)
+constexpr int kRowsX = 16;  // real rows per workgroup in the X passes (packed in pairs)
 
 __device__ __forceinline__ float load_src(const RealSrc& s, int b, int z, int y, int x) {
   const int gz = s.oz + z, gy = s.oy + y, gx = s.ox + x;
@@ -33,7 +33,7 @@ __device__ __forceinline__ unsigned short f32_to_bf16(float f) {
 
 // ---------------------------------------------------------------- X forward
 template <int N>
-__global__ __launch_bounds__(8 * Plan<N>::T) void k_r2c_x(RealSrc src, cf* __restrict__ spec,
+__global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) void k_r2c_x(RealSrc src, cf* __restrict__ spec,
                                                           size_t spec_stride,
                                                           const cf* __restrict__ tw) {
   constexpr int T = Plan<N>::T, E = N / T, NP = kRowsX / 2, NH = N / 2 + 1;
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(ColBlock<N>::CB * Plan<N>::T) void k_zinv_mul(
 
 // ---------------------------------------------------------------- X inverse
 template <int N>
-__global__ __launch_bounds__(8 * Plan<N>::T) void k_c2r_x(const cf* __restrict__ spec,
+__global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) void k_c2r_x(const cf* __restrict__ spec,
                                                           size_t spec_stride, RealDst dst,
                                                           const cf* __restrict__ tw) {
   constexpr int T = Plan<N>::T, E = N / T, NP = kRowsX / 2, NH = N / 2 + 1;
@@ -254,7 +254,7 @@ template <int N>
 int forward_n(const RealSrc& src, int batch, cf* spec, size_t spec_stride, const cf* tw,
               hipStream_t s) {
   constexpr int T = Plan<N>::T;
-  hipLaunchKernelGGL(k_r2c_x<N>, dim3(N / kRowsX, N, batch), dim3(8 * T), 0, s, src, spec,
+  hipLaunchKernelGGL(k_r2c_x<N>, dim3(N / kRowsX, N, batch), dim3(kRowsX / 2 * T), 0, s, src, spec,
                      spec_stride, tw);
   constexpr int RB = (128 / T > 0 ? 128 / T : 1);
   constexpr int NROWS = N * (N / 2 + 1);
@@ -279,7 +279,7 @@ int inverse_n(const cf* G, const cf* Sp, size_t s_stride, int A, const double* c
   constexpr int RB = (128 / T > 0 ? 128 / T : 1);
   hipLaunchKernelGGL((k_c2c_rows<N, true>), dim3(NROWS / RB, A), dim3(RB * T), 0, s, work,
                      work_stride, zlim, tw);
-  hipLaunchKernelGGL(k_c2r_x<N>, dim3(A, N / kRowsX, N), dim3(8 * T), 0, s, work, work_stride,
+  hipLaunchKernelGGL(k_c2r_x<N>, dim3(A, N / kRowsX, N), dim3(kRowsX / 2 * T), 0, s, work, work_stride,
                      dst, tw);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : hip_status(e, "fft inverse launch");
