@@ -238,15 +238,16 @@ def main():
 
     # roofline of the dominant kernel
     K = ttm.n_components(n, 3)
-    se = ttm.spectrum_elems(fft_n)
     step_ = fft_n - L + 1
     stage = R["stage"]
     corr_launch_ms, ext_launch_ms = R["corr"], R["ext"]
     corr_avg = float(np.mean(corr_launch_ms))
     ext_avg = float(np.mean([t for t, _ in ext_launch_ms]))
     # correlation launch (full interior tile): compulsory bytes = read the g tile,
-    # the K template spectra, the w crop, write the K cropped field planes
-    corr_bytes = 4 * fft_n ** 3 + K * se * 8 + 4 * step_ ** 3 + 4 * K * step_ ** 3
+    # the K x/y-transformed template planes, the w crop, write the K cropped
+    # field planes
+    tse = ttm.template_spectrum_elems(fft_n, L)
+    corr_bytes = 4 * fft_n ** 3 + K * tse * 8 + 4 * step_ ** 3 + 4 * K * step_ ** 3
     corr_full = [t for t, (blo, size) in zip(corr_launch_ms, R["eng"].boxes * args.steps)
                  if size == (step_, step_, step_)]
     corr_full_avg = float(np.mean(corr_full)) if corr_full else corr_avg

@@ -101,6 +101,9 @@ int ttm_n_components(int degree, int dprime);
 /* Complex (float2) elements of one half spectrum of an N^3 real array:
  * N * (N/2 + 1) * N.  Spectra are stored [kz][kx][ky] (ky fastest). */
 size_t ttm_spectrum_elems(int fft_n);
+/* Complex elements of one template spectrum from ttm_template_spectra:
+ * L * (N/2 + 1) * N, or 0 for an unsupported edge or L outside 1..fft_n. */
+size_t ttm_template_spectrum_elems(int fft_n, int L);
 /* FFT edges this build supports (powers of two 32..512): 1 if supported. */
 int ttm_fft_supported(int fft_n);
 
@@ -126,9 +129,13 @@ int ttm_build_tensor(ttm_ctx* ctx, const ttm_desc* desc, const float* tmpl,
 /*
  * Spectra of the template fields for correlation at FFT edge fft_n (Alg. 2,
  * F(T_i)): each field is placed at the origin of a zero N^3 array and
- * forward-transformed (unnormalised e^{-i}).  Output: K component spectra
- * followed by the spectrum of the mask m, (K + 1) x ttm_spectrum_elems(N)
- * float2, device.  Requires L <= fft_n.
+ * forward-transformed (unnormalised e^{-i}) along x and y.  Only z planes
+ * 0..L-1 of such an array are nonzero, and only those are stored: the z
+ * transform is taken inside ttm_correlate / ttm_normalize, column by column,
+ * so each tile reads L/N of the bytes of full spectra.  Output: K component
+ * arrays followed by the one of the mask m, (K + 1) x
+ * ttm_template_spectrum_elems(N, L) float2, device, each [z < L][kx][ky]
+ * (ky fastest, kx in 0..N/2).  Requires L <= fft_n.
  */
 int ttm_template_spectra(ttm_ctx* ctx, const ttm_desc* desc, const float* T, int fft_n,
                          void* spec_out, void* ws, size_t ws_bytes, void* stream);

@@ -45,6 +45,7 @@ SIGNATURES = {
     "ttm_last_error": (C.c_char_p, []),
     "ttm_n_components": (C.c_int, [C.c_int, C.c_int]),
     "ttm_spectrum_elems": (C.c_size_t, [C.c_int]),
+    "ttm_template_spectrum_elems": (C.c_size_t, [C.c_int, C.c_int]),
     "ttm_fft_supported": (C.c_int, [C.c_int]),
     "ttm_workspace_size": (C.c_size_t, [DP, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
     "ttm_build_tensor": (C.c_int, [vp, DP, vp, vp, C.c_int, vp, vp, vp]),

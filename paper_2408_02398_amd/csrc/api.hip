@@ -388,6 +388,8 @@ constexpr int kMlpInMax = kMlpIn;
 bool fft_ok(int N) { return N == 32 || N == 64 || N == 128 || N == 256 || N == 512; }
 
 size_t spec_elems(int N) { return (size_t)N * (N / 2 + 1) * N; }
+// x/y-transformed template: its L nonzero z planes only
+size_t tspec_elems(int N, int L) { return (size_t)L * (N / 2 + 1) * N; }
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 double mask_count(int L, float r) {
@@ -418,6 +420,10 @@ const char* ttm_last_error(void) { return ttm::g_err; }
 int ttm_n_components(int degree, int dprime) { return ncomp(degree, dprime); }
 
 size_t ttm_spectrum_elems(int fft_n) { return fft_ok(fft_n) ? spec_elems(fft_n) : 0; }
+
+size_t ttm_template_spectrum_elems(int fft_n, int L) {
+  return fft_ok(fft_n) && L >= 1 && L <= fft_n ? tspec_elems(fft_n, L) : 0;
+}
 
 int ttm_fft_supported(int fft_n) { return fft_ok(fft_n) ? 1 : 0; }
 
@@ -550,15 +556,16 @@ int ttm_template_spectra(ttm_ctx* ctx, const ttm_desc* desc, const float* T, int
   hipStream_t s = static_cast<hipStream_t>(stream);
   TTM_HIP(hipSetDevice(ctx->device));
   const int L = desc->L, K = ncomp(desc->degree, desc->dprime);
-  const size_t se = spec_elems(fft_n);
+  const size_t se = tspec_elems(fft_n, L);
   cf* out = static_cast<cf*>(spec_out);
+  // fields at the origin: z planes L.. of the padded tile are zero
   RealSrc src{T, (size_t)L * L * L, L, L, L, 0, 0, 0, nullptr, 0};
-  int rc = fft3d_forward(fft_n, src, K, out, se, ctx->twiddles, s);
+  int rc = fft3d_forward_planes(fft_n, src, K, L, out, se, ctx->twiddles, s);
   if (rc) return rc;
   float* m = static_cast<float*>(ws);
   hipLaunchKernelGGL(k_mask, dim3((L * L * L + 255) / 256), dim3(256), 0, s, m, L, desc->mask_radius);
   RealSrc msrc{m, 0, L, L, L, 0, 0, 0, nullptr, 0};
-  return fft3d_forward(fft_n, msrc, 1, out + (size_t)K * se, se, ctx->twiddles, s);
+  return fft3d_forward_planes(fft_n, msrc, 1, L, out + (size_t)K * se, se, ctx->twiddles, s);
 }
 
 namespace {
@@ -595,11 +602,11 @@ int normalize_boxes(ttm_ctx* ctx, const ttm_desc* desc, const float* g, int nz, 
         rc = fft3d_forward(fft_n, src, 1, G2, se, ctx->twiddles, s);
         if (rc) return rc;
         RealDst d1{s1, 0, 0, syy, sxx, 0, 0, 0, szz, syy, sxx, nullptr, 0, 0, 0, 0, 0, scale};
-        rc = fft3d_inverse_mul(fft_n, G1, mspec, 0, 1, nullptr, work, se, d1, ctx->twiddles, s);
+        rc = fft3d_inverse_mul(fft_n, G1, mspec, 0, L, 1, nullptr, work, se, d1, ctx->twiddles, s);
         if (rc) return rc;
         RealDst d2 = d1;
         d2.p = s2;
-        rc = fft3d_inverse_mul(fft_n, G2, mspec, 0, 1, nullptr, work, se, d2, ctx->twiddles, s);
+        rc = fft3d_inverse_mul(fft_n, G2, mspec, 0, L, 1, nullptr, work, se, d2, ctx->twiddles, s);
         if (rc) return rc;
         const size_t nbx = (size_t)szz * syy * sxx;
         hipLaunchKernelGGL(k_var_combine, dim3((unsigned)((nbx + 255) / 256)), dim3(256), 0, s, s1,
@@ -766,8 +773,8 @@ int ttm_correlate(ttm_ctx* ctx, const ttm_desc* desc, const float* g, const floa
         if (rc) return rc;
         RealDst d{C_out, out_dtype, plane, box_size[1], box_size[2], dz, dy, dx, szz, syy, sxx,
                   wmap, ny, nx, oz, oy, ox, scale};
-        rc = fft3d_inverse_mul(fft_n, G, static_cast<const cf*>(spec), se, K, stats, work, sb / 8, d,
-                               ctx->twiddles, s);
+        rc = fft3d_inverse_mul(fft_n, G, static_cast<const cf*>(spec), tspec_elems(fft_n, L), L,
+                               K, stats, work, sb / 8, d, ctx->twiddles, s);
         if (rc) return rc;
       }
     }
@@ -979,7 +986,7 @@ int ttm_fft3d_c2r(ttm_ctx* ctx, void* spec, int fft_n, float scale, float* x, vo
   TTM_HIP(hipSetDevice(ctx->device));
   RealDst d{x, 0, 0, fft_n, fft_n, 0, 0, 0, fft_n, fft_n, fft_n, nullptr, 0, 0, 0, 0, 0, scale};
   cf* sp = static_cast<cf*>(spec);
-  return fft3d_inverse_mul(fft_n, sp, nullptr, 0, 1, nullptr, sp, spec_elems(fft_n), d,
+  return fft3d_inverse_mul(fft_n, sp, nullptr, 0, 0, 1, nullptr, sp, spec_elems(fft_n), d,
                            ctx->twiddles, static_cast<hipStream_t>(stream));
 }
 

@@ -4,10 +4,12 @@
 // Forward = X pass (two real rows packed as one complex row, R2C split on
 // the way out, transposed store so ky becomes contiguous), Y pass (contiguous
 // rows), Z pass (strided columns, 16 columns per workgroup so every global
-// access is a 128-byte segment).  Inverse = Z pass with the spectral product
-// fused in (one read of G per tile for all components), Y pass, X pass with
-// the C2R merge, 1/N^3 scale, weight map, crop and dtype conversion fused
-// into the store.
+// access is a 128-byte segment).  Templates, which are nonzero only in their
+// first L z planes, stop after the Y pass and keep just those planes.
+// Inverse = Z pass with the spectral product fused in (one read of G per tile
+// for all components; each template column's z transform formed in registers
+// from its L stored values), Y pass, X pass with the C2R merge, 1/N^3 scale,
+// weight map, crop and dtype conversion fused into the store.
 #include "internal.hpp"
 
 namespace ttm {
@@ -23,6 +25,15 @@ __device__ __forceinline__ float load_src(const RealSrc& s, int b, int z, int y,
   if (s.center) v = (float)((double)v - s.center[0]);
   if (s.square) v = v * v;
   return v;
+}
+
+// Workgroups go to the 8 XCDs in turn (workgroup i to XCD i mod 8), and each
+// XCD has its own L2.  This renumbering hands every XCD one contiguous range
+// of work items, so neighbouring items -- the two halves of a 128-byte line,
+// the components that share a crop's weight-map rows -- meet in one L2.
+__device__ __forceinline__ unsigned xcd_item(unsigned bid, unsigned n) {
+  constexpr unsigned kXcd = 8;
+  return n % kXcd ? bid : (bid % kXcd) * (n / kXcd) + bid / kXcd;
 }
 
 __device__ __forceinline__ unsigned short f32_to_bf16(float f) {
@@ -88,15 +99,19 @@ k_c2c_rows(cf* __restrict__ data, size_t batch_stride, int row_limit, const cf* 
   const int tid = threadIdx.x;
   const int r = tid / T, t = tid % T;
   const int row = blockIdx.x * RB + r;
-  // rows are (z, kx): z = row / (N/2+1); rows with z >= row_limit are not needed
+  // rows are (z, kx): z = row / (N/2+1); rows with z >= row_limit are not
+  // needed and may lie past the end of the buffer, so they are not touched
   if ((int)(blockIdx.x * RB) / (N / 2 + 1) >= row_limit) return;  // uniform per workgroup
+  const bool live = row / (N / 2 + 1) < row_limit;
   cf* base = data + blockIdx.y * batch_stride + (size_t)row * N;
   cf v[E];
 #pragma unroll
-  for (int j = 0; j < E; ++j) v[j] = base[t + T * j];
+  for (int j = 0; j < E; ++j) v[j] = live ? base[t + T * j] : cf{0.0f, 0.0f};
   fft_1d<N, INV>(v, xl + r * S, tw, t);
+  if (live) {
 #pragma unroll
-  for (int j = 0; j < E; ++j) base[t + T * j] = v[j];
+    for (int j = 0; j < E; ++j) base[t + T * j] = v[j];
+  }
 }
 
 // ---------------------------------------------------------------- Z (columns)
@@ -120,45 +135,73 @@ __global__ __launch_bounds__(ColBlock<N>::CB * Plan<N>::T) void k_c2c_cols(
   for (int j = 0; j < E; ++j) base[(size_t)(t + T * j) * NC] = v[j];
 }
 
+// Element at byte offset `off` from `base`.  A 32-bit offset from a pointer
+// that is the same for the whole workgroup lets the compiler address through
+// a scalar base and one 32-bit register per access.
+__device__ __forceinline__ const cf& at_byte(const cf* base, unsigned off) {
+  return *reinterpret_cast<const cf*>(reinterpret_cast<const char*>(base) + off);
+}
+__device__ __forceinline__ cf& at_byte(cf* base, unsigned off) {
+  return *reinterpret_cast<cf*>(reinterpret_cast<char*>(base) + off);
+}
+
 // Inverse Z pass with the spectral product: out_a = Z^-1( G conj(S_a) ).
-template <int N>
+// P holds only the sp nonzero z planes of each template after its X and Y
+// passes; each column of S_a is their z transform, formed here in registers,
+// which reads sp/N of the bytes a stored S_a would cost.  Plane z of a column
+// sits in slot z / T of thread z mod T, and JP >= ceil(sp / T) slots are
+// kept (JP = 0: no template, G itself is inverted).  The planes of component
+// a + 1 load while component a is transformed.
+template <int N, int JP>
 __global__ __launch_bounds__(ColBlock<N>::CB * Plan<N>::T) void k_zinv_mul(
-    const cf* __restrict__ G, const cf* __restrict__ Sp, size_t s_stride, int A,
+    const cf* __restrict__ G, const cf* __restrict__ P, size_t p_stride, int sp, int A,
     const double* __restrict__ center, cf* __restrict__ out, size_t out_stride, int z_limit,
     const cf* __restrict__ tw) {
   constexpr int T = Plan<N>::T, E = N / T, CB = ColBlock<N>::CB, NC = (N / 2 + 1) * N;
   constexpr int S = lds_stride<N>();
+  // byte offsets inside one [z][kx][ky] spectrum stay below 2^32 for N <= 512
+  constexpr unsigned JSTEP = (unsigned)T * NC * 8u;
+  static_assert((unsigned long long)N * NC * 8ull < (1ull << 32), "32-bit offsets");
   __shared__ cf xl[CB * S];
   const int tid = threadIdx.x;
   const int c = tid % CB, t = tid / CB;
-  const int col = blockIdx.x * CB + c;
+  const unsigned col = xcd_item(blockIdx.x, gridDim.x) * CB + c;
+  const unsigned off0 = ((unsigned)t * NC + col) * 8u;
   cf g[E];
 #pragma unroll
-  for (int j = 0; j < E; ++j) g[j] = G[(size_t)(t + T * j) * NC + col];
+  for (int j = 0; j < E; ++j) g[j] = at_byte(G, off0 + j * JSTEP);
   // DC bin (kz = kx = ky = 0) is element j = 0 of thread t = 0 in column 0:
   // restore the mean removed before the forward transform.
-  const bool dc = (col == 0 && t == 0);
-  const float dc_add = (dc && center) ? (float)(center[0] * (double)N * (double)N * (double)N) : 0.0f;
+  if (JP > 0 && center && col == 0 && t == 0) {
+    g[0].x += (float)(center[0] * (double)N * (double)N * (double)N);
+  }
+  cf q[JP > 0 ? JP : 1];  // z planes of the next component
+  auto load_planes = [&](int a) {
+    const cf* pa = P + (size_t)a * p_stride;
+#pragma unroll
+    for (int j = 0; j < JP; ++j) {
+      q[j] = t + T * j < sp ? at_byte(pa, off0 + j * JSTEP) : cf{0.0f, 0.0f};
+    }
+  };
+  if constexpr (JP > 0) load_planes(0);
   for (int a = 0; a < A; ++a) {
     cf v[E];
-    const cf* sa = Sp ? Sp + a * s_stride + col : nullptr;
+    if constexpr (JP > 0) {
 #pragma unroll
-    for (int j = 0; j < E; ++j) {
-      if (sa) {
-        const cf s = sa[(size_t)(t + T * j) * NC];
-        cf gg = g[j];
-        if (j == 0 && dc) gg.x += dc_add;
-        v[j] = cmulc(gg, s);
-      } else {
-        v[j] = g[j];
-      }
+      for (int j = 0; j < E; ++j) v[j] = j < JP ? q[j] : cf{0.0f, 0.0f};
+      if (a + 1 < A) load_planes(a + 1);
+      fft_1d<N, false>(v, xl + c * S, tw, t);  // S_a along this column
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = cmulc(g[j], v[j]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = g[j];
     }
     fft_1d<N, true>(v, xl + c * S, tw, t);
-    cf* o = out + a * out_stride + col;
+    cf* o = out + (size_t)a * out_stride;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const int zz = t + T * j;
-      if (zz < z_limit) o[(size_t)zz * NC] = v[j];
+      if (t + T * j < z_limit) at_byte(o, off0 + j * JSTEP) = v[j];
     }
   }
 }
@@ -166,7 +209,7 @@ __global__ __launch_bounds__(ColBlock<N>::CB * Plan<N>::T) void k_zinv_mul(
 // ---------------------------------------------------------------- X inverse
 template <int N>
 __global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) void k_c2r_x(const cf* __restrict__ spec,
-                                                          size_t spec_stride, RealDst dst,
+                                                          size_t spec_stride, int A, RealDst dst,
                                                           const cf* __restrict__ tw) {
   constexpr int T = Plan<N>::T, E = N / T, NP = kRowsX / 2, NH = N / 2 + 1;
   constexpr int S = lds_stride<N>();
@@ -179,9 +222,11 @@ __global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) void k_c2r_x(const cf* __r
   cf* xl = reinterpret_cast<cf*>(smem);
   float* orow = reinterpret_cast<float*>(smem);
   const int tid = threadIdx.x;
-  // component fastest in the grid, so the workgroups that share a crop's
-  // weight-map rows run together and find them in the L2
-  const int b = blockIdx.x, y0 = blockIdx.y * kRowsX, z = blockIdx.z;
+  // work items: component fastest, then row block, then z plane, so the
+  // workgroups that share a crop's weight-map rows run together in one XCD
+  constexpr int NYB = N / kRowsX;
+  const int item = (int)xcd_item(blockIdx.x, gridDim.x);
+  const int b = item % A, y0 = (item / A) % NYB * kRowsX, z = item / A / NYB;
   if (z >= dst.sz || y0 >= dst.sy) return;  // uniform: nothing of this block is kept
   const cf* in = spec + b * spec_stride + (size_t)z * NH * N + y0;
   for (int e = tid; e < NH * kRowsX; e += NP * T) {
@@ -268,19 +313,49 @@ int forward_n(const RealSrc& src, int batch, cf* spec, size_t spec_stride, const
 }
 
 template <int N>
-int inverse_n(const cf* G, const cf* Sp, size_t s_stride, int A, const double* center, cf* work,
-              size_t work_stride, const RealDst& dst, const cf* tw, hipStream_t s) {
+int forward_planes_n(const RealSrc& src, int batch, int planes, cf* out, size_t out_stride,
+                     const cf* tw, hipStream_t s) {
+  constexpr int T = Plan<N>::T;
+  hipLaunchKernelGGL(k_r2c_x<N>, dim3(N / kRowsX, planes, batch), dim3(kRowsX / 2 * T), 0, s, src,
+                     out, out_stride, tw);
+  constexpr int RB = (128 / T > 0 ? 128 / T : 1);
+  const int rows = planes * (N / 2 + 1);
+  hipLaunchKernelGGL((k_c2c_rows<N, false>), dim3((rows + RB - 1) / RB, batch), dim3(RB * T), 0, s,
+                     out, out_stride, planes, tw);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : hip_status(e, "fft forward launch");
+}
+
+template <int N>
+int inverse_n(const cf* G, const cf* Sp, size_t s_stride, int s_planes, int A, const double* center,
+              cf* work, size_t work_stride, const RealDst& dst, const cf* tw, hipStream_t s) {
   constexpr int T = Plan<N>::T;
   constexpr int NROWS = N * (N / 2 + 1);
   constexpr int CB = ColBlock<N>::CB;
   const int zlim = dst.sz;
-  hipLaunchKernelGGL(k_zinv_mul<N>, dim3(NROWS / CB, 1), dim3(CB * T), 0, s, G, Sp, s_stride, A,
+  constexpr int E = N / T;
+  // template slots per thread: the next power of two >= ceil(s_planes / T)
+  int jp = 0;
+  if (Sp) {
+    jp = 1;
+    while (jp < E && jp * T < s_planes) jp *= 2;
+  }
+  auto kern = k_zinv_mul<N, 0>;
+  switch (jp) {
+    case 0: break;
+    case 1: kern = k_zinv_mul<N, 1>; break;
+    case 2: kern = k_zinv_mul<N, (2 < E ? 2 : E)>; break;
+    case 4: kern = k_zinv_mul<N, (4 < E ? 4 : E)>; break;
+    case 8: kern = k_zinv_mul<N, (8 < E ? 8 : E)>; break;
+    default: kern = k_zinv_mul<N, E>; break;
+  }
+  hipLaunchKernelGGL(kern, dim3(NROWS / CB, 1), dim3(CB * T), 0, s, G, Sp, s_stride, s_planes, A,
                      center, work, work_stride, zlim, tw);
   constexpr int RB = (128 / T > 0 ? 128 / T : 1);
   hipLaunchKernelGGL((k_c2c_rows<N, true>), dim3(NROWS / RB, A), dim3(RB * T), 0, s, work,
                      work_stride, zlim, tw);
-  hipLaunchKernelGGL(k_c2r_x<N>, dim3(A, N / kRowsX, N), dim3(kRowsX / 2 * T), 0, s, work, work_stride,
-                     dst, tw);
+  hipLaunchKernelGGL(k_c2r_x<N>, dim3(A * (N / kRowsX) * N), dim3(kRowsX / 2 * T), 0, s, work,
+                     work_stride, A, dst, tw);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : hip_status(e, "fft inverse launch");
 }
@@ -317,16 +392,29 @@ int fft3d_forward(int N, const RealSrc& src, int batch, cf* spec, size_t spec_st
   }
 }
 
-int fft3d_inverse_mul(int N, const cf* G, const cf* Sp, size_t s_stride, int A,
+int fft3d_forward_planes(int N, const RealSrc& src, int batch, int planes, cf* out,
+                         size_t out_stride, const cf* tw_all, hipStream_t s) {
+  const cf* tw = tw_all + twiddle_offset(N);
+  switch (N) {
+    case 32: return forward_planes_n<32>(src, batch, planes, out, out_stride, tw, s);
+    case 64: return forward_planes_n<64>(src, batch, planes, out, out_stride, tw, s);
+    case 128: return forward_planes_n<128>(src, batch, planes, out, out_stride, tw, s);
+    case 256: return forward_planes_n<256>(src, batch, planes, out, out_stride, tw, s);
+    case 512: return forward_planes_n<512>(src, batch, planes, out, out_stride, tw, s);
+    default: set_error("unsupported FFT edge %d", N); return -4;
+  }
+}
+
+int fft3d_inverse_mul(int N, const cf* G, const cf* Sp, size_t s_stride, int s_planes, int A,
                       const double* center, cf* work, size_t work_stride, const RealDst& dst,
                       const cf* tw_all, hipStream_t s) {
   const cf* tw = tw_all + twiddle_offset(N);
   switch (N) {
-    case 32: return inverse_n<32>(G, Sp, s_stride, A, center, work, work_stride, dst, tw, s);
-    case 64: return inverse_n<64>(G, Sp, s_stride, A, center, work, work_stride, dst, tw, s);
-    case 128: return inverse_n<128>(G, Sp, s_stride, A, center, work, work_stride, dst, tw, s);
-    case 256: return inverse_n<256>(G, Sp, s_stride, A, center, work, work_stride, dst, tw, s);
-    case 512: return inverse_n<512>(G, Sp, s_stride, A, center, work, work_stride, dst, tw, s);
+    case 32: return inverse_n<32>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s);
+    case 64: return inverse_n<64>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s);
+    case 128: return inverse_n<128>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s);
+    case 256: return inverse_n<256>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s);
+    case 512: return inverse_n<512>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s);
     default: set_error("unsupported FFT edge %d", N); return -4;
   }
 }

@@ -64,11 +64,20 @@ constexpr int kTwiddleTotal = 32 + 64 + 128 + 256 + 512;
 int fft3d_forward(int N, const RealSrc& src, int batch, cf* spec, size_t spec_stride,
                   const cf* tw_all, hipStream_t s);
 
+// The X and Y passes of fft3d_forward alone, for tiles whose z planes from
+// `planes` on are zero: out[b] = [z < planes][kx][ky] (out_stride complex
+// elements apart), the z transform left to fft3d_inverse_mul.
+int fft3d_forward_planes(int N, const RealSrc& src, int batch, int planes, cf* out,
+                         size_t out_stride, const cf* tw_all, hipStream_t s);
+
 // Inverse: for every a < A, spectrum_a = G * conj(S_a) (+ DC term
 // center * N^3 * Re S_a(0) when center is set) is inverse-transformed and the
 // cropped, scaled real output written through `dst` (batch index a).
+// S holds, s_stride complex elements apart, the first s_planes z planes of
+// each x/y-transformed template from fft3d_forward_planes; S_a is its z
+// transform, formed column by column inside the kernel.
 // `work` holds A spectra.  If S is null, G itself (A = 1) is inverted.
-int fft3d_inverse_mul(int N, const cf* G, const cf* S, size_t s_stride, int A,
+int fft3d_inverse_mul(int N, const cf* G, const cf* S, size_t s_stride, int s_planes, int A,
                       const double* center, cf* work, size_t work_stride, const RealDst& dst,
                       const cf* tw_all, hipStream_t s);
 

@@ -41,6 +41,10 @@ def spectrum_elems(fft_n: int) -> int:
     return load().ttm_spectrum_elems(fft_n)
 
 
+def template_spectrum_elems(fft_n: int, L: int) -> int:
+    return load().ttm_template_spectrum_elems(fft_n, L)
+
+
 def make_desc(degree: int, L_edge: int, mask_radius: float, dprime: int = 3,
               filter_a: float = 0.2, eps_w: float = 1e-6, axis=(0.0, 0.0, 1.0)) -> Desc:
     d = Desc()
@@ -92,10 +96,12 @@ def build_tensor(ctx: Context, desc: Desc, tmpl: torch.Tensor, quats: torch.Tens
 
 
 def template_spectra(ctx: Context, desc: Desc, T: torch.Tensor, fft_n: int) -> torch.Tensor:
-    """(K + 1) half spectra (last: mask), float32 view (K+1, N, N/2+1, N, 2)."""
+    """(K + 1) x/y-transformed templates (last: mask), their L nonzero z planes:
+    float32 view (K+1, L, N/2+1, N, 2); the z transform is taken per tile."""
     _need_cuda(T)
     K = n_components(desc.degree, desc.dprime)
-    out = torch.empty((K + 1, fft_n, fft_n // 2 + 1, fft_n, 2), dtype=torch.float32, device=T.device)
+    out = torch.empty((K + 1, desc.L, fft_n // 2 + 1, fft_n, 2), dtype=torch.float32,
+                      device=T.device)
     ws = _ws(desc, L.TTM_OP_SPECTRA, fft_n, device=T.device)
     call("ttm_template_spectra", ctx.h, C.byref(desc), _ptr(T), fft_n, _ptr(out), _ptr(ws),
          ws.numel(), _stream())

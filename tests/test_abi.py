@@ -41,6 +41,9 @@ def test_host_only_queries():
     assert lib.ttm_n_components(4, 4) == 35
     assert lib.ttm_n_components(3, 3) == 10 and lib.ttm_n_components(10, 3) == -1
     assert lib.ttm_spectrum_elems(256) == 256 * 129 * 256
+    assert lib.ttm_template_spectrum_elems(256, 32) == 32 * 129 * 256
+    assert lib.ttm_template_spectrum_elems(256, 257) == 0
+    assert lib.ttm_template_spectrum_elems(96, 16) == 0
     assert lib.ttm_fft_supported(256) == 1 and lib.ttm_fft_supported(96) == 0
     d = ttm.make_desc(6, 40, 17.0)
     ws = lib.ttm_workspace_size(ctypes.byref(d), L.TTM_OP_CORRELATE, 256, 512, 928, 928)
