@@ -56,12 +56,25 @@ __global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) void k_r2c_x(RealSrc src, 
   cf* xl = reinterpret_cast<cf*>(smem);
   const int tid = threadIdx.x;
   const int y0 = blockIdx.x * kRowsX, z = blockIdx.y, b = blockIdx.z;
-  for (int e = tid; e < kRowsX * N; e += NP * T) {
-    const int r = e / N, x = e % N;
-    rows[r * RS + x] = load_src(src, b, z, y0 + r, x);
+  const int p = tid / T, t = tid % T;
+  FftTw<N> twr;
+  twr.load(tw, t);
+  {
+    constexpr int NTH = NP * T, IT = kRowsX * N / NTH;
+    static_assert(kRowsX * N % NTH == 0, "tile rows");
+    float ld[IT];  // all loads in flight, then the LDS stores
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int e = tid + i * NTH;
+      ld[i] = load_src(src, b, z, y0 + e / N, e % N);
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int e = tid + i * NTH;
+      rows[(e / N) * RS + e % N] = ld[i];
+    }
   }
   __syncthreads();
-  const int p = tid / T, t = tid % T;
   cf v[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) {
@@ -69,7 +82,7 @@ __global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) void k_r2c_x(RealSrc src, 
     v[j] = cf{rows[(2 * p) * RS + n], rows[(2 * p + 1) * RS + n]};
   }
   __syncthreads();  // rows and xl share memory
-  fft_1d<N, false>(v, xl + p * S, tw, t);
+  fft_1d<N, false>(v, xl + p * S, twr, t);
 #pragma unroll
   for (int j = 0; j < E; ++j) xl[p * S + lds_idx(t + T * j)] = v[j];
   __syncthreads();
@@ -99,6 +112,8 @@ k_c2c_rows(cf* __restrict__ data, size_t batch_stride, int row_limit, const cf* 
   const int tid = threadIdx.x;
   const int r = tid / T, t = tid % T;
   const int row = blockIdx.x * RB + r;
+  FftTw<N> twr;
+  twr.load(tw, t);
   // rows are (z, kx): z = row / (N/2+1); rows with z >= row_limit are not
   // needed and may lie past the end of the buffer, so they are not touched
   if ((int)(blockIdx.x * RB) / (N / 2 + 1) >= row_limit) return;  // uniform per workgroup
@@ -107,7 +122,7 @@ k_c2c_rows(cf* __restrict__ data, size_t batch_stride, int row_limit, const cf* 
   cf v[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) v[j] = live ? base[t + T * j] : cf{0.0f, 0.0f};
-  fft_1d<N, INV>(v, xl + r * S, tw, t);
+  fft_1d<N, INV>(v, xl + r * S, twr, t);
   if (live) {
 #pragma unroll
     for (int j = 0; j < E; ++j) base[t + T * j] = v[j];
@@ -126,11 +141,13 @@ __global__ __launch_bounds__(ColBlock<N>::CB * Plan<N>::T) void k_c2c_cols(
   const int tid = threadIdx.x;
   const int c = tid % CB, t = tid / CB;
   const int col = blockIdx.x * CB + c;
+  FftTw<N> twr;
+  twr.load(tw, t);
   cf* base = data + blockIdx.y * batch_stride + col;
   cf v[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) v[j] = base[(size_t)(t + T * j) * NC];
-  fft_1d<N, INV>(v, xl + c * S, tw, t);
+  fft_1d<N, INV>(v, xl + c * S, twr, t);
 #pragma unroll
   for (int j = 0; j < E; ++j) base[(size_t)(t + T * j) * NC] = v[j];
 }
@@ -167,6 +184,8 @@ __global__ __launch_bounds__(ColBlock<N>::CB * Plan<N>::T) void k_zinv_mul(
   const int c = tid % CB, t = tid / CB;
   const unsigned col = xcd_item(blockIdx.x, gridDim.x) * CB + c;
   const unsigned off0 = ((unsigned)t * NC + col) * 8u;
+  FftTw<N> twr;
+  twr.load(tw, t);
   cf g[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) g[j] = at_byte(G, off0 + j * JSTEP);
@@ -190,14 +209,14 @@ __global__ __launch_bounds__(ColBlock<N>::CB * Plan<N>::T) void k_zinv_mul(
 #pragma unroll
       for (int j = 0; j < E; ++j) v[j] = j < JP ? q[j] : cf{0.0f, 0.0f};
       if (a + 1 < A) load_planes(a + 1);
-      fft_1d<N, false>(v, xl + c * S, tw, t);  // S_a along this column
+      fft_1d<N, false>(v, xl + c * S, twr, t);  // S_a along this column
 #pragma unroll
       for (int j = 0; j < E; ++j) v[j] = cmulc(g[j], v[j]);
     } else {
 #pragma unroll
       for (int j = 0; j < E; ++j) v[j] = g[j];
     }
-    fft_1d<N, true>(v, xl + c * S, tw, t);
+    fft_1d<N, true>(v, xl + c * S, twr, t);
     cf* o = out + (size_t)a * out_stride;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
@@ -208,7 +227,7 @@ __global__ __launch_bounds__(ColBlock<N>::CB * Plan<N>::T) void k_zinv_mul(
 
 // ---------------------------------------------------------------- X inverse
 template <int N>
-__global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) void k_c2r_x(const cf* __restrict__ spec,
+__global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) __attribute__((amdgpu_waves_per_eu(8))) void k_c2r_x(const cf* __restrict__ spec,
                                                           size_t spec_stride, int A, RealDst dst,
                                                           const cf* __restrict__ tw) {
   constexpr int T = Plan<N>::T, E = N / T, NP = kRowsX / 2, NH = N / 2 + 1;
@@ -228,13 +247,27 @@ __global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) void k_c2r_x(const cf* __r
   const int item = (int)xcd_item(blockIdx.x, gridDim.x);
   const int b = item % A, y0 = (item / A) % NYB * kRowsX, z = item / A / NYB;
   if (z >= dst.sz || y0 >= dst.sy) return;  // uniform: nothing of this block is kept
-  const cf* in = spec + b * spec_stride + (size_t)z * NH * N + y0;
-  for (int e = tid; e < NH * kRowsX; e += NP * T) {
-    const int r = e % kRowsX, kx = e / kRowsX;
-    sp[r * SPS + kx] = in[(size_t)kx * N + r];
-  }
-  __syncthreads();
   const int p = tid / T, t = tid % T;
+  constexpr int NTH = NP * T, NIN = NH * kRowsX, IT = (NIN + NTH - 1) / NTH;
+  const cf* in = spec + b * spec_stride + (size_t)z * NH * N + y0;
+  {
+    // all loads first (indices clamped, so every one is in bounds), then the
+    // LDS stores: the loads are in flight together
+    cf ld[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int e = min(tid + i * NTH, NIN - 1);
+      ld[i] = at_byte(in, (unsigned)((e / kRowsX) * N + e % kRowsX) * 8u);
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int e = tid + i * NTH;
+      if (e < NIN) sp[(e % kRowsX) * SPS + e / kRowsX] = ld[i];
+    }
+  }
+  FftTw<N> twr;  // in flight across the barrier
+  twr.load(tw, t);
+  __syncthreads();
   cf v[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) {
@@ -254,7 +287,7 @@ __global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) void k_c2r_x(const cf* __r
     v[j] = cf{a.x - bb.y, a.y + bb.x};  // A + iB
   }
   __syncthreads();
-  fft_1d<N, true>(v, xl + p * S, tw, t);
+  fft_1d<N, true>(v, xl + p * S, twr, t);
   constexpr int RS = N + 4;
 #pragma unroll
   for (int j = 0; j < E; ++j) {
@@ -265,18 +298,46 @@ __global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) void k_c2r_x(const cf* __r
   __syncthreads();
   const int nrows = min(kRowsX, dst.sy - y0);
   const int sx = dst.sx;
-  for (int e = tid; e < nrows * sx; e += NP * T) {
-    const int r = e / sx, x = e % sx;
-    float val = orow[r * RS + x] * dst.scale;
-    if (dst.w) {
-      val *= dst.w[((size_t)(dst.woz + z) * dst.wy + (dst.woy + y0 + r)) * dst.wx + dst.wox + x];
+  // row bases are the same for the whole workgroup, so each access takes a
+  // scalar base and the lane's 32-bit byte offset
+  const size_t o0 = b * dst.batch_stride +
+                    ((size_t)(dst.vz0 + z) * dst.by + (dst.vy0 + y0)) * dst.bx + dst.vx0;
+  const float* wr = dst.w ? dst.w + ((size_t)(dst.woz + z) * dst.wy + (dst.woy + y0)) * dst.wx + dst.wox
+                          : nullptr;
+  // one output column x per thread and pass, all kRowsX rows of it: the
+  // weight-map loads (row indices clamped into the crop) are in flight together
+  for (int x = tid; x < sx; x += NTH) {
+    float val[kRowsX];
+#pragma unroll
+    for (int r = 0; r < kRowsX; ++r) val[r] = orow[r * RS + x] * dst.scale;
+    if (wr) {
+      float wv[kRowsX];
+#pragma unroll
+      for (int r = 0; r < kRowsX; ++r) {
+        const float* row = wr + (size_t)min(r, nrows - 1) * dst.wx;
+        wv[r] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(row) + 4u * (unsigned)x);
+      }
+#pragma unroll
+      for (int r = 0; r < kRowsX; ++r) val[r] *= wv[r];
     }
-    const size_t o = b * dst.batch_stride +
-                     ((size_t)(dst.vz0 + z) * dst.by + (dst.vy0 + y0 + r)) * dst.bx + dst.vx0 + x;
     if (dst.dtype == 1) {
-      reinterpret_cast<unsigned short*>(dst.p)[o] = f32_to_bf16(val);
+      unsigned short* out = reinterpret_cast<unsigned short*>(dst.p) + o0;
+#pragma unroll
+      for (int r = 0; r < kRowsX; ++r) {
+        if (r < nrows) {
+          char* row = reinterpret_cast<char*>(out + (size_t)r * dst.bx);
+          *reinterpret_cast<unsigned short*>(row + 2u * (unsigned)x) = f32_to_bf16(val[r]);
+        }
+      }
     } else {
-      reinterpret_cast<float*>(dst.p)[o] = val;
+      float* out = reinterpret_cast<float*>(dst.p) + o0;
+#pragma unroll
+      for (int r = 0; r < kRowsX; ++r) {
+        if (r < nrows) {
+          char* row = reinterpret_cast<char*>(out + (size_t)r * dst.bx);
+          *reinterpret_cast<float*>(row + 4u * (unsigned)x) = val[r];
+        }
+      }
     }
   }
 }

@@ -156,22 +156,46 @@ template <int N>
 __host__ __device__ constexpr int lds_stride() { return N + N / 16 + 1; }
 __device__ __forceinline__ int lds_idx(int i) { return i + (i >> 4); }
 
-// Twiddle W_N^e (e < N) from the table tw[e] = exp(-2 pi i e / N).
-template <bool INV>
-__device__ __forceinline__ cf tw_get(const cf* __restrict__ tw, int e) {
-  cf w = tw[e];
-  return INV ? cconj(w) : w;
-}
+// Twiddles of one thread for the LDS stages of a length-N transform, held in
+// registers: stage s (radix R, span P) needs W_{P*R}^{(i mod P)*m} for its
+// butterflies i = t + T*b and m = 1..R-1, taken from the table
+// tw[e] = exp(-2 pi i e / N) as entry (i mod P)*m*N/(P*R).  Loading them at
+// kernel entry lets their latency overlap the data loads; the inverse uses
+// the conjugates of the same values.
+template <int N>
+struct FftTw {
+  using PL = Plan<N>;
+  static constexpr int T = PL::T, E = N / T;
+  static constexpr int N1 = E / PL::R1 * (PL::R1 - 1);
+  static constexpr int N2 = PL::R2 > 1 ? E / PL::R2 * (PL::R2 - 1) : 1;
+  cf w1[N1];
+  cf w2[N2];
+
+  template <int R, int P, int M>
+  __device__ __forceinline__ static void fill(cf (&w)[M], const cf* __restrict__ tw, int t) {
+    constexpr int NB = E / R, S = N / (P * R);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int k = (t + T * b) % P;
+#pragma unroll
+      for (int m = 1; m < R; ++m) w[b * (R - 1) + m - 1] = tw[k * m * S];
+    }
+  }
+  __device__ __forceinline__ void load(const cf* __restrict__ tw, int t) {
+    fill<PL::R1, PL::R0>(w1, tw, t);
+    if constexpr (PL::R2 > 1) fill<PL::R2, PL::R0 * PL::R1>(w2, tw, t);
+  }
+};
 
 // One Stockham stage from LDS to LDS (or registers for the last stage).
 // span = P (product of earlier radices).  Reads x[i + m*N/R], writes
-// x'[(i - k)*R + k + m*P] with k = i mod P.
+// x'[(i - k)*R + k + m*P] with k = i mod P.  wt: this stage's twiddles.
 template <int N, int T, int R, int P, bool LAST, bool INV>
-__device__ __forceinline__ void stage_lds(cf (&v)[N / T], cf* lds, const cf* __restrict__ tw,
-                                          int t) {
+__device__ __forceinline__ void stage_lds(cf (&v)[N / T], cf* lds, const cf* wt, int t) {
   constexpr int E = N / T;
   constexpr int NB = E / R;
   static_assert(E % R == 0, "plan: radix must divide per-thread count");
+  static_assert(P > 1, "LDS stages follow the first stage");
   cf u[E];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
@@ -185,10 +209,10 @@ __device__ __forceinline__ void stage_lds(cf (&v)[N / T], cf* lds, const cf* __r
     const int i = t + T * b;
     const int k = i % P;
     cf* w = &u[b * R];
-    if constexpr (P > 1) {
-      constexpr int S = N / (P * R);
 #pragma unroll
-      for (int m = 1; m < R; ++m) w[m] = cmul(w[m], tw_get<INV>(tw, k * m * S));
+    for (int m = 1; m < R; ++m) {
+      const cf tw = wt[b * (R - 1) + m - 1];
+      w[m] = cmul(w[m], INV ? cconj(tw) : tw);
     }
     dft<R, INV>(w);
     if constexpr (LAST) {
@@ -206,7 +230,7 @@ __device__ __forceinline__ void stage_lds(cf (&v)[N / T], cf* lds, const cf* __r
 // lds: this transform's exchange area (lds_stride<N>() elements).
 // Every thread of the workgroup must call it (it contains barriers).
 template <int N, bool INV>
-__device__ __forceinline__ void fft_1d(cf (&v)[N / Plan<N>::T], cf* lds, const cf* __restrict__ tw,
+__device__ __forceinline__ void fft_1d(cf (&v)[N / Plan<N>::T], cf* lds, const FftTw<N>& tw,
                                        int t) {
   using PL = Plan<N>;
   constexpr int T = PL::T, E = N / T, R0 = PL::R0, R1 = PL::R1, R2 = PL::R2;
@@ -225,10 +249,10 @@ __device__ __forceinline__ void fft_1d(cf (&v)[N / Plan<N>::T], cf* lds, const c
   }
   __syncthreads();
   if constexpr (R2 == 1) {
-    stage_lds<N, T, R1, R0, true, INV>(v, lds, tw, t);
+    stage_lds<N, T, R1, R0, true, INV>(v, lds, tw.w1, t);
   } else {
-    stage_lds<N, T, R1, R0, false, INV>(v, lds, tw, t);
-    stage_lds<N, T, R2, R0 * R1, true, INV>(v, lds, tw, t);
+    stage_lds<N, T, R1, R0, false, INV>(v, lds, tw.w1, t);
+    stage_lds<N, T, R2, R0 * R1, true, INV>(v, lds, tw.w2, t);
   }
 }
 
