@@ -148,7 +148,7 @@ def unpad_params(flat: np.ndarray, k_in: int, d_out: int = 3) -> dict:
 
 def orient_learned(Cv: np.ndarray, n: int, p: dict, starts: np.ndarray, kappa: float,
                    tol: float = 1e-5, max_iter: int = 500, newton: int = 2, bf16: bool = True,
-                   detail: bool = False, newton_first: int = 5):
+                   detail: bool = False, newton_first: int = 5, u0: np.ndarray | None = None):
     """Orientation with the learned start and its multistart fallback (d' = 3).
 
     From the network's direction u0, up to ``newton_first`` Riemannian Newton
@@ -162,7 +162,9 @@ def orient_learned(Cv: np.ndarray, n: int, p: dict, starts: np.ndarray, kappa: f
     far each fallback test was from flipping (beat_gap = best fixed-start value
     minus the learned lambda, kappa_gap = lambda / ||C||_F - kappa, both scaled
     by ||C||_F where they are values of the tensor) and, after a fallback, the
-    multistart's per-start lambdas and directions.
+    multistart's per-start lambdas and directions.  ``u0`` (a unit vector)
+    replaces the network's direction, to probe how the answer depends on the
+    start.
     """
     from . import ttm
     cn = float(sym.frobenius(Cv, n, 3))
@@ -170,11 +172,14 @@ def orient_learned(Cv: np.ndarray, n: int, p: dict, starts: np.ndarray, kappa: f
         out = (0.0, np.zeros(3), False)
         return out + ({"lam_learned": 0.0, "u_learned": np.zeros(3), "beat_gap": -np.inf,
                        "kappa_gap": np.inf, "lams": None, "us": None},) if detail else out
-    y, _ = forward(p, features(Cv[None, :], n), bf16=bf16)
-    y = y[0]
-    ny = np.linalg.norm(y)
+    if u0 is None:
+        y, _ = forward(p, features(Cv[None, :], n), bf16=bf16)
+        y = y[0]
+        ny = np.linalg.norm(y)
+        u0 = y / ny if ny > 0 else starts[0]
+    else:
+        ny = 1.0
     Cu = np.asarray(Cv, dtype=np.float64) / cn
-    u0 = y / ny if ny > 0 else starts[0]
     u, lam, conv = ttm.newton_ascent(Cu, n, u0, newton_first, tol)
     if not conv:
         alpha = ttm.unfolding_shift(Cu, n, 3)

@@ -14,7 +14,10 @@ Tolerances as in the small-size tests: w and the score within 1e-4 relative
 floor, plus the SS-HOPM stopping error score * tol * rate / (1 - rate) on flat
 maxima, plus the gap between nearly tied maxima; directions within 1 degree
 where the maximiser is well conditioned (SS-HOPM rate < 0.95 and a margin to
-other maxima above 1e-4 of the score).
+other maxima above 1e-4 of the score).  With the learned start, the network
+sees the GPU's FP32 field, not the oracle's FP64 one: at a voxel whose start
+sits on a basin boundary the GPU may reach another maximum, which must then be
+the answer from a start tilted by at most 1 degree (a few such voxels only).
 """
 import functools
 
@@ -89,6 +92,29 @@ def oracle_field(vol, pts, L, r, Tt):
 FFT_TILE = {"c2_256cube_n6": 256, "c3_512x928x928_n6": 512}
 
 
+def learned_alternatives(Cv, n, pl, st, kappa):
+    """(lambda, direction) of the learned path (Sec. 3.3 start, Sec. 3.1 ascent)
+    from starts tilted 0.25 and 1 degree around the network's direction.  The
+    GPU evaluates the network on its own FP32 field, whose rounding can move
+    the start by about that much; where such a tilt crosses into another basin,
+    each of these answers is one the method may give."""
+    y, _ = omlp.forward(pl, omlp.features(Cv[None, :], n), bf16=True)
+    u0 = y[0] / np.linalg.norm(y[0])
+    a = np.cross(u0, [1.0, 0.0, 0.0])
+    if np.linalg.norm(a) < 0.5:
+        a = np.cross(u0, [0.0, 1.0, 0.0])
+    a /= np.linalg.norm(a)
+    b = np.cross(u0, a)
+    out = []
+    for deg in (0.25, 1.0):
+        r = np.radians(deg)
+        for k in range(6):
+            ax = np.cos(np.pi * k / 3) * a + np.sin(np.pi * k / 3) * b
+            lam, u, _ = omlp.orient_learned(Cv, n, pl, st, kappa, u0=np.cos(r) * u0 + np.sin(r) * ax)
+            out.append((lam, u))
+    return out
+
+
 @pytest.mark.parametrize("name", ["c2_256cube_n6", "c3_512x928x928_n6"])
 @pytest.mark.parametrize("start", ["multistart", "learned"])
 def test_full_size_sampled_parity(T, ctx, name, start):
@@ -124,7 +150,7 @@ def test_full_size_sampled_parity(T, ctx, name, start):
     assert np.max(np.abs(wg - wo) / wo) < 1e-4
     assert np.max(np.abs(sg - so) / floor) < 1e-4
     st = starts.astype(np.float64)
-    checked = 0
+    checked = ambiguous = 0
     for i in range(len(pts)):
         if start == "multistart":
             lam_o, u_o, lams, us, _ = orc.orient_multistart(Co[i], n, st)
@@ -145,12 +171,26 @@ def test_full_size_sampled_parity(T, ctx, name, start):
         rate = orc.sshopm_rate(Co[i], n, u_o)
         stop = so[i] * 1e-5 * rate / (1.0 - rate) if rate < 1.0 else np.inf
         tie = margin if margin <= 1e-4 * so[i] else 0.0
+        if start == "learned" and abs(lg[i] - lam_o) > 1e-4 * floor[i] + stop + tie:
+            # the learned start lies within rounding of a basin boundary: the
+            # GPU's answer must be one that a start that close reaches
+            alts = learned_alternatives(Co[i], n, pl, st, kappa)
+            hit = False
+            for lam_a, u_a in alts:
+                ra = orc.sshopm_rate(Co[i], n, u_a)
+                sa = so[i] * 1e-5 * ra / (1.0 - ra) if ra < 1.0 else np.inf
+                hit |= abs(lg[i] - lam_a) <= 1e-4 * floor[i] + sa
+            assert hit, (i, pts[i], lg[i], lam_o, [a for a, _ in alts])
+            ambiguous += 1
+            continue
         assert abs(lg[i] - lam_o) <= 1e-4 * floor[i] + stop + tie, (i, pts[i], rate)
         if margin > 1e-4 * so[i] and rate < 0.95:
             assert orc.angle_deg(ug[i], u_o) < 1.0, (i, pts[i])
             checked += 1
-    say(f"[fullsize {name} {start}] orientation checked at {checked} of {len(pts)} voxels")
+    say(f"[fullsize {name} {start}] orientation checked at {checked} of {len(pts)} voxels, "
+        f"{ambiguous} at a basin boundary")
     assert checked >= len(pts) // 5
+    assert ambiguous <= max(2, len(pts) // 20)
     # Find Peaks (Sec. 3.4) on the GPU's own score map, checked by the property
     # that defines the greedy result: peak k holds the largest score among the
     # valid voxels farther than 2r from peaks 0..k-1 (ties: smallest index)
