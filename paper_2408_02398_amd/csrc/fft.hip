@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) void k_r2c_x(RealSrc src, 
     v[j] = cf{rows[(2 * p) * RS + n], rows[(2 * p + 1) * RS + n]};
   }
   __syncthreads();  // rows and xl share memory
-  fft_1d<N, false>(v, xl + p * S, twr, t);
+  fft_1d<N, false, true>(v, xl + p * S, twr, t);  // each pair's transform lies in one wavefront
 #pragma unroll
   for (int j = 0; j < E; ++j) xl[p * S + lds_idx(t + T * j)] = v[j];
   __syncthreads();
@@ -122,7 +122,7 @@ k_c2c_rows(cf* __restrict__ data, size_t batch_stride, int row_limit, const cf* 
   cf v[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) v[j] = live ? base[t + T * j] : cf{0.0f, 0.0f};
-  fft_1d<N, INV>(v, xl + r * S, twr, t);
+  fft_1d<N, INV, true>(v, xl + r * S, twr, t);  // each row's transform lies in one wavefront
   if (live) {
 #pragma unroll
     for (int j = 0; j < E; ++j) base[t + T * j] = v[j];
@@ -136,7 +136,7 @@ template <int N, bool INV>
 __global__ __launch_bounds__(ColBlock<N>::CB * Plan<N>::T) void k_c2c_cols(
     cf* __restrict__ data, size_t batch_stride, const cf* __restrict__ tw) {
   constexpr int T = Plan<N>::T, E = N / T, CB = ColBlock<N>::CB, NC = (N / 2 + 1) * N;
-  constexpr int S = lds_stride<N>();
+  constexpr int S = lds_stride_cols<N>();
   __shared__ cf xl[CB * S];
   const int tid = threadIdx.x;
   const int c = tid % CB, t = tid / CB;
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(ColBlock<N>::CB * Plan<N>::T) void k_zinv_mul(
     const double* __restrict__ center, cf* __restrict__ out, size_t out_stride, int z_limit,
     const cf* __restrict__ tw) {
   constexpr int T = Plan<N>::T, E = N / T, CB = ColBlock<N>::CB, NC = (N / 2 + 1) * N;
-  constexpr int S = lds_stride<N>();
+  constexpr int S = lds_stride_cols<N>();
   // byte offsets inside one [z][kx][ky] spectrum stay below 2^32 for N <= 512
   constexpr unsigned JSTEP = (unsigned)T * NC * 8u;
   static_assert((unsigned long long)N * NC * 8ull < (1ull << 32), "32-bit offsets");
@@ -287,7 +287,8 @@ __global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) __attribute__((amdgpu_wave
     v[j] = cf{a.x - bb.y, a.y + bb.x};  // A + iB
   }
   __syncthreads();
-  fft_1d<N, true>(v, xl + p * S, twr, t);
+  fft_1d<N, true, true>(v, xl + p * S, twr, t);  // each pair's transform lies in one wavefront
+  __syncthreads();  // the row buffer overlaps other pairs' exchange areas
   constexpr int RS = N + 4;
 #pragma unroll
   for (int j = 0; j < E; ++j) {

@@ -149,11 +149,22 @@ template <> struct Plan<128> { static constexpr int T = 8, R0 = 8, R1 = 16, R2 =
 template <> struct Plan<256> { static constexpr int T = 16, R0 = 16, R1 = 16, R2 = 1; };
 template <> struct Plan<512> { static constexpr int T = 64, R0 = 8, R1 = 8, R2 = 8; };
 
-// LDS footprint (complex elements) of one transform's exchange area: one
-// padding element per 16 keeps stride-16 exchanges conflict-free and one more
-// per transform separates transforms that share a wavefront.
+// LDS footprint (complex elements) of one transform's exchange area.  Inside
+// an area one padding element per 16 keeps stride-16 exchanges conflict-free.
+// The areas of the transforms that share a wavefront are set apart by a
+// stride chosen per edge and thread mapping (64 banks of 4 bytes, b64
+// accesses): with one transform per T consecutive threads (rows) and with
+// the transforms interleaved across consecutive threads (columns, thread
+// c + CB*t), every exchange of the plan then touches each bank at most twice,
+// the least a 64-lane b64 access can.
 template <int N>
-__host__ __device__ constexpr int lds_stride() { return N + N / 16 + 1; }
+__host__ __device__ constexpr int lds_stride() {
+  return N == 64 ? 76 : N == 128 ? 140 : N == 256 ? 280 : N + N / 16 + 1;
+}
+template <int N>
+__host__ __device__ constexpr int lds_stride_cols() {
+  return N == 64 ? 70 : N == 128 ? 138 : N == 256 ? 274 : N == 512 ? 548 : N + N / 16 + 1;
+}
 __device__ __forceinline__ int lds_idx(int i) { return i + (i >> 4); }
 
 // Twiddles of one thread for the LDS stages of a length-N transform, held in
@@ -187,10 +198,24 @@ struct FftTw {
   }
 };
 
+// Exchange barrier of a transform: the whole workgroup, or (WAVE) only the
+// wavefront, when every transform's T threads lie inside one wavefront and no
+// other wavefront touches its LDS area.  LDS accesses of one wavefront
+// complete in order; the fence keeps the compiler from moving them across.
+template <bool WAVE>
+__device__ __forceinline__ void fft_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
+
 // One Stockham stage from LDS to LDS (or registers for the last stage).
 // span = P (product of earlier radices).  Reads x[i + m*N/R], writes
 // x'[(i - k)*R + k + m*P] with k = i mod P.  wt: this stage's twiddles.
-template <int N, int T, int R, int P, bool LAST, bool INV>
+template <int N, int T, int R, int P, bool LAST, bool INV, bool WAVE>
 __device__ __forceinline__ void stage_lds(cf (&v)[N / T], cf* lds, const cf* wt, int t) {
   constexpr int E = N / T;
   constexpr int NB = E / R;
@@ -203,7 +228,7 @@ __device__ __forceinline__ void stage_lds(cf (&v)[N / T], cf* lds, const cf* wt,
 #pragma unroll
     for (int m = 0; m < R; ++m) u[b * R + m] = lds[lds_idx(i + m * (N / R))];
   }
-  __syncthreads();
+  fft_sync<WAVE>();
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int i = t + T * b;
@@ -223,13 +248,13 @@ __device__ __forceinline__ void stage_lds(cf (&v)[N / T], cf* lds, const cf* wt,
       for (int m = 0; m < R; ++m) lds[lds_idx((i - k) * R + k + m * P)] = w[m];
     }
   }
-  if constexpr (!LAST) __syncthreads();
+  if constexpr (!LAST) fft_sync<WAVE>();
 }
 
 // Full transform.  On entry v[j] = x[t + T*j]; on exit v[j] = X[t + T*j].
 // lds: this transform's exchange area (lds_stride<N>() elements).
-// Every thread of the workgroup must call it (it contains barriers).
-template <int N, bool INV>
+// Every thread of the workgroup (WAVE: of the wavefront) must call it.
+template <int N, bool INV, bool WAVE = false>
 __device__ __forceinline__ void fft_1d(cf (&v)[N / Plan<N>::T], cf* lds, const FftTw<N>& tw,
                                        int t) {
   using PL = Plan<N>;
@@ -247,12 +272,12 @@ __device__ __forceinline__ void fft_1d(cf (&v)[N / Plan<N>::T], cf* lds, const F
 #pragma unroll
     for (int m = 0; m < R0; ++m) lds[lds_idx(i * R0 + m)] = w[m];
   }
-  __syncthreads();
+  fft_sync<WAVE>();
   if constexpr (R2 == 1) {
-    stage_lds<N, T, R1, R0, true, INV>(v, lds, tw.w1, t);
+    stage_lds<N, T, R1, R0, true, INV, WAVE>(v, lds, tw.w1, t);
   } else {
-    stage_lds<N, T, R1, R0, false, INV>(v, lds, tw.w1, t);
-    stage_lds<N, T, R2, R0 * R1, true, INV>(v, lds, tw.w2, t);
+    stage_lds<N, T, R1, R0, false, INV, WAVE>(v, lds, tw.w1, t);
+    stage_lds<N, T, R2, R0 * R1, true, INV, WAVE>(v, lds, tw.w2, t);
   }
 }
 
