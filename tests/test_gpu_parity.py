@@ -67,6 +67,29 @@ def test_fft_small_direct_dft(T, ctx):
     assert np.linalg.norm(got - want) / np.linalg.norm(want) < 2e-6
 
 
+@pytest.mark.parametrize("N,L", [(32, 16), (64, 23), (256, 40)])
+def test_template_planes_match_dft(T, ctx, N, L):
+    """Template arrays of ttm_template_spectra: the K fields and the mask placed at
+    the origin of a zero N^3 tile, transformed along x (half spectrum) and y, their
+    L nonzero z planes kept, layout [z][kx][ky] (the z transform is left to the
+    correlation, Alg. 2)."""
+    print(f"[template planes N={N} L={L}]", flush=True)
+    r = 0.4 * L
+    d = T.make_desc(2, L, r)
+    K = 6
+    Tf = np.random.default_rng(N + L).standard_normal((K, L, L, L)).astype(np.float32)
+    spec = host(T.template_spectra(ctx, d, cuda(Tf.reshape(K, -1)), N))
+    assert spec.shape == (K + 1, L, N // 2 + 1, N, 2)
+    assert T.template_spectrum_elems(N, L) == L * (N // 2 + 1) * N
+    got = spec[..., 0] + 1j * spec[..., 1]
+    fields = np.concatenate([Tf.astype(np.float64), orc.ball_mask(L, r)[None].astype(np.float64)])
+    pad = np.zeros((K + 1, L, N, N))
+    pad[:, :, :L, :L] = fields
+    want = np.fft.fft(np.fft.rfft(pad, axis=3), axis=2).transpose(0, 1, 3, 2)   # [a][z][kx][ky]
+    for a in range(K + 1):
+        assert np.linalg.norm(got[a] - want[a]) / np.linalg.norm(want[a]) < 2e-6, a
+
+
 @pytest.mark.parametrize("N", [32, 64, 256])
 def test_fft_roundtrip(T, ctx, N):
     x = np.random.default_rng(N + 1).standard_normal((N, N, N)).astype(np.float32)
