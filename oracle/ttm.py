@@ -358,14 +358,17 @@ def newton_polish(Cu: np.ndarray, n: int, u: np.ndarray, steps: int = 2,
 
 
 def newton_ascent(Cu: np.ndarray, n: int, u0: np.ndarray, steps: int, tol: float,
-                  drop: float = 1e-7):
+                  drop: float = 1e-6, halvings: int = 2):
     """Riemannian Newton iterations for max <C, u^{(x)n}> on the unit sphere (d' = 3).
 
     From u0, each step needs the tangent Hessian (n-1) E^T H E - lambda I to be
-    negative definite and may not lower lambda by more than ``drop``; the
-    iteration has converged after a step that changes lambda by at most
-    ``tol``.  Returns (u, lambda, converged); when it fails or runs out of
-    steps, converged is False.
+    negative definite.  A step that lowers lambda by more than ``drop`` (for
+    C / ||C||_F, lambda <= 1; the default sits a few FP32 ulps above rounding,
+    so an FP32 implementation takes the same decisions) is halved, at most
+    ``halvings`` times, and the search fails if it still does.  The iteration
+    has converged after a full step that changes lambda by at most ``tol``.
+    Returns (u, lambda, converged); when it fails or runs out of steps,
+    converged is False.
     """
     u = np.asarray(u0, dtype=np.float64)
     u = u / np.linalg.norm(u)
@@ -376,13 +379,19 @@ def newton_ascent(Cu: np.ndarray, n: int, u0: np.ndarray, steps: int, tol: float
         Ht = (n - 1) * (E.T @ sym.contract_n_minus_2(Cu, u, n) @ E) - lam * np.eye(2)
         if not (np.linalg.det(Ht) > 0 and np.trace(Ht) < 0):
             return u, lam, False
-        un = u + E @ (-np.linalg.solve(Ht, E.T @ g))
-        un = un / np.linalg.norm(un)
-        gn = sym.contract_n_minus_1(Cu, un, n)
-        ln = float(gn @ un)
-        if ln < lam - drop:
+        d = E @ (-np.linalg.solve(Ht, E.T @ g))
+        t = 1.0
+        for _h in range(halvings + 1):
+            un = u + t * d
+            un = un / np.linalg.norm(un)
+            gn = sym.contract_n_minus_1(Cu, un, n)
+            ln = float(gn @ un)
+            if ln >= lam - drop:
+                break
+            t *= 0.5
+        else:
             return u, lam, False
-        done = abs(ln - lam) <= tol
+        done = t == 1.0 and abs(ln - lam) <= tol
         u, g, lam = un, gn, ln
         if done:
             return u, lam, True

@@ -24,7 +24,7 @@
 //     k_mlp_start  persistent wavefronts with the network in registers: the
 //                BF16 MLP on the matrix cores gives each voxel's start u0
 //     k_learned  one lane per voxel: at most kNewtonFirst Riemannian Newton steps
-//                (no shift needed); converged voxels are screened and
+//                (halved when lambda falls; no shift needed); converged voxels are screened and
 //                written.  The others run SS-HOPM from u0 in k_runs (queue of
 //                saved iterates, shift from k_prepare), then k_learned_post
 //                polishes, screens and writes them.  Voxels that fail the
@@ -166,17 +166,15 @@ __device__ __forceinline__ void contract2(const float (&c)[ncomp3(N)], float x, 
   }
 }
 
-// One Riemannian Newton step for max <C, u^n> on the sphere from u, where
+// Riemannian Newton direction for max <C, u^n> on the unit sphere at u with
 // (g, lambda) = (C u^{n-1}, <C, u^n>): tangent basis e1 = a x u/|a x u| (a =
 // axis of the smallest |u_i|), e2 = u x e1; the tangent Hessian
-// (n-1) E^T H E - lambda I (H = C u^{n-2}) must be negative definite, else the
-// step is refused (false).  Otherwise v = retraction of u + E eta with
-// eta = -Hess^{-1} E^T g, and (q, lambda_v) its gradient and value.
+// (n-1) E^T H E - lambda I (H = C u^{n-2}) must be negative definite, else
+// there is no step (false).  Otherwise d = E eta with eta = -Hess^{-1} E^T g.
 template <int N>
-__device__ __forceinline__ bool newton_step(const float (&c)[ncomp3(N)], float ux, float uy,
-                                            float uz, float g0, float g1, float g2, float lam,
-                                            float& vx, float& vy, float& vz, float& q0, float& q1,
-                                            float& q2, float& lam_v) {
+__device__ __forceinline__ bool newton_dir(const float (&c)[ncomp3(N)], float ux, float uy,
+                                           float uz, float g0, float g1, float g2, float lam,
+                                           float& dx, float& dy, float& dz) {
   const float fx = fabsf(ux), fy = fabsf(uy), fz = fabsf(uz);
   float e1x, e1y, e1z;
   if (fx <= fy && fx <= fz) {        // a = e_x: a x u = (0, -uz, uy)
@@ -207,13 +205,36 @@ __device__ __forceinline__ bool newton_step(const float (&c)[ncomp3(N)], float u
   const float inv = 1.0f / det;
   const float eta0 = -(a11 * t0 - a01 * t1) * inv;
   const float eta1 = -(a00 * t1 - a01 * t0) * inv;
-  vx = ux + eta0 * e1x + eta1 * e2x;
-  vy = uy + eta0 * e1y + eta1 * e2y;
-  vz = uz + eta0 * e1z + eta1 * e2z;
+  dx = eta0 * e1x + eta1 * e2x;
+  dy = eta0 * e1y + eta1 * e2y;
+  dz = eta0 * e1z + eta1 * e2z;
+  return true;
+}
+
+// v = (u + t d) / |u + t d| and (q, lambda_v) = (C v^{n-1}, <C, v^n>).
+template <int N>
+__device__ __forceinline__ void newton_move(const float (&c)[ncomp3(N)], float ux, float uy,
+                                            float uz, float dx, float dy, float dz, float t,
+                                            float& vx, float& vy, float& vz, float& q0, float& q1,
+                                            float& q2, float& lam_v) {
+  vx = ux + t * dx;
+  vy = uy + t * dy;
+  vz = uz + t * dz;
   const float rv = 1.0f / sqrtf(vx * vx + vy * vy + vz * vz);
   vx *= rv; vy *= rv; vz *= rv;
   contract<N>(c, vx, vy, vz, q0, q1, q2);
   lam_v = q0 * vx + q1 * vy + q2 * vz;
+}
+
+// One full Newton step (false if the tangent Hessian is not negative definite).
+template <int N>
+__device__ __forceinline__ bool newton_step(const float (&c)[ncomp3(N)], float ux, float uy,
+                                            float uz, float g0, float g1, float g2, float lam,
+                                            float& vx, float& vy, float& vz, float& q0, float& q1,
+                                            float& q2, float& lam_v) {
+  float dx, dy, dz;
+  if (!newton_dir<N>(c, ux, uy, uz, g0, g1, g2, lam, dx, dy, dz)) return false;
+  newton_move<N>(c, ux, uy, uz, dx, dy, dz, 1.0f, vx, vy, vz, q0, q1, q2, lam_v);
   return true;
 }
 
@@ -237,9 +258,15 @@ __device__ __forceinline__ int newton_polish(const float (&c)[ncomp3(N)], float&
   return taken;
 }
 
-// Newton iteration from a start: up to `steps` steps, each refused when the
-// tangent Hessian is not negative definite or lambda drops by more than 1e-7;
-// converged (ok) after a step that changes lambda by at most tol.
+// Newton iteration from a start: up to `steps` steps.  A step whose lambda
+// falls by more than 1e-6 (lambda <= 1 for C / ||C||_F; a few FP32 ulps, so
+// rounding near convergence is not taken for a fall) is halved, at most
+// kHalvings times; the search stops without convergence when the tangent
+// Hessian is not negative definite or the halved steps still fall.  Converged
+// (ok) after a full step that changes lambda by at most tol.  Returns the
+// Newton directions computed.
+constexpr int kHalvings = 2;
+
 template <int N>
 __device__ __forceinline__ int newton_ascent(const float (&c)[ncomp3(N)], float& ux, float& uy,
                                              float& uz, float& g0, float& g1, float& g2,
@@ -247,11 +274,22 @@ __device__ __forceinline__ int newton_ascent(const float (&c)[ncomp3(N)], float&
   int taken = 0;
   ok = false;
   for (int s = 0; s < steps; ++s) {
-    float vx, vy, vz, q0, q1, q2, lam_new;
-    if (!newton_step<N>(c, ux, uy, uz, g0, g1, g2, lam, vx, vy, vz, q0, q1, q2, lam_new)) break;
+    float dx, dy, dz;
+    if (!newton_dir<N>(c, ux, uy, uz, g0, g1, g2, lam, dx, dy, dz)) break;
     ++taken;
-    if (lam_new < lam - 1e-7f) break;
-    const bool done = fabsf(lam_new - lam) <= tol;
+    float vx, vy, vz, q0, q1, q2, lam_new;
+    float t = 1.0f;
+    bool up = false;
+    for (int h = 0; h <= kHalvings; ++h) {
+      newton_move<N>(c, ux, uy, uz, dx, dy, dz, t, vx, vy, vz, q0, q1, q2, lam_new);
+      if (lam_new >= lam - 1e-6f) {
+        up = true;
+        break;
+      }
+      t *= 0.5f;
+    }
+    if (!up) break;
+    const bool done = t == 1.0f && fabsf(lam_new - lam) <= tol;
     ux = vx; uy = vy; uz = vz;
     g0 = q0; g1 = q1; g2 = q2;
     lam = lam_new;

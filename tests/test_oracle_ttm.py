@@ -492,3 +492,40 @@ def test_newton_ascent_from_near_starts_matches_sshopm_with_polish():
             assert np.linalg.norm(g - (g @ u) * u) < 3e-5
             agree += ttm.angle_deg(u, u_s) < 0.05
     assert total >= 55 and agree == total
+
+
+def test_newton_ascent_halves_steps_that_fall():
+    """A Newton step that lowers lambda is halved (at most twice) instead of
+    ending the search.  Where the full-step search succeeds both take the same
+    steps; where only the halving search succeeds, its answer is checked by
+    plain evaluation: lambda rose from the start, and no point 0.5 or 2 degrees
+    around the answer has a larger value (a local maximum of <C, u^n>)."""
+    rng = np.random.default_rng(45)
+    n = 6
+    rescued = 0
+    for _ in range(600):
+        v = rng.standard_normal(3)
+        v /= np.linalg.norm(v)
+        C = sym.monomials(v, n) + 0.5 * rng.standard_normal(28)
+        Cu = C / ttm.score(C, n)
+        w = np.cross(v, rng.standard_normal(3))
+        u0 = np.cos(np.radians(25.0)) * v + np.sin(np.radians(25.0)) * w / np.linalg.norm(w)
+        u_f, lam_f, ok_f = ttm.newton_ascent(Cu, n, u0, 5, 1e-5, halvings=0)
+        u_h, lam_h, ok_h = ttm.newton_ascent(Cu, n, u0, 5, 1e-5)
+        if ok_f:
+            assert ok_h and np.array_equal(u_f, u_h) and lam_f == lam_h
+            continue
+        if not ok_h:
+            continue
+        rescued += 1
+        assert lam_h >= sym.inner_power(Cu, u0, n) - 5e-6
+        assert lam_h == pytest.approx(sym.inner_power(Cu, u_h, n), abs=1e-12)
+        e1 = np.cross(u_h, rng.standard_normal(3))
+        e1 /= np.linalg.norm(e1)
+        e2 = np.cross(u_h, e1)
+        for deg in (0.5, 2.0):
+            for k in range(64):
+                ph = 2 * np.pi * k / 64
+                p = np.cos(np.radians(deg)) * u_h + np.sin(np.radians(deg)) * (np.cos(ph) * e1 + np.sin(ph) * e2)
+                assert sym.inner_power(Cu, p, n) <= lam_h + 1e-9
+    assert rescued >= 5
