@@ -165,62 +165,89 @@ __device__ __forceinline__ cf& at_byte(cf* base, unsigned off) {
 // Inverse Z pass with the spectral product: out_a = Z^-1( G conj(S_a) ).
 // P holds only the sp nonzero z planes of each template after its X and Y
 // passes; each column of S_a is their z transform, formed here in registers,
-// which reads sp/N of the bytes a stored S_a would cost.  Plane z of a column
-// sits in slot z / T of thread z mod T, and JP >= ceil(sp / T) slots are
-// kept (JP = 0: no template, G itself is inverted).  The planes of component
-// a + 1 load while component a is transformed.
+// which reads sp/N of the bytes a stored S_a would cost.  JP >= ceil(sp / T)
+// plane slots per thread are kept (JP = 0: no template, G itself is
+// inverted).  Each column's transforms run on T consecutive threads, inside
+// one wavefront, so their exchanges need no workgroup barrier; global
+// accesses go through LDS in the other order (column fastest), so that a
+// wavefront reads and writes CB neighbouring columns of a z row together.
+// Two workgroup barriers per component: after its planes are staged, and
+// after its transformed columns are.  The planes of component a + 1 load
+// while component a is transformed.
 template <int N, int JP>
 __global__ __launch_bounds__(ColBlock<N>::CB * Plan<N>::T) void k_zinv_mul(
     const cf* __restrict__ G, const cf* __restrict__ P, size_t p_stride, int sp, int A,
     const double* __restrict__ center, cf* __restrict__ out, size_t out_stride, int z_limit,
     const cf* __restrict__ tw) {
   constexpr int T = Plan<N>::T, E = N / T, CB = ColBlock<N>::CB, NC = (N / 2 + 1) * N;
-  constexpr int S = lds_stride_cols<N>();
+  constexpr int S = lds_stride<N>();
+  constexpr int SB = CB + 1;                // staging row: CB columns, one pad element
+  constexpr int ZP = JP > 0 ? JP * T : 1;   // staged template planes
   // byte offsets inside one [z][kx][ky] spectrum stay below 2^32 for N <= 512
-  constexpr unsigned JSTEP = (unsigned)T * NC * 8u;
+  constexpr unsigned ZSTEP = (unsigned)T * NC * 8u;
   static_assert((unsigned long long)N * NC * 8ull < (1ull << 32), "32-bit offsets");
   __shared__ cf xl[CB * S];
+  __shared__ cf sb[N * SB];
+  __shared__ cf pb[ZP * SB];
   const int tid = threadIdx.x;
-  const int c = tid % CB, t = tid / CB;
-  const unsigned col = xcd_item(blockIdx.x, gridDim.x) * CB + c;
-  const unsigned off0 = ((unsigned)t * NC + col) * 8u;
+  const int c = tid / T, t = tid % T;       // transforms: column c, element t + T j
+  const int cc = tid % CB, tt = tid / CB;   // global accesses: column cc, z = tt + T k
+  const unsigned col0 = xcd_item(blockIdx.x, gridDim.x) * CB;
+  const unsigned offc = ((unsigned)tt * NC + col0 + cc) * 8u;
   FftTw<N> twr;
   twr.load(tw, t);
-  cf g[E];
+  {
+    cf gl[E];
 #pragma unroll
-  for (int j = 0; j < E; ++j) g[j] = at_byte(G, off0 + j * JSTEP);
-  // DC bin (kz = kx = ky = 0) is element j = 0 of thread t = 0 in column 0:
-  // restore the mean removed before the forward transform.
-  if (JP > 0 && center && col == 0 && t == 0) {
-    g[0].x += (float)(center[0] * (double)N * (double)N * (double)N);
+    for (int k = 0; k < E; ++k) gl[k] = at_byte(G, offc + k * ZSTEP);
+#pragma unroll
+    for (int k = 0; k < E; ++k) sb[(tt + T * k) * SB + cc] = gl[k];
   }
-  cf q[JP > 0 ? JP : 1];  // z planes of the next component
+  cf qn[JP > 0 ? JP : 1];  // planes of the next component, global-access order
   auto load_planes = [&](int a) {
     const cf* pa = P + (size_t)a * p_stride;
 #pragma unroll
-    for (int j = 0; j < JP; ++j) {
-      q[j] = t + T * j < sp ? at_byte(pa, off0 + j * JSTEP) : cf{0.0f, 0.0f};
+    for (int k = 0; k < JP; ++k) {
+      qn[k] = tt + T * k < sp ? at_byte(pa, offc + k * ZSTEP) : cf{0.0f, 0.0f};
     }
   };
   if constexpr (JP > 0) load_planes(0);
+  __syncthreads();
+  cf g[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) g[j] = sb[(t + T * j) * SB + c];
+  // DC bin (kz = kx = ky = 0) is element j = 0 of thread t = 0 in column 0:
+  // restore the mean removed before the forward transform.
+  if (JP > 0 && center && col0 + c == 0 && t == 0) {
+    g[0].x += (float)(center[0] * (double)N * (double)N * (double)N);
+  }
   for (int a = 0; a < A; ++a) {
     cf v[E];
     if constexpr (JP > 0) {
 #pragma unroll
-      for (int j = 0; j < E; ++j) v[j] = j < JP ? q[j] : cf{0.0f, 0.0f};
+      for (int k = 0; k < JP; ++k) pb[(tt + T * k) * SB + cc] = qn[k];
+      __syncthreads();  // planes staged; the previous component's columns are stored
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = j < JP ? pb[(t + T * j) * SB + c] : cf{0.0f, 0.0f};
       if (a + 1 < A) load_planes(a + 1);
-      fft_1d<N, false>(v, xl + c * S, twr, t);  // S_a along this column
+      fft_1d<N, false, true>(v, xl + c * S, twr, t);  // S_a along this column
 #pragma unroll
       for (int j = 0; j < E; ++j) v[j] = cmulc(g[j], v[j]);
     } else {
 #pragma unroll
       for (int j = 0; j < E; ++j) v[j] = g[j];
+      __syncthreads();  // the previous component's columns are stored
     }
-    fft_1d<N, true>(v, xl + c * S, twr, t);
-    cf* o = out + (size_t)a * out_stride;
+    fft_1d<N, true, true>(v, xl + c * S, twr, t);
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      if (t + T * j < z_limit) at_byte(o, off0 + j * JSTEP) = v[j];
+      if (t + T * j < z_limit) sb[(t + T * j) * SB + c] = v[j];
+    }
+    __syncthreads();  // columns staged
+    cf* o = out + (size_t)a * out_stride;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      if (tt + T * k < z_limit) at_byte(o, offc + k * ZSTEP) = sb[(tt + T * k) * SB + cc];
     }
   }
 }
@@ -396,10 +423,12 @@ int inverse_n(const cf* G, const cf* Sp, size_t s_stride, int s_planes, int A, c
   constexpr int CB = ColBlock<N>::CB;
   const int zlim = dst.sz;
   constexpr int E = N / T;
-  // template slots per thread: the next power of two >= ceil(s_planes / T)
+  // template slots per thread: the next power of two >= ceil(s_planes / T),
+  // and at least 2 at N = 512, whose one-slot variant the compiler keeps in
+  // more registers (137 against 123: one workgroup per CU instead of two)
   int jp = 0;
   if (Sp) {
-    jp = 1;
+    jp = N == 512 ? 2 : 1;
     while (jp < E && jp * T < s_planes) jp *= 2;
   }
   auto kern = k_zinv_mul<N, 0>;
