@@ -130,7 +130,10 @@ k_c2c_rows(cf* __restrict__ data, size_t batch_stride, int row_limit, const cf* 
 }
 
 // ---------------------------------------------------------------- Z (columns)
-template <int N> struct ColBlock { static constexpr int CB = (N >= 512 ? 8 : 16); };
+template <int N> struct ColBlock { static constexpr int CB = 16; };
+// Columns per Z-inverse workgroup: 16 (128-byte row segments), 8 at N = 512
+// with more than 2 plane slots, where 16 would not fit the LDS.
+template <int N, int JP> struct ZinvBlock { static constexpr int CB = (N >= 512 && JP > 2) ? 8 : 16; };
 
 template <int N, bool INV>
 __global__ __launch_bounds__(ColBlock<N>::CB * Plan<N>::T) void k_c2c_cols(
@@ -175,11 +178,11 @@ __device__ __forceinline__ cf& at_byte(cf* base, unsigned off) {
 // after its transformed columns are.  The planes of component a + 1 load
 // while component a is transformed.
 template <int N, int JP>
-__global__ __launch_bounds__(ColBlock<N>::CB * Plan<N>::T) void k_zinv_mul(
+__global__ __launch_bounds__((ZinvBlock<N, JP>::CB * Plan<N>::T)) void k_zinv_mul(
     const cf* __restrict__ G, const cf* __restrict__ P, size_t p_stride, int sp, int A,
     const double* __restrict__ center, cf* __restrict__ out, size_t out_stride, int z_limit,
     const cf* __restrict__ tw) {
-  constexpr int T = Plan<N>::T, E = N / T, CB = ColBlock<N>::CB, NC = (N / 2 + 1) * N;
+  constexpr int T = Plan<N>::T, E = N / T, CB = ZinvBlock<N, JP>::CB, NC = (N / 2 + 1) * N;
   constexpr int S = lds_stride<N>();
   constexpr int SB = CB + 1;                // staging row: CB columns, one pad element
   constexpr int ZP = JP > 0 ? JP * T : 1;   // staged template planes
@@ -420,28 +423,29 @@ int inverse_n(const cf* G, const cf* Sp, size_t s_stride, int s_planes, int A, c
               cf* work, size_t work_stride, const RealDst& dst, const cf* tw, hipStream_t s) {
   constexpr int T = Plan<N>::T;
   constexpr int NROWS = N * (N / 2 + 1);
-  constexpr int CB = ColBlock<N>::CB;
   const int zlim = dst.sz;
   constexpr int E = N / T;
   // template slots per thread: the next power of two >= ceil(s_planes / T),
   // and at least 2 at N = 512, whose one-slot variant the compiler keeps in
-  // more registers (137 against 123: one workgroup per CU instead of two)
+  // more registers (137 against 123)
   int jp = 0;
   if (Sp) {
     jp = N == 512 ? 2 : 1;
     while (jp < E && jp * T < s_planes) jp *= 2;
   }
-  auto kern = k_zinv_mul<N, 0>;
+  auto launch = [&](auto kern, int cb) {
+    hipLaunchKernelGGL(kern, dim3(NROWS / cb, 1), dim3(cb * T), 0, s, G, Sp, s_stride, s_planes, A,
+                       center, work, work_stride, zlim, tw);
+  };
+  constexpr int J2 = 2 < E ? 2 : E, J4 = 4 < E ? 4 : E, J8 = 8 < E ? 8 : E;
   switch (jp) {
-    case 0: break;
-    case 1: kern = k_zinv_mul<N, 1>; break;
-    case 2: kern = k_zinv_mul<N, (2 < E ? 2 : E)>; break;
-    case 4: kern = k_zinv_mul<N, (4 < E ? 4 : E)>; break;
-    case 8: kern = k_zinv_mul<N, (8 < E ? 8 : E)>; break;
-    default: kern = k_zinv_mul<N, E>; break;
+    case 0: launch(k_zinv_mul<N, 0>, ZinvBlock<N, 0>::CB); break;
+    case 1: launch(k_zinv_mul<N, 1>, ZinvBlock<N, 1>::CB); break;
+    case 2: launch(k_zinv_mul<N, J2>, ZinvBlock<N, J2>::CB); break;
+    case 4: launch(k_zinv_mul<N, J4>, ZinvBlock<N, J4>::CB); break;
+    case 8: launch(k_zinv_mul<N, J8>, ZinvBlock<N, J8>::CB); break;
+    default: launch(k_zinv_mul<N, E>, ZinvBlock<N, E>::CB); break;
   }
-  hipLaunchKernelGGL(kern, dim3(NROWS / CB, 1), dim3(CB * T), 0, s, G, Sp, s_stride, s_planes, A,
-                     center, work, work_stride, zlim, tw);
   constexpr int RB = (128 / T > 0 ? 128 / T : 1);
   hipLaunchKernelGGL((k_c2c_rows<N, true>), dim3(NROWS / RB, A), dim3(RB * T), 0, s, work,
                      work_stride, zlim, tw);
