@@ -21,15 +21,16 @@
 //     k_reduce   one lane per voxel: every run's answer takes the Newton
 //                polish, the largest polished lambda wins (first on ties)
 //   learned start:
-//     k_mlp_start  persistent wavefronts with the network in registers: the
-//                BF16 MLP on the matrix cores gives each voxel's start u0
-//     k_learned  one lane per voxel: at most kNewtonFirst Riemannian Newton steps
-//                (halved when lambda falls; no shift needed); converged voxels are screened and
-//                written.  The others run SS-HOPM from u0 in k_runs (queue of
-//                saved iterates, shift from k_prepare), then k_learned_post
-//                polishes, screens and writes them.  Voxels that fail the
-//                checks go to the multistart path above, whose answer replaces
-//                the learned one when it is larger.
+//     k_learned  persistent wavefronts, 64 voxels at a time: the BF16 MLP on
+//                the matrix cores gives each voxel's start u0, then each lane
+//                takes at most kNewtonFirst Riemannian Newton steps (halved
+//                when lambda falls; no shift needed); converged voxels are
+//                screened and written.  The others run SS-HOPM from u0 in
+//                k_runs (queue of saved iterates, shift from k_prepare), then
+//                k_learned_post polishes, screens and writes them.  Voxels
+//                that fail the checks go to the multistart path above, whose
+//                answer replaces the learned one when it is larger.
+//     k_mlp_start  the network alone, for the start directions only
 #include "internal.hpp"
 #include "mlp_core.hpp"
 #include "sym_tables.hpp"
@@ -829,69 +830,99 @@ __global__ __launch_bounds__(64) void k_mlp_start(ExtractArgs a) {
   }
 }
 
-// Learned-start search, one lane per voxel: up to kNewtonFirst Newton steps
-// from u0; converged voxels are screened and written (status 0 or 2), the
-// others marked for SS-HOPM from u0 (status 1, with u0 and its lambda kept
-// per voxel).  The workgroups are persistent and each lane loads its next
-// voxel's tensor before working on the current one; nothing in the loop
-// waits on a memory result, so the loads' latency hides behind the Newton
-// steps.
+// Learned start and Newton search in one pass over the field: persistent
+// workgroups of kLearnedWaves wavefronts, each taking 64 voxels at a time
+// (voxel = lane).  The network, read from an LDS copy shared by the
+// workgroup, gives u0 = y / |y| on the matrix cores (start 0 if y = 0, which
+// also forces the fallback); each lane then takes up to kNewtonFirst Newton
+// steps from u0.  Converged voxels are screened and written (status 0 or 2),
+// the others marked for SS-HOPM from u0 (status 1, with u0 and its lambda
+// kept per voxel).  Each lane loads its next voxel's tensor before working on
+// the current one, and nothing in the loop waits on a memory result, so the
+// loads' latency hides behind the network and the Newton steps.
 constexpr int kLearnedGroups = 1024;
+constexpr int kLearnedWaves = 4;
 
 template <int N>
-__global__ __launch_bounds__(256) void k_learned(ExtractArgs a) {
+__global__ __launch_bounds__(64 * kLearnedWaves) void k_learned(ExtractArgs a) {
   constexpr int K = ncomp3(N);
+  constexpr Sym3<N> sy{};
   __shared__ float st[64 * 3];
   __shared__ float mono[64 * K];
+  __shared__ __align__(16) unsigned char pk[kMlpPackedBytes];
+  __shared__ unsigned short xs_all[kLearnedWaves][64 * kMlpIn];
+  static_assert(kMlpPackedBytes % 16 == 0, "packed network copied in 16-byte pieces");
   for (int i = threadIdx.x; i < a.n_starts * 3; i += blockDim.x) st[i] = a.starts[i];
+  for (int i = threadIdx.x; i < kMlpPackedBytes / 16; i += blockDim.x)
+    reinterpret_cast<uint4*>(pk)[i] = reinterpret_cast<const uint4*>(a.mlp)[i];
   __syncthreads();
   if (a.screen) build_monomials<N>(st, a.n_starts, mono);
   __syncthreads();
   const Ws w = ws_layout(a.ws, a.plane);
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  unsigned short* xs = xs_all[wave];
+  const MlpLds net{pk, lane};
+  const float s0x = st[0], s0y = st[1], s0z = st[2];
+  const size_t n_groups = (a.plane + 63) / 64;
+  const size_t gstride = (size_t)gridDim.x * kLearnedWaves;
+  size_t gi = (size_t)blockIdx.x * kLearnedWaves + wave;
   unsigned long long n_newton = 0, n_oriented = 0;
-  size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   float c[K];
-  float4 s0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-  if (v < a.plane) {
-    load_raw<N>(a, v, c);
-    s0 = w.best[v];
+  if (gi < n_groups) {
+    const size_t v0 = gi * 64 + lane;
+    load_raw<N>(a, v0 < a.plane ? v0 : a.plane - 1, c);
   }
-  while (v < a.plane) {
-    const size_t vn = v + stride;
+  for (; gi < n_groups; gi += gstride) {
+    const size_t v0 = gi * 64 + lane;
+    const bool active = v0 < a.plane;
+    const size_t v = active ? v0 : a.plane - 1;
     float cx[K];
-    float4 s0x = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (vn < a.plane) {
-      load_raw<N>(a, vn, cx);
-      s0x = w.best[vn];
+    const size_t gn = gi + gstride;
+    if (gn < n_groups) {
+      const size_t vn = gn * 64 + lane;
+      load_raw<N>(a, vn < a.plane ? vn : a.plane - 1, cx);
     }
     const float cn = frob<N>(c);
-    if (cn > 0.0f) {
-      scale<N>(c, 1.0f / cn);
-      const bool forced = s0.w != 0.0f;
-      float ux = s0.x, uy = s0.y, uz = s0.z;
-      float g0, g1, g2;
-      contract<N>(c, ux, uy, uz, g0, g1, g2);
-      float lam = g0 * ux + g1 * uy + g2 * uz;
-      const float lam0 = lam;
-      bool ok;
-      n_newton += newton_ascent<N>(c, ux, uy, uz, g0, g1, g2, lam, kNewtonFirst, a.tol, ok);
-      n_oriented += 1;
-      if (ok) {
-        n_newton += learned_finish<N>(a, w, c, cn, v, mono, ux, uy, uz, g0, g1, g2, lam, true,
-                                      forced, 0);
+    const size_t o = map_index(a, v);
+    if ((a.mode & 1) && active) a.score[o] = cn;
+    const float inv = cn > 0.0f ? 1.0f / cn : 0.0f;
+#pragma unroll
+    for (int k = 0; k < kMlpIn; ++k)
+      xs[lane * kMlpIn + k] = k < K ? bf16_bits(sqrtf(sy.mu[k]) * c[k] * inv) : (unsigned short)0;
+    wave_lds_sync();
+    float y0, y1, y2;
+    mlp_forward_w(xs, net, lane, y0, y1, y2);
+    const float ny = sqrtf(y0 * y0 + y1 * y1 + y2 * y2);
+    const bool forced = !(ny > 0.0f);
+    float ux = forced ? s0x : y0, uy = forced ? s0y : y1, uz = forced ? s0z : y2;
+    const float r = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
+    ux *= r; uy *= r; uz *= r;
+    if (active) {
+      if (cn > 0.0f) {
+        scale<N>(c, inv);
+        const float u0x = ux, u0y = uy, u0z = uz;
+        float g0, g1, g2;
+        contract<N>(c, ux, uy, uz, g0, g1, g2);
+        float lam = g0 * ux + g1 * uy + g2 * uz;
+        const float lam0 = lam;
+        bool ok;
+        n_newton += newton_ascent<N>(c, ux, uy, uz, g0, g1, g2, lam, kNewtonFirst, a.tol, ok);
+        n_oriented += 1;
+        if (ok) {
+          n_newton += learned_finish<N>(a, w, c, cn, v, mono, ux, uy, uz, g0, g1, g2, lam, true,
+                                        forced, 0);
+        } else {
+          // SS-HOPM from the learned start, run by the pooled kernel
+          w.status[v] = 1;
+          w.cont_state[v] = make_float4(u0x, u0y, u0z, lam0);
+          w.cont_it[v] = forced ? (1 << 30) : 0;
+        }
       } else {
-        // SS-HOPM from the learned start, run by the pooled kernel
-        w.status[v] = 1;
-        w.cont_state[v] = make_float4(s0.x, s0.y, s0.z, lam0);
-        w.cont_it[v] = forced ? (1 << 30) : 0;
+        write_answer(a, o, 0.0f, 0.0f, 0.0f, 0.0f);
+        w.status[v] = 0;
       }
-    } else {
-      write_answer(a, map_index(a, v), 0.0f, 0.0f, 0.0f, 0.0f);
-      w.status[v] = 0;
     }
-    v = vn;
-    s0 = s0x;
+    wave_lds_sync();   // xs is rewritten by the next group
 #pragma unroll
     for (int k = 0; k < K; ++k) c[k] = cx[k];
   }
@@ -1056,11 +1087,13 @@ int launch_n(const ExtractArgs& a, hipStream_t s) {
         launch_multistart<N>(a, Items{nullptr, nullptr}, ctr + kHdrPoolDense / 2, 0, s);
       } else {
         const size_t n_groups = (a.plane + 63) / 64;
-        const unsigned mg = (unsigned)(n_groups < (size_t)kMlpGroups ? n_groups : kMlpGroups);
-        hipLaunchKernelGGL((k_mlp_start<N>), dim3(mg), dim3(64), 0, s, a);
-        if (!a.start_only) {
-          const unsigned lg = nb < (unsigned)kLearnedGroups ? nb : (unsigned)kLearnedGroups;
-          hipLaunchKernelGGL((k_learned<N>), dim3(lg), dim3(256), 0, s, a);
+        if (a.start_only) {
+          const unsigned mg = (unsigned)(n_groups < (size_t)kMlpGroups ? n_groups : kMlpGroups);
+          hipLaunchKernelGGL((k_mlp_start<N>), dim3(mg), dim3(64), 0, s, a);
+        } else {
+          const size_t wg = (n_groups + kLearnedWaves - 1) / kLearnedWaves;
+          const unsigned lg = (unsigned)(wg < (size_t)kLearnedGroups ? wg : kLearnedGroups);
+          hipLaunchKernelGGL((k_learned<N>), dim3(lg), dim3(64 * kLearnedWaves), 0, s, a);
           compact(w, a.plane, 1, w.cont_list, &w.hdr[kHdrContinue], s);
           const Items cont{w.cont_list, &w.hdr[kHdrContinue]};
           hipLaunchKernelGGL((k_prepare<N>), dim3(nb), dim3(256), 0, s, a, cont, 0, 0);

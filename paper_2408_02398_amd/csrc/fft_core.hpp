@@ -198,15 +198,21 @@ struct FftTw {
   }
 };
 
+// Orders one wavefront's LDS writes before its later reads by other lanes of
+// the same wavefront (a wavefront's LDS instructions execute in order; the
+// fence keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Exchange barrier of a transform: the whole workgroup, or (WAVE) only the
 // wavefront, when every transform's T threads lie inside one wavefront and no
-// other wavefront touches its LDS area.  LDS accesses of one wavefront
-// complete in order; the fence keeps the compiler from moving them across.
+// other wavefront touches its LDS area.
 template <bool WAVE>
 __device__ __forceinline__ void fft_sync() {
   if constexpr (WAVE) {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    wave_lds_sync();
   } else {
     __syncthreads();
   }

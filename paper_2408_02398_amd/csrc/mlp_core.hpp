@@ -104,22 +104,56 @@ __device__ __forceinline__ void load_mlp_regs(const unsigned char* __restrict__ 
   for (int j = 0; j < 4; ++j) r.b3[j] = b3[4 * q + j];
 }
 
-__device__ __forceinline__ bf16x4 relu_bf16(const f32x4& acc, const float (&b)[4]) {
+// Fragments and biases of the packed network read from an LDS copy of it on
+// demand (the same layout as in global memory), for kernels that keep their
+// registers for other work.
+struct MlpLds {
+  const unsigned char* pk;   // LDS copy of the kMlpPackedBytes packed bytes
+  int lane;
+  __device__ __forceinline__ bf16x4 w1(int f) const { return load_frag(pk, kPkW1, f, lane); }
+  __device__ __forceinline__ bf16x4 w2(int f) const { return load_frag(pk, kPkW2, f, lane); }
+  __device__ __forceinline__ bf16x4 w3(int f) const { return load_frag(pk, kPkW3, f, lane); }
+  __device__ __forceinline__ float b1(int m, int j) const {
+    return reinterpret_cast<const float*>(pk + kPkB1)[16 * m + 4 * (lane >> 4) + j];
+  }
+  __device__ __forceinline__ float b2(int m, int j) const {
+    return reinterpret_cast<const float*>(pk + kPkB2)[16 * m + 4 * (lane >> 4) + j];
+  }
+  __device__ __forceinline__ float b3(int j) const {
+    return reinterpret_cast<const float*>(pk + kPkB3)[4 * (lane >> 4) + j];
+  }
+};
+
+// The same accessors over the registers of MlpRegs.
+struct MlpRegView {
+  const MlpRegs& r;
+  __device__ __forceinline__ bf16x4 w1(int f) const { return r.w1[f]; }
+  __device__ __forceinline__ bf16x4 w2(int f) const { return r.w2[f]; }
+  __device__ __forceinline__ bf16x4 w3(int f) const { return r.w3[f]; }
+  __device__ __forceinline__ float b1(int m, int j) const { return r.b1[m][j]; }
+  __device__ __forceinline__ float b2(int m, int j) const { return r.b2[m][j]; }
+  __device__ __forceinline__ float b3(int j) const { return r.b3[j]; }
+};
+
+template <class W>
+__device__ __forceinline__ bf16x4 relu_bf16_w(const f32x4& acc, const W& w, int layer, int m) {
   bf16x4 h;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) h[j] = (short)bf16_bits(fmaxf(acc[j] + b[j], 0.0f));
+  for (int j = 0; j < 4; ++j) {
+    const float b = layer == 1 ? w.b1(m, j) : w.b2(m, j);
+    h[j] = (short)bf16_bits(fmaxf(acc[j] + b, 0.0f));
+  }
   return h;
 }
 
-// Forward pass of one wavefront's 64 voxels (voxel = lane).
+// Forward pass of one wavefront's 64 voxels (voxel = lane), weights from w.
 //   xs: this wavefront's [64][32] bf16 features in LDS, written by the lanes
-//       before the call (the call starts with a barrier of the one-wavefront
-//       workgroup).
+//       and made visible to the wavefront before the call.
 // Returns y (3 floats) of the calling lane's voxel.
-__device__ __forceinline__ void mlp_forward(const unsigned short* xs, const MlpRegs& w, int lane,
-                                            float& y0, float& y1, float& y2) {
+template <class W>
+__device__ __forceinline__ void mlp_forward_w(const unsigned short* xs, const W& w, int lane,
+                                              float& y0, float& y1, float& y2) {
   const int r16 = lane & 15, q = lane >> 4;
-  __syncthreads();
   // B fragments of X^T: lane L holds x[voxel 16 nt + L % 16][feature 16 s + 4 (L/16) + j]
   bf16x4 xb[2][4];
 #pragma unroll
@@ -131,35 +165,44 @@ __device__ __forceinline__ void mlp_forward(const unsigned short* xs, const MlpR
   // layer 1: H1^T (64 x 64) = W1^T (64 x 32) X^T (32 x 64)
   bf16x4 h1[4][4];
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
+  for (int m = 0; m < 4; ++m) {
+    const bf16x4 a0 = w.w1(m), a1 = w.w1(4 + m);
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
       f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int s = 0; s < 2; ++s) acc = mfma16(w.w1[s * 4 + m], xb[s][nt], acc);
-      h1[m][nt] = relu_bf16(acc, w.b1[m]);
+      acc = mfma16(a0, xb[0][nt], acc);
+      acc = mfma16(a1, xb[1][nt], acc);
+      h1[m][nt] = relu_bf16_w(acc, w, 1, m);
     }
+  }
   // layer 2: H2^T = W2^T H1^T
   bf16x4 h2[4][4];
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
+  for (int m = 0; m < 4; ++m) {
+    bf16x4 a[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) a[s] = w.w2(s * 4 + m);
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
       f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int s = 0; s < 4; ++s) acc = mfma16(w.w2[s * 4 + m], h1[s][nt], acc);
-      h2[m][nt] = relu_bf16(acc, w.b2[m]);
+      for (int s = 0; s < 4; ++s) acc = mfma16(a[s], h1[s][nt], acc);
+      h2[m][nt] = relu_bf16_w(acc, w, 2, m);
     }
+  }
   // layer 3: Y^T (16 x 64) = W3^T H2^T; lanes 0..15 hold rows 0..3 (outputs)
   // of voxel columns 16 nt + lane
+  bf16x4 a3[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) a3[s] = w.w3(s);
   float yv[3][4];
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
     f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int s = 0; s < 4; ++s) acc = mfma16(w.w3[s], h2[s][nt], acc);
+    for (int s = 0; s < 4; ++s) acc = mfma16(a3[s], h2[s][nt], acc);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) yv[i][nt] = acc[i] + w.b3[i];
+    for (int i = 0; i < 3; ++i) yv[i][nt] = acc[i] + w.b3(i);
   }
   // each voxel lane fetches its outputs from lane (voxel % 16) of tile voxel / 16
   const int src = lane & 15, tile = lane >> 4;
@@ -177,6 +220,14 @@ __device__ __forceinline__ void mlp_forward(const unsigned short* xs, const MlpR
   y0 = y[0];
   y1 = y[1];
   y2 = y[2];
+}
+
+// Forward pass with the network in registers, for one-wavefront workgroups
+// (starts with the workgroup barrier that makes xs visible).
+__device__ __forceinline__ void mlp_forward(const unsigned short* xs, const MlpRegs& w, int lane,
+                                            float& y0, float& y1, float& y2) {
+  __syncthreads();
+  mlp_forward_w(xs, MlpRegView{w}, lane, y0, y1, y2);
 }
 
 }  // namespace ttm

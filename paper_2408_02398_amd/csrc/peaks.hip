@@ -188,14 +188,6 @@ struct GreedyArgs {
   int* n_found;           // device
 };
 
-// Orders one wavefront's LDS writes before its later reads by other lanes
-// (a wavefront's LDS instructions execute in order; this keeps the compiler
-// from moving them).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
 __global__ __launch_bounds__(kGreedyThreads) void k_greedy(GreedyArgs g) {
   __shared__ short head[kMaxCells];
   __shared__ short next[kMaxPeaks];
