@@ -257,7 +257,7 @@ __global__ __launch_bounds__((ZinvBlock<N, JP>::CB * Plan<N>::T)) void k_zinv_mu
 
 // ---------------------------------------------------------------- X inverse
 template <int N>
-__global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) __attribute__((amdgpu_waves_per_eu(8))) void k_c2r_x(const cf* __restrict__ spec,
+__global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) __attribute__((amdgpu_waves_per_eu(N == 512 ? 8 : 1))) void k_c2r_x(const cf* __restrict__ spec,
                                                           size_t spec_stride, int A, RealDst dst,
                                                           const cf* __restrict__ tw) {
   constexpr int T = Plan<N>::T, E = N / T, NP = kRowsX / 2, NH = N / 2 + 1;
