@@ -502,10 +502,8 @@ __global__ __launch_bounds__(256) void k_prepare(ExtractArgs a, Items it, int wr
   const Ws w = ws_layout(a.ws, a.plane);
   const unsigned n = it.n(a);
   if (add_total && a.fb_total && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.fb_total, (int)n);
-  if ((size_t)blockIdx.x * blockDim.x >= n) return;   // whole block past the list
-  const unsigned j = blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long n_shift = 0;
-  if (j < n) {
+  for (unsigned j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
     const size_t v = it.voxel(j);
     float c[ncomp3(N)];
     const float cn = load_tensor<N>(a, v, c);
@@ -514,7 +512,7 @@ __global__ __launch_bounds__(256) void k_prepare(ExtractArgs a, Items it, int wr
     if (cn > 0.0f) {
       scale<N>(c, 1.0f / cn);
       alpha = fmaxf(0.0f, -unfolding_lambda_min<N, kShiftSteps>(c));
-      n_shift = 1;
+      n_shift += 1;
     }
     w.alpha[j] = alpha;
   }
@@ -703,9 +701,8 @@ __global__ __launch_bounds__(256) void k_reduce(ExtractArgs a, Items it, int nsb
   constexpr int K = ncomp3(N);
   const Ws w = ws_layout(a.ws, a.plane);
   const unsigned n = it.n(a);
-  const unsigned j = blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long n_newton = 0, n_oriented = 0;
-  if (j < n) {
+  for (unsigned j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
     const size_t v = it.voxel(j);
     float c[K];
     const float cn = load_tensor<N>(a, v, c);
@@ -729,7 +726,7 @@ __global__ __launch_bounds__(256) void k_reduce(ExtractArgs a, Items it, int nsb
         ux = b.x; uy = b.y; uz = b.z;
         canonical(ux, uy, uz);
         lam = b.w * cn;
-        n_oriented = merge ? 0 : 1;
+        n_oriented += merge ? 0 : 1;
       }
       const size_t o = map_index(a, v);
       if (!merge || lam > a.lam[o]) write_answer(a, o, lam, ux, uy, uz);
@@ -944,9 +941,8 @@ __global__ __launch_bounds__(256) void k_learned_post(ExtractArgs a) {
   __syncthreads();
   const Ws w = ws_layout(a.ws, a.plane);
   const unsigned n = w.hdr[kHdrContinue];
-  const unsigned j = blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long n_newton = 0;
-  if (j < n) {
+  for (unsigned j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
     const size_t v = w.cont_list[j];
     float c[K];
     const float cn = load_tensor<N>(a, v, c);
@@ -957,8 +953,8 @@ __global__ __launch_bounds__(256) void k_learned_post(ExtractArgs a) {
     contract<N>(c, ux, uy, uz, g0, g1, g2);
     const float lam = g0 * ux + g1 * uy + g2 * uz;
     const bool forced = (w.cont_it[v] >> 30) & 1;
-    n_newton = learned_finish<N>(a, w, c, cn, v, mono, ux, uy, uz, g0, g1, g2, lam,
-                                 w.conv[j] != 0, forced, a.newton);
+    n_newton += learned_finish<N>(a, w, c, cn, v, mono, ux, uy, uz, g0, g1, g2, lam,
+                                  w.conv[j] != 0, forced, a.newton);
   }
   if (a.counters) count_add(a.counters + 1, n_newton);
 }
@@ -1057,10 +1053,16 @@ size_t extract_workspace(size_t plane) {
          (size_t)kStartBlock * plane * 16;
 }
 
+// Workgroups of the per-item kernels (k_prepare, k_reduce, k_learned_post):
+// they loop over their items, so a list whose length only the device knows
+// costs no launch of hundreds of thousands of empty workgroups.
+constexpr unsigned kItemGroups = 1024;
+
 template <int N>
 int launch_multistart(const ExtractArgs& a, Items it, unsigned long long* ctr_base, int merge,
                       hipStream_t s) {
-  const unsigned nb = (unsigned)((a.plane + 255) / 256);
+  const unsigned nb0 = (unsigned)((a.plane + 255) / 256);
+  const unsigned nb = nb0 < kItemGroups ? nb0 : kItemGroups;
   const int n_blocks = (a.n_starts + kStartBlock - 1) / kStartBlock;
   hipLaunchKernelGGL((k_prepare<N>), dim3(nb), dim3(256), 0, s, a, it,
                      merge ? 0 : (a.mode & 1), merge);
@@ -1096,10 +1098,11 @@ int launch_n(const ExtractArgs& a, hipStream_t s) {
           hipLaunchKernelGGL((k_learned<N>), dim3(lg), dim3(64 * kLearnedWaves), 0, s, a);
           compact(w, a.plane, 1, w.cont_list, &w.hdr[kHdrContinue], s);
           const Items cont{w.cont_list, &w.hdr[kHdrContinue]};
-          hipLaunchKernelGGL((k_prepare<N>), dim3(nb), dim3(256), 0, s, a, cont, 0, 0);
+          const unsigned ib = nb < kItemGroups ? nb : kItemGroups;
+          hipLaunchKernelGGL((k_prepare<N>), dim3(ib), dim3(256), 0, s, a, cont, 0, 0);
           RunArgs r{cont, 1, 0, ctr + kHdrPoolCont / 2};
           hipLaunchKernelGGL((k_runs<N, true>), dim3(kPoolGroups), dim3(64), 0, s, a, r);
-          hipLaunchKernelGGL(k_learned_post<N>, dim3(nb), dim3(256), 0, s, a);
+          hipLaunchKernelGGL(k_learned_post<N>, dim3(ib), dim3(256), 0, s, a);
           compact(w, a.plane, 2, w.fb_list, &w.hdr[kHdrFallbacks], s);
           launch_multistart<N>(a, Items{w.fb_list, &w.hdr[kHdrFallbacks]}, ctr + kHdrPoolFb / 2,
                                1, s);
