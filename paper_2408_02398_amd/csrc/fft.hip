@@ -132,7 +132,8 @@ k_c2c_rows(cf* __restrict__ data, size_t batch_stride, int row_limit, const cf* 
 // ---------------------------------------------------------------- Z (columns)
 template <int N> struct ColBlock { static constexpr int CB = 16; };
 // Columns per Z-inverse workgroup: 16 (128-byte row segments), 8 at N = 512
-// with more than 2 plane slots, where 16 would not fit the LDS.
+// with more than 2 plane slots (templates over 128 planes, beyond the edge
+// the descriptor accepts today), where 16 would not fit the LDS.
 template <int N, int JP> struct ZinvBlock { static constexpr int CB = (N >= 512 && JP > 2) ? 8 : 16; };
 
 template <int N, bool INV>

@@ -189,6 +189,43 @@ def test_correlate_and_score_match_oracle(T, ctx, small, dtype):
     assert np.max(np.abs(sg - cs) / floor) < tol
 
 
+@pytest.mark.parametrize("N,L", [(64, 48), (128, 64), (256, 64), (512, 64)])
+def test_large_templates_sampled(T, ctx, N, L):
+    """The largest templates (L = 64) and ones whose z planes need several
+    slots per thread in the Z-inverse pass (8 at N = 64 and 128, 4 at N = 256,
+    2 at N = 512): w and C on one full tile, checked at sampled voxels against
+    the FP64 oracle's direct sums (Eq. norm_f, Eq. tcc)."""
+    print(f"[large template N={N} L={L}]", flush=True)
+    n, K, r = 2, 6, 0.4 * L
+    d = T.make_desc(n, L, r)
+    rng = np.random.default_rng(N + L)
+    D = L + 40
+    vol = rng.standard_normal((D, D, D)).astype(np.float32)
+    Tf = (rng.standard_normal((K, L, L, L)) / L ** 1.5).astype(np.float32)
+    spec = T.template_spectra(ctx, d, cuda(Tf.reshape(K, -1)), N)
+    g, w, stats = T.normalize(ctx, d, cuda(vol), spec, N)
+    lo, hi = T.valid_bounds(vol.shape, L)
+    size = tuple(h - l + 1 for l, h in zip(lo, hi))
+    Cg = host(T.correlate(ctx, d, g, w, stats, spec, N, lo, size))
+    wg = host(w)
+    pts = [tuple(lo), tuple(hi)] + [tuple(int(rng.integers(a, b + 1)) for a, b in zip(lo, hi))
+                                    for _ in range(4)]
+    c = L // 2
+    patches = np.stack([orc.prefilter_box(vol, (z - c, y - c, x - c), (z - c + L, y - c + L, x - c + L))
+                        for z, y, x in pts])
+    g2 = float(np.mean(orc.prefilter_volume(vol) ** 2))
+    wo, Co = orc.field_at(patches, orc.ball_mask(L, r), Tf.astype(np.float64), g2)
+    del patches
+    assert np.all(wo > 0)
+    wgs = np.array([wg[p] for p in pts])
+    assert np.max(np.abs(wgs - wo) / wo) < 1e-4
+    Cgs = np.stack([Cg[:, z - lo[0], y - lo[1], x - lo[2]] for z, y, x in pts])
+    so = orc.score(Co.T, n)
+    floor = np.maximum(so, np.median(so))
+    dC = np.sqrt(np.sum(sym.weights(n, 3) * (Cgs - Co) ** 2, axis=1))
+    assert np.max(dC / floor) < 1e-4
+
+
 def test_correlate_sub_box_and_single_voxel(T, ctx, small):
     n, L = small["n"], small["L"]
     d = T.make_desc(n, L, small["r"])
