@@ -229,8 +229,9 @@ typedef struct {
  *   n_fallback device int32 counter incremented per voxel whose learned start
  *             fell back to the multistart search, or NULL
  *   ws        device workspace of ttm_workspace_size(desc, TTM_OP_EXTRACT, 0,
- *             bz, by, bx) bytes (run queues and per-run results, about 300
- *             bytes per box voxel); required with TTM_ORIENT, may be NULL for
+ *             bz, by, bx) bytes (run queues, per-run results and the tensors
+ *             the learned start hands on, about 430 bytes per box voxel at
+ *             degree 6); required with TTM_ORIENT, may be NULL for
  *             TTM_SCORE alone.  Calls that share a workspace must be ordered
  *             on one stream.
  * Orientation: alpha = max(0, -lambda_min(U)) with U the square unfolding of

@@ -495,7 +495,7 @@ size_t ttm_workspace_size(const ttm_desc* desc, int op, int fft_n, int nz, int n
       return align256(peaks_workspace((int64_t)nz * ny * nx));
     case TTM_OP_EXTRACT:
       if (nz < 1 || ny < 1 || nx < 1) return 0;
-      return extract_workspace((size_t)nz * ny * nx);
+      return extract_workspace((size_t)nz * ny * nx, desc->degree);
     case TTM_OP_MLP_TRAIN:
       if (nz < 1) return 0;
       return align256(mlp_train_workspace(nz));
@@ -829,7 +829,7 @@ int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
         return TTM_EUNSUPPORTED;
       }
     }
-    const size_t need = extract_workspace(plane);
+    const size_t need = extract_workspace(plane, desc->degree);
     if (!ws || ws_bytes < need) {
       set_error("ttm_extract: workspace %zu < %zu", ws_bytes, need);
       return TTM_EWORKSPACE;

@@ -69,6 +69,7 @@ struct Ws {
   unsigned char* status;  // per box voxel: 0 answered, 1 continue with SS-HOPM, 2 fall back
   unsigned* blocksum;     // per compaction block: count, then offset
   float4* res;
+  float4* stage;   // per box voxel handed on by the learned start: C / ||C||_F, then ||C||_F
 };
 
 constexpr int kCompactBlock = 4096;   // voxels per compaction workgroup (256 threads x 16)
@@ -99,8 +100,13 @@ __host__ __device__ inline Ws ws_layout(void* base, size_t plane) {
   w.blocksum = reinterpret_cast<unsigned*>(p);
   p += al256(((plane + kCompactBlock - 1) / kCompactBlock) * 4);
   w.res = reinterpret_cast<float4*>(p);
+  p += (size_t)kStartBlock * plane * 16;
+  w.stage = reinterpret_cast<float4*>(p);
   return w;
 }
+
+// float4 slots of one staged voxel: the K normalised components, then ||C||_F.
+__host__ __device__ constexpr int stage_slots(int K) { return (K + 1 + 3) / 4; }
 
 __device__ __forceinline__ float bf16_to_f32(unsigned short h) {
   return __uint_as_float(((unsigned int)h) << 16);
@@ -485,14 +491,46 @@ __global__ __launch_bounds__(256) void k_score(ExtractArgs a) {
 // ---------------------------------------------------------------------------
 
 // Work list: `list` (box voxel per item, length *count) or all box voxels.
+// Items of a run: the voxels of a device-side list (or every box voxel).
+// stage: where the learned start left the listed voxels' normalised tensors
+// (one contiguous piece per voxel), else they are read from the K planes.
 struct Items {
   const unsigned* list;
   const unsigned* count;
+  const float4* stage;
   __device__ __forceinline__ unsigned n(const ExtractArgs& a) const {
     return list ? *count : (unsigned)a.plane;
   }
   __device__ __forceinline__ size_t voxel(unsigned j) const { return list ? list[j] : j; }
 };
+
+// Normalised tensor of box voxel v staged by the learned start; returns ||C||_F.
+template <int N>
+__device__ __forceinline__ float load_staged(const float4* stage, size_t v, float (&c)[ncomp3(N)]) {
+  constexpr int K = ncomp3(N), SQ = stage_slots(K);
+  float f[4 * SQ];
+  const float4* p = stage + v * SQ;
+#pragma unroll
+  for (int i = 0; i < SQ; ++i) {
+    const float4 q = p[i];
+    f[4 * i] = q.x; f[4 * i + 1] = q.y; f[4 * i + 2] = q.z; f[4 * i + 3] = q.w;
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) c[k] = f[k];
+  return f[K];
+}
+
+template <int N>
+__device__ __forceinline__ void store_staged(float4* stage, size_t v, const float (&c)[ncomp3(N)],
+                                             float cn) {
+  constexpr int K = ncomp3(N), SQ = stage_slots(K);
+  float f[4 * SQ];
+#pragma unroll
+  for (int k = 0; k < 4 * SQ; ++k) f[k] = k < K ? c[k] : (k == K ? cn : 0.0f);
+  float4* p = stage + v * SQ;
+#pragma unroll
+  for (int i = 0; i < SQ; ++i) p[i] = make_float4(f[4 * i], f[4 * i + 1], f[4 * i + 2], f[4 * i + 3]);
+}
 
 // Shift (and optionally the score) per item.  `add_total`: add the item
 // count to the caller's fallback counter.
@@ -506,11 +544,11 @@ __global__ __launch_bounds__(256) void k_prepare(ExtractArgs a, Items it, int wr
   for (unsigned j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
     const size_t v = it.voxel(j);
     float c[ncomp3(N)];
-    const float cn = load_tensor<N>(a, v, c);
+    const float cn = it.stage ? load_staged<N>(it.stage, v, c) : load_tensor<N>(a, v, c);
     if (write_score && a.score) a.score[map_index(a, v)] = cn;
     float alpha = 0.0f;
     if (cn > 0.0f) {
-      scale<N>(c, 1.0f / cn);
+      if (!it.stage) scale<N>(c, 1.0f / cn);
       alpha = fmaxf(0.0f, -unfolding_lambda_min<N, kShiftSteps>(c));
       n_shift += 1;
     }
@@ -591,29 +629,38 @@ __global__ __launch_bounds__(64) void k_runs(ExtractArgs a, RunArgs r) {
           if (lane < cnt) {
             const unsigned jj = chunk_base + lane;
             const size_t v = r.items.voxel(jj);
-            float f2 = 0.0f;
-            if (a.in_dtype == 1) {
-              const unsigned short* p = reinterpret_cast<const unsigned short*>(a.C);
+            if (r.items.stage) {
+              // normalised already
+              float cv[K];
+              const float cn = load_staged<N>(r.items.stage, v, cv);
 #pragma unroll
-              for (int k = 0; k < K; ++k) {
-                const float x = bf16_to_f32(p[k * a.plane + v]);
-                cs[k][lane] = x;
-                f2 = fmaf(sy.mu[k] * x, x, f2);
-              }
+              for (int k = 0; k < K; ++k) cs[k][lane] = cv[k];
+              cz[lane] = cn;
             } else {
-              const float* p = reinterpret_cast<const float*>(a.C);
+              float f2 = 0.0f;
+              if (a.in_dtype == 1) {
+                const unsigned short* p = reinterpret_cast<const unsigned short*>(a.C);
 #pragma unroll
-              for (int k = 0; k < K; ++k) {
-                const float x = p[k * a.plane + v];
-                cs[k][lane] = x;
-                f2 = fmaf(sy.mu[k] * x, x, f2);
+                for (int k = 0; k < K; ++k) {
+                  const float x = bf16_to_f32(p[k * a.plane + v]);
+                  cs[k][lane] = x;
+                  f2 = fmaf(sy.mu[k] * x, x, f2);
+                }
+              } else {
+                const float* p = reinterpret_cast<const float*>(a.C);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                  const float x = p[k * a.plane + v];
+                  cs[k][lane] = x;
+                  f2 = fmaf(sy.mu[k] * x, x, f2);
+                }
               }
-            }
-            const float cn = sqrtf(f2);
-            const float inv = cn > 0.0f ? 1.0f / cn : 0.0f;
+              const float cn = sqrtf(f2);
+              const float inv = cn > 0.0f ? 1.0f / cn : 0.0f;
 #pragma unroll
-            for (int k = 0; k < K; ++k) cs[k][lane] *= inv;
-            cz[lane] = cn;
+              for (int k = 0; k < K; ++k) cs[k][lane] *= inv;
+              cz[lane] = cn;
+            }
             ca[lane] = w.alpha[jj];
             if constexpr (CONT) {
               cu[lane] = w.cont_state[v];
@@ -705,10 +752,10 @@ __global__ __launch_bounds__(256) void k_reduce(ExtractArgs a, Items it, int nsb
   for (unsigned j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
     const size_t v = it.voxel(j);
     float c[K];
-    const float cn = load_tensor<N>(a, v, c);
+    const float cn = it.stage ? load_staged<N>(it.stage, v, c) : load_tensor<N>(a, v, c);
     float4 b = first_block ? make_float4(0.0f, 0.0f, 0.0f, -INFINITY) : w.best[j];
     if (cn > 0.0f) {
-      scale<N>(c, 1.0f / cn);
+      if (!it.stage) scale<N>(c, 1.0f / cn);
       for (int s = 0; s < nsb; ++s) {
         const float4 r = w.res[(size_t)s * a.plane + j];
         float ux = r.x, uy = r.y, uz = r.z, g0, g1, g2;
@@ -751,7 +798,7 @@ template <int N>
 __device__ __forceinline__ unsigned long long learned_finish(
     const ExtractArgs& a, const Ws& w, const float (&c)[ncomp3(N)], float cn, size_t v,
     const float* mono, float ux, float uy, float uz, float g0, float g1, float g2, float lam,
-    bool conv, bool forced, int polish) {
+    bool conv, bool forced, int polish, bool& fell) {
   constexpr int K = ncomp3(N);
   const unsigned long long taken = newton_polish<N>(c, ux, uy, uz, g0, g1, g2, lam, polish);
   bool beaten = false;
@@ -767,6 +814,7 @@ __device__ __forceinline__ unsigned long long learned_finish(
   canonical(ux, uy, uz);
   write_answer(a, map_index(a, v), lam * cn, ux, uy, uz);
   w.status[v] = fallback ? 2 : 0;
+  fell = fallback;
   return taken;
 }
 
@@ -905,15 +953,18 @@ __global__ __launch_bounds__(64 * kLearnedWaves) void k_learned(ExtractArgs a) {
         bool ok;
         n_newton += newton_ascent<N>(c, ux, uy, uz, g0, g1, g2, lam, kNewtonFirst, a.tol, ok);
         n_oriented += 1;
+        bool fell = true;
         if (ok) {
           n_newton += learned_finish<N>(a, w, c, cn, v, mono, ux, uy, uz, g0, g1, g2, lam, true,
-                                        forced, 0);
+                                        forced, 0, fell);
         } else {
           // SS-HOPM from the learned start, run by the pooled kernel
           w.status[v] = 1;
           w.cont_state[v] = make_float4(u0x, u0y, u0z, lam0);
           w.cont_it[v] = forced ? (1 << 30) : 0;
         }
+        // the voxels handed on read their tensor from here, in one piece
+        if (fell) store_staged<N>(w.stage, v, c, cn);
       } else {
         write_answer(a, o, 0.0f, 0.0f, 0.0f, 0.0f);
         w.status[v] = 0;
@@ -945,16 +996,16 @@ __global__ __launch_bounds__(256) void k_learned_post(ExtractArgs a) {
   for (unsigned j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
     const size_t v = w.cont_list[j];
     float c[K];
-    const float cn = load_tensor<N>(a, v, c);
-    scale<N>(c, 1.0f / cn);
+    const float cn = load_staged<N>(w.stage, v, c);
     const float4 r = w.res[j];
     float ux = r.x, uy = r.y, uz = r.z;
     float g0, g1, g2;
     contract<N>(c, ux, uy, uz, g0, g1, g2);
     const float lam = g0 * ux + g1 * uy + g2 * uz;
     const bool forced = (w.cont_it[v] >> 30) & 1;
+    bool fell;
     n_newton += learned_finish<N>(a, w, c, cn, v, mono, ux, uy, uz, g0, g1, g2, lam,
-                                  w.conv[j] != 0, forced, a.newton);
+                                  w.conv[j] != 0, forced, a.newton, fell);
   }
   if (a.counters) count_add(a.counters + 1, n_newton);
 }
@@ -1047,10 +1098,11 @@ void compact(const Ws& w, size_t plane, unsigned char value, unsigned* list, uns
 
 }  // namespace
 
-size_t extract_workspace(size_t plane) {
+size_t extract_workspace(size_t plane, int degree) {
+  const int K = (degree + 1) * (degree + 2) / 2;
   return 256 + al256(plane * 4) * 2 + al256(plane * 16) + al256(plane * 4) * 2 + al256(plane) +
          al256(plane * 16) + al256(plane) + al256(((plane + kCompactBlock - 1) / kCompactBlock) * 4) +
-         (size_t)kStartBlock * plane * 16;
+         (size_t)kStartBlock * plane * 16 + plane * 16 * (size_t)stage_slots(K);
 }
 
 // Workgroups of the per-item kernels (k_prepare, k_reduce, k_learned_post):
@@ -1086,7 +1138,7 @@ int launch_n(const ExtractArgs& a, hipStream_t s) {
       fill_zero(w.hdr, 256, s);
       unsigned long long* ctr = reinterpret_cast<unsigned long long*>(w.hdr);
       if ((a.mode & 4) == 0) {
-        launch_multistart<N>(a, Items{nullptr, nullptr}, ctr + kHdrPoolDense / 2, 0, s);
+        launch_multistart<N>(a, Items{nullptr, nullptr, nullptr}, ctr + kHdrPoolDense / 2, 0, s);
       } else {
         const size_t n_groups = (a.plane + 63) / 64;
         if (a.start_only) {
@@ -1097,14 +1149,14 @@ int launch_n(const ExtractArgs& a, hipStream_t s) {
           const unsigned lg = (unsigned)(wg < (size_t)kLearnedGroups ? wg : kLearnedGroups);
           hipLaunchKernelGGL((k_learned<N>), dim3(lg), dim3(64 * kLearnedWaves), 0, s, a);
           compact(w, a.plane, 1, w.cont_list, &w.hdr[kHdrContinue], s);
-          const Items cont{w.cont_list, &w.hdr[kHdrContinue]};
+          const Items cont{w.cont_list, &w.hdr[kHdrContinue], w.stage};
           const unsigned ib = nb < kItemGroups ? nb : kItemGroups;
           hipLaunchKernelGGL((k_prepare<N>), dim3(ib), dim3(256), 0, s, a, cont, 0, 0);
           RunArgs r{cont, 1, 0, ctr + kHdrPoolCont / 2};
           hipLaunchKernelGGL((k_runs<N, true>), dim3(kPoolGroups), dim3(64), 0, s, a, r);
           hipLaunchKernelGGL(k_learned_post<N>, dim3(ib), dim3(256), 0, s, a);
           compact(w, a.plane, 2, w.fb_list, &w.hdr[kHdrFallbacks], s);
-          launch_multistart<N>(a, Items{w.fb_list, &w.hdr[kHdrFallbacks]}, ctr + kHdrPoolFb / 2,
+          launch_multistart<N>(a, Items{w.fb_list, &w.hdr[kHdrFallbacks], w.stage}, ctr + kHdrPoolFb / 2,
                                1, s);
         }
       }

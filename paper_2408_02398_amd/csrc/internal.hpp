@@ -110,7 +110,7 @@ struct ExtractArgs {
   int* fb_total;                 // optional caller counter of fallbacks
 };
 // Workspace bytes of an orientation extraction over `plane` voxels.
-size_t extract_workspace(size_t plane);
+size_t extract_workspace(size_t plane, int degree);
 int launch_extract(int degree, const ExtractArgs& a, hipStream_t s);
 
 // Find Peaks (peaks.hip).
