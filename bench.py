@@ -214,6 +214,8 @@ def main():
         one_pass(False, count=True)
         torch.cuda.synchronize()
         per_pass = [int(v) for v in counters.cpu().tolist()]
+        eng.release()             # keep the maps for the accuracy gate, free the workspaces
+        torch.cuda.empty_cache()
         res = dict(eng=eng, pk=pk, stage=stage, ext=ext_launch_ms, corr=corr_launch_ms,
                    ms_step=start.elapsed_time(stop) / args.steps, wall=wall,
                    counters=[v * args.steps for v in per_pass], fallbacks=fallbacks)

@@ -380,6 +380,12 @@ class Engine:
         self.lam = torch.zeros(self.shape, dtype=torch.float32, device=dev) if orient else None
         self.dir = torch.zeros((*self.shape, 3), dtype=torch.float32, device=dev) if orient else None
 
+    def release(self) -> None:
+        """Free the tile buffers and workspaces and keep the output maps (score,
+        lam, dir); run() cannot be called afterwards."""
+        self.Cbufs = self.Cbuf = None
+        self.ws_pre = self.ws_norm = self.ws_corr = self.ws_peaks = self.ws_extract = None
+
     def run(self, vol: torch.Tensor, top_p: int | None = None, min_dist: float | None = None,
             tiles=None, overlap: bool = True, timing: dict | None = None,
             counters: torch.Tensor | None = None) -> PassResult:
