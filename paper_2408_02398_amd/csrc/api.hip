@@ -50,7 +50,7 @@ int hip_status(hipError_t e, const char* what) {
 
 namespace {
 
-constexpr int kPfZ = 8;  // z slices per prefilter thread
+constexpr int kPfZ = 16;  // z slices per prefilter thread
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
@@ -88,20 +88,30 @@ __global__ __launch_bounds__(256) void k_prefilter(const float* __restrict__ f, 
     const int xm = clampi(x - 1, 0, nx - 1), xp = clampi(x + 1, 0, nx - 1);
     const int ym = clampi(y - 1, 0, ny - 1), yp = clampi(y + 1, 0, ny - 1);
     const int ys[3] = {ym, y, yp};
-    for (int z = z0; z < min(z0 + kPfZ, nz); ++z) {
-      const int zs[3] = {clampi(z - 1, 0, nz - 1), z, clampi(z + 1, 0, nz - 1)};
-      float acc_z = 0.0f;
+    // x- and y-filtered value of plane zz at (y, x)
+    auto plane_yx = [&](int zz) {
+      float acc_y = 0.0f;
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        float acc_y = 0.0f;
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          const float* row = f + ((size_t)zs[i] * ny + ys[j]) * nx;
-          const float hx = w0 * row[xm] + w1 * row[x] + w0 * row[xp];
-          acc_y += (j == 1 ? w1 : w0) * hx;
-        }
-        acc_z += (i == 1 ? w1 : w0) * acc_y;
+      for (int j = 0; j < 3; ++j) {
+        const float* row = f + ((size_t)zz * ny + ys[j]) * nx;
+        const float hx = w0 * row[xm] + w1 * row[x] + w0 * row[xp];
+        acc_y += (j == 1 ? w1 : w0) * hx;
       }
+      return acc_y;
+    };
+    // planes z - 1, z, z + 1 slide along z: each plane is filtered once
+    float pm = plane_yx(clampi(z0 - 1, 0, nz - 1)), pc = plane_yx(min(z0, nz - 1));
+    float pp = plane_yx(clampi(z0 + 1, 0, nz - 1));
+    for (int z = z0; z < min(z0 + kPfZ, nz); ++z) {
+      if (z > z0) {
+        pm = pc;
+        pc = pp;
+        pp = plane_yx(clampi(z + 1, 0, nz - 1));
+      }
+      float acc_z = 0.0f;
+      acc_z += w0 * pm;
+      acc_z += w1 * pc;
+      acc_z += w0 * pp;
       g[((size_t)z * ny + y) * nx + x] = acc_z;
       s1 += (double)acc_z;
       s2 += (double)acc_z * (double)acc_z;
