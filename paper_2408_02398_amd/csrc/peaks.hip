@@ -57,19 +57,31 @@ __global__ __launch_bounds__(256) void k_hist(const float* __restrict__ score, R
   __syncthreads();
   const int z = r.z0 + blockIdx.z;
   const int nxv = r.x1 - r.x0 + 1;
+  // scores crowd into few bins: a thread counts a run of equal bins in a
+  // register and adds it at once, instead of one contended LDS atomic each
+  unsigned cur = 0xFFFFFFFFu, run = 0;
   for (int yy = 0; yy < 8; ++yy) {
     const int y = r.y0 + blockIdx.y * 8 + yy;
     if (y > r.y1) break;
     const float* row = score + ((size_t)z * r.ny + y) * r.nx + r.x0;
     for (int x = blockIdx.x * 256 + threadIdx.x; x < nxv; x += 256 * gridDim.x) {
       const unsigned b = score_bits(row[x]);
+      unsigned bin = 0xFFFFFFFFu;
       if (level == 0) {
-        atomicAdd(&h[b >> 20], 1u);
+        bin = b >> 20;
       } else if ((b >> 20) == top) {
-        atomicAdd(&h[(b >> 8) & 0xFFFu], 1u);
+        bin = (b >> 8) & 0xFFFu;
       }
+      if (bin == 0xFFFFFFFFu) continue;
+      if (bin != cur) {
+        if (run) atomicAdd(&h[cur], run);
+        cur = bin;
+        run = 0;
+      }
+      ++run;
     }
   }
+  if (run) atomicAdd(&h[cur], run);
   __syncthreads();
   for (int i = threadIdx.x; i < kHistBins; i += 256)
     if (h[i]) atomicAdd(&hist[i], h[i]);
