@@ -818,10 +818,10 @@ __device__ __forceinline__ unsigned long long learned_finish(
   return taken;
 }
 
-// Learned start directions: persistent wavefronts (one per workgroup) hold the
-// network in registers and run it on 64 voxels at a time; writes the score
-// and u0 = y / |y| (best[v] = (u0, 1 if the network gave no direction and
-// start 0 stands in)), or with start_only the direction maps.
+// Learned start directions alone (start_only): persistent wavefronts (one per
+// workgroup) hold the network in registers and run it on 64 voxels at a time;
+// writes the score and u0 = y / |y| (start 0 where the network gives no
+// direction) into the direction maps.
 constexpr int kMlpGroups = 2048;
 
 template <int N>
@@ -830,7 +830,6 @@ __global__ __launch_bounds__(64) void k_mlp_start(ExtractArgs a) {
   constexpr Sym3<N> sy{};
   __shared__ unsigned short xs[64 * kMlpIn];
   const int lane = threadIdx.x;
-  const Ws w = ws_layout(a.ws, a.plane);
   MlpRegs net;
   load_mlp_regs(a.mlp, lane, net);
   const float s0x = a.starts[0], s0y = a.starts[1], s0z = a.starts[2];
@@ -865,10 +864,7 @@ __global__ __launch_bounds__(64) void k_mlp_start(ExtractArgs a) {
     float ux = forced ? s0x : y0, uy = forced ? s0y : y1, uz = forced ? s0z : y2;
     const float r = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
     ux *= r; uy *= r; uz *= r;
-    if (active) {
-      if (a.start_only) write_answer(a, o, 0.0f, ux, uy, uz);
-      else w.best[v] = make_float4(ux, uy, uz, forced ? 1.0f : 0.0f);
-    }
+    if (active) write_answer(a, o, 0.0f, ux, uy, uz);
     __syncthreads();   // xs is rewritten by the next group
 #pragma unroll
     for (int k = 0; k < K; ++k) c[k] = cx[k];
