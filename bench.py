@@ -91,7 +91,7 @@ def main():
     ap.add_argument("--field-dtype", default="f32", choices=["f32", "bf16"])
     ap.add_argument("--start", default="both", choices=["plain", "learned", "both"],
                     help="both = plain, learned (screened fallback) and learned without screening")
-    ap.add_argument("--train-steps", type=int, default=60000)
+    ap.add_argument("--train-steps", type=int, default=120000)
     ap.add_argument("--train-volumes", type=int, default=10)
     ap.add_argument("--no-overlap", action="store_true",
                     help="run the tile correlations on the same stream as the extractions")
