@@ -101,7 +101,7 @@ def main():
                     help="fallback calibration: accepted learned voxels off by > 1 deg at most this often")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
@@ -230,7 +230,7 @@ def main():
     n_peaks = int(R["pk"].shape[0])
     n_tiles = len(R["eng"].boxes)
 
-    # accuracy gate: learned vs plain (plain is the judge) on the voxels that matter
+    # accuracy gate: learned vs plain (plain is the reference) on the voxels that matter
     gate = None
     if "learned" in results and "plain" in results:
         gate = accuracy_gate(results["plain"], results["learned"], lo, hi, top_p, ttm, torch)

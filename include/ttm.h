@@ -61,7 +61,7 @@ typedef enum {
   TTM_EINVAL = -1,        /* bad argument (shape, degree, pointer, option) */
   TTM_ENOMEM = -2,        /* context allocation failed                      */
   TTM_EDEVICE = -3,       /* HIP runtime or device error                    */
-  TTM_EUNSUPPORTED = -4,  /* valid request outside what this build computes */
+  TTM_EUNSUPPORTED = -4,  /* valid request outside what the library computes */
   TTM_EWORKSPACE = -5     /* workspace smaller than ttm_workspace_size()    */
 } ttm_status;
 
@@ -104,7 +104,7 @@ size_t ttm_spectrum_elems(int fft_n);
 /* Complex elements of one template spectrum from ttm_template_spectra:
  * L * (N/2 + 1) * N, or 0 for an unsupported edge or L outside 1..fft_n. */
 size_t ttm_template_spectrum_elems(int fft_n, int L);
-/* FFT edges this build supports (powers of two 32..512): 1 if supported. */
+/* FFT edges the library supports (powers of two 32..512): 1 if supported. */
 int ttm_fft_supported(int fft_n);
 
 /* Workspace bytes for an operation at FFT edge fft_n on an nz x ny x nx

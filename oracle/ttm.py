@@ -17,7 +17,7 @@ Everything here is the plain definition written out, in the paper's order:
                                                                -> find_peaks
 * rotation-sampled TM c(x, R) = w (f * t'_R) (Eq. lncc)        -> brute_force_tm
 
-Readings of points the paper leaves open (each is listed in the design doc):
+Readings of points the paper leaves open:
 * the image operator S reduces to h* on the image; the mask acts through t'
   and w; correlation outputs exist only on the valid region, where the whole
   template box lies inside the volume, and are 0 elsewhere;
