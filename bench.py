@@ -279,7 +279,7 @@ def main():
     corr_roof = {"bound": "hbm", "kernel": f"ttm_correlate, full {fft_n}^3 tile",
                  "achieved": corr_bytes / (corr_full_avg / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
                  "unit": "GB/s", "avg_launch_ms": corr_full_avg, "bytes_per_launch": corr_bytes,
-                 "traffic": None}
+                 "traffic": measured_traffic(fft_n, K)}
     corr_roof["frac"] = corr_roof["achieved"] / HBM_PEAK_GBS
     # the stage with the larger event-timed total is reported as "roofline"
     ext_roof = roofline
@@ -556,6 +556,24 @@ def precision_report(args, cfg_name, fft_n, top_p, n_sample=150):
             "angle_max_deg_unambiguous": float(np.max(a[ok])) if ok.any() else None,
             "unambiguous": int(ok.sum())}
     return out
+
+
+def measured_traffic(fft_n, K):
+    """HBM bytes of one full-tile correlation from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs summarised in profiles/, or None when the FFT kernel sources
+    differ from the ones measured (or the tile edge / component count differs)."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        rec = json.load(open(os.path.join(root, "profiles", "traffic_correlate_512tile_c3.json")))
+        h = hashlib.sha256()
+        for f in rec["sources"]:
+            h.update(open(os.path.join(root, f), "rb").read())
+    except (OSError, ValueError, KeyError):
+        return None
+    if h.hexdigest() != rec["sha256"] or rec["fft_n"] != fft_n or rec["K"] != K:
+        return None
+    return rec["bytes_per_launch"]
 
 
 def cpu_baseline(wl, Q, n, L, r, sample):
