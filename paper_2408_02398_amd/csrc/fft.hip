@@ -105,7 +105,8 @@ __global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) void k_r2c_x(RealSrc src, 
 // ---------------------------------------------------------------- Y (rows)
 template <int N, bool INV>
 __global__ __launch_bounds__((128 / Plan<N>::T > 0 ? 128 / Plan<N>::T : 1) * Plan<N>::T) void
-k_c2c_rows(cf* __restrict__ data, size_t batch_stride, int row_limit, const cf* __restrict__ tw) {
+k_c2c_rows(cf* __restrict__ data, size_t batch_stride, int row_limit, int out_limit,
+           const cf* __restrict__ tw) {
   constexpr int T = Plan<N>::T, E = N / T, RB = (128 / T > 0 ? 128 / T : 1);
   constexpr int S = lds_stride<N>();
   __shared__ cf xl[RB * S];
@@ -115,7 +116,9 @@ k_c2c_rows(cf* __restrict__ data, size_t batch_stride, int row_limit, const cf* 
   FftTw<N> twr;
   twr.load(tw, t);
   // rows are (z, kx): z = row / (N/2+1); rows with z >= row_limit are not
-  // needed and may lie past the end of the buffer, so they are not touched
+  // needed and may lie past the end of the buffer, so they are not touched.
+  // Only the first out_limit outputs of a row are stored (the inverse pass
+  // keeps the crop's rows; the X pass reads no others).
   if ((int)(blockIdx.x * RB) / (N / 2 + 1) >= row_limit) return;  // uniform per workgroup
   const bool live = row / (N / 2 + 1) < row_limit;
   cf* base = data + blockIdx.y * batch_stride + (size_t)row * N;
@@ -125,7 +128,9 @@ k_c2c_rows(cf* __restrict__ data, size_t batch_stride, int row_limit, const cf* 
   fft_1d<N, INV, true>(v, xl + r * S, twr, t);  // each row's transform lies in one wavefront
   if (live) {
 #pragma unroll
-    for (int j = 0; j < E; ++j) base[t + T * j] = v[j];
+    for (int j = 0; j < E; ++j) {
+      if (t + T * j < out_limit) base[t + T * j] = v[j];
+    }
   }
 }
 
@@ -283,12 +288,16 @@ __global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) __attribute__((amdgpu_wave
   const cf* in = spec + b * spec_stride + (size_t)z * NH * N + y0;
   {
     // all loads first (indices clamped, so every one is in bounds), then the
-    // LDS stores: the loads are in flight together
+    // LDS stores: the loads are in flight together.  Rows past the crop were
+    // not stored by the Y pass; they are read as zeros (each is paired with a
+    // kept row in one complex transform, so it must be finite).
+    const int nrows_in = min(kRowsX, dst.sy - y0);
     cf ld[IT];
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       const int e = min(tid + i * NTH, NIN - 1);
-      ld[i] = at_byte(in, (unsigned)((e / kRowsX) * N + e % kRowsX) * 8u);
+      ld[i] = e % kRowsX < nrows_in ? at_byte(in, (unsigned)((e / kRowsX) * N + e % kRowsX) * 8u)
+                                    : cf{0.0f, 0.0f};
     }
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
@@ -397,7 +406,7 @@ int forward_n(const RealSrc& src, int batch, cf* spec, size_t spec_stride, const
   constexpr int RB = (128 / T > 0 ? 128 / T : 1);
   constexpr int NROWS = N * (N / 2 + 1);
   hipLaunchKernelGGL((k_c2c_rows<N, false>), dim3(NROWS / RB, batch), dim3(RB * T), 0, s, spec,
-                     spec_stride, N, tw);
+                     spec_stride, N, N, tw);
   constexpr int CB = ColBlock<N>::CB;
   hipLaunchKernelGGL((k_c2c_cols<N, false>), dim3(NROWS / CB, batch), dim3(CB * T), 0, s, spec,
                      spec_stride, tw);
@@ -414,7 +423,7 @@ int forward_planes_n(const RealSrc& src, int batch, int planes, cf* out, size_t 
   constexpr int RB = (128 / T > 0 ? 128 / T : 1);
   const int rows = planes * (N / 2 + 1);
   hipLaunchKernelGGL((k_c2c_rows<N, false>), dim3((rows + RB - 1) / RB, batch), dim3(RB * T), 0, s,
-                     out, out_stride, planes, tw);
+                     out, out_stride, planes, N, tw);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : hip_status(e, "fft forward launch");
 }
@@ -449,7 +458,7 @@ int inverse_n(const cf* G, const cf* Sp, size_t s_stride, int s_planes, int A, c
   }
   constexpr int RB = (128 / T > 0 ? 128 / T : 1);
   hipLaunchKernelGGL((k_c2c_rows<N, true>), dim3(NROWS / RB, A), dim3(RB * T), 0, s, work,
-                     work_stride, zlim, tw);
+                     work_stride, zlim, dst.sy, tw);
   hipLaunchKernelGGL(k_c2r_x<N>, dim3(A * (N / kRowsX) * N), dim3(kRowsX / 2 * T), 0, s, work,
                      work_stride, A, dst, tw);
   hipError_t e = hipGetLastError();

@@ -58,14 +58,20 @@ __global__ __launch_bounds__(256) void k_hist(const float* __restrict__ score, R
   const int z = r.z0 + blockIdx.z;
   const int nxv = r.x1 - r.x0 + 1;
   // scores crowd into few bins: a thread counts a run of equal bins in a
-  // register and adds it at once, instead of one contended LDS atomic each
+  // register and adds it at once, instead of one contended LDS atomic each.
+  // A thread takes one column x of the 8 rows at a time, its 8 loads in
+  // flight together.
+  const int nyv = min(8, r.y1 - (r.y0 + (int)blockIdx.y * 8) + 1);
+  const float* col0 = score + ((size_t)z * r.ny + r.y0 + blockIdx.y * 8) * r.nx + r.x0;
   unsigned cur = 0xFFFFFFFFu, run = 0;
-  for (int yy = 0; yy < 8; ++yy) {
-    const int y = r.y0 + blockIdx.y * 8 + yy;
-    if (y > r.y1) break;
-    const float* row = score + ((size_t)z * r.ny + y) * r.nx + r.x0;
-    for (int x = blockIdx.x * 256 + threadIdx.x; x < nxv; x += 256 * gridDim.x) {
-      const unsigned b = score_bits(row[x]);
+  for (int x = blockIdx.x * 256 + threadIdx.x; x < nxv; x += 256 * gridDim.x) {
+    float v[8];
+#pragma unroll
+    for (int yy = 0; yy < 8; ++yy) v[yy] = yy < nyv ? col0[(size_t)yy * r.nx + x] : 0.0f;
+#pragma unroll
+    for (int yy = 0; yy < 8; ++yy) {
+      if (yy >= nyv) break;
+      const unsigned b = score_bits(v[yy]);
       unsigned bin = 0xFFFFFFFFu;
       if (level == 0) {
         bin = b >> 20;
@@ -217,12 +223,16 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy(GreedyArgs g) {
   }
   __syncthreads();
   const size_t yx = (size_t)g.ny * g.nx;
+  // each chunk's keys are loaded one chunk ahead
+  unsigned long long key_next = tid < g.m ? g.keys[tid] : 0ull;
   for (int base = 0; base < g.m; base += kGreedyThreads) {
     const int idx = base + tid;
+    const unsigned long long key_cur = key_next;
+    if (idx + kGreedyThreads < g.m) key_next = g.keys[idx + kGreedyThreads];
     int cz = 0, cy = 0, cxx = 0;
     bool alive = false;
     if (idx < g.m) {
-      const unsigned long long key = g.keys[idx];
+      const unsigned long long key = key_cur;
       const size_t lin = (size_t)(key & 0xffffffffull);
       cz = (int)(lin / yx);
       cy = (int)((lin / g.nx) % g.ny);
@@ -285,18 +295,25 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy(GreedyArgs g) {
             if (ddz * ddz + ddy * ddy + ddx * ddx < g.d2) cand = false;
           }
         }
-        // conflicts with the group's survivors ahead of this one
+        // conflicts with the group's survivors ahead of this one, whose
+        // coordinates are read from the lanes that hold them (gn and j are
+        // the same on every lane, so these are plain lane reads)
+        const int gn = min(64, ns - g0);
         unsigned long long conf = 0;
-        for (int j = 0; j < lane && g0 + j < ns; ++j) {
-          const float ddz = (float)(z - sz[g0 + j]), ddy = (float)(y - sy[g0 + j]),
-                      ddx = (float)(x - sx[g0 + j]);
-          if (ddz * ddz + ddy * ddy + ddx * ddx < g.d2) conf |= 1ull << j;
+        for (int j = 0; j < gn; ++j) {
+          const int zj = __builtin_amdgcn_readlane(z, j), yj = __builtin_amdgcn_readlane(y, j),
+                    xj = __builtin_amdgcn_readlane(x, j);
+          const float ddz = (float)(z - zj), ddy = (float)(y - yj), ddx = (float)(x - xj);
+          if (j < lane && ddz * ddz + ddy * ddy + ddx * ddx < g.d2) conf |= 1ull << j;
         }
         const unsigned long long cands = __ballot(cand);
+        const unsigned conf_lo = (unsigned)conf, conf_hi = (unsigned)(conf >> 32);
         unsigned long long kept = 0;
         int room = g.top_p - nkept;
-        for (int l = 0; l < 64 && room > 0; ++l) {
-          const unsigned long long cl = __shfl(conf, l);
+        for (int l = 0; l < gn && room > 0; ++l) {
+          const unsigned long long cl =
+              ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)conf_hi, l) << 32) |
+              (unsigned)__builtin_amdgcn_readlane((int)conf_lo, l);
           if (((cands >> l) & 1ull) && !(cl & kept)) {
             kept |= 1ull << l;
             --room;
