@@ -20,6 +20,7 @@
 //      in-order acceptance on those masks).
 // If fewer than P peaks are found while lower-ranked voxels remain, the host
 // doubles `want` and repeats.
+#include <climits>
 #include <cstring>
 #include <vector>
 
@@ -133,8 +134,17 @@ __global__ __launch_bounds__(1024) void k_scan(unsigned* __restrict__ a, int n) 
   const int t = threadIdx.x;
   const int per = (n + 1023) / 1024;
   const int lo = min(n, t * per), hi = min(n, lo + per);
+  // each thread's segment in batches of 8 loads in flight
   unsigned s = 0;
-  for (int i = lo; i < hi; ++i) s += a[i];
+  int i = lo;
+  for (; i + 8 <= hi; i += 8) {
+    unsigned v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = a[i + k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += v[k];
+  }
+  for (; i < hi; ++i) s += a[i];
   part[t] = s;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
@@ -144,7 +154,17 @@ __global__ __launch_bounds__(1024) void k_scan(unsigned* __restrict__ a, int n) 
     __syncthreads();
   }
   unsigned run = (t == 0) ? 0u : part[t - 1];
-  for (int i = lo; i < hi; ++i) {
+  for (i = lo; i + 8 <= hi; i += 8) {
+    unsigned v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = a[i + k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      a[i + k] = run;
+      run += v[k];
+    }
+  }
+  for (; i < hi; ++i) {
     const unsigned v = a[i];
     a[i] = run;
     run += v;
@@ -193,9 +213,17 @@ constexpr int kGreedyThreads = 1024;
 constexpr int kMaxPeaks = 2048;
 constexpr int kMaxCells = 16384;
 
+// The kept peaks' spatial hash as the greedy leaves it in global memory for
+// the filter and for the next walk: head[kMaxCells], then next, pz, py, px
+// (kMaxPeaks each), all 16-bit.
+constexpr int kHashShorts = kMaxCells + 4 * kMaxPeaks;
+
 struct GreedyArgs {
   const unsigned long long* keys;
   int m;                  // number of candidate keys (sorted ascending)
+  const int* m_dev;       // if set, the number of keys is read here instead
+  int limit;              // walk at most this many keys (a multiple of the chunk)
+  int resume;             // 1: continue from the peaks (and hash) already kept
   int nz, ny, nx;
   float d2;               // squared exclusion distance
   float cell;             // hash cell edge (>= exclusion distance)
@@ -204,76 +232,134 @@ struct GreedyArgs {
   int* peaks;             // top_p x 3
   float* vals;
   int* n_found;           // device
+  short* hash;            // kHashShorts, device
 };
 
+// Candidates per thread and chunk: the chunk's four hash lookups per thread
+// are issued together, and each chunk's barriers serve 4 * kGreedyThreads
+// candidates.
+constexpr int kGreedyPer = 4;
+constexpr int kGreedyChunk = kGreedyThreads * kGreedyPer;
+
 __global__ __launch_bounds__(kGreedyThreads) void k_greedy(GreedyArgs g) {
+  constexpr int NW = kGreedyThreads / 64;
   __shared__ short head[kMaxCells];
   __shared__ short next[kMaxPeaks];
   __shared__ short pz[kMaxPeaks], py[kMaxPeaks], px[kMaxPeaks];
-  __shared__ short sz[kGreedyThreads], sy[kGreedyThreads], sx[kGreedyThreads];
-  __shared__ int srank[kGreedyThreads];   // rank within the chunk of each survivor
-  __shared__ int wsum[kGreedyThreads / 64];
-  __shared__ int nkept, stop;
+  __shared__ short sz[kGreedyChunk], sy[kGreedyChunk], sx[kGreedyChunk];
+  __shared__ int srank[kGreedyChunk];   // rank within the chunk of each survivor
+  __shared__ int wsum[kGreedyPer * NW];
+  __shared__ int nkept, stop, mlen;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int ncell = g.gz * g.gy * g.gx;
-  for (int i = tid; i < ncell; i += kGreedyThreads) head[i] = (short)-1;
+  short* gnext = g.hash + kMaxCells;
+  short* gpz = gnext + kMaxPeaks;
+  short* gpy = gpz + kMaxPeaks;
+  short* gpx = gpy + kMaxPeaks;
   if (tid == 0) {
-    nkept = 0;
-    stop = 0;
+    nkept = g.resume ? *g.n_found : 0;
+    stop = nkept >= g.top_p ? 1 : 0;
+    mlen = g.m_dev ? *g.m_dev : g.m;
   }
   __syncthreads();
-  const size_t yx = (size_t)g.ny * g.nx;
-  // each chunk's keys are loaded one chunk ahead
-  unsigned long long key_next = tid < g.m ? g.keys[tid] : 0ull;
-  for (int base = 0; base < g.m; base += kGreedyThreads) {
-    const int idx = base + tid;
-    const unsigned long long key_cur = key_next;
-    if (idx + kGreedyThreads < g.m) key_next = g.keys[idx + kGreedyThreads];
-    int cz = 0, cy = 0, cxx = 0;
-    bool alive = false;
-    if (idx < g.m) {
-      const unsigned long long key = key_cur;
-      const size_t lin = (size_t)(key & 0xffffffffull);
-      cz = (int)(lin / yx);
-      cy = (int)((lin / g.nx) % g.ny);
-      cxx = (int)(lin % g.nx);
-      alive = true;
-      const int hz = (int)(cz / g.cell), hy = (int)(cy / g.cell), hx = (int)(cxx / g.cell);
-      for (int dz = -1; dz <= 1 && alive; ++dz) {
-        const int z2 = hz + dz;
-        if (z2 < 0 || z2 >= g.gz) continue;
-        for (int dy = -1; dy <= 1 && alive; ++dy) {
-          const int y2 = hy + dy;
-          if (y2 < 0 || y2 >= g.gy) continue;
-          for (int dx = -1; dx <= 1 && alive; ++dx) {
-            const int x2 = hx + dx;
-            if (x2 < 0 || x2 >= g.gx) continue;
-            for (int p = head[(z2 * g.gy + y2) * g.gx + x2]; p >= 0; p = next[p]) {
-              const float ddz = (float)(cz - pz[p]), ddy = (float)(cy - py[p]),
-                          ddx = (float)(cxx - px[p]);
-              if (ddz * ddz + ddy * ddy + ddx * ddx < g.d2) {
-                alive = false;
-                break;
-              }
-            }
+  if (stop) return;  // uniform: the peaks are complete
+  if (g.resume) {
+    for (int i = tid; i < ncell; i += kGreedyThreads) head[i] = g.hash[i];
+    for (int k = tid; k < nkept; k += kGreedyThreads) {
+      next[k] = gnext[k];
+      pz[k] = gpz[k];
+      py[k] = gpy[k];
+      px[k] = gpx[k];
+    }
+  } else {
+    for (int i = tid; i < ncell; i += kGreedyThreads) head[i] = (short)-1;
+  }
+  __syncthreads();
+  const int mm = min(mlen, g.limit);
+  // linear indices fit the key's low 32 bits and ny * nx < 2^30 (edges are
+  // below 2^15), so the decode divides in 32 bits
+  const unsigned yx = (unsigned)g.ny * (unsigned)g.nx, nxu = (unsigned)g.nx;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  // candidate k of a thread in a chunk has rank k * kGreedyThreads + tid; its
+  // key is loaded one chunk ahead
+  unsigned long long key_next[kGreedyPer];
+#pragma unroll
+  for (int k = 0; k < kGreedyPer; ++k) {
+    const int i = k * kGreedyThreads + tid;
+    key_next[k] = i < mm ? g.keys[i] : 0ull;
+  }
+  for (int base = 0; base < mm; base += kGreedyChunk) {
+    int cz[kGreedyPer], cy[kGreedyPer], cxx[kGreedyPer], hz[kGreedyPer], hy[kGreedyPer],
+        hx[kGreedyPer];
+    bool alive[kGreedyPer];
+#pragma unroll
+    for (int k = 0; k < kGreedyPer; ++k) {
+      const int idx = base + k * kGreedyThreads + tid;
+      alive[k] = idx < mm;
+      const unsigned lin = (unsigned)(key_next[k] & 0xffffffffull);
+      const unsigned qz = lin / yx, rz = lin - qz * yx, qy = rz / nxu;
+      cz[k] = alive[k] ? (int)qz : 0;
+      cy[k] = alive[k] ? (int)qy : 0;
+      cxx[k] = alive[k] ? (int)(rz - qy * nxu) : 0;
+      hz[k] = (int)(cz[k] / g.cell);
+      hy[k] = (int)(cy[k] / g.cell);
+      hx[k] = (int)(cxx[k] / g.cell);
+      if (idx + kGreedyChunk < mm) key_next[k] = g.keys[idx + kGreedyChunk];
+    }
+    // a candidate dies when a peak kept in an earlier chunk lies within D;
+    // such a peak sits in one of the 27 hash cells around the candidate's
+    for (int c = 0; c < 27; ++c) {
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < kGreedyPer; ++k) any = any || alive[k];
+      if (!any) break;
+      const int dz = c / 9 - 1, dy = (c / 3) % 3 - 1, dx = c % 3 - 1;
+      int p[kGreedyPer];
+#pragma unroll
+      for (int k = 0; k < kGreedyPer; ++k) {
+        const int z2 = hz[k] + dz, y2 = hy[k] + dy, x2 = hx[k] + dx;
+        const bool in = alive[k] && z2 >= 0 && z2 < g.gz && y2 >= 0 && y2 < g.gy && x2 >= 0 &&
+                        x2 < g.gx;
+        p[k] = in ? head[(z2 * g.gy + y2) * g.gx + x2] : -1;
+      }
+#pragma unroll
+      for (int k = 0; k < kGreedyPer; ++k) {
+        for (int q = p[k]; q >= 0; q = next[q]) {
+          const float ddz = (float)(cz[k] - pz[q]), ddy = (float)(cy[k] - py[q]),
+                      ddx = (float)(cxx[k] - px[q]);
+          if (ddz * ddz + ddy * ddy + ddx * ddx < g.d2) {
+            alive[k] = false;
+            break;
           }
         }
       }
     }
-    // survivors in rank order: wavefront ballots, then the waves' offsets
-    const unsigned long long bal = __ballot(alive);
-    if (lane == 0) wsum[wv] = __popcll(bal);
+    // survivors in rank order (k, then thread): wavefront ballots, then the
+    // offsets of the sub-chunks and waves ahead
+    unsigned long long bal[kGreedyPer];
+#pragma unroll
+    for (int k = 0; k < kGreedyPer; ++k) {
+      bal[k] = __ballot(alive[k]);
+      if (lane == 0) wsum[k * NW + wv] = __popcll(bal[k]);
+    }
     __syncthreads();
-    int off = 0;
-    for (int w = 0; w < wv; ++w) off += wsum[w];
     int ns = 0;
-    for (int w = 0; w < kGreedyThreads / 64; ++w) ns += wsum[w];
-    if (alive) {
-      const int pos = off + __popcll(bal & ((1ull << lane) - 1ull));
-      sz[pos] = (short)cz;
-      sy[pos] = (short)cy;
-      sx[pos] = (short)cxx;
-      srank[pos] = tid;
+#pragma unroll
+    for (int k = 0; k < kGreedyPer; ++k) {
+      int before = 0, tot = 0;
+      for (int w = 0; w < NW; ++w) {
+        const int v = wsum[k * NW + w];
+        before += w < wv ? v : 0;
+        tot += v;
+      }
+      if (alive[k]) {
+        const int pos = ns + before + __popcll(bal[k] & lt);
+        sz[pos] = (short)cz[k];
+        sy[pos] = (short)cy[k];
+        sx[pos] = (short)cxx[k];
+        srank[pos] = k * kGreedyThreads + tid;
+      }
+      ns += tot;
     }
     __syncthreads();
     // settle the survivors in order, 64 at a time on wavefront 0: a survivor
@@ -350,7 +436,187 @@ __global__ __launch_bounds__(kGreedyThreads) void k_greedy(GreedyArgs g) {
     __syncthreads();
     if (stop) break;
   }
-  if (tid == 0) *g.n_found = nkept;
+  // the hash and the count for the filter and the next walk
+  const int nk = nkept;
+  for (int i = tid; i < ncell; i += kGreedyThreads) g.hash[i] = head[i];
+  for (int k = tid; k < nk; k += kGreedyThreads) {
+    gnext[k] = next[k];
+    gpz[k] = pz[k];
+    gpy[k] = py[k];
+    gpx[k] = px[k];
+  }
+  if (tid == 0) *g.n_found = nk;
+}
+
+// ---------------------------------------------------------------- filter
+// Between two walks the rest of the sorted list is filtered on the whole
+// GPU: a key dies when a peak kept so far lies within D (it could never be
+// kept later, and only kept peaks decide anything), and the survivors are
+// written in their order.  k_filter<false> counts the survivors of each
+// block of kSortTile keys, k_scan turns the counts into offsets (the extra
+// last entry becomes the total), k_filter<true> writes the survivors and the
+// new list length.
+struct FilterArgs {
+  const unsigned long long* keys;
+  int from;               // first key to filter (the walk took the keys before)
+  int m;                  // list length, or
+  const int* m_dev;       // read here when set
+  int ny, nx;
+  float d2, cell;
+  int gz, gy, gx;
+  int top_p;
+  const int* n_found;
+  const short* hash;      // as the greedy leaves it
+  unsigned* counts;       // nb + 1 entries
+  int nb;
+  unsigned long long* out;
+  int* m_next;
+};
+
+template <bool SCATTER>
+__global__ __launch_bounds__(kSortBlock) void k_filter(FilterArgs f) {
+  constexpr int NW = kSortBlock / 64;
+  __shared__ short head[kMaxCells];
+  __shared__ short next[kMaxPeaks], pz[kMaxPeaks], py[kMaxPeaks], px[kMaxPeaks];
+  __shared__ unsigned wcnt[kSortIPT][NW];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int np = *f.n_found;
+  const int m = f.m_dev ? *f.m_dev : f.m;
+  const bool done = np >= f.top_p;
+  const int base = f.from + (int)blockIdx.x * kSortTile;
+  if (blockIdx.x == 0 && tid == 0) {
+    if (SCATTER) {
+      *f.m_next = done ? 0 : (int)f.counts[f.nb];
+    } else {
+      f.counts[f.nb] = 0u;
+    }
+  }
+  if (done || base >= m) {  // uniform per workgroup
+    if (!SCATTER && tid == 0) f.counts[blockIdx.x] = 0u;
+    return;
+  }
+  const int ncell = f.gz * f.gy * f.gx;
+  for (int i = tid; i < ncell; i += kSortBlock) head[i] = f.hash[i];
+  for (int k = tid; k < np; k += kSortBlock) {
+    next[k] = f.hash[kMaxCells + k];
+    pz[k] = f.hash[kMaxCells + kMaxPeaks + k];
+    py[k] = f.hash[kMaxCells + 2 * kMaxPeaks + k];
+    px[k] = f.hash[kMaxCells + 3 * kMaxPeaks + k];
+  }
+  __syncthreads();
+  const unsigned yx = (unsigned)f.ny * (unsigned)f.nx, nxu = (unsigned)f.nx;
+  unsigned long long key[kSortIPT];
+  bool alive[kSortIPT];
+#pragma unroll
+  for (int j = 0; j < kSortIPT; ++j) {
+    const int i = base + j * kSortBlock + tid;
+    alive[j] = i < m;
+    key[j] = alive[j] ? f.keys[i] : 0ull;
+  }
+  for (int j = 0; j < kSortIPT; ++j) {
+    if (!alive[j]) continue;
+    const unsigned lin = (unsigned)(key[j] & 0xffffffffull);
+    const unsigned qz = lin / yx, rz = lin - qz * yx, qy = rz / nxu;
+    const int cz = (int)qz, cy = (int)qy, cxx = (int)(rz - qy * nxu);
+    const int hz = (int)(cz / f.cell), hy = (int)(cy / f.cell), hx = (int)(cxx / f.cell);
+    bool al = true;
+    for (int c = 0; c < 27 && al; ++c) {
+      const int z2 = hz + c / 9 - 1, y2 = hy + (c / 3) % 3 - 1, x2 = hx + c % 3 - 1;
+      if (z2 < 0 || z2 >= f.gz || y2 < 0 || y2 >= f.gy || x2 < 0 || x2 >= f.gx) continue;
+      for (int q = head[(z2 * f.gy + y2) * f.gx + x2]; q >= 0; q = next[q]) {
+        const float ddz = (float)(cz - pz[q]), ddy = (float)(cy - py[q]), ddx = (float)(cxx - px[q]);
+        if (ddz * ddz + ddy * ddy + ddx * ddx < f.d2) {
+          al = false;
+          break;
+        }
+      }
+    }
+    alive[j] = al;
+  }
+  // survivors of each slice j, per wavefront; ranks follow (j, thread)
+  unsigned long long bal[kSortIPT];
+#pragma unroll
+  for (int j = 0; j < kSortIPT; ++j) {
+    bal[j] = __ballot(alive[j]);
+    if (lane == 0) wcnt[j][wv] = __popcll(bal[j]);
+  }
+  __syncthreads();
+  if (!SCATTER) {
+    if (tid == 0) {
+      unsigned t = 0;
+      for (int j = 0; j < kSortIPT; ++j)
+        for (int w = 0; w < NW; ++w) t += wcnt[j][w];
+      f.counts[blockIdx.x] = t;
+    }
+    return;
+  }
+  unsigned run = f.counts[blockIdx.x];
+  const unsigned long long lt = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int j = 0; j < kSortIPT; ++j) {
+    unsigned before = 0, tot = 0;
+    for (int w = 0; w < NW; ++w) {
+      const unsigned v = wcnt[j][w];
+      before += w < wv ? v : 0u;
+      tot += v;
+    }
+    if (alive[j]) f.out[run + before + __popcll(bal[j] & lt)] = key[j];
+    run += tot;
+  }
+}
+
+// Index bytes of the keys (their low 32 bits) that are zero for every linear
+// index of the map need no radix pass: the pass would keep the order.  The
+// padding keys (all ones) still sort after every real key, because the real
+// keys' index bytes that are sorted already stay below theirs or, at equality,
+// stable passes keep the real keys (placed first) ahead.
+bool index_byte_constant(int shift, const Region& r) {
+  const unsigned long long total = (unsigned long long)r.nz * r.ny * r.nx;
+  return shift < 32 && total <= (1ull << shift);
+}
+
+constexpr int kWalkRounds = 3;                // short walks, each followed by a filter
+constexpr int kWalkKeys = 2 * kGreedyChunk;    // keys per short walk
+
+// Bytes of the workspace before its tail (keys, histograms, counters,
+// sort counts), and the tail: the kept peaks' hash and the list lengths.
+size_t peaks_head_bytes(int64_t n_voxels) {
+  const size_t cand = (size_t)n_voxels + kSortTile;
+  const size_t nblk = (cand + kSortTile - 1) / kSortTile;
+  const size_t b = 2 * cand * 8 + kHistBins * 4 + 256 * nblk * 4 + 256 + 1024;
+  return (b + 255) / 256 * 256;
+}
+constexpr size_t kPeaksTailBytes = kHashShorts * 2 + 256;
+
+// The greedy walk over m sorted keys in `srt` (`spare` holds as many):
+// kWalkRounds times a walk over the first kWalkKeys keys of the list and the
+// filter of the rest into the other buffer, then a walk over what is left.
+// The result equals one walk over all m keys: a filtered key was within D of
+// a peak kept before it, and the survivors keep their order.
+void greedy_walks(unsigned long long* srt, unsigned long long* spare, size_t m, const Region& r,
+                  float min_dist, float cell, int gz, int gy, int gx, int top_p, int32_t* peaks,
+                  float* vals, int32_t* n_found, unsigned* counts, char* tail, hipStream_t s) {
+  short* hash = reinterpret_cast<short*>(tail);
+  int* mdev = reinterpret_cast<int*>(tail + kHashShorts * 2);
+  const int nb = m > (size_t)kWalkKeys ? (int)((m - kWalkKeys + kSortTile - 1) / kSortTile) : 0;
+  unsigned long long* cur = srt;
+  unsigned long long* other = spare;
+  const int* mcur = nullptr;
+  const float d2 = min_dist * min_dist;
+  for (int round = 0;; ++round) {
+    const bool last = round == kWalkRounds || nb == 0;
+    GreedyArgs ga{cur, (int)m, mcur, last ? INT_MAX : kWalkKeys, round > 0 ? 1 : 0, r.nz, r.ny,
+                  r.nx, d2, cell, gz, gy, gx, top_p, peaks, vals, n_found, hash};
+    hipLaunchKernelGGL(k_greedy, dim3(1), dim3(kGreedyThreads), 0, s, ga);
+    if (last) break;
+    FilterArgs fa{cur, kWalkKeys, (int)m, mcur, r.ny, r.nx, d2, cell, gz, gy, gx, top_p, n_found,
+                  hash, counts, nb, other, mdev + round};
+    hipLaunchKernelGGL(k_filter<false>, dim3(nb), dim3(kSortBlock), 0, s, fa);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, nb + 1);
+    hipLaunchKernelGGL(k_filter<true>, dim3(nb), dim3(kSortBlock), 0, s, fa);
+    mcur = mdev + round;
+    std::swap(cur, other);
+  }
 }
 
 }  // namespace
@@ -396,23 +662,21 @@ int find_peaks_async(const float* score, int nz, int ny, int nx, const int32_t l
   unsigned long long* src = keys_a;
   unsigned long long* dst = keys_b;
   for (int shift = 0; shift < 64; shift += 8) {
+    if (index_byte_constant(shift, r)) continue;
     hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(kSortBlock), 0, s, src, shift, shist, nblk);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, shist, 256 * nblk);
     hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(kSortBlock), 0, s, src, dst, shift, shist,
                        nblk);
     std::swap(src, dst);
   }
-  GreedyArgs ga{src, (int)m, nz, ny, nx, min_dist * min_dist, cell, gz, gy, gx, top_p,
-                peaks_out, vals_out, n_found_dev};
-  hipLaunchKernelGGL(k_greedy, dim3(1), dim3(kGreedyThreads), 0, s, ga);
+  greedy_walks(src, dst, m, r, min_dist, cell, gz, gy, gx, top_p, peaks_out, vals_out,
+               n_found_dev, shist, w + peaks_head_bytes(nvalid), s);
   TTM_HIP(hipGetLastError());
   return 0;
 }
 
 size_t peaks_workspace(int64_t n_voxels) {
-  const size_t cand = (size_t)n_voxels + kSortTile;
-  const size_t nblk = (cand + kSortTile - 1) / kSortTile;
-  return 2 * cand * 8 + kHistBins * 4 + 256 * nblk * 4 + 256 + 1024;
+  return peaks_head_bytes(n_voxels) + kPeaksTailBytes;
 }
 
 int find_peaks(const float* score, int nz, int ny, int nx, const int32_t lo[3],
@@ -496,15 +760,15 @@ int find_peaks(const float* score, int nz, int ny, int nx, const int32_t lo[3],
     unsigned long long* src = keys_a;
     unsigned long long* dst = keys_b;
     for (int shift = 0; shift < 64; shift += 8) {
+      if (index_byte_constant(shift, r)) continue;
       hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(kSortBlock), 0, s, src, shift, shist, nblk);
       hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, shist, 256 * nblk);
       hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(kSortBlock), 0, s, src, dst, shift, shist,
                          nblk);
       std::swap(src, dst);
     }
-    GreedyArgs ga{src, (int)m, nz, ny, nx, min_dist * min_dist, cell, gz, gy, gx, top_p,
-                  peaks_out, vals_out, nfound_dev};
-    hipLaunchKernelGGL(k_greedy, dim3(1), dim3(kGreedyThreads), 0, s, ga);
+    greedy_walks(src, dst, (size_t)m, r, min_dist, cell, gz, gy, gx, top_p, peaks_out, vals_out,
+                 nfound_dev, shist, w + peaks_head_bytes(nvalid), s);
     TTM_HIP(hipGetLastError());
     int nf = 0;
     TTM_HIP(hipMemcpyAsync(&nf, nfound_dev, 4, hipMemcpyDeviceToHost, s));
