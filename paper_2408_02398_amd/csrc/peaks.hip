@@ -235,10 +235,12 @@ struct GreedyArgs {
   short* hash;            // kHashShorts, device
 };
 
-// Candidates per thread and chunk: the chunk's four hash lookups per thread
-// are issued together, and each chunk's barriers serve 4 * kGreedyThreads
-// candidates.
-constexpr int kGreedyPer = 4;
+// Candidates per thread and chunk.  More than one lets a thread issue its
+// hash lookups together and a chunk's barriers serve more keys, but then more
+// keys reach the serial settle before the hash learns of the peaks kept in
+// their chunk; with many peaks (thousands at 2r apart) one per thread is
+// faster.
+constexpr int kGreedyPer = 1;
 constexpr int kGreedyChunk = kGreedyThreads * kGreedyPer;
 
 __global__ __launch_bounds__(kGreedyThreads) void k_greedy(GreedyArgs g) {
@@ -576,7 +578,7 @@ bool index_byte_constant(int shift, const Region& r) {
 }
 
 constexpr int kWalkRounds = 3;                // short walks, each followed by a filter
-constexpr int kWalkKeys = 2 * kGreedyChunk;    // keys per short walk
+constexpr int kWalkKeys = 8 * kGreedyChunk;    // keys per short walk
 
 // Bytes of the workspace before its tail (keys, histograms, counters,
 // sort counts), and the tail: the kept peaks' hash and the list lengths.
@@ -589,13 +591,16 @@ size_t peaks_head_bytes(int64_t n_voxels) {
 constexpr size_t kPeaksTailBytes = kHashShorts * 2 + 256;
 
 // The greedy walk over m sorted keys in `srt` (`spare` holds as many):
-// kWalkRounds times a walk over the first kWalkKeys keys of the list and the
+// `rounds` times a walk over the first kWalkKeys keys of the list and the
 // filter of the rest into the other buffer, then a walk over what is left.
 // The result equals one walk over all m keys: a filtered key was within D of
-// a peak kept before it, and the survivors keep their order.
+// a peak kept before it, and the survivors keep their order.  The rounds pay
+// when most keys die (every voxel a candidate, few peaks); over the top
+// candidates alone one walk is as fast.
 void greedy_walks(unsigned long long* srt, unsigned long long* spare, size_t m, const Region& r,
                   float min_dist, float cell, int gz, int gy, int gx, int top_p, int32_t* peaks,
-                  float* vals, int32_t* n_found, unsigned* counts, char* tail, hipStream_t s) {
+                  float* vals, int32_t* n_found, unsigned* counts, char* tail, int rounds,
+                  hipStream_t s) {
   short* hash = reinterpret_cast<short*>(tail);
   int* mdev = reinterpret_cast<int*>(tail + kHashShorts * 2);
   const int nb = m > (size_t)kWalkKeys ? (int)((m - kWalkKeys + kSortTile - 1) / kSortTile) : 0;
@@ -604,7 +609,7 @@ void greedy_walks(unsigned long long* srt, unsigned long long* spare, size_t m, 
   const int* mcur = nullptr;
   const float d2 = min_dist * min_dist;
   for (int round = 0;; ++round) {
-    const bool last = round == kWalkRounds || nb == 0;
+    const bool last = round == rounds || nb == 0;
     GreedyArgs ga{cur, (int)m, mcur, last ? INT_MAX : kWalkKeys, round > 0 ? 1 : 0, r.nz, r.ny,
                   r.nx, d2, cell, gz, gy, gx, top_p, peaks, vals, n_found, hash};
     hipLaunchKernelGGL(k_greedy, dim3(1), dim3(kGreedyThreads), 0, s, ga);
@@ -670,7 +675,7 @@ int find_peaks_async(const float* score, int nz, int ny, int nx, const int32_t l
     std::swap(src, dst);
   }
   greedy_walks(src, dst, m, r, min_dist, cell, gz, gy, gx, top_p, peaks_out, vals_out,
-               n_found_dev, shist, w + peaks_head_bytes(nvalid), s);
+               n_found_dev, shist, w + peaks_head_bytes(nvalid), kWalkRounds, s);
   TTM_HIP(hipGetLastError());
   return 0;
 }
@@ -768,7 +773,7 @@ int find_peaks(const float* score, int nz, int ny, int nx, const int32_t lo[3],
       std::swap(src, dst);
     }
     greedy_walks(src, dst, (size_t)m, r, min_dist, cell, gz, gy, gx, top_p, peaks_out, vals_out,
-                 nfound_dev, shist, w + peaks_head_bytes(nvalid), s);
+                 nfound_dev, shist, w + peaks_head_bytes(nvalid), 0, s);
     TTM_HIP(hipGetLastError());
     int nf = 0;
     TTM_HIP(hipMemcpyAsync(&nf, nfound_dev, 4, hipMemcpyDeviceToHost, s));

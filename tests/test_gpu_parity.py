@@ -293,8 +293,8 @@ def test_orientation_rank_one_and_zero(T, ctx):
 # ------------------------------------------------------------------ peaks
 @pytest.mark.parametrize("seed,shape,P,D", [(1, (20, 23, 26), 40, 3.0), (2, (40, 41, 42), 200, 5.5),
                                             (3, (9, 10, 11), 5000, 1.0),
-                                            # P beyond what fits at distance D: the walk
-                                            # takes every round and the final pass
+                                            # P beyond what fits at distance D: every
+                                            # candidate is walked
                                             (5, (40, 52, 60), 2000, 6.0)])
 def test_find_peaks_bit_exact_on_shared_map(T, ctx, seed, shape, P, D):
     rng = np.random.default_rng(seed)
