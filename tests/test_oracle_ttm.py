@@ -365,6 +365,38 @@ def test_find_peaks_brute_force_with_ties():
     assert np.array_equal(pv, s[pk[:, 0], pk[:, 1], pk[:, 2]])
 
 
+def test_find_peaks_filtered_rounds_give_the_same_peaks():
+    """Sec. 3.4's rule decides a voxel only from the peaks kept before it, so a
+    voxel within D of a peak kept from a prefix of the visiting order is never
+    kept; dropping such voxels from the rest of the order (several rounds of a
+    short walk and a filter, with P out of reach so every voxel is visited)
+    must leave the peaks unchanged."""
+    rng = np.random.default_rng(23)
+    s = np.round(rng.uniform(0, 1, (14, 16, 18)), 2)      # many exact ties
+    lo, hi = (1, 1, 2), (12, 15, 16)
+    P, D = 500, 3.5
+    pk, pv = ttm.find_peaks(s, lo, hi, P, D)
+    assert len(pk) < P                                     # every voxel is walked
+    zz, yy, xx = np.meshgrid(range(lo[0], hi[0] + 1), range(lo[1], hi[1] + 1),
+                             range(lo[2], hi[2] + 1), indexing="ij")
+    lin = (zz * 16 * 18 + yy * 18 + xx).ravel()
+    vals = s[lo[0]:hi[0] + 1, lo[1]:hi[1] + 1, lo[2]:hi[2] + 1].ravel()
+    order = np.lexsort((lin, -vals))
+    pos = np.stack([zz.ravel(), yy.ravel(), xx.ravel()], 1)[order]
+    kept, lst, walk = [], pos, 64
+    for last in (False, False, False, True):
+        n = len(lst) if last else min(walk, len(lst))
+        for p in lst[:n]:
+            if all(np.sum((p - q) ** 2) >= D * D for q in kept):
+                kept.append(p)
+        rest = lst[n:]
+        if len(rest) and kept:
+            d2 = np.min(np.sum((rest[:, None, :] - np.array(kept)[None]) ** 2, axis=-1), axis=1)
+            rest = rest[d2 >= D * D]
+        lst = rest
+    assert np.array_equal(np.array(kept), pk)
+
+
 def test_planted_copies_recovered_at_high_snr():
     w = synth.make_tomogram("p", (48, 48, 48), L=16, n_blobs=3, n_copies=4, min_sep=20,
                             mask_radius=7.0, degree=4, seed=21, snr=None, wedge=False,
