@@ -147,54 +147,64 @@ def unpad_params(flat: np.ndarray, k_in: int, d_out: int = 3) -> dict:
 
 
 def orient_learned(Cv: np.ndarray, n: int, p: dict, starts: np.ndarray, kappa: float,
-                   tol: float = 1e-5, max_iter: int = 500, newton: int = 2, bf16: bool = True,
+                   tol: float = 1e-5, max_iter: int = 500, bf16: bool = True,
                    detail: bool = False, newton_first: int = 5, u0: np.ndarray | None = None):
     """Orientation with the learned start and its multistart fallback (d' = 3).
 
-    From the network's direction u0, up to ``newton_first`` Riemannian Newton
-    steps (ttm.newton_ascent); if they do not converge, SS-HOPM (+ polish) from
-    u0 instead.  If that answer did not reach tol,
-    or lambda / ||C||_F < kappa, or some fixed start already has a larger value
-    of <C, s^n> than the learned lambda (SS-HOPM never decreases lambda, so the
-    multistart answer is then larger), the multistart search runs too and the
-    larger lambda wins.  Returns (lambda, u, fell_back), and with ``detail`` a
-    fourth item: a dict with the learned answer (lam_learned, u_learned), how
-    far each fallback test was from flipping (beat_gap = best fixed-start value
-    minus the learned lambda, kappa_gap = lambda / ||C||_F - kappa, both scaled
-    by ||C||_F where they are values of the tensor) and, after a fallback, the
-    multistart's per-start lambdas and directions.  ``u0`` (a unit vector)
-    replaces the network's direction, to probe how the answer depends on the
-    start.
+    The learned start replaces the paper's seeds of SS-HOPM (Sec. 3.1); its
+    search parameters (tol, max_iter, newton_first and the Newton search's
+    drop rule) are part of that method's definition, since they decide which
+    basin the answer comes from and whether the multistart runs:
+
+    1. u0 = y / |y| from the network (fixed start 0 where y = 0, which also
+       forces the fallback);
+    2. up to ``newton_first`` Riemannian Newton steps (ttm.newton_ascent); if
+       they do not converge, SS-HOPM from u0 with the unfolding shift until
+       |delta lambda| <= tol or max_iter updates; "converged" is the outcome of
+       the search that ran last;
+    3. the learned answer is the converged maximum of the basin the search
+       ended in (ttm.converge from its end point);
+    4. fallback when the search did not converge, lambda / ||C||_F < kappa, or
+       a fixed start s already has <C, s^n> > lambda (SS-HOPM never lowers
+       lambda, so the multistart answer is then larger): the multistart answer
+       (ttm.orient_multistart) is computed too and the larger lambda wins.
+
+    Returns (lambda, u, fell_back), and with ``detail`` a fourth item: a dict
+    with the learned answer (lam_learned, u_learned), how far each fallback
+    test was from flipping (beat_gap = best fixed-start value minus the
+    learned lambda, scaled by ||C||_F; kappa_gap = lambda / ||C||_F - kappa),
+    whether the search converged, and after a fallback the multistart's
+    per-start lambdas and directions.  ``u0`` (a unit vector) replaces the
+    network's direction, to probe how the answer depends on the start.
     """
     from . import ttm
     cn = float(sym.frobenius(Cv, n, 3))
     if cn == 0.0:
         out = (0.0, np.zeros(3), False)
         return out + ({"lam_learned": 0.0, "u_learned": np.zeros(3), "beat_gap": -np.inf,
-                       "kappa_gap": np.inf, "lams": None, "us": None},) if detail else out
+                       "kappa_gap": np.inf, "converged": True, "lams": None, "us": None},) \
+            if detail else out
+    forced = False
     if u0 is None:
         y, _ = forward(p, features(Cv[None, :], n), bf16=bf16)
         y = y[0]
         ny = np.linalg.norm(y)
-        u0 = y / ny if ny > 0 else starts[0]
-    else:
-        ny = 1.0
+        forced = not ny > 0
+        u0 = starts[0] / np.linalg.norm(starts[0]) if forced else y / ny
     Cu = np.asarray(Cv, dtype=np.float64) / cn
+    alpha = ttm.unfolding_shift(Cu, n, 3)
     u, lam, conv = ttm.newton_ascent(Cu, n, u0, newton_first, tol)
     if not conv:
-        alpha = ttm.unfolding_shift(Cu, n, 3)
         lam, u, _, conv = ttm.sshopm(Cu, n, u0, alpha, tol, max_iter)
-        u = ttm.newton_polish(Cu, n, u, newton)
-        lam = float(sym.contract_n_minus_1(Cu, u, n) @ u)
-    # a fixed start scoring above the learned answer means the multistart wins
+    lam, u, _ = ttm.converge(Cu, n, u, alpha)
     fs = max(sym.inner_power(Cu, s / np.linalg.norm(s), n) for s in starts)
     beaten = fs > lam
     info = {"lam_learned": cn * lam, "u_learned": ttm.canonical_sign(u), "beat_gap": cn * (fs - lam),
-            "kappa_gap": lam - kappa, "lams": None, "us": None}
-    if conv and ny > 0 and lam >= kappa and not beaten:
+            "kappa_gap": lam - kappa, "converged": conv, "lams": None, "us": None}
+    if conv and not forced and lam >= kappa and not beaten:
         out = (cn * lam, ttm.canonical_sign(u), False)
         return out + (info,) if detail else out
-    lam_p, u_p, lams, us, _ = ttm.orient_multistart(Cv, n, starts, tol, max_iter, newton=newton)
+    lam_p, u_p, lams, us, _ = ttm.orient_multistart(Cv, n, starts)
     info["lams"], info["us"] = lams, us
     if lam_p > cn * lam:
         out = (lam_p, u_p, True)

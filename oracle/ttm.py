@@ -12,7 +12,8 @@ Everything here is the plain definition written out, in the paper's order:
 * tensor field C_alpha = w (g * T_alpha), a correlation (Eq. tcc, Alg. 2,
   Eq. correlation), by direct spatial sums                     -> tensor_field
 * Frobenius score ||C||_F (Sec. 3.2)                           -> score
-* SS-HOPM dominant eigenpair from given starts (Sec. 3.1)      -> sshopm, orient_multistart
+* SS-HOPM dominant eigenpair from given starts (Sec. 3.1)      -> sshopm, converge,
+                                                                  orient_multistart
 * Find Peaks: P highest scores at least two mask radii apart (Sec. 3.4)
                                                                -> find_peaks
 * rotation-sampled TM c(x, R) = w (f * t'_R) (Eq. lncc)        -> brute_force_tm
@@ -29,13 +30,13 @@ Readings of points the paper leaves open:
 * w = 0 where var <= eps_w * M * mean(g^2 over the volume), eps_w = 1e-6;
 * SS-HOPM maximises the signed value, on the tensor divided by its Frobenius
   norm; its shift is alpha = max(0, -lambda_min(U)) with U the square matrix
-  unfolding (the paper's rule, Sec. 3.1); stop when |delta lambda| <= tol or
-  after max_iter steps (the paper states no stopping rule); each start's end
-  point is then polished by up to two Newton steps on the sphere, which
-  converge to the same local maximum quadratically (a step is taken only where
-  the tangent Hessian is negative definite and kept only if lambda does not
-  drop by more than 1e-7); best start by largest lambda, lowest index on ties;
-  sign canonicalised so the last non-zero coordinate is positive.
+  unfolding (the paper's rule, Sec. 3.1).  The paper states no stopping rule;
+  the oracle computes the converged maximum of each start's basin: SS-HOPM
+  until |delta lambda| <= 1e-13 or 10^4 updates, then Newton's method on the
+  sphere until lambda changes by <= 1e-15 (the same fixed point, reached
+  quadratically); best start by largest lambda, lowest index on ties; sign
+  canonicalised so the last non-zero coordinate is positive (d' = 3) or the
+  scalar part of the quaternion is (d' = 4).
 
 Parity status: every function here is pinned by tests/test_oracle_*.py
 (closed forms, invariants, brute force, textbook routines); the absolute
@@ -284,12 +285,20 @@ def score(C: np.ndarray, n: int, dprime: int = 3) -> np.ndarray:
 
 
 def canonical_sign(u: np.ndarray) -> np.ndarray:
-    """Flip u so that its last non-zero coordinate is positive (u and -u are one answer)."""
+    """u and -u are one answer.  d' = 3 (an axis): the last non-zero coordinate is
+    made positive; d' = 4 (a quaternion w, x, y, z): the first (w) is."""
     u = np.array(u, dtype=np.float64)
-    for i in range(len(u) - 1, -1, -1):
+    order = range(len(u)) if len(u) == 4 else range(len(u) - 1, -1, -1)
+    for i in order:
         if u[i] != 0.0:
             return u if u[i] > 0 else -u
     return u
+
+
+def gradient_many(Cv: np.ndarray, n: int, U: np.ndarray) -> np.ndarray:
+    """Rows of C u^{n-1} for every row u of U (S, d) -> (S, d)."""
+    mu, tab = sym._raise_table(n, U.shape[1])
+    return (mu * sym.monomials(U, n - 1)) @ np.asarray(Cv, dtype=np.float64)[tab]
 
 
 def sshopm(Cv: np.ndarray, n: int, u0, alpha: float, tol: float, max_iter: int):
@@ -297,21 +306,33 @@ def sshopm(Cv: np.ndarray, n: int, u0, alpha: float, tol: float, max_iter: int):
 
     u <- (C u^{n-1} + alpha u) / ||.||;  lambda = <C, u^{(x)n}>.
     Stops when |lambda_new - lambda| <= tol or after max_iter updates.
-    Returns (lambda, u, iterations, converged).
+    u0 is one start (d,) or several (S, d), each run on its own (a run that has
+    stopped is left as it is while the others go on).
+    Returns (lambda, u, iterations, converged), per start when u0 is 2-D.
     """
-    u = np.asarray(u0, dtype=np.float64)
-    u = u / np.linalg.norm(u)
-    g = sym.contract_n_minus_1(Cv, u, n)
-    lam = float(g @ u)
+    U = np.atleast_2d(np.asarray(u0, dtype=np.float64))
+    U = U / np.linalg.norm(U, axis=1, keepdims=True)
+    S = U.shape[0]
+    G = gradient_many(Cv, n, U)
+    lam = np.sum(G * U, axis=1)
+    its = np.zeros(S, dtype=np.int64)
+    conv = np.zeros(S, dtype=bool)
+    live = np.ones(S, dtype=bool)
     for it in range(1, max_iter + 1):
-        v = g + alpha * u
-        u = v / np.linalg.norm(v)
-        g = sym.contract_n_minus_1(Cv, u, n)
-        lam_new = float(g @ u)
-        if abs(lam_new - lam) <= tol:
-            return lam_new, u, it, True
-        lam = lam_new
-    return lam, u, max_iter, False
+        if not live.any():
+            break
+        V = G[live] + alpha * U[live]
+        Un = V / np.linalg.norm(V, axis=1, keepdims=True)
+        Gn = gradient_many(Cv, n, Un)
+        ln = np.sum(Gn * Un, axis=1)
+        idx = np.flatnonzero(live)
+        done = np.abs(ln - lam[idx]) <= tol
+        U[idx], G[idx], lam[idx], its[idx] = Un, Gn, ln, it
+        conv[idx[done]] = True
+        live[idx[done]] = False
+    if np.ndim(u0) == 1:
+        return float(lam[0]), U[0], int(its[0]), bool(conv[0])
+    return lam, U, its, conv
 
 
 def unfolding_shift(Cu: np.ndarray, n: int, d: int) -> float:
@@ -320,66 +341,88 @@ def unfolding_shift(Cu: np.ndarray, n: int, d: int) -> float:
 
 
 def tangent_basis(u: np.ndarray) -> np.ndarray:
-    """Two orthonormal vectors spanning the plane orthogonal to unit u (columns).
-
-    e1 = a x u / |a x u| with a the axis of the smallest |u_i| (first on ties),
-    e2 = u x e1.
-    """
-    a = np.zeros(3)
-    a[int(np.argmin(np.abs(u)))] = 1.0
-    e1 = np.cross(a, u)
-    e1 /= np.linalg.norm(e1)
-    return np.stack([e1, np.cross(u, e1)], axis=1)
-
-
-def newton_polish(Cu: np.ndarray, n: int, u: np.ndarray, steps: int = 2,
-                  drop: float = 1e-7) -> np.ndarray:
-    """Riemannian Newton steps for max <C, u^{(x)n}> on the unit sphere (d' = 3).
-
-    Tangent gradient E^T g and Hessian (n-1) E^T H E - lambda I of f/n, with
-    g = C u^{n-1}, H = C u^{n-2}, lambda = g.u.  A step is taken only when that
-    Hessian is negative definite, and kept only if lambda drops by <= drop.
-    """
+    """Orthonormal basis of the plane orthogonal to unit u, as d - 1 columns
+    (the last d - 1 columns of the QR factor of [u | I])."""
     u = np.asarray(u, dtype=np.float64)
-    for _ in range(steps):
-        g = sym.contract_n_minus_1(Cu, u, n)
-        lam = float(g @ u)
-        E = tangent_basis(u)
-        Ht = (n - 1) * (E.T @ sym.contract_n_minus_2(Cu, u, n) @ E) - lam * np.eye(2)
-        if not (np.linalg.det(Ht) > 0 and np.trace(Ht) < 0):
+    d = len(u)
+    Q, _ = np.linalg.qr(np.column_stack([u, np.eye(d)]))
+    return Q[:, 1:d]
+
+
+def tangent_hessian(Cu: np.ndarray, n: int, u: np.ndarray, lam: float, E: np.ndarray) -> np.ndarray:
+    """Hessian of <C, u^n> / n on the sphere in the tangent basis E:
+    (n - 1) E^T (C u^{n-2}) E - lambda I."""
+    return (n - 1) * (E.T @ sym.contract_n_minus_2(Cu, u, n) @ E) - lam * np.eye(E.shape[1])
+
+
+def newton_direction(Cu: np.ndarray, n: int, u: np.ndarray, g: np.ndarray, lam: float):
+    """Riemannian Newton direction for max <C, u^n> on the unit sphere at u
+    (g = C u^{n-1}, lambda = g.u), or None where the tangent Hessian is not
+    negative definite (u is then not near a local maximum)."""
+    E = tangent_basis(u)
+    Ht = tangent_hessian(Cu, n, u, lam, E)
+    if not np.all(np.linalg.eigvalsh(Ht) < 0.0):
+        return None
+    return E @ (-np.linalg.solve(Ht, E.T @ g))
+
+
+def newton_finish(Cu: np.ndarray, n: int, u: np.ndarray, max_steps: int = 30):
+    """Newton's method on the sphere from a point SS-HOPM has brought near a
+    local maximum, until a step changes lambda by at most 1e-15: the fixed point
+    that SS-HOPM converges to, reached quadratically instead of linearly.
+    A step is taken only where the tangent Hessian is negative definite and
+    kept only if lambda does not fall by more than 1e-15.  Returns (lambda, u)."""
+    u = np.asarray(u, dtype=np.float64)
+    u = u / np.linalg.norm(u)
+    g = sym.contract_n_minus_1(Cu, u, n)
+    lam = float(g @ u)
+    for _ in range(max_steps):
+        dvec = newton_direction(Cu, n, u, g, lam)
+        if dvec is None:
             break
-        eta = -np.linalg.solve(Ht, E.T @ g)
-        un = u + E @ eta
+        un = u + dvec
         un = un / np.linalg.norm(un)
-        if float(sym.contract_n_minus_1(Cu, un, n) @ un) < lam - drop:
+        gn = sym.contract_n_minus_1(Cu, un, n)
+        ln = float(gn @ un)
+        if ln < lam - 1e-15:
             break
-        u = un
-    return u
+        small = abs(ln - lam) <= 1e-15
+        u, g, lam = un, gn, ln
+        if small:
+            break
+    return lam, u
+
+
+def converge(Cu: np.ndarray, n: int, u0, alpha: float, tol: float = 1e-13, max_iter: int = 10000):
+    """The local maximum SS-HOPM reaches from u0 (Sec. 3.1), converged: SS-HOPM
+    until |delta lambda| <= tol or max_iter updates, then newton_finish.
+    Returns (lambda, u, SS-HOPM updates)."""
+    _, u, it, _ = sshopm(Cu, n, u0, alpha, tol, max_iter)
+    lam, u = newton_finish(Cu, n, u)
+    return lam, u, it
 
 
 def newton_ascent(Cu: np.ndarray, n: int, u0: np.ndarray, steps: int, tol: float,
                   drop: float = 1e-6, halvings: int = 2):
-    """Riemannian Newton iterations for max <C, u^{(x)n}> on the unit sphere (d' = 3).
+    """Riemannian Newton iterations for max <C, u^{(x)n}> on the unit sphere.
 
-    From u0, each step needs the tangent Hessian (n-1) E^T H E - lambda I to be
-    negative definite.  A step that lowers lambda by more than ``drop`` (for
-    C / ||C||_F, lambda <= 1; the default sits a few FP32 ulps above rounding,
-    so an FP32 implementation takes the same decisions) is halved, at most
-    ``halvings`` times, and the search fails if it still does.  The iteration
-    has converged after a full step that changes lambda by at most ``tol``.
-    Returns (u, lambda, converged); when it fails or runs out of steps,
-    converged is False.
+    This is the search of the learned start (not in the paper; its parameters
+    are part of that method's definition).  From u0, each step needs the tangent
+    Hessian (n-1) E^T H E - lambda I to be negative definite.  A step that
+    lowers lambda by more than ``drop`` (for C / ||C||_F, lambda <= 1) is
+    halved, at most ``halvings`` times, and the search fails if it still does.
+    The iteration has converged after a full step that changes lambda by at
+    most ``tol``.  Returns (u, lambda, converged); when it fails or runs out of
+    steps, converged is False.
     """
     u = np.asarray(u0, dtype=np.float64)
     u = u / np.linalg.norm(u)
     g = sym.contract_n_minus_1(Cu, u, n)
     lam = float(g @ u)
     for _ in range(steps):
-        E = tangent_basis(u)
-        Ht = (n - 1) * (E.T @ sym.contract_n_minus_2(Cu, u, n) @ E) - lam * np.eye(2)
-        if not (np.linalg.det(Ht) > 0 and np.trace(Ht) < 0):
+        d = newton_direction(Cu, n, u, g, lam)
+        if d is None:
             return u, lam, False
-        d = E @ (-np.linalg.solve(Ht, E.T @ g))
         t = 1.0
         for _h in range(halvings + 1):
             un = u + t * d
@@ -398,15 +441,16 @@ def newton_ascent(Cu: np.ndarray, n: int, u0: np.ndarray, steps: int, tol: float
     return u, lam, False
 
 
-def orient_multistart(Cv: np.ndarray, n: int, starts: np.ndarray, tol: float = 1e-5,
-                      max_iter: int = 500, shift: float | None = None, newton: int = 2):
+def orient_multistart(Cv: np.ndarray, n: int, starts: np.ndarray, tol: float = 1e-13,
+                      max_iter: int = 10000, shift: float | None = None):
     """Dominant eigenpair of one voxel's tensor from fixed starts (Sec. 3.1).
 
     Works on C / ||C||_F with the unfolding shift unless ``shift`` is given;
-    SS-HOPM from every start, then ``newton`` polishing steps (d' = 3).
-    Returns (lambda, u, per-start lambdas, per-start directions, per-start
-    iterations); lambdas are scaled back by ||C||_F.  A zero tensor gives
-    lambda = 0, u = 0.
+    from every start, the converged local maximum (``converge``: SS-HOPM to
+    tol, then Newton to rounding level); the largest lambda wins, the first
+    start on ties.  Returns (lambda, u, per-start lambdas, per-start
+    directions, per-start SS-HOPM updates); lambdas are scaled back by
+    ||C||_F.  A zero tensor gives lambda = 0, u = 0.
     """
     d = starts.shape[1]
     cn = float(sym.frobenius(Cv, n, d))
@@ -415,15 +459,12 @@ def orient_multistart(Cv: np.ndarray, n: int, starts: np.ndarray, tol: float = 1
                 np.zeros(len(starts), int))
     Cu = np.asarray(Cv, dtype=np.float64) / cn
     alpha = unfolding_shift(Cu, n, d) if shift is None else shift
-    lams, us, its = [], [], []
-    for s in starts:
-        lam, u, it, _ = sshopm(Cu, n, s, alpha, tol, max_iter)
-        if newton and d == 3:
-            u = newton_polish(Cu, n, u, newton)
-            lam = float(sym.contract_n_minus_1(Cu, u, n) @ u)
+    _, U, its, _ = sshopm(Cu, n, starts, alpha, tol, max_iter)
+    lams, us = [], []
+    for u in U:
+        lam, u = newton_finish(Cu, n, u)
         lams.append(lam)
         us.append(u)
-        its.append(it)
     lams = np.array(lams)
     best = int(np.argmax(lams))            # first maximum on ties
     return cn * lams[best], canonical_sign(us[best]), cn * lams, np.array(us), np.array(its)
@@ -445,9 +486,16 @@ def sshopm_rate(Cv: np.ndarray, n: int, u: np.ndarray, alpha: float | None = Non
     u = np.asarray(u, dtype=np.float64) / np.linalg.norm(u)
     lam = float(sym.contract_n_minus_1(Cu, u, n) @ u)
     H = sym.contract_n_minus_2(Cu, u, n)
-    E = np.linalg.svd(np.eye(d) - np.outer(u, u))[0][:, : d - 1]     # tangent basis
+    E = tangent_basis(u)
     mu = np.linalg.eigvalsh(E.T @ H @ E)
     return float(np.max(np.abs((n - 1) * mu + alpha)) / (lam + alpha))
+
+
+def axis_distance_deg(u: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """The angle metric of the form: arccos|u.v| for axes (d' = 3), the
+    rotation distance 2 arccos|q1.q2| for quaternions (d' = 4, Sec. 4.1)."""
+    u = np.asarray(u, dtype=np.float64)
+    return quat_angle_deg(u, v) if u.shape[-1] == 4 else angle_deg(u, v)
 
 
 def orientation_margin(lams: np.ndarray, us: np.ndarray, best_u: np.ndarray,
@@ -457,7 +505,7 @@ def orientation_margin(lams: np.ndarray, us: np.ndarray, best_u: np.ndarray,
     A small margin means two distinct local maxima are nearly tied and either
     answer is correct; such voxels are reported as ambiguous.
     """
-    far = angle_deg(us, best_u[None, :]) > sep_deg
+    far = axis_distance_deg(us, best_u[None, :]) > sep_deg
     if not np.any(far):
         return np.inf
     return float(np.max(lams) - np.max(lams[far]))
@@ -472,37 +520,50 @@ def fibonacci_sphere(n: int) -> np.ndarray:
     return np.stack([r * np.cos(phi), r * np.sin(phi), z], axis=1)
 
 
-def reference_maxima(Cv: np.ndarray, n: int, grid: int = 20000, polish: int = 8,
-                     sep_deg: float = 5.0):
-    """Global maximiser by dense sampling + SS-HOPM polishing (d' = 3).
+def spiral_s3(n: int) -> np.ndarray:
+    """n near-uniform points on S^3: the super-Fibonacci spiral (Alexa 2022),
+    s = i + 1/2, (sqrt(s/n) sin a, sqrt(s/n) cos a, sqrt(1-s/n) sin b,
+    sqrt(1-s/n) cos b) with a = 2 pi s / sqrt(2), b = 2 pi s / psi, psi^4 = psi + 4."""
+    psi = 1.533751168755204288118041
+    s = np.arange(n) + 0.5
+    r, R = np.sqrt(s / n), np.sqrt(1.0 - s / n)
+    a, b = 2.0 * np.pi * s / math.sqrt(2.0), 2.0 * np.pi * s / psi
+    return np.stack([r * np.sin(a), r * np.cos(a), R * np.sin(b), R * np.cos(b)], axis=1)
 
-    Evaluates <C, u^{(x)n}> on a Fibonacci sphere, polishes the best distinct
-    grid points, returns (lambda*, u*, lambda_2) where lambda_2 is the best
-    polished maximum more than sep_deg away from u* (up to sign), or -inf.
+
+def reference_maxima(Cv: np.ndarray, n: int, grid: int = 20000, polish: int = 8,
+                     sep_deg: float = 5.0, dprime: int = 3):
+    """Global maximiser by dense sampling, then convergence from the best points.
+
+    Evaluates <C, u^{(x)n}> on a near-uniform point set (Fibonacci sphere for
+    d' = 3, super-Fibonacci spiral on S^3 for d' = 4), converges (``converge``)
+    from the best grid points that lie more than sep_deg apart, and returns
+    (lambda*, u*, lambda_2): lambda_2 is the best converged maximum more than
+    sep_deg from u* (up to sign), or -inf.
     """
-    pts = fibonacci_sphere(grid)
-    vals = sym.weights(n, 3) * sym.monomials(pts, n) @ np.asarray(Cv, dtype=np.float64)
+    pts = fibonacci_sphere(grid) if dprime == 3 else spiral_s3(grid)
+    vals = sym.weights(n, dprime) * sym.monomials(pts, n) @ np.asarray(Cv, dtype=np.float64)
     order = np.argsort(-vals)
-    cos_sep = math.cos(math.radians(sep_deg))
     chosen = []
     for i in order:
-        if all(abs(pts[i] @ pts[j]) < cos_sep for j in chosen):
+        if all(axis_distance_deg(pts[i], pts[j]) > sep_deg for j in chosen):
             chosen.append(i)
         if len(chosen) >= polish:
             break
-    cn = float(sym.frobenius(Cv, n, 3))
+    cn = float(sym.frobenius(Cv, n, dprime))
     if cn == 0.0:
-        return 0.0, np.zeros(3), -np.inf
+        return 0.0, np.zeros(dprime), -np.inf
     Cu = np.asarray(Cv, dtype=np.float64) / cn
+    alpha = unfolding_shift(Cu, n, dprime)
     found = []
     for i in chosen:
-        lam, u, _, _ = sshopm(Cu, n, pts[i], float(n - 1), 1e-15, 50000)
+        lam, u, _ = converge(Cu, n, pts[i], alpha)
         found.append((lam * cn, canonical_sign(u)))
     found.sort(key=lambda t: -t[0])
     lam1, u1 = found[0]
     lam2 = -np.inf
     for lam, u in found[1:]:
-        if abs(u @ u1) < cos_sep:
+        if axis_distance_deg(u, u1) > sep_deg:
             lam2 = lam
             break
     return lam1, u1, lam2
@@ -517,8 +578,10 @@ def angle_deg(u: np.ndarray, v: np.ndarray) -> np.ndarray:
 
 
 def quat_angle_deg(q1: np.ndarray, q2: np.ndarray) -> np.ndarray:
-    """Rotation distance 2 arccos|q1.q2| in degrees (Sec. 5.1)."""
-    c = np.abs(np.sum(np.asarray(q1) * np.asarray(q2), axis=-1))
+    """Rotation distance 2 arccos|q1.q2| in degrees (Sec. 4.1), unit quaternions."""
+    q1 = np.asarray(q1, dtype=np.float64)
+    q2 = np.asarray(q2, dtype=np.float64)
+    c = np.abs(np.sum(q1 * q2, axis=-1)) / (np.linalg.norm(q1, axis=-1) * np.linalg.norm(q2, axis=-1))
     return np.degrees(2.0 * np.arccos(np.clip(c, 0.0, 1.0)))
 
 

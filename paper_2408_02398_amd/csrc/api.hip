@@ -505,7 +505,8 @@ size_t ttm_workspace_size(const ttm_desc* desc, int op, int fft_n, int nz, int n
       return align256(peaks_workspace((int64_t)nz * ny * nx));
     case TTM_OP_EXTRACT:
       if (nz < 1 || ny < 1 || nx < 1) return 0;
-      return extract_workspace((size_t)nz * ny * nx, desc->degree);
+      return desc->dprime == 4 ? extract_workspace4((size_t)nz * ny * nx)
+                               : extract_workspace((size_t)nz * ny * nx, desc->degree);
     case TTM_OP_MLP_TRAIN:
       if (nz < 1) return 0;
       return align256(mlp_train_workspace(nz));
@@ -817,9 +818,15 @@ int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
     return TTM_EINVAL;
   }
   const size_t plane = (size_t)box_size[0] * box_size[1] * box_size[2];
+  if (desc->dprime == 4 && desc->degree > 6) {
+    set_error("ttm_extract: d'=4 scores need degree <= 6");
+    return TTM_EUNSUPPORTED;
+  }
   if (mode & 2) {
-    if (desc->dprime != 3 || desc->degree < 2 || desc->degree > 6) {
-      set_error("ttm_extract: orientation needs d'=3 and degree 2..6");
+    if (desc->dprime == 3 ? (desc->degree < 2 || desc->degree > 6)
+                          : (desc->degree < 2 || desc->degree > 4 || (mode & 4))) {
+      set_error("ttm_extract: orientation needs degree 2..6 at d'=3, or degree 2..4 and the "
+                "multistart search at d'=4");
       return TTM_EUNSUPPORTED;
     }
     if (!opts->starts || opts->n_starts < 1 || opts->n_starts > 64 || opts->max_iter < 1 ||
@@ -839,7 +846,8 @@ int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
         return TTM_EUNSUPPORTED;
       }
     }
-    const size_t need = extract_workspace(plane, desc->degree);
+    const size_t need = desc->dprime == 4 ? extract_workspace4(plane)
+                                          : extract_workspace(plane, desc->degree);
     if (!ws || ws_bytes < need) {
       set_error("ttm_extract: workspace %zu < %zu", ws_bytes, need);
       return TTM_EWORKSPACE;
@@ -876,7 +884,8 @@ int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
     a.screen = (mode & 16) ? 0 : 1;
     a.fb_total = n_fallback;
   }
-  return launch_extract(desc->degree, a, s);
+  return desc->dprime == 4 ? launch_extract4(desc->degree, a, s)
+                           : launch_extract(desc->degree, a, s);
 }
 
 size_t ttm_mlp_param_count(void) { return kMlpParams; }

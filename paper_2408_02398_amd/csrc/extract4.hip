@@ -1,0 +1,601 @@
+// extract4.hip -- per-voxel score and orientation for the quaternion form
+// (d' = 4, the paper's construction: v_q = q, Sec. 3, Alg. 1).
+//
+// The tensor C(x) is a degree-n symmetric tensor over R^4 with
+// K = binom(n + 3, 3) independent components, alpha = (aw, ax, ay, az) in
+// graded-lex order (descending aw, then ax, then ay); component alpha holds
+// the full-tensor entry, so <C, q^n> = sum_a mu_a C_a q^a, mu_a = n!/prod(a_i!).
+//
+// Score: c = ||C||_F (Sec. 3.2).  Orientation (Sec. 3.1): the dominant
+// eigenpair of C / c on the unit sphere S^3 of quaternions by SS-HOPM with
+// the unfolding shift, from every fixed start, each answer polished by
+// Riemannian Newton steps, the largest lambda winning (first on ties).  The
+// quaternion and its negative are one rotation; the answer is signed so that
+// its first non-zero coordinate (w) is positive.
+//
+// The runs use the pooled scheme of the d' = 3 kernels: k_prepare4 (score and
+// shift per voxel), persistent k_runs4 wavefronts that drain a queue of
+// (voxel, start) runs and refill lanes as runs end, k_reduce4 (polish each
+// run, keep the best).  The tangent space of S^3 at u has the orthonormal
+// basis u*i, u*j, u*k (quaternion products with the imaginary units), so the
+// Newton system is a 3 x 3 Cholesky solve.
+#include "internal.hpp"
+#include "sym_tables.hpp"
+
+namespace ttm {
+
+namespace {
+
+__host__ __device__ constexpr int ncomp4(int n) { return (n + 1) * (n + 2) * (n + 3) / 6; }
+
+// Position of (a, b, c, n - a - b - c): the tuples with a larger first count
+// come first (binom(n - a + 2, 3) of them), then those with the same a and a
+// larger second count, then those with a larger third count.
+__host__ __device__ constexpr int comp_index4(int n, int a, int b, int c) {
+  return (n - a + 2) * (n - a + 1) * (n - a) / 6 + (n - a - b) * (n - a - b + 1) / 2 + (n - a - b - c);
+}
+
+__host__ __device__ constexpr int multinom4(int a, int b, int c, int d) {
+  return factorial(a + b + c + d) / (factorial(a) * factorial(b) * factorial(c) * factorial(d));
+}
+
+template <int N>
+struct Sym4 {
+  static constexpr int K = ncomp4(N);
+  int e[K > 0 ? K : 1][4];
+  float mu[K > 0 ? K : 1];
+  constexpr Sym4() : e(), mu() {
+    int i = 0;
+    for (int a = N; a >= 0; --a)
+      for (int b = N - a; b >= 0; --b)
+        for (int c = N - a - b; c >= 0; --c) {
+          e[i][0] = a;
+          e[i][1] = b;
+          e[i][2] = c;
+          e[i][3] = N - a - b - c;
+          mu[i] = (float)multinom4(a, b, c, N - a - b - c);
+          ++i;
+        }
+  }
+};
+
+constexpr int kRefill4 = 8;        // a pooled wavefront refills once this many lanes wait
+constexpr int kPoolGroups4 = 4096; // persistent pooled grid (one wavefront per group)
+constexpr int kStartBlock4 = 16;   // starts whose run results are held at once
+constexpr unsigned kItemGroups4 = 1024;
+constexpr float kShiftMargin4 = 1e-5f;
+constexpr int kShiftSteps4 = 12;
+
+// Workspace: header (64-bit pool counters, one per start block), shift per
+// voxel, carried best (u, lambda), run results [start][voxel] (u, lambda).
+struct Ws4 {
+  unsigned long long* ctr;
+  float* alpha;
+  float4* best_u;
+  float* best_l;
+  float4* res_u;
+  float* res_l;
+};
+
+__host__ __device__ inline size_t al256_4(size_t b) { return (b + 255) & ~(size_t)255; }
+
+__host__ __device__ inline Ws4 ws4_layout(void* base, size_t plane) {
+  char* p = static_cast<char*>(base);
+  Ws4 w;
+  w.ctr = reinterpret_cast<unsigned long long*>(p);
+  p += 256;
+  w.alpha = reinterpret_cast<float*>(p);
+  p += al256_4(plane * 4);
+  w.best_u = reinterpret_cast<float4*>(p);
+  p += al256_4(plane * 16);
+  w.best_l = reinterpret_cast<float*>(p);
+  p += al256_4(plane * 4);
+  w.res_u = reinterpret_cast<float4*>(p);
+  p += al256_4((size_t)kStartBlock4 * plane * 16);
+  w.res_l = reinterpret_cast<float*>(p);
+  return w;
+}
+
+__device__ __forceinline__ float bf16_to_f32_4(unsigned short h) {
+  return __uint_as_float(((unsigned int)h) << 16);
+}
+
+// Load the K components of box voxel v; returns ||C||_F.
+template <int N>
+__device__ __forceinline__ float load4(const ExtractArgs& a, size_t v, float (&c)[ncomp4(N)]) {
+  constexpr int K = ncomp4(N);
+  constexpr Sym4<N> sy{};
+  if (a.in_dtype == 1) {
+    const unsigned short* p = reinterpret_cast<const unsigned short*>(a.C);
+#pragma unroll
+    for (int k = 0; k < K; ++k) c[k] = bf16_to_f32_4(p[k * a.plane + v]);
+  } else {
+    const float* p = reinterpret_cast<const float*>(a.C);
+#pragma unroll
+    for (int k = 0; k < K; ++k) c[k] = p[k * a.plane + v];
+  }
+  float f2 = 0.0f;
+#pragma unroll
+  for (int k = 0; k < K; ++k) f2 = fmaf(sy.mu[k] * c[k], c[k], f2);
+  return sqrtf(f2);
+}
+
+// g = C u^{n-1}: g_i = sum_{|beta| = n-1} mu_beta C_{beta + e_i} u^beta.
+template <int N>
+__device__ __forceinline__ void contract4(const float (&c)[ncomp4(N)], const float (&u)[4],
+                                          float (&g)[4]) {
+  float p[4][N];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    p[d][0] = 1.0f;
+#pragma unroll
+    for (int k = 1; k < N; ++k) p[d][k] = p[d][k - 1] * u[d];
+  }
+  g[0] = g[1] = g[2] = g[3] = 0.0f;
+#pragma unroll
+  for (int a = N - 1; a >= 0; --a) {
+#pragma unroll
+    for (int b = N - 1 - a; b >= 0; --b) {
+#pragma unroll
+      for (int cc = N - 1 - a - b; cc >= 0; --cc) {
+        const int dd = N - 1 - a - b - cc;
+        const float m = (float)multinom4(a, b, cc, dd) * ((p[0][a] * p[1][b]) * (p[2][cc] * p[3][dd]));
+        g[0] = fmaf(m, c[comp_index4(N, a + 1, b, cc)], g[0]);
+        g[1] = fmaf(m, c[comp_index4(N, a, b + 1, cc)], g[1]);
+        g[2] = fmaf(m, c[comp_index4(N, a, b, cc + 1)], g[2]);
+        g[3] = fmaf(m, c[comp_index4(N, a, b, cc)], g[3]);
+      }
+    }
+  }
+}
+
+// H = C u^{n-2}, symmetric 4 x 4, packed {00, 01, 02, 03, 11, 12, 13, 22, 23, 33}.
+template <int N>
+__device__ __forceinline__ void contract4_2(const float (&c)[ncomp4(N)], const float (&u)[4],
+                                            float (&h)[10]) {
+  float p[4][N - 1];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    p[d][0] = 1.0f;
+#pragma unroll
+    for (int k = 1; k < N - 1; ++k) p[d][k] = p[d][k - 1] * u[d];
+  }
+#pragma unroll
+  for (int i = 0; i < 10; ++i) h[i] = 0.0f;
+#pragma unroll
+  for (int a = N - 2; a >= 0; --a) {
+#pragma unroll
+    for (int b = N - 2 - a; b >= 0; --b) {
+#pragma unroll
+      for (int cc = N - 2 - a - b; cc >= 0; --cc) {
+        const int dd = N - 2 - a - b - cc;
+        const float m = (float)multinom4(a, b, cc, dd) * ((p[0][a] * p[1][b]) * (p[2][cc] * p[3][dd]));
+        h[0] = fmaf(m, c[comp_index4(N, a + 2, b, cc)], h[0]);
+        h[1] = fmaf(m, c[comp_index4(N, a + 1, b + 1, cc)], h[1]);
+        h[2] = fmaf(m, c[comp_index4(N, a + 1, b, cc + 1)], h[2]);
+        h[3] = fmaf(m, c[comp_index4(N, a + 1, b, cc)], h[3]);
+        h[4] = fmaf(m, c[comp_index4(N, a, b + 2, cc)], h[4]);
+        h[5] = fmaf(m, c[comp_index4(N, a, b + 1, cc + 1)], h[5]);
+        h[6] = fmaf(m, c[comp_index4(N, a, b + 1, cc)], h[6]);
+        h[7] = fmaf(m, c[comp_index4(N, a, b, cc + 2)], h[7]);
+        h[8] = fmaf(m, c[comp_index4(N, a, b, cc + 1)], h[8]);
+        h[9] = fmaf(m, c[comp_index4(N, a, b, cc)], h[9]);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ float dot4(const float (&a)[4], const float (&b)[4]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3];
+}
+
+// Riemannian Newton direction on S^3 at u (g = C u^{n-1}, lambda = g.u):
+// tangent basis E = (u*i, u*j, u*k); the tangent Hessian
+// A = (n-1) E^T H E - lambda I must be negative definite (Cholesky of -A),
+// else there is no step.  d = E eta with -A eta = E^T g.
+template <int N>
+__device__ __forceinline__ bool newton_dir4(const float (&c)[ncomp4(N)], const float (&u)[4],
+                                            const float (&g)[4], float lam, float (&dv)[4]) {
+  const float E[3][4] = {{-u[1], u[0], u[3], -u[2]},
+                         {-u[2], -u[3], u[0], u[1]},
+                         {-u[3], u[2], -u[1], u[0]}};
+  float h[10];
+  contract4_2<N>(c, u, h);
+  float HE[3][4];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float* e = E[k];
+    HE[k][0] = h[0] * e[0] + h[1] * e[1] + h[2] * e[2] + h[3] * e[3];
+    HE[k][1] = h[1] * e[0] + h[4] * e[1] + h[5] * e[2] + h[6] * e[3];
+    HE[k][2] = h[2] * e[0] + h[5] * e[1] + h[7] * e[2] + h[8] * e[3];
+    HE[k][3] = h[3] * e[0] + h[6] * e[1] + h[8] * e[2] + h[9] * e[3];
+  }
+  constexpr float nm1 = (float)(N - 1);
+  float m[3][3];  // -A
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const float eh = E[i][0] * HE[j][0] + E[i][1] * HE[j][1] + E[i][2] * HE[j][2] + E[i][3] * HE[j][3];
+      m[i][j] = -(nm1 * eh - (i == j ? lam : 0.0f));
+    }
+  const float p0 = m[0][0];
+  if (!(p0 > 0.0f)) return false;
+  const float r00 = sqrtf(p0);
+  const float l10 = m[1][0] / r00, l20 = m[2][0] / r00;
+  const float p1 = m[1][1] - l10 * l10;
+  if (!(p1 > 0.0f)) return false;
+  const float r11 = sqrtf(p1);
+  const float l21 = (m[2][1] - l20 * l10) / r11;
+  const float p2 = m[2][2] - l20 * l20 - l21 * l21;
+  if (!(p2 > 0.0f)) return false;
+  const float r22 = sqrtf(p2);
+  float t[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) t[k] = E[k][0] * g[0] + E[k][1] * g[1] + E[k][2] * g[2] + E[k][3] * g[3];
+  const float y0 = t[0] / r00, y1 = (t[1] - l10 * y0) / r11, y2 = (t[2] - l20 * y0 - l21 * y1) / r22;
+  const float e2 = y2 / r22, e1 = (y1 - l21 * e2) / r11, e0 = (y0 - l10 * e1 - l20 * e2) / r00;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) dv[d] = e0 * E[0][d] + e1 * E[1][d] + e2 * E[2][d];
+  return true;
+}
+
+// Up to `steps` Newton steps from an SS-HOPM end point; a step is kept unless
+// lambda drops by more than 1e-7.  (g, lambda) hold C u^{n-1} and <C, u^n>.
+template <int N>
+__device__ __forceinline__ int newton_polish4(const float (&c)[ncomp4(N)], float (&u)[4],
+                                              float (&g)[4], float& lam, int steps) {
+  int taken = 0;
+  for (int s = 0; s < steps; ++s) {
+    float dv[4];
+    if (!newton_dir4<N>(c, u, g, lam, dv)) break;
+    ++taken;
+    float v[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) v[d] = u[d] + dv[d];
+    const float rv = 1.0f / sqrtf(dot4(v, v));
+#pragma unroll
+    for (int d = 0; d < 4; ++d) v[d] *= rv;
+    float q[4];
+    contract4<N>(c, v, q);
+    const float lam_v = dot4(q, v);
+    if (lam_v < lam - 1e-7f) break;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      u[d] = v[d];
+      g[d] = q[d];
+    }
+    lam = lam_v;
+  }
+  return taken;
+}
+
+// Lower bound of lambda_min of the unfolding's symmetric block
+// B[b, g] = sqrt(mu_b mu_g) c_{b+g}, |b| = |g| = n/2 (Gershgorin, narrowed by
+// bisection with Cholesky tests, minus a rounding margin), as for d' = 3.
+__host__ __device__ constexpr int tri4(int M, int p, int q) {
+  return p <= q ? p * M - p * (p - 1) / 2 + (q - p) : q * M - q * (q - 1) / 2 + (p - q);
+}
+
+template <int N>
+__device__ __forceinline__ float unfold4(const float (&c)[ncomp4(N)], int p, int q) {
+  constexpr Sym4<N / 2> hs{};
+  return sqrtf(hs.mu[p] * hs.mu[q]) *
+         c[comp_index4(N, hs.e[p][0] + hs.e[q][0], hs.e[p][1] + hs.e[q][1], hs.e[p][2] + hs.e[q][2])];
+}
+
+template <int N>
+__device__ __forceinline__ float unfolding_lambda_min4(const float (&c)[ncomp4(N)]) {
+  constexpr int M = ncomp4(N / 2);
+  float lo = INFINITY, hi = INFINITY;
+#pragma unroll
+  for (int p = 0; p < M; ++p) {
+    float rad = 0.0f;
+#pragma unroll
+    for (int q = 0; q < M; ++q)
+      if (q != p) rad += fabsf(unfold4<N>(c, p, q));
+    const float d = unfold4<N>(c, p, p);
+    lo = fminf(lo, d - rad);
+    hi = fminf(hi, d);
+  }
+  for (int step = 0; step < kShiftSteps4; ++step) {
+    const float mid = 0.5f * (lo + hi);
+    float R[M * (M + 1) / 2];
+    bool pd = true;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      float d = unfold4<N>(c, j, j) - mid;
+#pragma unroll
+      for (int k = 0; k < j; ++k) d = fmaf(-R[tri4(M, k, j)], R[tri4(M, k, j)], d);
+      pd = pd && d > 0.0f;
+      const float r = pd ? 1.0f / sqrtf(d) : 0.0f;
+      R[tri4(M, j, j)] = d * r;
+#pragma unroll
+      for (int i = j + 1; i < M; ++i) {
+        float e = unfold4<N>(c, j, i);
+#pragma unroll
+        for (int k = 0; k < j; ++k) e = fmaf(-R[tri4(M, k, j)], R[tri4(M, k, i)], e);
+        R[tri4(M, j, i)] = e * r;
+      }
+    }
+    if (pd) lo = mid; else hi = mid;
+  }
+  return lo - kShiftMargin4;
+}
+
+__device__ __forceinline__ size_t map_index4(const ExtractArgs& a, size_t v) {
+  const int vx = (int)(v % a.bx), vy = (int)((v / a.bx) % a.by), vz = (int)(v / ((size_t)a.bx * a.by));
+  return ((size_t)(a.oz + vz) * a.dy + (a.oy + vy)) * a.dx + (a.ox + vx);
+}
+
+__device__ __forceinline__ void count_add4(unsigned long long* ctr, unsigned long long v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(ctr, v);
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void k_score4(ExtractArgs a) {
+  const size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= a.plane) return;
+  float c[ncomp4(N)];
+  a.score[map_index4(a, v)] = load4<N>(a, v, c);
+}
+
+// Score (mode bit 1) and the SS-HOPM shift of every box voxel.
+template <int N>
+__global__ __launch_bounds__(256) void k_prepare4(ExtractArgs a) {
+  const Ws4 w = ws4_layout(a.ws, a.plane);
+  unsigned long long n_shift = 0;
+  for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < a.plane;
+       v += (size_t)gridDim.x * blockDim.x) {
+    float c[ncomp4(N)];
+    const float cn = load4<N>(a, v, c);
+    if ((a.mode & 1) && a.score) a.score[map_index4(a, v)] = cn;
+    float alpha = 0.0f;
+    if (cn > 0.0f) {
+      const float inv = 1.0f / cn;
+#pragma unroll
+      for (int k = 0; k < ncomp4(N); ++k) c[k] *= inv;
+      alpha = fmaxf(0.0f, -unfolding_lambda_min4<N>(c));
+      n_shift += 1;
+    }
+    w.alpha[v] = alpha;
+  }
+  if (a.counters) count_add4(a.counters + 3, n_shift);
+}
+
+// Persistent pooled SS-HOPM runs over (voxel, start) pairs: run q of a chunk
+// is voxel chunk_base + q / R with start s0 + q % R.  A wavefront takes up to
+// 64 voxels at a time from a global counter and stages their normalised
+// tensors and shifts in LDS; lanes whose run has ended take the chunk's next
+// runs as soon as kRefill4 of them wait.  A run ends at |delta lambda| <= tol
+// or max_iter updates; its (u, lambda) goes to slot (q % R) * plane + voxel.
+template <int N>
+__global__ __launch_bounds__(64) void k_runs4(ExtractArgs a, int R, int s0, unsigned long long* ctr) {
+  constexpr int K = ncomp4(N);
+  constexpr Sym4<N> sy{};
+  __shared__ float st[64 * 4];
+  __shared__ float cs[K][64];
+  __shared__ float ca[64];
+  __shared__ float cz[64];
+  const int lane = threadIdx.x;
+  for (int i = lane; i < a.n_starts * 4; i += 64) st[i] = a.starts[i];
+  __syncthreads();
+  const Ws4 w = ws4_layout(a.ws, a.plane);
+  const unsigned n_items = (unsigned)a.plane;
+  const unsigned per_wave = (n_items + 4 * gridDim.x - 1) / (4 * gridDim.x);
+  const unsigned chunk = per_wave < 1 ? 1 : (per_wave > 64 ? 64 : per_wave);
+  unsigned chunk_base = 0;
+  int chunk_runs = 0, next_q = 0;
+  bool exhausted = n_items == 0;
+  float c[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) c[k] = 0.0f;
+  float alpha = 0.0f, u[4] = {0.0f, 0.0f, 0.0f, 0.0f}, g[4] = {0.0f, 0.0f, 0.0f, 0.0f}, lam = 0.0f;
+  int iters = 0, s = 0;
+  unsigned j = 0;
+  bool first = false, busy = false;
+  unsigned long long n_steps = 0, n_runs = 0;
+  while (true) {
+    unsigned long long waiting = __ballot(!busy);
+    int n_wait = __popcll(waiting);
+    if (n_wait == 64 && exhausted && next_q == chunk_runs) break;
+    if (n_wait >= kRefill4 || n_wait == 64) {
+      while (n_wait > 0) {
+        if (next_q == chunk_runs) {
+          if (exhausted) break;
+          unsigned long long base = 0;
+          if (lane == 0) base = atomicAdd(ctr, (unsigned long long)chunk);
+          base = __shfl(base, 0);
+          if (base >= n_items) {
+            exhausted = true;
+            break;
+          }
+          const int cnt = (n_items - base) < chunk ? (int)(n_items - base) : (int)chunk;
+          if (base + chunk >= n_items) exhausted = true;
+          chunk_base = (unsigned)base;
+          chunk_runs = cnt * R;
+          next_q = 0;
+          __syncthreads();   // the previous chunk's LDS reads are complete
+          if (lane < cnt) {
+            const size_t v = chunk_base + lane;
+            float cv[K];
+            const float cn = load4<N>(a, v, cv);
+            const float inv = cn > 0.0f ? 1.0f / cn : 0.0f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) cs[k][lane] = cv[k] * inv;
+            cz[lane] = cn;
+            ca[lane] = w.alpha[v];
+          }
+          __syncthreads();
+        }
+        const int avail = chunk_runs - next_q;
+        const int take = n_wait < avail ? n_wait : avail;
+        if (!busy) {
+          const int rank = __popcll(waiting & ((1ull << lane) - 1ull));
+          if (rank < take) {
+            const int q = next_q + rank;
+            const int jl = q / R;
+            s = q % R;
+            j = chunk_base + jl;
+            if (cz[jl] > 0.0f) {
+#pragma unroll
+              for (int k = 0; k < K; ++k) c[k] = cs[k][jl];
+              alpha = ca[jl];
+              const float* sv = &st[4 * (s0 + s)];
+              const float rs = 1.0f / sqrtf(sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2] + sv[3] * sv[3]);
+#pragma unroll
+              for (int d = 0; d < 4; ++d) u[d] = sv[d] * rs;
+              iters = 0;
+              first = true;
+              busy = true;
+              ++n_runs;
+            } else {
+              w.res_u[(size_t)s * a.plane + j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+              w.res_l[(size_t)s * a.plane + j] = 0.0f;
+            }
+          }
+        }
+        next_q += take;
+        waiting = __ballot(!busy);
+        n_wait = __popcll(waiting);
+      }
+    }
+    if (busy) {
+      if (!first) {
+        float v[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) v[d] = fmaf(alpha, u[d], g[d]);
+        const float rn = 1.0f / sqrtf(dot4(v, v));
+#pragma unroll
+        for (int d = 0; d < 4; ++d) u[d] = v[d] * rn;
+      }
+      contract4<N>(c, u, g);
+      const float lam_new = dot4(g, u);
+      bool end = false;
+      if (first) {
+        first = false;
+      } else {
+        ++iters;
+        ++n_steps;
+        end = fabsf(lam_new - lam) <= a.tol || iters >= a.max_iter;
+      }
+      lam = lam_new;
+      if (end) {
+        w.res_u[(size_t)s * a.plane + j] = make_float4(u[0], u[1], u[2], u[3]);
+        w.res_l[(size_t)s * a.plane + j] = lam;
+        busy = false;
+      }
+    }
+  }
+  (void)sy;
+  if (a.counters) {
+    count_add4(a.counters + 0, n_steps);
+    count_add4(a.counters + 4, n_runs);
+  }
+}
+
+// Per voxel: every run of one start block takes the Newton polish and the
+// largest polished lambda wins (first in start order on ties), carried across
+// blocks; after the last block the winner is signed (w >= 0) and written.
+template <int N>
+__global__ __launch_bounds__(256) void k_reduce4(ExtractArgs a, int nsb, int first_block, int last_block) {
+  constexpr int K = ncomp4(N);
+  const Ws4 w = ws4_layout(a.ws, a.plane);
+  unsigned long long n_newton = 0, n_oriented = 0;
+  for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < a.plane;
+       v += (size_t)gridDim.x * blockDim.x) {
+    float c[K];
+    const float cn = load4<N>(a, v, c);
+    float4 bu = first_block ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : w.best_u[v];
+    float bl = first_block ? -INFINITY : w.best_l[v];
+    if (cn > 0.0f) {
+      const float inv = 1.0f / cn;
+#pragma unroll
+      for (int k = 0; k < K; ++k) c[k] *= inv;
+      for (int s = 0; s < nsb; ++s) {
+        const float4 r = w.res_u[(size_t)s * a.plane + v];
+        float u[4] = {r.x, r.y, r.z, r.w}, g[4];
+        contract4<N>(c, u, g);
+        float lam = dot4(g, u);
+        n_newton += newton_polish4<N>(c, u, g, lam, a.newton);
+        if (lam > bl) {
+          bl = lam;
+          bu = make_float4(u[0], u[1], u[2], u[3]);
+        }
+      }
+    }
+    if (!last_block) {
+      w.best_u[v] = bu;
+      w.best_l[v] = bl;
+    } else {
+      float out[4] = {0.0f, 0.0f, 0.0f, 0.0f}, lam = 0.0f;
+      if (cn > 0.0f) {
+        out[0] = bu.x; out[1] = bu.y; out[2] = bu.z; out[3] = bu.w;
+        const float sg = out[0] != 0.0f ? out[0] : (out[1] != 0.0f ? out[1] : (out[2] != 0.0f ? out[2] : out[3]));
+        if (sg < 0.0f) {
+#pragma unroll
+          for (int d = 0; d < 4; ++d) out[d] = -out[d];
+        }
+        lam = bl * cn;
+        n_oriented += 1;
+      }
+      const size_t o = map_index4(a, v);
+      if (a.lam) a.lam[o] = lam;
+      if (a.dir) {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) a.dir[4 * o + d] = out[d];
+      }
+    }
+  }
+  if (a.counters) {
+    count_add4(a.counters + 1, n_newton);
+    count_add4(a.counters + 2, n_oriented);
+  }
+}
+
+template <int N>
+int launch4_n(const ExtractArgs& a, hipStream_t s) {
+  const unsigned nb = (unsigned)((a.plane + 255) / 256);
+  if constexpr (N >= 2 && N <= 4) {
+    if (a.mode & 2) {
+      const Ws4 w = ws4_layout(a.ws, a.plane);
+      fill_zero(w.ctr, 256, s);
+      const unsigned ib = nb < kItemGroups4 ? nb : kItemGroups4;
+      hipLaunchKernelGGL(k_prepare4<N>, dim3(ib), dim3(256), 0, s, a);
+      const int n_blocks = (a.n_starts + kStartBlock4 - 1) / kStartBlock4;
+      for (int b = 0; b < n_blocks; ++b) {
+        const int nsb = (a.n_starts - b * kStartBlock4) < kStartBlock4 ? (a.n_starts - b * kStartBlock4)
+                                                                       : kStartBlock4;
+        hipLaunchKernelGGL(k_runs4<N>, dim3(kPoolGroups4), dim3(64), 0, s, a, nsb, b * kStartBlock4,
+                           w.ctr + b);
+        hipLaunchKernelGGL(k_reduce4<N>, dim3(ib), dim3(256), 0, s, a, nsb, b == 0 ? 1 : 0,
+                           b == n_blocks - 1 ? 1 : 0);
+      }
+      hipError_t e = hipGetLastError();
+      return e == hipSuccess ? 0 : hip_status(e, "extract (d'=4) launch");
+    }
+  }
+  hipLaunchKernelGGL(k_score4<N>, dim3(nb), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : hip_status(e, "extract (d'=4) launch");
+}
+
+}  // namespace
+
+size_t extract_workspace4(size_t plane) {
+  return 256 + al256_4(plane * 4) + al256_4(plane * 16) + al256_4(plane * 4) +
+         al256_4((size_t)kStartBlock4 * plane * 16) + (size_t)kStartBlock4 * plane * 4;
+}
+
+int launch_extract4(int degree, const ExtractArgs& a, hipStream_t s) {
+  switch (degree) {
+    case 0: return launch4_n<0>(a, s);
+    case 2: return launch4_n<2>(a, s);
+    case 4: return launch4_n<4>(a, s);
+    case 6: return launch4_n<6>(a, s);
+    default: set_error("ttm_extract: degree %d not built for d'=4", degree); return -4;
+  }
+}
+
+}  // namespace ttm

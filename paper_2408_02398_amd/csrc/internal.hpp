@@ -112,6 +112,10 @@ struct ExtractArgs {
 // Workspace bytes of an orientation extraction over `plane` voxels.
 size_t extract_workspace(size_t plane, int degree);
 int launch_extract(int degree, const ExtractArgs& a, hipStream_t s);
+// The quaternion form (d' = 4, extract4.hip): score at degree 0..6,
+// multistart orientation at degree 2 and 4; directions are 4 floats per voxel.
+size_t extract_workspace4(size_t plane);
+int launch_extract4(int degree, const ExtractArgs& a, hipStream_t s);
 
 // Find Peaks (peaks.hip).
 size_t peaks_workspace(int64_t n_voxels);

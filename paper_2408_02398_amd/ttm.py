@@ -195,7 +195,7 @@ def extract(ctx: Context, desc: Desc, Cf: torch.Tensor, *, score=None, lam=None,
         if lam is None:
             lam = torch.zeros(out_dims, dtype=torch.float32, device=dev)
         if direction is None:
-            direction = torch.zeros((*out_dims, 3), dtype=torch.float32, device=dev)
+            direction = torch.zeros((*out_dims, desc.dprime), dtype=torch.float32, device=dev)
         if starts is None:
             raise ValueError("orientation needs start vectors")
         opts.n_starts = starts.shape[0]
@@ -378,7 +378,8 @@ class Engine:
         self.fallbacks = torch.zeros(1, dtype=torch.int32, device=dev)
         self.score = torch.zeros(self.shape, dtype=torch.float32, device=dev)
         self.lam = torch.zeros(self.shape, dtype=torch.float32, device=dev) if orient else None
-        self.dir = torch.zeros((*self.shape, 3), dtype=torch.float32, device=dev) if orient else None
+        self.dir = (torch.zeros((*self.shape, desc.dprime), dtype=torch.float32, device=dev)
+                    if orient else None)
 
     def release(self) -> None:
         """Free the tile buffers and workspaces and keep the output maps (score,
@@ -525,7 +526,8 @@ class BatchEngine:
         self.volumes = [torch.zeros(s, dtype=torch.float32, device=dev) for s in self.shapes]
         self.score = [torch.zeros(s, dtype=torch.float32, device=dev) for s in self.shapes]
         self.lam = [torch.zeros(s, dtype=torch.float32, device=dev) for s in self.shapes]
-        self.direction = [torch.zeros((*s, 3), dtype=torch.float32, device=dev) for s in self.shapes]
+        self.direction = [torch.zeros((*s, templates[o][0].dprime), dtype=torch.float32, device=dev)
+                          for s, o in zip(self.shapes, owner)]
         self.peaks = [torch.zeros((top_p, 3), dtype=torch.int32, device=dev) for _ in self.shapes]
         self.vals = [torch.zeros(top_p, dtype=torch.float32, device=dev) for _ in self.shapes]
         self.n_found = torch.zeros(len(self.shapes), dtype=torch.int32, device=dev)

@@ -50,3 +50,45 @@ def oracle_trained_params(seed: int, n: int, steps: int = 300, batch: int = 2048
         _, cache = omlp.forward(p, omlp.features(C, n))
         omlp.adam_step(p, omlp.backward(p, cache, v), st, lr=lr)
     return p
+
+
+def classify_orientation(Cv, n, lam_g, u_g, lam_o, u_o, floor, alts=()):
+    """Class of one GPU orientation (lambda_g, u_g) against the oracle's
+    converged answer (lambda_o, u_o) for the FP64 tensor Cv (Sec. 3.1):
+
+    'agree'  u_g within 1 degree of u_o, lambda_g within 1e-4 floor of lambda_o;
+    'near'   the GPU found a maximiser of the FP64 function as good as the
+             oracle's up to the score tolerance, on a flat maximum or one of two
+             tied maxima, where the FP32 field (which differs from the FP64 one by
+             rounding) moves the maximiser by more than 1 degree:
+             lambda_g and <C, u_g^n> are both within 1e-4 floor of lambda_o, and
+             the converged ascent from u_g reaches a maximum within 1e-4 floor
+             of lambda_o;
+    'alt'    the same, against one of the answers in ``alts`` ((lambda, u)
+             pairs the method may give; e.g. from starts tilted by rounding);
+    None     unclassified: a parity failure.
+    Returns (class, details dict).
+    """
+    from oracle import sym
+    from oracle import ttm as orc
+    d = len(u_o)
+    tol = 1e-4 * floor
+    ang = float(orc.axis_distance_deg(u_g, u_o)) if np.linalg.norm(u_g) > 0 else 180.0
+    info = {"angle": ang, "dlam": float(lam_g - lam_o)}
+    if ang < 1.0 and abs(lam_g - lam_o) <= tol:
+        return "agree", info
+    cn = float(sym.frobenius(Cv, n, d))
+    if cn == 0.0 or not np.linalg.norm(u_g) > 0:
+        return None, info
+    Cu = np.asarray(Cv, dtype=np.float64) / cn
+    ug = np.asarray(u_g, dtype=np.float64) / np.linalg.norm(u_g)
+    f_g = cn * float(sym.inner_power(Cu, ug, n))
+    lam_a, u_a, _ = orc.converge(Cu, n, ug, orc.unfolding_shift(Cu, n, d))
+    lam_a *= cn
+    info.update({"f64_at_gpu_u": f_g, "ascent_lam": lam_a,
+                 "ascent_moved_deg": float(orc.axis_distance_deg(u_a, ug))})
+    for name, targets in (("near", [(lam_o, u_o)]), ("alt", list(alts))):
+        for lam_t, _ in targets:
+            if (abs(lam_g - lam_t) <= tol and abs(f_g - lam_t) <= tol and abs(lam_a - lam_t) <= tol):
+                return name, info
+    return None, info

@@ -119,3 +119,74 @@ def test_pick_fft_and_tiles(T):
     assert T.pick_fft((192, 160, 192), 24) == 128
     # a measured cost that makes small tiles cheap enough changes the choice
     assert T.pick_fft((192, 192, 192), 40, {64: 0.001, 128: 1.0, 256: 100.0, 512: 1e4}) == 64
+
+
+def test_batch_c5_shapes_match_oracle(T, ctx):
+    """Subtomograms of the 64-item batch's recipe (edges 96..192, degree 6,
+    three templates of edges 24, 32, 40), run as one graph: at sampled voxels
+    of every item (its peaks and random valid voxels) w, the score and the
+    orientation against the FP64 oracle's direct sums (Eq. norm_f, Eq. tcc,
+    Sec. 3.1, 3.2), with the tolerances of the single-volume tests."""
+    from oracle import sym, ttm as orc
+    from tests.gpu_common import classify_orientation
+    print("[batch c5 shapes] generating", flush=True)
+    tmpls, items = synth.batch_items(seed=5, n_items=64)
+    # the first item of each edge
+    pick = [next(k for k, it in enumerate(items) if it["volume"].shape[0] == e)
+            for e in (96, 128, 160, 192)]
+    n = 6
+    Q = synth.rotation_samples(10)
+    templates, oracle_T = [], []
+    for vol_t, r, tm in tmpls:
+        d = T.make_desc(n, vol_t.shape[0], r)
+        Tg, _ = T.build_tensor(ctx, d, cuda(vol_t), cuda(Q))
+        templates.append((d, Tg))
+        oracle_T.append(orc.tensor_template(orc.normalize_template(vol_t.astype(np.float64), r), Q, n))
+    shapes = [items[k]["volume"].shape for k in pick]
+    owner = [items[k]["template"] for k in pick]
+    starts = synth.start_vectors()
+    be = T.BatchEngine(ctx, templates, shapes, owner, cuda(starts), top_p=8)
+    for i, k in enumerate(pick):
+        be.volumes[i].copy_(cuda(items[k]["volume"]))
+    be.capture()
+    be.replay()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(77)
+    counts = {"agree": 0, "near": 0}
+    for i, k in enumerate(pick):
+        vol = items[k]["volume"]
+        d = templates[owner[i]][0]
+        L, r = d.L, d.mask_radius
+        print(f"[batch c5 shapes] item {i}: {shapes[i]}, L={L}, FFT edge {be.fft[i]}", flush=True)
+        lo, hi = T.valid_bounds(shapes[i], L)
+        nf = int(be.n_found[i].item())
+        pts = np.concatenate([be.peaks[i][:nf].cpu().numpy().astype(np.int64),
+                              np.stack([rng.integers(a, b + 1, 10) for a, b in zip(lo, hi)], 1)])
+        c = L // 2
+        patches = np.stack([orc.prefilter_box(vol, (z - c, y - c, x - c), (z - c + L, y - c + L, x - c + L))
+                            for z, y, x in pts])
+        g2 = orc.volume_g2_mean(orc.prefilter_volume(vol))
+        wo, Co = orc.field_at(patches, orc.ball_mask(L, r), oracle_T[owner[i]], g2)
+        idx = (pts[:, 0], pts[:, 1], pts[:, 2])
+        sg = be.score[i].cpu().numpy()[idx]
+        lg = be.lam[i].cpu().numpy()[idx]
+        ug = be.direction[i].cpu().numpy()[idx]
+        so = orc.score(Co.T, n)
+        floor = np.maximum(so, np.median(so))
+        assert np.all(wo > 0)
+        assert np.max(np.abs(sg - so) / floor) < 1e-4, i
+        for j in range(len(pts)):
+            lam_o, u_o, *_ = orc.orient_multistart(Co[j], n, starts.astype(np.float64))
+            cls, info = classify_orientation(Co[j], n, lg[j], ug[j], lam_o, u_o, floor[j])
+            assert cls is not None, (i, pts[j], info)
+            counts[cls] += 1
+        # the peaks are the greedy result on the item's own map (Sec. 3.4)
+        smap = be.score[i].cpu().numpy().astype(np.float64)
+        full = np.zeros_like(smap)
+        box = tuple(slice(a, b + 1) for a, b in zip(lo, hi))
+        full[box] = smap[box]
+        pko, _ = orc.find_peaks(full, lo, hi, 8, 2 * r)
+        assert np.array_equal(be.peaks[i][:nf].cpu().numpy().astype(np.int64), pko)
+    print(f"[batch c5 shapes] orientation {counts}", flush=True)
+    total = sum(counts.values())
+    assert counts["agree"] >= 0.8 * total

@@ -10,14 +10,16 @@ oracle within seconds; the rotation count does not change any kernel's work
 per voxel.
 
 Tolerances as in the small-size tests: w and the score within 1e-4 relative
-(score relative to max(score, median score)); lambda within 1e-4 of that
-floor, plus the SS-HOPM stopping error score * tol * rate / (1 - rate) on flat
-maxima, plus the gap between nearly tied maxima; directions within 1 degree
-where the maximiser is well conditioned (SS-HOPM rate < 0.95 and a margin to
-other maxima above 1e-4 of the score).  With the learned start, the network
-sees the GPU's FP32 field, not the oracle's FP64 one: at a voxel whose start
-sits on a basin boundary the GPU may reach another maximum, which must then be
-the answer from a start tilted by at most 1 degree (a few such voxels only).
+(score relative to max(score, median score)).  Orientation: every sampled
+voxel is classified against the oracle's converged answer (SS-HOPM to 1e-13,
+then Newton to rounding level): it agrees (within 1 degree, lambda within the
+score tolerance), or the GPU found a near-optimal maximiser of the FP64
+function (a flat maximum or one of two tied maxima, whose position the FP32
+field's rounding moves by more than a degree).  With the learned start the
+network sees the GPU's FP32 field, not the oracle's FP64 one: at a voxel whose
+start sits on a basin boundary, or whose fallback test is within rounding of
+flipping, the GPU may take the other branch, whose answer it must then match
+(a few such voxels only).  No voxel is left unclassified.
 """
 import functools
 
@@ -27,7 +29,7 @@ import pytest
 import synth
 from oracle import mlp as omlp
 from oracle import sym, ttm as orc
-from tests.gpu_common import oracle_trained_params, require_gpu
+from tests.gpu_common import classify_orientation, oracle_trained_params, require_gpu
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 torch = pytest.importorskip("torch")
@@ -150,47 +152,43 @@ def test_full_size_sampled_parity(T, ctx, name, start):
     assert np.max(np.abs(wg - wo) / wo) < 1e-4
     assert np.max(np.abs(sg - so) / floor) < 1e-4
     st = starts.astype(np.float64)
-    checked = ambiguous = 0
+    counts = {"agree": 0, "near": 0, "alt": 0}
     for i in range(len(pts)):
+        if i % 20 == 0:
+            say(f"[fullsize {name} {start}] oracle orientation {i}/{len(pts)}")
         if start == "multistart":
-            lam_o, u_o, lams, us, _ = orc.orient_multistart(Co[i], n, st)
+            lam_o, u_o, *_ = orc.orient_multistart(Co[i], n, st)
+            cls, info = classify_orientation(Co[i], n, lg[i], ug[i], lam_o, u_o, floor[i])
         else:
-            lam_o, u_o, fell, info = omlp.orient_learned(Co[i], n, pl, st, kappa, detail=True)
-            # a fallback test within rounding of flipping may go either way on the GPU
-            if abs(info["beat_gap"]) < 1e-4 * so[i] or abs(info["kappa_gap"]) < 1e-4:
-                continue
-            if fell:
-                lams = np.append(info["lams"], info["lam_learned"])
-                us = np.vstack([info["us"], info["u_learned"]])
-            else:
-                lams, us = np.array([lam_o]), u_o[None, :]
-        margin = orc.orientation_margin(lams, us, u_o)
-        # both sides stop SS-HOPM at |delta lambda| <= tol (on C / ||C||_F), which
-        # leaves lambda up to tol * rate / (1 - rate) below its limit on a flat
-        # maximum (rate = the linearised SS-HOPM factor there)
-        rate = orc.sshopm_rate(Co[i], n, u_o)
-        stop = so[i] * 1e-5 * rate / (1.0 - rate) if rate < 1.0 else np.inf
-        tie = margin if margin <= 1e-4 * so[i] else 0.0
-        if start == "learned" and abs(lg[i] - lam_o) > 1e-4 * floor[i] + stop + tie:
-            # the learned start lies within rounding of a basin boundary: the
-            # GPU's answer must be one that a start that close reaches
-            alts = learned_alternatives(Co[i], n, pl, st, kappa)
-            hit = False
-            for lam_a, u_a in alts:
-                ra = orc.sshopm_rate(Co[i], n, u_a)
-                sa = so[i] * 1e-5 * ra / (1.0 - ra) if ra < 1.0 else np.inf
-                hit |= abs(lg[i] - lam_a) <= 1e-4 * floor[i] + sa
-            assert hit, (i, pts[i], lg[i], lam_o, [a for a, _ in alts])
-            ambiguous += 1
-            continue
-        assert abs(lg[i] - lam_o) <= 1e-4 * floor[i] + stop + tie, (i, pts[i], rate)
-        if margin > 1e-4 * so[i] and rate < 0.95:
-            assert orc.angle_deg(ug[i], u_o) < 1.0, (i, pts[i])
-            checked += 1
-    say(f"[fullsize {name} {start}] orientation checked at {checked} of {len(pts)} voxels, "
-        f"{ambiguous} at a basin boundary")
-    assert checked >= len(pts) // 5
-    assert ambiguous <= max(2, len(pts) // 20)
+            lam_o, u_o, fell, det = omlp.orient_learned(Co[i], n, pl, st, kappa, detail=True)
+            cls, info = classify_orientation(Co[i], n, lg[i], ug[i], lam_o, u_o, floor[i])
+            if cls is None:
+                # the other branch of a fallback test within rounding of flipping,
+                # or a start within rounding of a basin boundary
+                alts = [(det["lam_learned"], det["u_learned"]), orc.orient_multistart(Co[i], n, st)[:2]]
+                alts += learned_alternatives(Co[i], n, pl, st, kappa)
+                cls, info = classify_orientation(Co[i], n, lg[i], ug[i], lam_o, u_o, floor[i], alts)
+        assert cls is not None, (i, pts[i], info)
+        counts[cls] += 1
+    say(f"[fullsize {name} {start}] orientation at {len(pts)} voxels: {counts}")
+    assert counts["agree"] >= 0.8 * len(pts)
+    assert counts["alt"] <= max(2, len(pts) // 20)
+    # each of the first peaks is a local maximum of the oracle's score up to the
+    # score tolerance (its face neighbours computed by the oracle)
+    nb = np.array([(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)])
+    pk16 = peaks[:16]
+    npts = (pk16[:, None, :] + nb[None]).reshape(-1, 3)
+    lo_v, hi_v = T.valid_bounds(wl.volume.shape, L)
+    npts = np.clip(npts, lo_v, hi_v)
+    _, Cn = oracle_field(wl.volume, npts, L, r, Tt)
+    sn = orc.score(Cn.T, n).reshape(len(pk16), 6)
+    so16 = so[:len(pk16)]
+    for k in range(len(pk16)):
+        for m_ in range(6):
+            q = npts[6 * k + m_]
+            # a neighbour that was a candidate (not excluded by an earlier peak)
+            if k == 0 or np.min(np.sum((pk16[:k] - q) ** 2, axis=1)) >= (2 * r) ** 2:
+                assert so16[k] >= sn[k, m_] - 2e-4 * floor[k], (k, q)
     # Find Peaks (Sec. 3.4) on the GPU's own score map, checked by the property
     # that defines the greedy result: peak k holds the largest score among the
     # valid voxels farther than 2r from peaks 0..k-1 (ties: smallest index)
@@ -203,7 +201,7 @@ def test_full_size_sampled_parity(T, ctx, name, start):
     m[box] = smap[box]
     D = 2 * r
     R = int(np.ceil(D))
-    for k in range(min(len(peaks), 16)):
+    for k in range(len(peaks)):
         top = m.max()
         assert pv[k] == top, k
         first = np.flatnonzero(m.ravel() == top)[0]

@@ -13,7 +13,7 @@ import pytest
 import synth
 from oracle import mlp as omlp
 from oracle import sym, ttm as orc
-from tests.gpu_common import oracle_trained_params, require_gpu
+from tests.gpu_common import classify_orientation, oracle_trained_params, require_gpu
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -142,16 +142,31 @@ def test_training_learns_and_learned_path_matches_oracle(T, ctx):
                           kappa=kappa, fallbacks=fb)
     lg, ug = lam.cpu().numpy().ravel(), u.cpu().numpy().reshape(Bt, 3)
     nfb = 0
+    counts = {"agree": 0, "near": 0, "alt": 0}
+    st64 = starts.astype(np.float64)
     for i in range(Bt):
-        lo, uo, fell = omlp.orient_learned(Ct[i], n, pl, starts.astype(np.float64), kappa)
+        lo, uo, fell, info = omlp.orient_learned(Ct[i], n, pl, st64, kappa, detail=True)
         nfb += fell
-        assert abs(lg[i] - lo) <= 1e-4 * max(orc.score(Ct[i], n), 1e-9)
-        if orc.sshopm_rate(Ct[i], n, uo) < 0.95:
-            assert orc.angle_deg(ug[i], uo) < 1.0
+        cn = orc.score(Ct[i], n)
+        # a fallback test within rounding of flipping may go either way on the
+        # GPU: then either branch's answer is one the method gives
+        alts = []
+        if abs(info["beat_gap"]) < 1e-4 * cn or abs(info["kappa_gap"]) < 1e-4:
+            alts.append((info["lam_learned"], info["u_learned"]))
+            alts.append(orc.orient_multistart(Ct[i], n, st64)[:2])
+        cls, det = classify_orientation(Ct[i], n, lg[i], ug[i], lo, uo, cn, alts)
+        assert cls is not None, (i, det, info["beat_gap"], info["kappa_gap"])
+        counts[cls] += 1
+    print(f"[learned path {Bt} voxels] {counts}, fallbacks oracle {nfb} gpu {int(fb.item())}", flush=True)
+    assert counts["agree"] >= 0.8 * Bt
     assert abs(int(fb.item()) - nfb) <= 2
 
 
 def test_forced_fallback_equals_multistart(T, ctx):
+    """kappa = +inf sends every voxel to the multistart fallback, and the merged
+    answer is, exactly, the larger of the learned-only answer (kappa = -inf,
+    no screening) and the plain multistart answer: the same kernels on the
+    same normalised tensors, so the comparison is bit for bit."""
     n, K, B = 6, 28, 200
     rng = np.random.default_rng(9)
     C = rng.standard_normal((B, K))
@@ -160,17 +175,13 @@ def test_forced_fallback_equals_multistart(T, ctx):
     starts = cuda(synth.start_vectors())
     Cg = cuda(C.T.reshape(K, 1, 1, B))
     fb = torch.zeros(1, dtype=torch.int32, device="cuda")
-    _, lam_l, u_l = T.extract(ctx, d, Cg, starts=starts, mlp=net, kappa=float("inf"), fallbacks=fb)
-    _, lam_p, u_p = T.extract(ctx, d, Cg, starts=starts)
+    _, lam_m, u_m = T.extract(ctx, d, Cg, starts=starts, mlp=net, kappa=float("inf"), fallbacks=fb)
     assert int(fb.item()) == B
-    ll, lp = lam_l.cpu().numpy().ravel(), lam_p.cpu().numpy().ravel()
-    # every voxel fell back, so the answer is the larger of the learned one and
-    # the multistart's, which is the plain multistart computed by the same kernels
-    assert np.all(ll >= lp)
-    eq = ll == lp
-    assert eq.mean() > 0.5
-    # equal lambda: the multistart answer, or the learned one at the same maximum
-    # (lambda is flat there, so FP32 lambda ties while u differs by rounding)
-    ang = orc.angle_deg(u_l.cpu().numpy().reshape(B, 3)[eq], u_p.cpu().numpy().reshape(B, 3)[eq])
-    assert np.max(ang) < 0.1
-
+    _, lam_l, u_l = T.extract(ctx, d, Cg, starts=starts, mlp=net, kappa=float("-inf"), screen=False)
+    _, lam_p, u_p = T.extract(ctx, d, Cg, starts=starts)
+    lm, ll, lp = (x.cpu().numpy().ravel() for x in (lam_m, lam_l, lam_p))
+    um, ul, up = (x.cpu().numpy().reshape(B, 3) for x in (u_m, u_l, u_p))
+    plain_wins = lp > ll
+    assert np.array_equal(lm, np.where(plain_wins, lp, ll))
+    assert np.array_equal(um, np.where(plain_wins[:, None], up, ul))
+    print(f"[forced fallback] plain larger at {int(plain_wins.sum())} of {B}", flush=True)

@@ -18,7 +18,7 @@ import pytest
 
 import synth
 from oracle import sym, ttm as orc
-from tests.gpu_common import rel_err, require_gpu
+from tests.gpu_common import classify_orientation, rel_err, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -244,6 +244,10 @@ def test_correlate_sub_box_and_single_voxel(T, ctx, small):
 
 
 def test_orientation_matches_oracle(T, ctx, small):
+    """Every one of 160 sampled voxels: the GPU's (lambda, u) agrees with the
+    oracle's converged multistart answer (within 1 degree, lambda within the
+    score tolerance) or is a near-optimal maximiser of the FP64 function
+    (flat or tied maxima); none is left unclassified."""
     n = small["n"]
     d = T.make_desc(n, small["L"], small["r"])
     Co = small["C"]
@@ -255,20 +259,16 @@ def test_orientation_matches_oracle(T, ctx, small):
     starts = synth.start_vectors()
     score, lam, u = T.extract(ctx, d, cuda(Cs), starts=cuda(starts), max_iter=500, tol=1e-5)
     lg, ug = host(lam).ravel(), host(u).reshape(-1, 3)
-    cs = orc.score(Co, n)
-    med = np.median(cs)
-    checked = 0
+    med = np.median(orc.score(Co, n))
+    counts = {"agree": 0, "near": 0}
     for j, i in enumerate(idx):
         v = flat[:, i]
-        lam_o, u_o, lams, us, _ = orc.orient_multistart(v, n, starts.astype(np.float64), tol=1e-5,
-                                                        max_iter=500)
-        cn = orc.score(v, n)
-        assert abs(lg[j] - lam_o) <= 1e-4 * max(cn, med)
-        margin = orc.orientation_margin(lams, us, u_o)
-        if margin > 1e-4 * cn:
-            assert orc.angle_deg(ug[j], u_o) < 1.0
-            checked += 1
-    assert checked >= 100
+        lam_o, u_o, *_ = orc.orient_multistart(v, n, starts.astype(np.float64))
+        cls, info = classify_orientation(v, n, lg[j], ug[j], lam_o, u_o, max(orc.score(v, n), med))
+        assert cls is not None, (j, info)
+        counts[cls] += 1
+    print(f"[orientation 160 voxels] {counts}", flush=True)
+    assert counts["agree"] >= 0.8 * len(idx)
 
 
 def test_orientation_rank_one_and_zero(T, ctx):
@@ -362,14 +362,106 @@ def test_full_pass_64cube(T, ctx):
     pko, pvo = orc.find_peaks(full, lo, hi, 5, 2 * r)
     pk = res.peaks.cpu().numpy().astype(np.int64)
     assert np.array_equal(pk, pko)
-    # orientation at the peaks
-    # orientation at the peaks, where the maximiser is well conditioned: the
-    # two sides see fields that differ by rounding (FP32 tensor template and
-    # FFTs), which moves a flat maximum (SS-HOPM factor near 1) by more than 1 deg
-    ug = host(res.direction)
+    # orientation at every peak: agreement with the oracle's converged answer,
+    # or a near-optimal maximiser of the FP64 function (flat or tied maxima)
+    ug, lgm = host(res.direction), host(res.lam)
+    counts = {"agree": 0, "near": 0}
     for p in pko:
         v = C[:, p[0] - lo[0], p[1] - lo[1], p[2] - lo[2]]
-        lam_o, u_o, lams, us, _ = orc.orient_multistart(v, n, synth.start_vectors().astype(np.float64))
-        rate = orc.sshopm_rate(v, n, u_o)
-        if orc.orientation_margin(lams, us, u_o) > 1e-4 * orc.score(v, n) and rate < 0.95:
-            assert orc.angle_deg(ug[p[0], p[1], p[2]], u_o) < 1.0
+        lam_o, u_o, *_ = orc.orient_multistart(v, n, synth.start_vectors().astype(np.float64))
+        cls, info = classify_orientation(v, n, lgm[tuple(p)], ug[tuple(p)], lam_o, u_o,
+                                         max(orc.score(v, n), np.median(cs)))
+        assert cls is not None, (p, info)
+        counts[cls] += 1
+    assert sum(counts.values()) == 5
+
+
+# ------------------------------------------------------------------ guard and quaternion form
+def test_constant_tomogram_gives_zero_weight(T, ctx):
+    """A constant tomogram has zero local variance everywhere: the guard of
+    Eq. norm_f gives w = 0, and with it C = 0 and a zero score (no division by
+    a vanishing variance)."""
+    n, L, r = 4, 12, 5.0
+    d = T.make_desc(n, L, r)
+    K = sym.n_components(n, 3)
+    Tf = np.random.default_rng(1).standard_normal((K, L, L, L)).astype(np.float32)
+    spec = T.template_spectra(ctx, d, cuda(Tf.reshape(K, -1)), 32)
+    vol = cuda(np.full((40, 37, 45), 2.5, np.float32))
+    g, w, stats = T.normalize(ctx, d, vol, spec, 32)
+    assert torch.count_nonzero(w).item() == 0
+    lo, hi = T.valid_bounds(tuple(vol.shape), L)
+    size = tuple(h - l + 1 for l, h in zip(lo, hi))
+    Cg = T.correlate(ctx, d, g, w, stats, spec, 32, lo, size)
+    assert torch.count_nonzero(Cg).item() == 0
+    score, lam, u = T.extract(ctx, d, Cg, starts=cuda(synth.start_vectors()))
+    assert torch.count_nonzero(score).item() == 0 and torch.count_nonzero(lam).item() == 0
+
+
+def test_quaternion_form_tensor_field_and_score(T, ctx, small):
+    """d' = 4 (the paper's quaternion form, K = 35 at n = 4): the tensor template
+    (Alg. 1 with v_q = q), the tensor field (Alg. 2) and the Frobenius score
+    against the oracle on the ragged multi-tile case."""
+    print("[quaternion form n=4]", flush=True)
+    n, L, r = 4, small["L"], small["r"]
+    d = T.make_desc(n, L, r, dprime=4)
+    K = sym.n_components(n, 4)
+    assert T.n_components(n, 4) == K == 35
+    Tg, _ = T.build_tensor(ctx, d, cuda(small["w"].template), cuda(small["Q"]))
+    T4 = orc.tensor_template(small["tn"], small["Q"], n, dprime=4)
+    assert np.linalg.norm(host(Tg) - T4) / np.linalg.norm(T4) < 1e-5
+    spec = T.template_spectra(ctx, d, Tg, 32)
+    g, w, stats = T.normalize(ctx, d, cuda(small["w"].volume), spec, 32)
+    lo, hi = T.valid_bounds(small["w"].volume.shape, L)
+    size = tuple(h - l + 1 for l, h in zip(lo, hi))
+    Cg = T.correlate(ctx, d, g, w, stats, spec, 32, lo, size)
+    Co = orc.tensor_field(small["g"], small["wmap"], T4)
+    cs = orc.score(Co, n, 4)
+    floor = np.maximum(cs, np.median(cs))
+    dC = np.sqrt(np.tensordot(sym.weights(n, 4), (host(Cg) - Co) ** 2, axes=(0, 0)))
+    assert np.max(dC / floor) < 1e-4
+    score, _, _ = T.extract(ctx, d, Cg, orient=False)
+    assert np.max(np.abs(host(score) - cs) / floor) < 1e-4
+
+
+def test_quaternion_orientation_matches_oracle(T, ctx, small):
+    """d' = 4 orientation (Sec. 3.1 on S^3, quaternions): rank-one tensors
+    lambda0 q^n give back (lambda0, +-q) with w >= 0, a zero tensor gives 0, and
+    at 120 sampled voxels of the d' = 4 field every answer agrees with the
+    oracle's converged multistart answer (rotation distance 2 arccos|q1.q2| <
+    1 degree) or is a near-optimal maximiser of the FP64 function."""
+    print("[quaternion orientation n=4]", flush=True)
+    n, L, r = 4, small["L"], small["r"]
+    d = T.make_desc(n, L, r, dprime=4)
+    K = 35
+    starts = synth.start_vectors(count=32, dim=4)
+    rng = np.random.default_rng(21)
+    qs = rng.standard_normal((64, 4))
+    qs /= np.linalg.norm(qs, axis=1, keepdims=True)
+    lam0 = rng.uniform(0.5, 2.0, 64)
+    C = (lam0[:, None] * sym.monomials(qs, n)).T.reshape(K, 1, 1, 64).copy()
+    C[:, 0, 0, 0] = 0.0
+    score, lam, u = T.extract(ctx, d, cuda(C), starts=cuda(starts))
+    lg, ug, sg = host(lam).ravel(), host(u).reshape(-1, 4), host(score).ravel()
+    assert lg[0] == 0 and np.all(ug[0] == 0) and sg[0] == 0
+    assert np.allclose(lg[1:], lam0[1:], rtol=1e-4)
+    assert np.allclose(sg[1:], lam0[1:], rtol=1e-5)
+    assert np.max(orc.quat_angle_deg(ug[1:], qs[1:])) < 0.05
+    assert np.all(ug[1:, 0] >= 0)
+    # sampled voxels of the d' = 4 field of the ragged case
+    T4 = orc.tensor_template(small["tn"], small["Q"], n, dprime=4)
+    Co = orc.tensor_field(small["g"], small["wmap"], T4)
+    flat = Co.reshape(K, -1)
+    idx = rng.choice(flat.shape[1], 120, replace=False)
+    Cs = np.ascontiguousarray(flat[:, idx]).reshape(K, 1, 1, -1)
+    _, lam, u = T.extract(ctx, d, cuda(Cs), starts=cuda(starts))
+    lg, ug = host(lam).ravel(), host(u).reshape(-1, 4)
+    med = np.median(orc.score(Co, n, 4))
+    counts = {"agree": 0, "near": 0}
+    for j, i in enumerate(idx):
+        v = flat[:, i]
+        lam_o, u_o, *_ = orc.orient_multistart(v, n, starts.astype(np.float64))
+        cls, info = classify_orientation(v, n, lg[j], ug[j], lam_o, u_o, max(orc.score(v, n, 4), med))
+        assert cls is not None, (j, info)
+        counts[cls] += 1
+    print(f"[quaternion orientation 120 voxels] {counts}", flush=True)
+    assert counts["agree"] >= 0.8 * len(idx)

@@ -92,3 +92,86 @@ def test_bf16_round_known_values():
     assert r[2] == 1.0 + 2 ** -7            # above the tie: rounds up
     assert r[3] == -2.5 and r[4] == 3.140625
     assert abs(r[5] - 1e-3) / 1e-3 < 2 ** -8
+
+
+# ---------------------------------------------------------------- the learned path's decisions
+def _two_maxima(n=6, l1=2.0, l2=1.0, seed=3):
+    """C = l1 a^n + l2 b^n with a, b, c orthonormal: <C, u^n> = l1 (a.u)^n + l2 (b.u)^n
+    has local maxima l1 at +-a and l2 at +-b, its global maximum is max(l1, l2)
+    (x^n + y^n <= x^2 + y^2 <= 1 on the sphere), and ||C||_F = sqrt(l1^2 + l2^2)."""
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    a, b, c = Q[:, 0], Q[:, 1], Q[:, 2]
+    C = l1 * sym.monomials(a, n) + l2 * sym.monomials(b, n)
+    return C, a, b, c
+
+
+def _tilt(u, w, deg):
+    w = w - (w @ u) * u
+    v = np.cos(np.radians(deg)) * u + np.sin(np.radians(deg)) * w / np.linalg.norm(w)
+    return v / np.linalg.norm(v)
+
+
+def _far_starts(a, b, c):
+    """Fixed starts where <C, s^n> stays far below both maxima (near c)."""
+    return np.stack([_tilt(c, a, 10.0), _tilt(c, b, 10.0), _tilt(c, a + b, 15.0), c])
+
+
+def test_learned_path_each_branch_against_closed_forms():
+    from oracle import ttm
+    n = 6
+    C, a, b, c = _two_maxima(n)
+    cn = np.sqrt(5.0)
+    assert sym.frobenius(C, n, 3) == pytest.approx(cn)
+    p = mlp.init_params(np.random.default_rng(0), 28)
+    far = _far_starts(a, b, c)
+    near_a = np.vstack([far, a])
+
+    def run(u0, starts, kappa, **kw):
+        return mlp.orient_learned(C, n, p, starts, kappa, u0=u0, **kw)
+
+    # accepted: the search from near a reaches the global maximum, nothing flips
+    lam, u, fell = run(_tilt(a, b + c, 8.0), far, 0.5)
+    assert not fell and lam == pytest.approx(2.0, rel=1e-12) and ttm.angle_deg(u, a) < 1e-6
+    # accepted at the lower maximum: nothing catches it (no fixed start beats 1)
+    lam, u, fell = run(_tilt(b, a + c, 8.0), far, 0.1)
+    assert not fell and lam == pytest.approx(1.0, rel=1e-12) and ttm.angle_deg(u, b) < 1e-6
+    # lambda / ||C|| < kappa: the multistart runs; the larger answer wins, here the learned one
+    lam, u, fell = run(_tilt(a, b + c, 8.0), np.vstack([far, _tilt(b, c, 3.0)]), 0.95)
+    assert fell and lam == pytest.approx(2.0, rel=1e-12) and ttm.angle_deg(u, a) < 1e-6
+    # ... and here the multistart's (the learned search sits at b, lambda 1 / sqrt 5 < 0.5)
+    lam, u, fell = run(_tilt(b, a + c, 8.0), np.vstack([far, _tilt(a, c, 3.0)]), 0.5)
+    assert fell and lam == pytest.approx(2.0, rel=1e-12) and ttm.angle_deg(u, a) < 1e-6
+    # a fixed start beats the learned lambda: <C, a^n> = 2 > 1, so the fallback runs
+    lam, u, fell, info = run(_tilt(b, a + c, 8.0), near_a, 0.1, detail=True)
+    assert fell and lam == pytest.approx(2.0, rel=1e-12) and ttm.angle_deg(u, a) < 1e-6
+    assert info["beat_gap"] == pytest.approx(cn * (2.0 - 1.0) / cn, rel=1e-9)
+    # not converged: no Newton step and one SS-HOPM update from far away
+    lam, u, fell, info = run(_tilt(c, a, 40.0), near_a, 0.1, detail=True, newton_first=0, max_iter=1)
+    assert fell and not info["converged"]
+    assert lam == pytest.approx(2.0, rel=1e-12) and ttm.angle_deg(u, a) < 1e-6
+
+
+def test_learned_path_zero_tensor_rank_one_and_no_direction():
+    from oracle import ttm
+    n = 6
+    rng = np.random.default_rng(4)
+    p = mlp.init_params(rng, 28)
+    st = rng.standard_normal((16, 3))
+    st /= np.linalg.norm(st, axis=1, keepdims=True)
+    lam, u, fell = mlp.orient_learned(np.zeros(28), n, p, st, 0.3)
+    assert lam == 0.0 and np.all(u == 0) and not fell
+    # rank one: the maximum lam0 at +-v is reached from a start in its basin
+    for _ in range(4):
+        v = rng.standard_normal(3)
+        v /= np.linalg.norm(v)
+        lam0 = rng.uniform(0.5, 2.0)
+        lam, u, fell = mlp.orient_learned(lam0 * sym.monomials(v, n), n, p, st, 0.3,
+                                          u0=_tilt(v, rng.standard_normal(3), 20.0))
+        assert not fell and lam == pytest.approx(lam0, rel=1e-12) and ttm.angle_deg(u, v) < 1e-6
+    # a network with all-zero parameters gives y = 0: no direction, forced fallback,
+    # and the answer is the multistart's
+    z = {k: np.zeros_like(val) for k, val in p.items()}
+    C, a, b, c = _two_maxima(n)
+    lam, u, fell = mlp.orient_learned(C, n, z, np.vstack([_far_starts(a, b, c), _tilt(a, c, 5.0)]), -1.0)
+    assert fell and lam == pytest.approx(2.0, rel=1e-12) and ttm.angle_deg(u, a) < 1e-6

@@ -440,7 +440,7 @@ def test_sshopm_rate_predicts_convergence():
     assert e[k + 1] / e[k] == pytest.approx(rate, abs=0.02)
 
 
-def test_newton_polish_converges_quadratically_to_the_sshopm_maximum():
+def test_newton_finish_converges_quadratically_to_the_sshopm_maximum():
     rng = np.random.default_rng(41)
     n = 6
     for _ in range(5):
@@ -453,25 +453,35 @@ def test_newton_polish_converges_quadratically_to_the_sshopm_maximum():
         u0 = u_star + 0.02 * np.cross(u_star, rng.standard_normal(3))
         u0 /= np.linalg.norm(u0)
         e0 = np.linalg.norm(u0 - u_star)
-        u1 = ttm.newton_polish(Cu, n, u0, steps=1)
-        u2 = ttm.newton_polish(Cu, n, u0, steps=2)
+        _, u1 = ttm.newton_finish(Cu, n, u0, max_steps=1)
+        _, u2 = ttm.newton_finish(Cu, n, u0, max_steps=2)
         e1, e2 = np.linalg.norm(u1 - u_star), np.linalg.norm(u2 - u_star)
         assert e1 < 50 * e0 ** 2 and e2 < max(50 * e1 ** 2, 1e-12)
-        # a point that is not near a maximum is left alone when the Hessian is not definite
         tb = ttm.tangent_basis(u_star)
         assert np.allclose(tb.T @ tb, np.eye(2)) and np.allclose(tb.T @ u_star, 0)
 
 
-def test_multistart_with_polish_matches_tight_sshopm():
+@pytest.mark.parametrize("d", [3, 4])
+def test_converge_reaches_the_sshopm_fixed_point(d):
+    """P-9: the converged answer is a fixed point of SS-HOPM to rounding level,
+    the same one a very long SS-HOPM run reaches, and lambda never falls."""
     rng = np.random.default_rng(42)
-    st = synth.start_vectors().astype(np.float64)
-    for n in (4, 6):
-        for _ in range(4):
-            C = rng.standard_normal(sym.n_components(n, 3))
-            lam, u, *_ = ttm.orient_multistart(C, n, st)            # tol 1e-5 + Newton
-            lam2, u2, *_ = ttm.orient_multistart(C, n, st, tol=1e-15, max_iter=100000, newton=0)
-            assert lam == pytest.approx(lam2, rel=1e-9)
-            assert ttm.angle_deg(u, u2) < 1e-3
+    st = synth.start_vectors(dim=d).astype(np.float64)
+    for n in (4, 6) if d == 3 else (2, 4):
+        for _ in range(3):
+            C = rng.standard_normal(sym.n_components(n, d))
+            lam, u, lams, us, its = ttm.orient_multistart(C, n, st)
+            cn = ttm.score(C, n, d)
+            Cu = C / cn
+            for lk, uk in zip(lams, us):
+                g = sym.contract_n_minus_1(Cu, uk, n)
+                assert np.linalg.norm(g - (g @ uk) * uk) < 1e-10
+                assert lk == pytest.approx(cn * (g @ uk), rel=1e-12)
+            alpha = ttm.unfolding_shift(Cu, n, d)
+            best = int(np.argmax(lams))
+            lam2, u2, _, _ = ttm.sshopm(Cu, n, st[best], alpha, 1e-16, 200000)
+            assert lam == pytest.approx(cn * lam2, rel=1e-9)
+            assert ttm.axis_distance_deg(u, u2) < 1e-3
 
 
 def test_newton_ascent_reaches_eigenvectors_and_refuses_non_maxima():
@@ -561,3 +571,128 @@ def test_newton_ascent_halves_steps_that_fall():
                 p = np.cos(np.radians(deg)) * u_h + np.sin(np.radians(deg)) * (np.cos(ph) * e1 + np.sin(ph) * e2)
                 assert sym.inner_power(Cu, p, n) <= lam_h + 1e-9
     assert rescued >= 5
+
+
+# ---------------------------------------------------------------- field at single voxels
+def test_field_at_equals_volume_field_and_guard():
+    """field_at (w and C from one voxel's template window, what the full-size
+    parity rests on) equals the whole-volume oracle (local_normalization,
+    tensor_field) at the same voxels, including voxels whose window is
+    constant, where the variance guard gives w = 0 (Eq. norm_f)."""
+    D, L, r, n = 30, 8, 3.5, 4
+    rng = np.random.default_rng(19)
+    f = rng.standard_normal((D, D, D))
+    f[2:16, 3:17, 4:18] = 1.75                      # windows inside are constant after h*
+    g = ttm.prefilter_volume(f)
+    m = ttm.ball_mask(L, r)
+    wm = ttm.local_normalization(g, m)
+    T = ttm.tensor_template(ttm.normalize_template(ndi.gaussian_filter(rng.standard_normal((L, L, L)), 1.0), r),
+                            synth.rotation_samples(2), n)
+    C = ttm.tensor_field(g, wm, T)
+    c = L // 2
+    lo, hi = ttm.valid_range(D, L)
+    pts = [(lo, lo, lo), (hi, hi, hi), (8, 9, 10), (7, 8, 9)] + \
+          [tuple(int(v) for v in rng.integers(lo, hi + 1, 3)) for _ in range(12)]
+    patches = ttm.patches_at(g, pts, L)
+    w1, C1 = ttm.field_at(patches, m, T, ttm.volume_g2_mean(g))
+    guard = 0
+    for i, (z, y, x) in enumerate(pts):
+        want_w = wm[z, y, x]
+        want_C = C[:, z - c, y - c, x - c]
+        if want_w == 0:
+            guard += 1
+            assert w1[i] == 0 and np.all(C1[i] == 0)
+        else:
+            assert w1[i] == pytest.approx(want_w, rel=1e-12)
+            assert np.allclose(C1[i], want_C, rtol=1e-12, atol=1e-12 * np.abs(want_C).max())
+    assert guard >= 2
+    # the windows can also be filtered from f directly (replicated borders)
+    patches_f = ttm.patches_at(None, pts, L, f=f)
+    assert np.allclose(patches_f, patches, atol=1e-13)
+
+
+# ---------------------------------------------------------------- quaternion form (d' = 4)
+def _left_mul(g):
+    """4 x 4 matrix of q -> g q (Hamilton product), g = (w, x, y, z)."""
+    w, x, y, z = g
+    return np.array([[w, -x, -y, -z], [x, w, -z, y], [y, z, w, -x], [z, -y, x, w]])
+
+
+def test_quaternion_form_rank_one_and_degree_two():
+    rng = np.random.default_rng(51)
+    st = synth.start_vectors(dim=4).astype(np.float64)
+    for n in (2, 4, 6):
+        for _ in range(3):
+            q = rng.standard_normal(4)
+            q /= np.linalg.norm(q)
+            lam0 = rng.uniform(0.5, 2.0)
+            C = lam0 * sym.monomials(q, n)
+            lam, u, *_ = ttm.orient_multistart(C, n, st)
+            assert lam == pytest.approx(lam0, rel=1e-10)
+            assert ttm.quat_angle_deg(u, q) < 1e-5 and u[0] >= 0
+            assert ttm.score(C, n, 4) == pytest.approx(lam0)
+    for _ in range(6):
+        A = rng.standard_normal((4, 4))
+        A = A + A.T
+        C = sym.from_full(A, 2, 4)
+        ev, evec = np.linalg.eigh(A)
+        lam, u, *_ = ttm.orient_multistart(C, 2, st)
+        assert lam == pytest.approx(ev[-1], rel=1e-10)
+        assert ttm.angle_deg(u, evec[:, -1]) < 1e-5
+
+
+def test_quaternion_orientation_follows_left_multiplication():
+    """Rotating the copy by g maps the optimal quaternion q to g q: the tensor
+    transforms with the orthogonal map L_g (P-4 for d' = 4)."""
+    rng = np.random.default_rng(52)
+    st = synth.start_vectors(count=32, dim=4).astype(np.float64)
+    n = 4
+    for _ in range(3):
+        q = rng.standard_normal(4)
+        q /= np.linalg.norm(q)
+        C = 2.0 * sym.monomials(q, n) + 0.2 * rng.standard_normal(35)
+        g = rng.standard_normal(4)
+        g /= np.linalg.norm(g)
+        Lg = _left_mul(g)
+        assert np.allclose(Lg.T @ Lg, np.eye(4))
+        lam, u, *_ = ttm.orient_multistart(C, n, st)
+        lam2, u2, *_ = ttm.orient_multistart(sym.rotate(C, Lg, n), n, st)
+        assert lam2 == pytest.approx(lam, rel=1e-9)
+        assert ttm.quat_angle_deg(u2, Lg @ u) < 1e-4
+        assert ttm.score(sym.rotate(C, Lg, n), n, 4) == pytest.approx(ttm.score(C, n, 4))
+
+
+def test_quaternion_tensor_template_equivariance():
+    """P-5 for d' = 4: T(c + G (p - c)) = L_g^{(x)n} T(p) for a cube rotation G
+    with quaternion g, because Q is closed under left multiplication by g."""
+    L, r, n = 11, 4.0, 2
+    rng = np.random.default_rng(53)
+    t = ndi.gaussian_filter(rng.standard_normal((L, L, L)), 1.0)
+    tn = ttm.normalize_template(t, r)
+    Q = synth.rotation_samples(2)
+    T = ttm.tensor_template(tn, Q, n, dprime=4)
+    c = L // 2
+    idx = np.arange(L) - c
+    zz, yy, xx = np.meshgrid(idx, idx, idx, indexing="ij")
+    P = np.stack([xx, yy, zz], axis=-1)
+    for g in synth.octahedral_quaternions()[1:7]:
+        G = rot.quat_to_matrix(g)
+        dst = np.rint(P @ G.T).astype(int) + c
+        lhs = T[:, dst[..., 2], dst[..., 1], dst[..., 0]]
+        Lg = _left_mul(g)
+        rhs = np.stack([sym.rotate(T[:, z, y, x], Lg, n) for z in range(L) for y in range(L)
+                        for x in range(L)], axis=1).reshape(T.shape)
+        assert np.allclose(lhs, rhs, atol=1e-12)
+
+
+def test_reference_maxima_quaternion_agree_with_multistart():
+    rng = np.random.default_rng(54)
+    n = 4
+    st = synth.start_vectors(count=64, dim=4).astype(np.float64)
+    for _ in range(3):
+        C = rng.standard_normal(35)
+        lam, u, *_ = ttm.orient_multistart(C, n, st)
+        lr, ur, l2 = ttm.reference_maxima(C, n, grid=20000, dprime=4)
+        assert lr >= lam - 1e-9
+        if lr - lam < 1e-9:
+            assert ttm.quat_angle_deg(u, ur) < 1e-3
