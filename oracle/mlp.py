@@ -148,42 +148,51 @@ def unpad_params(flat: np.ndarray, k_in: int, d_out: int = 3) -> dict:
 
 def orient_learned(Cv: np.ndarray, n: int, p: dict, starts: np.ndarray, kappa: float,
                    tol: float = 1e-5, max_iter: int = 500, bf16: bool = True,
-                   detail: bool = False, newton_first: int = 5, u0: np.ndarray | None = None):
+                   detail: bool = False, newton_first: int = 5, u0: np.ndarray | None = None,
+                   polish: int = 2, certify: float = 1e-2):
     """Orientation with the learned start and its multistart fallback (d' = 3).
 
     The learned start replaces the paper's seeds of SS-HOPM (Sec. 3.1); its
-    search parameters (tol, max_iter, newton_first and the Newton search's
-    drop rule) are part of that method's definition, since they decide which
-    basin the answer comes from and whether the multistart runs:
+    search parameters (tol, max_iter, newton_first, polish, certify and the
+    Newton search's drop rule) are part of that method's definition, since
+    they decide which basin the answer comes from and whether the multistart
+    runs:
 
     1. u0 = y / |y| from the network (fixed start 0 where y = 0, which also
        forces the fallback);
     2. up to ``newton_first`` Riemannian Newton steps (ttm.newton_ascent); if
        they do not converge, SS-HOPM from u0 with the unfolding shift until
-       |delta lambda| <= tol or max_iter updates; "converged" is the outcome of
-       the search that ran last;
-    3. the learned answer is the converged maximum of the basin the search
+       |delta lambda| <= tol or max_iter updates, then ``polish`` Newton steps
+       (ttm.newton_polish); "converged" is the outcome of the search that ran
+       last;
+    3. the end point is certified when the tangent Hessian there is negative
+       definite and the next Newton step is at most ``certify`` long (a slow
+       SS-HOPM run on a flat, curved ridge can meet its stopping rule far from
+       the maximum);
+    4. the learned answer is the converged maximum of the basin the search
        ended in (ttm.converge from its end point);
-    4. fallback when the search did not converge, lambda / ||C||_F < kappa, or
-       a fixed start s already has <C, s^n> > lambda (SS-HOPM never lowers
-       lambda, so the multistart answer is then larger): the multistart answer
-       (ttm.orient_multistart) is computed too and the larger lambda wins.
+    5. fallback when the search did not converge, the end point is not
+       certified, lambda / ||C||_F < kappa, or a fixed start s already has
+       <C, s^n> > lambda (SS-HOPM never lowers lambda, so the multistart
+       answer is then larger): the multistart answer (ttm.orient_multistart)
+       is computed too and the larger lambda wins.
 
     Returns (lambda, u, fell_back), and with ``detail`` a fourth item: a dict
     with the learned answer (lam_learned, u_learned), how far each fallback
     test was from flipping (beat_gap = best fixed-start value minus the
-    learned lambda, scaled by ||C||_F; kappa_gap = lambda / ||C||_F - kappa),
-    whether the search converged, and after a fallback the multistart's
-    per-start lambdas and directions.  ``u0`` (a unit vector) replaces the
-    network's direction, to probe how the answer depends on the start.
+    learned lambda, scaled by ||C||_F; kappa_gap = lambda / ||C||_F - kappa;
+    cert_step = the Newton step length at the end point), whether the search
+    converged, and after a fallback the multistart's per-start lambdas and
+    directions.  ``u0`` (a unit vector) replaces the network's direction, to
+    probe how the answer depends on the start.
     """
     from . import ttm
     cn = float(sym.frobenius(Cv, n, 3))
     if cn == 0.0:
         out = (0.0, np.zeros(3), False)
         return out + ({"lam_learned": 0.0, "u_learned": np.zeros(3), "beat_gap": -np.inf,
-                       "kappa_gap": np.inf, "converged": True, "lams": None, "us": None},) \
-            if detail else out
+                       "kappa_gap": np.inf, "cert_step": 0.0, "converged": True, "lams": None,
+                       "us": None},) if detail else out
     forced = False
     if u0 is None:
         y, _ = forward(p, features(Cv[None, :], n), bf16=bf16)
@@ -196,12 +205,14 @@ def orient_learned(Cv: np.ndarray, n: int, p: dict, starts: np.ndarray, kappa: f
     u, lam, conv = ttm.newton_ascent(Cu, n, u0, newton_first, tol)
     if not conv:
         lam, u, _, conv = ttm.sshopm(Cu, n, u0, alpha, tol, max_iter)
+        u = ttm.newton_polish(Cu, n, u, polish)
+    step = ttm.newton_step_length(Cu, n, u)
     lam, u, _ = ttm.converge(Cu, n, u, alpha)
     fs = max(sym.inner_power(Cu, s / np.linalg.norm(s), n) for s in starts)
     beaten = fs > lam
     info = {"lam_learned": cn * lam, "u_learned": ttm.canonical_sign(u), "beat_gap": cn * (fs - lam),
-            "kappa_gap": lam - kappa, "converged": conv, "lams": None, "us": None}
-    if conv and not forced and lam >= kappa and not beaten:
+            "kappa_gap": lam - kappa, "cert_step": step, "converged": conv, "lams": None, "us": None}
+    if conv and step <= certify and not forced and lam >= kappa and not beaten:
         out = (cn * lam, ttm.canonical_sign(u), False)
         return out + (info,) if detail else out
     lam_p, u_p, lams, us, _ = ttm.orient_multistart(Cv, n, starts)

@@ -441,6 +441,38 @@ def newton_ascent(Cu: np.ndarray, n: int, u0: np.ndarray, steps: int, tol: float
     return u, lam, False
 
 
+def newton_polish(Cu: np.ndarray, n: int, u: np.ndarray, steps: int = 2,
+                  drop: float = 1e-7) -> np.ndarray:
+    """Up to ``steps`` Newton steps on the sphere from u, each taken only where
+    the tangent Hessian is negative definite and kept only if lambda does not
+    fall by more than ``drop``.  The learned start's search ends its SS-HOPM
+    continuation with these steps (part of that method's definition: the point
+    they reach is the one its acceptance test looks at)."""
+    u = np.asarray(u, dtype=np.float64)
+    for _ in range(steps):
+        g = sym.contract_n_minus_1(Cu, u, n)
+        lam = float(g @ u)
+        d = newton_direction(Cu, n, u, g, lam)
+        if d is None:
+            break
+        un = u + d
+        un = un / np.linalg.norm(un)
+        if float(sym.contract_n_minus_1(Cu, un, n) @ un) < lam - drop:
+            break
+        u = un
+    return u
+
+
+def newton_step_length(Cu: np.ndarray, n: int, u: np.ndarray) -> float:
+    """Length of the Riemannian Newton step at u (an estimate of the distance to
+    the local maximum near u), or inf where the tangent Hessian is not negative
+    definite (u is then not near a local maximum)."""
+    u = np.asarray(u, dtype=np.float64)
+    g = sym.contract_n_minus_1(Cu, u, n)
+    d = newton_direction(Cu, n, u, g, float(g @ u))
+    return np.inf if d is None else float(np.linalg.norm(d))
+
+
 def orient_multistart(Cv: np.ndarray, n: int, starts: np.ndarray, tol: float = 1e-13,
                       max_iter: int = 10000, shift: float | None = None):
     """Dominant eigenpair of one voxel's tensor from fixed starts (Sec. 3.1).

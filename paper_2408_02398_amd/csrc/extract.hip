@@ -790,17 +790,26 @@ __global__ __launch_bounds__(256) void k_reduce(ExtractArgs a, Items it, int nsb
 // ---------------------------------------------------------------------------
 
 // Polish, screen and write a learned-start answer; mark the voxel for the
-// multistart search (status 2) when the run did not converge, lambda / ||C||_F < kappa,
-// the network gave no direction, or some fixed start s already has
-// <C, s^n> above lambda (SS-HOPM never lowers lambda, so the multistart
-// answer is then higher).
+// multistart search (status 2) when the run did not converge, the answer is
+// not certified near a local maximum (the tangent Hessian there is not
+// negative definite, or the next Newton step is longer than kCertify: a slow
+// SS-HOPM run on a flat, curved ridge can meet the stopping rule far from its
+// maximum), lambda / ||C||_F < kappa, the network gave no direction, or some
+// fixed start s already has <C, s^n> above lambda (SS-HOPM never lowers
+// lambda, so the multistart answer is then higher).
+constexpr float kCertify = 1e-2f;
+
 template <int N>
 __device__ __forceinline__ unsigned long long learned_finish(
     const ExtractArgs& a, const Ws& w, const float (&c)[ncomp3(N)], float cn, size_t v,
     const float* mono, float ux, float uy, float uz, float g0, float g1, float g2, float lam,
     bool conv, bool forced, int polish, bool& fell) {
   constexpr int K = ncomp3(N);
-  const unsigned long long taken = newton_polish<N>(c, ux, uy, uz, g0, g1, g2, lam, polish);
+  unsigned long long taken = newton_polish<N>(c, ux, uy, uz, g0, g1, g2, lam, polish);
+  float dx, dy, dz;
+  const bool certified = newton_dir<N>(c, ux, uy, uz, g0, g1, g2, lam, dx, dy, dz) &&
+                         dx * dx + dy * dy + dz * dz <= kCertify * kCertify;
+  taken += 1;
   bool beaten = false;
   if (a.screen) {
     for (int s = 0; s < a.n_starts; ++s) {
@@ -810,7 +819,7 @@ __device__ __forceinline__ unsigned long long learned_finish(
       beaten = beaten || f > lam;
     }
   }
-  const bool fallback = forced || !conv || !(lam >= a.kappa) || beaten;
+  const bool fallback = forced || !conv || !certified || !(lam >= a.kappa) || beaten;
   canonical(ux, uy, uz);
   write_answer(a, map_index(a, v), lam * cn, ux, uy, uz);
   w.status[v] = fallback ? 2 : 0;

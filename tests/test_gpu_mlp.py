@@ -151,7 +151,8 @@ def test_training_learns_and_learned_path_matches_oracle(T, ctx):
         # a fallback test within rounding of flipping may go either way on the
         # GPU: then either branch's answer is one the method gives
         alts = []
-        if abs(info["beat_gap"]) < 1e-4 * cn or abs(info["kappa_gap"]) < 1e-4:
+        if (abs(info["beat_gap"]) < 1e-4 * cn or abs(info["kappa_gap"]) < 1e-4
+                or abs(info["cert_step"] - 1e-2) < 3e-3):
             alts.append((info["lam_learned"], info["u_learned"]))
             alts.append(orc.orient_multistart(Ct[i], n, st64)[:2])
         cls, det = classify_orientation(Ct[i], n, lg[i], ug[i], lo, uo, cn, alts)

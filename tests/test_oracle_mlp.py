@@ -1,4 +1,6 @@
 """Pins of the FP64 learned-start network: finite differences, invariances, Adam's first step."""
+import math
+
 import numpy as np
 import pytest
 
@@ -112,6 +114,20 @@ def _tilt(u, w, deg):
     return v / np.linalg.norm(v)
 
 
+def _isotropic(n):
+    """E with <E, u^n> = (u.u)^{n/2}: the coefficient of u^alpha in (x^2 + y^2 + z^2)^{n/2},
+    divided by mu_alpha (components store full-tensor entries)."""
+    out = []
+    for al in sym.multi_indices(n, 3):
+        if any(x % 2 for x in al):
+            out.append(0.0)
+            continue
+        h = [x // 2 for x in al]
+        coef = math.factorial(n // 2) // (math.factorial(h[0]) * math.factorial(h[1]) * math.factorial(h[2]))
+        out.append(coef / sym.multinomial(al))
+    return np.array(out)
+
+
 def _far_starts(a, b, c):
     """Fixed starts where <C, s^n> stays far below both maxima (near c)."""
     return np.stack([_tilt(c, a, 10.0), _tilt(c, b, 10.0), _tilt(c, a + b, 15.0), c])
@@ -146,6 +162,16 @@ def test_learned_path_each_branch_against_closed_forms():
     lam, u, fell, info = run(_tilt(b, a + c, 8.0), near_a, 0.1, detail=True)
     assert fell and lam == pytest.approx(2.0, rel=1e-12) and ttm.angle_deg(u, a) < 1e-6
     assert info["beat_gap"] == pytest.approx(cn * (2.0 - 1.0) / cn, rel=1e-9)
+    # converged by a loose stopping rule far from the maximum: not certified.
+    # C2 = a^n + 2 E, with <E, u^n> = |u|^n, has <C2, u^n> = (a.u)^n + 2 on the
+    # sphere: its maximum 3 sits at +-a, and SS-HOPM moves slowly (the radial
+    # part of E); one update from 30 degrees away meets tol = 1 with the
+    # tangent Hessian not negative definite there, so the fallback runs
+    C2 = sym.monomials(a, n) + 2.0 * _isotropic(n)
+    lam, u, fell, info = mlp.orient_learned(C2, n, p, near_a, 0.1, u0=_tilt(a, b, 30.0), detail=True,
+                                            newton_first=0, tol=1.0, polish=0)
+    assert info["converged"] and info["cert_step"] > 1e-2
+    assert fell and lam == pytest.approx(3.0, rel=1e-12) and ttm.angle_deg(u, a) < 1e-6
     # not converged: no Newton step and one SS-HOPM update from far away
     lam, u, fell, info = run(_tilt(c, a, 40.0), near_a, 0.1, detail=True, newton_first=0, max_iter=1)
     assert fell and not info["converged"]
