@@ -260,6 +260,22 @@ int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
                 int32_t* n_fallback, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * ttm_extract without a workspace argument, for callers that cannot allocate
+ * device memory (code under stream / graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, rules and results as
+ * ttm_extract; the scratch is a 64 MiB array the library holds on each GPU
+ * it runs on (about 150 000 box voxels at degree 6), so the call allocates
+ * nothing.  A box whose orientation scratch would exceed it is rejected with
+ * TTM_EUNSUPPORTED before anything is enqueued.  Every call on one GPU shares
+ * that array (the kernels clear what must start at zero): calls that overlap
+ * on one GPU, on any streams, race and must be ordered by the caller.
+ */
+int ttm_extract_noalloc(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
+                        const int32_t box_size[3], const ttm_extract_opts* opts, float* score,
+                        float* lambda, float* dir, const int32_t out_lo[3],
+                        const int32_t out_dims[3], int32_t* n_fallback, void* stream);
+
+/*
  * Learned start network (a seed for the orientation search of Sec. 3.1):
  * x (K <= 32 features, zero padded) -> 64 -> relu -> 64 -> relu -> 3, BF16
  * weights, FP32 accumulation, activations rounded to BF16.

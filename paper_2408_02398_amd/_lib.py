@@ -63,6 +63,9 @@ SIGNATURES = {
     "ttm_extract": (C.c_int, [vp, DP, vp, C.c_int, C.POINTER(C.c_int32), C.POINTER(ExtractOpts),
                               vp, vp, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), vp, vp,
                               C.c_size_t, vp]),
+    "ttm_extract_noalloc": (C.c_int, [vp, DP, vp, C.c_int, C.POINTER(C.c_int32),
+                                      C.POINTER(ExtractOpts), vp, vp, vp, C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32), vp, vp]),
     "ttm_mlp_param_count": (C.c_size_t, []),
     "ttm_mlp_packed_bytes": (C.c_size_t, []),
     "ttm_mlp_pack": (C.c_int, [vp, vp, vp, vp]),

@@ -16,7 +16,15 @@
 struct ttm_ctx {
   int device;
   ttm::cf* twiddles;
+  void* scratch;   // device address of `scratch` on this context's GPU
 };
+
+// Scratch of ttm_extract_noalloc, for callers that cannot allocate: one copy
+// per GPU the library runs on, held until the process ends.  In host code the
+// name is a stand-in, not a device address: ttm_create resolves the address
+// on each context's device (hipGetSymbolAddress) and only that is used.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 namespace ttm {
 
@@ -450,7 +458,9 @@ int ttm_create(ttm_ctx** out, int device) {
     return TTM_EINVAL;
   }
   TTM_HIP(hipSetDevice(device));
-  ttm_ctx* c = new (std::nothrow) ttm_ctx{device, nullptr};
+  void* scratch_ptr = nullptr;
+  TTM_HIP(hipGetSymbolAddress(&scratch_ptr, HIP_SYMBOL(scratch)));
+  ttm_ctx* c = new (std::nothrow) ttm_ctx{device, nullptr, scratch_ptr};
   if (!c) {
     set_error("ttm_create: out of host memory");
     return TTM_ENOMEM;
@@ -886,6 +896,32 @@ int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
   }
   return desc->dprime == 4 ? launch_extract4(desc->degree, a, s)
                            : launch_extract(desc->degree, a, s);
+}
+
+int ttm_extract_noalloc(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
+                        const int32_t box_size[3], const ttm_extract_opts* opts, float* score,
+                        float* lambda, float* dir, const int32_t out_lo[3],
+                        const int32_t out_dims[3], int32_t* n_fallback, void* stream) {
+  if (!ctx || !valid_desc(desc)) return TTM_EINVAL;
+  if (!box_size || !opts) {
+    set_error("ttm_extract_noalloc: null pointer");
+    return TTM_EINVAL;
+  }
+  if (box_size[0] < 1 || box_size[1] < 1 || box_size[2] < 1) {
+    set_error("ttm_extract_noalloc: empty box");
+    return TTM_EINVAL;
+  }
+  const size_t plane = (size_t)box_size[0] * box_size[1] * box_size[2];
+  const size_t need = desc->dprime == 4 ? extract_workspace4(plane)
+                                        : extract_workspace(plane, desc->degree);
+  if ((opts->mode & 2) && need > kNoAllocScratchBytes) {
+    set_error("ttm_extract_noalloc: a box of %zu voxels needs %zu bytes of scratch, more than "
+              "the %zu bytes the library holds (use ttm_extract with a workspace)",
+              plane, need, kNoAllocScratchBytes);
+    return TTM_EUNSUPPORTED;
+  }
+  return ttm_extract(ctx, desc, C, in_dtype, box_size, opts, score, lambda, dir, out_lo, out_dims,
+                     n_fallback, ctx->scratch, kNoAllocScratchBytes, stream);
 }
 
 size_t ttm_mlp_param_count(void) { return kMlpParams; }

@@ -174,12 +174,14 @@ def extract(ctx: Context, desc: Desc, Cf: torch.Tensor, *, score=None, lam=None,
             orient: bool = True, max_iter: int = 500, tol: float = 1e-5, newton: int = 2,
             counters: torch.Tensor | None = None, mlp: "MLP | None" = None, kappa: float = 0.0,
             start_only: bool = False, fallbacks: torch.Tensor | None = None,
-            ws: torch.Tensor | None = None, screen: bool = True):
+            ws: torch.Tensor | None = None, screen: bool = True, noalloc: bool = False):
     """Score / lambda / direction maps for the box held in Cf (K x bz x by x bx).
 
     With ``mlp`` the orientation search starts from the learned start and falls
     back to the multistart search where lambda / ||C|| < kappa or SS-HOPM did
     not converge.  ``fallbacks`` (device int32[1]) accumulates the fallback count.
+    ``noalloc`` calls ttm_extract_noalloc (the library's own scratch, no
+    workspace argument).
     """
     _need_cuda(Cf, score, lam, direction, starts)
     box = tuple(Cf.shape[1:])
@@ -208,7 +210,7 @@ def extract(ctx: Context, desc: Desc, Cf: torch.Tensor, *, score=None, lam=None,
                 mode |= L.TTM_NO_SCREEN
             opts.mlp = mlp.packed.data_ptr()
             opts.fallback_kappa = kappa
-        if ws is None:
+        if ws is None and not noalloc:
             ws = _ws(desc, L.TTM_OP_EXTRACT, 0, box, device=dev)
     opts.mode = mode
     opts.max_iter = max_iter
@@ -219,6 +221,12 @@ def extract(ctx: Context, desc: Desc, Cf: torch.Tensor, *, score=None, lam=None,
             raise ValueError("counters must be a device int64 tensor of 5 elements")
         opts.work_counters = counters.data_ptr()
     code = L.TTM_BF16 if Cf.dtype == torch.bfloat16 else L.TTM_F32
+    if noalloc:
+        call("ttm_extract_noalloc", ctx.h, C.byref(desc), _ptr(Cf), code, I32x3(*box),
+             C.byref(opts), _ptr(score), _ptr(lam) if orient else None,
+             _ptr(direction) if orient else None, I32x3(*out_lo), I32x3(*out_dims),
+             _ptr(fallbacks), _stream())
+        return score, lam, direction
     call("ttm_extract", ctx.h, C.byref(desc), _ptr(Cf), code, I32x3(*box), C.byref(opts),
          _ptr(score), _ptr(lam) if orient else None, _ptr(direction) if orient else None,
          I32x3(*out_lo), I32x3(*out_dims), _ptr(fallbacks), _ptr(ws),
