@@ -22,9 +22,11 @@
  * - d' = 3: components are indexed by alpha = (ax, ay, az), |alpha| = n, in
  *   graded-lex order (descending ax, then descending ay); K = (n+1)(n+2)/2.
  *   Component alpha holds the full-tensor entry, so ||C||_F^2 = sum mu_a C_a^2
- *   with mu_a = n!/(ax! ay! az!).  d' = 4 (quaternion form, K = binom(n+3,3))
- *   is accepted by ttm_build_tensor / ttm_template_spectra / ttm_correlate and
- *   the score; orientation extraction at d' = 4 returns TTM_EUNSUPPORTED.
+ *   with mu_a = n!/(ax! ay! az!).  d' = 4 (the paper's quaternion form,
+ *   K = binom(n+3,3), alpha = (aw, ax, ay, az) in graded-lex order) is
+ *   accepted by every entry point; its orientation is a unit quaternion
+ *   (w, x, y, z), 4 floats per voxel, from the multistart search at degree
+ *   2..4 (the learned start is d' = 3 only).
  * - Template: cubic L^3, centre c = L/2 (integer division) on every axis,
  *   binary ball mask m(p) = [|p - c|^2 <= r^2].
  * - Valid region of a volume of extent D along an axis: voxels x with
@@ -75,7 +77,9 @@ typedef enum {
   TTM_OP_PEAKS = 4,
   TTM_OP_EXTRACT = 5,     /* nz x ny x nx = the extraction box            */
   TTM_OP_MLP_TRAIN = 6,   /* nz = batch size, ny = nx = 1                 */
-  TTM_OP_PREFILTER = 7    /* nz x ny x nx = the volume (fft_n unused)     */
+  TTM_OP_PREFILTER = 7,   /* nz x ny x nx = the volume (fft_n unused)     */
+  TTM_OP_REFINE = 8       /* nz = peaks, ny = the refinement radius r_s
+                             rounded up (the size covers every smaller r_s) */
 } ttm_op;
 
 typedef struct ttm_ctx ttm_ctx;
@@ -223,7 +227,7 @@ typedef struct {
  * Per-voxel score and orientation (Sec. 3.1, 3.2) for a box of field values.
  *   C         device, K x bz x by x bx (in_dtype float32 or bfloat16)
  *   score     device map or NULL; lambda device map or NULL; dir device map
- *             (3 floats per voxel, [z][y][x][3]) or NULL
+ *             (d' floats per voxel, [z][y][x][d']) or NULL
  *   out_lo    host int32[3]: where voxel (0,0,0) of the box lands in the maps
  *   out_dims  host int32[3]: extent (z, y, x) of the output maps
  *   n_fallback device int32 counter incremented per voxel whose learned start
@@ -242,7 +246,8 @@ typedef struct {
  * Riemannian Newton steps (taken where the tangent Hessian
  * (n-1) E^T (C u^{n-2}) E - lambda I is negative definite, kept unless lambda
  * drops by more than 1e-7); the largest lambda wins (first on ties); u is
- * signed so its last non-zero coordinate is positive.  The (voxel, start) runs are spread over the GPU's lanes from a
+ * signed so its last non-zero coordinate is positive (d' = 3) or its w is
+ * (d' = 4).  The (voxel, start) runs are spread over the GPU's lanes from a
  * work queue, so a slow run does not hold up other voxels.
  * Learned start (TTM_START_MLP): per wavefront of 64 voxels the network
  * (ttm_mlp_train_step) maps x = sqrt(mu_a) C_a / ||C||_F to a start direction
@@ -274,6 +279,41 @@ int ttm_extract_noalloc(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int i
                         const int32_t box_size[3], const ttm_extract_opts* opts, float* score,
                         float* lambda, float* dir, const int32_t out_lo[3],
                         const int32_t out_dims[3], int32_t* n_fallback, void* stream);
+
+/*
+ * Position refinement TTM-ref (Sec. 3.3, Alg. 3), quaternion form (d' = 4,
+ * degree 2 or 4).  For each peak x^i (device int32 n_peaks x 3, z y x, inside
+ * the valid region, e.g. from ttm_find_peaks) the voxels of the sphere
+ * |x - x^i| <= r_s are visited, the peak first and then the other offsets in
+ * lexicographic (dz, dy, dx) order; voxels whose template window leaves the
+ * volume are skipped.  At each voxel x:
+ *   C(x)    = w(x) sum_p g(x + p - c) T_a(p)        (Eq. tcc, real-space sums)
+ *   R(x)    = the optimal rotation of C(x): the multistart SS-HOPM of
+ *             ttm_extract on S^3 (opts: n_starts quaternion starts, max_iter,
+ *             tol, newton_steps; mode, mlp and kappa are ignored)
+ *   c(x)    = w(x) sum_p g(x + p - c) t'(c + R(x)^T (p - c))  (Eq. lncc at R(x))
+ * and the voxel of the largest c is kept (a later voxel only on a strictly
+ * larger value, so the peak stays on ties).  Reading of the printed
+ * algorithm: its loop runs over the sphere of x^i, and the search starts at
+ * x^i with the peak's own rotation and LNCC.
+ *   g, w      device, nz x ny x nx (from ttm_prefilter / ttm_normalize_box)
+ *   T         device, K x L^3 tensor template (ttm_build_tensor, d' = 4)
+ *   tn        device, L^3 normalised template t' (ttm_build_tensor's tn_out)
+ *   r_s       0 <= r_s < 9 (the paper uses 3)
+ *   pos_out   device int32 n_peaks x 3: refined positions (z, y, x)
+ *   quat_out  device float n_peaks x 4: their rotations (w, x, y, z), w >= 0
+ *   lncc_out  device float n_peaks: their LNCC
+ *   quat_peak_out, lncc_peak_out  device, optional (NULL): the rotation and
+ *             LNCC at each unrefined peak (TTM without refinement)
+ *   ws        ttm_workspace_size(desc, TTM_OP_REFINE, 0, n_peaks, ceil(r_s), 1) bytes
+ * Errors: TTM_EUNSUPPORTED unless d' = 4 and degree 2 or 4; TTM_EINVAL for
+ * null pointers, n_peaks < 1 or r_s out of range.
+ */
+int ttm_refine(ttm_ctx* ctx, const ttm_desc* desc, const float* g, const float* w, int nz, int ny,
+               int nx, const float* T, const float* tn, const int32_t* peaks, int n_peaks, float r_s,
+               const ttm_extract_opts* opts, int32_t* pos_out, float* quat_out, float* lncc_out,
+               float* quat_peak_out, float* lncc_peak_out, void* ws, size_t ws_bytes,
+               void* stream);
 
 /*
  * Learned start network (a seed for the orientation search of Sec. 3.1):

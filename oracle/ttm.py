@@ -16,7 +16,8 @@ Everything here is the plain definition written out, in the paper's order:
                                                                   orient_multistart
 * Find Peaks: P highest scores at least two mask radii apart (Sec. 3.4)
                                                                -> find_peaks
-* rotation-sampled TM c(x, R) = w (f * t'_R) (Eq. lncc)        -> brute_force_tm
+* position refinement TTM-ref (Sec. 3.3, Alg. 3)              -> refine_positions
+* rotation-sampled TM c(x, R) = w (f * t'_R) (Eq. lncc)        -> brute_force_tm, lncc_at
 
 Readings of points the paper leaves open:
 * the image operator S reduces to h* on the image; the mask acts through t'
@@ -652,6 +653,73 @@ def find_peaks(score_map: np.ndarray, valid_lo, valid_hi, top_p: int, min_dist: 
         out_pos.append(p.astype(np.int64))
         out_val.append(vals[i])
     return np.array(out_pos, dtype=np.int64).reshape(-1, 3), np.array(out_val)
+
+
+# ----------------------------------------------------------------------------
+# position refinement (TTM-ref, Alg. 3)
+# ----------------------------------------------------------------------------
+
+
+def sphere_offsets(rs: float) -> np.ndarray:
+    """Integer offsets (dz, dy, dx) with |d| <= rs, the zero offset first, the
+    others in lexicographic (dz, dy, dx) order.  The order fixes which voxel
+    wins a tie in the refinement."""
+    R = int(math.floor(rs))
+    out = [(0, 0, 0)]
+    for dz in range(-R, R + 1):
+        for dy in range(-R, R + 1):
+            for dx in range(-R, R + 1):
+                if (dz, dy, dx) != (0, 0, 0) and dz * dz + dy * dy + dx * dx <= rs * rs:
+                    out.append((dz, dy, dx))
+    return np.array(out, dtype=np.int64)
+
+
+def lncc_at(g: np.ndarray, w: np.ndarray, tn: np.ndarray, x, q) -> float:
+    """c(x, R(q)) = w(x) (g * t'_R)(x) at one voxel (Eq. lncc): t' rotated by
+    R(q) (trilinear pull-back, zero outside the box) dotted with the template
+    window of g at x."""
+    L = tn.shape[0]
+    c = L // 2
+    z, y, x0 = (int(v) for v in x)
+    tq = rotate_template(tn, quat_to_matrix(np.asarray(q, dtype=np.float64)))
+    patch = np.asarray(g[z - c:z - c + L, y - c:y - c + L, x0 - c:x0 - c + L], dtype=np.float64)
+    return float(w[z, y, x0]) * float(np.sum(patch * tq))
+
+
+def refine_positions(g: np.ndarray, w: np.ndarray, tn: np.ndarray, field_of, orient_of,
+                     peaks: np.ndarray, rs: float = 3.0):
+    """TTM-ref (Sec. 3.3, Alg. 3): for each peak x^i, the rotation R_opt from
+    C(x^i) and its LNCC c = c(x^i, R_opt) start the search (x~ = x^i); then for
+    every other voxel x^j of the sphere |x^j - x^i| <= r_s (sphere_offsets
+    order) the rotation R from C(x^j) and c~ = c(x^j, R); x^j replaces the
+    current best when c~ > c.  Readings: the sphere of the loop is V_{x^i}
+    (the printed index is garbled); x~ starts at x^i; voxels whose template
+    window leaves the volume (outside the valid region) are skipped.
+
+    field_of(x) -> C(x) (K,) and orient_of(C) -> unit quaternion (4,) supply
+    the tensor field and the optimal rotation (d' = 4).  Returns per peak:
+    (refined position (3,), its quaternion, its LNCC, the peak's own
+    quaternion, the peak's LNCC)."""
+    L = tn.shape[0]
+    c = L // 2
+    lo = np.array([c, c, c])
+    hi = np.array([d - L + c for d in g.shape])
+    offs = sphere_offsets(rs)
+    out = []
+    for p in np.asarray(peaks, dtype=np.int64):
+        q0 = orient_of(field_of(p))
+        c0 = lncc_at(g, w, tn, p, q0)
+        best = (p.copy(), q0, c0)
+        for d in offs[1:]:
+            xj = p + d
+            if np.any(xj < lo) or np.any(xj > hi):
+                continue
+            qj = orient_of(field_of(xj))
+            cj = lncc_at(g, w, tn, xj, qj)
+            if cj > best[2]:
+                best = (xj, qj, cj)
+        out.append((best[0], best[1], best[2], q0, c0))
+    return out
 
 
 # ----------------------------------------------------------------------------

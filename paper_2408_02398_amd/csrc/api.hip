@@ -520,6 +520,9 @@ size_t ttm_workspace_size(const ttm_desc* desc, int op, int fft_n, int nz, int n
     case TTM_OP_MLP_TRAIN:
       if (nz < 1) return 0;
       return align256(mlp_train_workspace(nz));
+    case TTM_OP_REFINE:
+      if (nz < 1 || ny < 0 || ny > max_refine_radius()) return 0;
+      return refine_workspace(K, nz, (float)ny);
     default:
       return 0;
   }
@@ -922,6 +925,48 @@ int ttm_extract_noalloc(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int i
   }
   return ttm_extract(ctx, desc, C, in_dtype, box_size, opts, score, lambda, dir, out_lo, out_dims,
                      n_fallback, ctx->scratch, kNoAllocScratchBytes, stream);
+}
+
+int ttm_refine(ttm_ctx* ctx, const ttm_desc* desc, const float* g, const float* w, int nz, int ny,
+               int nx, const float* T, const float* tn, const int32_t* peaks, int n_peaks, float r_s,
+               const ttm_extract_opts* opts, int32_t* pos_out, float* quat_out, float* lncc_out,
+               float* quat_peak_out, float* lncc_peak_out, void* ws, size_t ws_bytes,
+               void* stream) {
+  if (!ctx || !valid_desc(desc)) return TTM_EINVAL;
+  if (desc->dprime != 4 || desc->degree < 2 || desc->degree > 4) {
+    set_error("ttm_refine: needs the quaternion form (d'=4) at degree 2 or 4");
+    return TTM_EUNSUPPORTED;
+  }
+  if (!g || !w || !T || !tn || !peaks || !opts || !pos_out || !quat_out || !lncc_out || !ws ||
+      n_peaks < 1 || nz < desc->L || ny < desc->L || nx < desc->L || !(r_s >= 0.0f) ||
+      r_s >= (float)(max_refine_radius() + 1)) {
+    set_error("ttm_refine: null pointer, no peaks, volume smaller than the template, or r_s "
+              "outside [0, %d]", max_refine_radius());
+    return TTM_EINVAL;
+  }
+  if (!opts->starts || opts->n_starts < 1 || opts->n_starts > 64 || opts->max_iter < 1 ||
+      opts->max_iter > (1 << 24) || !(opts->tol >= 0.0f) || opts->newton_steps < 0 ||
+      opts->newton_steps > 8) {
+    set_error("ttm_refine: orientation options invalid");
+    return TTM_EINVAL;
+  }
+  const int K = ncomp(desc->degree, 4);
+  const size_t need = refine_workspace(K, n_peaks, r_s);
+  if (ws_bytes < need) {
+    set_error("ttm_refine: workspace %zu < %zu", ws_bytes, need);
+    return TTM_EWORKSPACE;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  TTM_HIP(hipSetDevice(ctx->device));
+  ExtractArgs a{};
+  a.starts = opts->starts;
+  a.n_starts = opts->n_starts;
+  a.max_iter = opts->max_iter;
+  a.tol = opts->tol;
+  a.newton = opts->newton_steps;
+  a.counters = reinterpret_cast<unsigned long long*>(opts->work_counters);
+  return refine(desc->degree, K, g, w, nz, ny, nx, T, tn, desc->L, desc->mask_radius, peaks, n_peaks,
+                r_s, a, pos_out, quat_out, lncc_out, quat_peak_out, lncc_peak_out, ws, s);
 }
 
 size_t ttm_mlp_param_count(void) { return kMlpParams; }

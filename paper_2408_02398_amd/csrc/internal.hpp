@@ -117,6 +117,17 @@ int launch_extract(int degree, const ExtractArgs& a, hipStream_t s);
 size_t extract_workspace4(size_t plane);
 int launch_extract4(int degree, const ExtractArgs& a, hipStream_t s);
 
+// Position refinement TTM-ref (refine.hip): voxels of the sphere |d| <= r_s,
+// workspace of a refinement of n_peaks peaks, and the refinement itself
+// (opts supplies the multistart options of the d' = 4 orientation).
+int sphere_count(float rs);
+int max_refine_radius();
+size_t refine_workspace(int K, int n_peaks, float rs);
+int refine(int degree, int K, const float* g, const float* w, int nz, int ny, int nx, const float* T,
+           const float* tn, int L, float r, const int32_t* peaks, int n_peaks, float rs,
+           const ExtractArgs& opts, int32_t* pos_out, float* quat_out, float* lncc_out,
+           float* quat_peak, float* lncc_peak, void* ws, hipStream_t s);
+
 // Find Peaks (peaks.hip).
 size_t peaks_workspace(int64_t n_voxels);
 int find_peaks(const float* score, int nz, int ny, int nx, const int32_t lo[3],

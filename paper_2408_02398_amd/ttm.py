@@ -234,6 +234,36 @@ def extract(ctx: Context, desc: Desc, Cf: torch.Tensor, *, score=None, lam=None,
     return score, lam, direction
 
 
+def refine(ctx: Context, desc: Desc, g: torch.Tensor, w: torch.Tensor, T: torch.Tensor,
+           tn: torch.Tensor, peaks: torch.Tensor, starts: torch.Tensor, r_s: float = 3.0,
+           max_iter: int = 500, tol: float = 1e-5, newton: int = 2,
+           ws: torch.Tensor | None = None) -> dict:
+    """TTM-ref (Alg. 3) of the peaks (device int32 P x 3), quaternion form:
+    refined positions, their rotations and LNCC, and the unrefined peak's own
+    rotation and LNCC (TTM without refinement)."""
+    _need_cuda(g, w, T, tn, peaks, starts)
+    nz, ny, nx = g.shape
+    P = peaks.shape[0]
+    dev = g.device
+    out = {"pos": torch.empty((P, 3), dtype=torch.int32, device=dev),
+           "quat": torch.empty((P, 4), dtype=torch.float32, device=dev),
+           "lncc": torch.empty(P, dtype=torch.float32, device=dev),
+           "quat_peak": torch.empty((P, 4), dtype=torch.float32, device=dev),
+           "lncc_peak": torch.empty(P, dtype=torch.float32, device=dev)}
+    if ws is None:
+        ws = _ws(desc, L.TTM_OP_REFINE, 0, (P, int(math.ceil(r_s)), 1), device=dev)
+    opts = ExtractOpts()
+    opts.mode = L.TTM_ORIENT
+    opts.n_starts = starts.shape[0]
+    opts.starts = starts.data_ptr()
+    opts.max_iter, opts.tol, opts.newton_steps = max_iter, tol, newton
+    call("ttm_refine", ctx.h, C.byref(desc), _ptr(g), _ptr(w), nz, ny, nx, _ptr(T), _ptr(tn),
+         _ptr(peaks), P, float(r_s), C.byref(opts), _ptr(out["pos"]), _ptr(out["quat"]),
+         _ptr(out["lncc"]), _ptr(out["quat_peak"]), _ptr(out["lncc_peak"]), _ptr(ws), ws.numel(),
+         _stream())
+    return out
+
+
 class MLP:
     """Learned start: FP32 master parameters, Adam moments and the packed BF16 copy."""
 

@@ -696,3 +696,72 @@ def test_reference_maxima_quaternion_agree_with_multistart():
         assert lr >= lam - 1e-9
         if lr - lam < 1e-9:
             assert ttm.quat_angle_deg(u, ur) < 1e-3
+
+
+# ---------------------------------------------------------------- TTM-ref (Alg. 3)
+def _planted_copy():
+    w = synth.make_tomogram("ref", (36, 36, 36), L=12, n_blobs=3, n_copies=1, min_sep=12,
+                            mask_radius=5.0, degree=4, seed=5, snr=None, wedge=False,
+                            copy_amplitude=50.0)
+    g = ttm.prefilter_volume(w.volume)
+    wm = ttm.local_normalization(g, ttm.ball_mask(12, 5.0))
+    tn = ttm.normalize_template(w.template, 5.0)
+    return w, g, wm, tn
+
+
+def test_sphere_offsets():
+    o = ttm.sphere_offsets(3.0)
+    assert len(o) == 123 and np.array_equal(o[0], [0, 0, 0])
+    assert np.all(np.sum(o ** 2, axis=1) <= 9)
+    rest = [tuple(v) for v in o[1:]]
+    assert rest == sorted(rest) and len(set(rest)) == 122
+
+
+def test_lncc_at_equals_rotation_sampled_tm():
+    """Eq. lncc at one voxel (a window of g and t' rotated by trilinear
+    pull-back) equals the whole-volume rotation-sampled TM of the oracle."""
+    w, g, wm, tn = _planted_copy()
+    rng = np.random.default_rng(61)
+    qs = synth.random_quaternions(rng, 3)
+    c = 6
+    full = ttm.brute_force_tm(g, wm, tn, qs)
+    for k, q in enumerate(qs):
+        for _ in range(4):
+            x = rng.integers(c, 36 - 12 + c + 1, 3)
+            assert ttm.lncc_at(g, wm, tn, x, q) == pytest.approx(full[k, x[0] - c, x[1] - c, x[2] - c],
+                                                                 rel=1e-12, abs=1e-14)
+
+
+def _quat_of(R):
+    """Unit quaternion of a rotation matrix (largest-component formula)."""
+    qw = np.sqrt(max(0.0, 1 + np.trace(R))) / 2
+    qx = np.copysign(np.sqrt(max(0.0, 1 + R[0, 0] - R[1, 1] - R[2, 2])) / 2, R[2, 1] - R[1, 2])
+    qy = np.copysign(np.sqrt(max(0.0, 1 - R[0, 0] + R[1, 1] - R[2, 2])) / 2, R[0, 2] - R[2, 0])
+    qz = np.copysign(np.sqrt(max(0.0, 1 - R[0, 0] - R[1, 1] + R[2, 2])) / 2, R[1, 0] - R[0, 1])
+    return np.array([qw, qx, qy, qz])
+
+
+def test_refine_returns_the_planted_centre_with_the_exact_rotation():
+    """Alg. 3 with the planted copy's own rotation at every voxel: the LNCC at
+    that rotation peaks at the planted centre, so a peak detected a few voxels
+    off (inside r_s) is moved onto it; the peak's own values are reported too."""
+    w, g, wm, tn = _planted_copy()
+    qt = _quat_of(w.rotations[0])
+    assert np.allclose(rot.quat_to_matrix(qt), w.rotations[0], atol=1e-12)
+    ctr = w.centres[0]
+    peaks = np.array([ctr + np.array([1, -1, 1]), ctr + np.array([0, 2, -1])])
+    res = ttm.refine_positions(g, wm, tn, lambda x: None, lambda C: qt, peaks, 3.0)
+    for (pos, q, c, q0, c0), p in zip(res, peaks):
+        assert np.array_equal(pos, ctr)
+        assert c == pytest.approx(ttm.lncc_at(g, wm, tn, ctr, qt), rel=1e-12)
+        assert c0 == pytest.approx(ttm.lncc_at(g, wm, tn, p, qt), rel=1e-12) and c > c0 > 0
+
+
+def test_refine_keeps_the_peak_on_ties():
+    """Only a strictly larger LNCC moves the position (x~ starts at x^i): with
+    w = 0 every LNCC is 0 and the peak stays."""
+    w, g, wm, tn = _planted_copy()
+    peaks = np.array([w.centres[0] + np.array([1, 1, 0])])
+    res = ttm.refine_positions(g, np.zeros_like(wm), tn, lambda x: None,
+                               lambda C: np.array([1.0, 0, 0, 0]), peaks, 3.0)
+    assert np.array_equal(res[0][0], peaks[0]) and res[0][2] == 0.0
