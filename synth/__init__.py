@@ -263,6 +263,7 @@ class Workload:
     centres: np.ndarray                # (N, 3) planted centres (z, y, x)
     rotations: np.ndarray              # (N, 3, 3) planted rotations
     params: dict = field(default_factory=dict)
+    quaternions: np.ndarray | None = None   # (N, 4) planted rotations (w, x, y, z), w >= 0
 
 
 def start_vectors(seed: int = 16, count: int = 16, dim: int = 3) -> np.ndarray:
@@ -313,6 +314,36 @@ def make_tomogram(name: str, shape, L: int, n_blobs: int, n_copies: int, min_sep
                     params=dict(shape=tuple(shape), L=L, n_blobs=n_blobs, n_copies=n_copies,
                                 min_sep=min_sep, seed=seed, snr=snr, wedge=wedge,
                                 noise_sd=noise_sd))
+
+
+def grid_tomogram(name: str, grid: int, spacing: int, L: int, n_blobs: int, mask_radius: float,
+                  degree: int, seed: int, snr: float, template_seed: int,
+                  margin: int | None = None) -> Workload:
+    """A grid x grid x grid lattice of rotated template copies in Gaussian noise,
+    as in the paper's synthetic tomograms (Sec. 4.1: a 5 x 5 x 5 grid of 125
+    randomly rotated copies; noise at a stated SNR).  Copy rotations are
+    Haar-uniform quaternions, kept in ``quaternions``; the noise variance is the
+    template's variance over its mask divided by ``snr``.  No missing wedge."""
+    rng = np.random.default_rng(seed)
+    tmpl = blob_template(np.random.default_rng(template_seed), L, n_blobs)
+    tvol = tmpl.volume()
+    m0 = L // 2 + 2 if margin is None else margin
+    edge = 2 * m0 + (grid - 1) * spacing + 1
+    shape = (edge, edge, edge)
+    ax = m0 + spacing * np.arange(grid)
+    zz, yy, xx = np.meshgrid(ax, ax, ax, indexing="ij")
+    centres = np.stack([zz.ravel(), yy.ravel(), xx.ravel()], 1).astype(np.int64)
+    quats = random_quaternions(rng, len(centres))
+    rots = _quat_to_rot(quats)
+    sig = render_copies(shape, tmpl, centres, rots)
+    noise_sd = math.sqrt(float(np.var(tvol[ball(L, mask_radius)])) / snr)
+    vol = sig + (noise_sd * rng.standard_normal(shape, dtype=np.float32)).astype(np.float32)
+    return Workload(name=name, volume=np.ascontiguousarray(vol, dtype=np.float32),
+                    template=tvol.astype(np.float32), template_model=tmpl,
+                    mask_radius=mask_radius, degree=degree, centres=centres, rotations=rots,
+                    params=dict(shape=shape, L=L, n_blobs=n_blobs, grid=grid, spacing=spacing,
+                                seed=seed, snr=snr, noise_sd=noise_sd, template_seed=template_seed),
+                    quaternions=quats)
 
 
 # Workload recipes.  The names carry the sizes; "r" is the mask radius.
