@@ -93,6 +93,8 @@ def main():
                     help="both = plain, learned (screened fallback) and learned without screening")
     ap.add_argument("--train-steps", type=int, default=120000)
     ap.add_argument("--train-volumes", type=int, default=10)
+    ap.add_argument("--also-fft", type=int, default=256,
+                    help="also time the learned pass on this FFT tile edge (0: no)")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run the tile correlations on the same stream as the extractions")
     ap.add_argument("--precision-report", action="store_true",
@@ -294,6 +296,31 @@ def main():
         roofline, corr_roof = corr_roof, ext_roof
     wall = R["wall"]
 
+    # ground truth at the planted copies (reported, not gated): recall and
+    # precision of the copies among the top-P peaks (a peak within r of a
+    # centre), position error, and the axis error against R_true a (a = z)
+    gt = ground_truth(wl, R["pk"], R["eng"].dir, r)
+    tile256 = None
+    if args.also_fft and args.also_fft != fft_n and main_mode.startswith("learned"):
+        spec2 = ttm.template_spectra(ctx, d, Tg, args.also_fft)
+        eng2 = ttm.Engine(ctx, d, spec2, args.also_fft, vol.shape, starts, field_dtype=field_dtype,
+                          mlp=net, kappa=kappa)
+        eng2.run(vol, top_p=top_p)
+        torch.cuda.synchronize()
+        a2, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a2.record(stream)
+        for i in range(args.steps):
+            r2 = eng2.run(vol, top_p=top_p)
+        b2.record(stream)
+        torch.cuda.synchronize()
+        ms2 = a2.elapsed_time(b2) / args.steps
+        tile256 = {"fft_tile": args.also_fft, "tiles": len(eng2.boxes), "ms_per_step": ms2,
+                   "voxels_per_s": nvox / (ms2 / 1e3),
+                   "peaks_identical": bool(torch.equal(r2.peaks, R["pk"]))}
+        log(f"[bench] learned pass on {args.also_fft}^3 tiles: {ms2:.1f} ms")
+        del eng2, spec2, r2
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, Q.cpu().numpy().astype(np.float64), n, L, r, args.cpu_sample)
@@ -331,9 +358,42 @@ def main():
         "dominant_stage": dominant,
         ("roofline_extract" if dominant == "correlate" else "roofline_correlate"): corr_roof,
         "cpu_baseline": cpu,
+        "ground_truth": gt,
+        "other_tile": tile256,
         "wall_s": wall,
     }
     print(json.dumps(clean(out)), flush=True)
+
+
+def ground_truth(wl, peaks, direction, r):
+    """Detected copies among the peaks (a peak within r of a planted centre),
+    position errors, and the axis error arccos|u . R_true a| (a = z axis) at
+    the detected copies' peaks (Sec. 4.1 metrics; reported, not gated)."""
+    pk = peaks.cpu().numpy().astype(np.float64)
+    cen = wl.centres.astype(np.float64)
+    if len(pk) == 0 or len(cen) == 0:
+        return None
+    found, used, pos_err, ang = 0, set(), [], []
+    dmap = direction
+    for j, c in enumerate(cen):
+        dist = np.linalg.norm(pk - c, axis=1)
+        i = int(np.argmin(dist))
+        if dist[i] > r:
+            continue
+        found += 1
+        used.add(i)
+        pos_err.append(float(dist[i]))
+        z, y, x = (int(v) for v in pk[i])
+        u = dmap[z, y, x].cpu().numpy().astype(np.float64)
+        a = wl.rotations[j][:, 2]
+        cosv = abs(float(u @ a)) / max(np.linalg.norm(u), 1e-30)
+        ang.append(float(np.degrees(np.arccos(min(1.0, cosv)))))
+    pe, an = np.array(pos_err), np.array(ang)
+    return {"copies": int(len(cen)), "peaks": int(len(pk)), "recall": found / len(cen),
+            "precision": len(used) / len(pk),
+            "position_err_vox": {"mean": float(pe.mean()), "max": float(pe.max())} if found else None,
+            "axis_err_deg": {"mean": float(an.mean()), "median": float(np.median(an)),
+                             "max": float(an.max())} if found else None}
 
 
 def accuracy_gate(plain, learned, lo, hi, top_p, ttm, torch):

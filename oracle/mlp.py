@@ -165,10 +165,10 @@ def orient_learned(Cv: np.ndarray, n: int, p: dict, starts: np.ndarray, kappa: f
        |delta lambda| <= tol or max_iter updates, then ``polish`` Newton steps
        (ttm.newton_polish); "converged" is the outcome of the search that ran
        last;
-    3. the end point is certified when the tangent Hessian there is negative
-       definite and the next Newton step is at most ``certify`` long (a slow
-       SS-HOPM run on a flat, curved ridge can meet its stopping rule far from
-       the maximum);
+    3. the end point is certified near a local maximum (ttm.certify: the
+       next Newton step is at most ``certify`` long, after at most four
+       guarded Newton steps; a slow SS-HOPM run on a flat, curved ridge can
+       meet its stopping rule far from the maximum);
     4. the learned answer is the converged maximum of the basin the search
        ended in (ttm.converge from its end point);
     5. fallback when the search did not converge, the end point is not
@@ -181,7 +181,7 @@ def orient_learned(Cv: np.ndarray, n: int, p: dict, starts: np.ndarray, kappa: f
     with the learned answer (lam_learned, u_learned), how far each fallback
     test was from flipping (beat_gap = best fixed-start value minus the
     learned lambda, scaled by ||C||_F; kappa_gap = lambda / ||C||_F - kappa;
-    cert_step = the Newton step length at the end point), whether the search
+    cert_step = the last Newton step length the certification measured), whether the search
     converged, and after a fallback the multistart's per-start lambdas and
     directions.  ``u0`` (a unit vector) replaces the network's direction, to
     probe how the answer depends on the start.
@@ -206,13 +206,13 @@ def orient_learned(Cv: np.ndarray, n: int, p: dict, starts: np.ndarray, kappa: f
     if not conv:
         lam, u, _, conv = ttm.sshopm(Cu, n, u0, alpha, tol, max_iter)
         u = ttm.newton_polish(Cu, n, u, polish)
-    step = ttm.newton_step_length(Cu, n, u)
+    u, certified, step = ttm.certify(Cu, n, u, certify)
     lam, u, _ = ttm.converge(Cu, n, u, alpha)
     fs = max(sym.inner_power(Cu, s / np.linalg.norm(s), n) for s in starts)
     beaten = fs > lam
     info = {"lam_learned": cn * lam, "u_learned": ttm.canonical_sign(u), "beat_gap": cn * (fs - lam),
             "kappa_gap": lam - kappa, "cert_step": step, "converged": conv, "lams": None, "us": None}
-    if conv and step <= certify and not forced and lam >= kappa and not beaten:
+    if conv and certified and not forced and lam >= kappa and not beaten:
         out = (cn * lam, ttm.canonical_sign(u), False)
         return out + (info,) if detail else out
     lam_p, u_p, lams, us, _ = ttm.orient_multistart(Cv, n, starts)

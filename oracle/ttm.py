@@ -474,6 +474,51 @@ def newton_step_length(Cu: np.ndarray, n: int, u: np.ndarray) -> float:
     return np.inf if d is None else float(np.linalg.norm(d))
 
 
+def certify(Cu: np.ndarray, n: int, u: np.ndarray, delta: float = 1e-2, steps: int = 4,
+            drop: float = 1e-6, halvings: int = 2, grad_tol: float = 3e-5,
+            curv_tol: float = 1e-3):
+    """Certify u as near a local maximum (the learned start's acceptance test,
+    part of that method's definition): the tangent gradient |g - lambda u| is
+    at most grad_tol and the tangent Hessian's largest eigenvalue at most
+    curv_tol (a critical point to rounding level that is not a minimum or a
+    clear saddle), or the tangent Hessian is negative definite and the Newton
+    step at u is at most delta long.  Otherwise a Newton step is taken
+    (halved, at most ``halvings`` times, while lambda falls by more than
+    ``drop``) and the test repeats, at most ``steps`` times; where the tangent
+    Hessian is not negative definite, or a halved step still falls, u is not
+    certified.  Returns (u, certified, the last step length measured; 0 when
+    certified by the gradient)."""
+    u = np.asarray(u, dtype=np.float64)
+    u = u / np.linalg.norm(u)
+    length = np.inf
+    for k in range(steps + 1):
+        g = sym.contract_n_minus_1(Cu, u, n)
+        lam = float(g @ u)
+        E = tangent_basis(u)
+        amax = float(np.linalg.eigvalsh(tangent_hessian(Cu, n, u, lam, E)).max())
+        if np.linalg.norm(g - lam * u) <= grad_tol and amax <= curv_tol:
+            return u, True, 0.0
+        d = newton_direction(Cu, n, u, g, lam)
+        if d is None:
+            return u, False, np.inf
+        length = float(np.linalg.norm(d))
+        if length <= delta:
+            return u, True, length
+        if k == steps:
+            break
+        t = 1.0
+        for _h in range(halvings + 1):
+            un = u + t * d
+            un = un / np.linalg.norm(un)
+            if float(sym.contract_n_minus_1(Cu, un, n) @ un) >= lam - drop:
+                break
+            t *= 0.5
+        else:
+            return u, False, length
+        u = un
+    return u, False, length
+
+
 def orient_multistart(Cv: np.ndarray, n: int, starts: np.ndarray, tol: float = 1e-13,
                       max_iter: int = 10000, shift: float | None = None):
     """Dominant eigenpair of one voxel's tensor from fixed starts (Sec. 3.1).

@@ -173,15 +173,15 @@ __device__ __forceinline__ void contract2(const float (&c)[ncomp3(N)], float x, 
   }
 }
 
-// Riemannian Newton direction for max <C, u^n> on the unit sphere at u with
-// (g, lambda) = (C u^{n-1}, <C, u^n>): tangent basis e1 = a x u/|a x u| (a =
-// axis of the smallest |u_i|), e2 = u x e1; the tangent Hessian
-// (n-1) E^T H E - lambda I (H = C u^{n-2}) must be negative definite, else
-// there is no step (false).  Otherwise d = E eta with eta = -Hess^{-1} E^T g.
+// Tangent model of max <C, u^n> on the unit sphere at u with (g, lambda) =
+// (C u^{n-1}, <C, u^n>): tangent basis e1 = a x u/|a x u| (a = axis of the
+// smallest |u_i|), e2 = u x e1 (e = {e1, e2}); the tangent Hessian
+// A = (n-1) E^T H E - lambda I (H = C u^{n-2}) and the tangent gradient t = E^T g.
 template <int N>
-__device__ __forceinline__ bool newton_dir(const float (&c)[ncomp3(N)], float ux, float uy,
-                                           float uz, float g0, float g1, float g2, float lam,
-                                           float& dx, float& dy, float& dz) {
+__device__ __forceinline__ void tangent_model(const float (&c)[ncomp3(N)], float ux, float uy,
+                                              float uz, float g0, float g1, float g2, float lam,
+                                              float (&e)[6], float& a00, float& a01, float& a11,
+                                              float& t0, float& t1) {
   const float fx = fabsf(ux), fy = fabsf(uy), fz = fabsf(uz);
   float e1x, e1y, e1z;
   if (fx <= fy && fx <= fz) {        // a = e_x: a x u = (0, -uz, uy)
@@ -203,19 +203,38 @@ __device__ __forceinline__ bool newton_dir(const float (&c)[ncomp3(N)], float ux
   const float hy2 = h[1] * e2x + h[3] * e2y + h[4] * e2z;
   const float hz2 = h[2] * e2x + h[4] * e2y + h[5] * e2z;
   constexpr float nm1 = (float)(N - 1);
-  const float a00 = nm1 * (e1x * hx1 + e1y * hy1 + e1z * hz1) - lam;
-  const float a01 = nm1 * (e1x * hx2 + e1y * hy2 + e1z * hz2);
-  const float a11 = nm1 * (e2x * hx2 + e2y * hy2 + e2z * hz2) - lam;
+  a00 = nm1 * (e1x * hx1 + e1y * hy1 + e1z * hz1) - lam;
+  a01 = nm1 * (e1x * hx2 + e1y * hy2 + e1z * hz2);
+  a11 = nm1 * (e2x * hx2 + e2y * hy2 + e2z * hz2) - lam;
+  t0 = e1x * g0 + e1y * g1 + e1z * g2;
+  t1 = e2x * g0 + e2y * g1 + e2z * g2;
+  e[0] = e1x; e[1] = e1y; e[2] = e1z; e[3] = e2x; e[4] = e2y; e[5] = e2z;
+}
+
+// Newton direction of a tangent model: d = E eta with eta = -A^{-1} t, where A
+// must be negative definite (false otherwise: no step).
+__device__ __forceinline__ bool tangent_step(const float (&e)[6], float a00, float a01, float a11,
+                                             float t0, float t1, float& dx, float& dy, float& dz) {
   const float det = a00 * a11 - a01 * a01;
   if (!(det > 0.0f && a00 + a11 < 0.0f)) return false;
-  const float t0 = e1x * g0 + e1y * g1 + e1z * g2, t1 = e2x * g0 + e2y * g1 + e2z * g2;
   const float inv = 1.0f / det;
   const float eta0 = -(a11 * t0 - a01 * t1) * inv;
   const float eta1 = -(a00 * t1 - a01 * t0) * inv;
-  dx = eta0 * e1x + eta1 * e2x;
-  dy = eta0 * e1y + eta1 * e2y;
-  dz = eta0 * e1z + eta1 * e2z;
+  dx = eta0 * e[0] + eta1 * e[3];
+  dy = eta0 * e[1] + eta1 * e[4];
+  dz = eta0 * e[2] + eta1 * e[5];
   return true;
+}
+
+// Riemannian Newton direction for max <C, u^n> on the unit sphere at u (false
+// where the tangent Hessian is not negative definite: no step).
+template <int N>
+__device__ __forceinline__ bool newton_dir(const float (&c)[ncomp3(N)], float ux, float uy,
+                                           float uz, float g0, float g1, float g2, float lam,
+                                           float& dx, float& dy, float& dz) {
+  float e[6], a00, a01, a11, t0, t1;
+  tangent_model<N>(c, ux, uy, uz, g0, g1, g2, lam, e, a00, a01, a11, t0, t1);
+  return tangent_step(e, a00, a01, a11, t0, t1, dx, dy, dz);
 }
 
 // v = (u + t d) / |u + t d| and (q, lambda_v) = (C v^{n-1}, <C, v^n>).
@@ -791,13 +810,21 @@ __global__ __launch_bounds__(256) void k_reduce(ExtractArgs a, Items it, int nsb
 
 // Polish, screen and write a learned-start answer; mark the voxel for the
 // multistart search (status 2) when the run did not converge, the answer is
-// not certified near a local maximum (the tangent Hessian there is not
-// negative definite, or the next Newton step is longer than kCertify: a slow
-// SS-HOPM run on a flat, curved ridge can meet the stopping rule far from its
-// maximum), lambda / ||C||_F < kappa, the network gave no direction, or some
-// fixed start s already has <C, s^n> above lambda (SS-HOPM never lowers
-// lambda, so the multistart answer is then higher).
+// not certified near a local maximum, lambda / ||C||_F < kappa, the network
+// gave no direction, or some fixed start s already has <C, s^n> above lambda
+// (SS-HOPM never lowers lambda, so the multistart answer is then higher).
+// Certified: the tangent gradient |g - lambda u| is at most kCertifyGrad and
+// the tangent Hessian's largest eigenvalue at most kCertifyCurv (a critical
+// point to rounding level that is not a minimum or a clear saddle: degenerate
+// maxima pass), or the tangent Hessian is negative definite and the next
+// Newton step is at most kCertify long (a slow SS-HOPM run on a flat, curved
+// ridge can meet its stopping rule far from the maximum); otherwise up to
+// kCertifySteps Newton steps are taken (halved while lambda falls, as in the
+// Newton search) and the test repeats.
 constexpr float kCertify = 1e-2f;
+constexpr float kCertifyGrad = 3e-5f;
+constexpr float kCertifyCurv = 1e-3f;
+constexpr int kCertifySteps = 4;
 
 template <int N>
 __device__ __forceinline__ unsigned long long learned_finish(
@@ -806,10 +833,38 @@ __device__ __forceinline__ unsigned long long learned_finish(
     bool conv, bool forced, int polish, bool& fell) {
   constexpr int K = ncomp3(N);
   unsigned long long taken = newton_polish<N>(c, ux, uy, uz, g0, g1, g2, lam, polish);
-  float dx, dy, dz;
-  const bool certified = newton_dir<N>(c, ux, uy, uz, g0, g1, g2, lam, dx, dy, dz) &&
-                         dx * dx + dy * dy + dz * dz <= kCertify * kCertify;
-  taken += 1;
+  bool certified = false;
+  for (int k = 0; k <= kCertifySteps; ++k) {
+    float e[6], a00, a01, a11, t0, t1;
+    ++taken;
+    tangent_model<N>(c, ux, uy, uz, g0, g1, g2, lam, e, a00, a01, a11, t0, t1);
+    const float amax = 0.5f * (a00 + a11) + 0.5f * sqrtf((a00 - a11) * (a00 - a11) + 4.0f * a01 * a01);
+    if (t0 * t0 + t1 * t1 <= kCertifyGrad * kCertifyGrad && amax <= kCertifyCurv) {
+      certified = true;
+      break;
+    }
+    float dx, dy, dz;
+    if (!tangent_step(e, a00, a01, a11, t0, t1, dx, dy, dz)) break;
+    if (dx * dx + dy * dy + dz * dz <= kCertify * kCertify) {
+      certified = true;
+      break;
+    }
+    if (k == kCertifySteps) break;
+    float vx, vy, vz, q0, q1, q2, lam_new, t = 1.0f;
+    bool up = false;
+    for (int h = 0; h <= kHalvings; ++h) {
+      newton_move<N>(c, ux, uy, uz, dx, dy, dz, t, vx, vy, vz, q0, q1, q2, lam_new);
+      if (lam_new >= lam - 1e-6f) {
+        up = true;
+        break;
+      }
+      t *= 0.5f;
+    }
+    if (!up) break;
+    ux = vx; uy = vy; uz = vz;
+    g0 = q0; g1 = q1; g2 = q2;
+    lam = lam_new;
+  }
   bool beaten = false;
   if (a.screen) {
     for (int s = 0; s < a.n_starts; ++s) {

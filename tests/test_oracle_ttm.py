@@ -765,3 +765,25 @@ def test_refine_keeps_the_peak_on_ties():
     res = ttm.refine_positions(g, np.zeros_like(wm), tn, lambda x: None,
                                lambda C: np.array([1.0, 0, 0, 0]), peaks, 3.0)
     assert np.array_equal(res[0][0], peaks[0]) and res[0][2] == 0.0
+
+
+def test_certify_accepts_near_maxima_and_refuses_others():
+    """The learned start's acceptance test: at a maximum the Newton step is
+    zero; 10 degrees from a rank-one maximum a few Newton steps bring it within
+    the step bound; at a minimum of <C, u^n> (the tangent Hessian is positive
+    definite) nothing is certified."""
+    rng = np.random.default_rng(71)
+    n = 6
+    for _ in range(4):
+        v = rng.standard_normal(3)
+        v /= np.linalg.norm(v)
+        C = sym.monomials(v, n)
+        u, ok, step = ttm.certify(C, n, v)
+        assert ok and step < 1e-12 and np.allclose(u, v)
+        w = np.cross(v, rng.standard_normal(3))
+        u0 = np.cos(np.radians(10.0)) * v + np.sin(np.radians(10.0)) * w / np.linalg.norm(w)
+        u, ok, step = ttm.certify(C, n, u0)
+        assert ok and step <= 1e-2 and ttm.angle_deg(u, v) < 1.0
+        # -C has its minimum (for <C, u^n>: the maximum of -C's value) at v
+        u, ok, step = ttm.certify(-C, n, v)
+        assert not ok
