@@ -8,7 +8,7 @@ normalisation, tensor construction, correlation, extraction, peak picking):
 both the CPU oracle (through the tests) and the GPU path consume what it
 produces, and neither imports the other.
 
-Workload recipes follow the paper's synthetic experiments in spirit (Sec. 5.1:
+Workload recipes follow the paper's synthetic experiments in spirit (Sec. 4.1:
 randomly rotated copies of one template in a tomogram, additive Gaussian noise
 at a stated SNR) with Gaussian-blob templates standing in for the PDB-derived
 densities and the EMPIAR-10988 tomogram, which are not available.

@@ -413,7 +413,7 @@ def test_planted_copies_recovered_at_high_snr():
     smap[lo:hi + 1, lo:hi + 1, lo:hi + 1] = s
     pk, _ = ttm.find_peaks(smap, (lo,) * 3, (hi,) * 3, len(w.centres), 14.0)
     # every planted copy has a peak within the mask radius (the Frobenius score is
-    # a position proxy that may shift by a few voxels, Sec. 5.1, Table 1)
+    # a position proxy that may shift by a few voxels, Sec. 4.1, Table 1)
     for c in w.centres:
         d = np.min(np.linalg.norm(pk - c, axis=1))
         assert d <= 7.0
