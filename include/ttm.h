@@ -367,6 +367,40 @@ int ttm_find_peaks_async(ttm_ctx* ctx, const float* score, int nz, int ny, int n
                          float min_dist, int32_t* peaks_out, float* vals_out, int32_t* n_found,
                          void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * Find Peaks over many score maps in one launch (Sec. 3.4, the rule and
+ * result of ttm_find_peaks for each map), for batches of subtomograms that
+ * each want a few peaks.  Each step keeps the first voxel in visiting order
+ * (descending score, ties by ascending linear index) at least min_dist from
+ * the peaks kept so far, i.e. the smallest key ~score_bits << 32 | index
+ * among the voxels not yet excluded; no host synchronisation (graph-capture
+ * safe).  Work per map is about top_p times the voxels of an exclusion ball,
+ * so it suits small top_p (ttm_find_peaks serves thousands of peaks better).
+ *   items     device array of n_items ttm_peak_item (the table itself lives
+ *             on the device so a captured graph can replay it)
+ *   max_valid host int32[3]: the largest valid-box extent (z, y, x) of any item
+ * Per item (the caller's responsibility; an item that breaks these gets
+ * *n_found = -1 and is skipped): valid box inside the map, map under 2^32
+ * voxels, 1 <= top_p <= 4096, scratch of ttm_peaks_batch_scratch_bytes(
+ * valid_lo, valid_hi) bytes (256-byte aligned, overwritten).
+ */
+typedef struct {
+  const float* score;       /* device map, dims[0] x dims[1] x dims[2]          */
+  int32_t* peaks;           /* device int32 top_p x 3 (z, y, x)                 */
+  float* vals;              /* device float top_p: the scores of the peaks      */
+  int32_t* n_found;         /* device int32: the number of peaks written        */
+  void* scratch;            /* device scratch of this item                      */
+  int32_t dims[3];
+  int32_t valid_lo[3];      /* inclusive valid box (z, y, x)                    */
+  int32_t valid_hi[3];
+  int32_t top_p;
+  float min_dist;
+} ttm_peak_item;
+
+size_t ttm_peaks_batch_scratch_bytes(const int32_t valid_lo[3], const int32_t valid_hi[3]);
+int ttm_find_peaks_batch(ttm_ctx* ctx, const ttm_peak_item* items, int n_items,
+                         const int32_t max_valid[3], void* stream);
+
 /* Stand-alone 3D FFT of an N^3 real array to its half spectrum and back
  * (the transforms used inside ttm_correlate), for tests and benchmarks.
  * Forward: spec = F(x) unnormalised; inverse: x = F^{-1}(spec) * scale.

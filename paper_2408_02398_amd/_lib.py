@@ -34,6 +34,13 @@ class ExtractOpts(C.Structure):
                 ("tol", C.c_float), ("newton_steps", C.c_int32), ("work_counters", C.c_void_p)]
 
 
+class PeakItem(C.Structure):
+    _fields_ = [("score", C.c_void_p), ("peaks", C.c_void_p), ("vals", C.c_void_p),
+                ("n_found", C.c_void_p), ("scratch", C.c_void_p), ("dims", C.c_int32 * 3),
+                ("valid_lo", C.c_int32 * 3), ("valid_hi", C.c_int32 * 3), ("top_p", C.c_int32),
+                ("min_dist", C.c_float)]
+
+
 I32x3 = C.c_int32 * 3
 vp = C.c_void_p
 DP = C.POINTER(Desc)
@@ -80,6 +87,8 @@ SIGNATURES = {
     "ttm_find_peaks_async": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int32),
                                        C.POINTER(C.c_int32), C.c_int, C.c_float, vp, vp, vp, vp,
                                        C.c_size_t, vp]),
+    "ttm_peaks_batch_scratch_bytes": (C.c_size_t, [C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "ttm_find_peaks_batch": (C.c_int, [vp, vp, C.c_int, C.POINTER(C.c_int32), vp]),
     "ttm_fft3d_r2c": (C.c_int, [vp, vp, C.c_int, vp, vp]),
     "ttm_fft3d_c2r": (C.c_int, [vp, vp, C.c_int, C.c_float, vp, vp]),
 }

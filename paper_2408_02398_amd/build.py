@@ -25,7 +25,7 @@ FLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
-SOURCES = ["fft.hip", "extract.hip", "extract4.hip", "refine.hip", "peaks.hip", "mlp.hip", "api.hip"]
+SOURCES = ["fft.hip", "extract.hip", "extract4.hip", "refine.hip", "peaks.hip", "peaks_batch.hip", "mlp.hip", "api.hip"]
 
 
 def _compile(src: str, verbose: bool) -> str:

@@ -2,6 +2,7 @@
 // that are not FFT passes (prefilter and its FP64 statistics, the local
 // variance combine, template normalisation, the tensor template of Alg. 1).
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -428,6 +429,11 @@ size_t prefilter_blocks(int nz, int ny, int nx) {
 
 }  // namespace
 }  // namespace ttm
+
+namespace ttm {
+int find_peaks_batch(const ttm_peak_item* items, int n_items, const int32_t max_valid[3],
+                     hipStream_t s);
+}
 
 using namespace ttm;
 
@@ -1057,6 +1063,32 @@ int ttm_find_peaks_async(ttm_ctx* ctx, const float* score, int nz, int ny, int n
   TTM_HIP(hipSetDevice(ctx->device));
   return find_peaks_async(score, nz, ny, nx, valid_lo, valid_hi, top_p, min_dist, peaks_out,
                           vals_out, n_found, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+static_assert(sizeof(ttm_peak_item) == 88 && offsetof(ttm_peak_item, dims) == 40,
+              "ttm_peak_item layout is part of the ABI");
+
+size_t ttm_peaks_batch_scratch_bytes(const int32_t valid_lo[3], const int32_t valid_hi[3]) {
+  if (!valid_lo || !valid_hi) return 0;
+  for (int a = 0; a < 3; ++a)
+    if (valid_lo[a] < 0 || valid_hi[a] < valid_lo[a]) return 0;
+  return peaks_batch_scratch(valid_lo, valid_hi);
+}
+
+int ttm_find_peaks_batch(ttm_ctx* ctx, const ttm_peak_item* items, int n_items,
+                         const int32_t max_valid[3], void* stream) {
+  if (!ctx || !items || n_items < 1 || n_items > 65535 || !max_valid) {
+    set_error("ttm_find_peaks_batch: null pointer or n_items outside 1..65535");
+    return TTM_EINVAL;
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (max_valid[a] < 1 || max_valid[a] > 32767) {
+      set_error("ttm_find_peaks_batch: max_valid axis %d = %d outside 1..32767", a, max_valid[a]);
+      return TTM_EINVAL;
+    }
+  }
+  TTM_HIP(hipSetDevice(ctx->device));
+  return find_peaks_batch(items, n_items, max_valid, static_cast<hipStream_t>(stream));
 }
 
 int ttm_fft3d_r2c(ttm_ctx* ctx, const float* x, int fft_n, void* spec, void* stream) {

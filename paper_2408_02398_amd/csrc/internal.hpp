@@ -128,6 +128,11 @@ int refine(int degree, int K, const float* g, const float* w, int nz, int ny, in
            const ExtractArgs& opts, int32_t* pos_out, float* quat_out, float* lncc_out,
            float* quat_peak, float* lncc_peak, void* ws, hipStream_t s);
 
+// Find Peaks over many maps in one launch (peaks_batch.hip); items is a
+// device array of ttm_peak_item (include/ttm.h).
+size_t peaks_batch_scratch(const int32_t lo[3], const int32_t hi[3]);
+int peaks_batch_max_peaks();
+
 // Find Peaks (peaks.hip).
 size_t peaks_workspace(int64_t n_voxels);
 int find_peaks(const float* score, int nz, int ny, int nx, const int32_t lo[3],

@@ -330,6 +330,49 @@ def find_peaks_async(ctx: Context, score: torch.Tensor, valid_lo, valid_hi, top_
          _ptr(ws), ws.numel(), _stream())
 
 
+class PeakBatch:
+    """Find Peaks over many score maps in one launch (ttm_find_peaks_batch).
+
+    entries: dicts with score (device map), lo, hi (inclusive valid box),
+    top_p, min_dist, and the outputs peaks (device int32 top_p x 3), vals
+    (device float top_p), n_found (device int32 view of one element).  The
+    item table and the per-item scratch are built once, on the device, so the
+    launch can be captured into a graph and replayed."""
+
+    def __init__(self, ctx: Context, entries):
+        lib = load()
+        dev = entries[0]["score"].device
+        self.ctx = ctx
+        sizes = []
+        for e in entries:
+            _need_cuda(e["score"], e["peaks"], e["vals"], e["n_found"])
+            n = lib.ttm_peaks_batch_scratch_bytes(I32x3(*e["lo"]), I32x3(*e["hi"]))
+            if n == 0:
+                raise ValueError("invalid valid box")
+            sizes.append((n + 255) // 256 * 256)
+        self.scratch = torch.empty(sum(sizes), dtype=torch.uint8, device=dev)
+        arr = (L.PeakItem * len(entries))()
+        off = 0
+        base = self.scratch.data_ptr()
+        for i, e in enumerate(entries):
+            it = arr[i]
+            it.score, it.peaks, it.vals = e["score"].data_ptr(), e["peaks"].data_ptr(), e["vals"].data_ptr()
+            it.n_found, it.scratch = e["n_found"].data_ptr(), base + off
+            off += sizes[i]
+            for a in range(3):
+                it.dims[a] = e["score"].shape[a]
+                it.valid_lo[a], it.valid_hi[a] = e["lo"][a], e["hi"][a]
+            it.top_p, it.min_dist = int(e["top_p"]), float(e["min_dist"])
+        raw = np.frombuffer(bytes(arr), dtype=np.uint8)
+        self.table = torch.from_numpy(raw.copy()).to(dev)
+        self.n = len(entries)
+        self.max_valid = [max(e["hi"][a] - e["lo"][a] + 1 for e in entries) for a in range(3)]
+
+    def run(self) -> None:
+        call("ttm_find_peaks_batch", self.ctx.h, _ptr(self.table), self.n, I32x3(*self.max_valid),
+             _stream())
+
+
 def fft3d_r2c(ctx: Context, x: torch.Tensor) -> torch.Tensor:
     _need_cuda(x)
     N = x.shape[0]
@@ -586,6 +629,15 @@ class BatchEngine:
         self.ws_corr = torch.empty(ws_corr, dtype=torch.uint8, device=dev)
         self.ws_peaks = torch.empty(ws_peaks, dtype=torch.uint8, device=dev)
         self.ws_ext = torch.empty(ws_ext, dtype=torch.uint8, device=dev)
+        # Find Peaks of every item in one launch
+        entries = []
+        for i, (s, o) in enumerate(zip(self.shapes, owner)):
+            d = templates[o][0]
+            lo, hi = valid_bounds(s, d.L)
+            entries.append(dict(score=self.score[i], lo=lo, hi=hi, top_p=top_p,
+                                min_dist=2.0 * d.mask_radius, peaks=self.peaks[i], vals=self.vals[i],
+                                n_found=self.n_found[i:i + 1]))
+        self.peak_batch = PeakBatch(ctx, entries)
         self.Cbuf = torch.empty(cmax, dtype=field_dtype, device=dev)
         self.g = [torch.empty(s, dtype=torch.float32, device=dev) for s in self.shapes]
         self.w = [torch.empty(s, dtype=torch.float32, device=dev) for s in self.shapes]
@@ -619,8 +671,8 @@ class BatchEngine:
             extract(self.ctx, d, Ct, score=self.score[i], lam=self.lam[i], direction=self.direction[i],
                     out_lo=lo, out_dims=s, starts=self.starts, orient=self.orient, mlp=mlp,
                     kappa=self.kappa, fallbacks=self.fallbacks, ws=self.ws_ext)
-            find_peaks_async(self.ctx, self.score[i], lo, hi, self.top_p, 2.0 * d.mask_radius,
-                             self.peaks[i], self.vals[i], self.n_found[i:i + 1], self.ws_peaks)
+
+        self.peak_batch.run()
 
     def capture(self):
         """Record the whole batch into one HIP graph (after a warm-up on a side stream)."""

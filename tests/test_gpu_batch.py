@@ -190,3 +190,30 @@ def test_batch_c5_shapes_match_oracle(T, ctx):
     print(f"[batch c5 shapes] orientation {counts}", flush=True)
     total = sum(counts.values())
     assert counts["agree"] >= 0.8 * total
+
+
+def test_peak_batch_equals_find_peaks_per_map(T, ctx):
+    """Find Peaks over several maps in one launch (ttm_find_peaks_batch) gives,
+    for each map, exactly the peaks and values of ttm_find_peaks (Sec. 3.4),
+    on maps with many exact ties, including a map where P is out of reach."""
+    cases = [(1, (20, 23, 26), 40, 3.0), (2, (40, 41, 42), 200, 5.5), (3, (9, 10, 11), 300, 1.0),
+             (5, (40, 52, 60), 2000, 6.0), (6, (64, 70, 50), 60, 20.0), (7, (33, 30, 31), 7, 0.0)]
+    entries, maps = [], []
+    for seed, shape, P, D in cases:
+        rng = np.random.default_rng(seed)
+        s = cuda(np.round(rng.uniform(0, 1, shape), 3).astype(np.float32))
+        lo, hi = (1, 2, 3), (shape[0] - 2, shape[1] - 1, shape[2] - 4)
+        maps.append((s, lo, hi, P, D))
+        entries.append(dict(score=s, lo=lo, hi=hi, top_p=P, min_dist=D,
+                            peaks=torch.zeros((P, 3), dtype=torch.int32, device="cuda"),
+                            vals=torch.zeros(P, dtype=torch.float32, device="cuda"),
+                            n_found=torch.zeros(1, dtype=torch.int32, device="cuda")))
+    pb = T.PeakBatch(ctx, entries)
+    for rep in range(2):                      # a second run on the same scratch
+        pb.run()
+        torch.cuda.synchronize()
+        for (s, lo, hi, P, D), e in zip(maps, entries):
+            pk, pv = T.find_peaks(ctx, s, lo, hi, P, D)
+            n = int(e["n_found"].item())
+            assert n == pk.shape[0], (rep, s.shape, P, D)
+            assert torch.equal(e["peaks"][:n], pk) and torch.equal(e["vals"][:n], pv)
