@@ -316,6 +316,40 @@ int ttm_refine(ttm_ctx* ctx, const ttm_desc* desc, const float* g, const float* 
                void* stream);
 
 /*
+ * ttm_extract over many boxes in one call (d' = 3): a batch of subtomograms
+ * whose field boxes share the descriptor (and, with TTM_START_MLP, the
+ * network), extracted by the same launches as one box of total_voxels
+ * voxels, so a batch costs about the kernels of one call instead of one call
+ * per box.  Rules, options and results per voxel are those of ttm_extract.
+ *   items       device array of n_items ttm_extract_item; item i's voxels are
+ *               numbers first_i .. first_i + its box volume - 1 of the batch,
+ *               with first_0 = 0 and first_{i+1} = first_i + box volume of i
+ *               (the caller's responsibility, as are the pointers: field
+ *               planes K x box, maps of out_dims holding the box at out_lo;
+ *               score may be NULL without TTM_SCORE; lambda and dir are
+ *               required with TTM_ORIENT)
+ *   total_voxels the batch's voxel count (sum of the box volumes)
+ *   ws          ttm_workspace_size(desc, TTM_OP_EXTRACT, 0, total_voxels, 1, 1) bytes
+ * Errors: as ttm_extract; TTM_EUNSUPPORTED at d' = 4.
+ */
+typedef struct {
+  const void* C;            /* device, K x box[0] x box[1] x box[2] (in_dtype)  */
+  float* score;             /* device map or NULL                               */
+  float* lambda;            /* device map or NULL                               */
+  float* dir;               /* device map (3 floats per voxel) or NULL          */
+  uint64_t first;           /* index of the box's first voxel in the batch      */
+  int32_t box[3];           /* bz, by, bx                                       */
+  int32_t out_lo[3];        /* where box voxel (0,0,0) lands in the maps        */
+  int32_t out_dims[3];      /* extent (z, y, x) of the maps                     */
+  int32_t reserved;
+} ttm_extract_item;
+
+int ttm_extract_batch(ttm_ctx* ctx, const ttm_desc* desc, const ttm_extract_item* items,
+                      int n_items, uint64_t total_voxels, int in_dtype,
+                      const ttm_extract_opts* opts, int32_t* n_fallback, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/*
  * Learned start network (a seed for the orientation search of Sec. 3.1):
  * x (K <= 32 features, zero padded) -> 64 -> relu -> 64 -> relu -> 3, BF16
  * weights, FP32 accumulation, activations rounded to BF16.

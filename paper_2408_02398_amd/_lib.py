@@ -41,6 +41,12 @@ class PeakItem(C.Structure):
                 ("min_dist", C.c_float)]
 
 
+class ExtractItem(C.Structure):
+    _fields_ = [("C", C.c_void_p), ("score", C.c_void_p), ("lam", C.c_void_p), ("dir", C.c_void_p),
+                ("first", C.c_uint64), ("box", C.c_int32 * 3), ("out_lo", C.c_int32 * 3),
+                ("out_dims", C.c_int32 * 3), ("reserved", C.c_int32)]
+
+
 I32x3 = C.c_int32 * 3
 vp = C.c_void_p
 DP = C.POINTER(Desc)
@@ -76,6 +82,8 @@ SIGNATURES = {
     "ttm_refine": (C.c_int, [vp, DP, vp, vp, C.c_int, C.c_int, C.c_int, vp, vp, vp, C.c_int,
                              C.c_float, C.POINTER(ExtractOpts), vp, vp, vp, vp, vp, vp, C.c_size_t,
                              vp]),
+    "ttm_extract_batch": (C.c_int, [vp, DP, vp, C.c_int, C.c_uint64, C.c_int, C.POINTER(ExtractOpts),
+                                    vp, vp, C.c_size_t, vp]),
     "ttm_mlp_param_count": (C.c_size_t, []),
     "ttm_mlp_packed_bytes": (C.c_size_t, []),
     "ttm_mlp_pack": (C.c_int, [vp, vp, vp, vp]),

@@ -975,6 +975,80 @@ int ttm_refine(ttm_ctx* ctx, const ttm_desc* desc, const float* g, const float* 
                 r_s, a, pos_out, quat_out, lncc_out, quat_peak_out, lncc_peak_out, ws, s);
 }
 
+static_assert(sizeof(ttm_extract_item) == 80, "ttm_extract_item layout is part of the ABI");
+
+int ttm_extract_batch(ttm_ctx* ctx, const ttm_desc* desc, const ttm_extract_item* items,
+                      int n_items, uint64_t total_voxels, int in_dtype,
+                      const ttm_extract_opts* opts, int32_t* n_fallback, void* ws,
+                      size_t ws_bytes, void* stream) {
+  if (!ctx || !valid_desc(desc)) return TTM_EINVAL;
+  if (!items || n_items < 1 || total_voxels < 1 || total_voxels >= ((uint64_t)1 << 32) || !opts ||
+      (in_dtype != TTM_F32 && in_dtype != TTM_BF16)) {
+    set_error("ttm_extract_batch: null pointer, no items, total voxels outside 1..2^32-1, or bad dtype");
+    return TTM_EINVAL;
+  }
+  if (desc->dprime != 3) {
+    set_error("ttm_extract_batch: d'=3 only");
+    return TTM_EUNSUPPORTED;
+  }
+  const int mode = opts->mode;
+  if ((mode & ~31) || !(mode & 3) || ((mode & 24) && !(mode & 4)) || ((mode & 4) && !(mode & 2))) {
+    set_error("ttm_extract_batch: mode %d invalid", mode);
+    return TTM_EINVAL;
+  }
+  const size_t plane = (size_t)total_voxels;
+  if (mode & 2) {
+    if (desc->degree < 2 || desc->degree > 6) {
+      set_error("ttm_extract_batch: orientation needs degree 2..6");
+      return TTM_EUNSUPPORTED;
+    }
+    if (!opts->starts || opts->n_starts < 1 || opts->n_starts > 64 || opts->max_iter < 1 ||
+        opts->max_iter > (1 << 24) || !(opts->tol >= 0.0f) || opts->newton_steps < 0 ||
+        opts->newton_steps > 8) {
+      set_error("ttm_extract_batch: orientation options invalid");
+      return TTM_EINVAL;
+    }
+    if ((mode & 4) && (!opts->mlp || !(opts->fallback_kappa == opts->fallback_kappa) ||
+                       ncomp(desc->degree, 3) > kMlpInMax)) {
+      set_error("ttm_extract_batch: learned start needs mlp and a kappa, at most %d components",
+                kMlpInMax);
+      return TTM_EINVAL;
+    }
+    const size_t need = extract_workspace(plane, desc->degree);
+    if (!ws || ws_bytes < need) {
+      set_error("ttm_extract_batch: workspace %zu < %zu", ws_bytes, need);
+      return TTM_EWORKSPACE;
+    }
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  TTM_HIP(hipSetDevice(ctx->device));
+  ExtractArgs a{};
+  a.in_dtype = in_dtype;
+  a.plane = plane;
+  a.by = 1;
+  a.bx = (int)plane;
+  a.dy = 1;
+  a.dx = (int)plane;
+  a.mode = mode & 7;
+  a.starts = opts->starts;
+  a.n_starts = (mode & 2) ? opts->n_starts : 0;
+  a.max_iter = opts->max_iter;
+  a.tol = opts->tol;
+  a.newton = opts->newton_steps;
+  a.counters = reinterpret_cast<unsigned long long*>(opts->work_counters);
+  a.ws = ws;
+  a.items = items;
+  a.n_items = n_items;
+  if (mode & 4) {
+    a.mlp = static_cast<const unsigned char*>(opts->mlp);
+    a.kappa = opts->fallback_kappa;
+    a.start_only = (mode & 8) ? 1 : 0;
+    a.screen = (mode & 16) ? 0 : 1;
+    a.fb_total = n_fallback;
+  }
+  return launch_extract(desc->degree, a, s);
+}
+
 size_t ttm_mlp_param_count(void) { return kMlpParams; }
 size_t ttm_mlp_packed_bytes(void) { return kMlpPackedBytes; }
 

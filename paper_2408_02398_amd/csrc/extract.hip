@@ -408,40 +408,77 @@ __device__ __forceinline__ void canonical(float& x, float& y, float& z) {
   }
 }
 
-// Load the K components of box voxel v, return ||C||_F.
+__device__ __forceinline__ size_t map_index(const ExtractArgs& a, size_t v) {
+  const int vx = (int)(v % a.bx), vy = (int)((v / a.bx) % a.by), vz = (int)(v / ((size_t)a.bx * a.by));
+  return ((size_t)(a.oz + vz) * a.dy + (a.oy + vy)) * a.dx + (a.ox + vx);
+}
+
+// Where voxel v of the call reads its field and writes its answer: the single
+// box, or in a batched call the item holding v (the last whose first voxel is
+// <= v), with v's place inside it.
+struct Vox {
+  const void* C;
+  size_t stride;     // voxels per component plane
+  size_t lv;         // v within the planes
+  size_t o;          // index in the output maps
+  float* score;
+  float* lam;
+  float* dir;
+};
+
+__device__ __forceinline__ Vox vox(const ExtractArgs& a, size_t v) {
+  if (!a.items) return Vox{a.C, a.plane, v, map_index(a, v), a.score, a.lam, a.dir};
+  int lo = 0, hi = a.n_items - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.items[mid].first <= v) lo = mid; else hi = mid - 1;
+  }
+  const ExtractItem& it = a.items[lo];
+  const size_t lv = v - it.first;
+  const int by = it.box[1], bx = it.box[2];
+  const int vx = (int)(lv % bx), vy = (int)((lv / bx) % by), vz = (int)(lv / ((size_t)bx * by));
+  const size_t o = ((size_t)(it.out_lo[0] + vz) * it.out_dims[1] + (it.out_lo[1] + vy)) * it.out_dims[2] +
+                   (it.out_lo[2] + vx);
+  return Vox{it.C, (size_t)it.box[0] * by * bx, lv, o, it.score, it.lambda, it.dir};
+}
+
+// The K components of a voxel, as stored (no arithmetic, so a lane can
+// issue them for its next voxel and keep working on the current one).
 template <int N>
-__device__ __forceinline__ float load_tensor(const ExtractArgs& a, size_t v, float (&c)[ncomp3(N)]) {
+__device__ __forceinline__ void load_raw_at(const ExtractArgs& a, const Vox& r, float (&c)[ncomp3(N)]) {
+  constexpr int K = ncomp3(N);
+  if (a.in_dtype == 1) {
+    const unsigned short* p = reinterpret_cast<const unsigned short*>(r.C);
+#pragma unroll
+    for (int k = 0; k < K; ++k) c[k] = bf16_to_f32(p[k * r.stride + r.lv]);
+  } else {
+    const float* p = reinterpret_cast<const float*>(r.C);
+#pragma unroll
+    for (int k = 0; k < K; ++k) c[k] = p[k * r.stride + r.lv];
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void load_raw(const ExtractArgs& a, size_t v, float (&c)[ncomp3(N)]) {
+  load_raw_at<N>(a, vox(a, v), c);
+}
+
+// Load the K components of a voxel, return ||C||_F.
+template <int N>
+__device__ __forceinline__ float load_tensor_at(const ExtractArgs& a, const Vox& r,
+                                                float (&c)[ncomp3(N)]) {
   constexpr int K = ncomp3(N);
   constexpr Sym3<N> sy{};
-  if (a.in_dtype == 1) {
-    const unsigned short* p = reinterpret_cast<const unsigned short*>(a.C);
-#pragma unroll
-    for (int k = 0; k < K; ++k) c[k] = bf16_to_f32(p[k * a.plane + v]);
-  } else {
-    const float* p = reinterpret_cast<const float*>(a.C);
-#pragma unroll
-    for (int k = 0; k < K; ++k) c[k] = p[k * a.plane + v];
-  }
+  load_raw_at<N>(a, r, c);
   float f2 = 0.0f;
 #pragma unroll
   for (int k = 0; k < K; ++k) f2 = fmaf(sy.mu[k] * c[k], c[k], f2);
   return sqrtf(f2);
 }
 
-// The K components of box voxel v, as stored (no arithmetic, so a lane can
-// issue them for its next voxel and keep working on the current one).
 template <int N>
-__device__ __forceinline__ void load_raw(const ExtractArgs& a, size_t v, float (&c)[ncomp3(N)]) {
-  constexpr int K = ncomp3(N);
-  if (a.in_dtype == 1) {
-    const unsigned short* p = reinterpret_cast<const unsigned short*>(a.C);
-#pragma unroll
-    for (int k = 0; k < K; ++k) c[k] = bf16_to_f32(p[k * a.plane + v]);
-  } else {
-    const float* p = reinterpret_cast<const float*>(a.C);
-#pragma unroll
-    for (int k = 0; k < K; ++k) c[k] = p[k * a.plane + v];
-  }
+__device__ __forceinline__ float load_tensor(const ExtractArgs& a, size_t v, float (&c)[ncomp3(N)]) {
+  return load_tensor_at<N>(a, vox(a, v), c);
 }
 
 // ||C||_F of loaded components (the same sum load_tensor forms).
@@ -460,18 +497,12 @@ __device__ __forceinline__ void scale(float (&c)[ncomp3(N)], float inv) {
   for (int k = 0; k < ncomp3(N); ++k) c[k] *= inv;
 }
 
-__device__ __forceinline__ size_t map_index(const ExtractArgs& a, size_t v) {
-  const int vx = (int)(v % a.bx), vy = (int)((v / a.bx) % a.by), vz = (int)(v / ((size_t)a.bx * a.by));
-  return ((size_t)(a.oz + vz) * a.dy + (a.oy + vy)) * a.dx + (a.ox + vx);
-}
-
-__device__ __forceinline__ void write_answer(const ExtractArgs& a, size_t o, float lam, float x,
-                                             float y, float z) {
-  if (a.lam) a.lam[o] = lam;
-  if (a.dir) {
-    a.dir[3 * o + 0] = x;
-    a.dir[3 * o + 1] = y;
-    a.dir[3 * o + 2] = z;
+__device__ __forceinline__ void write_answer(const Vox& r, float lam, float x, float y, float z) {
+  if (r.lam) r.lam[r.o] = lam;
+  if (r.dir) {
+    r.dir[3 * r.o + 0] = x;
+    r.dir[3 * r.o + 1] = y;
+    r.dir[3 * r.o + 2] = z;
   }
 }
 
@@ -502,7 +533,9 @@ __global__ __launch_bounds__(256) void k_score(ExtractArgs a) {
   const size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= a.plane) return;
   float c[ncomp3(N)];
-  a.score[map_index(a, v)] = load_tensor<N>(a, v, c);
+  const Vox r = vox(a, v);
+  const float cn = load_tensor_at<N>(a, r, c);
+  if (r.score) r.score[r.o] = cn;
 }
 
 // ---------------------------------------------------------------------------
@@ -564,7 +597,10 @@ __global__ __launch_bounds__(256) void k_prepare(ExtractArgs a, Items it, int wr
     const size_t v = it.voxel(j);
     float c[ncomp3(N)];
     const float cn = it.stage ? load_staged<N>(it.stage, v, c) : load_tensor<N>(a, v, c);
-    if (write_score && a.score) a.score[map_index(a, v)] = cn;
+    if (write_score) {
+      const Vox r = vox(a, v);
+      if (r.score) r.score[r.o] = cn;
+    }
     float alpha = 0.0f;
     if (cn > 0.0f) {
       if (!it.stage) scale<N>(c, 1.0f / cn);
@@ -656,25 +692,10 @@ __global__ __launch_bounds__(64) void k_runs(ExtractArgs a, RunArgs r) {
               for (int k = 0; k < K; ++k) cs[k][lane] = cv[k];
               cz[lane] = cn;
             } else {
-              float f2 = 0.0f;
-              if (a.in_dtype == 1) {
-                const unsigned short* p = reinterpret_cast<const unsigned short*>(a.C);
+              float cv[K];
+              const float cn = load_tensor<N>(a, v, cv);
 #pragma unroll
-                for (int k = 0; k < K; ++k) {
-                  const float x = bf16_to_f32(p[k * a.plane + v]);
-                  cs[k][lane] = x;
-                  f2 = fmaf(sy.mu[k] * x, x, f2);
-                }
-              } else {
-                const float* p = reinterpret_cast<const float*>(a.C);
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                  const float x = p[k * a.plane + v];
-                  cs[k][lane] = x;
-                  f2 = fmaf(sy.mu[k] * x, x, f2);
-                }
-              }
-              const float cn = sqrtf(f2);
+              for (int k = 0; k < K; ++k) cs[k][lane] = cv[k];
               const float inv = cn > 0.0f ? 1.0f / cn : 0.0f;
 #pragma unroll
               for (int k = 0; k < K; ++k) cs[k][lane] *= inv;
@@ -794,8 +815,8 @@ __global__ __launch_bounds__(256) void k_reduce(ExtractArgs a, Items it, int nsb
         lam = b.w * cn;
         n_oriented += merge ? 0 : 1;
       }
-      const size_t o = map_index(a, v);
-      if (!merge || lam > a.lam[o]) write_answer(a, o, lam, ux, uy, uz);
+      const Vox r = vox(a, v);
+      if (!merge || lam > r.lam[r.o]) write_answer(r, lam, ux, uy, uz);
     }
   }
   if (a.counters) {
@@ -876,7 +897,7 @@ __device__ __forceinline__ unsigned long long learned_finish(
   }
   const bool fallback = forced || !conv || !certified || !(lam >= a.kappa) || beaten;
   canonical(ux, uy, uz);
-  write_answer(a, map_index(a, v), lam * cn, ux, uy, uz);
+  write_answer(vox(a, v), lam * cn, ux, uy, uz);
   w.status[v] = fallback ? 2 : 0;
   fell = fallback;
   return taken;
@@ -915,8 +936,8 @@ __global__ __launch_bounds__(64) void k_mlp_start(ExtractArgs a) {
       load_raw<N>(a, vn < a.plane ? vn : a.plane - 1, cx);
     }
     const float cn = frob<N>(c);
-    const size_t o = map_index(a, v);
-    if ((a.mode & 1) && active) a.score[o] = cn;
+    const Vox vr = vox(a, v);
+    if ((a.mode & 1) && active && vr.score) vr.score[vr.o] = cn;
     const float inv = cn > 0.0f ? 1.0f / cn : 0.0f;
 #pragma unroll
     for (int k = 0; k < kMlpIn; ++k)
@@ -928,7 +949,7 @@ __global__ __launch_bounds__(64) void k_mlp_start(ExtractArgs a) {
     float ux = forced ? s0x : y0, uy = forced ? s0y : y1, uz = forced ? s0z : y2;
     const float r = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
     ux *= r; uy *= r; uz *= r;
-    if (active) write_answer(a, o, 0.0f, ux, uy, uz);
+    if (active) write_answer(vr, 0.0f, ux, uy, uz);
     __syncthreads();   // xs is rewritten by the next group
 #pragma unroll
     for (int k = 0; k < K; ++k) c[k] = cx[k];
@@ -988,8 +1009,8 @@ __global__ __launch_bounds__(64 * kLearnedWaves) void k_learned(ExtractArgs a) {
       load_raw<N>(a, vn < a.plane ? vn : a.plane - 1, cx);
     }
     const float cn = frob<N>(c);
-    const size_t o = map_index(a, v);
-    if ((a.mode & 1) && active) a.score[o] = cn;
+    const Vox vr = vox(a, v);
+    if ((a.mode & 1) && active && vr.score) vr.score[vr.o] = cn;
     const float inv = cn > 0.0f ? 1.0f / cn : 0.0f;
 #pragma unroll
     for (int k = 0; k < kMlpIn; ++k)
@@ -1026,7 +1047,7 @@ __global__ __launch_bounds__(64 * kLearnedWaves) void k_learned(ExtractArgs a) {
         // the voxels handed on read their tensor from here, in one piece
         if (fell) store_staged<N>(w.stage, v, c, cn);
       } else {
-        write_answer(a, o, 0.0f, 0.0f, 0.0f, 0.0f);
+        write_answer(vr, 0.0f, 0.0f, 0.0f, 0.0f);
         w.status[v] = 0;
       }
     }

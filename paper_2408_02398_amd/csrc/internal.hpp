@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "../../include/ttm.h"
 #include "fft_core.hpp"
 
 namespace ttm {
@@ -83,6 +84,9 @@ int fft3d_inverse_mul(int N, const cf* G, const cf* S, size_t s_stride, int s_pl
 
 int init_twiddles(cf* tw_all, hipStream_t s);
 
+// One box of a batched extraction: the ABI's device table entry.
+using ExtractItem = ttm_extract_item;
+
 // Per-voxel extraction launch (extract.hip).
 struct ExtractArgs {
   const void* C;       // K planes of `plane` voxels (float32 or bfloat16)
@@ -108,6 +112,10 @@ struct ExtractArgs {
   int screen;                    // fall back when a fixed start beats the learned lambda
   void* ws;                      // work queues and run results (extract_workspace bytes)
   int* fb_total;                 // optional caller counter of fallbacks
+  // batched call: `plane` voxels over n_items boxes of a device table (C, the
+  // box geometry and the maps above are then unused)
+  const ExtractItem* items;
+  int n_items;
 };
 // Workspace bytes of an orientation extraction over `plane` voxels.
 size_t extract_workspace(size_t plane, int degree);

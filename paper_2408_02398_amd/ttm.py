@@ -330,6 +330,58 @@ def find_peaks_async(ctx: Context, score: torch.Tensor, valid_lo, valid_hi, top_
          _ptr(ws), ws.numel(), _stream())
 
 
+class ExtractBatch:
+    """ttm_extract over many boxes in one call: entries are dicts with C (device
+    K x bz x by x bx), the maps score, lam, direction and out_lo (where the box
+    sits in them).  The item table is built once on the device."""
+
+    def __init__(self, ctx: Context, desc: Desc, entries):
+        dev = entries[0]["C"].device
+        self.ctx, self.desc = ctx, desc
+        arr = (L.ExtractItem * len(entries))()
+        first = 0
+        self.dtype = entries[0]["C"].dtype
+        for i, e in enumerate(entries):
+            _need_cuda(e["C"], e.get("score"), e["lam"], e["direction"])
+            if e["C"].dtype != self.dtype:
+                raise ValueError("one field dtype per batch")
+            it = arr[i]
+            it.C = e["C"].data_ptr()
+            it.score = e["score"].data_ptr() if e.get("score") is not None else None
+            it.lam, it.dir = e["lam"].data_ptr(), e["direction"].data_ptr()
+            it.first = first
+            box = tuple(e["C"].shape[1:])
+            for a in range(3):
+                it.box[a], it.out_lo[a], it.out_dims[a] = box[a], e["out_lo"][a], e["lam"].shape[a]
+            first += int(np.prod(box))
+        self.table = torch.from_numpy(np.frombuffer(bytes(arr), dtype=np.uint8).copy()).to(dev)
+        self.n, self.total = len(entries), first
+
+    def workspace_bytes(self) -> int:
+        return load().ttm_workspace_size(C.byref(self.desc), L.TTM_OP_EXTRACT, 0, self.total, 1, 1)
+
+    def run(self, starts: torch.Tensor, ws: torch.Tensor, mlp: "MLP | None" = None,
+            kappa: float = 0.0, fallbacks: torch.Tensor | None = None, max_iter: int = 500,
+            tol: float = 1e-5, newton: int = 2, screen: bool = True, orient: bool = True) -> None:
+        _need_cuda(starts, ws, fallbacks)
+        opts = ExtractOpts()
+        mode = L.TTM_SCORE
+        if orient:
+            mode |= L.TTM_ORIENT
+            if mlp is not None:
+                mode |= L.TTM_START_MLP
+                if not screen:
+                    mode |= L.TTM_NO_SCREEN
+                opts.mlp = mlp.packed.data_ptr()
+                opts.fallback_kappa = kappa
+        opts.mode = mode
+        opts.n_starts, opts.starts = starts.shape[0], starts.data_ptr()
+        opts.max_iter, opts.tol, opts.newton_steps = max_iter, tol, newton
+        code = L.TTM_BF16 if self.dtype == torch.bfloat16 else L.TTM_F32
+        call("ttm_extract_batch", self.ctx.h, C.byref(self.desc), _ptr(self.table), self.n,
+             self.total, code, C.byref(opts), _ptr(fallbacks), _ptr(ws), ws.numel(), _stream())
+
+
 class PeakBatch:
     """Find Peaks over many score maps in one launch (ttm_find_peaks_batch).
 
@@ -614,20 +666,44 @@ class BatchEngine:
         self.n_found = torch.zeros(len(self.shapes), dtype=torch.int32, device=dev)
         self.fallbacks = torch.zeros(1, dtype=torch.int32, device=dev)
         # shared workspaces, each sized for the largest request of its kind
-        ws_norm = ws_corr = ws_peaks = ws_ext = 0
-        cmax = 0
+        ws_norm = ws_corr = 0
         lib = load()
         for s, o, N in zip(self.shapes, owner, self.fft):
             d = templates[o][0]
             ws_norm = max(ws_norm, lib.ttm_workspace_size(C.byref(d), L.TTM_OP_NORMALIZE, N, *s))
             ws_corr = max(ws_corr, lib.ttm_workspace_size(C.byref(d), L.TTM_OP_CORRELATE, N, *s))
-            ws_peaks = max(ws_peaks, lib.ttm_workspace_size(C.byref(d), L.TTM_OP_PEAKS, N, *s))
-            v = [x - d.L + 1 for x in s]
-            ws_ext = max(ws_ext, lib.ttm_workspace_size(C.byref(d), L.TTM_OP_EXTRACT, 0, *v))
-            cmax = max(cmax, n_components(d.degree, d.dprime) * int(np.prod(v)))
         self.ws_norm = torch.empty(ws_norm, dtype=torch.uint8, device=dev)
         self.ws_corr = torch.empty(ws_corr, dtype=torch.uint8, device=dev)
-        self.ws_peaks = torch.empty(ws_peaks, dtype=torch.uint8, device=dev)
+        # each item's field in its own slice of its template's buffer, so that one
+        # extraction call serves every item of a template
+        self.groups = sorted(set(owner))
+        self.Cslice = [None] * len(self.shapes)
+        self.extract_batches = {}
+        self.Cgroup = {}
+        ws_ext = 0
+        for o in self.groups:
+            d = templates[o][0]
+            K = n_components(d.degree, d.dprime)
+            idx = [i for i in range(len(self.shapes)) if owner[i] == o]
+            sizes = []
+            for i in idx:
+                lo, hi = valid_bounds(self.shapes[i], d.L)
+                sizes.append(tuple(h - l + 1 for l, h in zip(lo, hi)))
+            total = sum(int(np.prod(sz)) for sz in sizes)
+            buf = torch.empty(K * total, dtype=field_dtype, device=dev)
+            self.Cgroup[o] = buf
+            off = 0
+            entries = []
+            for i, sz in zip(idx, sizes):
+                nv = int(np.prod(sz))
+                self.Cslice[i] = buf[K * off: K * (off + nv)].view(K, *sz)
+                off += nv
+                lo, _ = valid_bounds(self.shapes[i], d.L)
+                entries.append(dict(C=self.Cslice[i], score=self.score[i], lam=self.lam[i],
+                                    direction=self.direction[i], out_lo=lo))
+            eb = ExtractBatch(ctx, d, entries)
+            self.extract_batches[o] = eb
+            ws_ext = max(ws_ext, eb.workspace_bytes())
         self.ws_ext = torch.empty(ws_ext, dtype=torch.uint8, device=dev)
         # Find Peaks of every item in one launch
         entries = []
@@ -638,7 +714,6 @@ class BatchEngine:
                                 min_dist=2.0 * d.mask_radius, peaks=self.peaks[i], vals=self.vals[i],
                                 n_found=self.n_found[i:i + 1]))
         self.peak_batch = PeakBatch(ctx, entries)
-        self.Cbuf = torch.empty(cmax, dtype=field_dtype, device=dev)
         self.g = [torch.empty(s, dtype=torch.float32, device=dev) for s in self.shapes]
         self.w = [torch.empty(s, dtype=torch.float32, device=dev) for s in self.shapes]
         self.stats = torch.zeros((len(self.shapes), 2), dtype=torch.float64, device=dev)
@@ -654,24 +729,24 @@ class BatchEngine:
              _ptr(self.ws_norm), self.ws_norm.numel(), _stream())
 
     def run_eager(self):
-        """All items in order on the current stream (also what the graph records)."""
+        """The whole batch on the current stream (also what the graph records):
+        each item's normalisation and correlation into its slice of its
+        template's field buffer, one extraction per template, one Find Peaks
+        launch for every item."""
         for i, s in enumerate(self.shapes):
             o = self.owner[i]
             d = self.templates[o][0]
             N = self.fft[i]
             spec = self.spectra[(o, N)]
-            K = n_components(d.degree, d.dprime)
             self._normalize_into(i)
             lo, hi = valid_bounds(s, d.L)
             size = tuple(h - l + 1 for l, h in zip(lo, hi))
-            Ct = self.Cbuf[: K * int(np.prod(size))].view(K, *size)
-            correlate(self.ctx, d, self.g[i], self.w[i], self.stats[i], spec, N, lo, size, out=Ct,
-                      ws=self.ws_corr)
+            correlate(self.ctx, d, self.g[i], self.w[i], self.stats[i], spec, N, lo, size,
+                      out=self.Cslice[i], ws=self.ws_corr)
+        for o in self.groups:
             mlp = self.mlps[o] if self.mlps is not None else None
-            extract(self.ctx, d, Ct, score=self.score[i], lam=self.lam[i], direction=self.direction[i],
-                    out_lo=lo, out_dims=s, starts=self.starts, orient=self.orient, mlp=mlp,
-                    kappa=self.kappa, fallbacks=self.fallbacks, ws=self.ws_ext)
-
+            self.extract_batches[o].run(self.starts, self.ws_ext, mlp=mlp, kappa=self.kappa,
+                                        fallbacks=self.fallbacks, orient=self.orient)
         self.peak_batch.run()
 
     def capture(self):

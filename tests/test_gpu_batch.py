@@ -217,3 +217,43 @@ def test_peak_batch_equals_find_peaks_per_map(T, ctx):
             n = int(e["n_found"].item())
             assert n == pk.shape[0], (rep, s.shape, P, D)
             assert torch.equal(e["peaks"][:n], pk) and torch.equal(e["vals"][:n], pv)
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_extract_batch_equals_per_box_extract(T, ctx, learned):
+    """ttm_extract_batch over boxes of different shapes (each written into its
+    own maps at an offset) gives, voxel for voxel, exactly what ttm_extract
+    gives for each box on its own: plain multistart and learned start with its
+    fallback."""
+    from oracle import mlp as omlp
+    from oracle import sym
+    from tests.gpu_common import oracle_trained_params
+    n, K = 6, 28
+    d = T.make_desc(n, 16, 7.0)
+    starts = cuda(synth.start_vectors())
+    net = T.MLP(ctx, d, cuda(omlp.pad_params(oracle_trained_params(12, n), K))) if learned else None
+    rng = np.random.default_rng(41)
+    boxes = [(5, 7, 9), (1, 1, 37), (12, 3, 20), (8, 8, 8)]
+    dims = [(9, 12, 14), (3, 4, 40), (16, 5, 22), (8, 8, 8)]
+    lows = [(2, 3, 4), (1, 2, 1), (0, 1, 2), (0, 0, 0)]
+    entries, singles = [], []
+    for box, dm, lo in zip(boxes, dims, lows):
+        nv = int(np.prod(box))
+        v = rng.standard_normal((nv, 3))
+        v /= np.linalg.norm(v, axis=1, keepdims=True)
+        Cb = cuda((sym.monomials(v, n) + 0.3 * rng.standard_normal((nv, K))).T.reshape(K, *box))
+        maps = [torch.zeros(dm, device="cuda"), torch.zeros(dm, device="cuda"),
+                torch.zeros((*dm, 3), device="cuda")]
+        entries.append(dict(C=Cb, score=maps[0], lam=maps[1], direction=maps[2], out_lo=lo))
+        fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+        s1, l1, u1 = T.extract(ctx, d, Cb, starts=starts, out_lo=lo, out_dims=dm, mlp=net, kappa=0.3,
+                               fallbacks=fb)
+        singles.append((s1, l1, u1, int(fb.item())))
+    eb = T.ExtractBatch(ctx, d, entries)
+    ws = torch.empty(eb.workspace_bytes(), dtype=torch.uint8, device="cuda")
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    eb.run(starts, ws, mlp=net, kappa=0.3, fallbacks=fb)
+    torch.cuda.synchronize()
+    for e, (s1, l1, u1, f1) in zip(entries, singles):
+        assert torch.equal(e["score"], s1) and torch.equal(e["lam"], l1) and torch.equal(e["direction"], u1)
+    assert int(fb.item()) == sum(x[3] for x in singles)
