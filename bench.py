@@ -390,7 +390,12 @@ def main():
 def ground_truth(wl, peaks, direction, r):
     """Detected copies among the peaks (a peak within r of a planted centre),
     position errors, and the axis error arccos|u . R_true a| (a = z axis) at
-    the detected copies' peaks (Sec. 4.1 metrics; reported, not gated)."""
+    the detected copies' peaks (Sec. 4.1 metrics; reported, not gated).  The
+    axis form recovers R a only for a template symmetric about a: for any
+    other template the field integrates each direction over all spins about
+    it, and its maximiser need not be R a (the blob templates here have no
+    such symmetry, so the axis error is context only; the quaternion form's
+    rotation errors are measured by the noise sweep)."""
     pk = peaks.cpu().numpy().astype(np.float64)
     cen = wl.centres.astype(np.float64)
     if len(pk) == 0 or len(cen) == 0:
@@ -415,7 +420,9 @@ def ground_truth(wl, peaks, direction, r):
             "precision": len(used) / len(pk),
             "position_err_vox": {"mean": float(pe.mean()), "max": float(pe.max())} if found else None,
             "axis_err_deg": {"mean": float(an.mean()), "median": float(np.median(an)),
-                             "max": float(an.max())} if found else None}
+                             "max": float(an.max())} if found else None,
+            "axis_err_note": "axis form on a template without axial symmetry: not an "
+                             "estimate of the copy's rotation"}
 
 
 def accuracy_gate(plain, learned, lo, hi, top_p, ttm, torch):

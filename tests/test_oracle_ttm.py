@@ -787,3 +787,52 @@ def test_certify_accepts_near_maxima_and_refuses_others():
         # -C has its minimum (for <C, u^n>: the maximum of -C's value) at v
         u, ok, step = ttm.certify(-C, n, v)
         assert not ok
+
+
+def _axial_template(L):
+    """Three blobs on the z axis, round across it: a template symmetric about z."""
+    s = L / 24.0
+    cz = s * np.array([[0, 0, -6.0], [0, 0, 1.0], [0, 0, 6.0]])
+    return synth.BlobTemplate(L=L, centres=cz, axes=np.stack([np.eye(3)] * 3),
+                              sigmas=s * np.array([[1.2, 1.2, 1.5], [2.2, 2.2, 1.2],
+                                                   [0.9, 0.9, 0.9]]))
+
+
+def _chiral_template(L):
+    """Three unequal blobs on three different axes: no rotation maps it near itself."""
+    s = L / 24.0
+    c = s * np.array([[6.0, 0, 0], [0, 4.0, 0], [0, 0, -3.0]])
+    return synth.BlobTemplate(L=L, centres=c, axes=np.stack([np.eye(3)] * 3),
+                              sigmas=s * np.array([[1.0, 1.0, 1.0], [1.4, 1.4, 1.4],
+                                                   [1.9, 1.9, 1.9]]))
+
+
+@pytest.mark.parametrize("dprime", [3, 4])
+def test_orientation_recovers_the_planted_rotation(dprime):
+    """Ground truth from the renderer, not from the oracle: a copy rendered as
+    t(R^T (p - x)) gives, at its centre, a field whose maximiser is R a in the
+    axis form (for a template symmetric about a, the case that form is for) and
+    the quaternion of R in the quaternion form (for a template that no rotation
+    maps near itself).  A transposed rotation, a wrong monomial order or an
+    axis in the wrong coordinate order lands tens of degrees away."""
+    rng = np.random.default_rng(11)
+    L, r, n, D = 24, 10.0, 4, 40
+    tm = _axial_template(L) if dprime == 3 else _chiral_template(L)
+    cen = np.array([[20, 19, 21]])
+    m = ttm.ball_mask(L, r)
+    tn = ttm.normalize_template(tm.volume(), r)
+    T = ttm.tensor_template(tn, synth.rotation_samples(40), n, dprime=dprime)
+    st = synth.start_vectors(count=64, dim=dprime).astype(np.float64)
+    errs = []
+    for R in synth.random_rotations(rng, 3):
+        vol = synth.render_copies((D, D, D), tm, cen, R[None], scale=1.0)
+        vol += 0.02 * rng.standard_normal(vol.shape)
+        g = ttm.prefilter_volume(vol)
+        Cv = ttm.field_at(ttm.patches_at(g, [cen[0]], L), m, T, ttm.volume_g2_mean(g))[1][0]
+        u = ttm.orient_multistart(Cv, n, st)[1]
+        u = u / np.linalg.norm(u)
+        if dprime == 3:
+            errs.append(np.degrees(np.arccos(min(1.0, abs(u @ R[:, 2])))))
+        else:
+            errs.append(np.degrees(2 * np.arccos(min(1.0, abs(u @ _quat_of(R))))))
+    assert max(errs) < 8.0, errs
