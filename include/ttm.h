@@ -26,7 +26,7 @@
  *   K = binom(n+3,3), alpha = (aw, ax, ay, az) in graded-lex order) is
  *   accepted by every entry point; its orientation is a unit quaternion
  *   (w, x, y, z), 4 floats per voxel, from the multistart search at degree
- *   2..4 (the learned start is d' = 3 only).
+ *   2..6 (the learned start is d' = 3 only).
  * - Template: cubic L^3, centre c = L/2 (integer division) on every axis,
  *   binary ball mask m(p) = [|p - c|^2 <= r^2].
  * - Valid region of a volume of extent D along an axis: voxels x with
@@ -282,7 +282,7 @@ int ttm_extract_noalloc(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int i
 
 /*
  * Position refinement TTM-ref (Sec. 3.3, Alg. 3), quaternion form (d' = 4,
- * degree 2 or 4).  For each peak x^i (device int32 n_peaks x 3, z y x, inside
+ * degree 2, 4 or 6).  For each peak x^i (device int32 n_peaks x 3, z y x, inside
  * the valid region, e.g. from ttm_find_peaks) the voxels of the sphere
  * |x - x^i| <= r_s are visited, the peak first and then the other offsets in
  * lexicographic (dz, dy, dx) order; voxels whose template window leaves the
@@ -306,7 +306,7 @@ int ttm_extract_noalloc(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int i
  *   quat_peak_out, lncc_peak_out  device, optional (NULL): the rotation and
  *             LNCC at each unrefined peak (TTM without refinement)
  *   ws        ttm_workspace_size(desc, TTM_OP_REFINE, 0, n_peaks, ceil(r_s), 1) bytes
- * Errors: TTM_EUNSUPPORTED unless d' = 4 and degree 2 or 4; TTM_EINVAL for
+ * Errors: TTM_EUNSUPPORTED unless d' = 4 and degree 2, 4 or 6; TTM_EINVAL for
  * null pointers, n_peaks < 1 or r_s out of range.
  */
 int ttm_refine(ttm_ctx* ctx, const ttm_desc* desc, const float* g, const float* w, int nz, int ny,

@@ -843,8 +843,8 @@ int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
   }
   if (mode & 2) {
     if (desc->dprime == 3 ? (desc->degree < 2 || desc->degree > 6)
-                          : (desc->degree < 2 || desc->degree > 4 || (mode & 4))) {
-      set_error("ttm_extract: orientation needs degree 2..6 at d'=3, or degree 2..4 and the "
+                          : (desc->degree < 2 || desc->degree > 6 || (mode & 4))) {
+      set_error("ttm_extract: orientation needs degree 2..6 at d'=3, or degree 2..6 and the "
                 "multistart search at d'=4");
       return TTM_EUNSUPPORTED;
     }
@@ -939,8 +939,8 @@ int ttm_refine(ttm_ctx* ctx, const ttm_desc* desc, const float* g, const float* 
                float* quat_peak_out, float* lncc_peak_out, void* ws, size_t ws_bytes,
                void* stream) {
   if (!ctx || !valid_desc(desc)) return TTM_EINVAL;
-  if (desc->dprime != 4 || desc->degree < 2 || desc->degree > 4) {
-    set_error("ttm_refine: needs the quaternion form (d'=4) at degree 2 or 4");
+  if (desc->dprime != 4 || desc->degree < 2 || desc->degree > 6) {
+    set_error("ttm_refine: needs the quaternion form (d'=4) at degree 2, 4 or 6");
     return TTM_EUNSUPPORTED;
   }
   if (!g || !w || !T || !tn || !peaks || !opts || !pos_out || !quat_out || !lncc_out || !ws ||

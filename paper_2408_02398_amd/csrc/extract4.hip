@@ -557,7 +557,7 @@ __global__ __launch_bounds__(256) void k_reduce4(ExtractArgs a, int nsb, int fir
 template <int N>
 int launch4_n(const ExtractArgs& a, hipStream_t s) {
   const unsigned nb = (unsigned)((a.plane + 255) / 256);
-  if constexpr (N >= 2 && N <= 4) {
+  if constexpr (N >= 2 && N <= 6) {
     if (a.mode & 2) {
       const Ws4 w = ws4_layout(a.ws, a.plane);
       fill_zero(w.ctr, 256, s);

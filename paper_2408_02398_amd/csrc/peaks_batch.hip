@@ -13,8 +13,10 @@
 //                 region (one workgroup per block)
 //   k_nms         one workgroup per item: P times, the smallest block key is
 //                 the next peak (or none is left); the ball's voxels are set
-//                 in the item's exclusion bitmask, and the keys of the blocks
-//                 the ball touches are recomputed without the excluded voxels.
+//                 in the item's exclusion bitmask, and the blocks the ball
+//                 touches are updated: emptied when they lie inside it,
+//                 rescanned without the excluded voxels when their smallest
+//                 key's voxel was excluded, and otherwise left as they are.
 // Every item's work is independent, so one launch serves the whole batch.
 #include "../../include/ttm.h"
 #include "internal.hpp"
@@ -215,13 +217,34 @@ __global__ __launch_bounds__(kNmsThreads) void k_nms(const ttm_peak_item* __rest
     }
     __threadfence_block();
     __syncthreads();
-    // 3. the keys of the blocks the ball touches, without the excluded voxels
+    // 3. the keys of the blocks the ball touches, without the excluded voxels.
+    // Exclusion only removes voxels, so a block whose smallest key belongs to
+    // a voxel outside the ball keeps it; a block inside the ball is emptied;
+    // only a block whose smallest-key voxel was just excluded is rescanned.
     const int bz0 = max(vz0 - R, 0) / kBlk, bz1 = min(vz0 + R, g.vz - 1) / kBlk;
     const int by0 = max(vy0 - R, 0) / kBlk, by1 = min(vy0 + R, g.vy - 1) / kBlk;
     const int bx0 = max(vx0 - R, 0) / kBlk, bx1 = min(vx0 + R, g.vx - 1) / kBlk;
     const int nbz = bz1 - bz0 + 1, nby = by1 - by0 + 1, nbx = bx1 - bx0 + 1;
     for (int q = wave; q < nbz * nby * nbx; q += kNmsThreads / 64) {
-      const int b = ((bz0 + q / (nby * nbx)) * g.by + (by0 + (q / nbx) % nby)) * g.bx + (bx0 + q % nbx);
+      const int qz = bz0 + q / (nby * nbx), qy = by0 + (q / nbx) % nby, qx = bx0 + q % nbx;
+      const int b = (qz * g.by + qy) * g.bx + qx;
+      const unsigned long long kb = keys[b];     // the same value in every lane
+      if (kb == ~0ull) continue;                 // already empty
+      // farthest corner of the block's valid part from the peak
+      const int cz0 = qz * kBlk - vz0, cz1 = min(qz * kBlk + kBlk, g.vz) - 1 - vz0;
+      const int cy0 = qy * kBlk - vy0, cy1 = min(qy * kBlk + kBlk, g.vy) - 1 - vy0;
+      const int cx0 = qx * kBlk - vx0, cx1 = min(qx * kBlk + kBlk, g.vx) - 1 - vx0;
+      const int fz = max(cz0 * cz0, cz1 * cz1), fy = max(cy0 * cy0, cy1 * cy1), fx = max(cx0 * cx0, cx1 * cx1);
+      if ((float)(fz + fy + fx) < D2) {
+        if (lane == 0) keys[b] = ~0ull;          // every voxel of the block is excluded
+        continue;
+      }
+      const unsigned kl = (unsigned)(kb & 0xFFFFFFFFull);
+      const int mx = (int)(kl % (unsigned)it.dims[2]) - x;
+      const int my = (int)((kl / (unsigned)it.dims[2]) % (unsigned)it.dims[1]) - y;
+      const int mz = (int)(kl / ((unsigned)it.dims[2] * (unsigned)it.dims[1])) - z;
+      const bool gone = (mx | my | mz) == 0 || (float)(mx * mx + my * my + mz * mz) < D2;
+      if (!gone) continue;                       // its smallest key is still there
       unsigned long long mm = block_min(it, g, bits, b, lane, 64);
       mm = wave_min(mm);
       if (lane == 0) keys[b] = mm;

@@ -26,6 +26,11 @@ namespace {
 
 constexpr int kFieldThreads = 128;   // candidates per k_field_at workgroup
 constexpr int kFieldChunk = 256;     // template voxels staged per LDS chunk
+// Template voxels per LDS chunk for K components: kFieldChunk, or half of it
+// where that many would take more than 48 KB (K = 84 at degree 6: 128 voxels).
+__host__ __device__ constexpr int field_chunk(int K) {
+  return ((K + 3) / 4 * 4) * kFieldChunk * 4 <= 48 * 1024 ? kFieldChunk : kFieldChunk / 2;
+}
 constexpr int kMaxRefineRadius = 8;
 
 struct RefineWs {
@@ -105,7 +110,7 @@ __global__ void k_candidates(const int32_t* __restrict__ peaks, int n_peaks, con
 
 // C_k(x) = w(x) sum_p g(x + p - c) T_k(p) at every candidate x (Eq. tcc at
 // single voxels).  Workgroup (peak, block of kFieldThreads candidates); the
-// template components of kFieldChunk template voxels at a time sit in LDS as
+// template components of field_chunk(K) template voxels at a time sit in LDS as
 // [p][K] (every thread reads the same entry: a broadcast).
 template <int K>
 __global__ __launch_bounds__(kFieldThreads) void k_field_at(const float* __restrict__ g,
@@ -114,7 +119,8 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_at(const float* __restr
                                                             const int4* __restrict__ cand, int V,
                                                             size_t n_cand, float* __restrict__ C) {
   constexpr int KP = (K + 3) / 4 * 4;
-  __shared__ __align__(16) float tl[kFieldChunk * KP];
+  constexpr int CH = field_chunk(K);
+  __shared__ __align__(16) float tl[CH * KP];
   const int j = blockIdx.y * kFieldThreads + threadIdx.x;
   const size_t k = (size_t)blockIdx.x * V + j;
   const bool live = j < V && cand[k].w != 0;
@@ -125,8 +131,8 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_at(const float* __restr
 #pragma unroll
   for (int a = 0; a < K; ++a) acc[a] = 0.0f;
   const int np = L * L * L;
-  for (int p0 = 0; p0 < np; p0 += kFieldChunk) {
-    const int cnt = min(kFieldChunk, np - p0);
+  for (int p0 = 0; p0 < np; p0 += CH) {
+    const int cnt = min(CH, np - p0);
     __syncthreads();
     for (int e = threadIdx.x; e < cnt * K; e += kFieldThreads) {
       const int a = e / cnt, pp = e % cnt;   // read each component's run of voxels in order
@@ -294,6 +300,7 @@ int field_at(int K, const float* g, const float* w, int ny, int nx, const float*
     case 15: launch_field_at<15>(g, w, ny, nx, T, L, cand, n_groups, V, n_cand, C, s); break;
     case 28: launch_field_at<28>(g, w, ny, nx, T, L, cand, n_groups, V, n_cand, C, s); break;
     case 35: launch_field_at<35>(g, w, ny, nx, T, L, cand, n_groups, V, n_cand, C, s); break;
+    case 84: launch_field_at<84>(g, w, ny, nx, T, L, cand, n_groups, V, n_cand, C, s); break;
     default: set_error("field at listed voxels: %d components not built", K); return -4;
   }
   hipError_t e = hipGetLastError();

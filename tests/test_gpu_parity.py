@@ -423,16 +423,18 @@ def test_quaternion_form_tensor_field_and_score(T, ctx, small):
     assert np.max(np.abs(host(score) - cs) / floor) < 1e-4
 
 
-def test_quaternion_orientation_matches_oracle(T, ctx, small):
-    """d' = 4 orientation (Sec. 3.1 on S^3, quaternions): rank-one tensors
-    lambda0 q^n give back (lambda0, +-q) with w >= 0, a zero tensor gives 0, and
-    at 120 sampled voxels of the d' = 4 field every answer agrees with the
-    oracle's converged multistart answer (rotation distance 2 arccos|q1.q2| <
-    1 degree) or is a near-optimal maximiser of the FP64 function."""
-    print("[quaternion orientation n=4]", flush=True)
-    n, L, r = 4, small["L"], small["r"]
+@pytest.mark.parametrize("n,n_vox", [(4, 120), (6, 48)])
+def test_quaternion_orientation_matches_oracle(T, ctx, small, n, n_vox):
+    """d' = 4 orientation (Sec. 3.1 on S^3, quaternions; K = 35 at n = 4, 84 at
+    n = 6): rank-one tensors lambda0 q^n give back (lambda0, +-q) with w >= 0, a
+    zero tensor gives 0, and at sampled voxels of the d' = 4 field every answer
+    agrees with the oracle's converged multistart answer (rotation distance
+    2 arccos|q1.q2| < 1 degree) or is a near-optimal maximiser of the FP64
+    function."""
+    print(f"[quaternion orientation n={n}]", flush=True)
+    L, r = small["L"], small["r"]
     d = T.make_desc(n, L, r, dprime=4)
-    K = 35
+    K = T.n_components(n, 4)
     starts = synth.start_vectors(count=32, dim=4)
     rng = np.random.default_rng(21)
     qs = rng.standard_normal((64, 4))
@@ -451,7 +453,7 @@ def test_quaternion_orientation_matches_oracle(T, ctx, small):
     T4 = orc.tensor_template(small["tn"], small["Q"], n, dprime=4)
     Co = orc.tensor_field(small["g"], small["wmap"], T4)
     flat = Co.reshape(K, -1)
-    idx = rng.choice(flat.shape[1], 120, replace=False)
+    idx = rng.choice(flat.shape[1], n_vox, replace=False)
     Cs = np.ascontiguousarray(flat[:, idx]).reshape(K, 1, 1, -1)
     _, lam, u = T.extract(ctx, d, cuda(Cs), starts=cuda(starts))
     lg, ug = host(lam).ravel(), host(u).reshape(-1, 4)
@@ -463,5 +465,5 @@ def test_quaternion_orientation_matches_oracle(T, ctx, small):
         cls, info = classify_orientation(v, n, lg[j], ug[j], lam_o, u_o, max(orc.score(v, n, 4), med))
         assert cls is not None, (j, info)
         counts[cls] += 1
-    print(f"[quaternion orientation 120 voxels] {counts}", flush=True)
+    print(f"[quaternion orientation n={n}, {n_vox} voxels] {counts}", flush=True)
     assert counts["agree"] >= 0.8 * len(idx)

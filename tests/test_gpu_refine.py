@@ -118,3 +118,49 @@ def test_refine_matches_oracle_alg3():
             assert np.array_equal(gpu["pos"][i], cpos)
             recovered += 1
     assert recovered >= 1
+
+
+def test_refine_degree6_peaks_match_oracle():
+    """ttm_refine at degree 6 (K = 84 components, d' = 4): at each peak's own
+    voxel the rotation is classified against the oracle's converged multistart
+    answer on the oracle's field (a wrong field or orientation fails it), and
+    the LNCC of the peak and of the chosen voxel, each at the GPU's rotation,
+    match the oracle's real-space LNCC within 1e-4."""
+    require_gpu()
+    from paper_2408_02398_amd import ttm
+    ctx = ttm.Context(0)
+    n, L, r, N, rs = 6, 12, 5.0, 32, 2.0
+    print("[refine n=6]", flush=True)
+    wl = synth.make_tomogram("refine6", (40, 40, 40), L=L, n_blobs=3, n_copies=2, min_sep=14,
+                             mask_radius=r, degree=n, seed=9, snr=None, wedge=False,
+                             copy_amplitude=3.0)
+    Q = synth.rotation_samples(10)
+    d = ttm.make_desc(n, L, r, dprime=4)
+    Tg, tng = ttm.build_tensor(ctx, d, cuda(wl.template), cuda(Q))
+    spec = ttm.template_spectra(ctx, d, Tg, N)
+    st4 = synth.start_vectors(count=32, dim=4)
+    eng = ttm.Engine(ctx, d, spec, N, wl.volume.shape, None, orient=False)
+    res = eng.run(cuda(wl.volume), top_p=2)
+    peaks = res.peaks.clone()
+    out = ttm.refine(ctx, d, res.g, res.w, Tg, tng, peaks, cuda(st4), r_s=rs)
+    torch.cuda.synchronize()
+    gpu = {k: v.cpu().numpy() for k, v in out.items()}
+    g = orc.prefilter_volume(wl.volume)
+    m = orc.ball_mask(L, r)
+    wm = orc.local_normalization(g, m)
+    tn = orc.normalize_template(wl.template, r)
+    T4 = orc.tensor_template(tn, Q, n, dprime=4)
+    g2 = orc.volume_g2_mean(g)
+    pk = peaks.cpu().numpy().astype(np.int64)
+    for i in range(len(pk)):
+        Cv = orc.field_at(orc.patches_at(g, [pk[i]], L), m, T4, g2)[1][0]
+        lam_o, u_o, *_ = orc.orient_multistart(Cv, n, st4.astype(np.float64))
+        qg = gpu["quat_peak"][i]
+        lam_g = sym.inner_power(Cv, qg / np.linalg.norm(qg), n)
+        cls, info = classify_orientation(Cv, n, lam_g, qg, lam_o, u_o, orc.score(Cv, n, 4))
+        print(f"[refine n=6] peak {pk[i]}: {cls}; lncc peak {gpu['lncc_peak'][i]:.5f}, "
+              f"chosen {gpu['pos'][i]} lncc {gpu['lncc'][i]:.5f}", flush=True)
+        assert cls is not None, (i, info)
+        assert abs(gpu["lncc_peak"][i] - orc.lncc_at(g, wm, tn, pk[i], qg)) < 1e-4
+        assert abs(gpu["lncc"][i] - orc.lncc_at(g, wm, tn, gpu["pos"][i], gpu["quat"][i])) < 1e-4
+        assert gpu["lncc"][i] >= gpu["lncc_peak"][i]
