@@ -26,7 +26,7 @@
  *   K = binom(n+3,3), alpha = (aw, ax, ay, az) in graded-lex order) is
  *   accepted by every entry point; its orientation is a unit quaternion
  *   (w, x, y, z), 4 floats per voxel, from the multistart search at degree
- *   2..6 (the learned start is d' = 3 only).
+ *   2..6, or from the learned start at degree 2 and 4.
  * - Template: cubic L^3, centre c = L/2 (integer division) on every axis,
  *   binary ball mask m(p) = [|p - c|^2 <= r^2].
  * - Valid region of a volume of extent D along an axis: voxels x with
@@ -251,13 +251,16 @@ typedef struct {
  * work queue, so a slow run does not hold up other voxels.
  * Learned start (TTM_START_MLP): per wavefront of 64 voxels the network
  * (ttm_mlp_train_step) maps x = sqrt(mu_a) C_a / ||C||_F to a start direction
- * on the BF16 matrix cores; SS-HOPM runs from it, then the Newton polish.
- * Voxels whose
- * result is not converged, has lambda < fallback_kappa * ||C||_F, or is
- * beaten by the value of <C, s^n> at one of the fixed starts s (SS-HOPM never
- * lowers lambda, so the multistart answer is then higher) are queued for the
- * multistart search above; the better of the two answers is kept.  Requires
- * lambda and dir.
+ * on the BF16 matrix cores.  d' = 3: up to five guarded Newton steps from it,
+ * else SS-HOPM from it and the Newton polish; d' = 4: SS-HOPM from it and the
+ * Newton polish.  The end point must then be certified near a local maximum
+ * (tangent gradient <= 3e-5 with no tangent-Hessian eigenvalue above 1e-3, or
+ * a negative definite tangent Hessian and a Newton step <= 0.01, after up to
+ * four more guarded Newton steps).  Voxels whose result is not converged, not
+ * certified, has lambda < fallback_kappa * ||C||_F, or is beaten by the value
+ * of <C, s^n> at one of the fixed starts s (SS-HOPM never lowers lambda, so
+ * the multistart answer is then higher) are queued for the multistart search
+ * above; the better of the two answers is kept.  Requires lambda and dir.
  */
 int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
                 const int32_t box_size[3], const ttm_extract_opts* opts, float* score,
@@ -350,21 +353,25 @@ int ttm_extract_batch(ttm_ctx* ctx, const ttm_desc* desc, const ttm_extract_item
                       size_t ws_bytes, void* stream);
 
 /*
- * Learned start network (a seed for the orientation search of Sec. 3.1):
- * x (K <= 32 features, zero padded) -> 64 -> relu -> 64 -> relu -> 3, BF16
- * weights, FP32 accumulation, activations rounded to BF16.
- * FP32 master parameters (ttm_mlp_param_count() floats, layout W1[32][64],
- * b1[64], W2[64][64], b2[64], W3[64][16], b3[16]; rows of W1 beyond K and
- * columns of W3 beyond 3 are kept 0); packed inference copy of
- * ttm_mlp_packed_bytes() bytes.
+ * Learned start network (a seed for the orientation search of Sec. 3.1), for
+ * d' = 3 at degree 2, 4, 6 and d' = 4 at degree 2, 4:
+ * x (K features, zero padded to kin = 32 when K <= 32, else 48) -> 64 -> relu
+ * -> 64 -> relu -> d', BF16 weights, FP32 accumulation, activations rounded
+ * to BF16.  FP32 master parameters (ttm_mlp_param_count(desc) floats, layout
+ * W1[kin][64], b1[64], W2[64][64], b2[64], W3[64][16], b3[16]; rows of W1
+ * beyond K and columns of W3 beyond d' are kept 0); packed inference copy of
+ * ttm_mlp_packed_bytes(desc) bytes.  Both return 0 for a form or degree
+ * without a learned start.
  */
-size_t ttm_mlp_param_count(void);
-size_t ttm_mlp_packed_bytes(void);
-/* packed = BF16 fragment-ordered copy of params (device -> device). */
-int ttm_mlp_pack(ttm_ctx* ctx, const float* params, void* packed, void* stream);
+size_t ttm_mlp_param_count(const ttm_desc* desc);
+size_t ttm_mlp_packed_bytes(const ttm_desc* desc);
+/* packed = BF16 fragment-ordered copy of params (device -> device), for the
+ * network of desc's form and degree. */
+int ttm_mlp_pack(ttm_ctx* ctx, const ttm_desc* desc, const float* params, void* packed,
+                 void* stream);
 /*
- * One training step on B pairs (d' = 3): C device B x K raw tensors (row per
- * sample), targets device B x 3 directions.  Loss mean(1 - (u.t/|t|)^2), u =
+ * One training step on B pairs: C device B x K raw tensors (row per sample),
+ * targets device B x d' directions (axes, or quaternions at d' = 4).  Loss mean(1 - (u.t/|t|)^2), u =
  * y/|y| (sign invariant).  Adam (beta 0.9, 0.999, eps 1e-8, bias corrected,
  * step >= 1) on params with moments adam_m, adam_v (device, param_count
  * floats each) when lr > 0.  Optional outputs: packed (updated inference

@@ -122,10 +122,15 @@ def predict(p: dict, C: np.ndarray, n: int, d: int = 3) -> np.ndarray:
     return y / np.linalg.norm(y, axis=1, keepdims=True)
 
 
+def padded_inputs(k_in: int) -> int:
+    """Rows of W1 in the kernels' master layout: 32 for k_in <= 32, else 48."""
+    return 32 if k_in <= 32 else 48
+
+
 def pad_params(p: dict, k_in: int, d_out: int = 3) -> np.ndarray:
-    """Flatten to the kernels' master layout: W1[32][64], b1[64], W2[64][64], b2[64],
-    W3[64][16], b3[16] (padding rows / columns zero)."""
-    W1 = np.zeros((32, HIDDEN))
+    """Flatten to the kernels' master layout: W1[kin][64] (kin = padded_inputs),
+    b1[64], W2[64][64], b2[64], W3[64][16], b3[16] (padding rows / columns zero)."""
+    W1 = np.zeros((padded_inputs(k_in), HIDDEN))
     W1[:k_in] = p["W1"]
     W3 = np.zeros((HIDDEN, 16))
     W3[:, :d_out] = p["W3"]
@@ -137,7 +142,8 @@ def pad_params(p: dict, k_in: int, d_out: int = 3) -> np.ndarray:
 def unpad_params(flat: np.ndarray, k_in: int, d_out: int = 3) -> dict:
     flat = np.asarray(flat, dtype=np.float64)
     o = 0
-    W1 = flat[o:o + 32 * HIDDEN].reshape(32, HIDDEN)[:k_in]; o += 32 * HIDDEN
+    kin = padded_inputs(k_in)
+    W1 = flat[o:o + kin * HIDDEN].reshape(kin, HIDDEN)[:k_in]; o += kin * HIDDEN
     b1 = flat[o:o + HIDDEN]; o += HIDDEN
     W2 = flat[o:o + HIDDEN * HIDDEN].reshape(HIDDEN, HIDDEN); o += HIDDEN * HIDDEN
     b2 = flat[o:o + HIDDEN]; o += HIDDEN
@@ -150,7 +156,9 @@ def orient_learned(Cv: np.ndarray, n: int, p: dict, starts: np.ndarray, kappa: f
                    tol: float = 1e-5, max_iter: int = 500, bf16: bool = True,
                    detail: bool = False, newton_first: int = 5, u0: np.ndarray | None = None,
                    polish: int = 2, certify: float = 1e-2):
-    """Orientation with the learned start and its multistart fallback (d' = 3).
+    """Orientation with the learned start and its multistart fallback, for the
+    axis form (d' = 3) and the quaternion form (d' = 4; d' is the starts'
+    dimension, and the network has d' outputs).
 
     The learned start replaces the paper's seeds of SS-HOPM (Sec. 3.1); its
     search parameters (tol, max_iter, newton_first, polish, certify and the
@@ -160,7 +168,8 @@ def orient_learned(Cv: np.ndarray, n: int, p: dict, starts: np.ndarray, kappa: f
 
     1. u0 = y / |y| from the network (fixed start 0 where y = 0, which also
        forces the fallback);
-    2. up to ``newton_first`` Riemannian Newton steps (ttm.newton_ascent); if
+    2. up to ``newton_first`` Riemannian Newton steps (ttm.newton_ascent; the
+       quaternion form's learned start takes none); if
        they do not converge, SS-HOPM from u0 with the unfolding shift until
        |delta lambda| <= tol or max_iter updates, then ``polish`` Newton steps
        (ttm.newton_polish); "converged" is the outcome of the search that ran
@@ -187,21 +196,23 @@ def orient_learned(Cv: np.ndarray, n: int, p: dict, starts: np.ndarray, kappa: f
     probe how the answer depends on the start.
     """
     from . import ttm
-    cn = float(sym.frobenius(Cv, n, 3))
+    starts = np.asarray(starts, dtype=np.float64)
+    d = starts.shape[1]
+    cn = float(sym.frobenius(Cv, n, d))
     if cn == 0.0:
-        out = (0.0, np.zeros(3), False)
-        return out + ({"lam_learned": 0.0, "u_learned": np.zeros(3), "beat_gap": -np.inf,
+        out = (0.0, np.zeros(d), False)
+        return out + ({"lam_learned": 0.0, "u_learned": np.zeros(d), "beat_gap": -np.inf,
                        "kappa_gap": np.inf, "cert_step": 0.0, "converged": True, "lams": None,
                        "us": None},) if detail else out
     forced = False
     if u0 is None:
-        y, _ = forward(p, features(Cv[None, :], n), bf16=bf16)
+        y, _ = forward(p, features(Cv[None, :], n, d), bf16=bf16)
         y = y[0]
         ny = np.linalg.norm(y)
         forced = not ny > 0
         u0 = starts[0] / np.linalg.norm(starts[0]) if forced else y / ny
     Cu = np.asarray(Cv, dtype=np.float64) / cn
-    alpha = ttm.unfolding_shift(Cu, n, 3)
+    alpha = ttm.unfolding_shift(Cu, n, d)
     u, lam, conv = ttm.newton_ascent(Cu, n, u0, newton_first, tol)
     if not conv:
         lam, u, _, conv = ttm.sshopm(Cu, n, u0, alpha, tol, max_iter)

@@ -84,9 +84,9 @@ SIGNATURES = {
                              vp]),
     "ttm_extract_batch": (C.c_int, [vp, DP, vp, C.c_int, C.c_uint64, C.c_int, C.POINTER(ExtractOpts),
                                     vp, vp, C.c_size_t, vp]),
-    "ttm_mlp_param_count": (C.c_size_t, []),
-    "ttm_mlp_packed_bytes": (C.c_size_t, []),
-    "ttm_mlp_pack": (C.c_int, [vp, vp, vp, vp]),
+    "ttm_mlp_param_count": (C.c_size_t, [DP]),
+    "ttm_mlp_packed_bytes": (C.c_size_t, [DP]),
+    "ttm_mlp_pack": (C.c_int, [vp, DP, vp, vp, vp]),
     "ttm_mlp_train_step": (C.c_int, [vp, DP, vp, vp, C.c_int, vp, vp, vp, C.c_int, C.c_float, vp,
                                      vp, vp, vp, C.c_size_t, vp]),
     "ttm_find_peaks": (C.c_int, [vp, vp, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int32),

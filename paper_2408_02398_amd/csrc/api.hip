@@ -402,7 +402,11 @@ bool valid_desc(const ttm_desc* d) {
   return true;
 }
 
-constexpr int kMlpInMax = kMlpIn;
+// Forms and degrees the learned start is built for (K <= kMlpInMax inputs).
+bool mlp_form_ok(const ttm_desc* d) {
+  return (d->dprime == 3 && (d->degree == 2 || d->degree == 4 || d->degree == 6)) ||
+         (d->dprime == 4 && (d->degree == 2 || d->degree == 4));
+}
 
 bool fft_ok(int N) { return N == 32 || N == 64 || N == 128 || N == 256 || N == 512; }
 
@@ -843,9 +847,10 @@ int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
   }
   if (mode & 2) {
     if (desc->dprime == 3 ? (desc->degree < 2 || desc->degree > 6)
-                          : (desc->degree < 2 || desc->degree > 6 || (mode & 4))) {
-      set_error("ttm_extract: orientation needs degree 2..6 at d'=3, or degree 2..6 and the "
-                "multistart search at d'=4");
+                          : (desc->degree < 2 || desc->degree > 6 ||
+                             ((mode & 4) && (desc->degree > 4 || (mode & 8))))) {
+      set_error("ttm_extract: orientation needs degree 2..6 (d'=3, or d'=4 with the multistart "
+                "search); the learned start at d'=4 needs degree 2 or 4 and no start-only mode");
       return TTM_EUNSUPPORTED;
     }
     if (!opts->starts || opts->n_starts < 1 || opts->n_starts > 64 || opts->max_iter < 1 ||
@@ -860,8 +865,8 @@ int ttm_extract(ttm_ctx* ctx, const ttm_desc* desc, const void* C, int in_dtype,
         set_error("ttm_extract: learned start needs mlp, lambda, dir and a kappa");
         return TTM_EINVAL;
       }
-      if (ncomp(desc->degree, 3) > kMlpInMax) {
-        set_error("ttm_extract: learned start takes at most %d components", kMlpInMax);
+      if (!mlp_form_ok(desc)) {
+        set_error("ttm_extract: no learned start for d'=%d, degree %d", desc->dprime, desc->degree);
         return TTM_EUNSUPPORTED;
       }
     }
@@ -1049,16 +1054,28 @@ int ttm_extract_batch(ttm_ctx* ctx, const ttm_desc* desc, const ttm_extract_item
   return launch_extract(desc->degree, a, s);
 }
 
-size_t ttm_mlp_param_count(void) { return kMlpParams; }
-size_t ttm_mlp_packed_bytes(void) { return kMlpPackedBytes; }
+size_t ttm_mlp_param_count(const ttm_desc* desc) {
+  if (!valid_desc(desc) || !mlp_form_ok(desc)) return 0;
+  return (size_t)mlp_rt_for(ncomp(desc->degree, desc->dprime)).params;
+}
+size_t ttm_mlp_packed_bytes(const ttm_desc* desc) {
+  if (!valid_desc(desc) || !mlp_form_ok(desc)) return 0;
+  return (size_t)mlp_rt_for(ncomp(desc->degree, desc->dprime)).packed;
+}
 
-int ttm_mlp_pack(ttm_ctx* ctx, const float* params, void* packed, void* stream) {
-  if (!ctx || !params || !packed) {
-    set_error("ttm_mlp_pack: null pointer");
+int ttm_mlp_pack(ttm_ctx* ctx, const ttm_desc* desc, const float* params, void* packed,
+                 void* stream) {
+  if (!ctx || !params || !packed || !valid_desc(desc)) {
+    set_error("ttm_mlp_pack: null pointer or invalid descriptor");
     return TTM_EINVAL;
   }
+  if (!mlp_form_ok(desc)) {
+    set_error("ttm_mlp_pack: no learned start for d'=%d, degree %d", desc->dprime, desc->degree);
+    return TTM_EUNSUPPORTED;
+  }
   TTM_HIP(hipSetDevice(ctx->device));
-  return mlp_pack(params, static_cast<unsigned char*>(packed), static_cast<hipStream_t>(stream));
+  return mlp_pack(ncomp(desc->degree, desc->dprime), params, static_cast<unsigned char*>(packed),
+                  static_cast<hipStream_t>(stream));
 }
 
 int ttm_mlp_train_step(ttm_ctx* ctx, const ttm_desc* desc, const float* Cin, const float* targets,
@@ -1066,8 +1083,8 @@ int ttm_mlp_train_step(ttm_ctx* ctx, const ttm_desc* desc, const float* Cin, con
                        void* packed, float* loss_out, float* grads_out, void* ws, size_t ws_bytes,
                        void* stream) {
   if (!ctx || !valid_desc(desc)) return TTM_EINVAL;
-  if (desc->dprime != 3 || desc->degree < 2 || desc->degree > 6) {
-    set_error("ttm_mlp_train_step: needs d'=3 and degree 2..6");
+  if (!mlp_form_ok(desc)) {
+    set_error("ttm_mlp_train_step: needs d'=3 at degree 2, 4 or 6, or d'=4 at degree 2 or 4");
     return TTM_EUNSUPPORTED;
   }
   if (!Cin || !targets || !params || !loss_out || !ws || B < 1 ||
@@ -1081,7 +1098,7 @@ int ttm_mlp_train_step(ttm_ctx* ctx, const ttm_desc* desc, const float* Cin, con
     return TTM_EWORKSPACE;
   }
   TTM_HIP(hipSetDevice(ctx->device));
-  return mlp_train_step(desc->degree, Cin, targets, B, params, adam_m, adam_v, step, lr,
+  return mlp_train_step(desc->degree, desc->dprime, Cin, targets, B, params, adam_m, adam_v, step, lr,
                         static_cast<unsigned char*>(packed), loss_out, grads_out, ws,
                         static_cast<hipStream_t>(stream));
 }

@@ -153,10 +153,10 @@ int find_peaks_async(const float* score, int nz, int ny, int nx, const int32_t l
 
 // Learned start training (mlp.hip).
 size_t mlp_train_workspace(int B);
-int mlp_train_step(int degree, const float* Cin, const float* T, int B, float* params, float* adam_m,
-                   float* adam_v, int step, float lr, unsigned char* packed, float* loss_out,
-                   float* grads_out, void* ws, hipStream_t s);
-int mlp_pack(const float* params, unsigned char* packed, hipStream_t s);
+int mlp_train_step(int degree, int dprime, const float* Cin, const float* T, int B, float* params,
+                   float* adam_m, float* adam_v, int step, float lr, unsigned char* packed,
+                   float* loss_out, float* grads_out, void* ws, hipStream_t s);
+int mlp_pack(int K, const float* params, unsigned char* packed, hipStream_t s);
 
 // Zero-fill with a kernel (graph-capture friendly, unlike memset nodes).
 void fill_zero(void* p, size_t bytes, hipStream_t s);

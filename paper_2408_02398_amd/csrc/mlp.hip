@@ -2,11 +2,12 @@
 // accumulation and FP32 master weights with Adam), and packing of the
 // inference parameters.
 //
-// One training step on a batch of B (tensor, target direction) pairs:
-//   X  = features(C)                         B x 32
+// One training step on a batch of B (tensor, target direction) pairs, for the
+// network of kin = 32 (K <= 32) or 48 (K <= 48) inputs and d' outputs:
+//   X  = features(C)                         B x kin
 //   Z1 = X W1 + b1,  H1 = bf16(relu Z1)      B x 64
 //   Z2 = H1 W2 + b2, H2 = bf16(relu Z2)      B x 64
-//   Y  = H2 W3 + b3                          B x 16 (3 used)
+//   Y  = H2 W3 + b3                          B x 16 (d' used)
 //   L  = mean_b 1 - (y_b . t_b / |y_b||t_b|)^2
 //   dY, then dW3 = H2^T dY, dZ2 = (dY W3^T) * [Z2 > 0], dW2 = H1^T dZ2,
 //   dZ1 = (dZ2 W2^T) * [Z1 > 0], dW1 = X^T dZ1, bias gradients = column sums,
@@ -90,47 +91,67 @@ __global__ void k_splitk_sum(const float* __restrict__ part, int nsplit, size_t 
   out[i] = s;
 }
 
-// x = sqrt(mu_a) C_a / ||C||_F, zero padded to 32 columns; C is B x K (row per sample).
-template <int N>
-__global__ void k_features(const float* __restrict__ Cin, int B, float* __restrict__ X) {
-  constexpr int K = ncomp3(N);
-  constexpr Sym3<N> sy{};
+// x = sqrt(mu_a) C_a / ||C||_F, zero padded to kin columns; C is B x K (row
+// per sample); the weights mu of the d' = 3 (DP = 3) or quaternion (DP = 4) form.
+template <int N, int DP>
+__global__ void k_features(const float* __restrict__ Cin, int B, int kin, float* __restrict__ X) {
+  constexpr int K = DP == 3 ? ncomp3(N) : ncomp4(N);
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   float c[K];
   float f2 = 0.0f;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    c[k] = Cin[(size_t)b * K + k] * sqrtf(sy.mu[k]);
+    float mu;
+    if constexpr (DP == 3) {
+      constexpr Sym3<N> sy{};
+      mu = sy.mu[k];
+    } else {
+      constexpr Sym4<N> sy{};
+      mu = sy.mu[k];
+    }
+    c[k] = Cin[(size_t)b * K + k] * sqrtf(mu);
     f2 = fmaf(c[k], c[k], f2);
   }
   const float inv = f2 > 0.0f ? 1.0f / sqrtf(f2) : 0.0f;
+  for (int k = 0; k < kin; ++k) X[(size_t)b * kin + k] = 0.0f;
 #pragma unroll
-  for (int k = 0; k < kMlpIn; ++k) X[(size_t)b * kMlpIn + k] = k < K ? c[k] * inv : 0.0f;
+  for (int k = 0; k < K; ++k) X[(size_t)b * kin + k] = c[k] * inv;
 }
 
-// dL/dY for L = mean 1 - (u.t)^2, u = y/|y|: dY = -2 c (t - c u) / (|y| B); per-block loss sums.
+// dL/dY for L = mean 1 - (u.t)^2, u = y/|y| over the first dout outputs:
+// dY = -2 c (t - c u) / (|y| B); per-block loss sums.
 __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ Y, const float* __restrict__ T,
-                                              int B, float* __restrict__ dY,
+                                              int B, int dout, float* __restrict__ dY,
                                               float* __restrict__ part) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   float l = 0.0f;
   if (b < B) {
-    const float y0 = Y[(size_t)b * kMlpOut], y1 = Y[(size_t)b * kMlpOut + 1], y2 = Y[(size_t)b * kMlpOut + 2];
-    float t0 = T[3 * b], t1 = T[3 * b + 1], t2 = T[3 * b + 2];
-    const float tn = 1.0f / sqrtf(t0 * t0 + t1 * t1 + t2 * t2);
-    t0 *= tn; t1 *= tn; t2 *= tn;
-    const float ny = sqrtf(y0 * y0 + y1 * y1 + y2 * y2);
+    float y[4], t[4], tt = 0.0f, yy = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      y[i] = i < dout ? Y[(size_t)b * kMlpOut + i] : 0.0f;
+      t[i] = i < dout ? T[(size_t)dout * b + i] : 0.0f;
+      tt = fmaf(t[i], t[i], tt);
+      yy = fmaf(y[i], y[i], yy);
+    }
+    const float tn = 1.0f / sqrtf(tt);
+    const float ny = sqrtf(yy);
     const float iy = ny > 0.0f ? 1.0f / ny : 0.0f;
-    const float u0 = y0 * iy, u1 = y1 * iy, u2 = y2 * iy;
-    const float c = u0 * t0 + u1 * t1 + u2 * t2;
+    float u[4], c = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      t[i] *= tn;
+      u[i] = y[i] * iy;
+      c = fmaf(u[i], t[i], c);
+    }
     l = 1.0f - c * c;
     const float s = -2.0f * c * iy / (float)B;
     float* d = dY + (size_t)b * kMlpOut;
-    d[0] = s * (t0 - c * u0);
-    d[1] = s * (t1 - c * u1);
-    d[2] = s * (t2 - c * u2);
-    for (int k = 3; k < kMlpOut; ++k) d[k] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (i < dout) d[i] = s * (t[i] - c * u[i]);
+    for (int k = dout; k < kMlpOut; ++k) d[k] = 0.0f;
   }
   __shared__ float red[256];
   red[threadIdx.x] = l;
@@ -168,14 +189,14 @@ __global__ void k_sum(const float* __restrict__ part, int n, float scale, float*
 
 // Adam with bias correction on the FP32 masters; padded rows / columns stay 0.
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-                       float* __restrict__ v, int n_params, float lr, float b1, float b2, float eps,
+                       float* __restrict__ v, MlpRt r, float lr, float b1, float b2, float eps,
                        float bc1, float bc2, int K, int dout) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_params) return;
+  if (i >= r.params) return;
   bool pad = false;
-  if (i < kOffB1) pad = (i / kMlpHid) >= K;                               // W1 rows >= K
-  else if (i >= kOffW3 && i < kOffB3) pad = ((i - kOffW3) % kMlpOut) >= dout;
-  else if (i >= kOffB3) pad = (i - kOffB3) >= dout;
+  if (i < r.off_b1) pad = (i / kMlpHid) >= K;                               // W1 rows >= K
+  else if (i >= r.off_w3 && i < r.off_b3) pad = ((i - r.off_w3) % kMlpOut) >= dout;
+  else if (i >= r.off_b3) pad = (i - r.off_b3) >= dout;
   if (pad) {
     p[i] = 0.0f;
     m[i] = 0.0f;
@@ -191,21 +212,22 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
 }
 
 // FP32 masters -> BF16 fragment-ordered weights + FP32 biases.
-__global__ void k_pack(const float* __restrict__ p, unsigned char* __restrict__ out) {
+__global__ void k_pack(const float* __restrict__ p, MlpRt r, unsigned char* __restrict__ out) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  // fragments: W1 8, W2 16, W3 4 -> 28 fragments x 64 lanes x 4 values
-  if (t < 28 * 64) {
+  // fragments: W1 4 KT, W2 16, W3 4, each 64 lanes x 4 values
+  const int nw12 = r.w1_frags + 16;
+  if (t < (nw12 + 4) * 64) {
     const int frag = t / 64, lane = t % 64, r16 = lane & 15, q = lane >> 4;
     const float* W;
     int ld, s, nt, off, f;
-    if (frag < 8) {
-      W = p + kOffW1; ld = kMlpHid; f = frag; off = kPkW1;
-    } else if (frag < 24) {
-      W = p + kOffW2; ld = kMlpHid; f = frag - 8; off = kPkW2;
+    if (frag < r.w1_frags) {
+      W = p; ld = kMlpHid; f = frag; off = 0;
+    } else if (frag < nw12) {
+      W = p + r.off_w2; ld = kMlpHid; f = frag - r.w1_frags; off = r.pk_w2;
     } else {
-      W = p + kOffW3; ld = kMlpOut; f = frag - 24; off = kPkW3;
+      W = p + r.off_w3; ld = kMlpOut; f = frag - nw12; off = r.pk_w3;
     }
-    if (frag < 24) {
+    if (frag < nw12) {
       s = f / 4; nt = f % 4;
     } else {
       s = f; nt = 0;
@@ -214,10 +236,15 @@ __global__ void k_pack(const float* __restrict__ p, unsigned char* __restrict__ 
     for (int j = 0; j < 4; ++j) o[j] = bf16_bits(W[(16 * s + 4 * q + j) * ld + 16 * nt + r16]);
   }
   if (t < kMlpHid) {
-    reinterpret_cast<float*>(out + kPkB1)[t] = p[kOffB1 + t];
-    reinterpret_cast<float*>(out + kPkB2)[t] = p[kOffB2 + t];
+    reinterpret_cast<float*>(out + r.pk_b1)[t] = p[r.off_b1 + t];
+    reinterpret_cast<float*>(out + r.pk_b2)[t] = p[r.off_b2 + t];
   }
-  if (t < kMlpOut) reinterpret_cast<float*>(out + kPkB3)[t] = p[kOffB3 + t];
+  if (t < kMlpOut) reinterpret_cast<float*>(out + r.pk_b3)[t] = p[r.off_b3 + t];
+}
+
+void launch_pack(const float* params, const MlpRt& r, unsigned char* packed, hipStream_t s) {
+  const int threads = (r.w1_frags + 20) * 64;
+  hipLaunchKernelGGL(k_pack, dim3((threads + 255) / 256), dim3(256), 0, s, params, r, packed);
 }
 
 template <bool TA, bool TB>
@@ -249,19 +276,22 @@ constexpr int kSplit = 64;
 }  // namespace
 
 size_t mlp_train_workspace(int B) {
-  // X (32) + Z1, H1, Z2, H2, dZ1, dZ2 (64 each) + Y, dY (16 each) per sample,
+  // X (up to 48) + Z1, H1, Z2, H2, dZ1, dZ2 (64 each) + Y, dY (16 each) per sample,
   // gradient block, loss partials
   // + split-K partial tiles (kSplit x 64 x 64) + column-sum partials
-  return ((size_t)B * (32 + 6 * 64 + 2 * 16) + kMlpParams + (B + 255) / 256 + 64 +
+  return ((size_t)B * (kMlpInMax + 6 * 64 + 2 * 16) + MlpLayout<3>::params + (B + 255) / 256 + 64 +
           (size_t)kSplit * 64 * 64 + (size_t)((B + 255) / 256) * 64) * 4 + 1024;
 }
 
-int mlp_train_step(int degree, const float* Cin, const float* T, int B, float* params, float* adam_m,
-                   float* adam_v, int step, float lr, unsigned char* packed, float* loss_out,
-                   float* grads_out, void* ws, hipStream_t s) {
+int mlp_train_step(int degree, int dprime, const float* Cin, const float* T, int B, float* params,
+                   float* adam_m, float* adam_v, int step, float lr, unsigned char* packed,
+                   float* loss_out, float* grads_out, void* ws, hipStream_t s) {
+  const int K = dprime == 3 ? ncomp3(degree) : ncomp4(degree);
+  const MlpRt r = mlp_rt_for(K);
+  const int kin = r.kin, dout = dprime;
   float* w = static_cast<float*>(ws);
   float* X = w;
-  float* Z1 = X + (size_t)B * 32;
+  float* Z1 = X + (size_t)B * kin;
   float* H1 = Z1 + (size_t)B * 64;
   float* Z2 = H1 + (size_t)B * 64;
   float* H2 = Z2 + (size_t)B * 64;
@@ -270,51 +300,53 @@ int mlp_train_step(int degree, const float* Cin, const float* T, int B, float* p
   float* Y = dZ2 + (size_t)B * 64;
   float* dY = Y + (size_t)B * 16;
   float* G = dY + (size_t)B * 16;
-  float* part = G + kMlpParams;
+  float* part = G + r.params;
   const int nb = (B + 255) / 256;
   float* skw = part + nb + 64;                         // split-K partials
   float* cpart = skw + (size_t)kSplit * 64 * 64;       // column-sum partials
-  switch (degree) {
-    case 2: hipLaunchKernelGGL(k_features<2>, dim3(nb), dim3(256), 0, s, Cin, B, X); break;
-    case 4: hipLaunchKernelGGL(k_features<4>, dim3(nb), dim3(256), 0, s, Cin, B, X); break;
-    case 6: hipLaunchKernelGGL(k_features<6>, dim3(nb), dim3(256), 0, s, Cin, B, X); break;
-    default: set_error("mlp: degree %d not built", degree); return -4;
+  switch (dprime * 10 + degree) {
+    case 32: hipLaunchKernelGGL((k_features<2, 3>), dim3(nb), dim3(256), 0, s, Cin, B, kin, X); break;
+    case 34: hipLaunchKernelGGL((k_features<4, 3>), dim3(nb), dim3(256), 0, s, Cin, B, kin, X); break;
+    case 36: hipLaunchKernelGGL((k_features<6, 3>), dim3(nb), dim3(256), 0, s, Cin, B, kin, X); break;
+    case 42: hipLaunchKernelGGL((k_features<2, 4>), dim3(nb), dim3(256), 0, s, Cin, B, kin, X); break;
+    case 44: hipLaunchKernelGGL((k_features<4, 4>), dim3(nb), dim3(256), 0, s, Cin, B, kin, X); break;
+    default: set_error("mlp: degree %d not built for d'=%d", degree, dprime); return -4;
   }
-  const float* W1 = params + kOffW1;
-  const float* W2 = params + kOffW2;
-  const float* W3 = params + kOffW3;
+  const float* W1 = params;
+  const float* W2 = params + r.off_w2;
+  const float* W3 = params + r.off_w3;
   // forward
-  gemm<false, false>(X, 32, W1, 64, Z1, 64, B, 64, 32, 2, params + kOffB1, H1, nullptr, s);
-  gemm<false, false>(H1, 64, W2, 64, Z2, 64, B, 64, 64, 2, params + kOffB2, H2, nullptr, s);
-  gemm<false, false>(H2, 64, W3, 16, Y, 16, B, 16, 64, 1, params + kOffB3, nullptr, nullptr, s);
-  hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, s, Y, T, B, dY, part);
+  gemm<false, false>(X, kin, W1, 64, Z1, 64, B, 64, kin, 2, params + r.off_b1, H1, nullptr, s);
+  gemm<false, false>(H1, 64, W2, 64, Z2, 64, B, 64, 64, 2, params + r.off_b2, H2, nullptr, s);
+  gemm<false, false>(H2, 64, W3, 16, Y, 16, B, 16, 64, 1, params + r.off_b3, nullptr, nullptr, s);
+  hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, s, Y, T, B, dout, dY, part);
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(64), 0, s, part, nb, 1.0f / (float)B, loss_out);
   // backward
   const int ns = B >= 2048 ? kSplit : 1;
-  gemm<true, false>(H2, 64, dY, 16, G + kOffW3, 16, 64, 16, B, 0, nullptr, nullptr, nullptr, s, skw, ns);
-  colsum(dY, B, 16, G + kOffB3, cpart, s);
+  gemm<true, false>(H2, 64, dY, 16, G + r.off_w3, 16, 64, 16, B, 0, nullptr, nullptr, nullptr, s, skw, ns);
+  colsum(dY, B, 16, G + r.off_b3, cpart, s);
   gemm<false, true>(dY, 16, W3, 16, dZ2, 64, B, 64, 16, 3, nullptr, nullptr, Z2, s);
-  gemm<true, false>(H1, 64, dZ2, 64, G + kOffW2, 64, 64, 64, B, 0, nullptr, nullptr, nullptr, s, skw, ns);
-  colsum(dZ2, B, 64, G + kOffB2, cpart, s);
+  gemm<true, false>(H1, 64, dZ2, 64, G + r.off_w2, 64, 64, 64, B, 0, nullptr, nullptr, nullptr, s, skw, ns);
+  colsum(dZ2, B, 64, G + r.off_b2, cpart, s);
   gemm<false, true>(dZ2, 64, W2, 64, dZ1, 64, B, 64, 64, 3, nullptr, nullptr, Z1, s);
-  gemm<true, false>(X, 32, dZ1, 64, G + kOffW1, 64, 32, 64, B, 0, nullptr, nullptr, nullptr, s, skw, ns);
-  colsum(dZ1, B, 64, G + kOffB1, cpart, s);
+  gemm<true, false>(X, kin, dZ1, 64, G, 64, kin, 64, B, 0, nullptr, nullptr, nullptr, s, skw, ns);
+  colsum(dZ1, B, 64, G + r.off_b1, cpart, s);
   if (grads_out) {
-    TTM_HIP(hipMemcpyAsync(grads_out, G, kMlpParams * 4, hipMemcpyDeviceToDevice, s));
+    TTM_HIP(hipMemcpyAsync(grads_out, G, (size_t)r.params * 4, hipMemcpyDeviceToDevice, s));
   }
   if (lr > 0.0f) {
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     const float bc1 = 1.0f - powf(b1, (float)step), bc2 = 1.0f - powf(b2, (float)step);
-    hipLaunchKernelGGL(k_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, params, G, adam_m,
-                       adam_v, kMlpParams, lr, b1, b2, eps, bc1, bc2, ncomp3(degree), 3);
+    hipLaunchKernelGGL(k_adam, dim3((r.params + 255) / 256), dim3(256), 0, s, params, G, adam_m,
+                       adam_v, r, lr, b1, b2, eps, bc1, bc2, K, dout);
   }
-  if (packed) hipLaunchKernelGGL(k_pack, dim3(7), dim3(256), 0, s, params, packed);
+  if (packed) launch_pack(params, r, packed, s);
   TTM_HIP(hipGetLastError());
   return 0;
 }
 
-int mlp_pack(const float* params, unsigned char* packed, hipStream_t s) {
-  hipLaunchKernelGGL(k_pack, dim3(7), dim3(256), 0, s, params, packed);
+int mlp_pack(int K, const float* params, unsigned char* packed, hipStream_t s) {
+  launch_pack(params, mlp_rt_for(K), packed, s);
   TTM_HIP(hipGetLastError());
   return 0;
 }

@@ -1,8 +1,9 @@
 // mlp_core.hpp -- BF16 matrix-core (MFMA) building blocks of the learned start.
 //
-// Network: x (K <= 32 features, zero padded) -> 64 -> relu -> 64 -> relu -> 3
-// (output padded to 16).  Weights are BF16, products accumulate in FP32,
-// activations are rounded to BF16 before they feed the next product.
+// Network: x (K features, zero padded to 16 KT: 32 for K <= 32, 48 for
+// K <= 48) -> 64 -> relu -> 64 -> relu -> d' (output padded to 16).  Weights
+// are BF16, products accumulate in FP32, activations are rounded to BF16
+// before they feed the next product.
 //
 // v_mfma_f32_16x16x16_bf16 operand layout (wave64, lane L, j = 0..3):
 //   A (16 x 16, row-major M x K): lane L holds A[L % 16][4 (L / 16) + j]
@@ -17,9 +18,10 @@ namespace ttm {
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kMlpIn = 32;     // padded input width
+constexpr int kMlpIn = 32;     // padded input width of the K <= 32 network
+constexpr int kMlpInMax = 48;  // the widest network (K <= 48)
 constexpr int kMlpHid = 64;
-constexpr int kMlpOut = 16;    // padded output width (3 used)
+constexpr int kMlpOut = 16;    // padded output width (d' used)
 
 // FP32 master parameter layout (floats): W1 [32][64], b1[64], W2 [64][64], b2[64],
 // W3 [64][16], b3[16].  Rows of W1 beyond K and columns of W3 beyond d' are 0.
@@ -44,6 +46,47 @@ constexpr int kPkB1 = kPkW3 + 4 * kFragBytes;
 constexpr int kPkB2 = kPkB1 + kMlpHid * 4;
 constexpr int kPkB3 = kPkB2 + kMlpHid * 4;
 constexpr int kMlpPackedBytes = kPkB3 + kMlpOut * 4;   // 14912
+
+// The same layouts for a network of KT input tiles of 16 (W1 [16 KT][64]:
+// 4 KT fragments); KT = 2 is the layout above.
+template <int KT>
+struct MlpLayout {
+  static constexpr int kin = 16 * KT;
+  static constexpr int off_w1 = 0;
+  static constexpr int off_b1 = off_w1 + kin * kMlpHid;
+  static constexpr int off_w2 = off_b1 + kMlpHid;
+  static constexpr int off_b2 = off_w2 + kMlpHid * kMlpHid;
+  static constexpr int off_w3 = off_b2 + kMlpHid;
+  static constexpr int off_b3 = off_w3 + kMlpHid * kMlpOut;
+  static constexpr int params = off_b3 + kMlpOut;
+  static constexpr int w1_frags = 4 * KT;
+  static constexpr int pk_w1 = 0;
+  static constexpr int pk_w2 = pk_w1 + w1_frags * kFragBytes;
+  static constexpr int pk_w3 = pk_w2 + 16 * kFragBytes;
+  static constexpr int pk_b1 = pk_w3 + 4 * kFragBytes;
+  static constexpr int pk_b2 = pk_b1 + kMlpHid * 4;
+  static constexpr int pk_b3 = pk_b2 + kMlpHid * 4;
+  static constexpr int packed = pk_b3 + kMlpOut * 4;
+};
+static_assert(MlpLayout<2>::params == kMlpParams && MlpLayout<2>::packed == kMlpPackedBytes &&
+                  MlpLayout<2>::pk_b3 == kPkB3 && MlpLayout<2>::off_w3 == kOffW3,
+              "the K <= 32 network is MlpLayout<2>");
+
+// Input tiles of the network for K components.
+__host__ __device__ constexpr int mlp_tiles(int K) { return K <= 32 ? 2 : 3; }
+
+// MlpLayout as run-time values, for the training kernels and the host.
+struct MlpRt {
+  int kt, kin, off_b1, off_w2, off_b2, off_w3, off_b3, params, w1_frags, pk_w2, pk_w3, pk_b1,
+      pk_b2, pk_b3, packed;
+};
+template <int KT>
+__host__ __device__ constexpr MlpRt mlp_rt() {
+  using L = MlpLayout<KT>;
+  return MlpRt{KT, L::kin, L::off_b1, L::off_w2, L::off_b2, L::off_w3, L::off_b3, L::params,
+               L::w1_frags, L::pk_w2, L::pk_w3, L::pk_b1, L::pk_b2, L::pk_b3, L::packed};
+}
+__host__ __device__ constexpr MlpRt mlp_rt_for(int K) { return K <= 32 ? mlp_rt<2>() : mlp_rt<3>(); }
 
 __device__ __forceinline__ unsigned short bf16_bits(float f) {
   unsigned int u = __float_as_uint(f);
@@ -107,22 +150,25 @@ __device__ __forceinline__ void load_mlp_regs(const unsigned char* __restrict__ 
 // Fragments and biases of the packed network read from an LDS copy of it on
 // demand (the same layout as in global memory), for kernels that keep their
 // registers for other work.
-struct MlpLds {
-  const unsigned char* pk;   // LDS copy of the kMlpPackedBytes packed bytes
+template <int KT>
+struct MlpLdsT {
+  using Lay = MlpLayout<KT>;
+  const unsigned char* pk;   // LDS copy of the Lay::packed packed bytes
   int lane;
-  __device__ __forceinline__ bf16x4 w1(int f) const { return load_frag(pk, kPkW1, f, lane); }
-  __device__ __forceinline__ bf16x4 w2(int f) const { return load_frag(pk, kPkW2, f, lane); }
-  __device__ __forceinline__ bf16x4 w3(int f) const { return load_frag(pk, kPkW3, f, lane); }
+  __device__ __forceinline__ bf16x4 w1(int f) const { return load_frag(pk, Lay::pk_w1, f, lane); }
+  __device__ __forceinline__ bf16x4 w2(int f) const { return load_frag(pk, Lay::pk_w2, f, lane); }
+  __device__ __forceinline__ bf16x4 w3(int f) const { return load_frag(pk, Lay::pk_w3, f, lane); }
   __device__ __forceinline__ float b1(int m, int j) const {
-    return reinterpret_cast<const float*>(pk + kPkB1)[16 * m + 4 * (lane >> 4) + j];
+    return reinterpret_cast<const float*>(pk + Lay::pk_b1)[16 * m + 4 * (lane >> 4) + j];
   }
   __device__ __forceinline__ float b2(int m, int j) const {
-    return reinterpret_cast<const float*>(pk + kPkB2)[16 * m + 4 * (lane >> 4) + j];
+    return reinterpret_cast<const float*>(pk + Lay::pk_b2)[16 * m + 4 * (lane >> 4) + j];
   }
   __device__ __forceinline__ float b3(int j) const {
-    return reinterpret_cast<const float*>(pk + kPkB3)[4 * (lane >> 4) + j];
+    return reinterpret_cast<const float*>(pk + Lay::pk_b3)[4 * (lane >> 4) + j];
   }
 };
+using MlpLds = MlpLdsT<2>;
 
 // The same accessors over the registers of MlpRegs.
 struct MlpRegView {
@@ -146,32 +192,36 @@ __device__ __forceinline__ bf16x4 relu_bf16_w(const f32x4& acc, const W& w, int 
   return h;
 }
 
-// Forward pass of one wavefront's 64 voxels (voxel = lane), weights from w.
-//   xs: this wavefront's [64][32] bf16 features in LDS, written by the lanes
-//       and made visible to the wavefront before the call.
-// Returns y (3 floats) of the calling lane's voxel.
-template <class W>
-__device__ __forceinline__ void mlp_forward_w(const unsigned short* xs, const W& w, int lane,
-                                              float& y0, float& y1, float& y2) {
+// Forward pass of one wavefront's 64 voxels (voxel = lane), weights from w,
+// for a network of KT input tiles.
+//   xs: this wavefront's [64][16 KT] bf16 features in LDS, written by the
+//       lanes and made visible to the wavefront before the call.
+// Returns y[0..3] (the first four outputs) of the calling lane's voxel.
+template <int KT, class W>
+__device__ __forceinline__ void mlp_forward_t(const unsigned short* xs, const W& w, int lane,
+                                              float (&y)[4]) {
+  constexpr int kin = 16 * KT;
   const int r16 = lane & 15, q = lane >> 4;
   // B fragments of X^T: lane L holds x[voxel 16 nt + L % 16][feature 16 s + 4 (L/16) + j]
-  bf16x4 xb[2][4];
+  bf16x4 xb[KT][4];
 #pragma unroll
-  for (int s = 0; s < 2; ++s)
+  for (int s = 0; s < KT; ++s)
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) xb[s][nt][j] = (short)xs[(16 * nt + r16) * kMlpIn + 16 * s + 4 * q + j];
-  // layer 1: H1^T (64 x 64) = W1^T (64 x 32) X^T (32 x 64)
+      for (int j = 0; j < 4; ++j) xb[s][nt][j] = (short)xs[(16 * nt + r16) * kin + 16 * s + 4 * q + j];
+  // layer 1: H1^T (64 x 64) = W1^T (64 x 16 KT) X^T (16 KT x 64)
   bf16x4 h1[4][4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    const bf16x4 a0 = w.w1(m), a1 = w.w1(4 + m);
+    bf16x4 a[KT];
+#pragma unroll
+    for (int s = 0; s < KT; ++s) a[s] = w.w1(4 * s + m);
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
       f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-      acc = mfma16(a0, xb[0][nt], acc);
-      acc = mfma16(a1, xb[1][nt], acc);
+#pragma unroll
+      for (int s = 0; s < KT; ++s) acc = mfma16(a[s], xb[s][nt], acc);
       h1[m][nt] = relu_bf16_w(acc, w, 1, m);
     }
   }
@@ -195,20 +245,19 @@ __device__ __forceinline__ void mlp_forward_w(const unsigned short* xs, const W&
   bf16x4 a3[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) a3[s] = w.w3(s);
-  float yv[3][4];
+  float yv[4][4];
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
     f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < 4; ++s) acc = mfma16(a3[s], h2[s][nt], acc);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) yv[i][nt] = acc[i] + w.b3(i);
+    for (int i = 0; i < 4; ++i) yv[i][nt] = acc[i] + w.b3(i);
   }
   // each voxel lane fetches its outputs from lane (voxel % 16) of tile voxel / 16
   const int src = lane & 15, tile = lane >> 4;
-  float y[3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < 4; ++i) {
     float pick = 0.0f;
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
@@ -217,6 +266,14 @@ __device__ __forceinline__ void mlp_forward_w(const unsigned short* xs, const W&
     }
     y[i] = pick;
   }
+}
+
+// The K <= 32 network with three outputs (d' = 3).
+template <class W>
+__device__ __forceinline__ void mlp_forward_w(const unsigned short* xs, const W& w, int lane,
+                                              float& y0, float& y1, float& y2) {
+  float y[4];
+  mlp_forward_t<2>(xs, w, lane, y);
   y0 = y[0];
   y1 = y[1];
   y2 = y[2];

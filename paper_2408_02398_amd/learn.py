@@ -27,7 +27,7 @@ from . import ttm
 @dataclass
 class TrainingSet:
     C: torch.Tensor        # B x K raw tensors
-    u: torch.Tensor        # B x 3 multistart directions
+    u: torch.Tensor        # B x d' multistart directions
     score: torch.Tensor    # B Frobenius scores
 
 
@@ -54,7 +54,7 @@ def collect(ctx, desc, spectra, fft_n, vol: torch.Tensor, starts: torch.Tensor, 
         m = sample.shape[1]
         _, _, u = ttm.extract(ctx, desc, sample.view(K, 1, 1, m), starts=starts)
         Cs.append(sample.t().contiguous())
-        us.append(u.view(m, 3).clone())
+        us.append(u.view(m, desc.dprime).clone())
         ss.append(sflat[idx].clone())
     return TrainingSet(torch.cat(Cs), torch.cat(us), torch.cat(ss))
 
@@ -87,7 +87,9 @@ def evaluate(ctx, desc, net, data: TrainingSet, starts, kappa: float):
     Cb = data.C.t().contiguous().view(K, 1, 1, B)
     fb = torch.zeros(1, dtype=torch.int32, device=data.C.device)
     s, lam, u = ttm.extract(ctx, desc, Cb, starts=starts, mlp=net, kappa=kappa, fallbacks=fb)
-    ang = angles_deg(u.view(B, 3), data.u)
+    ang = angles_deg(u.view(B, desc.dprime), data.u)
+    if desc.dprime == 4:
+        ang = 2.0 * ang                          # rotation distance 2 arccos|q1.q2|
     return ang, (lam.view(B) / s.view(B).clamp_min(1e-30)), int(fb.item())
 
 
@@ -109,14 +111,15 @@ def calibrate(ctx, desc, net, data: TrainingSet, starts, max_wrong: float = 0.02
             "not_converged_fraction": fb_conv / len(wrong)}
 
 
-def init_params(K: int, seed: int = 0, device="cuda") -> torch.Tensor:
-    """He-normal initial master parameters in the kernels' layout (random inputs, host-drawn)."""
+def init_params(K: int, seed: int = 0, device="cuda", dout: int = 3) -> torch.Tensor:
+    """He-normal initial master parameters in the kernels' layout (W1 [kin][64],
+    kin = 32 for K <= 32 else 48; dout = d' outputs; random inputs, host-drawn)."""
     rng = np.random.default_rng(seed)
-    W1 = np.zeros((32, 64))
+    W1 = np.zeros((32 if K <= 32 else 48, 64))
     W1[:K] = rng.standard_normal((K, 64)) * np.sqrt(2.0 / K)
     W2 = rng.standard_normal((64, 64)) * np.sqrt(2.0 / 64)
     W3 = np.zeros((64, 16))
-    W3[:, :3] = rng.standard_normal((64, 3)) * np.sqrt(1.0 / 64)
+    W3[:, :dout] = rng.standard_normal((64, dout)) * np.sqrt(1.0 / 64)
     flat = np.concatenate([W1.ravel(), np.zeros(64), W2.ravel(), np.zeros(64), W3.ravel(), np.zeros(16)])
     return torch.from_numpy(flat.astype(np.float32)).to(device)
 
@@ -135,7 +138,7 @@ def build_learned_start(ctx, desc, spectra, fft_n, tomograms, starts, *, n_unifo
     torch.cuda.synchronize()
     t1 = time.time()
     K = ttm.n_components(desc.degree, desc.dprime)
-    net = ttm.MLP(ctx, desc, init_params(K, seed, device=spectra.device))
+    net = ttm.MLP(ctx, desc, init_params(K, seed, device=spectra.device, dout=desc.dprime))
     curve = train(net, data, steps=steps, batch=batch, lr=lr, seed=seed, log_every=max(steps // 10, 1))
     torch.cuda.synchronize()
     t2 = time.time()

@@ -269,25 +269,29 @@ class MLP:
 
     def __init__(self, ctx: Context, desc: Desc, params: torch.Tensor):
         lib = load()
-        self.n_params = lib.ttm_mlp_param_count()
+        self.n_params = lib.ttm_mlp_param_count(C.byref(desc))
+        if self.n_params == 0:
+            raise ValueError(f"no learned start for d'={desc.dprime}, degree {desc.degree}")
         if params.numel() != self.n_params or params.dtype != torch.float32 or not params.is_cuda:
             raise ValueError(f"params must be {self.n_params} float32 device values")
         self.ctx, self.desc = ctx, desc
         self.params = params.contiguous().clone()
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
-        self.packed = torch.empty(lib.ttm_mlp_packed_bytes(), dtype=torch.uint8, device=params.device)
+        self.packed = torch.empty(lib.ttm_mlp_packed_bytes(C.byref(desc)), dtype=torch.uint8,
+                                  device=params.device)
         self.step = 0
         self.loss = torch.zeros(1, dtype=torch.float32, device=params.device)
         self._ws = None
         self.pack()
 
     def pack(self):
-        call("ttm_mlp_pack", self.ctx.h, _ptr(self.params), _ptr(self.packed), _stream())
+        call("ttm_mlp_pack", self.ctx.h, C.byref(self.desc), _ptr(self.params), _ptr(self.packed),
+             _stream())
 
     def train_step(self, Cs: torch.Tensor, targets: torch.Tensor, lr: float,
                    grads: torch.Tensor | None = None) -> torch.Tensor:
-        """One Adam step on a batch (Cs: B x K raw tensors, targets: B x 3); returns the loss."""
+        """One Adam step on a batch (Cs: B x K raw tensors, targets: B x d'); returns the loss."""
         _need_cuda(Cs, targets, grads)
         B = Cs.shape[0]
         if self._ws is None or self._ws.numel() < load().ttm_workspace_size(

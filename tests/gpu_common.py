@@ -30,24 +30,25 @@ def rel_err(a, b):
 
 
 def oracle_trained_params(seed: int, n: int, steps: int = 300, batch: int = 2048,
-                          noise: float = 0.15, lr: float = 3e-3):
+                          noise: float = 0.15, lr: float = 3e-3, d: int = 3):
     """Learned-start network parameters trained by the FP64 oracle on the CPU.
 
-    Training tensors are rank-one tensors v^n of random unit directions plus
-    Gaussian noise, with v as the target.  Both sides of a parity test consume
-    these parameters, so no input of the oracle comes from the GPU path.
+    Training tensors are rank-one tensors v^n of random unit vectors of R^d
+    (axes, or quaternions at d = 4) plus Gaussian noise, with v as the target.
+    Both sides of a parity test consume these parameters, so no input of the
+    oracle comes from the GPU path.
     """
     from oracle import mlp as omlp
     from oracle import sym
     rng = np.random.default_rng(seed)
-    K = sym.n_components(n, 3)
-    p = omlp.init_params(rng, K)
+    K = sym.n_components(n, d)
+    p = omlp.init_params(rng, K, d_out=d)
     st = omlp.adam_init(p)
     for _ in range(steps):
-        v = rng.standard_normal((batch, 3))
+        v = rng.standard_normal((batch, d))
         v /= np.linalg.norm(v, axis=1, keepdims=True)
         C = sym.monomials(v, n) + noise * rng.standard_normal((batch, K))
-        _, cache = omlp.forward(p, omlp.features(C, n))
+        _, cache = omlp.forward(p, omlp.features(C, n, d))
         omlp.adam_step(p, omlp.backward(p, cache, v), st, lr=lr)
     return p
 

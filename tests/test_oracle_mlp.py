@@ -201,3 +201,35 @@ def test_learned_path_zero_tensor_rank_one_and_no_direction():
     C, a, b, c = _two_maxima(n)
     lam, u, fell = mlp.orient_learned(C, n, z, np.vstack([_far_starts(a, b, c), _tilt(a, c, 5.0)]), -1.0)
     assert fell and lam == pytest.approx(2.0, rel=1e-12) and ttm.angle_deg(u, a) < 1e-6
+
+
+def test_quaternion_learned_path_rank_one_zero_network_and_layout():
+    """The learned path of the quaternion form (d' = 4, degree 4, K = 35, the
+    48-input network, no Newton-first steps): on rank-one tensors lam0 q^n the
+    answer is (lam0, +-q) with w >= 0 and no fallback, wherever the network
+    points (SS-HOPM reaches +-q from any start with u.q != 0, and the value
+    lam0 (s.q)^n of every fixed start lies below lam0); a network with zero
+    parameters forces the fallback, whose answer is the multistart's; the
+    master layout keeps 48 rows of W1 and unpads to the same dict."""
+    from oracle import ttm
+    n, K, d = 4, 35, 4
+    rng = np.random.default_rng(6)
+    p = mlp.init_params(rng, K, d_out=d)
+    flat = mlp.pad_params(p, K, d)
+    assert mlp.padded_inputs(K) == 48 and flat.size == 48 * 64 + 64 + 4096 + 64 + 64 * 16 + 16
+    q2 = mlp.unpad_params(flat, K, d)
+    assert all(np.array_equal(q2[k], p[k]) for k in p)
+    st = rng.standard_normal((32, d))
+    st /= np.linalg.norm(st, axis=1, keepdims=True)
+    for _ in range(4):
+        q = rng.standard_normal(d)
+        q /= np.linalg.norm(q)
+        lam0 = rng.uniform(0.5, 2.0)
+        lam, u, fell = mlp.orient_learned(lam0 * sym.monomials(q, n), n, p, st, 0.3, newton_first=0)
+        assert not fell and lam == pytest.approx(lam0, rel=1e-10)
+        assert ttm.quat_angle_deg(u, q) < 1e-5 and u[0] >= 0
+    z = {k: np.zeros_like(val) for k, val in p.items()}
+    C = rng.standard_normal(K)
+    lam, u, fell = mlp.orient_learned(C, n, z, st, -1.0, newton_first=0)
+    lam_m, u_m, *_ = ttm.orient_multistart(C, n, st)
+    assert fell and lam == pytest.approx(lam_m, rel=1e-12) and ttm.quat_angle_deg(u, u_m) < 1e-6
