@@ -191,7 +191,7 @@ __device__ __forceinline__ void tangent_model(const float (&c)[ncomp3(N)], float
   } else {                           // a = e_z: (-uy, ux, 0)
     e1x = -uy; e1y = ux; e1z = 0.0f;
   }
-  const float r1 = 1.0f / sqrtf(e1x * e1x + e1y * e1y + e1z * e1z);
+  const float r1 = rsqrtf(e1x * e1x + e1y * e1y + e1z * e1z);
   e1x *= r1; e1y *= r1; e1z *= r1;
   const float e2x = uy * e1z - uz * e1y, e2y = uz * e1x - ux * e1z, e2z = ux * e1y - uy * e1x;
   float h[6];
@@ -246,7 +246,7 @@ __device__ __forceinline__ void newton_move(const float (&c)[ncomp3(N)], float u
   vx = ux + t * dx;
   vy = uy + t * dy;
   vz = uz + t * dz;
-  const float rv = 1.0f / sqrtf(vx * vx + vy * vy + vz * vz);
+  const float rv = rsqrtf(vx * vx + vy * vy + vz * vz);
   vx *= rv; vy *= rv; vz *= rv;
   contract<N>(c, vx, vy, vz, q0, q1, q2);
   lam_v = q0 * vx + q1 * vy + q2 * vz;
@@ -381,7 +381,7 @@ __device__ __forceinline__ float unfolding_lambda_min(const float (&c)[ncomp3(N)
 #pragma unroll
       for (int k = 0; k < j; ++k) d = fmaf(-R[tri(M, k, j)], R[tri(M, k, j)], d);
       pd = pd && d > 0.0f;
-      const float r = pd ? 1.0f / sqrtf(d) : 0.0f;
+      const float r = pd ? rsqrtf(d) : 0.0f;
       R[tri(M, j, j)] = d * r;
 #pragma unroll
       for (int i = j + 1; i < M; ++i) {
@@ -750,7 +750,7 @@ __global__ __launch_bounds__(64) void k_runs(ExtractArgs a, RunArgs r) {
     if (busy) {
       if (!first) {
         const float wx = fmaf(alpha, ux, g0), wy = fmaf(alpha, uy, g1), wz = fmaf(alpha, uz, g2);
-        const float rn = 1.0f / sqrtf(wx * wx + wy * wy + wz * wz);
+        const float rn = rsqrtf(wx * wx + wy * wy + wz * wz);
         ux = wx * rn; uy = wy * rn; uz = wz * rn;
       }
       contract<N>(c, ux, uy, uz, g0, g1, g2);

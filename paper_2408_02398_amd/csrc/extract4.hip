@@ -475,7 +475,7 @@ __global__ __launch_bounds__(64) void k_runs4(ExtractArgs a, Items4 it, int R, i
         float v[4];
 #pragma unroll
         for (int d = 0; d < 4; ++d) v[d] = fmaf(alpha, u[d], g[d]);
-        const float rn = 1.0f / sqrtf(dot4(v, v));
+        const float rn = rsqrtf(dot4(v, v));
 #pragma unroll
         for (int d = 0; d < 4; ++d) u[d] = v[d] * rn;
       }
@@ -722,7 +722,7 @@ __global__ __launch_bounds__(64 * kLearnedWaves4) void k_learned4(ExtractArgs a)
       float vv[4];
 #pragma unroll
       for (int d = 0; d < 4; ++d) vv[d] = fmaf(alpha, u[d], g[d]);
-      const float rn = 1.0f / sqrtf(dot4(vv, vv));
+      const float rn = rsqrtf(dot4(vv, vv));
 #pragma unroll
       for (int d = 0; d < 4; ++d) u[d] = vv[d] * rn;
       contract4<N>(c, u, g);
