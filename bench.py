@@ -106,6 +106,11 @@ def main():
                     help="rotation and position error against the planted copies over SNR levels "
                          "(quaternion form, TTM and TTM-ref)")
     ap.add_argument("--snr", type=str, default="10,3,1,0.3,0.1", help="SNR levels of the noise sweep")
+    ap.add_argument("--wedge", action="store_true",
+                    help="noise sweep with a +-60 degree missing wedge and the wedge-aware template")
+    ap.add_argument("--dense-snr", type=float, default=1.0,
+                    help="noise sweep: SNR of the dense orientation pass, plain vs learned start "
+                         "(0: none)")
     ap.add_argument("--max-wrong", type=float, default=0.05,
                     help="fallback calibration: accepted learned voxels off by > 1 deg at most this often")
     args = ap.parse_args()
@@ -585,7 +590,13 @@ def noise_sweep(args, grid=5, spacing=40, L=32, r=14.0, n=4, fft_n=256, rs=3.0):
     Peaks (125 peaks, 2r apart), then TTM-ref (Alg. 3, r_s = 3), whose output
     also holds each unrefined peak's own rotation (TTM).  Each planted copy is
     matched to the nearest peak within r; errors are the Euclidean position
-    distance and the rotation distance 2 arccos|q1.q2| (Sec. 4.1)."""
+    distance and the rotation distance 2 arccos|q1.q2| (Sec. 4.1).  With
+    --wedge the tomograms lose the +-60 degree missing wedge and the tensor
+    template is the wedge-aware one (ttm_build_tensor_wedge).  At --dense-snr the orientation of every
+    valid voxel is computed too, with the multistart search and with the
+    learned start (trained on four further tomograms of the same SNR), timed,
+    with the fallback count and the learned answers' rotation distance to the
+    multistart ones."""
     import torch
 
     import synth
@@ -600,9 +611,10 @@ def noise_sweep(args, grid=5, spacing=40, L=32, r=14.0, n=4, fft_n=256, rs=3.0):
     rows = []
     for k, snr in enumerate(snrs):
         wl = synth.grid_tomogram(f"sweep_snr{snr:g}", grid, spacing, L, 4, r, n, seed=500 + k,
-                                 snr=snr, template_seed=2)
+                                 snr=snr, template_seed=2, wedge=args.wedge)
         if T is None:
-            T, tn = ttm.build_tensor(ctx, d, torch.from_numpy(wl.template).to(dev), Q)
+            T, tn = ttm.build_tensor(ctx, d, torch.from_numpy(wl.template).to(dev), Q,
+                                     wedge=60.0 if args.wedge else None)
             spec = ttm.template_spectra(ctx, d, T, fft_n)
             eng = ttm.Engine(ctx, d, spec, fft_n, wl.volume.shape, None, orient=False)
         vol = torch.from_numpy(wl.volume).to(dev)
@@ -648,13 +660,74 @@ def noise_sweep(args, grid=5, spacing=40, L=32, r=14.0, n=4, fft_n=256, rs=3.0):
                "ms_refine": e[1].elapsed_time(e[2]) / args.steps}
         log(f"[sweep] {row}")
         rows.append(row)
+    dense = None
+    if args.dense_snr > 0:
+        dense = dense_quaternion_pass(args, ctx, d, spec, fft_n, starts, grid, spacing, L, r, n)
     return {"metric": "rotation and position error vs SNR, TTM and TTM-ref (quaternion form)",
             "unit": "deg / voxels", "data": "synthetic", "n_gpus": 1, "steps": args.steps,
             "config": {"workload": f"grid {grid}^3 copies, spacing {spacing}, template {L}^3 "
                                    f"(4 Gaussian blobs), r {r}, volume {2 * (L // 2 + 2) + (grid - 1) * spacing + 1}^3",
                        "degree": n, "dprime": 4, "K": 35, "fft_tile": fft_n, "r_s": rs,
-                       "rotations": int(Q.shape[0]), "quaternion_starts": int(starts.shape[0])},
-            "sweep": rows}
+                       "rotations": int(Q.shape[0]), "quaternion_starts": int(starts.shape[0]),
+                       "missing_wedge": bool(args.wedge)},
+            "sweep": rows, "dense_orientation": dense}
+
+
+def dense_quaternion_pass(args, ctx, d, spec, fft_n, starts, grid, spacing, L, r, n):
+    """Every valid voxel's rotation (quaternion form) on a grid tomogram at
+    --dense-snr: the multistart pass and the learned-start pass (network trained
+    on three further tomograms of the same SNR, kappa calibrated on a fourth),
+    timed over --steps passes each."""
+    import torch
+
+    import synth
+    from paper_2408_02398_amd import learn, ttm
+    snr = args.dense_snr
+
+    def tomo(seed):
+        return synth.grid_tomogram(f"dense_{seed}", grid, spacing, L, 4, r, n, seed=seed, snr=snr,
+                                   template_seed=2, wedge=args.wedge)
+
+    vol = torch.from_numpy(tomo(700).volume).cuda()
+    train = [torch.from_numpy(tomo(s).volume).cuda() for s in (701, 702, 703, 704)]
+    t0 = time.time()
+    net, kappa, info = learn.build_learned_start(ctx, d, spec, fft_n, train, starts, n_uniform=100000,
+                                                 n_top=100000, steps=60000, batch=8192, lr=3e-3,
+                                                 max_wrong=args.max_wrong, log=log)
+    t_train = time.time() - t0
+    out = {"snr": snr, "train_s": t_train, "kappa": kappa,
+           "valid_voxels": int(np.prod([s - L + 1 for s in vol.shape])),
+           "training": {k: info[k] for k in ("train_samples", "accepted_fraction",
+                                             "wrong_without_fallback", "not_converged_fraction",
+                                             "heldout_uniform_fallback", "heldout_uniform_within_1deg")}}
+    maps = {}
+    for mode in ("plain", "learned"):
+        eng = ttm.Engine(ctx, d, spec, fft_n, vol.shape, starts, mlp=net if mode == "learned" else None,
+                         kappa=kappa)
+        eng.run(vol, top_p=grid ** 3)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        eng.fallbacks.zero_()
+        e0.record()
+        for _ in range(args.steps):
+            eng.run(vol, top_p=grid ** 3)
+        e1.record()
+        torch.cuda.synchronize()
+        out[mode] = {"ms_pass": e0.elapsed_time(e1) / args.steps,
+                     "fallback_voxels": int(eng.fallbacks.item()) // args.steps if mode == "learned" else None}
+        maps[mode] = eng.dir.clone()
+        del eng
+        torch.cuda.empty_cache()
+    lo, hi = ttm.valid_bounds(vol.shape, L)
+    sl = tuple(slice(a, b + 1) for a, b in zip(lo, hi))
+    qa, qb = maps["plain"][sl].reshape(-1, 4), maps["learned"][sl].reshape(-1, 4)
+    cq = torch.abs((qa * qb).sum(-1)) / (qa.norm(dim=-1) * qb.norm(dim=-1)).clamp_min(1e-30)
+    ang = torch.rad2deg(2.0 * torch.arccos(cq.clamp(max=1.0)))
+    out["learned_vs_plain_rotation_deg"] = {"median": float(ang.median().item()),
+                                            "frac_within_1deg": float((ang <= 1.0).float().mean().item())}
+    out["speedup"] = out["plain"]["ms_pass"] / out["learned"]["ms_pass"]
+    log(f"[sweep dense] {out}")
+    return out
 
 
 def precision_report(args, cfg_name, fft_n, top_p, n_sample=150):

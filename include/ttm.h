@@ -78,8 +78,9 @@ typedef enum {
   TTM_OP_EXTRACT = 5,     /* nz x ny x nx = the extraction box            */
   TTM_OP_MLP_TRAIN = 6,   /* nz = batch size, ny = nx = 1                 */
   TTM_OP_PREFILTER = 7,   /* nz x ny x nx = the volume (fft_n unused)     */
-  TTM_OP_REFINE = 8       /* nz = peaks, ny = the refinement radius r_s
+  TTM_OP_REFINE = 8,      /* nz = peaks, ny = the refinement radius r_s
                              rounded up (the size covers every smaller r_s) */
+  TTM_OP_TENSOR_WEDGE = 9 /* ttm_build_tensor_wedge (fft_n, nz, ny, nx unused) */
 } ttm_op;
 
 typedef struct ttm_ctx ttm_ctx;
@@ -129,6 +130,30 @@ size_t ttm_workspace_size(const ttm_desc* desc, int op, int fft_n, int nz, int n
  */
 int ttm_build_tensor(ttm_ctx* ctx, const ttm_desc* desc, const float* tmpl,
                      const float* quats, int nq, float* T_out, float* tn_out, void* stream);
+
+/*
+ * Wedge-aware tensor template (a reading of Eq. tt for tomograms with a
+ * missing wedge; the paper does not treat the wedge).  As ttm_build_tensor,
+ * but every rotated template passes through the tomogram's missing-wedge
+ * filter and is renormalised over the mask before it is added:
+ *   T_a(p) = (1/nq) sum_q v_q^a N_m(W t'_q)(p)
+ * t'_q = t' rotated by R(q) (trilinear, as ttm_build_tensor); W zeroes the
+ * Fourier coefficients with |k_z| > tan(wedge_deg) |k_x| (tilt axis y, beam z;
+ * DC kept), applied on the template box zero-padded to P^3, P the smallest
+ * supported FFT edge >= L (periodic transform); N_m(v) = m (v - mu) / sigma
+ * with mu = <v, m>/M and sigma^2 = <v^2, m> - <v, m>^2/M (Eq. norm_t without
+ * a second prefilter).  The wedge lies in the tomogram's frame, so it acts
+ * after each rotation: filtering t' once before Alg. 1 would turn it with the
+ * template.  Correlating a wedged tomogram with T then scores every rotation
+ * by the part of the template the tomogram can show.
+ *   wedge_deg  half-angle in (0, 90) degrees (60 for a +-60 degree tilt range)
+ *   ws         ttm_workspace_size(desc, TTM_OP_TENSOR_WEDGE, 0, 0, 0, 0) bytes
+ * Other arguments as ttm_build_tensor.  Errors: TTM_EINVAL as there, or for
+ * wedge_deg outside (0, 90); TTM_EUNSUPPORTED for L > 512; TTM_EWORKSPACE.
+ */
+int ttm_build_tensor_wedge(ttm_ctx* ctx, const ttm_desc* desc, const float* tmpl,
+                           const float* quats, int nq, float wedge_deg, float* T_out,
+                           float* tn_out, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Spectra of the template fields for correlation at FFT edge fft_n (Alg. 2,

@@ -165,6 +165,57 @@ def tensor_template(tn: np.ndarray, quats: np.ndarray, n: int, dprime: int = 3,
     return T / len(quats)
 
 
+def wedge_keep(P: int, half_angle_deg: float) -> np.ndarray:
+    """Missing-wedge filter on the half spectrum of a real P^3 box (numpy.fft.rfftn
+    layout [kz][ky][kx], kx halved): 1 where a Fourier coefficient is kept, 0 where
+    |k_z| > tan(angle) |k_x| (tilt axis y, beam z, as the tomogram's wedge); the
+    DC coefficient is kept."""
+    kz = np.fft.fftfreq(P)[:, None, None]
+    kx = np.fft.rfftfreq(P)[None, None, :]
+    drop = np.abs(kz) > np.tan(np.radians(half_angle_deg)) * np.abs(kx)
+    keep = np.broadcast_to(~drop, (P, P, P // 2 + 1)).astype(np.float64).copy()
+    keep[0, 0, 0] = 1.0
+    return keep
+
+
+def mask_normalize(v: np.ndarray, m: np.ndarray) -> np.ndarray:
+    """m (v - mu) / sigma over the mask m (Eq. norm_t without the prefilter):
+    mu = <v, m> / M, sigma^2 = <v^2, m> - <v, m>^2 / M."""
+    v = np.asarray(v, dtype=np.float64)
+    M = float(m.sum())
+    s1 = float((v * m).sum())
+    s2 = float((v * v * m).sum())
+    return m * (v - s1 / M) / np.sqrt(s2 - s1 * s1 / M)
+
+
+def tensor_template_wedge(tn: np.ndarray, quats: np.ndarray, n: int, r: float,
+                          half_angle_deg: float | None, P: int, dprime: int = 3,
+                          axis=(0.0, 0.0, 1.0)) -> np.ndarray:
+    """Wedge-aware tensor template (a reading of Eq. tt for tomograms with a
+    missing wedge): T_alpha = (1/N_q) sum_q v_q^alpha N_m(W t'_q), where t'_q is
+    t' rotated by R(q) as in tensor_template, W the tomogram's missing-wedge
+    filter applied on the template box zero-padded to P^3 (periodic FFT; the
+    wedge lies in the tomogram's frame, so it acts after the rotation), and N_m
+    the renormalisation over the mask (mask_normalize), so that every rotated,
+    filtered template has zero mean and unit norm on the mask.  With
+    half_angle_deg None, W is the identity."""
+    L = tn.shape[0]
+    m = ball_mask(L, r)
+    keep = None if half_angle_deg is None else wedge_keep(P, half_angle_deg)
+    K = sym.n_components(n, dprime)
+    T = np.zeros((K, L, L, L))
+    for q in quats:
+        tq = rotate_template(tn, quat_to_matrix(q))
+        if keep is not None:
+            box = np.zeros((P, P, P))
+            box[:L, :L, :L] = tq
+            tq = np.fft.irfftn(np.fft.rfftn(box) * keep, s=(P, P, P), axes=(0, 1, 2))[:L, :L, :L]
+        tq = mask_normalize(tq, m)
+        k = sym.monomials(direction_of(q, dprime, axis), n)
+        T += k[:, None, None, None] * tq[None]
+    return T / len(quats)
+
+
 # ----------------------------------------------------------------------------
 # valid region, local normalisation, tensor field
 # ----------------------------------------------------------------------------

@@ -17,6 +17,7 @@ TTM_F32, TTM_BF16 = 0, 1
 TTM_OP_SPECTRA, TTM_OP_NORMALIZE, TTM_OP_CORRELATE, TTM_OP_PEAKS = 1, 2, 3, 4
 TTM_SCORE, TTM_ORIENT, TTM_START_MLP, TTM_START_ONLY, TTM_NO_SCREEN = 1, 2, 4, 8, 16
 TTM_OP_EXTRACT, TTM_OP_MLP_TRAIN, TTM_OP_PREFILTER, TTM_OP_REFINE = 5, 6, 7, 8
+TTM_OP_TENSOR_WEDGE = 9
 
 STATUS_NAMES = {0: "TTM_OK", -1: "TTM_EINVAL", -2: "TTM_ENOMEM", -3: "TTM_EDEVICE",
                 -4: "TTM_EUNSUPPORTED", -5: "TTM_EWORKSPACE"}
@@ -62,6 +63,8 @@ SIGNATURES = {
     "ttm_fft_supported": (C.c_int, [C.c_int]),
     "ttm_workspace_size": (C.c_size_t, [DP, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
     "ttm_build_tensor": (C.c_int, [vp, DP, vp, vp, C.c_int, vp, vp, vp]),
+    "ttm_build_tensor_wedge": (C.c_int, [vp, DP, vp, vp, C.c_int, C.c_float, vp, vp, vp, C.c_size_t,
+                                         vp]),
     "ttm_template_spectra": (C.c_int, [vp, DP, vp, C.c_int, vp, vp, C.c_size_t, vp]),
     "ttm_normalize": (C.c_int, [vp, DP, vp, C.c_int, C.c_int, C.c_int, vp, C.c_int, vp, vp, vp,
                                 vp, C.c_size_t, vp]),

@@ -335,6 +335,203 @@ __global__ __launch_bounds__(256) void k_build(const float* __restrict__ tn, int
   }
 }
 
+// ---------------------------------------------------------------------------
+// wedge-aware tensor template: every rotated t' through the missing-wedge
+// filter (on its box zero-padded to P^3) and renormalised over the mask
+// ---------------------------------------------------------------------------
+
+// Edge of the padded box: the smallest supported FFT edge >= L.
+int wedge_box(int L) {
+  int P = 32;
+  while (P < L) P *= 2;
+  return P;
+}
+// Rotations handled per batch: at most 2^24 box voxels, at most 256.
+int wedge_batch(int P) {
+  const long b = (1L << 24) / ((long)P * P * P);
+  return (int)(b < 1 ? 1 : (b > 256 ? 256 : b));
+}
+
+__device__ __forceinline__ void quat_rotation(const float* q, float (&R)[9], float (&qn)[4]) {
+  float w = q[0], x = q[1], y = q[2], z = q[3];
+  const float rn = 1.0f / sqrtf(w * w + x * x + y * y + z * z);
+  w *= rn; x *= rn; y *= rn; z *= rn;
+  qn[0] = w; qn[1] = x; qn[2] = y; qn[3] = z;
+  R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z); R[2] = 2 * (x * z + w * y);
+  R[3] = 2 * (x * y + w * z); R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+  R[6] = 2 * (x * z - w * y); R[7] = 2 * (y * z + w * x); R[8] = 1 - 2 * (x * x + y * y);
+}
+
+// Box b (rotation q0 + b) holds t'(c + R^T (p - c)) at p in [0, L)^3 and 0
+// elsewhere in [0, P)^3 (trilinear, zero outside the template box).
+__global__ __launch_bounds__(256) void k_rotate_boxes(const float* __restrict__ tn, int L,
+                                                      const float* __restrict__ quats, int q0, int P,
+                                                      float* __restrict__ boxes) {
+  const int b = blockIdx.y;
+  const size_t n = (size_t)P * P * P;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int x = (int)(i % P), y = (int)((i / P) % P), z = (int)(i / ((size_t)P * P));
+  float val = 0.0f;
+  if (x < L && y < L && z < L) {
+    float R[9], qn[4];
+    quat_rotation(quats + 4 * (size_t)(q0 + b), R, qn);
+    const float c = (float)(L / 2);
+    const float px = (float)x - c, py = (float)y - c, pz = (float)z - c;
+    const float sx = c + R[0] * px + R[3] * py + R[6] * pz;
+    const float sy = c + R[1] * px + R[4] * py + R[7] * pz;
+    const float sz = c + R[2] * px + R[5] * py + R[8] * pz;
+    const float fx = floorf(sx), fy = floorf(sy), fz = floorf(sz);
+    const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
+    const float tx = sx - fx, ty = sy - fy, tz = sz - fz;
+    for (int dz = 0; dz < 2; ++dz) {
+      const int zz = iz + dz;
+      if (zz < 0 || zz >= L) continue;
+      const float wz = dz ? tz : 1.0f - tz;
+      for (int dy = 0; dy < 2; ++dy) {
+        const int yy = iy + dy;
+        if (yy < 0 || yy >= L) continue;
+        const float wy = dy ? ty : 1.0f - ty;
+        for (int dx = 0; dx < 2; ++dx) {
+          const int xx = ix + dx;
+          if (xx < 0 || xx >= L) continue;
+          const float wx = dx ? tx : 1.0f - tx;
+          val += wz * wy * wx * tn[((size_t)zz * L + yy) * L + xx];
+        }
+      }
+    }
+  }
+  boxes[(size_t)b * n + i] = val;
+}
+
+// Zero the half-spectrum coefficients ([kz][kx][ky], ky fastest) inside the
+// wedge: |f_z| > tan * f_x (integer frequencies, f_z signed), DC kept.
+__global__ __launch_bounds__(256) void k_wedge(cf* __restrict__ spec, size_t stride, int P, float tanv) {
+  const int b = blockIdx.y;
+  const size_t n = (size_t)P * (P / 2 + 1) * P;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int kx = (int)((i / P) % (P / 2 + 1)), kz = (int)(i / ((size_t)P * (P / 2 + 1)));
+  const int fz = kz <= P / 2 ? kz : P - kz;   // |f_z|; kz = P/2 is the Nyquist plane
+  if ((float)fz > tanv * (float)kx) spec[(size_t)b * stride + i] = cf{0.0f, 0.0f};
+}
+
+// Per box: mu = <v, m>/M and 1/sigma over the ball mask of the template box,
+// in FP64 (0 where sigma = 0).
+__global__ __launch_bounds__(256) void k_box_stats(const float* __restrict__ boxes, int P, int L,
+                                                   float r, double* __restrict__ stats) {
+  __shared__ double r1[256], r2[256], rm[256];
+  const int b = blockIdx.x;
+  const size_t n = (size_t)P * P * P;
+  const int c = L / 2;
+  double s1 = 0.0, s2 = 0.0, sm = 0.0;
+  for (int i = threadIdx.x; i < L * L * L; i += blockDim.x) {
+    const int x = i % L, y = (i / L) % L, z = i / (L * L);
+    const float dx = (float)(x - c), dy = (float)(y - c), dz = (float)(z - c);
+    if (dx * dx + dy * dy + dz * dz > r * r) continue;
+    const double v = boxes[(size_t)b * n + ((size_t)z * P + y) * P + x];
+    s1 += v;
+    s2 += v * v;
+    sm += 1.0;
+  }
+  r1[threadIdx.x] = s1;
+  r2[threadIdx.x] = s2;
+  rm[threadIdx.x] = sm;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      r1[threadIdx.x] += r1[threadIdx.x + off];
+      r2[threadIdx.x] += r2[threadIdx.x + off];
+      rm[threadIdx.x] += rm[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double M = rm[0];
+    const double var = r2[0] - r1[0] * r1[0] / M;
+    stats[2 * b] = r1[0] / M;
+    stats[2 * b + 1] = var > 0.0 ? 1.0 / sqrt(var) : 0.0;
+  }
+}
+
+// Tacc[a][p] += sum_b v_b^a m(p) (box_b(p) - mu_b) / sigma_b for a in
+// [a0, a0 + na), p in [0, L)^3, boxes of rotations q0 .. q0 + nb - 1.
+__global__ __launch_bounds__(256) void k_wedge_accumulate(const float* __restrict__ boxes, int P, int L,
+                                                          float r, const float* __restrict__ quats,
+                                                          int q0, int nb, int dprime, float ax, float ay,
+                                                          float az, int a0, int na, Exponents ex,
+                                                          const double* __restrict__ stats,
+                                                          double* __restrict__ Tacc) {
+  __shared__ float sMono[kQChunk][kCompBlock];
+  __shared__ float sMu[kQChunk], sIs[kQChunk];
+  const int n = L * L * L;
+  const size_t nbox = (size_t)P * P * P;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = L / 2;
+  int x = 0, y = 0, z = 0;
+  bool inside = false;
+  if (i < n) {
+    x = i % L; y = (i / L) % L; z = i / (L * L);
+    const float dx = (float)(x - c), dy = (float)(y - c), dz = (float)(z - c);
+    inside = dx * dx + dy * dy + dz * dz <= r * r;
+  }
+  double acc[kCompBlock];
+#pragma unroll
+  for (int k = 0; k < kCompBlock; ++k) acc[k] = 0.0;
+  for (int b0 = 0; b0 < nb; b0 += kQChunk) {
+    const int nc = min(kQChunk, nb - b0);
+    __syncthreads();
+    if (threadIdx.x < nc) {
+      float R[9], qn[4];
+      quat_rotation(quats + 4 * (size_t)(q0 + b0 + threadIdx.x), R, qn);
+      float v[4];
+      if (dprime == 4) {
+        v[0] = qn[0]; v[1] = qn[1]; v[2] = qn[2]; v[3] = qn[3];
+      } else {
+        v[0] = R[0] * ax + R[1] * ay + R[2] * az;
+        v[1] = R[3] * ax + R[4] * ay + R[5] * az;
+        v[2] = R[6] * ax + R[7] * ay + R[8] * az;
+        v[3] = 1.0f;
+      }
+      for (int k = 0; k < na; ++k) {
+        float m = 1.0f;
+        for (int d = 0; d < dprime; ++d)
+          for (int e = 0; e < ex.e[a0 + k][d]; ++e) m *= v[d];
+        sMono[threadIdx.x][k] = m;
+      }
+      sMu[threadIdx.x] = (float)stats[2 * (b0 + threadIdx.x)];
+      sIs[threadIdx.x] = (float)stats[2 * (b0 + threadIdx.x) + 1];
+    }
+    __syncthreads();
+    if (inside) {
+      float part[kCompBlock];
+#pragma unroll
+      for (int k = 0; k < kCompBlock; ++k) part[k] = 0.0f;
+      const size_t off = ((size_t)z * P + y) * P + x;
+      for (int bi = 0; bi < nc; ++bi) {
+        const float val = (boxes[(size_t)(b0 + bi) * nbox + off] - sMu[bi]) * sIs[bi];
+#pragma unroll
+        for (int k = 0; k < kCompBlock; ++k) part[k] = fmaf(sMono[bi][k], val, part[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < kCompBlock; ++k) acc[k] += (double)part[k];
+    }
+  }
+  if (i < n)
+    for (int k = 0; k < na; ++k) Tacc[(size_t)(a0 + k) * n + i] += acc[k];
+}
+
+__global__ void k_wedge_finish(const double* __restrict__ Tacc, size_t total, double inv,
+                               float* __restrict__ T) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < total) T[i] = (float)(Tacc[i] * inv);
+}
+
+__global__ void k_zero_f64(double* __restrict__ p, size_t total) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < total) p[i] = 0.0;
+}
+
 int ncomp(int n, int d) {
   if (n < 0 || n > 8 || (d != 3 && d != 4)) return -1;
   long num = 1, den = 1;
@@ -414,6 +611,14 @@ size_t spec_elems(int N) { return (size_t)N * (N / 2 + 1) * N; }
 // x/y-transformed template: its L nonzero z planes only
 size_t tspec_elems(int N, int L) { return (size_t)L * (N / 2 + 1) * N; }
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t wedge_workspace(int L, int K) {
+  const int P = wedge_box(L), B = wedge_batch(P);
+  const size_t nbox = (size_t)P * P * P;
+  return align256((size_t)B * nbox * 4) + align256((size_t)B * spec_elems(P) * 8) +
+         align256((size_t)B * 16) + align256((size_t)K * L * L * L * 8);
+}
+
 
 double mask_count(int L, float r) {
   const int c = L / 2;
@@ -533,6 +738,9 @@ size_t ttm_workspace_size(const ttm_desc* desc, int op, int fft_n, int nz, int n
     case TTM_OP_REFINE:
       if (nz < 1 || ny < 0 || ny > max_refine_radius()) return 0;
       return refine_workspace(K, nz, (float)ny);
+    case TTM_OP_TENSOR_WEDGE:
+      if (desc->L < 1 || desc->L > 512) return 0;
+      return wedge_workspace(desc->L, K);
     default:
       return 0;
   }
@@ -567,6 +775,83 @@ int ttm_build_tensor(ttm_ctx* ctx, const ttm_desc* desc, const float* tmpl, cons
     hipLaunchKernelGGL(k_build, dim3((n + 255) / 256), dim3(256), 0, s, tn_out, L, quats, nq,
                        desc->dprime, ax, ay, az, a0, na, ex, T_out);
   }
+  TTM_HIP(hipGetLastError());
+  return TTM_OK;
+}
+
+int ttm_build_tensor_wedge(ttm_ctx* ctx, const ttm_desc* desc, const float* tmpl,
+                           const float* quats, int nq, float wedge_deg, float* T_out,
+                           float* tn_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || !valid_desc(desc)) return TTM_EINVAL;
+  if (!tmpl || !quats || !T_out || !tn_out || !ws || nq < 1 || !(wedge_deg > 0.0f) ||
+      !(wedge_deg < 90.0f)) {
+    set_error("ttm_build_tensor_wedge: null pointer, nq < 1 or wedge angle outside (0, 90)");
+    return TTM_EINVAL;
+  }
+  const int L = desc->L, K = ncomp(desc->degree, desc->dprime);
+  if (L > 512) {
+    set_error("ttm_build_tensor_wedge: L = %d above 512", L);
+    return TTM_EUNSUPPORTED;
+  }
+  const size_t need = wedge_workspace(L, K);
+  if (ws_bytes < need) {
+    set_error("ttm_build_tensor_wedge: workspace %zu < %zu", ws_bytes, need);
+    return TTM_EWORKSPACE;
+  }
+  float ax = desc->axis[0], ay = desc->axis[1], az = desc->axis[2];
+  const float an = std::sqrt(ax * ax + ay * ay + az * az);
+  if (desc->dprime == 3) {
+    if (!(an > 0.0f)) {
+      set_error("ttm_build_tensor_wedge: template axis is zero");
+      return TTM_EINVAL;
+    }
+    ax /= an; ay /= an; az /= an;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  TTM_HIP(hipSetDevice(ctx->device));
+  hipLaunchKernelGGL(k_template_norm, dim3(1), dim3(1024), 0, s, tmpl, L, desc->mask_radius,
+                     desc->filter_a, tn_out);
+  const int P = wedge_box(L), B = wedge_batch(P);
+  const size_t nbox = (size_t)P * P * P, nspec = spec_elems(P), n = (size_t)L * L * L;
+  char* p = static_cast<char*>(ws);
+  float* boxes = reinterpret_cast<float*>(p);
+  p += align256((size_t)B * nbox * 4);
+  cf* spec = reinterpret_cast<cf*>(p);
+  p += align256((size_t)B * nspec * 8);
+  double* stats = reinterpret_cast<double*>(p);
+  p += align256((size_t)B * 16);
+  double* Tacc = reinterpret_cast<double*>(p);
+  const size_t total = (size_t)K * n;
+  hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, Tacc, total);
+  Exponents ex;
+  exponents(desc->degree, desc->dprime, ex);
+  const float tanv = std::tan(wedge_deg * 3.14159265358979323846f / 180.0f);
+  for (int q0 = 0; q0 < nq; q0 += B) {
+    const int nb = std::min(B, nq - q0);
+    hipLaunchKernelGGL(k_rotate_boxes, dim3((unsigned)((nbox + 255) / 256), nb), dim3(256), 0, s,
+                       tn_out, L, quats, q0, P, boxes);
+    RealSrc src{boxes, nbox, P, P, P, 0, 0, 0, nullptr, 0};
+    int rc = fft3d_forward(P, src, nb, spec, nspec, ctx->twiddles, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_wedge, dim3((unsigned)((nspec + 255) / 256), nb), dim3(256), 0, s, spec,
+                       nspec, P, tanv);
+    for (int b = 0; b < nb; ++b) {
+      RealDst d{boxes + (size_t)b * nbox, 0, 0, P, P, 0, 0, 0, P, P, P, nullptr, 0, 0, 0, 0, 0,
+                1.0f / (float)nbox};
+      cf* sp = spec + (size_t)b * nspec;
+      rc = fft3d_inverse_mul(P, sp, nullptr, 0, 0, 1, nullptr, sp, nspec, d, ctx->twiddles, s);
+      if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_box_stats, dim3(nb), dim3(256), 0, s, boxes, P, L, desc->mask_radius, stats);
+    for (int a0 = 0; a0 < K; a0 += kCompBlock) {
+      const int na = std::min(kCompBlock, K - a0);
+      hipLaunchKernelGGL(k_wedge_accumulate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                         boxes, P, L, desc->mask_radius, quats, q0, nb, desc->dprime, ax, ay, az,
+                         a0, na, ex, stats, Tacc);
+    }
+  }
+  hipLaunchKernelGGL(k_wedge_finish, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, Tacc,
+                     total, 1.0 / (double)nq, T_out);
   TTM_HIP(hipGetLastError());
   return TTM_OK;
 }

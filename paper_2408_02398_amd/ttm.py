@@ -83,15 +83,23 @@ def _ws(desc: Desc, op: int, fft_n: int, dims=(0, 0, 0), device=None) -> torch.T
     return torch.empty(n, dtype=torch.uint8, device=device)
 
 
-def build_tensor(ctx: Context, desc: Desc, tmpl: torch.Tensor, quats: torch.Tensor):
-    """Tensor template T (K x L^3) and t' (L^3), Alg. 1."""
+def build_tensor(ctx: Context, desc: Desc, tmpl: torch.Tensor, quats: torch.Tensor,
+                 wedge: float | None = None):
+    """Tensor template T (K x L^3) and t' (L^3), Alg. 1; with ``wedge`` (the
+    missing wedge's half-angle in degrees) the wedge-aware template of
+    ttm_build_tensor_wedge."""
     _need_cuda(tmpl, quats)
     K = n_components(desc.degree, desc.dprime)
     Le = desc.L
     T = torch.empty((K, Le, Le, Le), dtype=torch.float32, device=tmpl.device)
     tn = torch.empty((Le, Le, Le), dtype=torch.float32, device=tmpl.device)
-    call("ttm_build_tensor", ctx.h, C.byref(desc), _ptr(tmpl), _ptr(quats), quats.shape[0],
-         _ptr(T), _ptr(tn), _stream())
+    if wedge is None:
+        call("ttm_build_tensor", ctx.h, C.byref(desc), _ptr(tmpl), _ptr(quats), quats.shape[0],
+             _ptr(T), _ptr(tn), _stream())
+    else:
+        ws = _ws(desc, L.TTM_OP_TENSOR_WEDGE, 0, device=tmpl.device)
+        call("ttm_build_tensor_wedge", ctx.h, C.byref(desc), _ptr(tmpl), _ptr(quats),
+             quats.shape[0], float(wedge), _ptr(T), _ptr(tn), _ptr(ws), ws.numel(), _stream())
     return T, tn
 
 

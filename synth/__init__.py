@@ -318,12 +318,15 @@ def make_tomogram(name: str, shape, L: int, n_blobs: int, n_copies: int, min_sep
 
 def grid_tomogram(name: str, grid: int, spacing: int, L: int, n_blobs: int, mask_radius: float,
                   degree: int, seed: int, snr: float, template_seed: int,
-                  margin: int | None = None) -> Workload:
+                  margin: int | None = None, wedge: bool = False) -> Workload:
     """A grid x grid x grid lattice of rotated template copies in Gaussian noise,
     as in the paper's synthetic tomograms (Sec. 4.1: a 5 x 5 x 5 grid of 125
     randomly rotated copies; noise at a stated SNR).  Copy rotations are
     Haar-uniform quaternions, kept in ``quaternions``; the noise variance is the
-    template's variance over its mask divided by ``snr``.  No missing wedge."""
+    template's variance over its mask divided by ``snr``.  With ``wedge`` the
+    tomogram (signal and noise) loses the +-60 degree missing wedge; the
+    template is returned unfiltered (the wedge lies in the tomogram's frame, so
+    filtering the template before it is rotated would turn the wedge with it)."""
     rng = np.random.default_rng(seed)
     tmpl = blob_template(np.random.default_rng(template_seed), L, n_blobs)
     tvol = tmpl.volume()
@@ -338,11 +341,14 @@ def grid_tomogram(name: str, grid: int, spacing: int, L: int, n_blobs: int, mask
     sig = render_copies(shape, tmpl, centres, rots)
     noise_sd = math.sqrt(float(np.var(tvol[ball(L, mask_radius)])) / snr)
     vol = sig + (noise_sd * rng.standard_normal(shape, dtype=np.float32)).astype(np.float32)
+    if wedge:
+        vol = missing_wedge(vol)
     return Workload(name=name, volume=np.ascontiguousarray(vol, dtype=np.float32),
                     template=tvol.astype(np.float32), template_model=tmpl,
                     mask_radius=mask_radius, degree=degree, centres=centres, rotations=rots,
                     params=dict(shape=shape, L=L, n_blobs=n_blobs, grid=grid, spacing=spacing,
-                                seed=seed, snr=snr, noise_sd=noise_sd, template_seed=template_seed),
+                                seed=seed, snr=snr, noise_sd=noise_sd, template_seed=template_seed,
+                                wedge=wedge),
                     quaternions=quats)
 
 

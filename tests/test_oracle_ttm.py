@@ -836,3 +836,84 @@ def test_orientation_recovers_the_planted_rotation(dprime):
         else:
             errs.append(np.degrees(2 * np.arccos(min(1.0, abs(u @ _quat_of(R))))))
     assert max(errs) < 8.0, errs
+
+
+# ------------------------------------------------------- wedge-aware template
+def test_wedge_filter_is_a_projection_that_removes_the_wedge():
+    """W keeps a plane wave along x (k_z = 0), removes one along z (|k_z| > 0 =
+    tan * |k_x|), keeps the mean, and is an orthogonal projection: W W = W and
+    <W a, b> = <a, W b> (Parseval on the kept coefficients)."""
+    P = 16
+    keep = ttm.wedge_keep(P, 60.0)
+    z, y, x = np.meshgrid(*[np.arange(P)] * 3, indexing="ij")
+
+    def W(v):
+        return np.fft.irfftn(np.fft.rfftn(v) * keep, s=(P, P, P), axes=(0, 1, 2))
+
+    along_x = np.cos(2 * np.pi * 3 * x / P)
+    along_z = np.cos(2 * np.pi * 2 * z / P)
+    assert np.allclose(W(along_x), along_x, atol=1e-12)
+    assert np.allclose(W(along_z), 0.0, atol=1e-12)
+    assert np.allclose(W(np.full((P, P, P), 2.5)), 2.5, atol=1e-12)
+    # |k_z| = 1, |k_x| = 1: kept at 60 degrees (tan 60 > 1), dropped at 30 degrees
+    diag = np.cos(2 * np.pi * (x + z) / P)
+    assert np.allclose(W(diag), diag, atol=1e-12)
+    assert np.allclose(np.fft.irfftn(np.fft.rfftn(diag) * ttm.wedge_keep(P, 30.0), s=(P,) * 3,
+                                     axes=(0, 1, 2)), 0.0,
+                       atol=1e-12)
+    rng = np.random.default_rng(3)
+    a, b = rng.standard_normal((2, P, P, P))
+    assert np.allclose(W(W(a)), W(a), atol=1e-12)
+    assert abs(np.sum(W(a) * b) - np.sum(a * W(b))) < 1e-9
+
+
+def test_wedge_template_without_wedge_on_grid_rotations_is_alg1():
+    """With W = I and the 24 grid-preserving rotations (no interpolation), each
+    rotated t' is a permutation of t' inside the ball mask, already normalised,
+    so the wedge-aware template equals Alg. 1's."""
+    L, r, n = 13, 4.0, 4
+    rng = np.random.default_rng(12)
+    tn = ttm.normalize_template(ndi.gaussian_filter(rng.standard_normal((L, L, L)), 1.0), r)
+    Q = synth.octahedral_quaternions()
+    for dprime in (3, 4):
+        T0 = ttm.tensor_template(tn, Q, n, dprime=dprime)
+        T1 = ttm.tensor_template_wedge(tn, Q, n, r, None, 16, dprime=dprime)
+        assert np.allclose(T0, T1, atol=1e-12)
+
+
+def test_wedge_template_normalised_and_equivariant_under_wedge_symmetries():
+    """The half turns G about x, y and z map the wedge onto itself and the
+    rotation set onto itself, so the wedge-aware template is equivariant as
+    Alg. 1's is: T(c + G (p - c)) = G^{(x)n} . T(p) (on the periodic padded box
+    a half turn about c is the map x -> 2c - x mod P, which commutes with W).
+    A rotation that does not map the wedge onto itself breaks it.
+    Every rotated, filtered template has zero mean and unit norm on the mask."""
+    L, r, n, P = 13, 4.0, 4, 16
+    rng = np.random.default_rng(13)
+    tn = ttm.normalize_template(ndi.gaussian_filter(rng.standard_normal((L, L, L)), 1.0), r)
+    Q = synth.rotation_samples(1)
+    m = ttm.ball_mask(L, r)
+    T = ttm.tensor_template_wedge(tn, Q, n, r, 60.0, P)
+    c = L // 2
+    idx = np.arange(L) - c
+    zz, yy, xx = np.meshgrid(idx, idx, idx, indexing="ij")
+    Pts = np.stack([xx, yy, zz], axis=-1)
+    for G in (np.diag([1.0, -1.0, -1.0]), np.diag([-1.0, 1.0, -1.0]), np.diag([-1.0, -1.0, 1.0])):
+        dst = np.rint(Pts @ G.T).astype(int) + c
+        lhs = T[:, dst[..., 2], dst[..., 1], dst[..., 0]]
+        rhs = np.stack([sym.rotate(T[:, z, y, x], G, n) for z in range(L) for y in range(L)
+                        for x in range(L)], axis=1).reshape(T.shape)
+        assert np.allclose(lhs, rhs, atol=1e-10), np.abs(lhs - rhs).max()
+    # a quarter turn about z does not preserve the wedge: the identity fails
+    G = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    dst = np.rint(Pts @ G.T).astype(int) + c
+    lhs = T[:, dst[..., 2], dst[..., 1], dst[..., 0]]
+    rhs = np.stack([sym.rotate(T[:, z, y, x], G, n) for z in range(L) for y in range(L)
+                    for x in range(L)], axis=1).reshape(T.shape)
+    assert np.abs(lhs - rhs).max() > 1e-3
+    keep = ttm.wedge_keep(P, 60.0)
+    box = np.zeros((P, P, P))
+    box[:L, :L, :L] = ttm.rotate_template(tn, ttm.quat_to_matrix(Q[5]))
+    f = np.fft.irfftn(np.fft.rfftn(box) * keep, s=(P,) * 3, axes=(0, 1, 2))[:L, :L, :L]
+    f = ttm.mask_normalize(f, m)
+    assert abs(f.sum()) < 1e-10 and abs(np.sum(f * f) - 1.0) < 1e-10
