@@ -236,14 +236,20 @@ def main():
         fallbacks = int(eng.fallbacks.item()) // max(args.steps, 1)
         wall = time.time() - wall0
         # work counts (SS-HOPM updates, Newton steps, ...) come from one more,
-        # untimed pass: their per-wavefront atomics would slow the timed ones
+        # untimed pass: their per-wavefront atomics would slow the timed ones.
+        # It runs the correlations on the caller's stream, so its per-launch
+        # event times are each stage's own (in the overlapped passes a side-stream
+        # launch also spans the time it waits for CUs the extraction holds).
         counters.zero_()
-        one_pass(False, count=True)
+        tm_s = {}
+        eng.run(vol, top_p=top_p, timing=tm_s, overlap=False, counters=counters)
         torch.cuda.synchronize()
+        serial = {"correlate": [(a.elapsed_time(b), size) for a, b, size in tm_s["correlate"]],
+                  "extract": [a.elapsed_time(b) for a, b, _ in tm_s["extract"]]}
         per_pass = [int(v) for v in counters.cpu().tolist()]
         eng.release()             # keep the maps for the accuracy gate, free the workspaces
         torch.cuda.empty_cache()
-        res = dict(eng=eng, pk=pk, stage=stage, ext=ext_launch_ms, corr=corr_launch_ms,
+        res = dict(eng=eng, pk=pk, stage=stage, ext=ext_launch_ms, corr=corr_launch_ms, serial=serial,
                    ms_step=start.elapsed_time(stop) / args.steps, wall=wall,
                    counters=[v * args.steps for v in per_pass], fallbacks=fallbacks)
         return res
@@ -272,15 +278,22 @@ def main():
     corr_launch_ms, ext_launch_ms = R["corr"], R["ext"]
     corr_avg = float(np.mean(corr_launch_ms))
     ext_avg = float(np.mean([t for t, _ in ext_launch_ms]))
-    # correlation launch (full interior tile): compulsory bytes = read the g tile,
-    # the K x/y-transformed template planes, the w crop, write the K cropped
-    # field planes
+    # per-tile launch (ttm_normalize_correlate on a full interior tile):
+    # compulsory bytes = read the g tile, the K x/y-transformed template planes
+    # and the mask's, write the w crop and read it back for the product, write
+    # the K cropped field planes
     tse = ttm.template_spectrum_elems(fft_n, L)
-    corr_bytes = 4 * fft_n ** 3 + K * tse * 8 + 4 * step_ ** 3 + 4 * K * step_ ** 3
+    corr_bytes = 4 * fft_n ** 3 + (K + 1) * tse * 8 + 2 * 4 * step_ ** 3 + 4 * K * step_ ** 3
     corr_full = [t for t, (blo, size) in zip(corr_launch_ms, R["eng"].boxes * args.steps)
                  if size == (step_, step_, step_)]
     corr_full_avg = float(np.mean(corr_full)) if corr_full else corr_avg
-    dominant = "extract" if stage["extract"] >= stage["correlate"] else "correlate"
+    ser = R["serial"]
+    ser_corr_full = [t for t, size in ser["correlate"] if size == (step_, step_, step_)]
+    ser_corr = float(np.mean(ser_corr_full)) if ser_corr_full else float(np.mean([t for t, _ in ser["correlate"]]))
+    ser_ext = float(np.mean(ser["extract"]))
+    # the dominant stage by its own kernel time (the untimed serial pass)
+    dominant = ("extract" if sum(ser["extract"]) >= sum(t for t, _ in ser["correlate"])
+                else "correlate")
     f = extract_flops(n)
     steps_, newton_, oriented, shifts, runs = R["counters"]
     voxels = sum(nv for _, nv in ext_launch_ms)
@@ -307,17 +320,26 @@ def main():
                 "achieved_algorithmic": alg_ach,
                 "frac_algorithmic": alg_ach / FP32_VECTOR_PEAK_TFLOPS,
                 "avg_launch_ms": ext_avg,
+                "isolated_avg_launch_ms": ser_ext,
                 "flops_per_launch": flops / len(ext_launch_ms),
                 "mlp_mfma_flops_per_launch": mfma / len(ext_launch_ms),
                 "sshopm_updates_per_oriented_voxel": steps_ / max(oriented, 1),
                 "newton_steps_per_oriented_voxel": newton_ / max(oriented, 1),
                 "shift_bounds_per_oriented_voxel": shifts / max(oriented, 1),
                 "runs_per_oriented_voxel": runs / max(oriented, 1)}
-    corr_roof = {"bound": "hbm", "kernel": f"ttm_correlate, full {fft_n}^3 tile",
+    corr_roof = {"bound": "hbm",
+                 "kernel": f"ttm_normalize_correlate (local normalisation and the K correlations "
+                           f"of one tile), full {fft_n}^3 tile",
                  "achieved": corr_bytes / (corr_full_avg / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
                  "unit": "GB/s", "avg_launch_ms": corr_full_avg, "bytes_per_launch": corr_bytes,
-                 "traffic": measured_traffic(fft_n, K)}
+                 "traffic": measured_traffic(fft_n, K),
+                 "isolated_avg_launch_ms": ser_corr,
+                 "achieved_isolated": corr_bytes / (ser_corr / 1e3) / 1e9,
+                 "avg_launch_ms_note": "the timed passes overlap the correlations with the "
+                                       "extraction, so a launch's event span includes time spent "
+                                       "waiting for CUs; isolated_avg_launch_ms is its own time"}
     corr_roof["frac"] = corr_roof["achieved"] / HBM_PEAK_GBS
+    corr_roof["frac_isolated"] = corr_roof["achieved_isolated"] / HBM_PEAK_GBS
     # the stage with the larger event-timed total is reported as "roofline"
     ext_roof = roofline
     if dominant == "correlate":
@@ -813,9 +835,10 @@ def precision_report(args, cfg_name, fft_n, top_p, n_sample=150):
 
 
 def measured_traffic(fft_n, K):
-    """HBM bytes of one full-tile correlation from the rocprofv3 FETCH_SIZE /
-    WRITE_SIZE runs summarised in profiles/, or None when the FFT kernel sources
-    differ from the ones measured (or the tile edge / component count differs)."""
+    """HBM bytes of one full-tile ttm_normalize_correlate call from the rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs summarised in profiles/, or None when the
+    kernel sources differ from the ones measured (or the tile edge, component
+    count or call differs)."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     try:
@@ -825,7 +848,8 @@ def measured_traffic(fft_n, K):
             h.update(open(os.path.join(root, f), "rb").read())
     except (OSError, ValueError, KeyError):
         return None
-    if h.hexdigest() != rec["sha256"] or rec["fft_n"] != fft_n or rec["K"] != K:
+    if (h.hexdigest() != rec["sha256"] or rec["fft_n"] != fft_n or rec["K"] != K
+            or rec.get("call") != "ttm_normalize_correlate"):
         return None
     return rec["bytes_per_launch"]
 

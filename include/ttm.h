@@ -80,7 +80,8 @@ typedef enum {
   TTM_OP_PREFILTER = 7,   /* nz x ny x nx = the volume (fft_n unused)     */
   TTM_OP_REFINE = 8,      /* nz = peaks, ny = the refinement radius r_s
                              rounded up (the size covers every smaller r_s) */
-  TTM_OP_TENSOR_WEDGE = 9 /* ttm_build_tensor_wedge (fft_n, nz, ny, nx unused) */
+  TTM_OP_TENSOR_WEDGE = 9, /* ttm_build_tensor_wedge (fft_n, nz, ny, nx unused) */
+  TTM_OP_NORM_CORR = 10    /* ttm_normalize_correlate (nz, ny, nx unused) */
 } ttm_op;
 
 typedef struct ttm_ctx ttm_ctx;
@@ -221,6 +222,24 @@ int ttm_correlate(ttm_ctx* ctx, const ttm_desc* desc, const float* g, const floa
                   int nz, int ny, int nx, const double* stats, const void* spec, int fft_n,
                   const int32_t box_lo[3], const int32_t box_size[3], int out_dtype,
                   void* C_out, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * ttm_normalize_box followed by ttm_correlate on one FFT tile, sharing the
+ * tile's forward transform of the centred g (both calls transform the same
+ * tile of g; the results equal those of the two calls, bit for bit):
+ *   w_out on the box (Eq. norm_f), then C_out = w * F^{-1}{F(g) conj(F(T_a))}.
+ *   spec       the template planes from ttm_template_spectra; their last
+ *              entry (index K) is the mask's, as for ttm_normalize_box
+ *   box_lo, box_size  host int32[3]: inside the valid region, at most
+ *              fft_n - L + 1 voxels along each axis (one tile)
+ *   ws         ttm_workspace_size(desc, TTM_OP_NORM_CORR, fft_n, 0, 0, 0) bytes
+ * Other arguments as the two calls.  Errors: as theirs, and TTM_EINVAL for a
+ * box larger than one tile.
+ */
+int ttm_normalize_correlate(ttm_ctx* ctx, const ttm_desc* desc, const float* g, int nz, int ny,
+                            int nx, const double* stats, const void* spec, int fft_n,
+                            const int32_t box_lo[3], const int32_t box_size[3], float* w_out,
+                            int out_dtype, void* C_out, void* ws, size_t ws_bytes, void* stream);
 
 /* ttm_extract mode bits. */
 #define TTM_SCORE 1       /* write c = ||C||_F                                   */

@@ -17,7 +17,7 @@ TTM_F32, TTM_BF16 = 0, 1
 TTM_OP_SPECTRA, TTM_OP_NORMALIZE, TTM_OP_CORRELATE, TTM_OP_PEAKS = 1, 2, 3, 4
 TTM_SCORE, TTM_ORIENT, TTM_START_MLP, TTM_START_ONLY, TTM_NO_SCREEN = 1, 2, 4, 8, 16
 TTM_OP_EXTRACT, TTM_OP_MLP_TRAIN, TTM_OP_PREFILTER, TTM_OP_REFINE = 5, 6, 7, 8
-TTM_OP_TENSOR_WEDGE = 9
+TTM_OP_TENSOR_WEDGE, TTM_OP_NORM_CORR = 9, 10
 
 STATUS_NAMES = {0: "TTM_OK", -1: "TTM_EINVAL", -2: "TTM_ENOMEM", -3: "TTM_EDEVICE",
                 -4: "TTM_EUNSUPPORTED", -5: "TTM_EWORKSPACE"}
@@ -76,6 +76,9 @@ SIGNATURES = {
     "ttm_correlate": (C.c_int, [vp, DP, vp, vp, C.c_int, C.c_int, C.c_int, vp, vp, C.c_int,
                                 C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int, vp, vp,
                                 C.c_size_t, vp]),
+    "ttm_normalize_correlate": (C.c_int, [vp, DP, vp, C.c_int, C.c_int, C.c_int, vp, vp, C.c_int,
+                                          C.POINTER(C.c_int32), C.POINTER(C.c_int32), vp, C.c_int, vp,
+                                          vp, C.c_size_t, vp]),
     "ttm_extract": (C.c_int, [vp, DP, vp, C.c_int, C.POINTER(C.c_int32), C.POINTER(ExtractOpts),
                               vp, vp, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), vp, vp,
                               C.c_size_t, vp]),

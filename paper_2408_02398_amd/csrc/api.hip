@@ -741,6 +741,12 @@ size_t ttm_workspace_size(const ttm_desc* desc, int op, int fft_n, int nz, int n
     case TTM_OP_TENSOR_WEDGE:
       if (desc->L < 1 || desc->L > 512) return 0;
       return wedge_workspace(desc->L, K);
+    case TTM_OP_NORM_CORR: {
+      if (!fft_ok(fft_n) || desc->L > fft_n) return 0;
+      const size_t step = (size_t)(fft_n - desc->L + 1);
+      return (size_t)(2 + K) * align256(spec_elems(fft_n) * 8) +
+             2 * align256(step * step * step * 4);
+    }
     default:
       return 0;
   }
@@ -1098,6 +1104,80 @@ int ttm_correlate(ttm_ctx* ctx, const ttm_desc* desc, const float* g, const floa
       }
     }
   }
+  return TTM_OK;
+}
+
+int ttm_normalize_correlate(ttm_ctx* ctx, const ttm_desc* desc, const float* g, int nz, int ny,
+                            int nx, const double* stats, const void* spec, int fft_n,
+                            const int32_t box_lo[3], const int32_t box_size[3], float* w_out,
+                            int out_dtype, void* C_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!ctx || !valid_desc(desc)) return TTM_EINVAL;
+  if (!fft_ok(fft_n)) {
+    set_error("ttm_normalize_correlate: FFT edge %d not supported", fft_n);
+    return TTM_EUNSUPPORTED;
+  }
+  const int L = desc->L, c = L / 2;
+  if (!g || !stats || !spec || !w_out || !C_out || !ws || !box_lo || !box_size || L > fft_n ||
+      (out_dtype != TTM_F32 && out_dtype != TTM_BF16)) {
+    set_error("ttm_normalize_correlate: null pointer, bad dtype or L > fft_n");
+    return TTM_EINVAL;
+  }
+  const int step = fft_n - L + 1;
+  const int dims[3] = {nz, ny, nx};
+  for (int a = 0; a < 3; ++a) {
+    if (box_size[a] < 1 || box_size[a] > step || box_lo[a] < c ||
+        box_lo[a] + box_size[a] - 1 > dims[a] - L + c) {
+      set_error("ttm_normalize_correlate: box axis %d [%d, +%d) outside the valid region [%d, %d] "
+                "or longer than one tile (%d)", a, box_lo[a], box_size[a], c, dims[a] - L + c, step);
+      return TTM_EINVAL;
+    }
+  }
+  const size_t need = ttm_workspace_size(desc, TTM_OP_NORM_CORR, fft_n, 0, 0, 0);
+  if (ws_bytes < need) {
+    set_error("ttm_normalize_correlate: workspace %zu < %zu", ws_bytes, need);
+    return TTM_EWORKSPACE;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  TTM_HIP(hipSetDevice(ctx->device));
+  const int K = ncomp(desc->degree, desc->dprime);
+  const size_t se = spec_elems(fft_n);
+  const size_t sb = align256(se * 8);
+  char* w = static_cast<char*>(ws);
+  cf* G1 = reinterpret_cast<cf*>(w);
+  cf* G2 = reinterpret_cast<cf*>(w + sb);
+  cf* work = reinterpret_cast<cf*>(w + 2 * sb);
+  float* s1 = reinterpret_cast<float*>(w + (2 + K) * sb);
+  float* s2 = reinterpret_cast<float*>(w + (2 + K) * sb + align256((size_t)step * step * step * 4));
+  const double M = mask_count(L, desc->mask_radius);
+  const size_t tse = tspec_elems(fft_n, L);
+  const cf* tspec = static_cast<const cf*>(spec);
+  const cf* mspec = tspec + (size_t)K * tse;
+  const float scale = 1.0f / ((float)fft_n * fft_n * fft_n);
+  const int oz = box_lo[0], oy = box_lo[1], ox = box_lo[2];
+  const int szz = box_size[0], syy = box_size[1], sxx = box_size[2];
+  // the centred g tile and its square, forward
+  RealSrc src{g, 0, nz, ny, nx, oz - c, oy - c, ox - c, stats, 0};
+  int rc = fft3d_forward(fft_n, src, 1, G1, se, ctx->twiddles, s);
+  if (rc) return rc;
+  src.square = 1;
+  rc = fft3d_forward(fft_n, src, 1, G2, se, ctx->twiddles, s);
+  if (rc) return rc;
+  // local sums with the mask, then w on the box
+  RealDst d1{s1, 0, 0, syy, sxx, 0, 0, 0, szz, syy, sxx, nullptr, 0, 0, 0, 0, 0, scale};
+  rc = fft3d_inverse_mul(fft_n, G1, mspec, 0, L, 1, nullptr, work, se, d1, ctx->twiddles, s);
+  if (rc) return rc;
+  RealDst d2 = d1;
+  d2.p = s2;
+  rc = fft3d_inverse_mul(fft_n, G2, mspec, 0, L, 1, nullptr, work, se, d2, ctx->twiddles, s);
+  if (rc) return rc;
+  const size_t nbx = (size_t)szz * syy * sxx;
+  hipLaunchKernelGGL(k_var_combine, dim3((unsigned)((nbx + 255) / 256)), dim3(256), 0, s, s1, s2,
+                     szz, syy, sxx, M, (double)desc->eps_w, stats, w_out, ny, nx, oz, oy, ox);
+  // the K correlations from the same forward transform
+  RealDst d{C_out, out_dtype, nbx, syy, sxx, 0, 0, 0, szz, syy, sxx, w_out, ny, nx, oz, oy, ox, scale};
+  rc = fft3d_inverse_mul(fft_n, G1, tspec, tse, L, K, stats, work, sb / 8, d, ctx->twiddles, s);
+  if (rc) return rc;
+  TTM_HIP(hipGetLastError());
   return TTM_OK;
 }
 

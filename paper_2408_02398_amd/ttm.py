@@ -177,6 +177,26 @@ def correlate(ctx: Context, desc: Desc, g: torch.Tensor, w: torch.Tensor, stats:
     return out
 
 
+def normalize_correlate(ctx: Context, desc: Desc, g: torch.Tensor, stats: torch.Tensor,
+                        spectra: torch.Tensor, fft_n: int, box_lo, box_size, w: torch.Tensor,
+                        dtype=torch.float32, out: torch.Tensor | None = None,
+                        ws: torch.Tensor | None = None) -> torch.Tensor:
+    """normalize_box then correlate on one FFT tile, sharing the tile's forward
+    transform of g: w on the box and C (K x bz x by x bx)."""
+    _need_cuda(g, stats, spectra, w)
+    nz, ny, nx = g.shape
+    K = n_components(desc.degree, desc.dprime)
+    if out is None:
+        out = torch.empty((K, *box_size), dtype=dtype, device=g.device)
+    code = L.TTM_BF16 if out.dtype == torch.bfloat16 else L.TTM_F32
+    if ws is None:
+        ws = _ws(desc, L.TTM_OP_NORM_CORR, fft_n, device=g.device)
+    call("ttm_normalize_correlate", ctx.h, C.byref(desc), _ptr(g), nz, ny, nx, _ptr(stats),
+         _ptr(spectra), fft_n, I32x3(*box_lo), I32x3(*box_size), _ptr(w), code, _ptr(out),
+         _ptr(ws), ws.numel(), _stream())
+    return out
+
+
 def extract(ctx: Context, desc: Desc, Cf: torch.Tensor, *, score=None, lam=None, direction=None,
             out_lo=(0, 0, 0), out_dims=None, starts: torch.Tensor | None = None,
             orient: bool = True, max_iter: int = 500, tol: float = 1e-5, newton: int = 2,
@@ -517,7 +537,7 @@ class Engine:
         self.side = torch.cuda.Stream(device=dev)
         self.ws_pre = _ws(desc, L.TTM_OP_PREFILTER, 0, self.shape, device=dev)
         self.ws_norm = _ws(desc, L.TTM_OP_NORMALIZE, fft_n, self.shape, device=dev)
-        self.ws_corr = _ws(desc, L.TTM_OP_CORRELATE, fft_n, self.shape, device=dev)
+        self.ws_nc = _ws(desc, L.TTM_OP_NORM_CORR, fft_n, device=dev)
         self.ws_peaks = _ws(desc, L.TTM_OP_PEAKS, fft_n, self.shape, device=dev)
         self.ws_extract = _ws(desc, L.TTM_OP_EXTRACT, 0, (step, step, step), device=dev)
         self.fallbacks = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -565,24 +585,18 @@ class Engine:
             b = k % 2
             Ct = self.Cbufs[b][: self.K * size[0] * size[1] * size[2]].view(self.K, *size)
             with torch.cuda.stream(side):
-                # the tile's local normalisation (Eq. norm_f) runs just before its
-                # correlation, so only the first tile's is on the critical path
-                n0, n1 = ev(), ev()
-                rec(n0, side)
-                normalize_box(self.ctx, self.desc, g, stats, self.spectra, self.fft_n, lo, size, w,
-                              ws=self.ws_norm)
-                rec(n1, side)
+                # the tile's local normalisation (Eq. norm_f) and its correlation
+                # share the forward transform of the tile of g
                 if free[b] is not None:
                     side.wait_event(free[b])
                 a0, a1 = ev(), ev()
                 rec(a0, side)
-                correlate(self.ctx, self.desc, g, w, stats, self.spectra, self.fft_n, lo, size,
-                          out=Ct, ws=self.ws_corr)
+                normalize_correlate(self.ctx, self.desc, g, stats, self.spectra, self.fft_n, lo,
+                                    size, w, out=Ct, ws=self.ws_nc)
                 rec(a1, side)
                 ready = torch.cuda.Event()
                 ready.record(side)
             if timing is not None:
-                timing["normalize"].append((n0, n1))
                 timing["correlate"].append((a0, a1, size))
             main.wait_event(ready)
             x0, x1 = ev(), ev()

@@ -490,3 +490,28 @@ def test_wedge_tensor_template_matches_oracle(T, ctx, L, dprime):
     # the wedge changes the template: Alg. 1 without it differs
     T0 = orc.tensor_template(tn, Q, n, dprime=dprime)
     assert np.linalg.norm(T0 - To) / np.linalg.norm(To) > 1e-2
+
+
+def test_normalize_correlate_equals_the_two_calls(T, ctx, small):
+    """ttm_normalize_correlate on one tile = ttm_normalize_box then
+    ttm_correlate on it, bit for bit (the same forward transform of g)."""
+    d = T.make_desc(small["n"], small["L"], small["r"])
+    N = 32
+    spec = T.template_spectra(ctx, d, cuda(small["Tt"]), N)
+    vol = cuda(small["w"].volume)
+    g, w, stats = T.normalize(ctx, d, vol, spec, N)
+    step = N - small["L"] + 1
+    lo, hi = T.valid_bounds(vol.shape, small["L"])
+    for box_lo, size in (((lo[0], lo[1], lo[2]), (step, step, step)),
+                         ((hi[0] - 6, hi[1] - 13, lo[2] + 3), (7, 14, 9))):
+        w1 = torch.zeros_like(w)
+        T.normalize_box(ctx, d, g, stats, spec, N, box_lo, size, w1)
+        C1 = T.correlate(ctx, d, g, w1, stats, spec, N, box_lo, size)
+        w2 = torch.zeros_like(w)
+        C2 = T.normalize_correlate(ctx, d, g, stats, spec, N, box_lo, size, w2)
+        torch.cuda.synchronize()
+        assert torch.equal(w1, w2) and torch.equal(C1, C2)
+    from paper_2408_02398_amd._lib import TTMError
+    with pytest.raises(TTMError):
+        T.normalize_correlate(ctx, d, g, stats, spec, N, (lo[0], lo[1], lo[2]), (step + 1, 4, 4),
+                              torch.zeros_like(w))
