@@ -110,7 +110,8 @@ size_t ttm_spectrum_elems(int fft_n);
 /* Complex elements of one template spectrum from ttm_template_spectra:
  * L * (N/2 + 1) * N, or 0 for an unsupported edge or L outside 1..fft_n. */
 size_t ttm_template_spectrum_elems(int fft_n, int L);
-/* FFT edges the library supports (powers of two 32..512): 1 if supported. */
+/* FFT edges the library supports (32, 64, 128, 256, 512 and the mixed-radix
+ * 96, 160, 192): 1 if supported. */
 int ttm_fft_supported(int fft_n);
 
 /* Workspace bytes for an operation at FFT edge fft_n on an nz x ny x nx
@@ -141,7 +142,7 @@ int ttm_build_tensor(ttm_ctx* ctx, const ttm_desc* desc, const float* tmpl,
  * t'_q = t' rotated by R(q) (trilinear, as ttm_build_tensor); W zeroes the
  * Fourier coefficients with |k_z| > tan(wedge_deg) |k_x| (tilt axis y, beam z;
  * DC kept), applied on the template box zero-padded to P^3, P the smallest
- * supported FFT edge >= L (periodic transform); N_m(v) = m (v - mu) / sigma
+ * power of two >= max(L, 32) (periodic transform); N_m(v) = m (v - mu) / sigma
  * with mu = <v, m>/M and sigma^2 = <v^2, m> - <v, m>^2/M (Eq. norm_t without
  * a second prefilter).  The wedge lies in the tomogram's frame, so it acts
  * after each rotation: filtering t' once before Alg. 1 would turn it with the

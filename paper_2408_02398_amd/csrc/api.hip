@@ -605,7 +605,9 @@ bool mlp_form_ok(const ttm_desc* d) {
          (d->dprime == 4 && (d->degree == 2 || d->degree == 4));
 }
 
-bool fft_ok(int N) { return N == 32 || N == 64 || N == 128 || N == 256 || N == 512; }
+bool fft_ok(int N) {
+  return N == 32 || N == 64 || N == 128 || N == 256 || N == 512 || N == 96 || N == 160 || N == 192;
+}
 
 size_t spec_elems(int N) { return (size_t)N * (N / 2 + 1) * N; }
 // x/y-transformed template: its L nonzero z planes only

@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) void k_r2c_x(RealSrc src, 
   for (int e = tid; e < NH * kRowsX; e += NP * T) {
     const int r = e % kRowsX, kx = e / kRowsX, pp = r >> 1;
     const cf zk = xl[pp * S + lds_idx(kx)];
-    const cf zn = cconj(xl[pp * S + lds_idx((N - kx) & (N - 1))]);
+    const cf zn = cconj(xl[pp * S + lds_idx((N - kx) % N)]);
     cf o;
     if ((r & 1) == 0) {
       o = cscale(cadd(zk, zn), 0.5f);              // (Z[k] + conj Z[N-k]) / 2
@@ -384,9 +384,9 @@ __global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) __attribute__((amdgpu_wave
 }
 
 __global__ void k_twiddles(cf* tw_all) {
-  const int sizes[5] = {32, 64, 128, 256, 512};
+  const int sizes[8] = {32, 64, 128, 256, 512, 96, 160, 192};
   int off = 0;
-  for (int s = 0; s < 5; ++s) {
+  for (int s = 0; s < 8; ++s) {
     const int N = sizes[s];
     for (int e = threadIdx.x; e < N; e += blockDim.x) {
       double sv, cv;
@@ -474,6 +474,9 @@ int twiddle_offset(int N) {
     case 128: return 96;
     case 256: return 224;
     case 512: return 480;
+    case 96: return 992;
+    case 160: return 1088;
+    case 192: return 1248;
     default: return -1;
   }
 }
@@ -493,6 +496,9 @@ int fft3d_forward(int N, const RealSrc& src, int batch, cf* spec, size_t spec_st
     case 128: return forward_n<128>(src, batch, spec, spec_stride, tw, s);
     case 256: return forward_n<256>(src, batch, spec, spec_stride, tw, s);
     case 512: return forward_n<512>(src, batch, spec, spec_stride, tw, s);
+    case 96: return forward_n<96>(src, batch, spec, spec_stride, tw, s);
+    case 160: return forward_n<160>(src, batch, spec, spec_stride, tw, s);
+    case 192: return forward_n<192>(src, batch, spec, spec_stride, tw, s);
     default: set_error("unsupported FFT edge %d", N); return -4;
   }
 }
@@ -506,6 +512,9 @@ int fft3d_forward_planes(int N, const RealSrc& src, int batch, int planes, cf* o
     case 128: return forward_planes_n<128>(src, batch, planes, out, out_stride, tw, s);
     case 256: return forward_planes_n<256>(src, batch, planes, out, out_stride, tw, s);
     case 512: return forward_planes_n<512>(src, batch, planes, out, out_stride, tw, s);
+    case 96: return forward_planes_n<96>(src, batch, planes, out, out_stride, tw, s);
+    case 160: return forward_planes_n<160>(src, batch, planes, out, out_stride, tw, s);
+    case 192: return forward_planes_n<192>(src, batch, planes, out, out_stride, tw, s);
     default: set_error("unsupported FFT edge %d", N); return -4;
   }
 }
@@ -520,6 +529,9 @@ int fft3d_inverse_mul(int N, const cf* G, const cf* Sp, size_t s_stride, int s_p
     case 128: return inverse_n<128>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s);
     case 256: return inverse_n<256>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s);
     case 512: return inverse_n<512>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s);
+    case 96: return inverse_n<96>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s);
+    case 160: return inverse_n<160>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s);
+    case 192: return inverse_n<192>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s);
     default: set_error("unsupported FFT edge %d", N); return -4;
   }
 }

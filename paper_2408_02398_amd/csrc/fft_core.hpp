@@ -3,7 +3,8 @@
 //
 // A length-N transform is spread over T threads; thread t owns the E = N/T
 // elements with index t + T*j (j < E), before and after the transform.  The
-// transform runs as a sequence of Stockham radix-R stages (N = R0*R1[*R2]):
+// transform runs as a sequence of Stockham radix-R stages (N = R0*R1[*R2];
+// R0 may be a composite 6, 10 or 12 for the edges 96, 160 and 192):
 // butterfly i = t + T*b reads x[i + m*N/R] (m < R), twiddles by
 // W_{P*R}^{(i mod P)*m}, applies a radix-R DFT in registers and writes
 // x'[(i - i mod P)*R + i mod P + m*P], P being the product of the earlier
@@ -81,11 +82,131 @@ __device__ __forceinline__ void dft4(cf& a0, cf& a1, cf& a2, cf& a3) {
   a3 = csub(t1, t3);
 }
 
-// Radix-R DFT of a[0..R-1] in place, natural order in and out, R in {2,4,8,16}.
-// R = 8 and 16 use one four-step split: n = n1 + R1 n2, k = R2 k1 + k2.
+// Radix-3 DFT: X1,2 = a0 - (a1 + a2)/2 -+ i (sqrt(3)/2)(a1 - a2) (forward; +- inverse).
+template <bool INV>
+__device__ __forceinline__ void dft3(cf& a0, cf& a1, cf& a2) {
+  const cf t1 = cadd(a1, a2), t2 = csub(a1, a2);
+  const cf m = cf{a0.x - 0.5f * t1.x, a0.y - 0.5f * t1.y};
+  const cf r = rot_quarter<INV>(cscale(t2, 0.86602540378443865f));
+  a0 = cadd(a0, t1);
+  a1 = cadd(m, r);
+  a2 = csub(m, r);
+}
+
+// Radix-5 DFT with c_k = cos(2 pi k/5), s_k = sin(2 pi k/5):
+// X1,4 = a0 + c1 (a1 + a4) + c2 (a2 + a3) -+ i (s1 (a1 - a4) + s2 (a2 - a3)),
+// X2,3 = a0 + c2 (a1 + a4) + c1 (a2 + a3) -+ i (s2 (a1 - a4) - s1 (a2 - a3))
+// (forward; the signs of the i terms swap for the inverse).
+template <bool INV>
+__device__ __forceinline__ void dft5(cf& a0, cf& a1, cf& a2, cf& a3, cf& a4) {
+  constexpr float c1 = 0.30901699437494742f, c2 = -0.80901699437494742f;
+  constexpr float s1 = 0.95105651629515357f, s2 = 0.58778525229247313f;
+  const cf t1 = cadd(a1, a4), t2 = cadd(a2, a3), t3 = csub(a1, a4), t4 = csub(a2, a3);
+  const cf m1 = cf{a0.x + c1 * t1.x + c2 * t2.x, a0.y + c1 * t1.y + c2 * t2.y};
+  const cf m2 = cf{a0.x + c2 * t1.x + c1 * t2.x, a0.y + c2 * t1.y + c1 * t2.y};
+  const cf n1 = rot_quarter<INV>(cf{s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y});
+  const cf n2 = rot_quarter<INV>(cf{s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y});
+  a0 = cadd(a0, cadd(t1, t2));
+  a1 = cadd(m1, n1);
+  a4 = csub(m1, n1);
+  a2 = cadd(m2, n2);
+  a3 = csub(m2, n2);
+}
+
+// cos and sin of 2 pi e / R for the composite radices 6, 10, 12
+template <int R> struct RootTable;
+template <> struct RootTable<6> {
+  static constexpr float c[6] = {1.0f, 0.5f, -0.5f, -1.0f, -0.5f, 0.5f};
+  static constexpr float s[6] = {0.0f, 0.86602540378443865f, 0.86602540378443865f, 0.0f,
+                                 -0.86602540378443865f, -0.86602540378443865f};
+};
+template <> struct RootTable<10> {
+  static constexpr float c[10] = {1.0f, 0.80901699437494742f, 0.30901699437494742f,
+                                  -0.30901699437494742f, -0.80901699437494742f, -1.0f,
+                                  -0.80901699437494742f, -0.30901699437494742f,
+                                  0.30901699437494742f, 0.80901699437494742f};
+  static constexpr float s[10] = {0.0f, 0.58778525229247313f, 0.95105651629515357f,
+                                  0.95105651629515357f, 0.58778525229247313f, 0.0f,
+                                  -0.58778525229247313f, -0.95105651629515357f,
+                                  -0.95105651629515357f, -0.58778525229247313f};
+};
+template <> struct RootTable<12> {
+  static constexpr float c[12] = {1.0f, 0.86602540378443865f, 0.5f, 0.0f, -0.5f,
+                                  -0.86602540378443865f, -1.0f, -0.86602540378443865f, -0.5f,
+                                  0.0f, 0.5f, 0.86602540378443865f};
+  static constexpr float s[12] = {0.0f, 0.5f, 0.86602540378443865f, 1.0f, 0.86602540378443865f,
+                                  0.5f, 0.0f, -0.5f, -0.86602540378443865f, -1.0f,
+                                  -0.86602540378443865f, -0.5f};
+};
+
+// a * W_R^e, W_R = exp(-2 pi i / R) (forward) or its conjugate (inverse)
+template <int R, int E, bool INV>
+__device__ __forceinline__ cf twiddle_r(cf a) {
+  constexpr int e = ((E % R) + R) % R;
+  if constexpr (e == 0) {
+    return a;
+  } else {
+    const float c = RootTable<R>::c[e];
+    const float s = INV ? RootTable<R>::s[e] : -RootTable<R>::s[e];
+    return cf{a.x * c - a.y * s, a.x * s + a.y * c};
+  }
+}
+
+template <int R, bool INV> __device__ __forceinline__ void dft(cf* a);
+
+// y[n1 R2 + k2] *= W_R^{n1 k2} for every n1, k2 (exponents fixed at compile time)
+template <int R, int R2, bool INV, int I = 0>
+__device__ __forceinline__ void twiddle_split(cf* y) {
+  if constexpr (I < R) {
+    y[I] = twiddle_r<R, (I / R2) * (I % R2), INV>(y[I]);
+    twiddle_split<R, R2, INV, I + 1>(y);
+  }
+}
+
+// Composite radix R = R1 * R2 by one four-step split: n = n1 + R1 n2,
+// k = R2 k1 + k2: R1 transforms of length R2 over n2, twiddles W_R^{n1 k2},
+// R2 transforms of length R1 over n1.
+template <int R1, int R2, bool INV>
+__device__ __forceinline__ void dft_split(cf* a) {
+  constexpr int R = R1 * R2;
+  cf y[R];
+#pragma unroll
+  for (int n1 = 0; n1 < R1; ++n1) {
+    cf b[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) b[n2] = a[n1 + R1 * n2];
+    dft<R2, INV>(b);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) y[n1 * R2 + k2] = b[k2];
+  }
+  twiddle_split<R, R2, INV>(y);
+#pragma unroll
+  for (int k2 = 0; k2 < R2; ++k2) {
+    cf b[R1];
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) b[n1] = y[n1 * R2 + k2];
+    dft<R1, INV>(b);
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) a[R2 * k1 + k2] = b[k1];
+  }
+}
+
+// Radix-R DFT of a[0..R-1] in place, natural order in and out, R in
+// {2, 3, 4, 5, 6, 8, 10, 12, 16}.  R = 8 and 16 use one four-step split:
+// n = n1 + R1 n2, k = R2 k1 + k2; 6, 10 and 12 use dft_split.
 template <int R, bool INV>
 __device__ __forceinline__ void dft(cf* a) {
   if constexpr (R == 1) {
+  } else if constexpr (R == 3) {
+    dft3<INV>(a[0], a[1], a[2]);
+  } else if constexpr (R == 5) {
+    dft5<INV>(a[0], a[1], a[2], a[3], a[4]);
+  } else if constexpr (R == 6) {
+    dft_split<2, 3, INV>(a);
+  } else if constexpr (R == 10) {
+    dft_split<2, 5, INV>(a);
+  } else if constexpr (R == 12) {
+    dft_split<3, 4, INV>(a);
   } else if constexpr (R == 2) {
     dft2<INV>(a[0], a[1]);
   } else if constexpr (R == 4) {
@@ -148,6 +269,10 @@ template <> struct Plan<64> { static constexpr int T = 8, R0 = 8, R1 = 8, R2 = 1
 template <> struct Plan<128> { static constexpr int T = 8, R0 = 8, R1 = 16, R2 = 1; };
 template <> struct Plan<256> { static constexpr int T = 16, R0 = 16, R1 = 16, R2 = 1; };
 template <> struct Plan<512> { static constexpr int T = 64, R0 = 8, R1 = 8, R2 = 8; };
+// edges with a factor 3 or 5 (96 = 6 * 4 * 4, 160 = 10 * 4 * 4, 192 = 12 * 4 * 4)
+template <> struct Plan<96> { static constexpr int T = 8, R0 = 6, R1 = 4, R2 = 4; };
+template <> struct Plan<160> { static constexpr int T = 8, R0 = 10, R1 = 4, R2 = 4; };
+template <> struct Plan<192> { static constexpr int T = 16, R0 = 12, R1 = 4, R2 = 4; };
 
 // LDS footprint (complex elements) of one transform's exchange area.  Inside
 // an area one padding element per 16 keeps stride-16 exchanges conflict-free.

@@ -58,7 +58,7 @@ struct RealDst {
 
 // Twiddle table for edge N inside the context table.
 int twiddle_offset(int N);
-constexpr int kTwiddleTotal = 32 + 64 + 128 + 256 + 512;
+constexpr int kTwiddleTotal = 32 + 64 + 128 + 256 + 512 + 96 + 160 + 192;
 
 // Forward 3D R2C of `batch` N^3 tiles into half spectra [kz][kx][ky]
 // (spec_stride complex elements apart).

@@ -631,7 +631,7 @@ class Engine:
 # batches of uneven subtomograms and several templates (one graph launch)
 # ----------------------------------------------------------------------------
 
-FFT_EDGES = (64, 128, 256, 512)
+FFT_EDGES = (64, 96, 128, 160, 192, 256, 512)
 
 
 def tiles_for(shape, L_edge: int, fft_n: int) -> int:
@@ -642,13 +642,14 @@ def tiles_for(shape, L_edge: int, fft_n: int) -> int:
 
 
 def pick_fft(shape, L_edge: int, cost: dict | None = None) -> int:
-    """FFT edge of least modelled cost: tiles(N) x cost(N); cost defaults to N^3 log2 N."""
+    """FFT edge of least modelled cost: tiles(N) x cost(N); cost defaults to
+    N^3 log2 N; with a measured cost only the measured edges compete."""
     best, best_c = None, None
     for N in FFT_EDGES:
         t = tiles_for(shape, L_edge, N)
-        if t == 0:
+        if t == 0 or (cost and N not in cost):
             continue
-        c = t * (cost[N] if cost and N in cost else N ** 3 * np.log2(N))
+        c = t * (cost[N] if cost else N ** 3 * np.log2(N))
         if best_c is None or c < best_c:
             best, best_c = N, c
     if best is None:

@@ -43,8 +43,11 @@ def test_host_only_queries():
     assert lib.ttm_spectrum_elems(256) == 256 * 129 * 256
     assert lib.ttm_template_spectrum_elems(256, 32) == 32 * 129 * 256
     assert lib.ttm_template_spectrum_elems(256, 257) == 0
-    assert lib.ttm_template_spectrum_elems(96, 16) == 0
-    assert lib.ttm_fft_supported(256) == 1 and lib.ttm_fft_supported(96) == 0
+    assert lib.ttm_template_spectrum_elems(96, 16) == 16 * 49 * 96
+    assert lib.ttm_template_spectrum_elems(100, 16) == 0
+    assert lib.ttm_fft_supported(256) == 1 and lib.ttm_fft_supported(96) == 1
+    assert lib.ttm_fft_supported(160) == 1 and lib.ttm_fft_supported(192) == 1
+    assert lib.ttm_fft_supported(100) == 0 and lib.ttm_fft_supported(1024) == 0
     d = ttm.make_desc(6, 40, 17.0)
     ws = lib.ttm_workspace_size(ctypes.byref(d), L.TTM_OP_CORRELATE, 256, 512, 928, 928)
     assert ws >= 29 * 256 * 129 * 256 * 8

@@ -114,11 +114,14 @@ def test_batch_graph_replays_match_eager_and_single_passes(T, ctx):
 def test_pick_fft_and_tiles(T):
     assert T.tiles_for((96, 96, 96), 40, 128) == 1
     assert T.tiles_for((192, 192, 192), 40, 128) == 8
-    assert T.pick_fft((96, 96, 96), 40) == 128
-    # default model N^3 log2 N: one 256^3 tile (1.3e8) loses to eight 128^3 tiles (1.2e8)
-    assert T.pick_fft((192, 160, 192), 24) == 128
-    # a measured cost that makes small tiles cheap enough changes the choice
+    assert T.tiles_for((192, 192, 192), 40, 192) == 1
+    # default model N^3 log2 N: one 96^3 tile beats one 128^3 tile
+    assert T.pick_fft((96, 96, 96), 40) == 96
+    # one 192^3 tile (5.4e7) beats eight 128^3 tiles (1.2e8) and four 160^3 tiles (1.2e8)
+    assert T.pick_fft((192, 160, 192), 24) == 192
+    # with measured costs only the measured edges compete; cheap small tiles win
     assert T.pick_fft((192, 192, 192), 40, {64: 0.001, 128: 1.0, 256: 100.0, 512: 1e4}) == 64
+    assert T.pick_fft((192, 192, 192), 40, {128: 1.0, 192: 2.0}) == 192
 
 
 def test_batch_c5_shapes_match_oracle(T, ctx):

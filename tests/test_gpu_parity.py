@@ -46,7 +46,7 @@ def host(t):
 
 
 # ------------------------------------------------------------------ FFT
-@pytest.mark.parametrize("N", [32, 64, 128, 256])
+@pytest.mark.parametrize("N", [32, 64, 96, 128, 160, 192, 256])
 def test_fft_r2c_matches_numpy(T, ctx, N):
     print(f"[fft r2c N={N}]", flush=True)
     x = np.random.default_rng(N).standard_normal((N, N, N)).astype(np.float32)
@@ -56,8 +56,10 @@ def test_fft_r2c_matches_numpy(T, ctx, N):
     assert np.linalg.norm(got - want) / np.linalg.norm(want) < 2e-6
 
 
-def test_fft_small_direct_dft(T, ctx):
-    N = 32
+@pytest.mark.parametrize("N", [32, 96])
+def test_fft_small_direct_dft(T, ctx, N):
+    """The forward transform against the DFT written out (no FFT library),
+    for a power of two and for a mixed-radix edge (96 = 6 * 4 * 4)."""
     x = np.random.default_rng(5).standard_normal((N, N, N)).astype(np.float32)
     n = np.arange(N)
     W = np.exp(-2j * np.pi * np.outer(n, n) / N)              # DFT matrix, by definition
@@ -67,7 +69,7 @@ def test_fft_small_direct_dft(T, ctx):
     assert np.linalg.norm(got - want) / np.linalg.norm(want) < 2e-6
 
 
-@pytest.mark.parametrize("N,L", [(32, 16), (64, 23), (256, 40)])
+@pytest.mark.parametrize("N,L", [(32, 16), (64, 23), (96, 24), (160, 40), (192, 33), (256, 40)])
 def test_template_planes_match_dft(T, ctx, N, L):
     """Template arrays of ttm_template_spectra: the K fields and the mask placed at
     the origin of a zero N^3 tile, transformed along x (half spectrum) and y, their
@@ -90,7 +92,7 @@ def test_template_planes_match_dft(T, ctx, N, L):
         assert np.linalg.norm(got[a] - want[a]) / np.linalg.norm(want[a]) < 2e-6, a
 
 
-@pytest.mark.parametrize("N", [32, 64, 256])
+@pytest.mark.parametrize("N", [32, 64, 96, 160, 192, 256])
 def test_fft_roundtrip(T, ctx, N):
     x = np.random.default_rng(N + 1).standard_normal((N, N, N)).astype(np.float32)
     spec = T.fft3d_r2c(ctx, cuda(x))
@@ -189,7 +191,8 @@ def test_correlate_and_score_match_oracle(T, ctx, small, dtype):
     assert np.max(np.abs(sg - cs) / floor) < tol
 
 
-@pytest.mark.parametrize("N,L", [(64, 48), (128, 64), (256, 64), (512, 64)])
+@pytest.mark.parametrize("N,L", [(64, 48), (96, 40), (128, 64), (160, 48), (192, 64), (256, 64),
+                                 (512, 64)])
 def test_large_templates_sampled(T, ctx, N, L):
     """The largest templates (L = 64) and ones whose z planes need several
     slots per thread in the Z-inverse pass (8 at N = 64 and 128, 4 at N = 256,
