@@ -597,7 +597,9 @@ def bench_batch(args, top_p):
             "config": {"workload": "c5_batch64_n6", "items": len(items), "degree": n, "K": 28,
                        "edges": sorted(set(int(s[0]) for s in shapes)), "templates": len(templates),
                        "fft_edges_chosen": {str(k): ttm.BatchEngine.__name__ and int(sum(1 for f in results[main]["be"].fft if f == k)) for k in sorted(set(results[main]["be"].fft))},
-                       "voxels": nvox, "top_p_per_item": top_p, "launch": "one HIP graph per batch"},
+                       "voxels": nvox, "top_p_per_item": top_p,
+                       "launch": "one HIP graph per batch",
+                       "graph_branches": results[main]["be"].branches},
             "start_mode": {m: {"voxels_per_s": nvox / (results[m]["ms"] / 1e3), "ms_per_step": results[m]["ms"],
                                "fallback_voxels_per_step": results[m]["fallbacks"] if m != "plain" else None}
                            for m in results},

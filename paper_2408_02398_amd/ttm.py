@@ -667,14 +667,25 @@ class BatchEngine:
     ``score[i]``, ``lam[i]``, ``direction[i]``, ``peaks[i]``, ``vals[i]`` and
     ``n_found[i]`` (device).  ``cost`` maps FFT edge -> measured cost of one tile
     (see ``autotune``); without it the edge is chosen by N^3 log N.
+
+    The items' normalisation and correlation chains are independent, and one
+    small tile does not fill the GPU, so they are recorded on ``branches``
+    streams (items dealt out by modelled cost, largest first, each to the
+    least loaded branch, every branch with its own workspaces): the graph holds
+    them as parallel branches.  The extractions follow once every branch is
+    done (letting a template's extraction overlap the next template's
+    correlations was slower: the persistent extraction kernels hold the CUs),
+    then Find Peaks.  The outputs do not depend on the branch count.
     """
 
     def __init__(self, ctx: Context, templates, shapes, owner, starts: torch.Tensor, top_p: int,
                  mlps=None, kappa: float = 0.0, field_dtype=torch.float32, cost: dict | None = None,
-                 orient: bool = True):
+                 orient: bool = True, branches: int = 8):
         self.ctx, self.templates, self.shapes, self.owner = ctx, templates, [tuple(s) for s in shapes], owner
         self.starts, self.top_p, self.mlps, self.kappa = starts, top_p, mlps, kappa
         self.orient, self.field_dtype = orient, field_dtype
+        if branches < 1:
+            raise ValueError("branches must be at least 1")
         dev = starts.device
         self.fft = [pick_fft(s, templates[o][0].L, cost) for s, o in zip(self.shapes, owner)]
         self.spectra = {}
@@ -699,8 +710,20 @@ class BatchEngine:
             d = templates[o][0]
             ws_norm = max(ws_norm, lib.ttm_workspace_size(C.byref(d), L.TTM_OP_NORMALIZE, N, *s))
             ws_corr = max(ws_corr, lib.ttm_workspace_size(C.byref(d), L.TTM_OP_CORRELATE, N, *s))
-        self.ws_norm = torch.empty(ws_norm, dtype=torch.uint8, device=dev)
-        self.ws_corr = torch.empty(ws_corr, dtype=torch.uint8, device=dev)
+        # branch assignment: items by modelled cost (largest first), each to
+        # the least loaded branch
+        self.branches = min(branches, len(self.shapes)) if self.shapes else 1
+        self.branch_items = [[] for _ in range(self.branches)]
+        load_b = [0.0] * self.branches
+        item_cost = [tiles_for(s, templates[o][0].L, N) * (cost[N] if cost else N ** 3 * np.log2(N))
+                     for s, o, N in zip(self.shapes, owner, self.fft)]
+        for i in sorted(range(len(self.shapes)), key=lambda j: -item_cost[j]):
+            b = min(range(self.branches), key=lambda k: load_b[k])
+            self.branch_items[b].append(i)
+            load_b[b] += item_cost[i]
+        self.ws_norm = [torch.empty(ws_norm, dtype=torch.uint8, device=dev) for _ in range(self.branches)]
+        self.ws_corr = [torch.empty(ws_corr, dtype=torch.uint8, device=dev) for _ in range(self.branches)]
+        self.streams = [torch.cuda.Stream(device=dev) for _ in range(self.branches)]
         # each item's field in its own slice of its template's buffer, so that one
         # extraction call serves every item of a template
         self.groups = sorted(set(owner))
@@ -746,30 +769,36 @@ class BatchEngine:
         self.stats = torch.zeros((len(self.shapes), 2), dtype=torch.float64, device=dev)
         self.graph = None
 
-    def _normalize_into(self, i):
-        d = self.templates[self.owner[i]][0]
+    def _correlate_item(self, i, b):
+        """Item i's normalisation and correlation on the current stream with
+        branch b's workspaces."""
+        o = self.owner[i]
+        d = self.templates[o][0]
         N = self.fft[i]
         nz, ny, nx = self.shapes[i]
-        spec = self.spectra[(self.owner[i], N)]
+        spec = self.spectra[(o, N)]
         call("ttm_normalize", self.ctx.h, C.byref(d), _ptr(self.volumes[i]), nz, ny, nx,
              _ptr(spec[-1]), N, _ptr(self.g[i]), _ptr(self.w[i]), _ptr(self.stats[i]),
-             _ptr(self.ws_norm), self.ws_norm.numel(), _stream())
+             _ptr(self.ws_norm[b]), self.ws_norm[b].numel(), _stream())
+        lo, hi = valid_bounds(self.shapes[i], d.L)
+        size = tuple(h - l + 1 for l, h in zip(lo, hi))
+        correlate(self.ctx, d, self.g[i], self.w[i], self.stats[i], spec, N, lo, size,
+                  out=self.Cslice[i], ws=self.ws_corr[b])
 
     def run_eager(self):
-        """The whole batch on the current stream (also what the graph records):
-        each item's normalisation and correlation into its slice of its
-        template's field buffer, one extraction per template, one Find Peaks
-        launch for every item."""
-        for i, s in enumerate(self.shapes):
-            o = self.owner[i]
-            d = self.templates[o][0]
-            N = self.fft[i]
-            spec = self.spectra[(o, N)]
-            self._normalize_into(i)
-            lo, hi = valid_bounds(s, d.L)
-            size = tuple(h - l + 1 for l, h in zip(lo, hi))
-            correlate(self.ctx, d, self.g[i], self.w[i], self.stats[i], spec, N, lo, size,
-                      out=self.Cslice[i], ws=self.ws_corr)
+        """The whole batch, ordered after the current stream's earlier work and
+        before its later work (also what the graph records): each item's
+        normalisation and correlation into its slice of its template's field
+        buffer on its branch, then one extraction per template, then one Find
+        Peaks launch for every item."""
+        main = torch.cuda.current_stream()
+        for b, st in enumerate(self.streams):
+            st.wait_stream(main)
+            with torch.cuda.stream(st):
+                for i in self.branch_items[b]:
+                    self._correlate_item(i, b)
+        for st in self.streams:
+            main.wait_stream(st)
         for o in self.groups:
             mlp = self.mlps[o] if self.mlps is not None else None
             self.extract_batches[o].run(self.starts, self.ws_ext, mlp=mlp, kappa=self.kappa,

@@ -52,7 +52,7 @@ def test_async_peaks_equal_sync_peaks(T, ctx, seed, shape, P, D):
     assert torch.equal(peaks[:n], pk) and torch.equal(vals[:n], pv)
 
 
-def _batch(T, ctx):
+def _batch(T, ctx, branches=4):
     rng = np.random.default_rng(11)
     templates, tmodels = [], []
     for i, (L, r) in enumerate([(12, 5.0), (16, 7.0)]):
@@ -71,7 +71,7 @@ def _batch(T, ctx):
         rot = synth.random_rotations(rng, 1)
         v += 3.0 * synth.render_copies(v.shape, tm, c[None], rot)
     starts = cuda(synth.start_vectors())
-    be = T.BatchEngine(ctx, templates, shapes, owner, starts, top_p=3)
+    be = T.BatchEngine(ctx, templates, shapes, owner, starts, top_p=3, branches=branches)
     return be, vols, templates, shapes, owner, starts
 
 
@@ -109,6 +109,28 @@ def test_batch_graph_replays_match_eager_and_single_passes(T, ctx):
             assert torch.equal(be.direction[i], ref[i][2]), (rep, i)
             assert int(be.n_found[i].item()) == ref[i][4]
             assert torch.equal(be.peaks[i], ref[i][3]), (rep, i)
+
+
+def test_batch_branch_count_does_not_change_outputs(T, ctx):
+    """The items' correlation chains on 1, 3 or 4 graph branches give the
+    same fields, maps and peaks bit for bit, over two replays."""
+    outs = []
+    for branches in (1, 3, 4):
+        be, vols, *_ = _batch(T, ctx, branches=branches)
+        assert be.branches == branches
+        assert sorted(i for b in be.branch_items for i in b) == list(range(len(be.shapes)))
+        for i, v in enumerate(vols):
+            be.volumes[i].copy_(cuda(v))
+        be.capture()
+        for _ in range(2):
+            be.replay()
+        torch.cuda.synchronize()
+        outs.append([torch.cat([be.Cslice[i].reshape(-1).float(), be.score[i].reshape(-1),
+                                be.lam[i].reshape(-1), be.direction[i].reshape(-1),
+                                be.peaks[i].reshape(-1).float()]) for i in range(len(be.shapes))])
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert torch.equal(a, b)
 
 
 def test_pick_fft_and_tiles(T):
