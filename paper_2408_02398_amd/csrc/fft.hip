@@ -171,6 +171,18 @@ __device__ __forceinline__ cf& at_byte(cf* base, unsigned off) {
   return *reinterpret_cast<cf*>(reinterpret_cast<char*>(base) + off);
 }
 
+// Raw buffer accesses (a resource of `bytes` bytes from its base; the
+// offset is in bytes).  kBufferWord3 is the gfx9 resource word that selects
+// 32-bit elements, the format raw byte-offset accesses take.
+constexpr int kBufferWord3 = 0x00020000;
+typedef int int2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ cf buffer_load_cf(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(cf, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void buffer_store_cf(cf v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(int2v, v), r, (int)off, 0, 0);
+}
+
 // Inverse Z pass with the spectral product: out_a = Z^-1( G conj(S_a) ).
 // P holds only the sp nonzero z planes of each template after its X and Y
 // passes; each column of S_a is their z transform, formed here in registers,
@@ -212,16 +224,19 @@ __global__ __launch_bounds__((ZinvBlock<N, JP>::CB * Plan<N>::T)) void k_zinv_mu
 #pragma unroll
     for (int k = 0; k < E; ++k) sb[(tt + T * k) * SB + cc] = gl[k];
   }
+  // The template planes are read and the columns written through buffer
+  // resources whose size ends at the sp stored planes and at the crop's
+  // z_limit rows: the hardware returns 0 for a read past the end and drops a
+  // write past it, so no lane needs a branch or a select for its row.
   cf qn[JP > 0 ? JP : 1];  // planes of the next component, global-access order
   auto load_planes = [&](int a) {
-    const cf* pa = P + (size_t)a * p_stride;
+    const auto rp = __builtin_amdgcn_make_buffer_rsrc(const_cast<cf*>(P + (size_t)a * p_stride), (short)0,
+                                                      sp * NC * 8, kBufferWord3);
 #pragma unroll
-    for (int k = 0; k < JP; ++k) {
-      qn[k] = tt + T * k < sp ? at_byte(pa, offc + k * ZSTEP) : cf{0.0f, 0.0f};
-    }
+    for (int k = 0; k < JP; ++k) qn[k] = buffer_load_cf(rp, offc + k * ZSTEP);
   };
   if constexpr (JP > 0) load_planes(0);
-  __syncthreads();
+  __syncthreads();  // G staged
   cf g[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) g[j] = sb[(t + T * j) * SB + c];
@@ -230,12 +245,20 @@ __global__ __launch_bounds__((ZinvBlock<N, JP>::CB * Plan<N>::T)) void k_zinv_mu
   if (JP > 0 && center && col0 + c == 0 && t == 0) {
     g[0].x += (float)(center[0] * (double)N * (double)N * (double)N);
   }
+  if constexpr (JP > 0) {
+#pragma unroll
+    for (int k = 0; k < JP; ++k) pb[(tt + T * k) * SB + cc] = qn[k];
+  }
+  // Component a: its planes are in pb; the planes of a + 1 load during its
+  // transforms and are staged right after its columns are, before its
+  // stores are issued.  Waiting for a load also waits for every earlier
+  // store (one counter covers both), so staging the planes there waits only
+  // for stores issued a whole component earlier, which have drained, and
+  // this component's stores drain during the next one's transforms.
   for (int a = 0; a < A; ++a) {
     cf v[E];
+    __syncthreads();  // component a's planes staged; the previous columns read from sb
     if constexpr (JP > 0) {
-#pragma unroll
-      for (int k = 0; k < JP; ++k) pb[(tt + T * k) * SB + cc] = qn[k];
-      __syncthreads();  // planes staged; the previous component's columns are stored
 #pragma unroll
       for (int j = 0; j < E; ++j) v[j] = j < JP ? pb[(t + T * j) * SB + c] : cf{0.0f, 0.0f};
       if (a + 1 < A) load_planes(a + 1);
@@ -245,19 +268,23 @@ __global__ __launch_bounds__((ZinvBlock<N, JP>::CB * Plan<N>::T)) void k_zinv_mu
     } else {
 #pragma unroll
       for (int j = 0; j < E; ++j) v[j] = g[j];
-      __syncthreads();  // the previous component's columns are stored
     }
     fft_1d<N, true, true>(v, xl + c * S, twr, t);
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       if (t + T * j < z_limit) sb[(t + T * j) * SB + c] = v[j];
     }
-    __syncthreads();  // columns staged
-    cf* o = out + (size_t)a * out_stride;
+    __syncthreads();  // columns staged; every wave has read component a's planes
+    if constexpr (JP > 0) {
+      if (a + 1 < A) {
 #pragma unroll
-    for (int k = 0; k < E; ++k) {
-      if (tt + T * k < z_limit) at_byte(o, offc + k * ZSTEP) = sb[(tt + T * k) * SB + cc];
+        for (int k = 0; k < JP; ++k) pb[(tt + T * k) * SB + cc] = qn[k];
+      }
     }
+    const auto ro = __builtin_amdgcn_make_buffer_rsrc(out + (size_t)a * out_stride, (short)0,
+                                                      z_limit * NC * 8, kBufferWord3);
+#pragma unroll
+    for (int k = 0; k < E; ++k) buffer_store_cf(sb[(tt + T * k) * SB + cc], ro, offc + k * ZSTEP);
   }
 }
 
