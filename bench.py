@@ -111,6 +111,9 @@ def main():
     ap.add_argument("--dense-snr", type=float, default=1.0,
                     help="noise sweep: SNR of the dense orientation pass, plain vs learned start "
                          "(0: none)")
+    ap.add_argument("--tile-call", action="store_true",
+                    help="time one full 512^3 tile's normalisation-and-correlation call alone "
+                         "(degree 6, L = 40), for kernel profiling")
     ap.add_argument("--max-wrong", type=float, default=0.05,
                     help="fallback calibration: accepted learned voxels off by > 1 deg at most this often")
     args = ap.parse_args()
@@ -128,6 +131,9 @@ def main():
         sys.exit(2)
     if args.noise_sweep:
         print(json.dumps(clean(noise_sweep(args))), flush=True)
+        return
+    if args.tile_call:
+        print(json.dumps(clean(tile_call(args))), flush=True)
         return
     cfg_name, fft_n, top_p = WORKLOADS[args.workload]
     if args.fft:
@@ -834,6 +840,40 @@ def precision_report(args, cfg_name, fft_n, top_p, n_sample=150):
             "angle_max_deg_unambiguous": float(np.max(a[ok])) if ok.any() else None,
             "unambiguous": int(ok.sum())}
     return out
+
+
+def tile_call(args, n=6, L=40, r=17.0, N=512):
+    """One full-tile ttm_normalize_correlate call (random tomogram and tensor
+    template of the c3 shapes), repeated: ms per call by HIP events."""
+    import torch
+
+    from paper_2408_02398_amd import ttm
+    ctx = ttm.Context(0)
+    d = ttm.make_desc(n, L, r)
+    K = ttm.n_components(n)
+    rng = np.random.default_rng(1)
+    T = torch.from_numpy(rng.standard_normal((K, L ** 3)).astype(np.float32)).cuda()
+    spec = ttm.template_spectra(ctx, d, T, N)
+    vol = torch.from_numpy(rng.standard_normal((N, N, N), dtype=np.float32)).cuda()
+    g, w, stats = ttm.prefilter(ctx, d, vol)
+    c = L // 2
+    crop = N - L + 1
+    out = torch.empty((K, crop, crop, crop), dtype=torch.float32, device="cuda")
+    ws = ttm._ws(d, ttm.L.TTM_OP_NORM_CORR, N, device="cuda")
+
+    def call():
+        ttm.normalize_correlate(ctx, d, g, stats, spec, N, (c, c, c), (crop,) * 3, w, out=out, ws=ws)
+    for _ in range(args.warmup):
+        call()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(args.steps):
+        call()
+    b.record()
+    torch.cuda.synchronize()
+    return {"mode": "tile_call", "call": "ttm_normalize_correlate", "fft_n": N, "K": K, "L": L,
+            "steps": args.steps, "ms_per_call": a.elapsed_time(b) / args.steps}
 
 
 def measured_traffic(fft_n, K):
