@@ -364,7 +364,7 @@ int ttm_refine(ttm_ctx* ctx, const ttm_desc* desc, const float* g, const float* 
                void* stream);
 
 /*
- * ttm_extract over many boxes in one call (d' = 3): a batch of subtomograms
+ * ttm_extract over many boxes in one call (d' = 3 or 4): a batch of subtomograms
  * whose field boxes share the descriptor (and, with TTM_START_MLP, the
  * network), extracted by the same launches as one box of total_voxels
  * voxels, so a batch costs about the kernels of one call instead of one call
@@ -378,13 +378,13 @@ int ttm_refine(ttm_ctx* ctx, const ttm_desc* desc, const float* g, const float* 
  *               required with TTM_ORIENT)
  *   total_voxels the batch's voxel count (sum of the box volumes)
  *   ws          ttm_workspace_size(desc, TTM_OP_EXTRACT, 0, total_voxels, 1, 1) bytes
- * Errors: as ttm_extract; TTM_EUNSUPPORTED at d' = 4.
+ * Errors: as ttm_extract (the same degree and learned-start limits per form).
  */
 typedef struct {
   const void* C;            /* device, K x box[0] x box[1] x box[2] (in_dtype)  */
   float* score;             /* device map or NULL                               */
   float* lambda;            /* device map or NULL                               */
-  float* dir;               /* device map (3 floats per voxel) or NULL          */
+  float* dir;               /* device map (d' floats per voxel) or NULL         */
   uint64_t first;           /* index of the box's first voxel in the batch      */
   int32_t box[3];           /* bz, by, bx                                       */
   int32_t out_lo[3];        /* where box voxel (0,0,0) lands in the maps        */

@@ -1359,19 +1359,21 @@ int ttm_extract_batch(ttm_ctx* ctx, const ttm_desc* desc, const ttm_extract_item
     set_error("ttm_extract_batch: null pointer, no items, total voxels outside 1..2^32-1, or bad dtype");
     return TTM_EINVAL;
   }
-  if (desc->dprime != 3) {
-    set_error("ttm_extract_batch: d'=3 only");
-    return TTM_EUNSUPPORTED;
-  }
   const int mode = opts->mode;
   if ((mode & ~31) || !(mode & 3) || ((mode & 24) && !(mode & 4)) || ((mode & 4) && !(mode & 2))) {
     set_error("ttm_extract_batch: mode %d invalid", mode);
     return TTM_EINVAL;
   }
   const size_t plane = (size_t)total_voxels;
+  if (desc->dprime == 4 && desc->degree > 6) {
+    set_error("ttm_extract_batch: d'=4 scores need degree <= 6");
+    return TTM_EUNSUPPORTED;
+  }
   if (mode & 2) {
-    if (desc->degree < 2 || desc->degree > 6) {
-      set_error("ttm_extract_batch: orientation needs degree 2..6");
+    if (desc->degree < 2 || desc->degree > 6 ||
+        (desc->dprime == 4 && (mode & 4) && (desc->degree > 4 || (mode & 8)))) {
+      set_error("ttm_extract_batch: orientation needs degree 2..6; the learned start at d'=4 "
+                "needs degree 2 or 4 and no start-only mode");
       return TTM_EUNSUPPORTED;
     }
     if (!opts->starts || opts->n_starts < 1 || opts->n_starts > 64 || opts->max_iter < 1 ||
@@ -1380,13 +1382,16 @@ int ttm_extract_batch(ttm_ctx* ctx, const ttm_desc* desc, const ttm_extract_item
       set_error("ttm_extract_batch: orientation options invalid");
       return TTM_EINVAL;
     }
-    if ((mode & 4) && (!opts->mlp || !(opts->fallback_kappa == opts->fallback_kappa) ||
-                       ncomp(desc->degree, 3) > kMlpInMax)) {
-      set_error("ttm_extract_batch: learned start needs mlp and a kappa, at most %d components",
-                kMlpInMax);
+    if ((mode & 4) && (!opts->mlp || !(opts->fallback_kappa == opts->fallback_kappa))) {
+      set_error("ttm_extract_batch: learned start needs mlp and a kappa");
       return TTM_EINVAL;
     }
-    const size_t need = extract_workspace(plane, desc->degree);
+    if ((mode & 4) && !mlp_form_ok(desc)) {
+      set_error("ttm_extract_batch: no learned start for d'=%d, degree %d", desc->dprime, desc->degree);
+      return TTM_EUNSUPPORTED;
+    }
+    const size_t need = desc->dprime == 4 ? extract_workspace4(plane)
+                                          : extract_workspace(plane, desc->degree);
     if (!ws || ws_bytes < need) {
       set_error("ttm_extract_batch: workspace %zu < %zu", ws_bytes, need);
       return TTM_EWORKSPACE;
@@ -1418,7 +1423,8 @@ int ttm_extract_batch(ttm_ctx* ctx, const ttm_desc* desc, const ttm_extract_item
     a.screen = (mode & 16) ? 0 : 1;
     a.fb_total = n_fallback;
   }
-  return launch_extract(desc->degree, a, s);
+  return desc->dprime == 4 ? launch_extract4(desc->degree, a, s)
+                           : launch_extract(desc->degree, a, s);
 }
 
 size_t ttm_mlp_param_count(const ttm_desc* desc) {

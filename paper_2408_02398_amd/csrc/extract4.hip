@@ -90,24 +90,63 @@ __device__ __forceinline__ float bf16_to_f32_4(unsigned short h) {
   return __uint_as_float(((unsigned int)h) << 16);
 }
 
-// Load the K components of box voxel v; returns ||C||_F.
+__device__ __forceinline__ size_t map_index4(const ExtractArgs& a, size_t v) {
+  const int vx = (int)(v % a.bx), vy = (int)((v / a.bx) % a.by), vz = (int)(v / ((size_t)a.bx * a.by));
+  return ((size_t)(a.oz + vz) * a.dy + (a.oy + vy)) * a.dx + (a.ox + vx);
+}
+
+// Where voxel v of the call reads its field and writes its answer: the single
+// box, or in a batched call the item that holds v (the last one whose first
+// voxel is <= v), with v's place inside that item.
+struct Vox4 {
+  const void* C;
+  size_t stride;   // voxels per component plane
+  size_t lv;       // v within the planes
+  size_t o;        // index in the output maps
+  float* score;
+  float* lam;
+  float* dir;      // 4 floats per map voxel
+};
+
+__device__ __forceinline__ Vox4 vox4(const ExtractArgs& a, size_t v) {
+  if (!a.items) return Vox4{a.C, a.plane, v, map_index4(a, v), a.score, a.lam, a.dir};
+  int lo = 0, hi = a.n_items - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.items[mid].first <= v) lo = mid; else hi = mid - 1;
+  }
+  const ExtractItem& it = a.items[lo];
+  const size_t lv = v - it.first;
+  const int by = it.box[1], bx = it.box[2];
+  const int vx = (int)(lv % bx), vy = (int)((lv / bx) % by), vz = (int)(lv / ((size_t)bx * by));
+  const size_t o = ((size_t)(it.out_lo[0] + vz) * it.out_dims[1] + (it.out_lo[1] + vy)) * it.out_dims[2] +
+                   (it.out_lo[2] + vx);
+  return Vox4{it.C, (size_t)it.box[0] * by * bx, lv, o, it.score, it.lambda, it.dir};
+}
+
+// Load the K components of a voxel; returns ||C||_F.
 template <int N>
-__device__ __forceinline__ float load4(const ExtractArgs& a, size_t v, float (&c)[ncomp4(N)]) {
+__device__ __forceinline__ float load4_at(const ExtractArgs& a, const Vox4& r, float (&c)[ncomp4(N)]) {
   constexpr int K = ncomp4(N);
   constexpr Sym4<N> sy{};
   if (a.in_dtype == 1) {
-    const unsigned short* p = reinterpret_cast<const unsigned short*>(a.C);
+    const unsigned short* p = reinterpret_cast<const unsigned short*>(r.C);
 #pragma unroll
-    for (int k = 0; k < K; ++k) c[k] = bf16_to_f32_4(p[k * a.plane + v]);
+    for (int k = 0; k < K; ++k) c[k] = bf16_to_f32_4(p[k * r.stride + r.lv]);
   } else {
-    const float* p = reinterpret_cast<const float*>(a.C);
+    const float* p = reinterpret_cast<const float*>(r.C);
 #pragma unroll
-    for (int k = 0; k < K; ++k) c[k] = p[k * a.plane + v];
+    for (int k = 0; k < K; ++k) c[k] = p[k * r.stride + r.lv];
   }
   float f2 = 0.0f;
 #pragma unroll
   for (int k = 0; k < K; ++k) f2 = fmaf(sy.mu[k] * c[k], c[k], f2);
   return sqrtf(f2);
+}
+
+template <int N>
+__device__ __forceinline__ float load4(const ExtractArgs& a, size_t v, float (&c)[ncomp4(N)]) {
+  return load4_at<N>(a, vox4(a, v), c);
 }
 
 // g = C u^{n-1}: g_i = sum_{|beta| = n-1} mu_beta C_{beta + e_i} u^beta.
@@ -328,11 +367,6 @@ __device__ __forceinline__ float unfolding_lambda_min4(const float (&c)[ncomp4(N
   return lo - kShiftMargin4;
 }
 
-__device__ __forceinline__ size_t map_index4(const ExtractArgs& a, size_t v) {
-  const int vx = (int)(v % a.bx), vy = (int)((v / a.bx) % a.by), vz = (int)(v / ((size_t)a.bx * a.by));
-  return ((size_t)(a.oz + vz) * a.dy + (a.oy + vy)) * a.dx + (a.ox + vx);
-}
-
 __device__ __forceinline__ void count_add4(unsigned long long* ctr, unsigned long long v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
   if ((threadIdx.x & 63) == 0 && v) atomicAdd(ctr, v);
@@ -343,7 +377,8 @@ __global__ __launch_bounds__(256) void k_score4(ExtractArgs a) {
   const size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= a.plane) return;
   float c[ncomp4(N)];
-  a.score[map_index4(a, v)] = load4<N>(a, v, c);
+  const Vox4 r = vox4(a, v);
+  r.score[r.o] = load4_at<N>(a, r, c);
 }
 
 // Score (mode bit 1, all voxels only) and the SS-HOPM shift of every item,
@@ -357,8 +392,9 @@ __global__ __launch_bounds__(256) void k_prepare4(ExtractArgs a, Items4 it) {
        j += (size_t)gridDim.x * blockDim.x) {
     const size_t v = it.voxel(j);
     float c[ncomp4(N)];
-    const float cn = load4<N>(a, v, c);
-    if ((a.mode & 1) && a.score && !it.list) a.score[map_index4(a, v)] = cn;
+    const Vox4 r = vox4(a, v);
+    const float cn = load4_at<N>(a, r, c);
+    if ((a.mode & 1) && r.score && !it.list) r.score[r.o] = cn;
     float alpha = 0.0f;
     if (cn > 0.0f) {
       const float inv = 1.0f / cn;
@@ -519,7 +555,8 @@ __global__ __launch_bounds__(256) void k_reduce4(ExtractArgs a, Items4 it, int n
        j += (size_t)gridDim.x * blockDim.x) {
     const size_t v = it.voxel(j);
     float c[K];
-    const float cn = load4<N>(a, v, c);
+    const Vox4 rv = vox4(a, v);
+    const float cn = load4_at<N>(a, rv, c);
     float4 bu = first_block ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : w.best_u[j];
     float bl = first_block ? -INFINITY : w.best_l[j];
     if (cn > 0.0f) {
@@ -553,12 +590,12 @@ __global__ __launch_bounds__(256) void k_reduce4(ExtractArgs a, Items4 it, int n
         lam = bl * cn;
         n_oriented += merge ? 0 : 1;
       }
-      const size_t o = map_index4(a, v);
-      if (!merge || lam > a.lam[o]) {
-        if (a.lam) a.lam[o] = lam;
-        if (a.dir) {
+      const size_t o = rv.o;
+      if (!merge || lam > rv.lam[o]) {
+        if (rv.lam) rv.lam[o] = lam;
+        if (rv.dir) {
 #pragma unroll
-          for (int d = 0; d < 4; ++d) a.dir[4 * o + d] = out[d];
+          for (int d = 0; d < 4; ++d) rv.dir[4 * o + d] = out[d];
         }
       }
     }
@@ -682,9 +719,10 @@ __global__ __launch_bounds__(64 * kLearnedWaves4) void k_learned4(ExtractArgs a)
     const bool active = v0 < a.plane;
     const size_t v = active ? v0 : a.plane - 1;
     float c[K];
-    const float cn = load4<N>(a, v, c);
-    const size_t o = map_index4(a, v);
-    if ((a.mode & 1) && active && a.score) a.score[o] = cn;
+    const Vox4 rv = vox4(a, v);
+    const float cn = load4_at<N>(a, rv, c);
+    const size_t o = rv.o;
+    if ((a.mode & 1) && active && rv.score) rv.score[o] = cn;
     const float inv = cn > 0.0f ? 1.0f / cn : 0.0f;
     for (int k = 0; k < kin; ++k) xs[lane * kin + k] = 0;
 #pragma unroll
@@ -703,10 +741,10 @@ __global__ __launch_bounds__(64 * kLearnedWaves4) void k_learned4(ExtractArgs a)
     for (int d = 0; d < 4; ++d) u[d] *= ru;
     if (!active) continue;
     if (!(cn > 0.0f)) {
-      if (a.lam) a.lam[o] = 0.0f;
-      if (a.dir) {
+      if (rv.lam) rv.lam[o] = 0.0f;
+      if (rv.dir) {
 #pragma unroll
-        for (int d = 0; d < 4; ++d) a.dir[4 * o + d] = 0.0f;
+        for (int d = 0; d < 4; ++d) rv.dir[4 * o + d] = 0.0f;
       }
       continue;
     }
@@ -750,10 +788,10 @@ __global__ __launch_bounds__(64 * kLearnedWaves4) void k_learned4(ExtractArgs a)
 #pragma unroll
       for (int d = 0; d < 4; ++d) u[d] = -u[d];
     }
-    if (a.lam) a.lam[o] = lam * cn;
-    if (a.dir) {
+    if (rv.lam) rv.lam[o] = lam * cn;
+    if (rv.dir) {
 #pragma unroll
-      for (int d = 0; d < 4; ++d) a.dir[4 * o + d] = u[d];
+      for (int d = 0; d < 4; ++d) rv.dir[4 * o + d] = u[d];
     }
     if (fallback) {
       const unsigned long long slot = atomicAdd(&w.ctr[kListCount4], 1ull);

@@ -322,6 +322,8 @@ int refine(int degree, int K, const float* g, const float* w, int nz, int ny, in
   int rc = field_at(K, g, w, ny, nx, T, L, rw.cand, n_peaks, V, n_cand, rw.C, s);
   if (rc) return rc;
   ExtractArgs a = opts;
+  a.items = nullptr;
+  a.n_items = 0;
   a.C = rw.C;
   a.in_dtype = 0;
   a.plane = n_cand;

@@ -133,6 +133,50 @@ def test_batch_branch_count_does_not_change_outputs(T, ctx):
             assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("learned", [False, True])
+def test_quaternion_extract_batch_equals_per_box_extract(T, ctx, learned):
+    """The quaternion form (d' = 4, degree 4, K = 35, four floats per
+    direction) through ttm_extract_batch gives, voxel for voxel, exactly what
+    ttm_extract gives for each box on its own: the multistart search, and the
+    learned start with its fallback."""
+    from oracle import mlp as omlp
+    from oracle import sym
+    from tests.gpu_common import oracle_trained_params
+    n, D, K = 4, 4, 35
+    d = T.make_desc(n, 12, 5.0, dprime=D)
+    starts = cuda(synth.start_vectors(count=32, dim=D))
+    net = (T.MLP(ctx, d, cuda(omlp.pad_params(oracle_trained_params(21, n, d=D), K, D)))
+           if learned else None)
+    rng = np.random.default_rng(43)
+    boxes = [(5, 7, 9), (1, 1, 37), (12, 3, 20), (8, 8, 8)]
+    dims = [(9, 12, 14), (3, 4, 40), (16, 5, 22), (8, 8, 8)]
+    lows = [(2, 3, 4), (1, 2, 1), (0, 1, 2), (0, 0, 0)]
+    entries, singles = [], []
+    for box, dm, lo in zip(boxes, dims, lows):
+        nv = int(np.prod(box))
+        q = rng.standard_normal((nv, D))
+        q /= np.linalg.norm(q, axis=1, keepdims=True)
+        Cb = cuda((sym.monomials(q, n) + 0.25 * rng.standard_normal((nv, K))).T.reshape(K, *box))
+        maps = [torch.zeros(dm, device="cuda"), torch.zeros(dm, device="cuda"),
+                torch.zeros((*dm, D), device="cuda")]
+        entries.append(dict(C=Cb, score=maps[0], lam=maps[1], direction=maps[2], out_lo=lo))
+        fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+        s1, l1, u1 = T.extract(ctx, d, Cb, starts=starts, out_lo=lo, out_dims=dm, mlp=net, kappa=0.3,
+                               fallbacks=fb)
+        assert u1.shape[-1] == D
+        singles.append((s1, l1, u1, int(fb.item())))
+    eb = T.ExtractBatch(ctx, d, entries)
+    ws = torch.empty(eb.workspace_bytes(), dtype=torch.uint8, device="cuda")
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    eb.run(starts, ws, mlp=net, kappa=0.3, fallbacks=fb)
+    torch.cuda.synchronize()
+    for e, (s1, l1, u1, f1) in zip(entries, singles):
+        assert torch.equal(e["score"], s1) and torch.equal(e["lam"], l1) and torch.equal(e["direction"], u1)
+    assert int(fb.item()) == sum(x[3] for x in singles)
+    if learned:
+        assert int(fb.item()) < sum(int(np.prod(b)) for b in boxes)
+
+
 def test_pick_fft_and_tiles(T):
     assert T.tiles_for((96, 96, 96), 40, 128) == 1
     assert T.tiles_for((192, 192, 192), 40, 128) == 8
