@@ -675,7 +675,9 @@ class BatchEngine:
     them as parallel branches.  The extractions follow once every branch is
     done (letting a template's extraction overlap the next template's
     correlations was slower: the persistent extraction kernels hold the CUs),
-    then Find Peaks.  The outputs do not depend on the branch count.
+    one branch per template, each with its own workspace, so one template's
+    small list kernels overlap another's pooled runs; then Find Peaks.  The
+    outputs do not depend on the branch count.
     """
 
     def __init__(self, ctx: Context, templates, shapes, owner, starts: torch.Tensor, top_p: int,
@@ -730,7 +732,7 @@ class BatchEngine:
         self.Cslice = [None] * len(self.shapes)
         self.extract_batches = {}
         self.Cgroup = {}
-        ws_ext = 0
+
         for o in self.groups:
             d = templates[o][0]
             K = n_components(d.degree, d.dprime)
@@ -753,8 +755,10 @@ class BatchEngine:
                                     direction=self.direction[i], out_lo=lo))
             eb = ExtractBatch(ctx, d, entries)
             self.extract_batches[o] = eb
-            ws_ext = max(ws_ext, eb.workspace_bytes())
-        self.ws_ext = torch.empty(ws_ext, dtype=torch.uint8, device=dev)
+        # each template's extraction on a branch of its own, with its own workspace
+        self.ws_ext = {o: torch.empty(self.extract_batches[o].workspace_bytes(), dtype=torch.uint8,
+                                      device=dev) for o in self.groups}
+        self.ext_streams = {o: torch.cuda.Stream(device=dev) for o in self.groups}
         # Find Peaks of every item in one launch
         entries = []
         for i, (s, o) in enumerate(zip(self.shapes, owner)):
@@ -789,8 +793,8 @@ class BatchEngine:
         """The whole batch, ordered after the current stream's earlier work and
         before its later work (also what the graph records): each item's
         normalisation and correlation into its slice of its template's field
-        buffer on its branch, then one extraction per template, then one Find
-        Peaks launch for every item."""
+        buffer on its branch, then one extraction per template (each on its
+        own branch), then one Find Peaks launch for every item."""
         main = torch.cuda.current_stream()
         for b, st in enumerate(self.streams):
             st.wait_stream(main)
@@ -800,9 +804,14 @@ class BatchEngine:
         for st in self.streams:
             main.wait_stream(st)
         for o in self.groups:
-            mlp = self.mlps[o] if self.mlps is not None else None
-            self.extract_batches[o].run(self.starts, self.ws_ext, mlp=mlp, kappa=self.kappa,
-                                        fallbacks=self.fallbacks, orient=self.orient)
+            st = self.ext_streams[o]
+            st.wait_stream(main)
+            with torch.cuda.stream(st):
+                mlp = self.mlps[o] if self.mlps is not None else None
+                self.extract_batches[o].run(self.starts, self.ws_ext[o], mlp=mlp, kappa=self.kappa,
+                                            fallbacks=self.fallbacks, orient=self.orient)
+        for o in self.groups:
+            main.wait_stream(self.ext_streams[o])
         self.peak_batch.run()
 
     def capture(self):
