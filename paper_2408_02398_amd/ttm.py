@@ -657,6 +657,23 @@ def pick_fft(shape, L_edge: int, cost: dict | None = None) -> int:
     return best
 
 
+def deal_items(costs, branches: int) -> list:
+    """Items dealt out to at most ``branches`` branches (never more branches
+    than items, at least one): largest cost first, each to the branch with the
+    least cost so far (the lowest-numbered one on ties).  Returns the item
+    indices of each branch in the order they were dealt."""
+    if branches < 1:
+        raise ValueError("branches must be at least 1")
+    nb = max(1, min(branches, len(costs)))
+    out = [[] for _ in range(nb)]
+    load_b = [0.0] * nb
+    for i in sorted(range(len(costs)), key=lambda j: -costs[j]):
+        b = min(range(nb), key=lambda k: load_b[k])
+        out[b].append(i)
+        load_b[b] += costs[i]
+    return out
+
+
 class BatchEngine:
     """Full TTM passes over many subtomograms of uneven size with several
     templates, recorded once into a HIP graph and replayed with one launch.
@@ -686,8 +703,6 @@ class BatchEngine:
         self.ctx, self.templates, self.shapes, self.owner = ctx, templates, [tuple(s) for s in shapes], owner
         self.starts, self.top_p, self.mlps, self.kappa = starts, top_p, mlps, kappa
         self.orient, self.field_dtype = orient, field_dtype
-        if branches < 1:
-            raise ValueError("branches must be at least 1")
         dev = starts.device
         self.fft = [pick_fft(s, templates[o][0].L, cost) for s, o in zip(self.shapes, owner)]
         self.spectra = {}
@@ -712,17 +727,10 @@ class BatchEngine:
             d = templates[o][0]
             ws_norm = max(ws_norm, lib.ttm_workspace_size(C.byref(d), L.TTM_OP_NORMALIZE, N, *s))
             ws_corr = max(ws_corr, lib.ttm_workspace_size(C.byref(d), L.TTM_OP_CORRELATE, N, *s))
-        # branch assignment: items by modelled cost (largest first), each to
-        # the least loaded branch
-        self.branches = min(branches, len(self.shapes)) if self.shapes else 1
-        self.branch_items = [[] for _ in range(self.branches)]
-        load_b = [0.0] * self.branches
         item_cost = [tiles_for(s, templates[o][0].L, N) * (cost[N] if cost else N ** 3 * np.log2(N))
                      for s, o, N in zip(self.shapes, owner, self.fft)]
-        for i in sorted(range(len(self.shapes)), key=lambda j: -item_cost[j]):
-            b = min(range(self.branches), key=lambda k: load_b[k])
-            self.branch_items[b].append(i)
-            load_b[b] += item_cost[i]
+        self.branch_items = deal_items(item_cost, branches)
+        self.branches = len(self.branch_items)
         self.ws_norm = [torch.empty(ws_norm, dtype=torch.uint8, device=dev) for _ in range(self.branches)]
         self.ws_corr = [torch.empty(ws_corr, dtype=torch.uint8, device=dev) for _ in range(self.branches)]
         self.streams = [torch.cuda.Stream(device=dev) for _ in range(self.branches)]

@@ -53,3 +53,23 @@ def test_host_only_queries():
     assert ws >= 29 * 256 * 129 * 256 * 8
     assert lib.ttm_workspace_size(ctypes.byref(d), L.TTM_OP_CORRELATE, 32, 64, 64, 64) == 0  # L > N
     assert lib.ttm_workspace_size(None, L.TTM_OP_CORRELATE, 256, 1, 1, 1) == 0
+
+
+def test_deal_items_balances_and_covers():
+    """The batch's branch assignment (host logic): every item on exactly one
+    branch, never more branches than items, largest first to the least loaded
+    branch (lowest index on ties), and the load spread at most the largest item."""
+    from paper_2408_02398_amd.ttm import deal_items
+    import numpy as np
+    assert deal_items([], 8) == [[]]
+    assert deal_items([5.0], 8) == [[0]]
+    assert deal_items([1.0, 3.0, 2.0], 2) == [[1], [2, 0]]
+    rng = np.random.default_rng(3)
+    costs = list(rng.uniform(0.1, 1.0, 64))
+    out = deal_items(costs, 8)
+    assert len(out) == 8
+    assert sorted(i for b in out for i in b) == list(range(64))
+    loads = [sum(costs[i] for i in b) for b in out]
+    assert max(loads) - min(loads) <= max(costs)
+    with pytest.raises(ValueError):
+        deal_items(costs, 0)
