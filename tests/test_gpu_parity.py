@@ -518,3 +518,37 @@ def test_normalize_correlate_equals_the_two_calls(T, ctx, small):
     with pytest.raises(TTMError):
         T.normalize_correlate(ctx, d, g, stats, spec, N, (lo[0], lo[1], lo[2]), (step + 1, 4, 4),
                               torch.zeros_like(w))
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_full_pass_is_deterministic(T, ctx, learned):
+    """A full pass run twice, with the tile correlations overlapped on a side
+    stream, gives the same w, score, lambda and direction maps and the same
+    peaks, bit for bit: the pooled runs write each (voxel, start) result to its
+    own slot whatever lane ran it, the reductions take the first maximum in
+    start order, and the learned path's fallback list order does not reach any
+    voxel's answer.  A 150 x 170 x 190 volume of the 256^3 workload's recipe on
+    64^3 tiles (many tiles, ragged edges), degree 6."""
+    from oracle import mlp as omlp
+    from tests.gpu_common import oracle_trained_params
+    print(f"[determinism learned={learned}]", flush=True)
+    wl = synth.make_config("c2_256cube_n6", shape=(150, 170, 190), n_copies=20, min_sep=32)
+    n, L, r = 6, 32, 14.0
+    d = T.make_desc(n, L, r)
+    Tg, _ = T.build_tensor(ctx, d, cuda(wl.template), cuda(synth.rotation_samples(10)))
+    spec = T.template_spectra(ctx, d, Tg, 64)
+    starts = cuda(synth.start_vectors())
+    mlp = None
+    if learned:
+        mlp = T.MLP(ctx, d, cuda(omlp.pad_params(oracle_trained_params(13, n), 28)))
+    eng = T.Engine(ctx, d, spec, 64, wl.volume.shape, starts, mlp=mlp, kappa=0.3)
+    assert len(eng.boxes) > 8
+    vol = cuda(wl.volume)
+    outs = []
+    for _ in range(2):
+        res = eng.run(vol, top_p=20)
+        torch.cuda.synchronize()
+        outs.append([res.w.clone(), res.score.clone(), res.lam.clone(), res.direction.clone(),
+                     res.peaks.clone(), res.peak_vals.clone()])
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
