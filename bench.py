@@ -95,6 +95,9 @@ def main():
     ap.add_argument("--net-cache", default="",
                     help="file for the trained learned-start network: loaded if present, else "
                          "written after training")
+    ap.add_argument("--template-cache", default="",
+                    help="file for the tensor template (Alg. 1): loaded if its key (template, "
+                         "degree, form, rotations, mask) matches, else built and written")
     ap.add_argument("--train-volumes", type=int, default=10)
     ap.add_argument("--also-fft", type=int, default=256,
                     help="also time the learned pass on this FFT tile edge (0: no)")
@@ -158,7 +161,7 @@ def main():
     Q = torch.from_numpy(synth.rotation_samples(args.nq_base)).float().to(dev)
     p = synth.CONFIGS[cfg_name]
     t1 = time.time()
-    Tg, _ = ttm.build_tensor(ctx, d, torch.from_numpy(wl.template).to(dev), Q)
+    Tg = tensor_template_cached(args.template_cache, ctx, d, wl.template, Q, ttm, torch)
     spec = ttm.template_spectra(ctx, d, Tg, fft_n)
     torch.cuda.synchronize()
     log(f"[bench] tensor template ({Q.shape[0]} rotations) + spectra in {time.time() - t1:.2f}s")
@@ -840,6 +843,29 @@ def precision_report(args, cfg_name, fft_n, top_p, n_sample=150):
             "angle_max_deg_unambiguous": float(np.max(a[ok])) if ok.any() else None,
             "unambiguous": int(ok.sum())}
     return out
+
+
+def tensor_template_cached(path, ctx, d, template, Q, ttm, torch):
+    """The tensor template (Alg. 1, built once per template: the paper computes
+    it once and reuses it), from ``path`` when the file's key matches this
+    template, degree, form, rotation set and mask, else built on the GPU (and
+    written to ``path`` if one is given)."""
+    import hashlib
+    h = hashlib.sha256()
+    for a in (np.ascontiguousarray(template, dtype=np.float32), Q.cpu().numpy().astype(np.float32)):
+        h.update(a.tobytes())
+    h.update(np.array([d.degree, d.dprime, d.L], dtype=np.int64).tobytes())
+    h.update(np.array([d.mask_radius, d.filter_a, *d.axis], dtype=np.float64).tobytes())
+    key = h.hexdigest()
+    if path and os.path.exists(path):
+        z = np.load(path, allow_pickle=False)
+        if str(z["key"]) == key:
+            log(f"[bench] tensor template loaded from {path}")
+            return torch.from_numpy(z["T"]).cuda()
+    T, _ = ttm.build_tensor(ctx, d, torch.from_numpy(template).cuda(), Q)
+    if path:
+        np.savez(path, T=T.cpu().numpy(), key=np.array(key))
+    return T
 
 
 def tile_call(args, n=6, L=40, r=17.0, N=512):
