@@ -174,9 +174,22 @@ def main():
 
     learn_info = None
     net, kappa = None, 0.0
+    # the trained network depends on the workload's recipe and the training
+    # settings: a cached one is used only under the same key
+    import hashlib
+    hk = hashlib.sha256()
+    hk.update(np.ascontiguousarray(wl.template, dtype=np.float32).tobytes())
+    hk.update(json.dumps([cfg_name, n, L, r, p["snr"], p["wedge"], p["n_blobs"], p["min_sep"],
+                          args.train_steps, args.train_volumes, args.max_wrong, args.nq_base]).encode())
+    net_key = hk.hexdigest()
+    cache = None
     if args.start in ("learned", "both") and args.net_cache and os.path.exists(args.net_cache):
-        # a network this script trained and saved earlier (same workload)
         cache = np.load(args.net_cache, allow_pickle=False)
+        if "key" not in cache.files or str(cache["key"]) != net_key:
+            log(f"[bench] {args.net_cache} holds a network for other settings: training anew")
+            cache = None
+    if cache is not None:
+        # a network this script trained and saved earlier under the same key
         net = ttm.MLP(ctx, d, torch.from_numpy(cache["params"]).to(dev))
         kappa = float(cache["kappa"])
         learn_info = {"loaded_from": args.net_cache, "kappa": kappa}
@@ -197,7 +210,8 @@ def main():
             log=log)
         del vols
         if args.net_cache:
-            np.savez(args.net_cache, params=net.params.cpu().numpy(), kappa=np.float64(kappa))
+            np.savez(args.net_cache, params=net.params.cpu().numpy(), kappa=np.float64(kappa),
+                     key=np.array(net_key))
 
     # per-stage timing with events on the stream the library launches on
     stream = torch.cuda.current_stream()
