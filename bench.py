@@ -335,13 +335,17 @@ def main():
     roofline = {"bound": "alu",
                 "kernel": f"ttm_extract call ({'k_learned + ' if learned else ''}k_prepare, "
                           f"k_runs, k_reduce), degree {n}, {main_mode} start",
-                "achieved": ach, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
-                "achieved_is": "executed FP32 flops (op-count model of the kernels times the work "
-                               "counters; hardware FP32 counts agree, profiles/pmc_extract_c3_512x928x928_n6.md)",
+                "achieved": alg_ach, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": alg_ach / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                "achieved_is": "algorithmic FP32 flops per launch (the per-voxel model of the "
+                               "useful work times the launch's valid voxels) / the launch's "
+                               "average duration",
                 "algorithmic_flops_per_voxel": alg_per_voxel,
-                "achieved_algorithmic": alg_ach,
-                "frac_algorithmic": alg_ach / FP32_VECTOR_PEAK_TFLOPS,
+                "achieved_executed": ach,
+                "frac_executed": ach / FP32_VECTOR_PEAK_TFLOPS,
+                "achieved_executed_is": "executed FP32 flops (op-count model of the kernels times "
+                                        "the work counters; hardware FP32 counts agree, "
+                                        "profiles/pmc_extract_c3_512x928x928_n6.md)",
                 "avg_launch_ms": ext_avg,
                 "isolated_avg_launch_ms": ser_ext,
                 "flops_per_launch": flops / len(ext_launch_ms),
