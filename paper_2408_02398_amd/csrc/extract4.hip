@@ -27,6 +27,7 @@
 // start without its Newton-first search; the voxels that fall back are
 // listed and take the pooled multistart above, whose answer replaces the
 // learned one only where its lambda is larger.
+#include "extract_items.hpp"
 #include "internal.hpp"
 #include "mlp_core.hpp"
 #include "sym_tables.hpp"
@@ -90,39 +91,8 @@ __device__ __forceinline__ float bf16_to_f32_4(unsigned short h) {
   return __uint_as_float(((unsigned int)h) << 16);
 }
 
-__device__ __forceinline__ size_t map_index4(const ExtractArgs& a, size_t v) {
-  const int vx = (int)(v % a.bx), vy = (int)((v / a.bx) % a.by), vz = (int)(v / ((size_t)a.bx * a.by));
-  return ((size_t)(a.oz + vz) * a.dy + (a.oy + vy)) * a.dx + (a.ox + vx);
-}
-
-// Where voxel v of the call reads its field and writes its answer: the single
-// box, or in a batched call the item that holds v (the last one whose first
-// voxel is <= v), with v's place inside that item.
-struct Vox4 {
-  const void* C;
-  size_t stride;   // voxels per component plane
-  size_t lv;       // v within the planes
-  size_t o;        // index in the output maps
-  float* score;
-  float* lam;
-  float* dir;      // 4 floats per map voxel
-};
-
-__device__ __forceinline__ Vox4 vox4(const ExtractArgs& a, size_t v) {
-  if (!a.items) return Vox4{a.C, a.plane, v, map_index4(a, v), a.score, a.lam, a.dir};
-  int lo = 0, hi = a.n_items - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (a.items[mid].first <= v) lo = mid; else hi = mid - 1;
-  }
-  const ExtractItem& it = a.items[lo];
-  const size_t lv = v - it.first;
-  const int by = it.box[1], bx = it.box[2];
-  const int vx = (int)(lv % bx), vy = (int)((lv / bx) % by), vz = (int)(lv / ((size_t)bx * by));
-  const size_t o = ((size_t)(it.out_lo[0] + vz) * it.out_dims[1] + (it.out_lo[1] + vy)) * it.out_dims[2] +
-                   (it.out_lo[2] + vx);
-  return Vox4{it.C, (size_t)it.box[0] * by * bx, lv, o, it.score, it.lambda, it.dir};
-}
+using Vox4 = VoxelRef;
+__device__ __forceinline__ Vox4 vox4(const ExtractArgs& a, size_t v) { return voxel_ref(a, v); }
 
 // Load the K components of a voxel; returns ||C||_F.
 template <int N>
