@@ -722,7 +722,7 @@ size_t ttm_workspace_size(const ttm_desc* desc, int op, int fft_n, int nz, int n
     case TTM_OP_NORMALIZE: {
       if (!fft_ok(fft_n) || desc->L > fft_n) return 0;
       const size_t step = (size_t)(fft_n - desc->L + 1);
-      return 3 * align256(spec_elems(fft_n) * 8) + 2 * align256(step * step * step * 4) +
+      return 4 * align256(spec_elems(fft_n) * 8) + 2 * align256(step * step * step * 4) +
              align256(prefilter_blocks(nz, ny, nx) * 16);
     }
     case TTM_OP_CORRELATE:
@@ -746,7 +746,7 @@ size_t ttm_workspace_size(const ttm_desc* desc, int op, int fft_n, int nz, int n
     case TTM_OP_NORM_CORR: {
       if (!fft_ok(fft_n) || desc->L > fft_n) return 0;
       const size_t step = (size_t)(fft_n - desc->L + 1);
-      return (size_t)(2 + K) * align256(spec_elems(fft_n) * 8) +
+      return (size_t)(2 + std::max(K, 2)) * align256(spec_elems(fft_n) * 8) +
              2 * align256(step * step * step * 4);
     }
     default:
@@ -905,12 +905,14 @@ int normalize_boxes(ttm_ctx* ctx, const ttm_desc* desc, const float* g, int nz, 
   const size_t se = spec_elems(fft_n);
   const size_t sb = align256(se * 8);
   const int step = fft_n - L + 1;
+  // G of the centred tile and of its square (sb bytes apart), their two
+  // products' work spectra, the local sums s1 and s2 (s_gap floats apart)
   char* w = static_cast<char*>(ws);
   cf* G1 = reinterpret_cast<cf*>(w);
-  cf* G2 = reinterpret_cast<cf*>(w + sb);
   cf* work = reinterpret_cast<cf*>(w + 2 * sb);
-  float* s1 = reinterpret_cast<float*>(w + 3 * sb);
-  float* s2 = reinterpret_cast<float*>(w + 3 * sb + align256((size_t)step * step * step * 4));
+  const size_t s_gap = align256((size_t)step * step * step * 4) / 4;
+  float* s1 = reinterpret_cast<float*>(w + 4 * sb);
+  float* s2 = s1 + s_gap;
   const int c = L / 2;
   const double M = mask_count(L, desc->mask_radius);
   const cf* mspec = static_cast<const cf*>(mask_spec);
@@ -922,18 +924,14 @@ int normalize_boxes(ttm_ctx* ctx, const ttm_desc* desc, const float* g, int nz, 
       for (int dx = 0; dx < box_size[2]; dx += step) {
         const int sxx = std::min(step, box_size[2] - dx);
         const int oz = box_lo[0] + dz, oy = box_lo[1] + dy, ox = box_lo[2] + dx;
-        RealSrc src{g, 0, nz, ny, nx, oz - c, oy - c, ox - c, stats, 0};
-        int rc = fft3d_forward(fft_n, src, 1, G1, se, ctx->twiddles, s);
+        // the centred tile and its square in one batched forward transform,
+        // both products with the mask spectrum in one batched inverse
+        RealSrc src{g, 0, nz, ny, nx, oz - c, oy - c, ox - c, stats, 0, 1};
+        int rc = fft3d_forward(fft_n, src, 2, G1, sb / 8, ctx->twiddles, s);
         if (rc) return rc;
-        src.square = 1;
-        rc = fft3d_forward(fft_n, src, 1, G2, se, ctx->twiddles, s);
-        if (rc) return rc;
-        RealDst d1{s1, 0, 0, syy, sxx, 0, 0, 0, szz, syy, sxx, nullptr, 0, 0, 0, 0, 0, scale};
-        rc = fft3d_inverse_mul(fft_n, G1, mspec, 0, L, 1, nullptr, work, se, d1, ctx->twiddles, s);
-        if (rc) return rc;
-        RealDst d2 = d1;
-        d2.p = s2;
-        rc = fft3d_inverse_mul(fft_n, G2, mspec, 0, L, 1, nullptr, work, se, d2, ctx->twiddles, s);
+        RealDst d1{s1, 0, s_gap, syy, sxx, 0, 0, 0, szz, syy, sxx, nullptr, 0, 0, 0, 0, 0, scale};
+        rc = fft3d_inverse_mul(fft_n, G1, mspec, 0, L, 1, nullptr, work, sb / 8, d1, ctx->twiddles, s,
+                               2, sb / 8);
         if (rc) return rc;
         const size_t nbx = (size_t)szz * syy * sxx;
         hipLaunchKernelGGL(k_var_combine, dim3((unsigned)((nbx + 255) / 256)), dim3(256), 0, s, s1,
@@ -1038,7 +1036,7 @@ int ttm_normalize(ttm_ctx* ctx, const ttm_desc* desc, const float* vol, int nz, 
   TTM_HIP(hipSetDevice(ctx->device));
   const size_t sb = align256(spec_elems(fft_n) * 8);
   const size_t step = (size_t)(fft_n - L + 1);
-  double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + 3 * sb +
+  double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + 4 * sb +
                                            2 * align256(step * step * step * 4));
   prefilter_stats(desc, vol, nz, ny, nx, g_out, stats_out, part, s);
   fill_zero(w_out, (size_t)nz * ny * nx * 4, s);
@@ -1144,12 +1142,14 @@ int ttm_normalize_correlate(ttm_ctx* ctx, const ttm_desc* desc, const float* g, 
   const int K = ncomp(desc->degree, desc->dprime);
   const size_t se = spec_elems(fft_n);
   const size_t sb = align256(se * 8);
+  // G of the centred tile and of its square (sb bytes apart), max(K, 2) work
+  // spectra, the local sums s1 and s2 (s_gap floats apart)
   char* w = static_cast<char*>(ws);
   cf* G1 = reinterpret_cast<cf*>(w);
-  cf* G2 = reinterpret_cast<cf*>(w + sb);
   cf* work = reinterpret_cast<cf*>(w + 2 * sb);
-  float* s1 = reinterpret_cast<float*>(w + (2 + K) * sb);
-  float* s2 = reinterpret_cast<float*>(w + (2 + K) * sb + align256((size_t)step * step * step * 4));
+  const size_t s_gap = align256((size_t)step * step * step * 4) / 4;
+  float* s1 = reinterpret_cast<float*>(w + (2 + std::max(K, 2)) * sb);
+  float* s2 = s1 + s_gap;
   const double M = mask_count(L, desc->mask_radius);
   const size_t tse = tspec_elems(fft_n, L);
   const cf* tspec = static_cast<const cf*>(spec);
@@ -1157,20 +1157,14 @@ int ttm_normalize_correlate(ttm_ctx* ctx, const ttm_desc* desc, const float* g, 
   const float scale = 1.0f / ((float)fft_n * fft_n * fft_n);
   const int oz = box_lo[0], oy = box_lo[1], ox = box_lo[2];
   const int szz = box_size[0], syy = box_size[1], sxx = box_size[2];
-  // the centred g tile and its square, forward
-  RealSrc src{g, 0, nz, ny, nx, oz - c, oy - c, ox - c, stats, 0};
-  int rc = fft3d_forward(fft_n, src, 1, G1, se, ctx->twiddles, s);
+  // the centred g tile and its square, forward in one batched transform
+  RealSrc src{g, 0, nz, ny, nx, oz - c, oy - c, ox - c, stats, 0, 1};
+  int rc = fft3d_forward(fft_n, src, 2, G1, sb / 8, ctx->twiddles, s);
   if (rc) return rc;
-  src.square = 1;
-  rc = fft3d_forward(fft_n, src, 1, G2, se, ctx->twiddles, s);
-  if (rc) return rc;
-  // local sums with the mask, then w on the box
-  RealDst d1{s1, 0, 0, syy, sxx, 0, 0, 0, szz, syy, sxx, nullptr, 0, 0, 0, 0, 0, scale};
-  rc = fft3d_inverse_mul(fft_n, G1, mspec, 0, L, 1, nullptr, work, se, d1, ctx->twiddles, s);
-  if (rc) return rc;
-  RealDst d2 = d1;
-  d2.p = s2;
-  rc = fft3d_inverse_mul(fft_n, G2, mspec, 0, L, 1, nullptr, work, se, d2, ctx->twiddles, s);
+  // local sums with the mask (both products in one batched inverse), then w on the box
+  RealDst d1{s1, 0, s_gap, syy, sxx, 0, 0, 0, szz, syy, sxx, nullptr, 0, 0, 0, 0, 0, scale};
+  rc = fft3d_inverse_mul(fft_n, G1, mspec, 0, L, 1, nullptr, work, sb / 8, d1, ctx->twiddles, s,
+                         2, sb / 8);
   if (rc) return rc;
   const size_t nbx = (size_t)szz * syy * sxx;
   hipLaunchKernelGGL(k_var_combine, dim3((unsigned)((nbx + 255) / 256)), dim3(256), 0, s, s1, s2,

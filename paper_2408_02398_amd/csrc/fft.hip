@@ -23,7 +23,7 @@ __device__ __forceinline__ float load_src(const RealSrc& s, int b, int z, int y,
   if (gz < 0 || gz >= s.dz || gy < 0 || gy >= s.dy || gx < 0 || gx >= s.dx) return 0.0f;
   float v = s.p[b * s.batch_stride + ((size_t)gz * s.dy + gy) * s.dx + gx];
   if (s.center) v = (float)((double)v - s.center[0]);
-  if (s.square) v = v * v;
+  if (s.square || (s.square_odd && (b & 1))) v = v * v;
   return v;
 }
 
@@ -194,13 +194,17 @@ __device__ __forceinline__ void buffer_store_cf(cf v, __amdgpu_buffer_rsrc_t r, 
 // wavefront reads and writes CB neighbouring columns of a z row together.
 // Two workgroup barriers per component: after its planes are staged, and
 // after its transformed columns are.  The planes of component a + 1 load
-// while component a is transformed.
+// while component a is transformed.  Grid y picks one of several G spectra
+// (g_stride apart) for a one-component product: its output is work
+// spectrum blockIdx.y.
 template <int N, int JP>
 __global__ __launch_bounds__((ZinvBlock<N, JP>::CB * Plan<N>::T)) void k_zinv_mul(
     const cf* __restrict__ G, const cf* __restrict__ P, size_t p_stride, int sp, int A,
     const double* __restrict__ center, cf* __restrict__ out, size_t out_stride, int z_limit,
-    const cf* __restrict__ tw) {
+    const cf* __restrict__ tw, size_t g_stride) {
   constexpr int T = Plan<N>::T, E = N / T, CB = ZinvBlock<N, JP>::CB, NC = (N / 2 + 1) * N;
+  G += blockIdx.y * g_stride;
+  out += blockIdx.y * out_stride;
   constexpr int S = lds_stride<N>();
   constexpr int SB = CB + 1;                // staging row: CB columns, one pad element
   constexpr int ZP = JP > 0 ? JP * T : 1;   // staged template planes
@@ -457,7 +461,8 @@ int forward_planes_n(const RealSrc& src, int batch, int planes, cf* out, size_t 
 
 template <int N>
 int inverse_n(const cf* G, const cf* Sp, size_t s_stride, int s_planes, int A, const double* center,
-              cf* work, size_t work_stride, const RealDst& dst, const cf* tw, hipStream_t s) {
+              cf* work, size_t work_stride, const RealDst& dst, const cf* tw, hipStream_t s,
+              int gb, size_t g_stride) {
   constexpr int T = Plan<N>::T;
   constexpr int NROWS = N * (N / 2 + 1);
   const int zlim = dst.sz;
@@ -471,8 +476,8 @@ int inverse_n(const cf* G, const cf* Sp, size_t s_stride, int s_planes, int A, c
     while (jp < E && jp * T < s_planes) jp *= 2;
   }
   auto launch = [&](auto kern, int cb) {
-    hipLaunchKernelGGL(kern, dim3(NROWS / cb, 1), dim3(cb * T), 0, s, G, Sp, s_stride, s_planes, A,
-                       center, work, work_stride, zlim, tw);
+    hipLaunchKernelGGL(kern, dim3(NROWS / cb, gb), dim3(cb * T), 0, s, G, Sp, s_stride, s_planes, A,
+                       center, work, work_stride, zlim, tw, g_stride);
   };
   constexpr int J2 = 2 < E ? 2 : E, J4 = 4 < E ? 4 : E, J8 = 8 < E ? 8 : E;
   switch (jp) {
@@ -483,11 +488,12 @@ int inverse_n(const cf* G, const cf* Sp, size_t s_stride, int s_planes, int A, c
     case 8: launch(k_zinv_mul<N, J8>, ZinvBlock<N, J8>::CB); break;
     default: launch(k_zinv_mul<N, E>, ZinvBlock<N, E>::CB); break;
   }
+  const int nb = A * gb;  // work spectra written by the Z pass
   constexpr int RB = (128 / T > 0 ? 128 / T : 1);
-  hipLaunchKernelGGL((k_c2c_rows<N, true>), dim3(NROWS / RB, A), dim3(RB * T), 0, s, work,
+  hipLaunchKernelGGL((k_c2c_rows<N, true>), dim3(NROWS / RB, nb), dim3(RB * T), 0, s, work,
                      work_stride, zlim, dst.sy, tw);
-  hipLaunchKernelGGL(k_c2r_x<N>, dim3(A * (N / kRowsX) * N), dim3(kRowsX / 2 * T), 0, s, work,
-                     work_stride, A, dst, tw);
+  hipLaunchKernelGGL(k_c2r_x<N>, dim3(nb * (N / kRowsX) * N), dim3(kRowsX / 2 * T), 0, s, work,
+                     work_stride, nb, dst, tw);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : hip_status(e, "fft inverse launch");
 }
@@ -548,17 +554,21 @@ int fft3d_forward_planes(int N, const RealSrc& src, int batch, int planes, cf* o
 
 int fft3d_inverse_mul(int N, const cf* G, const cf* Sp, size_t s_stride, int s_planes, int A,
                       const double* center, cf* work, size_t work_stride, const RealDst& dst,
-                      const cf* tw_all, hipStream_t s) {
+                      const cf* tw_all, hipStream_t s, int gb, size_t g_stride) {
+  if (gb < 1 || (gb > 1 && A != 1)) {
+    set_error("fft inverse: a batch of %d G spectra needs one component (A = %d)", gb, A);
+    return -1;
+  }
   const cf* tw = tw_all + twiddle_offset(N);
   switch (N) {
-    case 32: return inverse_n<32>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s);
-    case 64: return inverse_n<64>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s);
-    case 128: return inverse_n<128>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s);
-    case 256: return inverse_n<256>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s);
-    case 512: return inverse_n<512>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s);
-    case 96: return inverse_n<96>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s);
-    case 160: return inverse_n<160>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s);
-    case 192: return inverse_n<192>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s);
+    case 32: return inverse_n<32>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s, gb, g_stride);
+    case 64: return inverse_n<64>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s, gb, g_stride);
+    case 128: return inverse_n<128>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s, gb, g_stride);
+    case 256: return inverse_n<256>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s, gb, g_stride);
+    case 512: return inverse_n<512>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s, gb, g_stride);
+    case 96: return inverse_n<96>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s, gb, g_stride);
+    case 160: return inverse_n<160>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s, gb, g_stride);
+    case 192: return inverse_n<192>(G, Sp, s_stride, s_planes, A, center, work, work_stride, dst, tw, s, gb, g_stride);
     default: set_error("unsupported FFT edge %d", N); return -4;
   }
 }

@@ -29,7 +29,9 @@ int hip_status(hipError_t e, const char* what);
 
 // Tile element (z, y, x) of batch b is src[b][oz + z][oy + y][ox + x] when that
 // voxel lies inside the dz x dy x dx source, else 0.  If `center` is set the
-// value is (v - center[0]); if `square` it is then squared.
+// value is (v - center[0]); if `square` it is then squared, and with
+// `square_odd` so are the odd batch entries (batch_stride 0: a tile and its
+// square from one source in one launch).
 struct RealSrc {
   const float* p;
   size_t batch_stride;
@@ -37,6 +39,7 @@ struct RealSrc {
   int oz, oy, ox;
   const double* center;
   int square;
+  int square_odd;
 };
 
 // Tile output (z, y, x) with z < sz, y < sy, x < sx lands at
@@ -78,9 +81,11 @@ int fft3d_forward_planes(int N, const RealSrc& src, int batch, int planes, cf* o
 // each x/y-transformed template from fft3d_forward_planes; S_a is its z
 // transform, formed column by column inside the kernel.
 // `work` holds A spectra.  If S is null, G itself (A = 1) is inverted.
+// With gb > 1 (A = 1 only), gb spectra G + i g_stride are each multiplied by
+// the same S in one launch: work spectrum i and dst batch entry i are theirs.
 int fft3d_inverse_mul(int N, const cf* G, const cf* S, size_t s_stride, int s_planes, int A,
                       const double* center, cf* work, size_t work_stride, const RealDst& dst,
-                      const cf* tw_all, hipStream_t s);
+                      const cf* tw_all, hipStream_t s, int gb = 1, size_t g_stride = 0);
 
 int init_twiddles(cf* tw_all, hipStream_t s);
 
