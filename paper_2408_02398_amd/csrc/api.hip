@@ -262,7 +262,7 @@ __global__ __launch_bounds__(256) void k_build(const float* __restrict__ tn, int
   for (int q0 = 0; q0 < nq; q0 += kQChunk) {
     const int nc = min(kQChunk, nq - q0);
     __syncthreads();
-    if (threadIdx.x < nc) {
+    if ((int)threadIdx.x < nc) {
       const float* q = quats + 4 * (q0 + threadIdx.x);
       float w = q[0], x = q[1], y = q[2], z = q[3];
       const float rn = 1.0f / sqrtf(w * w + x * x + y * y + z * z);
@@ -439,7 +439,7 @@ __global__ __launch_bounds__(256) void k_box_stats(const float* __restrict__ box
   rm[threadIdx.x] = sm;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) {
+    if ((int)threadIdx.x < off) {
       r1[threadIdx.x] += r1[threadIdx.x + off];
       r2[threadIdx.x] += r2[threadIdx.x + off];
       rm[threadIdx.x] += rm[threadIdx.x + off];
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(256) void k_wedge_accumulate(const float* __restric
   for (int b0 = 0; b0 < nb; b0 += kQChunk) {
     const int nc = min(kQChunk, nb - b0);
     __syncthreads();
-    if (threadIdx.x < nc) {
+    if ((int)threadIdx.x < nc) {
       float R[9], qn[4];
       quat_rotation(quats + 4 * (size_t)(q0 + b0 + threadIdx.x), R, qn);
       float v[4];
@@ -838,7 +838,7 @@ int ttm_build_tensor_wedge(ttm_ctx* ctx, const ttm_desc* desc, const float* tmpl
     const int nb = std::min(B, nq - q0);
     hipLaunchKernelGGL(k_rotate_boxes, dim3((unsigned)((nbox + 255) / 256), nb), dim3(256), 0, s,
                        tn_out, L, quats, q0, P, boxes);
-    RealSrc src{boxes, nbox, P, P, P, 0, 0, 0, nullptr, 0};
+    RealSrc src{boxes, nbox, P, P, P, 0, 0, 0, nullptr, 0, 0};
     int rc = fft3d_forward(P, src, nb, spec, nspec, ctx->twiddles, s);
     if (rc) return rc;
     hipLaunchKernelGGL(k_wedge, dim3((unsigned)((nspec + 255) / 256), nb), dim3(256), 0, s, spec,
@@ -886,12 +886,12 @@ int ttm_template_spectra(ttm_ctx* ctx, const ttm_desc* desc, const float* T, int
   const size_t se = tspec_elems(fft_n, L);
   cf* out = static_cast<cf*>(spec_out);
   // fields at the origin: z planes L.. of the padded tile are zero
-  RealSrc src{T, (size_t)L * L * L, L, L, L, 0, 0, 0, nullptr, 0};
+  RealSrc src{T, (size_t)L * L * L, L, L, L, 0, 0, 0, nullptr, 0, 0};
   int rc = fft3d_forward_planes(fft_n, src, K, L, out, se, ctx->twiddles, s);
   if (rc) return rc;
   float* m = static_cast<float*>(ws);
   hipLaunchKernelGGL(k_mask, dim3((L * L * L + 255) / 256), dim3(256), 0, s, m, L, desc->mask_radius);
-  RealSrc msrc{m, 0, L, L, L, 0, 0, 0, nullptr, 0};
+  RealSrc msrc{m, 0, L, L, L, 0, 0, 0, nullptr, 0, 0};
   return fft3d_forward_planes(fft_n, msrc, 1, L, out + (size_t)K * se, se, ctx->twiddles, s);
 }
 
@@ -1093,7 +1093,7 @@ int ttm_correlate(ttm_ctx* ctx, const ttm_desc* desc, const float* g, const floa
       for (int dx = 0; dx < box_size[2]; dx += step) {
         const int sxx = std::min(step, box_size[2] - dx);
         const int oz = box_lo[0] + dz, oy = box_lo[1] + dy, ox = box_lo[2] + dx;
-        RealSrc src{g, 0, nz, ny, nx, oz - c, oy - c, ox - c, stats, 0};
+        RealSrc src{g, 0, nz, ny, nx, oz - c, oy - c, ox - c, stats, 0, 0};
         int rc = fft3d_forward(fft_n, src, 1, G, se, ctx->twiddles, s);
         if (rc) return rc;
         RealDst d{C_out, out_dtype, plane, box_size[1], box_size[2], dz, dy, dx, szz, syy, sxx,
@@ -1559,7 +1559,7 @@ int ttm_fft3d_r2c(ttm_ctx* ctx, const float* x, int fft_n, void* spec, void* str
     return TTM_EUNSUPPORTED;
   }
   TTM_HIP(hipSetDevice(ctx->device));
-  RealSrc src{x, 0, fft_n, fft_n, fft_n, 0, 0, 0, nullptr, 0};
+  RealSrc src{x, 0, fft_n, fft_n, fft_n, 0, 0, 0, nullptr, 0, 0};
   return fft3d_forward(fft_n, src, 1, static_cast<cf*>(spec), spec_elems(fft_n), ctx->twiddles,
                        static_cast<hipStream_t>(stream));
 }

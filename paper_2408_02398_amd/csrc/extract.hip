@@ -599,7 +599,6 @@ struct RunArgs {
 template <int N, bool CONT>
 __global__ __launch_bounds__(64) void k_runs(ExtractArgs a, RunArgs r) {
   constexpr int K = ncomp3(N);
-  constexpr Sym3<N> sy{};
   __shared__ float st[64 * 3];
   __shared__ float cs[K][64];     // chunk tensors, [component][item]
   __shared__ float ca[64];        // shift per item

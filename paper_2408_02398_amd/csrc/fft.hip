@@ -167,9 +167,6 @@ __global__ __launch_bounds__(ColBlock<N>::CB * Plan<N>::T) void k_c2c_cols(
 __device__ __forceinline__ const cf& at_byte(const cf* base, unsigned off) {
   return *reinterpret_cast<const cf*>(reinterpret_cast<const char*>(base) + off);
 }
-__device__ __forceinline__ cf& at_byte(cf* base, unsigned off) {
-  return *reinterpret_cast<cf*>(reinterpret_cast<char*>(base) + off);
-}
 
 // Raw buffer accesses (a resource of `bytes` bytes from its base; the
 // offset is in bytes).  kBufferWord3 is the gfx9 resource word that selects
