@@ -17,6 +17,7 @@ namespace ttm {
 namespace {
 
 constexpr int kRowsX = 16;  // real rows per workgroup in the X passes (packed in pairs)
+constexpr int kRowsC = 32;  // the same in the inverse X pass: its input columns are read in 256-byte pieces
 
 __device__ __forceinline__ float load_src(const RealSrc& s, int b, int z, int y, int x) {
   const int gz = s.oz + z, gy = s.oy + y, gx = s.ox + x;
@@ -291,13 +292,13 @@ __global__ __launch_bounds__((ZinvBlock<N, JP>::CB * Plan<N>::T)) void k_zinv_mu
 
 // ---------------------------------------------------------------- X inverse
 template <int N>
-__global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) __attribute__((amdgpu_waves_per_eu(N == 512 ? 8 : 1))) void k_c2r_x(const cf* __restrict__ spec,
+__global__ __launch_bounds__(kRowsC / 2 * Plan<N>::T) __attribute__((amdgpu_waves_per_eu(N == 512 ? 8 : 1))) void k_c2r_x(const cf* __restrict__ spec,
                                                           size_t spec_stride, int A, RealDst dst,
                                                           const cf* __restrict__ tw) {
-  constexpr int T = Plan<N>::T, E = N / T, NP = kRowsX / 2, NH = N / 2 + 1;
+  constexpr int T = Plan<N>::T, E = N / T, NP = kRowsC / 2, NH = N / 2 + 1;
   constexpr int S = lds_stride<N>();
   constexpr int SPS = NH + 1;  // padded spectrum row
-  constexpr int BYTES_A = kRowsX * SPS * 8, BYTES_B = NP * S * 8, BYTES_C = kRowsX * (N + 4) * 4;
+  constexpr int BYTES_A = kRowsC * SPS * 8, BYTES_B = NP * S * 8, BYTES_C = kRowsC * (N + 4) * 4;
   constexpr int BYTES = BYTES_A > BYTES_B ? (BYTES_A > BYTES_C ? BYTES_A : BYTES_C)
                                           : (BYTES_B > BYTES_C ? BYTES_B : BYTES_C);
   __shared__ __align__(16) unsigned char smem[BYTES];
@@ -307,30 +308,30 @@ __global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) __attribute__((amdgpu_wave
   const int tid = threadIdx.x;
   // work items: component fastest, then row block, then z plane, so the
   // workgroups that share a crop's weight-map rows run together in one XCD
-  constexpr int NYB = N / kRowsX;
+  constexpr int NYB = N / kRowsC;
   const int item = (int)xcd_item(blockIdx.x, gridDim.x);
-  const int b = item % A, y0 = (item / A) % NYB * kRowsX, z = item / A / NYB;
+  const int b = item % A, y0 = (item / A) % NYB * kRowsC, z = item / A / NYB;
   if (z >= dst.sz || y0 >= dst.sy) return;  // uniform: nothing of this block is kept
   const int p = tid / T, t = tid % T;
-  constexpr int NTH = NP * T, NIN = NH * kRowsX, IT = (NIN + NTH - 1) / NTH;
+  constexpr int NTH = NP * T, NIN = NH * kRowsC, IT = (NIN + NTH - 1) / NTH;
   const cf* in = spec + b * spec_stride + (size_t)z * NH * N + y0;
   {
     // all loads first (indices clamped, so every one is in bounds), then the
     // LDS stores: the loads are in flight together.  Rows past the crop were
     // not stored by the Y pass; they are read as zeros (each is paired with a
     // kept row in one complex transform, so it must be finite).
-    const int nrows_in = min(kRowsX, dst.sy - y0);
+    const int nrows_in = min(kRowsC, dst.sy - y0);
     cf ld[IT];
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       const int e = min(tid + i * NTH, NIN - 1);
-      ld[i] = e % kRowsX < nrows_in ? at_byte(in, (unsigned)((e / kRowsX) * N + e % kRowsX) * 8u)
+      ld[i] = e % kRowsC < nrows_in ? at_byte(in, (unsigned)((e / kRowsC) * N + e % kRowsC) * 8u)
                                     : cf{0.0f, 0.0f};
     }
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       const int e = tid + i * NTH;
-      if (e < NIN) sp[(e % kRowsX) * SPS + e / kRowsX] = ld[i];
+      if (e < NIN) sp[(e % kRowsC) * SPS + e / kRowsC] = ld[i];
     }
   }
   FftTw<N> twr;  // in flight across the barrier
@@ -365,7 +366,7 @@ __global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) __attribute__((amdgpu_wave
     orow[(2 * p + 1) * RS + n] = v[j].y;
   }
   __syncthreads();
-  const int nrows = min(kRowsX, dst.sy - y0);
+  const int nrows = min(kRowsC, dst.sy - y0);
   const int sx = dst.sx;
   // row bases are the same for the whole workgroup, so each access takes a
   // scalar base and the lane's 32-bit byte offset
@@ -373,37 +374,40 @@ __global__ __launch_bounds__(kRowsX / 2 * Plan<N>::T) __attribute__((amdgpu_wave
                     ((size_t)(dst.vz0 + z) * dst.by + (dst.vy0 + y0)) * dst.bx + dst.vx0;
   const float* wr = dst.w ? dst.w + ((size_t)(dst.woz + z) * dst.wy + (dst.woy + y0)) * dst.wx + dst.wox
                           : nullptr;
-  // one output column x per thread and pass, all kRowsX rows of it: the
-  // weight-map loads (row indices clamped into the crop) are in flight together
-  for (int x = tid; x < sx; x += NTH) {
-    float val[kRowsX];
+  // one output column x of one group of RH rows per thread and pass: the
+  // group's weight-map loads (row indices clamped into the crop) are in flight
+  // together
+  constexpr int RH = 16, NG = kRowsC / RH;
+  for (int i = tid; i < sx * NG; i += NTH) {
+    const int g = i / sx, x = i - g * sx, r0 = g * RH;
+    float val[RH];
 #pragma unroll
-    for (int r = 0; r < kRowsX; ++r) val[r] = orow[r * RS + x] * dst.scale;
+    for (int r = 0; r < RH; ++r) val[r] = orow[(r0 + r) * RS + x] * dst.scale;
     if (wr) {
-      float wv[kRowsX];
+      float wv[RH];
 #pragma unroll
-      for (int r = 0; r < kRowsX; ++r) {
-        const float* row = wr + (size_t)min(r, nrows - 1) * dst.wx;
+      for (int r = 0; r < RH; ++r) {
+        const float* row = wr + (size_t)min(r0 + r, nrows - 1) * dst.wx;
         wv[r] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(row) + 4u * (unsigned)x);
       }
 #pragma unroll
-      for (int r = 0; r < kRowsX; ++r) val[r] *= wv[r];
+      for (int r = 0; r < RH; ++r) val[r] *= wv[r];
     }
     if (dst.dtype == 1) {
       unsigned short* out = reinterpret_cast<unsigned short*>(dst.p) + o0;
 #pragma unroll
-      for (int r = 0; r < kRowsX; ++r) {
-        if (r < nrows) {
-          char* row = reinterpret_cast<char*>(out + (size_t)r * dst.bx);
+      for (int r = 0; r < RH; ++r) {
+        if (r0 + r < nrows) {
+          char* row = reinterpret_cast<char*>(out + (size_t)(r0 + r) * dst.bx);
           *reinterpret_cast<unsigned short*>(row + 2u * (unsigned)x) = f32_to_bf16(val[r]);
         }
       }
     } else {
       float* out = reinterpret_cast<float*>(dst.p) + o0;
 #pragma unroll
-      for (int r = 0; r < kRowsX; ++r) {
-        if (r < nrows) {
-          char* row = reinterpret_cast<char*>(out + (size_t)r * dst.bx);
+      for (int r = 0; r < RH; ++r) {
+        if (r0 + r < nrows) {
+          char* row = reinterpret_cast<char*>(out + (size_t)(r0 + r) * dst.bx);
           *reinterpret_cast<float*>(row + 4u * (unsigned)x) = val[r];
         }
       }
@@ -489,7 +493,7 @@ int inverse_n(const cf* G, const cf* Sp, size_t s_stride, int s_planes, int A, c
   constexpr int RB = (128 / T > 0 ? 128 / T : 1);
   hipLaunchKernelGGL((k_c2c_rows<N, true>), dim3(NROWS / RB, nb), dim3(RB * T), 0, s, work,
                      work_stride, zlim, dst.sy, tw);
-  hipLaunchKernelGGL(k_c2r_x<N>, dim3(nb * (N / kRowsX) * N), dim3(kRowsX / 2 * T), 0, s, work,
+  hipLaunchKernelGGL(k_c2r_x<N>, dim3(nb * (N / kRowsC) * N), dim3(kRowsC / 2 * T), 0, s, work,
                      work_stride, nb, dst, tw);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : hip_status(e, "fft inverse launch");
