@@ -269,10 +269,15 @@ def main():
         torch.cuda.synchronize()
         serial = {"correlate": [(a.elapsed_time(b), size) for a, b, size in tm_s["correlate"]],
                   "extract": [a.elapsed_time(b) for a, b, _ in tm_s["extract"]]}
+        serial_stages = {"normalize": sum(a.elapsed_time(b) for a, b in tm_s["normalize"]),
+                         "correlate": sum(t for t, _ in serial["correlate"]),
+                         "extract": sum(serial["extract"]),
+                         "peaks": sum(a.elapsed_time(b) for a, b in tm_s["peaks"])}
         per_pass = [int(v) for v in counters.cpu().tolist()]
         eng.release()             # keep the maps for the accuracy gate, free the workspaces
         torch.cuda.empty_cache()
         res = dict(eng=eng, pk=pk, stage=stage, ext=ext_launch_ms, corr=corr_launch_ms, serial=serial,
+                   serial_stages=serial_stages,
                    ms_step=start.elapsed_time(stop) / args.steps, wall=wall,
                    counters=[v * args.steps for v in per_pass], fallbacks=fallbacks)
         return res
@@ -427,11 +432,18 @@ def main():
         "start_mode": {m: {"voxels_per_s": nvox / (results[m]["ms_step"] / 1e3),
                            "ms_per_step": results[m]["ms_step"],
                            "stages_ms_per_step": {k: v / args.steps for k, v in results[m]["stage"].items()},
+                           "stages_isolated_ms_per_pass": results[m]["serial_stages"],
                            "fallback_voxels_per_step": results[m]["fallbacks"] if m != "plain" else None}
                        for m in results},
         "accuracy_gate": gate,
         "learned_start_training": learn_info,
         "stages_ms_per_step": {k: v / args.steps for k, v in stage.items()},
+        "stages_isolated_ms_per_pass": R["serial_stages"],
+        "stages_note": ("stages_ms_per_step are HIP-event spans of the timed passes: with the "
+                        "correlations on a side stream under the extractions, a span includes time "
+                        "spent waiting for CUs the other stream holds, so the spans add up to more "
+                        "than ms_per_step; stages_isolated_ms_per_pass are each stage's own times "
+                        "from one untimed pass with every stage on the caller's stream"),
         "valid_voxels_per_s": nvalid / (ms_step / 1e3),
         "peaks_found": n_peaks,
         "roofline": roofline,
