@@ -50,7 +50,9 @@ struct Region {
 // Histogram of one 12-bit field of the score bit patterns over the region,
 // privatised in LDS per workgroup.  level 0: bits [31:20] of every voxel;
 // level 1: bits [19:8] of the voxels whose bits [31:20] equal `top`.
-// Each workgroup covers 8 rows (y) of one z slice.
+// Each workgroup covers kHistRows rows (y) of one z slice, in groups of 8, so
+// clearing and flushing its 16 KB of bins is spread over enough voxels.
+constexpr int kHistRows = 32;
 __global__ __launch_bounds__(256) void k_hist(const float* __restrict__ score, Region r, int level,
                                               unsigned top, unsigned* __restrict__ hist) {
   __shared__ unsigned h[kHistBins];
@@ -60,32 +62,35 @@ __global__ __launch_bounds__(256) void k_hist(const float* __restrict__ score, R
   const int nxv = r.x1 - r.x0 + 1;
   // scores crowd into few bins: a thread counts a run of equal bins in a
   // register and adds it at once, instead of one contended LDS atomic each.
-  // A thread takes one column x of the 8 rows at a time, its 8 loads in
-  // flight together.
-  const int nyv = min(8, r.y1 - (r.y0 + (int)blockIdx.y * 8) + 1);
-  const float* col0 = score + ((size_t)z * r.ny + r.y0 + blockIdx.y * 8) * r.nx + r.x0;
+  // A thread takes one column x of 8 rows at a time, its 8 loads in flight
+  // together.
   unsigned cur = 0xFFFFFFFFu, run = 0;
-  for (int x = blockIdx.x * 256 + threadIdx.x; x < nxv; x += 256 * gridDim.x) {
-    float v[8];
+  for (int y8 = r.y0 + (int)blockIdx.y * kHistRows;
+       y8 < min(r.y0 + ((int)blockIdx.y + 1) * kHistRows, r.y1 + 1); y8 += 8) {
+    const int nyv = min(8, r.y1 - y8 + 1);
+    const float* col0 = score + ((size_t)z * r.ny + y8) * r.nx + r.x0;
+    for (int x = blockIdx.x * 256 + threadIdx.x; x < nxv; x += 256 * gridDim.x) {
+      float v[8];
 #pragma unroll
-    for (int yy = 0; yy < 8; ++yy) v[yy] = yy < nyv ? col0[(size_t)yy * r.nx + x] : 0.0f;
+      for (int yy = 0; yy < 8; ++yy) v[yy] = yy < nyv ? col0[(size_t)yy * r.nx + x] : 0.0f;
 #pragma unroll
-    for (int yy = 0; yy < 8; ++yy) {
-      if (yy >= nyv) break;
-      const unsigned b = score_bits(v[yy]);
-      unsigned bin = 0xFFFFFFFFu;
-      if (level == 0) {
-        bin = b >> 20;
-      } else if ((b >> 20) == top) {
-        bin = (b >> 8) & 0xFFFu;
+      for (int yy = 0; yy < 8; ++yy) {
+        if (yy >= nyv) break;
+        const unsigned b = score_bits(v[yy]);
+        unsigned bin = 0xFFFFFFFFu;
+        if (level == 0) {
+          bin = b >> 20;
+        } else if ((b >> 20) == top) {
+          bin = (b >> 8) & 0xFFFu;
+        }
+        if (bin == 0xFFFFFFFFu) continue;
+        if (bin != cur) {
+          if (run) atomicAdd(&h[cur], run);
+          cur = bin;
+          run = 0;
+        }
+        ++run;
       }
-      if (bin == 0xFFFFFFFFu) continue;
-      if (bin != cur) {
-        if (run) atomicAdd(&h[cur], run);
-        cur = bin;
-        run = 0;
-      }
-      ++run;
     }
   }
   if (run) atomicAdd(&h[cur], run);
@@ -712,7 +717,7 @@ int find_peaks(const float* score, int nz, int ny, int nx, const int32_t lo[3],
   unsigned* shist = reinterpret_cast<unsigned*>(nfound_dev + 64);
 
   const dim3 grid((hi[2] - lo[2] + 1 + 255) / 256, hi[1] - lo[1] + 1, hi[0] - lo[0] + 1);
-  const dim3 hgrid(1, (hi[1] - lo[1] + 1 + 7) / 8, hi[0] - lo[0] + 1);
+  const dim3 hgrid(1, (hi[1] - lo[1] + kHistRows) / kHistRows, hi[0] - lo[0] + 1);
   std::vector<unsigned> h0(kHistBins), h1(kHistBins);
   fill_zero(hist, kHistBins * 4, s);
   hipLaunchKernelGGL(k_hist, hgrid, dim3(256), 0, s, score, r, 0, 0u, hist);
