@@ -99,16 +99,40 @@ __global__ __launch_bounds__(256) void k_hist(const float* __restrict__ score, R
     if (h[i]) atomicAdd(&hist[i], h[i]);
 }
 
-__global__ void k_compact(const float* __restrict__ score, Region r, unsigned key_lo,
-                          unsigned long long* __restrict__ keys, unsigned* __restrict__ counter) {
-  const int x = r.x0 + blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = r.y0 + blockIdx.y, z = r.z0 + blockIdx.z;
-  if (x > r.x1) return;
-  const size_t lin = ((size_t)z * r.ny + y) * r.nx + x;
-  const unsigned bits = score_bits(score[lin]);
-  if (bits >= key_lo) {
-    const unsigned slot = atomicAdd(counter, 1u);
-    keys[slot] = ((unsigned long long)(~bits) << 32) | (unsigned long long)lin;
+// Keys of the voxels whose score bits are >= key_lo, in any order (they are
+// sorted next).  A workgroup takes kCompactRows rows of one z slice and 1024
+// columns of each, 4 loads per thread in flight; a wavefront reserves the
+// slots of all its keys with one atomic.
+constexpr int kCompactRows = 4;
+__global__ __launch_bounds__(256) void k_compact(const float* __restrict__ score, Region r,
+                                                 unsigned key_lo,
+                                                 unsigned long long* __restrict__ keys,
+                                                 unsigned* __restrict__ counter) {
+  const int z = r.z0 + blockIdx.z, y0 = r.y0 + blockIdx.y * kCompactRows;
+  const int xb = r.x0 + blockIdx.x * 1024 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  const int nrows = min(kCompactRows, r.y1 - y0 + 1);
+  for (int yy = 0; yy < nrows; ++yy) {
+    const size_t row = ((size_t)z * r.ny + y0 + yy) * r.nx;
+    float v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = xb + 256 * k <= r.x1 ? score[row + xb + 256 * k] : 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int x = xb + 256 * k;
+      const unsigned bits = score_bits(v[k]);
+      const bool take = x <= r.x1 && bits >= key_lo;
+      const unsigned long long bal = __ballot(take);
+      if (bal == 0ull) continue;  // uniform across the wavefront
+      const int leader = __ffsll((long long)bal) - 1;
+      unsigned base = 0;
+      if (lane == leader) base = atomicAdd(counter, (unsigned)__popcll(bal));
+      base = (unsigned)__shfl((int)base, leader);
+      if (take)
+        keys[base + __popcll(bal & lt)] = ((unsigned long long)(~bits) << 32) |
+                                          (unsigned long long)(row + x);
+    }
   }
 }
 
@@ -659,12 +683,13 @@ int find_peaks_async(const float* score, int nz, int ny, int nx, const int32_t l
   unsigned* hist = reinterpret_cast<unsigned*>(keys_b + cand_cap);
   unsigned* counter = hist + kHistBins;
   unsigned* shist = reinterpret_cast<unsigned*>(counter + 128);
-  const dim3 grid((hi[2] - lo[2] + 1 + 255) / 256, hi[1] - lo[1] + 1, hi[0] - lo[0] + 1);
+  const dim3 cgrid((hi[2] - lo[2] + 1 + 1023) / 1024, (hi[1] - lo[1] + kCompactRows) / kCompactRows,
+                   hi[0] - lo[0] + 1);
   const size_t m = (size_t)nvalid;
   const size_t mpad = (m + kSortTile - 1) / kSortTile * kSortTile;
   const int nblk = (int)(mpad / kSortTile);
   fill_zero(counter, 4, s);
-  hipLaunchKernelGGL(k_compact, grid, dim3(256), 0, s, score, r, 0u, keys_a, counter);
+  hipLaunchKernelGGL(k_compact, cgrid, dim3(256), 0, s, score, r, 0u, keys_a, counter);
   if (mpad > m) {
     hipLaunchKernelGGL(k_fill, dim3((unsigned)((mpad - m + 255) / 256)), dim3(256), 0, s, keys_a, m,
                        mpad);
@@ -716,7 +741,8 @@ int find_peaks(const float* score, int nz, int ny, int nx, const int32_t lo[3],
   int* nfound_dev = reinterpret_cast<int*>(counter + 64);
   unsigned* shist = reinterpret_cast<unsigned*>(nfound_dev + 64);
 
-  const dim3 grid((hi[2] - lo[2] + 1 + 255) / 256, hi[1] - lo[1] + 1, hi[0] - lo[0] + 1);
+  const dim3 cgrid((hi[2] - lo[2] + 1 + 1023) / 1024, (hi[1] - lo[1] + kCompactRows) / kCompactRows,
+                   hi[0] - lo[0] + 1);
   const dim3 hgrid(1, (hi[1] - lo[1] + kHistRows) / kHistRows, hi[0] - lo[0] + 1);
   std::vector<unsigned> h0(kHistBins), h1(kHistBins);
   fill_zero(hist, kHistBins * 4, s);
@@ -762,7 +788,7 @@ int find_peaks(const float* score, int nz, int ny, int nx, const int32_t lo[3],
     const size_t mpad = ((size_t)m + kSortTile - 1) / kSortTile * kSortTile;
     const int nblk = (int)(mpad / kSortTile);
     fill_zero(counter, 4, s);
-    hipLaunchKernelGGL(k_compact, grid, dim3(256), 0, s, score, r, key_lo, keys_a, counter);
+    hipLaunchKernelGGL(k_compact, cgrid, dim3(256), 0, s, score, r, key_lo, keys_a, counter);
     if (mpad > (size_t)m) {
       hipLaunchKernelGGL(k_fill, dim3((unsigned)((mpad - m + 255) / 256)), dim3(256), 0, s, keys_a,
                          (size_t)m, mpad);
