@@ -35,7 +35,8 @@ def cuda(a, dtype=torch.float32):
                                             # the map of the oracle-checked case of the
                                             # same shape: the all-voxel walk takes its
                                             # rounds and the final pass
-                                            (5, (40, 52, 60), 2000, 6.0)])
+                                            (5, (40, 52, 60), 2000, 6.0),
+                                            (6, (6, 37, 1100), 300, 4.5)])
 def test_async_peaks_equal_sync_peaks(T, ctx, seed, shape, P, D):
     rng = np.random.default_rng(seed)
     s = cuda(np.round(rng.uniform(0, 1, shape), 3).astype(np.float32))

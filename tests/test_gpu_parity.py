@@ -298,7 +298,10 @@ def test_orientation_rank_one_and_zero(T, ctx):
                                             (3, (9, 10, 11), 5000, 1.0),
                                             # P beyond what fits at distance D: every
                                             # candidate is walked
-                                            (5, (40, 52, 60), 2000, 6.0)])
+                                            (5, (40, 52, 60), 2000, 6.0),
+                                            # rows wider than one 1024-column compaction
+                                            # block, ragged row blocks in y
+                                            (6, (6, 37, 1100), 300, 4.5)])
 def test_find_peaks_bit_exact_on_shared_map(T, ctx, seed, shape, P, D):
     rng = np.random.default_rng(seed)
     s = np.round(rng.uniform(0, 1, shape), 3).astype(np.float32)   # many exact ties
