@@ -141,6 +141,27 @@ def test_local_variance_textbook_and_invariances():
     assert np.all(wc == 0)
 
 
+def test_field_and_score_invariant_under_intensity_scale():
+    """Eq. norm_f with Eq. tcc: for f -> a f (a > 0) the prefiltered image and the
+    correlations scale by a and w by 1/a (the guard scales with the variance), so C
+    and its score are unchanged."""
+    w = _tiny(seed=12, D=24, L=10, r=4.0, copies=1)
+    m = ttm.ball_mask(10, 4.0)
+    tn = ttm.normalize_template(w.template, 4.0)
+    T = ttm.tensor_template(tn, synth.rotation_samples(2), 4)
+
+    def field(f):
+        g = ttm.prefilter_volume(f)
+        return ttm.tensor_field(g, ttm.local_normalization(g, m), T)
+
+    f = w.volume.astype(np.float64)   # scaled in FP64, so the only rounding is the oracle's
+    C1 = field(f)
+    for a in (1e-3, 7.5):
+        Ca = field(a * f)
+        assert np.allclose(Ca, C1, rtol=1e-9, atol=1e-12 * np.abs(C1).max())
+        assert np.allclose(ttm.score(Ca, 4), ttm.score(C1, 4), rtol=1e-9)
+
+
 # ---------------------------------------------------------------- P-3 TTM vs TM identity
 @pytest.mark.parametrize("n,dprime", [(4, 3), (2, 3), (2, 4)])
 def test_field_equals_rotation_average_of_tm(n, dprime):
