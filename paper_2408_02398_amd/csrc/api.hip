@@ -148,6 +148,20 @@ __global__ __launch_bounds__(1024) void k_stats(const double* __restrict__ part,
   }
 }
 
+// var = s2 - s1^2 / M in FP64; w = 1/sqrt(var) above the guard, else 0.
+__global__ void k_var_combine(const float* __restrict__ s1, const float* __restrict__ s2, int sz,
+                              int sy, int sx, double M, double eps, const double* __restrict__ stats,
+                              float* __restrict__ w, int ny, int nx, int oz, int oy, int ox) {
+  const size_t n = (size_t)sz * sy * sx;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int x = (int)(i % sx), y = (int)((i / sx) % sy), z = (int)(i / ((size_t)sx * sy));
+  const double a = (double)s1[i], b = (double)s2[i];
+  const double var = b - a * a / M;
+  const double thr = eps * M * stats[1];
+  w[((size_t)(oz + z) * ny + (oy + y)) * nx + (ox + x)] = (var > thr) ? (float)(1.0 / sqrt(var)) : 0.0f;
+}
+
 __global__ void k_mask(float* __restrict__ m, int L, float r) {
   const int n = L * L * L;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -707,7 +721,9 @@ size_t ttm_workspace_size(const ttm_desc* desc, int op, int fft_n, int nz, int n
       return align256(prefilter_blocks(nz, ny, nx) * 16);
     case TTM_OP_NORMALIZE: {
       if (!fft_ok(fft_n) || desc->L > fft_n) return 0;
-      return 4 * align256(spec_elems(fft_n) * 8) + align256(prefilter_blocks(nz, ny, nx) * 16);
+      const size_t step = (size_t)(fft_n - desc->L + 1);
+      return 4 * align256(spec_elems(fft_n) * 8) + 2 * align256(step * step * step * 4) +
+             align256(prefilter_blocks(nz, ny, nx) * 16);
     }
     case TTM_OP_CORRELATE:
       if (!fft_ok(fft_n) || desc->L > fft_n) return 0;
@@ -727,9 +743,12 @@ size_t ttm_workspace_size(const ttm_desc* desc, int op, int fft_n, int nz, int n
     case TTM_OP_TENSOR_WEDGE:
       if (desc->L < 1 || desc->L > 512) return 0;
       return wedge_workspace(desc->L, K);
-    case TTM_OP_NORM_CORR:
+    case TTM_OP_NORM_CORR: {
       if (!fft_ok(fft_n) || desc->L > fft_n) return 0;
-      return (size_t)(2 + std::max(K, 2)) * align256(spec_elems(fft_n) * 8);
+      const size_t step = (size_t)(fft_n - desc->L + 1);
+      return (size_t)(2 + std::max(K, 2)) * align256(spec_elems(fft_n) * 8) +
+             2 * align256(step * step * step * 4);
+    }
     default:
       return 0;
   }
@@ -886,11 +905,14 @@ int normalize_boxes(ttm_ctx* ctx, const ttm_desc* desc, const float* g, int nz, 
   const size_t se = spec_elems(fft_n);
   const size_t sb = align256(se * 8);
   const int step = fft_n - L + 1;
-  // G of the centred tile and of its square (sb bytes apart), then their two
-  // products' work spectra
+  // G of the centred tile and of its square (sb bytes apart), their two
+  // products' work spectra, the local sums s1 and s2 (s_gap floats apart)
   char* w = static_cast<char*>(ws);
   cf* G1 = reinterpret_cast<cf*>(w);
   cf* work = reinterpret_cast<cf*>(w + 2 * sb);
+  const size_t s_gap = align256((size_t)step * step * step * 4) / 4;
+  float* s1 = reinterpret_cast<float*>(w + 4 * sb);
+  float* s2 = s1 + s_gap;
   const int c = L / 2;
   const double M = mask_count(L, desc->mask_radius);
   const cf* mspec = static_cast<const cf*>(mask_spec);
@@ -903,16 +925,18 @@ int normalize_boxes(ttm_ctx* ctx, const ttm_desc* desc, const float* g, int nz, 
         const int sxx = std::min(step, box_size[2] - dx);
         const int oz = box_lo[0] + dz, oy = box_lo[1] + dy, ox = box_lo[2] + dx;
         // the centred tile and its square in one batched forward transform,
-        // both products with the mask spectrum in one batched inverse, whose
-        // last pass forms w from the two local sums
+        // both products with the mask spectrum in one batched inverse
         RealSrc src{g, 0, nz, ny, nx, oz - c, oy - c, ox - c, stats, 0, 1};
         int rc = fft3d_forward(fft_n, src, 2, G1, sb / 8, ctx->twiddles, s);
         if (rc) return rc;
-        RealDst dw{w_out, 0, 0, ny, nx, oz, oy, ox, szz, syy, sxx, nullptr, 0, 0, 0, 0, 0, scale,
-                   stats, M, (double)desc->eps_w};
-        rc = fft3d_inverse_mul(fft_n, G1, mspec, 0, L, 1, nullptr, work, sb / 8, dw, ctx->twiddles, s,
+        RealDst d1{s1, 0, s_gap, syy, sxx, 0, 0, 0, szz, syy, sxx, nullptr, 0, 0, 0, 0, 0, scale};
+        rc = fft3d_inverse_mul(fft_n, G1, mspec, 0, L, 1, nullptr, work, sb / 8, d1, ctx->twiddles, s,
                                2, sb / 8);
         if (rc) return rc;
+        const size_t nbx = (size_t)szz * syy * sxx;
+        hipLaunchKernelGGL(k_var_combine, dim3((unsigned)((nbx + 255) / 256)), dim3(256), 0, s, s1,
+                           s2, szz, syy, sxx, M, (double)desc->eps_w, stats, w_out, ny, nx, oz,
+                           oy, ox);
       }
     }
   }
@@ -1011,7 +1035,9 @@ int ttm_normalize(ttm_ctx* ctx, const ttm_desc* desc, const float* vol, int nz, 
   hipStream_t s = static_cast<hipStream_t>(stream);
   TTM_HIP(hipSetDevice(ctx->device));
   const size_t sb = align256(spec_elems(fft_n) * 8);
-  double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + 4 * sb);
+  const size_t step = (size_t)(fft_n - L + 1);
+  double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + 4 * sb +
+                                           2 * align256(step * step * step * 4));
   prefilter_stats(desc, vol, nz, ny, nx, g_out, stats_out, part, s);
   fill_zero(w_out, (size_t)nz * ny * nx * 4, s);
   const int c = L / 2;
@@ -1116,11 +1142,14 @@ int ttm_normalize_correlate(ttm_ctx* ctx, const ttm_desc* desc, const float* g, 
   const int K = ncomp(desc->degree, desc->dprime);
   const size_t se = spec_elems(fft_n);
   const size_t sb = align256(se * 8);
-  // G of the centred tile and of its square (sb bytes apart), then max(K, 2)
-  // work spectra
+  // G of the centred tile and of its square (sb bytes apart), max(K, 2) work
+  // spectra, the local sums s1 and s2 (s_gap floats apart)
   char* w = static_cast<char*>(ws);
   cf* G1 = reinterpret_cast<cf*>(w);
   cf* work = reinterpret_cast<cf*>(w + 2 * sb);
+  const size_t s_gap = align256((size_t)step * step * step * 4) / 4;
+  float* s1 = reinterpret_cast<float*>(w + (2 + std::max(K, 2)) * sb);
+  float* s2 = s1 + s_gap;
   const double M = mask_count(L, desc->mask_radius);
   const size_t tse = tspec_elems(fft_n, L);
   const cf* tspec = static_cast<const cf*>(spec);
@@ -1132,14 +1161,14 @@ int ttm_normalize_correlate(ttm_ctx* ctx, const ttm_desc* desc, const float* g, 
   RealSrc src{g, 0, nz, ny, nx, oz - c, oy - c, ox - c, stats, 0, 1};
   int rc = fft3d_forward(fft_n, src, 2, G1, sb / 8, ctx->twiddles, s);
   if (rc) return rc;
-  // local sums with the mask (both products in one batched inverse, whose last
-  // pass forms w on the box from them)
-  RealDst dw{w_out, 0, 0, ny, nx, oz, oy, ox, szz, syy, sxx, nullptr, 0, 0, 0, 0, 0, scale,
-             stats, M, (double)desc->eps_w};
-  rc = fft3d_inverse_mul(fft_n, G1, mspec, 0, L, 1, nullptr, work, sb / 8, dw, ctx->twiddles, s,
+  // local sums with the mask (both products in one batched inverse), then w on the box
+  RealDst d1{s1, 0, s_gap, syy, sxx, 0, 0, 0, szz, syy, sxx, nullptr, 0, 0, 0, 0, 0, scale};
+  rc = fft3d_inverse_mul(fft_n, G1, mspec, 0, L, 1, nullptr, work, sb / 8, d1, ctx->twiddles, s,
                          2, sb / 8);
   if (rc) return rc;
   const size_t nbx = (size_t)szz * syy * sxx;
+  hipLaunchKernelGGL(k_var_combine, dim3((unsigned)((nbx + 255) / 256)), dim3(256), 0, s, s1, s2,
+                     szz, syy, sxx, M, (double)desc->eps_w, stats, w_out, ny, nx, oz, oy, ox);
   // the K correlations from the same forward transform
   RealDst d{C_out, out_dtype, nbx, syy, sxx, 0, 0, 0, szz, syy, sxx, w_out, ny, nx, oz, oy, ox, scale};
   rc = fft3d_inverse_mul(fft_n, G1, tspec, tse, L, K, stats, work, sb / 8, d, ctx->twiddles, s);

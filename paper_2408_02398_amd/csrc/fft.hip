@@ -415,105 +415,6 @@ __global__ __launch_bounds__(kRowsC / 2 * Plan<N>::T) __attribute__((amdgpu_wave
   }
 }
 
-// Inverse X pass of the local normalisation (Eq. norm_f): work spectrum 0
-// holds the mask's product with the centred tile, 1 its product with the
-// square.  Row y of each is packed into one complex transform (s1 + i s2), so
-// a workgroup of kRowsC / 2 transforms covers kRowsC / 2 rows of both sums;
-// the variance s2 - s1^2 / M is formed in FP64 from the two FP32 sums and only
-// w is written.
-template <int N>
-__global__ __launch_bounds__(kRowsC / 2 * Plan<N>::T) __attribute__((amdgpu_waves_per_eu(N == 512 ? 8 : 1))) void k_c2r_var(
-    const cf* __restrict__ spec, size_t spec_stride, RealDst dst, const cf* __restrict__ tw) {
-  constexpr int T = Plan<N>::T, E = N / T, NP = kRowsC / 2, NH = N / 2 + 1;
-  constexpr int S = lds_stride<N>();
-  constexpr int SPS = NH + 1;  // padded spectrum row
-  constexpr int BYTES_A = kRowsC * SPS * 8, BYTES_B = NP * S * 8, BYTES_C = kRowsC * (N + 4) * 4;
-  constexpr int BYTES = BYTES_A > BYTES_B ? (BYTES_A > BYTES_C ? BYTES_A : BYTES_C)
-                                          : (BYTES_B > BYTES_C ? BYTES_B : BYTES_C);
-  __shared__ __align__(16) unsigned char smem[BYTES];
-  cf* sp = reinterpret_cast<cf*>(smem);
-  cf* xl = reinterpret_cast<cf*>(smem);
-  float* orow = reinterpret_cast<float*>(smem);
-  const int tid = threadIdx.x;
-  constexpr int NYB = N / NP;
-  const int item = (int)xcd_item(blockIdx.x, gridDim.x);
-  const int y0 = item % NYB * NP, z = item / NYB;
-  if (z >= dst.sz || y0 >= dst.sy) return;  // uniform: nothing of this block is kept
-  const int p = tid / T, t = tid % T;
-  constexpr int NTH = NP * T, NIN = NH * kRowsC, IT = (NIN + NTH - 1) / NTH;
-  const cf* in1 = spec + (size_t)z * NH * N + y0;
-  const cf* in2 = in1 + spec_stride;
-  {
-    // LDS rows 0 .. NP-1: the sum s1 of rows y0 .. y0+NP-1; rows NP .. 2NP-1:
-    // s2 of the same rows.  Rows past the crop were not stored by the Y pass
-    // and are read as zeros.
-    const int nrows_in = min(NP, dst.sy - y0);
-    cf ld[IT];
-#pragma unroll
-    for (int i = 0; i < IT; ++i) {
-      const int e = min(tid + i * NTH, NIN - 1);
-      const int r = e % kRowsC, rr = r % NP;
-      ld[i] = rr < nrows_in ? at_byte(r < NP ? in1 : in2, (unsigned)((e / kRowsC) * N + rr) * 8u)
-                            : cf{0.0f, 0.0f};
-    }
-#pragma unroll
-    for (int i = 0; i < IT; ++i) {
-      const int e = tid + i * NTH;
-      if (e < NIN) sp[(e % kRowsC) * SPS + e / kRowsC] = ld[i];
-    }
-  }
-  FftTw<N> twr;
-  twr.load(tw, t);
-  __syncthreads();
-  cf v[E];
-#pragma unroll
-  for (int j = 0; j < E; ++j) {
-    const int n = t + T * j;
-    cf a, bb;
-    if (n <= N / 2) {
-      a = sp[p * SPS + n];
-      bb = sp[(NP + p) * SPS + n];
-      if (n == 0 || n == N / 2) {  // spectra of real rows: these bins are real
-        a.y = 0.0f;
-        bb.y = 0.0f;
-      }
-    } else {
-      a = cconj(sp[p * SPS + (N - n)]);
-      bb = cconj(sp[(NP + p) * SPS + (N - n)]);
-    }
-    v[j] = cf{a.x - bb.y, a.y + bb.x};  // S1 + i S2
-  }
-  __syncthreads();
-  fft_1d<N, true, true>(v, xl + p * S, twr, t);
-  __syncthreads();  // the row buffer overlaps other transforms' exchange areas
-  constexpr int RS = N + 4;
-#pragma unroll
-  for (int j = 0; j < E; ++j) {
-    const int n = t + T * j;
-    orow[(2 * p) * RS + n] = v[j].x;
-    orow[(2 * p + 1) * RS + n] = v[j].y;
-  }
-  __syncthreads();
-  const int nrows = min(NP, dst.sy - y0);
-  const int sx = dst.sx;
-  const double M = dst.var_M;
-  const double thr = dst.var_eps * M * dst.var_stats[1];
-  float* out = reinterpret_cast<float*>(dst.p) +
-               ((size_t)(dst.vz0 + z) * dst.by + (dst.vy0 + y0)) * dst.bx + dst.vx0;
-  for (int x = tid; x < sx; x += NTH) {
-#pragma unroll
-    for (int r = 0; r < NP; ++r) {
-      if (r < nrows) {
-        const double a = (double)(orow[(2 * r) * RS + x] * dst.scale);
-        const double b = (double)(orow[(2 * r + 1) * RS + x] * dst.scale);
-        const double var = b - a * a / M;
-        char* row = reinterpret_cast<char*>(out + (size_t)r * dst.bx);
-        *reinterpret_cast<float*>(row + 4u * (unsigned)x) = var > thr ? (float)(1.0 / sqrt(var)) : 0.0f;
-      }
-    }
-  }
-}
-
 __global__ void k_twiddles(cf* tw_all) {
   const int sizes[8] = {32, 64, 128, 256, 512, 96, 160, 192};
   int off = 0;
@@ -592,13 +493,8 @@ int inverse_n(const cf* G, const cf* Sp, size_t s_stride, int s_planes, int A, c
   constexpr int RB = (128 / T > 0 ? 128 / T : 1);
   hipLaunchKernelGGL((k_c2c_rows<N, true>), dim3(NROWS / RB, nb), dim3(RB * T), 0, s, work,
                      work_stride, zlim, dst.sy, tw);
-  if (dst.var_stats) {  // two work spectra, checked by fft3d_inverse_mul
-    hipLaunchKernelGGL(k_c2r_var<N>, dim3((N / (kRowsC / 2)) * N), dim3(kRowsC / 2 * T), 0, s,
-                       work, work_stride, dst, tw);
-  } else {
-    hipLaunchKernelGGL(k_c2r_x<N>, dim3(nb * (N / kRowsC) * N), dim3(kRowsC / 2 * T), 0, s, work,
-                       work_stride, nb, dst, tw);
-  }
+  hipLaunchKernelGGL(k_c2r_x<N>, dim3(nb * (N / kRowsC) * N), dim3(kRowsC / 2 * T), 0, s, work,
+                     work_stride, nb, dst, tw);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : hip_status(e, "fft inverse launch");
 }
@@ -662,10 +558,6 @@ int fft3d_inverse_mul(int N, const cf* G, const cf* Sp, size_t s_stride, int s_p
                       const cf* tw_all, hipStream_t s, int gb, size_t g_stride) {
   if (gb < 1 || (gb > 1 && A != 1)) {
     set_error("fft inverse: a batch of %d G spectra needs one component (A = %d)", gb, A);
-    return -1;
-  }
-  if (dst.var_stats && A * gb != 2) {
-    set_error("fft inverse: the local variance needs two work spectra (got %d)", A * gb);
     return -1;
   }
   const cf* tw = tw_all + twiddle_offset(N);

@@ -57,13 +57,6 @@ struct RealDst {
   int wy, wx;
   int woz, woy, wox;
   float scale;
-  // Set for the local normalisation: the two work spectra are the mask's
-  // products with the centred tile (s1) and with its square (s2), and the
-  // pass writes w = 1 / sqrt(s2 - s1^2 / M) (0 where that variance is at most
-  // var_eps * M * var_stats[1]) as FP32 at p instead of the sums.
-  const double* var_stats;
-  double var_M;
-  double var_eps;
 };
 
 // Twiddle table for edge N inside the context table.
