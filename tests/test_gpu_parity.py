@@ -142,6 +142,21 @@ def test_normalize_matches_oracle(T, ctx, small):
     assert np.max(np.abs(wg[nz] - wo[nz]) / wo[nz]) < 1e-4
 
 
+@pytest.mark.parametrize("a", [2.0 ** -14, 2.0 ** 13])
+def test_normalize_at_intensity_scales(T, ctx, small, a):
+    """w of the tomogram scaled by a is the oracle's w / a (Eq. norm_f; the oracle's
+    scale invariance is pinned on the CPU).  a is a power of two, so the scaled input
+    is exact: the local sums must keep their relative precision at any intensity scale
+    (a pass that mixes the first and second sums in one FP32 transform would not)."""
+    d = T.make_desc(small["n"], small["L"], small["r"])
+    spec = T.template_spectra(ctx, d, cuda(small["Tt"]), 32)
+    _, w, _ = T.normalize(ctx, d, cuda(small["w"].volume * np.float32(a)), spec, 32)
+    wg, wo = host(w) * a, small["wmap"]
+    assert np.all(wg[wo == 0] == 0)
+    nz = wo > 0
+    assert np.max(np.abs(wg[nz] - wo[nz]) / wo[nz]) < 1e-4
+
+
 def test_prefilter_and_box_normalisation_reproduce_normalize(T, ctx, small):
     """ttm_prefilter + ttm_normalize_box over the tile boxes == ttm_normalize, bit for bit,
     and a box that is not step-aligned still matches to FP32 rounding."""
